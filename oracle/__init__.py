@@ -1,0 +1,382 @@
+"""FP64 CPU oracle of the magnification-map hot path (test infrastructure).
+
+Only the test-suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It wraps ``liboracle.so`` (plain C,
+built from ``oracle.c`` with gcc) and composes its steps in the order the
+paper gives them:
+
+  set-up of the shooting region and ray grid (sec. 2.3, appendix A)
+  -> lens equation for every grid vertex, the star deflection either by direct
+     summation (sec. 2.2) or by the FMM of appendix C
+  -> IPM: apportion every mapped triangle among source pixels (sec. 3.2)
+  -> magnification = deposited image area / pixel area.
+
+Nothing here is shared with, or calls into, the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+CFLAGS = ["-O2", "-fPIC", "-shared", "-std=c11", "-ffp-contract=off",
+          "-fcx-limited-range", "-pthread", "-Wall", "-Wno-unused-function"]
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (generic x86-64, no host-specific ISA)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+_dp = C.POINTER(C.c_double)
+_lp = C.POINTER(C.c_long)
+_ip = C.POINTER(C.c_int)
+
+
+class Region(C.Structure):
+    _fields_ = [
+        ("y1c", C.c_double), ("y2c", C.c_double), ("hw1", C.c_double), ("hw2", C.c_double),
+        ("n1", C.c_long), ("n2", C.c_long),
+        ("rays_per_pixel", C.c_double),
+        ("nray1", C.c_long), ("nray2", C.c_long),
+        ("flux_fraction", C.c_double),
+        ("dx1_set", C.c_double), ("dx2_set", C.c_double),
+        ("kappa", C.c_double), ("lam1", C.c_double), ("lam2", C.c_double), ("mu_macro", C.c_double),
+        ("mean_m", C.c_double), ("mean_m2", C.c_double), ("border", C.c_double),
+        ("X1", C.c_double), ("X2", C.c_double), ("dX1", C.c_double), ("dX2", C.c_double),
+        ("pix1", C.c_double), ("pix2", C.c_double),
+        ("nr1", C.c_long), ("nr2", C.c_long),
+        ("d1", C.c_double), ("d2", C.c_double), ("x0", C.c_double), ("y0", C.c_double),
+        ("L0", C.c_double),
+    ]
+
+    def asdict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        L.orc_alpha_direct.argtypes = [C.c_long, _dp, _dp, _dp, C.c_long, _dp, _dp, _dp, _dp, C.c_int]
+        L.orc_alpha_direct_reversed.argtypes = [C.c_long, _dp, _dp, _dp, C.c_long, _dp, _dp, _dp, _dp]
+        L.orc_lens_equation.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int, C.c_double,
+                                        C.c_long, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.orc_star_radius.argtypes = [C.c_long, _dp, C.c_double]
+        L.orc_star_radius.restype = C.c_double
+        L.orc_region_setup.argtypes = [C.POINTER(Region), C.c_double, C.c_double, C.c_double,
+                                       C.c_long, _dp, _dp, _dp]
+        L.orc_region_setup.restype = C.c_int
+        L.orc_grid_points.argtypes = [C.POINTER(Region), C.c_long, C.c_long, _dp, _dp]
+        L.orc_fmm_build.argtypes = [C.c_long, _dp, _dp, _dp, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int]
+        L.orc_fmm_build.restype = C.c_void_p
+        L.orc_fmm_free.argtypes = [C.c_void_p]
+        L.orc_fmm_num_nodes.argtypes = [C.c_void_p]
+        L.orc_fmm_num_nodes.restype = C.c_long
+        L.orc_fmm_num_levels.argtypes = [C.c_void_p]
+        L.orc_fmm_num_levels.restype = C.c_int
+        L.orc_fmm_nodes.argtypes = [C.c_void_p, _ip, _lp, _lp, _ip, _lp, _lp]
+        L.orc_fmm_coeffs.argtypes = [C.c_void_p, _dp, _dp]
+        L.orc_fmm_alpha.argtypes = [C.c_void_p, C.c_long, _dp, _dp, _dp, _dp, _lp, C.c_int]
+        L.orc_fmm_eval_multipole.argtypes = [C.c_void_p, C.c_long, C.c_long, _dp, _dp, _dp, _dp]
+        L.orc_fmm_eval_local.argtypes = [C.c_void_p, C.c_long, C.c_long, _dp, _dp, _dp, _dp]
+        L.orc_fmm_sorted_stars.argtypes = [C.c_void_p, _dp, _dp, _dp]
+        L.orc_fmm_sorted_stars.restype = C.c_long
+        for nm in ("orc_op_m2m", "orc_op_m2l", "orc_op_l2l"):
+            getattr(L, nm).argtypes = [C.c_int, _dp, C.c_double, C.c_double, _dp]
+        L.orc_tri_pixel_area.argtypes = [_dp, _dp, C.c_long, C.c_long]
+        L.orc_tri_pixel_area.restype = C.c_double
+        L.orc_ipm_rows.argtypes = [C.POINTER(Region), C.c_long, C.c_long, _dp, _dp, _dp, _dp]
+        L.orc_normalise.argtypes = [C.POINTER(Region), _dp, _dp]
+        L.orc_shoot_rows.argtypes = [C.POINTER(Region), C.c_double, C.c_double, C.c_double, C.c_int,
+                                     C.c_double, C.c_long, _dp, _dp, _dp, C.c_void_p, C.c_long,
+                                     C.c_long, _dp, _dp, C.c_int]
+        _lib = L
+    return _lib
+
+
+def _d(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# --------------------------------------------------------------------------
+# lens
+# --------------------------------------------------------------------------
+
+@dataclass
+class Lens:
+    """Macro model + star field (sec. 2.2).  sheet=True adds the circular
+    compensating sheet of radius R_* = sqrt(sum m / kappa_*) (sec. 3.1)."""
+    kappa_star: float
+    kappa_smooth: float
+    gamma: float
+    x: np.ndarray
+    y: np.ndarray
+    m: np.ndarray
+    sheet: bool = True
+
+    def __post_init__(self):
+        self.x, self.y, self.m = _f64(self.x), _f64(self.y), _f64(self.m)
+        self.r_star = lib().orc_star_radius(len(self.m), _d(self.m), self.kappa_star)
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+
+def alpha_direct(lens: Lens, zx, zy, nthreads: int = 0, reversed_order: bool = False):
+    """Star deflection a_*(z) by direct summation (sec. 2.2)."""
+    zx, zy = _f64(zx), _f64(zy)
+    ax, ay = np.empty_like(zx), np.empty_like(zy)
+    if reversed_order:
+        lib().orc_alpha_direct_reversed(lens.n, _d(lens.x), _d(lens.y), _d(lens.m), zx.size,
+                                        _d(zx), _d(zy), _d(ax), _d(ay))
+    else:
+        lib().orc_alpha_direct(lens.n, _d(lens.x), _d(lens.y), _d(lens.m), zx.size,
+                               _d(zx), _d(zy), _d(ax), _d(ay), nthreads)
+    return ax, ay
+
+
+def lens_equation(lens: Lens, zx, zy, ax, ay):
+    zx, zy, ax, ay = map(_f64, (zx, zy, ax, ay))
+    wx, wy = np.empty_like(zx), np.empty_like(zy)
+    lib().orc_lens_equation(lens.kappa_star, lens.kappa_smooth, lens.gamma, int(lens.sheet),
+                            lens.r_star, zx.size, _d(zx), _d(zy), _d(ax), _d(ay), _d(wx), _d(wy))
+    return wx, wy
+
+
+def shoot_direct(lens: Lens, zx, zy, nthreads: int = 0):
+    ax, ay = alpha_direct(lens, zx, zy, nthreads)
+    return lens_equation(lens, zx, zy, ax, ay)
+
+
+# --------------------------------------------------------------------------
+# region
+# --------------------------------------------------------------------------
+
+class DegenerateMacro(ValueError):
+    pass
+
+
+def region(lens: Lens, y1c=0.0, y2c=0.0, hw1=5.0, hw2=5.0, n1=256, n2=256, rays_per_pixel=1.0,
+           nray1=0, nray2=0, flux_fraction=0.01, dx1=0.0, dx2=0.0, **_ignored) -> Region:
+    R = Region(y1c=y1c, y2c=y2c, hw1=hw1, hw2=hw2, n1=n1, n2=n2, rays_per_pixel=rays_per_pixel,
+               nray1=nray1, nray2=nray2, flux_fraction=flux_fraction, dx1_set=dx1, dx2_set=dx2)
+    rc = lib().orc_region_setup(C.byref(R), lens.kappa_star, lens.kappa_smooth, lens.gamma,
+                                lens.n, _d(lens.x), _d(lens.y), _d(lens.m))
+    if rc == 2:
+        raise DegenerateMacro("|1-kappa+-gamma| vanishes: shooting region is unbounded")
+    if rc != 0:
+        raise ValueError("invalid map request")
+    return R
+
+
+def grid_points(R: Region, row_lo: int, row_hi: int):
+    n = (row_hi - row_lo) * R.nr1
+    zx, zy = np.empty(n), np.empty(n)
+    lib().orc_grid_points(C.byref(R), row_lo, row_hi, _d(zx), _d(zy))
+    return zx, zy
+
+
+# --------------------------------------------------------------------------
+# FMM (appendix C)
+# --------------------------------------------------------------------------
+
+MAX_LEVEL = 24
+
+
+class FMM:
+    """Tree + multipole/local coefficients of appendix C, built on the CPU."""
+
+    def __init__(self, lens: Lens, L0: float, p: int, nmax: int = 32, lmax: int = MAX_LEVEL,
+                 nthreads: int = 0):
+        self.lens, self.L0, self.p, self.nmax, self.lmax = lens, L0, p, nmax, lmax
+        self._h = lib().orc_fmm_build(lens.n, _d(lens.x), _d(lens.y), _d(lens.m), L0, p, nmax,
+                                      lmax, nthreads)
+        if not self._h:
+            raise ValueError("oracle FMM build failed")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_fmm_free(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def num_nodes(self) -> int:
+        return lib().orc_fmm_num_nodes(self._h)
+
+    @property
+    def num_levels(self) -> int:
+        return lib().orc_fmm_num_levels(self._h)
+
+    def nodes(self):
+        n = self.num_nodes
+        level = np.empty(n, np.int32); i = np.empty(n, np.int64); j = np.empty(n, np.int64)
+        leaf = np.empty(n, np.int32); ns = np.empty(n, np.int64); blk = np.empty(n, np.int64)
+        lib().orc_fmm_nodes(self._h, level.ctypes.data_as(_ip), i.ctypes.data_as(_lp),
+                            j.ctypes.data_as(_lp), leaf.ctypes.data_as(_ip),
+                            ns.ctypes.data_as(_lp), blk.ctypes.data_as(_lp))
+        return dict(level=level, i=i, j=j, leaf=leaf, nstars=ns, block=blk)
+
+    def coeffs(self):
+        n, P1 = self.num_nodes, self.p + 1
+        a = np.empty(2 * n * P1); c = np.empty(2 * n * P1)
+        lib().orc_fmm_coeffs(self._h, _d(a), _d(c))
+        a = a.view(np.complex128).reshape(n, P1)
+        c = c.view(np.complex128).reshape(n, P1)
+        return a, c
+
+    def alpha(self, zx, zy, nthreads: int = 0, want_leaf: bool = False):
+        zx, zy = _f64(zx), _f64(zy)
+        ax, ay = np.empty_like(zx), np.empty_like(zy)
+        leaf = np.empty(zx.size, np.int64) if want_leaf else None
+        lib().orc_fmm_alpha(self._h, zx.size, _d(zx), _d(zy), _d(ax), _d(ay),
+                            leaf.ctypes.data_as(_lp) if want_leaf else None, nthreads)
+        return (ax, ay, leaf) if want_leaf else (ax, ay)
+
+    def eval_multipole(self, q: int, zx, zy):
+        zx, zy = _f64(zx), _f64(zy)
+        gx, gy = np.empty_like(zx), np.empty_like(zy)
+        lib().orc_fmm_eval_multipole(self._h, q, zx.size, _d(zx), _d(zy), _d(gx), _d(gy))
+        return gx + 1j * gy
+
+    def eval_local(self, q: int, zx, zy):
+        zx, zy = _f64(zx), _f64(zy)
+        gx, gy = np.empty_like(zx), np.empty_like(zy)
+        lib().orc_fmm_eval_local(self._h, q, zx.size, _d(zx), _d(zy), _d(gx), _d(gy))
+        return gx + 1j * gy
+
+    def sorted_stars(self):
+        n = self.lens.n
+        x, y, m = np.empty(n), np.empty(n), np.empty(n)
+        lib().orc_fmm_sorted_stars(self._h, _d(x), _d(y), _d(m))
+        return x, y, m
+
+
+def _op(name: str, p: int, coeffs: np.ndarray, z0: complex) -> np.ndarray:
+    ci = np.ascontiguousarray(np.asarray(coeffs, np.complex128)).view(np.float64).copy()
+    out = np.empty(2 * (p + 1))
+    getattr(lib(), name)(p, _d(ci), float(np.real(z0)), float(np.imag(z0)), _d(out))
+    return out.view(np.complex128)
+
+
+def op_m2m(p, a, z0):
+    return _op("orc_op_m2m", p, a, z0)
+
+
+def op_m2l(p, b, z0):
+    return _op("orc_op_m2l", p, b, z0)
+
+
+def op_l2l(p, c, z0):
+    return _op("orc_op_l2l", p, c, z0)
+
+
+def auto_order(mean_m: float, mean_m2: float, L: float, eps: float, pmax: int = 31) -> int:
+    """Expansion order of appendix C.3: smallest integer p with
+    p > log2( (<m^2>/<m>) / (L |eps|) ), capped at pmax."""
+    import math
+    if mean_m <= 0:
+        return 1
+    t = math.log2((mean_m2 / mean_m) / (L * eps))
+    p = int(math.floor(t)) + 1
+    return max(1, min(pmax, p))
+
+
+# --------------------------------------------------------------------------
+# IPM (sec. 3.2)
+# --------------------------------------------------------------------------
+
+def tri_pixel_area(tu, tv, i: int, j: int) -> float:
+    tu, tv = _f64(tu), _f64(tv)
+    return lib().orc_tri_pixel_area(_d(tu), _d(tv), i, j)
+
+
+def shoot_rows(R: Region, lens: Lens, row_lo: int, row_hi: int, fmm: Optional[FMM] = None,
+               nthreads: int = 0):
+    """Source positions w of vertex rows [row_lo, row_hi)."""
+    n = (row_hi - row_lo) * R.nr1
+    wx, wy = np.empty(n), np.empty(n)
+    lib().orc_shoot_rows(C.byref(R), lens.kappa_star, lens.kappa_smooth, lens.gamma,
+                         int(lens.sheet), lens.r_star, lens.n, _d(lens.x), _d(lens.y), _d(lens.m),
+                         fmm.handle if fmm is not None else None, row_lo, row_hi, _d(wx), _d(wy),
+                         nthreads)
+    return wx, wy
+
+
+def ipm_rows(R: Region, row_lo: int, row_hi: int, wx, wy, dep: np.ndarray, stats: np.ndarray):
+    """Apportion the triangles of cell rows [row_lo, row_hi); wx, wy hold vertex
+    rows row_lo .. row_hi inclusive."""
+    wx, wy = _f64(wx), _f64(wy)
+    assert wx.size == (row_hi - row_lo + 1) * R.nr1
+    lib().orc_ipm_rows(C.byref(R), row_lo, row_hi, _d(wx), _d(wy), _d(dep), _d(stats))
+
+
+@dataclass
+class MapResult:
+    mu: np.ndarray             # (n2, n1), row j = y2 ascending, column i = y1 ascending
+    region: Region
+    dep_total: float           # image area deposited inside the map
+    a_out: float               # image area mapped outside the map
+    a_skip: float              # image area of skipped (non-finite) triangles
+    n_skip: int
+    n_zero: int
+    rows: tuple
+
+
+def magnification_map(lens: Lens, spec: dict, method: str = "fmm", p: int = 0,
+                      nmax: int = 32, lmax: int = MAX_LEVEL, rows=None, eps: float = 1e-7,
+                      nthreads: int = 0, chunk_rows: int = 256) -> MapResult:
+    """Whole map (or the cell rows `rows` = (lo, hi)) in FP64 on the CPU."""
+    R = region(lens, **spec)
+    row_lo, row_hi = rows if rows is not None else (0, R.nr2 - 1)
+    fmm = None
+    if method == "fmm":
+        if p <= 0:
+            p = spec.get("order", 0) or 0
+        if p <= 0:
+            # smallest node half-length the tree can have with these stars is not
+            # known before building; use the root / 2^levels estimate after build
+            fmm_probe = FMM(lens, R.L0, 1, nmax, lmax, nthreads)
+            nl = fmm_probe.num_levels
+            del fmm_probe
+            p = auto_order(R.mean_m, R.mean_m2, R.L0 / 2 ** (nl - 1), eps)
+        fmm = FMM(lens, R.L0, p, nmax, lmax, nthreads)
+    elif method != "direct":
+        raise ValueError(method)
+    dep = np.zeros(R.n1 * R.n2)
+    stats = np.zeros(5)
+    b = row_lo
+    while b < row_hi:
+        e = min(row_hi, b + chunk_rows)
+        wx, wy = shoot_rows(R, lens, b, e + 1, fmm, nthreads)
+        ipm_rows(R, b, e, wx, wy, dep, stats)
+        b = e
+    mu = np.empty_like(dep)
+    lib().orc_normalise(C.byref(R), _d(dep), _d(mu))
+    return MapResult(mu.reshape(R.n2, R.n1), R, stats[0], stats[1], stats[2], int(stats[3]),
+                     int(stats[4]), (row_lo, row_hi))
