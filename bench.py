@@ -1,0 +1,154 @@
+"""Benchmark: magnification-map throughput on one MI355X.
+
+A step is one whole map of the plain FP64 workload (1e5 Kroupa stars,
+kappa_* = 0.45, kappa_s = 0, gamma = 0.45, 2000 x 2000 px of half-width 25,
+1 ray per pixel, FMM order 20): tree build, P2M/M2M/M2L/P2L/L2L, leaf tables,
+ray shooting and IPM, with the stars already resident in device memory and
+the map left in device memory.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "rays/sec and maps/hour on 1 MI355X at ≤1e-4 pixel error; plain vs mixed/batched"
+FP64_VECTOR_PEAK_TFLOPS = 78.6          # MI355X FP64 vector, dense
+
+
+def shoot_flops(stats: dict) -> float:
+    """Algorithmic FP64 flops of the ray-shooting kernel for one map:
+    10 per ray-star pair (2 sub, |dz|^2 3, divide 1, 2 x fused accumulate 4),
+    8 per Horner step of the degree p-1 derivative polynomial (p-1 steps),
+    26 per ray for the vertex position, zeta, macro model, sheet and pixel
+    coordinates."""
+    p = stats["order"]
+    return 10.0 * stats["near_pairs"] + (8.0 * (p - 1) + 26.0) * stats["n_rays"]
+
+
+def cpu_baseline(wl, spec, region, nthreads: int) -> dict:
+    """The oracle (plain FP64 C, FMM + per-pixel IPM) on a bounded sample of the
+    same map: its full FMM build plus a strip of ray rows through the middle
+    of the grid, extrapolated to all rows."""
+    import numpy as np
+    import oracle
+
+    sf = wl.stars()
+    L = wl.lens
+    ol = oracle.Lens(L.kappa_star, L.kappa_smooth, L.gamma, sf.x, sf.y, sf.m)
+    R = oracle.region(ol, **spec)
+    t0 = time.perf_counter()
+    F = oracle.FMM(ol, R.L0, spec["order"], nthreads=nthreads)
+    t_build = time.perf_counter() - t0
+    rows = 64
+    r0 = R.nr2 // 2 - rows // 2
+    dep = np.zeros(R.n1 * R.n2)
+    st = np.zeros(5)
+    t0 = time.perf_counter()
+    done = 0
+    while done < rows or time.perf_counter() - t0 < 8.0:
+        b = r0 + done
+        if b + 16 >= R.nr2:
+            break
+        wx, wy = oracle.shoot_rows(R, ol, b, b + 17, F, nthreads)
+        oracle.ipm_rows(R, b, b + 16, wx, wy, dep, st)
+        done += 16
+        if time.perf_counter() - t0 > 20.0:
+            break
+    t_rows = time.perf_counter() - t0
+    t_full = t_build + t_rows * (R.nr2 - 1) / done
+    rays = R.nr1 * R.nr2
+    return {"value": rays / t_full, "unit": "rays/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"oracle FMM build ({t_build:.1f} s, p={spec['order']}) + {done} of {R.nr2 - 1} cell rows "
+                      f"shot and apportioned ({t_rows:.1f} s), extrapolated to the full map "
+                      f"({t_full:.0f} s for {rays} rays)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the map path has no multi-GPU mode); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2506_02114_amd as mlm
+    import workloads as W
+
+    wl = W.config("plain_large")
+    spec = wl.map.asdict()
+    sf = wl.stars()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    L = wl.lens
+    lens = mlm.Lens(L.kappa_star, L.kappa_smooth, L.gamma, torch.from_numpy(sf.x).to(dev),
+                    torch.from_numpy(sf.y).to(dev), torch.from_numpy(sf.m).to(dev))
+    region = lens.region(**spec)
+    out = torch.empty((spec["n2"], spec["n1"]), dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        lens.map(out=out, **spec)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, s = lens.map(out=out, timing=1, **spec)
+        stats.append(s)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    rays = stats[0]["n_rays"]
+    value = rays / (ms * 1e-3)
+
+    def avg(k):
+        return sum(s[k] for s in stats) / len(stats)
+
+    t_shoot, t_ipm = avg("t_shoot_ms"), avg("t_ipm_ms")
+    flops = shoot_flops(stats[0])
+    shoot_roof = {"bound": "alu", "achieved": flops / (t_shoot * 1e-3) / 1e12, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                  "unit": "TFLOP/s", "traffic": None, "kernel": "k_shoot"}
+    shoot_roof["frac"] = shoot_roof["achieved"] / shoot_roof["peak"]
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded star field of the workload's shape)",
+        "config": {"workload": "plain_large: 1e5 Kroupa (0.08-1.5) stars, kappa*=0.45, kappa_s=0, gamma=0.45, "
+                               "2000x2000 px, half-width 25, 1 ray/px, FMM order 20, leaf <= 32 block stars",
+                   "rays_per_map": rays, "grid": [region["nr1"], region["nr2"]], "precision": "fp64"},
+        "maps_per_hour": 3600.0 / (ms * 1e-3),
+        "stages_ms": {"tree": avg("t_tree_ms"), "fmm": avg("t_fmm_ms"), "shoot": t_shoot, "ipm": t_ipm,
+                      "total_device": avg("t_total_ms")},
+        "roofline": shoot_roof,
+        "tree": {"nodes": stats[0]["n_nodes"], "leaves": stats[0]["n_leaves"], "levels": stats[0]["n_levels"],
+                 "near_pairs_per_ray": stats[0]["near_pairs"] / rays},
+    }
+    if not args.no_cpu_baseline:
+        nthreads = min(16, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), os.cpu_count() or 1)
+        line["cpu_baseline"] = cpu_baseline(wl, spec, region, nthreads)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

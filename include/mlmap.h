@@ -1,0 +1,268 @@
+/*
+ * mlmap.h -- C ABI of the MI355X microlensing magnification-map library.
+ *
+ * The library computes source-plane magnification maps of a field of point
+ * mass microlenses embedded in a macro model (convergence kappa, shear gamma),
+ * following Weisenbach 2025, "Rootin' Tootin' Efficient Ray Shootin'":
+ *
+ *   lens equation (sec. 2.2)   w = (1-kappa) z + gamma conj(z) - a_*(z) - a_s(z)
+ *   star deflection            a_*(z) = sum_i m_i / conj(z - z_i), evaluated with a
+ *                              quadtree fast multipole method (sec. 3.3, app. C)
+ *   compensating sheet         a_s(z) = -kappa_* z inside the star disc (sec. 3.1)
+ *   map                        inverse polygon mapping of the ray grid's triangular
+ *                              cells onto source pixels (sec. 3.2)
+ *
+ * Units: theta_* = 1 (lengths in Einstein radii of a unit-mass lens).
+ * Complex positions are passed as interleaved (x1, x2) double pairs.
+ *
+ * General rules
+ *   - Every call returns an mlm_status; the library never aborts or exits.
+ *     On error, out-parameters are left untouched and mlm_last_error()
+ *     returns a description (per calling thread).
+ *   - "device" pointers are HIP device allocations of the current device
+ *     (for example the data_ptr() of a torch tensor on cuda:0); "host"
+ *     pointers are ordinary process memory.  Which one a pointer is is
+ *     stated by an explicit flag, never guessed.
+ *   - Objects returned through `**out` are owned by the library and must be
+ *     released with the matching destroy call.  Caller arrays are copied on
+ *     entry; the library keeps no reference to them.
+ *   - A lens may be used from several threads, but map calls on one lens are
+ *     serialised (they share the lens's device workspace).
+ */
+#ifndef MLMAP_H
+#define MLMAP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MLM_ABI_VERSION 1
+
+typedef enum mlm_status {
+    MLM_OK = 0,
+    MLM_EINVAL = 1,       /* invalid argument (NaN, negative size, bad enum, NULL) */
+    MLM_EDEGENERATE = 2,  /* |1 - kappa +- gamma| < 1e-9: shooting region unbounded */
+    MLM_ERANGE = 3,       /* a size exceeds what the library supports */
+    MLM_ENOMEM = 4,       /* host or device allocation failed */
+    MLM_EDEVICE = 5,      /* a HIP runtime call failed */
+    MLM_ENOTSUP = 6       /* option not supported by this build */
+} mlm_status;
+
+/* ABI version of the loaded library (MLM_ABI_VERSION of its build). */
+int32_t mlm_abi_version(void);
+
+/* Static, human-readable name of a status code. */
+const char *mlm_status_str(mlm_status s);
+
+/* Detail of the last failing call on this thread ("" if none).  The pointer
+   stays valid until the next failing call on the same thread. */
+const char *mlm_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* lens                                                                      */
+/* ------------------------------------------------------------------------ */
+
+enum { MLM_SHEET_CIRCLE = 0, MLM_SHEET_NONE = 1 };
+
+/*
+ * Macro model and microlens field (sec. 2.1-2.2, 3.1).
+ *   kappa_star   convergence in microlenses, >= 0.  With MLM_SHEET_CIRCLE the
+ *                stars are taken to fill a disc of radius
+ *                R_* = sqrt(sum m_i / kappa_star), the compensating sheet is
+ *                a_s = -kappa_* z for |z| <= R_* and -kappa_* R_*^2 / conj(z)
+ *                outside (sec. 3.1, both branches of its footnote).
+ *   kappa_smooth smooth convergence; kappa = kappa_star + kappa_smooth.
+ *   gamma        external shear, real (the frame is rotated onto it, sec. 2.1).
+ *   sheet        MLM_SHEET_CIRCLE or MLM_SHEET_NONE (no compensating sheet:
+ *                for isolated lenses such as the point lens).
+ */
+typedef struct mlm_lens_params {
+    double kappa_star;
+    double kappa_smooth;
+    double gamma;
+    int32_t sheet;
+    int32_t reserved;
+} mlm_lens_params;
+
+typedef struct mlm_lens mlm_lens;
+
+/*
+ * Create a lens from a star field: x[i], y[i] position (theta_*), m[i] > 0
+ * mass, i < n, n >= 0.  With device_ptrs != 0 the three arrays are device
+ * pointers, else host pointers; either way they are copied.  The stars are
+ * kept resident in device memory for the lens's lifetime.
+ * Errors: MLM_EINVAL for NULL out, n < 0, non-finite values, m <= 0,
+ * kappa_star < 0 (or kappa_star == 0 with stars and a sheet); MLM_ENOMEM;
+ * MLM_EDEVICE.
+ */
+mlm_status mlm_lens_create(const mlm_lens_params *params, const double *x, const double *y,
+                           const double *m, int64_t n, int32_t device_ptrs, mlm_lens **out);
+
+/* Release a lens (NULL is accepted). */
+void mlm_lens_destroy(mlm_lens *lens);
+
+/* Derived lens quantities (sec. 2.1, 3.1). */
+typedef struct mlm_lens_info {
+    int64_t n_stars;
+    double mass_sum;      /* sum m_i */
+    double mean_m;        /* <m> */
+    double mean_m2;       /* <m^2> */
+    double r_star;        /* radius of the star disc, sqrt(sum m / kappa_*) */
+    double kappa;         /* kappa_* + kappa_s */
+    double mu_macro;      /* 1 / ((1-kappa)^2 - gamma^2) */
+    double max_abs;       /* max over stars of max(|x|, |y|) */
+} mlm_lens_info;
+
+mlm_status mlm_lens_get_info(const mlm_lens *lens, mlm_lens_info *out);
+
+/* ------------------------------------------------------------------------ */
+/* map request                                                               */
+/* ------------------------------------------------------------------------ */
+
+enum { MLM_PREC_FP64 = 0, MLM_PREC_MIXED = 1 };
+enum { MLM_METHOD_FMM = 0, MLM_METHOD_DIRECT = 1 };
+
+/*
+ * Map request.  Fill with mlm_map_request_init() and override fields.
+ *
+ *   y1c, y2c       source-plane map centre (Y1, Y2)                  (sec. 2.3)
+ *   hw1, hw2       map half-widths (dY1, dY2) > 0
+ *   n1, n2         pixels along y1 and y2, >= 1
+ *   rays_per_pixel ray-grid density "in the absence of lensing": cell side
+ *                  pix_i / sqrt(rho) (sec. 4), default 1
+ *   nray1, nray2   explicit ray-grid vertex counts (> 1 both), spanning
+ *                  exactly [X - dX, X + dX]; 0 = derive from rays_per_pixel
+ *   flux_fraction  f of appendix A: border r = sqrt(kappa_* <m^2> / (f <m>)),
+ *                  default 0.01
+ *   dx1, dx2       explicit image-plane half-sizes of the shooting region;
+ *                  0 = (dY_i + r) / |1 - kappa +- gamma| (sec. 2.3)
+ *   order          FMM expansion order p in [1, 31]; 0 = the rule of
+ *                  appendix C.3 with the accuracy `eps`
+ *   leaf_max       maximum stars in a node's 3x3 block of same-level
+ *                  squares before it is divided (app. C.1), default 32
+ *   max_level      deepest tree level, default and maximum 24
+ *   precision      MLM_PREC_FP64 (everything in double); MLM_PREC_MIXED is
+ *                  reserved and returns MLM_ENOTSUP in this build
+ *   method         MLM_METHOD_FMM or MLM_METHOD_DIRECT (every star summed
+ *                  for every ray; the no-FMM reference of sec. 4)
+ *   device_out     != 0: `mu` (and `w_out`) are device pointers
+ *   eps            absolute deflection accuracy for the automatic order,
+ *                  default 1e-7
+ *   row_begin,     map only the ray-grid cell rows [row_begin, row_end);
+ *   row_end        row_end < 0 means all rows.  Maps are additive over
+ *                  disjoint row ranges.
+ *   stream         hipStream_t to run on (NULL: the default stream).  The
+ *                  call returns after the work on it has completed.
+ *   w_out          optional: receives the mapped source positions (y1, y2)
+ *                  of the vertex rows row_begin .. row_end (inclusive),
+ *                  nray1 per row, interleaved doubles (2 * nr1 * rows).
+ *   timing         != 0: record device times of each stage into the stats
+ */
+typedef struct mlm_map_request {
+    double y1c, y2c, hw1, hw2;
+    int32_t n1, n2;
+    double rays_per_pixel;
+    int32_t nray1, nray2;
+    double flux_fraction;
+    double dx1, dx2;
+    int32_t order;
+    int32_t leaf_max;
+    int32_t max_level;
+    int32_t precision;
+    int32_t method;
+    int32_t device_out;
+    double eps;
+    int64_t row_begin, row_end;
+    void *stream;
+    double *w_out;
+    int32_t timing;
+    int32_t reserved;
+} mlm_map_request;
+
+void mlm_map_request_init(mlm_map_request *req);
+
+/* Shooting region, ray grid and tree root of a request (sec. 2.3, app. A). */
+typedef struct mlm_region {
+    double lam1, lam2;      /* 1 - kappa + gamma, 1 - kappa - gamma */
+    double mu_macro;
+    double border;          /* r of appendix A */
+    double X1, X2;          /* shooting-region centre */
+    double dX1, dX2;        /* shooting-region half-sizes */
+    double pix1, pix2;      /* pixel sides */
+    double d1, d2;          /* ray-grid spacing */
+    double x0, y0;          /* position of vertex (0, 0); vertex (a, b) is
+                               (x0 + a d1, y0 + b d2) */
+    double L0;              /* half-length of the tree's root square (power of 2) */
+    int64_t nr1, nr2;       /* ray-grid vertices per row / per column */
+    int32_t order;          /* expansion order the map would use (0 if it needs the tree) */
+    int32_t reserved;
+} mlm_region;
+
+/* Compute the region of a request without mapping.  Errors as mlm_map. */
+mlm_status mlm_map_region(const mlm_lens *lens, const mlm_map_request *req, mlm_region *out);
+
+typedef struct mlm_map_stats {
+    int64_t n_rays;          /* grid vertices shot */
+    int64_t n_cells;         /* grid cells apportioned (2 triangles each) */
+    int64_t n_skipped;       /* triangles skipped for a non-finite vertex */
+    int64_t n_nodes, n_leaves;
+    int32_t n_levels, order;
+    int64_t near_pairs;      /* ray-star pairs summed directly */
+    int64_t n_tiles;         /* ray tiles launched */
+    double tri_area;         /* image-plane area of one triangle, d1 d2 / 2 */
+    double t_tree_ms;        /* sort + tree + lists (device time, if timing) */
+    double t_fmm_ms;         /* P2M, M2M, M2L/P2L/L2L, leaf tables */
+    double t_shoot_ms;       /* ray shooting kernels */
+    double t_ipm_ms;         /* IPM kernels */
+    double t_total_ms;       /* whole call, device time */
+    int32_t n_shoot_launches, n_ipm_launches;
+} mlm_map_stats;
+
+/*
+ * Magnification map (sec. 3.2): mu[j * n1 + i] is the magnification of pixel
+ * (i, j) = [y1c - hw1 + i pix1, +pix1) x [y2c - hw2 + j pix2, +pix2), i.e.
+ * row-major with rows along y2 ascending.  `mu` (n1 * n2 doubles, caller
+ * owned, host or device per req->device_out) is overwritten.  stats may be
+ * NULL.
+ * Errors: MLM_EINVAL (bad request), MLM_EDEGENERATE (|1-kappa+-gamma| < 1e-9),
+ * MLM_ERANGE (grid larger than 2^31 vertices per row or 2^31 rows),
+ * MLM_ENOMEM, MLM_EDEVICE, MLM_ENOTSUP.
+ */
+mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_stats *stats);
+
+/*
+ * Source positions w(z) of arbitrary image-plane points through the same
+ * FMM (or direct sum) the map uses (sec. 2.2, app. C): z_xy and w_xy are n
+ * interleaved (x1, x2) pairs, host or device per req->device_out.  Points
+ * outside the tree's root square (mlm_map_region's L0) give MLM_ERANGE.
+ */
+mlm_status mlm_deflect(mlm_lens *lens, const mlm_map_request *req, const double *z_xy, int64_t n,
+                       double *w_xy);
+
+/*
+ * Export of the FMM tree and coefficients built for a request (app. C), for
+ * inspection and parity checks.  Host buffers of capacity `cap` nodes; the
+ * call fails with MLM_ERANGE if the tree has more nodes (info is still
+ * filled).  Per node q: level, square indices (ix, iy) at that level, leaf
+ * flag, stars in the node, stars in its 3x3 block; mult and local hold the
+ * (order + 1) multipole and Taylor coefficients as interleaved (re, im)
+ * doubles, in units of the node half-length (local[0] is not formed and is
+ * zero).  Any output pointer may be NULL.
+ */
+typedef struct mlm_tree_info {
+    int64_t n_nodes, n_leaves;
+    int32_t n_levels, order;
+    double L0;
+} mlm_tree_info;
+
+mlm_status mlm_fmm_export(mlm_lens *lens, const mlm_map_request *req, mlm_tree_info *info,
+                          int32_t *level, int64_t *ix, int64_t *iy, int32_t *leaf, int64_t *nstars,
+                          int64_t *block, double *mult, double *local, int64_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLMAP_H */

@@ -217,8 +217,11 @@ class FMM:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            lib().orc_fmm_free(h)
+        if h and _lib is not None:
+            try:
+                _lib.orc_fmm_free(h)
+            except Exception:
+                pass
             self._h = None
 
     @property

@@ -1,0 +1,263 @@
+"""Python binding of libmlmap (MI355X microlensing magnification maps).
+
+Argument marshalling only: every step of a map runs in the HIP library
+(``libmlmap.so``, built in-tree by ``paper_2506_02114_amd._build``).  Arrays
+may be numpy arrays (host) or torch tensors on a HIP device (device); the
+binding passes their pointers and a flag saying which they are.  If the
+library is not built, importing the binding's entry points raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmlmap.so")
+
+MLM_OK, MLM_EINVAL, MLM_EDEGENERATE, MLM_ERANGE, MLM_ENOMEM, MLM_EDEVICE, MLM_ENOTSUP = range(7)
+SHEET_CIRCLE, SHEET_NONE = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
+METHOD_FMM, METHOD_DIRECT = 0, 1
+
+EXPORTED = [
+    "mlm_abi_version", "mlm_status_str", "mlm_last_error", "mlm_lens_create", "mlm_lens_destroy",
+    "mlm_lens_get_info", "mlm_map_request_init", "mlm_map_region", "mlm_map", "mlm_deflect",
+    "mlm_fmm_export",
+]
+
+
+class MLMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_lib().mlm_status_str(status).decode()}: {msg}")
+        self.status = status
+
+
+class LensParams(C.Structure):
+    _fields_ = [("kappa_star", C.c_double), ("kappa_smooth", C.c_double), ("gamma", C.c_double),
+                ("sheet", C.c_int32), ("reserved", C.c_int32)]
+
+
+class LensInfo(C.Structure):
+    _fields_ = [("n_stars", C.c_int64), ("mass_sum", C.c_double), ("mean_m", C.c_double),
+                ("mean_m2", C.c_double), ("r_star", C.c_double), ("kappa", C.c_double),
+                ("mu_macro", C.c_double), ("max_abs", C.c_double)]
+
+
+class MapRequest(C.Structure):
+    _fields_ = [("y1c", C.c_double), ("y2c", C.c_double), ("hw1", C.c_double), ("hw2", C.c_double),
+                ("n1", C.c_int32), ("n2", C.c_int32), ("rays_per_pixel", C.c_double),
+                ("nray1", C.c_int32), ("nray2", C.c_int32), ("flux_fraction", C.c_double),
+                ("dx1", C.c_double), ("dx2", C.c_double), ("order", C.c_int32), ("leaf_max", C.c_int32),
+                ("max_level", C.c_int32), ("precision", C.c_int32), ("method", C.c_int32),
+                ("device_out", C.c_int32), ("eps", C.c_double), ("row_begin", C.c_int64),
+                ("row_end", C.c_int64), ("stream", C.c_void_p), ("w_out", C.c_void_p),
+                ("timing", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Region(C.Structure):
+    _fields_ = [("lam1", C.c_double), ("lam2", C.c_double), ("mu_macro", C.c_double), ("border", C.c_double),
+                ("X1", C.c_double), ("X2", C.c_double), ("dX1", C.c_double), ("dX2", C.c_double),
+                ("pix1", C.c_double), ("pix2", C.c_double), ("d1", C.c_double), ("d2", C.c_double),
+                ("x0", C.c_double), ("y0", C.c_double), ("L0", C.c_double), ("nr1", C.c_int64),
+                ("nr2", C.c_int64), ("order", C.c_int32), ("reserved", C.c_int32)]
+
+
+class MapStats(C.Structure):
+    _fields_ = [("n_rays", C.c_int64), ("n_cells", C.c_int64), ("n_skipped", C.c_int64),
+                ("n_nodes", C.c_int64), ("n_leaves", C.c_int64), ("n_levels", C.c_int32),
+                ("order", C.c_int32), ("near_pairs", C.c_int64), ("n_tiles", C.c_int64),
+                ("tri_area", C.c_double), ("t_tree_ms", C.c_double), ("t_fmm_ms", C.c_double),
+                ("t_shoot_ms", C.c_double), ("t_ipm_ms", C.c_double), ("t_total_ms", C.c_double),
+                ("n_shoot_launches", C.c_int32), ("n_ipm_launches", C.c_int32)]
+
+
+class TreeInfo(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("n_leaves", C.c_int64), ("n_levels", C.c_int32),
+                ("order", C.c_int32), ("L0", C.c_double)]
+
+
+def _asdict(s: C.Structure) -> dict:
+    return {k: getattr(s, k) for k, _ in s._fields_ if k != "reserved"}
+
+
+_L = None
+
+
+def _lib():
+    """Load libmlmap.so; raises if it has not been built (no fallback path)."""
+    global _L
+    if _L is not None:
+        return _L
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2506_02114_amd._build.build()")
+    L = C.CDLL(LIB_PATH)
+    vp, i64, i32, dp = C.c_void_p, C.c_int64, C.c_int32, C.POINTER(C.c_double)
+    L.mlm_abi_version.restype = i32
+    L.mlm_status_str.argtypes = [C.c_int]
+    L.mlm_status_str.restype = C.c_char_p
+    L.mlm_last_error.restype = C.c_char_p
+    L.mlm_lens_create.argtypes = [C.POINTER(LensParams), vp, vp, vp, i64, i32, C.POINTER(vp)]
+    L.mlm_lens_create.restype = C.c_int
+    L.mlm_lens_destroy.argtypes = [vp]
+    L.mlm_lens_destroy.restype = None
+    L.mlm_lens_get_info.argtypes = [vp, C.POINTER(LensInfo)]
+    L.mlm_lens_get_info.restype = C.c_int
+    L.mlm_map_request_init.argtypes = [C.POINTER(MapRequest)]
+    L.mlm_map_request_init.restype = None
+    L.mlm_map_region.argtypes = [vp, C.POINTER(MapRequest), C.POINTER(Region)]
+    L.mlm_map_region.restype = C.c_int
+    L.mlm_map.argtypes = [vp, C.POINTER(MapRequest), vp, C.POINTER(MapStats)]
+    L.mlm_map.restype = C.c_int
+    L.mlm_deflect.argtypes = [vp, C.POINTER(MapRequest), vp, i64, vp]
+    L.mlm_deflect.restype = C.c_int
+    L.mlm_fmm_export.argtypes = [vp, C.POINTER(MapRequest), C.POINTER(TreeInfo), vp, vp, vp, vp, vp, vp, vp, vp, i64]
+    L.mlm_fmm_export.restype = C.c_int
+    _L = L
+    return L
+
+
+def load():
+    return _lib()
+
+
+def _check(st: int):
+    if st != MLM_OK:
+        raise MLMError(st, _lib().mlm_last_error().decode())
+
+
+def _is_torch_cuda(a) -> bool:
+    return type(a).__module__.startswith("torch") and getattr(a, "is_cuda", False)
+
+
+def _current_stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+REQUEST_KEYS = {k for k, _ in MapRequest._fields_} - {"stream", "w_out", "device_out", "reserved"}
+
+
+def make_request(**kw) -> MapRequest:
+    r = MapRequest()
+    _lib().mlm_map_request_init(C.byref(r))
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = {"fp64": PREC_FP64, "mixed": PREC_MIXED}[v]
+        if k == "method" and isinstance(v, str):
+            v = {"fmm": METHOD_FMM, "direct": METHOD_DIRECT}[v]
+        if k == "rows":
+            if v is not None:
+                r.row_begin, r.row_end = int(v[0]), int(v[1])
+            continue
+        if k not in REQUEST_KEYS:
+            raise TypeError(f"unknown map request field {k!r}")
+        setattr(r, k, v)
+    return r
+
+
+class Lens:
+    """Macro model + star field resident on the GPU (see mlm_lens_create)."""
+
+    def __init__(self, kappa_star: float, kappa_smooth: float, gamma: float, x, y, m, sheet: bool = True):
+        L = _lib()
+        self._h = C.c_void_p()
+        p = LensParams(kappa_star, kappa_smooth, gamma, SHEET_CIRCLE if sheet else SHEET_NONE, 0)
+        if _is_torch_cuda(x):
+            import torch
+            x, y, m = (t.to(torch.float64).contiguous() for t in (x, y, m))
+            n = x.numel()
+            _check(L.mlm_lens_create(C.byref(p), C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                     C.c_void_p(m.data_ptr()), n, 1, C.byref(self._h)))
+        else:
+            x, y, m = (np.ascontiguousarray(a, dtype=np.float64) for a in (x, y, m))
+            n = x.size
+            _check(L.mlm_lens_create(C.byref(p), x.ctypes.data_as(C.c_void_p), y.ctypes.data_as(C.c_void_p),
+                                     m.ctypes.data_as(C.c_void_p), n, 0, C.byref(self._h)))
+        self.n = n
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib().mlm_lens_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        I = LensInfo()
+        _check(_lib().mlm_lens_get_info(self._h, C.byref(I)))
+        return _asdict(I)
+
+    def region(self, **req) -> dict:
+        r = make_request(**req)
+        R = Region()
+        _check(_lib().mlm_map_region(self._h, C.byref(r), C.byref(R)))
+        return _asdict(R)
+
+    def map(self, out=None, w_out=None, stream=None, **req):
+        """Magnification map, (n2, n1) row-major.  `out` may be a float64 torch
+        tensor on the GPU (the map stays on the device) or None (host numpy)."""
+        r = make_request(**req)
+        device = out is not None and _is_torch_cuda(out)
+        if out is None:
+            out = np.empty((r.n2, r.n1), dtype=np.float64)
+        if device:
+            import torch
+            assert out.dtype == torch.float64 and out.is_contiguous() and out.numel() == r.n1 * r.n2
+            r.device_out = 1
+            r.stream = stream if stream is not None else _current_stream()
+            ptr = C.c_void_p(out.data_ptr())
+            if w_out is not None:
+                assert _is_torch_cuda(w_out) and w_out.dtype == torch.float64 and w_out.is_contiguous()
+                r.w_out = C.c_void_p(w_out.data_ptr())
+        else:
+            assert out.dtype == np.float64 and out.flags.c_contiguous and out.size == r.n1 * r.n2
+            ptr = out.ctypes.data_as(C.c_void_p)
+            if w_out is not None:
+                assert isinstance(w_out, np.ndarray) and w_out.dtype == np.float64 and w_out.flags.c_contiguous
+                r.w_out = w_out.ctypes.data_as(C.c_void_p)
+        s = MapStats()
+        _check(_lib().mlm_map(self._h, C.byref(r), ptr, C.byref(s)))
+        return out, _asdict(s)
+
+    def deflect(self, z, stream=None, **req):
+        """Source positions w of image-plane points z ((n, 2) float64)."""
+        r = make_request(**req)
+        if _is_torch_cuda(z):
+            import torch
+            z = z.to(torch.float64).contiguous()
+            w = torch.empty_like(z)
+            r.device_out = 1
+            r.stream = stream if stream is not None else _current_stream()
+            _check(_lib().mlm_deflect(self._h, C.byref(r), C.c_void_p(z.data_ptr()), z.shape[0],
+                                      C.c_void_p(w.data_ptr())))
+            return w
+        z = np.ascontiguousarray(z, dtype=np.float64).reshape(-1, 2)
+        w = np.empty_like(z)
+        _check(_lib().mlm_deflect(self._h, C.byref(r), z.ctypes.data_as(C.c_void_p), z.shape[0],
+                                  w.ctypes.data_as(C.c_void_p)))
+        return w
+
+    def fmm_export(self, **req) -> dict:
+        r = make_request(**req)
+        I = TreeInfo()
+        st = _lib().mlm_fmm_export(self._h, C.byref(r), C.byref(I), None, None, None, None, None, None, None,
+                                   None, 0)
+        if st not in (MLM_OK, MLM_ERANGE):
+            _check(st)
+        n, P1 = I.n_nodes, I.order + 1
+        level = np.empty(n, np.int32); ix = np.empty(n, np.int64); iy = np.empty(n, np.int64)
+        leaf = np.empty(n, np.int32); ns = np.empty(n, np.int64); blk = np.empty(n, np.int64)
+        mult = np.empty(2 * n * P1); loc = np.empty(2 * n * P1)
+        ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+        _check(_lib().mlm_fmm_export(self._h, C.byref(r), C.byref(I), ptr(level), ptr(ix), ptr(iy), ptr(leaf),
+                                     ptr(ns), ptr(blk), ptr(mult), ptr(loc), n))
+        return dict(info=_asdict(I), level=level, i=ix, j=iy, leaf=leaf, nstars=ns, block=blk,
+                    mult=mult.view(np.complex128).reshape(n, P1), local=loc.view(np.complex128).reshape(n, P1))

@@ -1,0 +1,548 @@
+// C ABI of the library and the orchestration of a map.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "dev.hpp"
+
+namespace mlm {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void fail(mlm_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    throw Error{st, buf};
+}
+
+void *DevBuf::reserve(size_t bytes)
+{
+    if (p && bytes <= cap) return p;
+    if (p) {
+        MLM_HIP(hipDeviceSynchronize());   // the old buffer may still be in use by queued work
+        MLM_HIP(hipFree(p));
+        p = nullptr;
+        cap = 0;
+    }
+    size_t c = bytes + bytes / 4;
+    if (c < 256) c = 256;
+    MLM_HIP(hipMalloc(&p, c));
+    cap = c;
+    return p;
+}
+
+void DevBuf::release()
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+}
+
+Workspace::~Workspace()
+{
+    if (pinned) (void)hipHostFree(pinned);
+}
+
+void *pinned(mlm_lens *lens, size_t bytes)
+{
+    Workspace &ws = lens->ws;
+    if (ws.pinned && bytes <= ws.pinned_cap) return ws.pinned;
+    if (ws.pinned) {
+        MLM_HIP(hipDeviceSynchronize());
+        MLM_HIP(hipHostFree(ws.pinned));
+        ws.pinned = nullptr;
+    }
+    size_t c = bytes < 4096 ? 4096 : bytes;
+    MLM_HIP(hipHostMalloc(&ws.pinned, c, hipHostMallocDefault));
+    ws.pinned_cap = c;
+    return ws.pinned;
+}
+
+namespace {
+
+constexpr int64_t STRIP_VERTS = 1ll << 26;   // vertices per strip buffer (1 GiB of double2)
+
+__global__ void k_fill(double *p, int64_t n, double v)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = v;
+}
+
+__global__ void k_zero_u64(unsigned long long *p, int n)
+{
+    if (threadIdx.x < n) p[threadIdx.x] = 0;
+}
+
+// ray-star pairs and rays of a strip (for the statistics)
+__global__ void k_strip_work(int64_t nleaves, const LeafInfo *__restrict__ lv, unsigned long long *cnt)
+{
+    int64_t lf = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long rays = 0, pairs = 0;
+    if (lf < nleaves) {
+        LeafInfo li = lv[lf];
+        if (li.na > 0 && li.nb > 0) {
+            rays = (unsigned long long)li.na * (unsigned long long)li.nb;
+            pairs = rays * (unsigned long long)li.near_cnt;
+        }
+    }
+    if (rays) {
+        atomicAdd(cnt + 1, pairs);
+        atomicAdd(cnt + 2, rays);
+    }
+}
+
+void fill(double *p, int64_t n, double v, hipStream_t st)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+}
+
+struct Timer {
+    bool on;
+    hipStream_t st;
+    std::vector<hipEvent_t> ev;
+    Timer(bool on_, hipStream_t st_) : on(on_), st(st_) {}
+    int mark()
+    {
+        if (!on) return -1;
+        hipEvent_t e;
+        MLM_HIP(hipEventCreate(&e));
+        MLM_HIP(hipEventRecord(e, st));
+        ev.push_back(e);
+        return (int)ev.size() - 1;
+    }
+    double ms(int a, int b) const
+    {
+        if (!on || a < 0 || b < 0) return 0.0;
+        float t = 0;
+        MLM_HIP(hipEventElapsedTime(&t, ev[a], ev[b]));
+        return t;
+    }
+    ~Timer()
+    {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+void check_request(const mlm_map_request *q)
+{
+    if (!q) fail(MLM_EINVAL, "request is NULL");
+    if (q->precision == MLM_PREC_MIXED) fail(MLM_ENOTSUP, "mixed precision is not available in this build");
+    if (q->precision != MLM_PREC_FP64) fail(MLM_EINVAL, "unknown precision %d", q->precision);
+    if (q->method != MLM_METHOD_FMM && q->method != MLM_METHOD_DIRECT) fail(MLM_EINVAL, "unknown method %d", q->method);
+    if (q->order < 0 || q->order > MAX_ORDER) fail(MLM_EINVAL, "order %d outside [0, %d]", q->order, MAX_ORDER);
+    if (q->leaf_max < 0 || q->max_level < 0 || q->max_level > KEY_BITS)
+        fail(MLM_EINVAL, "leaf_max must be >= 0 and max_level in [0, %d]", KEY_BITS);
+    if (!(q->eps >= 0) || !std::isfinite(q->eps)) fail(MLM_EINVAL, "eps must be finite and >= 0");
+}
+
+// tree + FMM + leaf tables for a request
+void prepare_fmm(mlm_lens *lens, const Region &R, const mlm_map_request &q, Tree &T, hipStream_t st)
+{
+    build_tree(lens, R, q, T, st);
+    int p = q.order;
+    if (p <= 0) {
+        double Lmin = std::ldexp(R.L0, -(T.nlevels - 1));
+        p = auto_order(R.mean_m, R.mean_m2, Lmin, q.eps > 0 ? q.eps : 1e-7);
+    }
+    run_fmm(lens, T, p, st);
+    build_leaf_tables(lens, T, st);
+}
+
+hipStream_t stream_of(const mlm_map_request *q) { return q ? static_cast<hipStream_t>(q->stream) : nullptr; }
+
+}  // namespace
+}  // namespace mlm
+
+using namespace mlm;
+
+#define API_BEGIN try {
+#define API_END                                                        \
+    }                                                                  \
+    catch (const Error &e)                                             \
+    {                                                                  \
+        g_last_error = e.msg;                                          \
+        return e.status;                                               \
+    }                                                                  \
+    catch (const std::bad_alloc &)                                     \
+    {                                                                  \
+        g_last_error = "host allocation failed";                       \
+        return MLM_ENOMEM;                                             \
+    }                                                                  \
+    catch (...)                                                        \
+    {                                                                  \
+        g_last_error = "unexpected internal error";                    \
+        return MLM_EDEVICE;                                            \
+    }                                                                  \
+    return MLM_OK;
+
+extern "C" {
+
+int32_t mlm_abi_version(void) { return MLM_ABI_VERSION; }
+
+const char *mlm_status_str(mlm_status s)
+{
+    switch (s) {
+    case MLM_OK: return "MLM_OK";
+    case MLM_EINVAL: return "MLM_EINVAL";
+    case MLM_EDEGENERATE: return "MLM_EDEGENERATE";
+    case MLM_ERANGE: return "MLM_ERANGE";
+    case MLM_ENOMEM: return "MLM_ENOMEM";
+    case MLM_EDEVICE: return "MLM_EDEVICE";
+    case MLM_ENOTSUP: return "MLM_ENOTSUP";
+    }
+    return "MLM_UNKNOWN";
+}
+
+const char *mlm_last_error(void) { return g_last_error.c_str(); }
+
+void mlm_map_request_init(mlm_map_request *r)
+{
+    if (!r) return;
+    std::memset(r, 0, sizeof *r);
+    r->hw1 = r->hw2 = 1.0;
+    r->n1 = r->n2 = 1;
+    r->rays_per_pixel = 1.0;
+    r->flux_fraction = 0.01;
+    r->leaf_max = 32;
+    r->max_level = KEY_BITS;
+    r->precision = MLM_PREC_FP64;
+    r->method = MLM_METHOD_FMM;
+    r->eps = 1e-7;
+    r->row_begin = 0;
+    r->row_end = -1;
+}
+
+mlm_status mlm_lens_create(const mlm_lens_params *params, const double *x, const double *y, const double *m,
+                           int64_t n, int32_t device_ptrs, mlm_lens **out)
+{
+    mlm_lens *L = nullptr;
+    API_BEGIN
+    if (!params || !out) fail(MLM_EINVAL, "params and out must not be NULL");
+    if (n < 0) fail(MLM_EINVAL, "n must be >= 0");
+    if (n > 0 && (!x || !y || !m)) fail(MLM_EINVAL, "star arrays must not be NULL");
+    if (n >= (int64_t)INT32_MAX / 2) fail(MLM_ERANGE, "too many stars");
+    const mlm_lens_params &P = *params;
+    if (!std::isfinite(P.kappa_star) || !std::isfinite(P.kappa_smooth) || !std::isfinite(P.gamma))
+        fail(MLM_EINVAL, "kappa_star, kappa_smooth, gamma must be finite");
+    if (P.kappa_star < 0) fail(MLM_EINVAL, "kappa_star must be >= 0");
+    if (P.sheet != MLM_SHEET_CIRCLE && P.sheet != MLM_SHEET_NONE) fail(MLM_EINVAL, "unknown sheet %d", P.sheet);
+    if (n > 0 && P.sheet == MLM_SHEET_CIRCLE && P.kappa_star == 0)
+        fail(MLM_EINVAL, "a compensating sheet needs kappa_star > 0");
+    std::vector<double> hx(n), hy(n), hm(n);
+    if (n > 0 && device_ptrs) {
+        MLM_HIP(hipMemcpy(hx.data(), x, n * sizeof(double), hipMemcpyDeviceToHost));
+        MLM_HIP(hipMemcpy(hy.data(), y, n * sizeof(double), hipMemcpyDeviceToHost));
+        MLM_HIP(hipMemcpy(hm.data(), m, n * sizeof(double), hipMemcpyDeviceToHost));
+    } else if (n > 0) {
+        std::memcpy(hx.data(), x, n * sizeof(double));
+        std::memcpy(hy.data(), y, n * sizeof(double));
+        std::memcpy(hm.data(), m, n * sizeof(double));
+    }
+    double s1 = 0.0, s2 = 0.0, amax = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!std::isfinite(hx[i]) || !std::isfinite(hy[i]) || !std::isfinite(hm[i]) || !(hm[i] > 0))
+            fail(MLM_EINVAL, "star %lld has a non-finite position or a mass <= 0", (long long)i);
+        s1 += hm[i];
+        s2 += hm[i] * hm[i];
+        if (std::fabs(hx[i]) > amax) amax = std::fabs(hx[i]);
+        if (std::fabs(hy[i]) > amax) amax = std::fabs(hy[i]);
+    }
+    L = new mlm_lens();
+    L->params = P;
+    L->n = n;
+    MLM_HIP(hipGetDevice(&L->device));
+    L->mass_sum = s1;
+    L->mass2_sum = s2;
+    L->max_abs = amax;
+    L->r_star = (n > 0 && P.kappa_star > 0) ? std::sqrt(s1 / P.kappa_star) : 0.0;
+    size_t bytes = (size_t)(n > 0 ? n : 1) * sizeof(double);
+    MLM_HIP(hipMalloc(&L->d_x, bytes));
+    MLM_HIP(hipMalloc(&L->d_y, bytes));
+    MLM_HIP(hipMalloc(&L->d_m, bytes));
+    if (n > 0) {
+        MLM_HIP(hipMemcpy(L->d_x, hx.data(), n * sizeof(double), hipMemcpyHostToDevice));
+        MLM_HIP(hipMemcpy(L->d_y, hy.data(), n * sizeof(double), hipMemcpyHostToDevice));
+        MLM_HIP(hipMemcpy(L->d_m, hm.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    }
+    *out = L;
+    L = nullptr;
+    }
+    catch (const Error &e) {
+        mlm_lens_destroy(L);
+        g_last_error = e.msg;
+        return e.status;
+    }
+    catch (const std::bad_alloc &) {
+        mlm_lens_destroy(L);
+        g_last_error = "host allocation failed";
+        return MLM_ENOMEM;
+    }
+    return MLM_OK;
+}
+
+void mlm_lens_destroy(mlm_lens *lens)
+{
+    if (!lens) return;
+    (void)hipDeviceSynchronize();
+    if (lens->d_x) (void)hipFree(lens->d_x);
+    if (lens->d_y) (void)hipFree(lens->d_y);
+    if (lens->d_m) (void)hipFree(lens->d_m);
+    delete lens;
+}
+
+mlm_status mlm_lens_get_info(const mlm_lens *lens, mlm_lens_info *out)
+{
+    API_BEGIN
+    if (!lens || !out) fail(MLM_EINVAL, "lens and out must not be NULL");
+    mlm_lens_info I{};
+    I.n_stars = lens->n;
+    I.mass_sum = lens->mass_sum;
+    I.mean_m = lens->n ? lens->mass_sum / (double)lens->n : 0.0;
+    I.mean_m2 = lens->n ? lens->mass2_sum / (double)lens->n : 0.0;
+    I.r_star = lens->r_star;
+    I.kappa = lens->params.kappa_star + lens->params.kappa_smooth;
+    double l1 = 1.0 - I.kappa + lens->params.gamma, l2 = 1.0 - I.kappa - lens->params.gamma;
+    I.mu_macro = 1.0 / (l1 * l2);
+    I.max_abs = lens->max_abs;
+    *out = I;
+    API_END
+}
+
+mlm_status mlm_map_region(const mlm_lens *lens, const mlm_map_request *req, mlm_region *out)
+{
+    API_BEGIN
+    if (!lens || !out) fail(MLM_EINVAL, "lens and out must not be NULL");
+    check_request(req);
+    Region R{};
+    setup_region(lens, req, &R);
+    mlm_region o{};
+    o.lam1 = R.lam1;
+    o.lam2 = R.lam2;
+    o.mu_macro = R.mu_macro;
+    o.border = R.border;
+    o.X1 = R.X1;
+    o.X2 = R.X2;
+    o.dX1 = R.dX1;
+    o.dX2 = R.dX2;
+    o.pix1 = R.pix1;
+    o.pix2 = R.pix2;
+    o.d1 = R.d1;
+    o.d2 = R.d2;
+    o.x0 = R.x0;
+    o.y0 = R.y0;
+    o.L0 = R.L0;
+    o.nr1 = R.nr1;
+    o.nr2 = R.nr2;
+    o.order = req->order;
+    *out = o;
+    API_END
+}
+
+mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_stats *stats)
+{
+    API_BEGIN
+    if (!lens || !mu) fail(MLM_EINVAL, "lens and mu must not be NULL");
+    check_request(req);
+    std::lock_guard<std::mutex> guard(lens->mu);
+    const mlm_map_request &q = *req;
+    Region R{};
+    setup_region(lens, req, &R);
+    int64_t cb0 = q.row_begin > 0 ? q.row_begin : 0;
+    int64_t cb1 = q.row_end < 0 ? R.nr2 - 1 : q.row_end;
+    if (cb0 > cb1 || cb1 > R.nr2 - 1) fail(MLM_EINVAL, "cell rows [%lld, %lld) outside [0, %lld)", (long long)cb0,
+                                           (long long)cb1, (long long)(R.nr2 - 1));
+    Workspace &ws = lens->ws;
+    hipStream_t st = stream_of(req);
+    Timer tm(q.timing != 0, st);
+    int e_start = tm.mark();
+
+    int64_t npix = (int64_t)q.n1 * q.n2;
+    double *map = q.device_out ? mu : static_cast<double *>(ws.map.reserve(npix * sizeof(double)));
+    fill(map, npix, 0.0, st);
+    unsigned long long *cnt = static_cast<unsigned long long *>(ws.counters.reserve(8 * sizeof(unsigned long long)));
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, cnt, 8);
+
+    Tree T;
+    const bool fmm = q.method == MLM_METHOD_FMM;
+    int e_tree = -1, e_fmm = -1;
+    if (fmm) {
+        build_tree(lens, R, q, T, st);
+        e_tree = tm.mark();
+        int p = q.order;
+        if (p <= 0) p = auto_order(R.mean_m, R.mean_m2, std::ldexp(R.L0, -(T.nlevels - 1)), q.eps > 0 ? q.eps : 1e-7);
+        run_fmm(lens, T, p, st);
+        build_leaf_tables(lens, T, st);
+        e_fmm = tm.mark();
+    }
+
+    MapGeom g;
+    g.ylo1 = q.y1c - q.hw1;
+    g.ylo2 = q.y2c - q.hw2;
+    g.pix1 = R.pix1;
+    g.pix2 = R.pix2;
+    g.n1 = q.n1;
+    g.n2 = q.n2;
+    g.tri_weight = 0.5 * R.d1 * R.d2 / (R.pix1 * R.pix2);
+    LensConst lc = lens_const(lens, R);
+
+    int64_t rows_per_strip = STRIP_VERTS / R.nr1;
+    if (rows_per_strip < 2) rows_per_strip = 2;
+    int64_t nbuf = rows_per_strip * R.nr1;
+    int64_t vrows = cb1 - cb0 + 1;
+    if (vrows < rows_per_strip) nbuf = vrows * R.nr1;
+    double2 *verts = static_cast<double2 *>(ws.verts.reserve((size_t)nbuf * sizeof(double2)));
+    double *wdev = nullptr;
+    if (q.w_out) wdev = q.device_out ? q.w_out : static_cast<double *>(ws.wbuf.reserve((size_t)nbuf * sizeof(double2)));
+
+    double t_shoot = 0.0, t_ipm = 0.0;
+    int64_t tiles = 0;
+    int nstrips = 0;
+    for (int64_t r0 = cb0; r0 < cb1; ++nstrips) {
+        int64_t r1 = std::min(cb1, r0 + rows_per_strip - 1);   // cells [r0, r1), vertex rows [r0, r1]
+        int64_t vb0 = r0, vb1 = r1 + 1;
+        double *w_here = nullptr;
+        if (wdev) w_here = q.device_out ? wdev + 2 * (vb0 - cb0) * R.nr1 : wdev;
+        int64_t nt = 0;
+        if (fmm) {
+            nt = plan_tiles(lens, T, R, vb0, vb1, st);
+            hipLaunchKernelGGL(k_strip_work, dim3((unsigned)((T.nleaves + 255) / 256)), dim3(256), 0, st, T.nleaves,
+                               T.leaves, cnt);
+        }
+        int ea = tm.mark();
+        if (fmm) launch_shoot(lens, T, R, lc, g, nt, vb0, verts, w_here, st);
+        else launch_shoot_direct(lens, R, lc, g, vb0, vb1, verts, w_here, st);
+        int eb = tm.mark();
+        launch_ipm(verts, R.nr1, r0, r1, vb0, g, map, cnt, st);
+        int ec = tm.mark();
+        if (q.w_out && !q.device_out)
+            MLM_HIP(hipMemcpyAsync(q.w_out + 2 * (vb0 - cb0) * R.nr1, wdev, (size_t)(vb1 - vb0) * R.nr1 * 2 * sizeof(double),
+                                   hipMemcpyDeviceToHost, st));
+        MLM_HIP(hipStreamSynchronize(st));
+        t_shoot += tm.ms(ea, eb);
+        t_ipm += tm.ms(eb, ec);
+        tiles += nt;
+        r0 = r1;
+    }
+    if (!q.device_out) MLM_HIP(hipMemcpyAsync(mu, map, npix * sizeof(double), hipMemcpyDeviceToHost, st));
+    unsigned long long *hc = static_cast<unsigned long long *>(pinned(lens, 8 * sizeof(unsigned long long)));
+    MLM_HIP(hipMemcpyAsync(hc, cnt, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    int e_end = tm.mark();
+    MLM_HIP(hipStreamSynchronize(st));
+    if (stats) {
+        mlm_map_stats S{};
+        S.n_rays = (cb1 - cb0 + 1) * R.nr1;
+        S.n_cells = (cb1 - cb0) * (R.nr1 - 1);
+        S.n_skipped = (int64_t)hc[0];
+        S.n_nodes = T.nnodes;
+        S.n_leaves = T.nleaves;
+        S.n_levels = T.nlevels;
+        S.order = T.p;
+        S.near_pairs = (int64_t)hc[1];
+        S.n_tiles = tiles;
+        S.tri_area = 0.5 * R.d1 * R.d2;
+        S.t_tree_ms = fmm ? tm.ms(e_start, e_tree) : 0.0;
+        S.t_fmm_ms = fmm ? tm.ms(e_tree, e_fmm) : 0.0;
+        S.t_shoot_ms = t_shoot;
+        S.t_ipm_ms = t_ipm;
+        S.t_total_ms = tm.ms(e_start, e_end);
+        S.n_shoot_launches = nstrips;
+        S.n_ipm_launches = nstrips;
+        *stats = S;
+    }
+    API_END
+}
+
+mlm_status mlm_deflect(mlm_lens *lens, const mlm_map_request *req, const double *z_xy, int64_t n, double *w_xy)
+{
+    API_BEGIN
+    if (!lens || (n > 0 && (!z_xy || !w_xy))) fail(MLM_EINVAL, "lens, z and w must not be NULL");
+    if (n < 0) fail(MLM_EINVAL, "n must be >= 0");
+    check_request(req);
+    std::lock_guard<std::mutex> guard(lens->mu);
+    Region R{};
+    setup_region(lens, req, &R);
+    hipStream_t st = stream_of(req);
+    Workspace &ws = lens->ws;
+    const double *zd = z_xy;
+    double *wd = w_xy;
+    if (!req->device_out && n > 0) {
+        double *buf = static_cast<double *>(ws.pts.reserve((size_t)n * 4 * sizeof(double)));
+        MLM_HIP(hipMemcpyAsync(buf, z_xy, n * 2 * sizeof(double), hipMemcpyHostToDevice, st));
+        zd = buf;
+        wd = buf + 2 * n;
+    }
+    if (n > 0) {
+        // every point must lie in the root square
+        std::vector<double> hz(2 * n);
+        MLM_HIP(hipMemcpyAsync(hz.data(), zd, n * 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        MLM_HIP(hipStreamSynchronize(st));
+        for (int64_t i = 0; i < 2 * n; ++i)
+            if (!(std::fabs(hz[i]) < R.L0)) fail(MLM_ERANGE, "point %lld lies outside the root square", (long long)(i / 2));
+    }
+    LensConst lc = lens_const(lens, R);
+    Tree T;
+    if (req->method == MLM_METHOD_FMM) {
+        prepare_fmm(lens, R, *req, T, st);
+        launch_deflect_points(lens, &T, lc, zd, n, wd, st);
+    } else {
+        launch_deflect_points(lens, nullptr, lc, zd, n, wd, st);
+    }
+    if (!req->device_out && n > 0) MLM_HIP(hipMemcpyAsync(w_xy, wd, n * 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    MLM_HIP(hipStreamSynchronize(st));
+    API_END
+}
+
+mlm_status mlm_fmm_export(mlm_lens *lens, const mlm_map_request *req, mlm_tree_info *info, int32_t *level,
+                          int64_t *ix, int64_t *iy, int32_t *leaf, int64_t *nstars, int64_t *block, double *mult,
+                          double *local, int64_t cap)
+{
+    API_BEGIN
+    if (!lens || !info) fail(MLM_EINVAL, "lens and info must not be NULL");
+    check_request(req);
+    std::lock_guard<std::mutex> guard(lens->mu);
+    Region R{};
+    setup_region(lens, req, &R);
+    hipStream_t st = stream_of(req);
+    Tree T;
+    prepare_fmm(lens, R, *req, T, st);
+    MLM_HIP(hipStreamSynchronize(st));
+    mlm_tree_info I{};
+    I.n_nodes = T.nnodes;
+    I.n_leaves = T.nleaves;
+    I.n_levels = T.nlevels;
+    I.order = T.p;
+    I.L0 = T.L0;
+    *info = I;
+    if (T.nnodes > cap) fail(MLM_ERANGE, "tree has %lld nodes, capacity %lld", (long long)T.nnodes, (long long)cap);
+    int64_t N = T.nnodes, P1 = T.p + 1;
+    std::vector<uint64_t> code(N);
+    std::vector<int32_t> lv(N), lf(N), lo(N), hi(N), bk(N);
+    MLM_HIP(hipMemcpy(code.data(), T.code, N * 8, hipMemcpyDeviceToHost));
+    MLM_HIP(hipMemcpy(lv.data(), T.level, N * 4, hipMemcpyDeviceToHost));
+    MLM_HIP(hipMemcpy(lf.data(), T.leaf, N * 4, hipMemcpyDeviceToHost));
+    MLM_HIP(hipMemcpy(lo.data(), T.slo, N * 4, hipMemcpyDeviceToHost));
+    MLM_HIP(hipMemcpy(hi.data(), T.shi, N * 4, hipMemcpyDeviceToHost));
+    MLM_HIP(hipMemcpy(bk.data(), T.block, N * 4, hipMemcpyDeviceToHost));
+    for (int64_t k = 0; k < N; ++k) {
+        if (level) level[k] = lv[k];
+        if (ix) ix[k] = compact_bits(code[k]);
+        if (iy) iy[k] = compact_bits(code[k] >> 1);
+        if (leaf) leaf[k] = lf[k];
+        if (nstars) nstars[k] = hi[k] - lo[k];
+        if (block) block[k] = bk[k];
+    }
+    if (mult) MLM_HIP(hipMemcpy(mult, T.mult, N * P1 * sizeof(double2), hipMemcpyDeviceToHost));
+    if (local) MLM_HIP(hipMemcpy(local, T.local, N * P1 * sizeof(double2), hipMemcpyDeviceToHost));
+    API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// Device helpers shared by the library's kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.hpp"
+
+namespace mlm {
+
+// 2-D Morton interleave: bit b of i goes to bit 2b, bit b of j to bit 2b+1
+__device__ __host__ inline uint64_t spread_bits(uint32_t v)
+{
+    uint64_t x = v;
+    x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
+    x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
+    x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | (x << 2)) & 0x3333333333333333ull;
+    x = (x | (x << 1)) & 0x5555555555555555ull;
+    return x;
+}
+
+__device__ __host__ inline uint32_t compact_bits(uint64_t x)
+{
+    x &= 0x5555555555555555ull;
+    x = (x | (x >> 1)) & 0x3333333333333333ull;
+    x = (x | (x >> 2)) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | (x >> 4)) & 0x00FF00FF00FF00FFull;
+    x = (x | (x >> 8)) & 0x0000FFFF0000FFFFull;
+    x = (x | (x >> 16)) & 0x00000000FFFFFFFFull;
+    return (uint32_t)x;
+}
+
+__device__ __host__ inline uint64_t morton2(uint32_t i, uint32_t j)
+{
+    return spread_bits(i) | (spread_bits(j) << 1);
+}
+
+// square index of coordinate t at the finest level: floor((t + L0) * 2^KEY_BITS / (2 L0)),
+// where scale = 2^KEY_BITS / (2 L0) is a power of two (exact product of the rounded sum)
+__device__ inline uint32_t fine_cell(double t, double L0, double scale)
+{
+    double u = floor((t + L0) * scale);
+    const double top = (double)((1u << KEY_BITS) - 1);
+    u = u < 0.0 ? 0.0 : (u > top ? top : u);
+    return (uint32_t)u;
+}
+
+// first index in sorted a[0, n) with a[k] >= v
+__device__ inline int32_t lower_bound_u64(const uint64_t *a, int32_t n, uint64_t v)
+{
+    int32_t lo = 0, hi = n;
+    while (lo < hi) {
+        int32_t mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <class T>
+__device__ inline int64_t upper_bound_i64(const T *a, int64_t n, T v)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (a[mid] <= v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// complex helpers on double2 (x = real, y = imaginary)
+__device__ __host__ inline double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __host__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __host__ inline double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ inline double2 cinv(double2 a)
+{
+    double r = 1.0 / (a.x * a.x + a.y * a.y);
+    return make_double2(a.x * r, -a.y * r);
+}
+// z^n for n >= 0 by binary powering
+__device__ inline double2 cpowi(double2 z, int n)
+{
+    double2 r = make_double2(1.0, 0.0);
+    while (n) {
+        if (n & 1) r = cmul(r, z);
+        z = cmul(z, z);
+        n >>= 1;
+    }
+    return r;
+}
+
+}  // namespace mlm

@@ -1,0 +1,184 @@
+// Internal declarations of the MI355X magnification-map library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "mlmap.h"
+
+namespace mlm {
+
+// ---------------------------------------------------------------------------
+// errors: thrown inside the library, turned into mlm_status at the C ABI
+// ---------------------------------------------------------------------------
+struct Error {
+    mlm_status status;
+    std::string msg;
+};
+
+[[noreturn]] void fail(mlm_status st, const char *fmt, ...);
+
+#define MLM_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            ::mlm::fail(e_ == hipErrorOutOfMemory ? MLM_ENOMEM : MLM_EDEVICE, "%s: %s", \
+                        #call, hipGetErrorString(e_));                                 \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device buffers that grow on demand and are reused across calls
+// ---------------------------------------------------------------------------
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    void *reserve(size_t bytes);  // contents are not preserved when it grows
+    void release();
+    ~DevBuf() { release(); }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// ---------------------------------------------------------------------------
+// constants of the tree
+// ---------------------------------------------------------------------------
+constexpr int KEY_BITS = 24;     // square index bits per axis at the finest level
+constexpr int MAX_ORDER = 31;    // expansion order limit (32 coefficients)
+constexpr int NLIST = 27;        // interaction squares per node
+constexpr int TILE = 8;          // ray tiles are TILE x TILE grid vertices
+
+// interaction entry of a node: an M2L source node, or the stars of a square
+// lying inside a coarser leaf (P2L), or nothing
+struct IEntry {
+    int32_t src;   // >= 0: source node;  -1: P2L from stars [slo, shi);  -2: empty
+    int32_t off;   // offset index (dx + 3) + 7 (dy + 3) of the source square
+    int32_t slo, shi;
+};
+
+// per-leaf data used by the ray kernels
+struct LeafInfo {
+    double cx, cy;        // centre
+    double L, invL;       // half-length and its inverse
+    int32_t near_off;     // first near star in the near-star array
+    int32_t near_cnt;     // stars in the leaf's 3x3 block of same-level squares
+    int32_t a_lo, na;     // grid columns [a_lo, a_lo + na) inside the leaf
+    int32_t b_lo, nb;     // grid rows [b_lo, b_lo + nb) inside the leaf
+    int32_t ntx, pad;     // tiles per tile-row
+};
+
+// shooting region and ray grid
+struct Region {
+    double kappa, lam1, lam2, mu_macro;
+    double mean_m, mean_m2, border;
+    double X1, X2, dX1, dX2;
+    double pix1, pix2;
+    int64_t nr1, nr2;
+    double d1, d2, x0, y0;
+    double L0;
+    int32_t L0_exp;       // L0 = 2^(L0_exp - 1)
+};
+
+// the lens equation's constant terms, passed by value to kernels
+struct LensConst {
+    double lam1, lam2;      // 1 - kappa + gamma, 1 - kappa - gamma
+    double kappa_star;
+    double r_star2;         // R_*^2
+    int32_t sheet;          // 1: circular compensating sheet
+    int32_t pad;
+};
+
+// map geometry for the IPM, in pixel units
+struct MapGeom {
+    double ylo1, ylo2;      // lower-left corner of the map
+    double pix1, pix2;
+    int32_t n1, n2;
+    double tri_weight;      // image area of a triangle / pixel area
+};
+
+// FMM tree with coefficients (device arrays) and host metadata
+struct Tree {
+    double L0 = 0;
+    int L0_exp = 0;
+    int nmax = 32, lmax = KEY_BITS, p = 0;
+    int64_t n = 0;                       // stars
+    int nlevels = 0;
+    std::vector<int64_t> level_lo, level_hi;
+    int64_t nnodes = 0, nleaves = 0, near_total = 0;
+    // stars in Morton order
+    uint64_t *keys = nullptr;
+    double *x = nullptr, *y = nullptr, *m = nullptr;
+    // nodes
+    uint64_t *code = nullptr;
+    int32_t *level = nullptr, *leaf = nullptr, *slo = nullptr, *shi = nullptr, *block = nullptr;
+    int32_t *parent = nullptr, *child0 = nullptr, *node_leaf = nullptr;
+    int32_t *leaf_node = nullptr;
+    IEntry *ilist = nullptr;
+    double2 *mult = nullptr, *local = nullptr;
+    // leaf tables
+    LeafInfo *leaves = nullptr;
+    double4 *near = nullptr;             // (dx, dy, m, 0) relative to the leaf centre
+    double2 *deriv = nullptr;            // [nleaves][p]: (l+1) c_{l+1} / L
+};
+
+struct Workspace {
+    DevBuf keys_in, keys, idx_in, idx, sx, sy, sm, cub_tmp;
+    DevBuf code, level, leaf, slo, shi, block, parent, child0, node_leaf, leaf_node, flags, offs;
+    DevBuf ilist, mult, local, ops_m2m, ops_m2l, ops_l2l;
+    DevBuf leaves, near, deriv, near_offs;
+    DevBuf tile_off, tile_leaf, verts, map, wbuf, pts, counters;
+    void *pinned = nullptr;               // small pinned host buffer for read-backs
+    size_t pinned_cap = 0;
+    int ops_p = -1;                       // order the operator tables were built for
+    ~Workspace();
+};
+
+}  // namespace mlm
+
+struct mlm_lens {
+    mlm_lens_params params{};
+    int64_t n = 0;
+    int device = 0;
+    double *d_x = nullptr, *d_y = nullptr, *d_m = nullptr;
+    double mass_sum = 0, mass2_sum = 0, max_abs = 0, r_star = 0;
+    mlm::Workspace ws;
+    std::mutex mu;
+};
+
+namespace mlm {
+
+// region.cpp (host arithmetic, compiled without floating-point contraction)
+mlm_status setup_region(const mlm_lens *lens, const mlm_map_request *req, Region *R);
+int auto_order(double mean_m, double mean_m2, double L, double eps);
+
+// tree.hip
+void build_tree(mlm_lens *lens, const Region &R, const mlm_map_request &req, Tree &T,
+                hipStream_t st);
+
+// fmm.hip
+void run_fmm(mlm_lens *lens, Tree &T, int p, hipStream_t st);
+void build_leaf_tables(mlm_lens *lens, Tree &T, hipStream_t st);
+
+// shoot.hip
+LensConst lens_const(const mlm_lens *lens, const Region &R);
+int64_t plan_tiles(mlm_lens *lens, Tree &T, const Region &R, int64_t vb0, int64_t vb1,
+                   hipStream_t st);
+void launch_shoot(mlm_lens *lens, const Tree &T, const Region &R, const LensConst &lc,
+                  const MapGeom &g, int64_t ntiles, int64_t vb0, double2 *verts, double *w_out,
+                  hipStream_t st);
+void launch_shoot_direct(mlm_lens *lens, const Region &R, const LensConst &lc, const MapGeom &g,
+                         int64_t vb0, int64_t vb1, double2 *verts, double *w_out,
+                         hipStream_t st);
+void launch_deflect_points(mlm_lens *lens, const Tree *T, const LensConst &lc, const double *z,
+                           int64_t n, double *w, hipStream_t st);
+
+// ipm.hip
+void launch_ipm(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int64_t vb0,
+                const MapGeom &g, double *map, unsigned long long *counters, hipStream_t st);
+
+// helpers
+void *pinned(mlm_lens *lens, size_t bytes);
+
+}  // namespace mlm

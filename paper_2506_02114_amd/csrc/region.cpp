@@ -1,0 +1,94 @@
+// Shooting region, ray grid, tree root and expansion order of a map request.
+// Host arithmetic only; built with -ffp-contract=off so every formula is
+// evaluated as written (plain IEEE double operations).
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace mlm {
+
+/*
+ * sec. 2.3 and appendix A:
+ *   centre      X = (Y1 / (1-k+g), Y2 / (1-k-g))
+ *   half-size   dX_i = (dY_i + r) / |1-k+-g|,  r = sqrt(k_* <m^2> / (f <m>))
+ * The ray grid has cells of side pix_i / sqrt(rho) ("rays per pixel in the
+ * absence of lensing", sec. 4) and n_r = ceil(2 dX / Delta) + 1 vertices
+ * centred on X; explicit vertex counts span exactly [X - dX, X + dX].
+ * The tree's root square is centred on the origin (app. C.1); its half-length
+ * is the smallest power of two above every star and ray coordinate, which
+ * makes every square's centre and size exact binary fractions.
+ */
+mlm_status setup_region(const mlm_lens *lens, const mlm_map_request *q, Region *R)
+{
+    if (!(q->hw1 > 0) || !(q->hw2 > 0) || !std::isfinite(q->hw1) || !std::isfinite(q->hw2) ||
+        q->n1 <= 0 || q->n2 <= 0 || !std::isfinite(q->y1c) || !std::isfinite(q->y2c))
+        fail(MLM_EINVAL, "map centre/half-widths must be finite, half-widths > 0, pixels >= 1");
+    if (!(q->rays_per_pixel >= 0) || !(q->flux_fraction >= 0) || !(q->dx1 >= 0) || !(q->dx2 >= 0))
+        fail(MLM_EINVAL, "rays_per_pixel, flux_fraction, dx1, dx2 must be >= 0");
+    if ((q->nray1 != 0 || q->nray2 != 0) && (q->nray1 < 2 || q->nray2 < 2))
+        fail(MLM_EINVAL, "explicit ray-grid vertex counts must both be >= 2");
+    const mlm_lens_params &P = lens->params;
+    R->kappa = P.kappa_star + P.kappa_smooth;
+    R->lam1 = 1.0 - R->kappa + P.gamma;
+    R->lam2 = 1.0 - R->kappa - P.gamma;
+    if (std::fabs(R->lam1) < 1e-9 || std::fabs(R->lam2) < 1e-9)
+        fail(MLM_EDEGENERATE, "|1-kappa+-gamma| = (%g, %g): the shooting region is unbounded",
+             std::fabs(R->lam1), std::fabs(R->lam2));
+    R->mu_macro = 1.0 / (R->lam1 * R->lam2);
+
+    int64_t n = lens->n;
+    R->mean_m = n ? lens->mass_sum / (double)n : 0.0;
+    R->mean_m2 = n ? lens->mass2_sum / (double)n : 0.0;
+    double f = q->flux_fraction > 0 ? q->flux_fraction : 0.01;
+    R->border = (n && P.kappa_star > 0) ? std::sqrt(P.kappa_star * R->mean_m2 / (f * R->mean_m)) : 0.0;
+
+    R->X1 = q->y1c / R->lam1;
+    R->X2 = q->y2c / R->lam2;
+    R->dX1 = q->dx1 > 0 ? q->dx1 : (q->hw1 + R->border) / std::fabs(R->lam1);
+    R->dX2 = q->dx2 > 0 ? q->dx2 : (q->hw2 + R->border) / std::fabs(R->lam2);
+    R->pix1 = 2.0 * q->hw1 / (double)q->n1;
+    R->pix2 = 2.0 * q->hw2 / (double)q->n2;
+
+    if (q->nray1 > 1 && q->nray2 > 1) {
+        R->nr1 = q->nray1;
+        R->nr2 = q->nray2;
+        R->d1 = 2.0 * R->dX1 / (double)(R->nr1 - 1);
+        R->d2 = 2.0 * R->dX2 / (double)(R->nr2 - 1);
+    } else {
+        double rho = q->rays_per_pixel > 0 ? q->rays_per_pixel : 1.0;
+        R->d1 = R->pix1 / std::sqrt(rho);
+        R->d2 = R->pix2 / std::sqrt(rho);
+        double c1 = std::ceil(2.0 * R->dX1 / R->d1), c2 = std::ceil(2.0 * R->dX2 / R->d2);
+        if (!(c1 < 2147483000.0) || !(c2 < 2147483000.0))
+            fail(MLM_ERANGE, "ray grid of %g x %g vertices is too large", c1 + 1, c2 + 1);
+        R->nr1 = (int64_t)c1 + 1;
+        R->nr2 = (int64_t)c2 + 1;
+    }
+    R->x0 = R->X1 - 0.5 * (double)(R->nr1 - 1) * R->d1;
+    R->y0 = R->X2 - 0.5 * (double)(R->nr2 - 1) * R->d2;
+
+    double amax = lens->max_abs;
+    double e1 = std::fabs(R->X1) + 0.5 * (double)(R->nr1 - 1) * R->d1;
+    double e2 = std::fabs(R->X2) + 0.5 * (double)(R->nr2 - 1) * R->d2;
+    if (e1 > amax) amax = e1;
+    if (e2 > amax) amax = e2;
+    int ex;
+    std::frexp(amax > 0 ? amax : 1.0, &ex);
+    R->L0 = std::ldexp(1.0, ex);
+    R->L0_exp = ex + 1;   // L0 = 2^(L0_exp - 1): 2 L0 = 2^L0_exp
+    if (!std::isfinite(R->L0)) fail(MLM_ERANGE, "coordinates too large");
+    return MLM_OK;
+}
+
+/* appendix C.3: smallest integer p with p > log2((<m^2>/<m>) / (L eps)), in [1, 31] */
+int auto_order(double mean_m, double mean_m2, double L, double eps)
+{
+    if (mean_m <= 0) return 1;
+    double t = std::log2((mean_m2 / mean_m) / (L * eps));
+    int p = (int)std::floor(t) + 1;
+    if (p < 1) p = 1;
+    if (p > MAX_ORDER) p = MAX_ORDER;
+    return p;
+}
+
+}  // namespace mlm

@@ -1,0 +1,348 @@
+// Ray shooting (sec. 2.2, 3.3): the source position of every ray-grid vertex,
+//   w = (1-kappa) z + gamma conj(z) - a_*(z) - a_s(z),
+// with a_* = (near field summed directly over the stars of the vertex's leaf
+// and its neighbours) + conj(d/dz of the leaf's Taylor series).
+//
+// Work is leaf-major: the grid vertices inside each leaf form a rectangle,
+// cut into 8 x 8 tiles; one 64-lane wavefront shoots one tile.  All lanes of a
+// wavefront share the leaf, so the near stars and the Taylor coefficients are
+// wavefront-uniform and are read through the scalar cache into SGPRs.
+#include "dev.hpp"
+
+namespace mlm {
+
+int64_t scan_total_public(mlm_lens *lens, const int32_t *in, int32_t *out, int64_t n, hipStream_t st);
+
+namespace {
+
+constexpr int BLK = 256;
+inline unsigned nblocks(int64_t n, int b = BLK) { return (unsigned)((n + b - 1) / b); }
+
+// grid coordinate of vertex a: x0 + a d, evaluated as written (no fused multiply-add)
+__device__ inline double grid_pos(double x0, double d, int64_t a)
+{
+#pragma clang fp contract(off)
+    return x0 + (double)a * d;
+}
+
+// square index of t at level lev (root [-L0, L0)), clamped like the star keys
+__device__ inline int64_t level_cell(double t, double L0, double scale_lev, int lev)
+{
+    double u = floor((t + L0) * scale_lev);
+    double top = (double)((1ll << lev) - 1);
+    u = u < 0.0 ? 0.0 : (u > top ? top : u);
+    return (int64_t)u;
+}
+
+// first a in [lo, hi) whose vertex lies in square index >= target at level lev
+__device__ inline int64_t first_in_cell(double x0, double d, int64_t lo, int64_t hi, double L0, double scale_lev,
+                                        int lev, int64_t target)
+{
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (level_cell(grid_pos(x0, d, mid), L0, scale_lev, lev) < target) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// grid columns and rows (within vertex rows [vb0, vb1)) inside each leaf
+__global__ void k_tile_counts(int64_t nleaves, const int32_t *__restrict__ leaf_node,
+                              const uint64_t *__restrict__ code, const int32_t *__restrict__ level, double L0,
+                              int L0_exp, double x0, double d1, int64_t nr1, double y0, double d2, int64_t vb0,
+                              int64_t vb1, LeafInfo *__restrict__ info, int32_t *__restrict__ cnt)
+{
+    int64_t lf = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (lf >= nleaves) return;
+    int32_t q = leaf_node[lf];
+    int lev = level[q];
+    uint64_t c = code[q];
+    int64_t i = compact_bits(c), j = compact_bits(c >> 1);
+    double scale = ldexp(1.0, lev - L0_exp);   // 2^lev / (2 L0)
+    int64_t a0 = first_in_cell(x0, d1, 0, nr1, L0, scale, lev, i);
+    int64_t a1 = first_in_cell(x0, d1, a0, nr1, L0, scale, lev, i + 1);
+    int64_t b0 = first_in_cell(y0, d2, vb0, vb1, L0, scale, lev, j);
+    int64_t b1 = first_in_cell(y0, d2, b0, vb1, L0, scale, lev, j + 1);
+    LeafInfo &li = info[lf];
+    li.a_lo = (int32_t)a0;
+    li.na = (int32_t)(a1 - a0);
+    li.b_lo = (int32_t)b0;
+    li.nb = (int32_t)(b1 - b0);
+    li.ntx = (li.na + TILE - 1) / TILE;
+    int32_t nty = (li.nb + TILE - 1) / TILE;
+    cnt[lf] = (li.na > 0 && li.nb > 0) ? li.ntx * nty : 0;
+}
+
+__global__ void k_tile_leaf(int64_t ntiles, int64_t nleaves, const int32_t *__restrict__ tile_off,
+                            int32_t *__restrict__ tile_leaf)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    tile_leaf[t] = (int32_t)(upper_bound_i64<int32_t>(tile_off, nleaves, (int32_t)t) - 1);
+}
+
+struct ShootArgs {
+    double x0, y0, d1, d2;
+    int64_t nr1, vb0;
+    int p;
+    int pad;
+};
+
+__device__ inline void finish_vertex(const LensConst &lc, const MapGeom &g, double x, double y, double ax,
+                                     double ay, double &w1, double &w2, double2 &uv)
+{
+    // macro model
+    w1 = lc.lam1 * x - ax;
+    w2 = lc.lam2 * y - ay;
+    // compensating sheet: a_s = -k_* z inside R_*, -k_* R_*^2 / conj(z) outside
+    if (lc.sheet) {
+        double r2 = x * x + y * y;
+        double f = (r2 <= lc.r_star2) ? lc.kappa_star : lc.kappa_star * lc.r_star2 / r2;
+        w1 += f * x;
+        w2 += f * y;
+    }
+    uv = make_double2((w1 - g.ylo1) / g.pix1, (w2 - g.ylo2) / g.pix2);
+}
+
+// one wavefront (64 lanes) per 8 x 8 tile
+__global__ __launch_bounds__(64) void k_shoot(ShootArgs sa, LensConst lc, MapGeom g,
+                                              const int32_t *__restrict__ tile_leaf,
+                                              const int32_t *__restrict__ tile_off,
+                                              const LeafInfo *__restrict__ leaves,
+                                              const double4 *__restrict__ near, const double2 *__restrict__ deriv,
+                                              double2 *__restrict__ verts, double2 *__restrict__ w_out)
+{
+    const int64_t t = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int32_t lf = tile_leaf[t];
+    const LeafInfo li = leaves[lf];
+    const int32_t local = (int32_t)t - tile_off[lf];
+    const int32_t ty = local / li.ntx, tx = local - ty * li.ntx;
+    const int32_t ia = tx * TILE + (lane & (TILE - 1)), ib = ty * TILE + (lane >> 3);
+    const bool valid = ia < li.na && ib < li.nb;
+    const int64_t a = li.a_lo + ia, b = li.b_lo + ib;
+    const double x = grid_pos(sa.x0, sa.d1, a), y = grid_pos(sa.y0, sa.d2, b);
+    const double dx = x - li.cx, dy = y - li.cy;
+
+    // near field: a_* += m (z - z_i) / |z - z_i|^2
+    double ax = 0.0, ay = 0.0;
+    const double4 *ns = near + li.near_off;
+    for (int32_t s = 0; s < li.near_cnt; ++s) {
+        const double4 st = ns[s];
+        const double ex = dx - st.x, ey = dy - st.y;
+        const double f = st.z / (ex * ex + ey * ey);
+        ax += f * ex;
+        ay += f * ey;
+    }
+    // far field: conj( sum_{l<p} deriv_l zeta^l ), Horner
+    const double zr = dx * li.invL, zi = dy * li.invL;
+    const double2 *dv = deriv + (int64_t)lf * sa.p;
+    double sr = dv[sa.p - 1].x, si = dv[sa.p - 1].y;
+    for (int l = sa.p - 2; l >= 0; --l) {
+        const double2 c = dv[l];
+        const double nr = sr * zr - si * zi + c.x;
+        const double ni = sr * zi + si * zr + c.y;
+        sr = nr;
+        si = ni;
+    }
+    ax += sr;
+    ay -= si;
+
+    double w1, w2;
+    double2 uv;
+    finish_vertex(lc, g, x, y, ax, ay, w1, w2, uv);
+    if (valid) {
+        const int64_t o = (b - sa.vb0) * sa.nr1 + a;
+        verts[o] = uv;
+        if (w_out) w_out[o] = make_double2(w1, w2);
+    }
+}
+
+// direct summation over every star (no FMM): one thread per vertex, stars
+// staged through LDS in tiles
+constexpr int DTILE = 256;
+__global__ __launch_bounds__(256) void k_shoot_direct(ShootArgs sa, LensConst lc, MapGeom g, int64_t nverts,
+                                                      const double *__restrict__ sx, const double *__restrict__ sy,
+                                                      const double *__restrict__ sm, int32_t n,
+                                                      double2 *__restrict__ verts, double2 *__restrict__ w_out)
+{
+    __shared__ double3 tile[DTILE];
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t a = v % sa.nr1, b = sa.vb0 + v / sa.nr1;
+    double x = grid_pos(sa.x0, sa.d1, a), y = grid_pos(sa.y0, sa.d2, b);
+    double ax = 0.0, ay = 0.0;
+    for (int32_t s0 = 0; s0 < n; s0 += DTILE) {
+        int32_t s = s0 + threadIdx.x;
+        __syncthreads();
+        if (s < n) tile[threadIdx.x] = make_double3(sx[s], sy[s], sm[s]);
+        __syncthreads();
+        int32_t cnt = min(DTILE, n - s0);
+        for (int32_t k = 0; k < cnt; ++k) {
+            double3 st = tile[k];
+            double ex = x - st.x, ey = y - st.y;
+            double f = st.z / (ex * ex + ey * ey);
+            ax += f * ex;
+            ay += f * ey;
+        }
+    }
+    if (v >= nverts) return;
+    double w1, w2;
+    double2 uv;
+    finish_vertex(lc, g, x, y, ax, ay, w1, w2, uv);
+    verts[v] = uv;
+    if (w_out) w_out[v] = make_double2(w1, w2);
+}
+
+struct LevelRanges {
+    int64_t lo[KEY_BITS + 2], hi[KEY_BITS + 2];
+};
+
+// w at arbitrary points: leaf by descending the levels, then as k_shoot
+__global__ void k_deflect_points(int64_t npts, const double2 *__restrict__ z, LevelRanges lr, int nlevels,
+                                 double L0, int L0_exp, const uint64_t *__restrict__ code,
+                                 const int32_t *__restrict__ leaf, const int32_t *__restrict__ node_leaf,
+                                 const LeafInfo *__restrict__ leaves, const double4 *__restrict__ near,
+                                 const double2 *__restrict__ deriv, int p, LensConst lc,
+                                 double2 *__restrict__ w)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= npts) return;
+    double x = z[t].x, y = z[t].y;
+    int64_t lf = -1;
+    for (int lev = 0; lev < nlevels && lf < 0; ++lev) {
+        double scale = ldexp(1.0, lev - L0_exp);
+        uint64_t c = morton2((uint32_t)level_cell(x, L0, scale, lev), (uint32_t)level_cell(y, L0, scale, lev));
+        int64_t a = lr.lo[lev], b = lr.hi[lev];
+        while (a < b) {
+            int64_t mid = (a + b) >> 1;
+            if (code[mid] < c) a = mid + 1;
+            else b = mid;
+        }
+        if (a >= lr.hi[lev] || code[a] != c) break;
+        if (leaf[a]) lf = node_leaf[a];
+    }
+    if (lf < 0) {
+        w[t] = make_double2(nan(""), nan(""));
+        return;
+    }
+    LeafInfo li = leaves[lf];
+    double dx = x - li.cx, dy = y - li.cy;
+    double ax = 0.0, ay = 0.0;
+    for (int32_t s = 0; s < li.near_cnt; ++s) {
+        double4 st = near[li.near_off + s];
+        double ex = dx - st.x, ey = dy - st.y;
+        double f = st.z / (ex * ex + ey * ey);
+        ax += f * ex;
+        ay += f * ey;
+    }
+    double zr = dx * li.invL, zi = dy * li.invL;
+    const double2 *dv = deriv + lf * p;
+    double sr = dv[p - 1].x, si = dv[p - 1].y;
+    for (int l = p - 2; l >= 0; --l) {
+        double nr = sr * zr - si * zi + dv[l].x;
+        double ni = sr * zi + si * zr + dv[l].y;
+        sr = nr;
+        si = ni;
+    }
+    ax += sr;
+    ay -= si;
+    MapGeom g{0, 0, 1, 1, 1, 1, 0};
+    double w1, w2;
+    double2 uv;
+    finish_vertex(lc, g, x, y, ax, ay, w1, w2, uv);
+    w[t] = make_double2(w1, w2);
+}
+
+__global__ void k_deflect_direct(int64_t npts, const double2 *__restrict__ z, const double *__restrict__ sx,
+                                 const double *__restrict__ sy, const double *__restrict__ sm, int32_t n,
+                                 LensConst lc, double2 *__restrict__ w)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= npts) return;
+    double x = z[t].x, y = z[t].y, ax = 0.0, ay = 0.0;
+    for (int32_t s = 0; s < n; ++s) {
+        double ex = x - sx[s], ey = y - sy[s];
+        double f = sm[s] / (ex * ex + ey * ey);
+        ax += f * ex;
+        ay += f * ey;
+    }
+    MapGeom g{0, 0, 1, 1, 1, 1, 0};
+    double w1, w2;
+    double2 uv;
+    finish_vertex(lc, g, x, y, ax, ay, w1, w2, uv);
+    w[t] = make_double2(w1, w2);
+}
+
+}  // namespace
+
+LensConst lens_const(const mlm_lens *lens, const Region &R)
+{
+    LensConst lc;
+    lc.lam1 = R.lam1;
+    lc.lam2 = R.lam2;
+    lc.kappa_star = lens->params.kappa_star;
+    lc.r_star2 = lens->r_star * lens->r_star;
+    lc.sheet = lens->params.sheet == MLM_SHEET_CIRCLE ? 1 : 0;
+    lc.pad = 0;
+    return lc;
+}
+
+int64_t plan_tiles(mlm_lens *lens, Tree &T, const Region &R, int64_t vb0, int64_t vb1, hipStream_t st)
+{
+    Workspace &ws = lens->ws;
+    int64_t nl = T.nleaves;
+    int32_t *cnt = static_cast<int32_t *>(ws.flags.reserve(nl * 4));
+    int32_t *off = static_cast<int32_t *>(ws.tile_off.reserve(nl * 4));
+    hipLaunchKernelGGL(k_tile_counts, dim3(nblocks(nl)), dim3(BLK), 0, st, nl, T.leaf_node, T.code, T.level, T.L0,
+                       T.L0_exp, R.x0, R.d1, R.nr1, R.y0, R.d2, vb0, vb1, T.leaves, cnt);
+    int64_t ntiles = scan_total_public(lens, cnt, off, nl, st);
+    if (ntiles > (int64_t)INT32_MAX) fail(MLM_ERANGE, "too many ray tiles in one strip");
+    if (ntiles > 0) {
+        int32_t *tl = static_cast<int32_t *>(ws.tile_leaf.reserve(ntiles * 4));
+        hipLaunchKernelGGL(k_tile_leaf, dim3(nblocks(ntiles)), dim3(BLK), 0, st, ntiles, nl, off, tl);
+    }
+    return ntiles;
+}
+
+void launch_shoot(mlm_lens *lens, const Tree &T, const Region &R, const LensConst &lc, const MapGeom &g,
+                  int64_t ntiles, int64_t vb0, double2 *verts, double *w_out, hipStream_t st)
+{
+    if (ntiles <= 0) return;
+    Workspace &ws = lens->ws;
+    ShootArgs sa{R.x0, R.y0, R.d1, R.d2, R.nr1, vb0, T.p, 0};
+    hipLaunchKernelGGL(k_shoot, dim3((unsigned)ntiles), dim3(64), 0, st, sa, lc, g, ws.tile_leaf.as<int32_t>(),
+                       ws.tile_off.as<int32_t>(), T.leaves, T.near, T.deriv, verts,
+                       reinterpret_cast<double2 *>(w_out));
+}
+
+void launch_shoot_direct(mlm_lens *lens, const Region &R, const LensConst &lc, const MapGeom &g, int64_t vb0,
+                         int64_t vb1, double2 *verts, double *w_out, hipStream_t st)
+{
+    int64_t nv = (vb1 - vb0) * R.nr1;
+    if (nv <= 0) return;
+    ShootArgs sa{R.x0, R.y0, R.d1, R.d2, R.nr1, vb0, 0, 0};
+    hipLaunchKernelGGL(k_shoot_direct, dim3(nblocks(nv)), dim3(256), 0, st, sa, lc, g, nv, lens->d_x, lens->d_y,
+                       lens->d_m, (int32_t)lens->n, verts, reinterpret_cast<double2 *>(w_out));
+}
+
+void launch_deflect_points(mlm_lens *lens, const Tree *T, const LensConst &lc, const double *z, int64_t n,
+                           double *w, hipStream_t st)
+{
+    if (n <= 0) return;
+    const double2 *z2 = reinterpret_cast<const double2 *>(z);
+    double2 *w2 = reinterpret_cast<double2 *>(w);
+    if (!T) {
+        hipLaunchKernelGGL(k_deflect_direct, dim3(nblocks(n)), dim3(BLK), 0, st, n, z2, lens->d_x, lens->d_y,
+                           lens->d_m, (int32_t)lens->n, lc, w2);
+        return;
+    }
+    LevelRanges lr{};
+    for (int l = 0; l < T->nlevels; ++l) {
+        lr.lo[l] = T->level_lo[l];
+        lr.hi[l] = T->level_hi[l];
+    }
+    hipLaunchKernelGGL(k_deflect_points, dim3(nblocks(n)), dim3(BLK), 0, st, n, z2, lr, T->nlevels, T->L0,
+                       T->L0_exp, T->code, T->leaf, T->node_leaf, T->leaves, T->near, T->deriv, T->p, lc, w2);
+}
+
+}  // namespace mlm

@@ -1,0 +1,107 @@
+"""The C ABI without a GPU: the library loads, exports every function the
+header declares, the binding's struct layouts match the header's, and
+argument validation answers before any device work."""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mlmap.h")
+
+
+@pytest.fixture(scope="module")
+def mlm():
+    import paper_2506_02114_amd as m
+    if not os.path.exists(m.LIB_PATH):
+        from paper_2506_02114_amd import _build
+        _build.build()
+    m.load()
+    return m
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mlm_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(mlm):
+    names = declared_functions()
+    assert len(names) >= 10
+    lib = C.CDLL(mlm.LIB_PATH)
+    for nm in names:
+        assert hasattr(lib, nm), nm
+    assert sorted(mlm.EXPORTED) == names
+
+
+def test_struct_layouts_match_header(mlm):
+    structs = {"mlm_lens_params": mlm.LensParams, "mlm_lens_info": mlm.LensInfo,
+               "mlm_map_request": mlm.MapRequest, "mlm_region": mlm.Region,
+               "mlm_map_stats": mlm.MapStats, "mlm_tree_info": mlm.TreeInfo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mlmap.h"', "int main(void){"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0;}")
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "probe.c")
+        exe = os.path.join(d, "probe")
+        open(src, "w").write("\n".join(lines))
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
+    for line in out:
+        if not line:
+            continue
+        cname, what, val = line.split()
+        py = structs[cname]
+        if what == "size":
+            assert C.sizeof(py) == int(val), cname
+        else:
+            assert getattr(py, what).offset == int(val), (cname, what)
+
+
+def test_version_and_status_strings(mlm):
+    lib = mlm.load()
+    assert lib.mlm_abi_version() == 1
+    assert lib.mlm_status_str(0) == b"MLM_OK"
+    assert lib.mlm_status_str(2) == b"MLM_EDEGENERATE"
+    assert lib.mlm_status_str(99) == b"MLM_UNKNOWN"
+
+
+def test_request_defaults(mlm):
+    r = mlm.make_request()
+    assert r.rays_per_pixel == 1.0 and r.flux_fraction == 0.01 and r.leaf_max == 32
+    assert r.max_level == 24 and r.eps == 1e-7 and r.row_end == -1
+    with pytest.raises(TypeError):
+        mlm.make_request(bogus=1)
+
+
+def test_validation_errors_before_device_work(mlm):
+    lib = mlm.load()
+    h = C.c_void_p()
+    p = mlm.LensParams(0.3, 0.0, 0.3, 0, 0)
+    # negative count, NULL out, negative kappa_star, bad sheet: rejected on the host
+    assert lib.mlm_lens_create(C.byref(p), None, None, None, -1, 0, C.byref(h)) == mlm.MLM_EINVAL
+    assert b"n must be" in lib.mlm_last_error()
+    assert lib.mlm_lens_create(C.byref(p), None, None, None, 0, 0, None) == mlm.MLM_EINVAL
+    bad = mlm.LensParams(-0.1, 0.0, 0.3, 0, 0)
+    assert lib.mlm_lens_create(C.byref(bad), None, None, None, 0, 0, C.byref(h)) == mlm.MLM_EINVAL
+    bad = mlm.LensParams(0.1, float("nan"), 0.3, 0, 0)
+    assert lib.mlm_lens_create(C.byref(bad), None, None, None, 0, 0, C.byref(h)) == mlm.MLM_EINVAL
+    bad = mlm.LensParams(0.1, 0.0, 0.3, 7, 0)
+    assert lib.mlm_lens_create(C.byref(bad), None, None, None, 0, 0, C.byref(h)) == mlm.MLM_EINVAL
+    # stars with a non-positive mass are rejected after the host copy
+    x = np.zeros(2); m = np.array([1.0, 0.0])
+    st = lib.mlm_lens_create(C.byref(p), x.ctypes.data_as(C.c_void_p), x.ctypes.data_as(C.c_void_p),
+                             m.ctypes.data_as(C.c_void_p), 2, 0, C.byref(h))
+    assert st == mlm.MLM_EINVAL
+    # requests: NULL lens / NULL output
+    r = mlm.make_request()
+    assert lib.mlm_map(None, C.byref(r), None, None) == mlm.MLM_EINVAL
+    mlm.load().mlm_lens_destroy(None)   # NULL-safe
