@@ -99,14 +99,16 @@ def main():
                     torch.from_numpy(sf.y).to(dev), torch.from_numpy(sf.m).to(dev))
     region = lens.region(**spec)
     out = torch.empty((spec["n2"], spec["n1"]), dtype=torch.float64, device=dev)
-    for _ in range(args.warmup):
+    for k in range(args.warmup):
         lens.map(out=out, **spec)
+        print(f"[bench] warmup {k + 1}/{args.warmup} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     stats = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         _, s = lens.map(out=out, timing=1, **spec)
         stats.append(s)
+        print(f"[bench] step {k + 1}/{args.steps}: {s['t_total_ms']:.2f} ms device", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / args.steps
@@ -143,6 +145,8 @@ def main():
         "roofline": shoot_roof,
         "tree": {"nodes": stats[0]["n_nodes"], "leaves": stats[0]["n_leaves"], "levels": stats[0]["n_levels"],
                  "near_pairs_per_ray": stats[0]["near_pairs"] / rays},
+        "ipm": {"triangles": 2 * stats[0]["n_cells"], "row_path_triangles": stats[0]["n_big"],
+                "row_path_rows": stats[0]["n_big_rows"]},
     }
     if not args.no_cpu_baseline:
         nthreads = min(16, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), os.cpu_count() or 1)

@@ -218,6 +218,8 @@ typedef struct mlm_map_stats {
     double t_ipm_ms;         /* IPM kernels */
     double t_total_ms;       /* whole call, device time */
     int32_t n_shoot_launches, n_ipm_launches;
+    int64_t n_big;           /* triangles apportioned row by row (large mapped area) */
+    int64_t n_big_rows;      /* pixel rows those triangles cover inside the map */
 } mlm_map_stats;
 
 /*

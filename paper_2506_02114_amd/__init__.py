@@ -72,7 +72,8 @@ class MapStats(C.Structure):
                 ("order", C.c_int32), ("near_pairs", C.c_int64), ("n_tiles", C.c_int64),
                 ("tri_area", C.c_double), ("t_tree_ms", C.c_double), ("t_fmm_ms", C.c_double),
                 ("t_shoot_ms", C.c_double), ("t_ipm_ms", C.c_double), ("t_total_ms", C.c_double),
-                ("n_shoot_launches", C.c_int32), ("n_ipm_launches", C.c_int32)]
+                ("n_shoot_launches", C.c_int32), ("n_ipm_launches", C.c_int32),
+                ("n_big", C.c_int64), ("n_big_rows", C.c_int64)]
 
 
 class TreeInfo(C.Structure):

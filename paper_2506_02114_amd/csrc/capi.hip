@@ -1,4 +1,5 @@
 // C ABI of the library and the orchestration of a map.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -368,8 +369,13 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
     int64_t npix = (int64_t)q.n1 * q.n2;
     double *map = q.device_out ? mu : static_cast<double *>(ws.map.reserve(npix * sizeof(double)));
     fill(map, npix, 0.0, st);
+    // counters: [0] skipped triangles, [1] ray-star pairs, [2] rays, [3] queue
+    // overflows, [4] queued big triangles of the current strip
     unsigned long long *cnt = static_cast<unsigned long long *>(ws.counters.reserve(8 * sizeof(unsigned long long)));
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, cnt, 8);
+    int64_t ndiff = (int64_t)q.n2 * (q.n1 + 1);
+    double *diff = static_cast<double *>(ws.diff.reserve(ndiff * sizeof(double)));
+    fill(diff, ndiff, 0.0, st);
 
     Tree T;
     const bool fmm = q.method == MLM_METHOD_FMM;
@@ -403,6 +409,14 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
     double *wdev = nullptr;
     if (q.w_out) wdev = q.device_out ? q.w_out : static_cast<double *>(ws.wbuf.reserve((size_t)nbuf * sizeof(double2)));
 
+    int64_t qcap = std::min<int64_t>(2 * (int64_t)(rows_per_strip - 1) * (R.nr1 - 1), (int64_t)1 << 24);
+    if (qcap < 1024) qcap = 1024;
+    BigTri *bigq = static_cast<BigTri *>(ws.bigq.reserve((size_t)qcap * sizeof(BigTri)));
+    int64_t *bigrows = static_cast<int64_t *>(ws.bigrows.reserve((size_t)qcap * sizeof(int64_t)));
+    int64_t *bigoff = static_cast<int64_t *>(ws.bigoff.reserve((size_t)qcap * sizeof(int64_t)));
+    unsigned long long *hq = static_cast<unsigned long long *>(pinned(lens, 8 * sizeof(unsigned long long)));
+    int64_t n_big = 0, n_big_rows = 0;
+
     double t_shoot = 0.0, t_ipm = 0.0;
     int64_t tiles = 0;
     int nstrips = 0;
@@ -421,7 +435,18 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
         if (fmm) launch_shoot(lens, T, R, lc, g, nt, vb0, verts, w_here, st);
         else launch_shoot_direct(lens, R, lc, g, vb0, vb1, verts, w_here, st);
         int eb = tm.mark();
-        launch_ipm(verts, R.nr1, r0, r1, vb0, g, map, cnt, st);
+        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, cnt + 4, 1);
+        launch_ipm(verts, R.nr1, r0, r1, vb0, g, map, cnt, bigq, qcap, st);
+        MLM_HIP(hipMemcpyAsync(hq, cnt + 4, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+        MLM_HIP(hipStreamSynchronize(st));
+        int64_t nq = std::min<int64_t>((int64_t)hq[0], qcap);
+        if (nq > 0) {
+            launch_big_rows(nq, bigq, g, bigrows, st);
+            int64_t total_rows = scan_total_i64(lens, bigrows, bigoff, nq, st);
+            launch_big_apportion(total_rows, nq, bigoff, bigq, g, map, diff, st);
+            n_big += nq;
+            n_big_rows += total_rows;
+        }
         int ec = tm.mark();
         if (q.w_out && !q.device_out)
             MLM_HIP(hipMemcpyAsync(q.w_out + 2 * (vb0 - cb0) * R.nr1, wdev, (size_t)(vb1 - vb0) * R.nr1 * 2 * sizeof(double),
@@ -432,6 +457,7 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
         tiles += nt;
         r0 = r1;
     }
+    launch_diff_rows(g, diff, map, st);
     if (!q.device_out) MLM_HIP(hipMemcpyAsync(mu, map, npix * sizeof(double), hipMemcpyDeviceToHost, st));
     unsigned long long *hc = static_cast<unsigned long long *>(pinned(lens, 8 * sizeof(unsigned long long)));
     MLM_HIP(hipMemcpyAsync(hc, cnt, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
@@ -456,6 +482,8 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
         S.t_total_ms = tm.ms(e_start, e_end);
         S.n_shoot_launches = nstrips;
         S.n_ipm_launches = nstrips;
+        S.n_big = n_big;
+        S.n_big_rows = n_big_rows;
         *stats = S;
     }
     API_END

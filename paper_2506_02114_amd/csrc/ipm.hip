@@ -10,6 +10,14 @@
 // polygon the gaps so closed run along the strip's boundary lines, so the
 // slots trace exactly the clipped polygon, with every index known at compile
 // time (no dynamically indexed arrays, nothing spilled to scratch).
+//
+// Triangles next to a star map to huge triangles (the linear interpolation
+// of a singular mapping), covering up to millions of pixels.  Their cost is
+// made proportional to their perimeter instead of their area: they are queued
+// and processed one (triangle, pixel row) per thread; in each row only the
+// pixels on the triangle's boundary are clipped, and the run of fully covered
+// pixels between them is recorded as two entries of a per-row difference
+// buffer, whose prefix sums are added to the map at the end.
 #include "dev.hpp"
 
 namespace mlm {
@@ -18,6 +26,14 @@ namespace {
 
 struct P2 {
     double u, v;
+};
+
+constexpr int64_t BIG_PIXELS = 48;   // bounding-box pixels above which a triangle is queued
+
+struct BigQueue {
+    BigTri *tri;
+    unsigned long long *count;
+    unsigned long long cap;
 };
 
 __device__ inline P2 lerp2(P2 P, P2 Q, double t)
@@ -107,12 +123,14 @@ __device__ inline void deposit(double *map, const MapGeom &g, int64_t i, int64_t
     unsafeAtomicAdd(map + j * (int64_t)g.n1 + i, val);
 }
 
-// apportion one triangle (pixel coordinates); weight = its image area / pixel area
+// apportion one triangle (pixel coordinates); weight = its image area / pixel area.
+// Triangles whose bounding box within the map exceeds BIG_PIXELS go to the
+// big-triangle queue (unless it is full).
 __device__ void apportion(P2 A, P2 B, P2 C, double weight, const MapGeom &g, double *map,
-                          unsigned long long *skipped)
+                          unsigned long long *counters, BigQueue q)
 {
     if (!(isfinite(A.u) && isfinite(A.v) && isfinite(B.u) && isfinite(B.v) && isfinite(C.u) && isfinite(C.v))) {
-        atomicAdd(skipped, 1ull);
+        atomicAdd(counters, 1ull);
         return;
     }
     const double umin = fmin(A.u, fmin(B.u, C.u)), umax = fmax(A.u, fmax(B.u, C.u));
@@ -138,6 +156,14 @@ __device__ void apportion(P2 A, P2 B, P2 C, double weight, const MapGeom &g, dou
     const double scale = weight / S2;
     const int64_t i0 = (int64_t)fmax(fu0, 0.0), i1 = (int64_t)fmin(fu1, (double)(g.n1 - 1));
     const int64_t j0 = (int64_t)fmax(fv0, 0.0), j1 = (int64_t)fmin(fv1, (double)(g.n2 - 1));
+    if ((i1 - i0 + 1) * (j1 - j0 + 1) > BIG_PIXELS) {
+        unsigned long long k = atomicAdd(q.count, 1ull);
+        if (k < q.cap) {
+            q.tri[k] = BigTri{A.u, A.v, B.u, B.v, C.u, C.v};
+            return;
+        }
+        atomicAdd(counters + 3, 1ull);   // queue full: apportion here
+    }
     for (int64_t i = i0; i <= i1; ++i) {
         const double cl = (double)i - fu0;
         P2 col[6];
@@ -168,7 +194,7 @@ __device__ void apportion(P2 A, P2 B, P2 C, double weight, const MapGeom &g, dou
 // one thread per grid cell of cell rows [cb0, cb1)
 __global__ __launch_bounds__(256) void k_ipm(const double2 *__restrict__ verts, int64_t nr1, int64_t cb0,
                                              int64_t ncells, int64_t vb0, MapGeom g, double *__restrict__ map,
-                                             unsigned long long *__restrict__ counters)
+                                             unsigned long long *__restrict__ counters, BigQueue q)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ncells) return;
@@ -186,19 +212,141 @@ __global__ __launch_bounds__(256) void k_ipm(const double2 *__restrict__ verts, 
         return;
     }
     // T1 = (v00, v10, v11), T2 = (v00, v11, v01): split along v00-v11
-    apportion(v00, v10, v11, g.tri_weight, g, map, counters);
-    apportion(v00, v11, v01, g.tri_weight, g, map, counters);
+    apportion(v00, v10, v11, g.tri_weight, g, map, counters, q);
+    apportion(v00, v11, v01, g.tri_weight, g, map, counters, q);
+}
+
+// pixel rows of each queued triangle inside the map
+__global__ void k_big_rows(int64_t nq, const BigTri *__restrict__ tri, MapGeom g, int64_t *__restrict__ rows)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nq) return;
+    const BigTri t = tri[k];
+    const double vmin = fmin(t.v0, fmin(t.v1, t.v2)), vmax = fmax(t.v0, fmax(t.v1, t.v2));
+    const double j0 = fmax(floor(vmin), 0.0), j1 = fmin(floor(vmax), (double)(g.n2 - 1));
+    rows[k] = j1 >= j0 ? (int64_t)(j1 - j0) + 1 : 0;
+}
+
+// one (queued triangle, pixel row) per thread
+__global__ __launch_bounds__(256) void k_big_apportion(int64_t total, int64_t nq, const int64_t *__restrict__ row_off,
+                                                       const BigTri *__restrict__ tri, MapGeom g,
+                                                       double *__restrict__ map, double *__restrict__ diff)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int64_t k = upper_bound_i64<int64_t>(row_off, nq, t) - 1;
+    const BigTri bt = tri[k];
+    const double umin = fmin(bt.u0, fmin(bt.u1, bt.u2)), vmin = fmin(bt.v0, fmin(bt.v1, bt.v2));
+    // integer local origin inside or at the edge of the map: exact pixel boundaries nearby
+    const double ou = fmax(floor(umin), 0.0), ov = fmax(floor(vmin), 0.0);
+    const int64_t j = (int64_t)ov + (t - row_off[k]);
+    P2 T[3] = {P2{bt.u0 - ou, bt.v0 - ov}, P2{bt.u1 - ou, bt.v1 - ov}, P2{bt.u2 - ou, bt.v2 - ov}};
+    double S2 = (T[1].u - T[0].u) * (T[2].v - T[0].v) - (T[2].u - T[0].u) * (T[1].v - T[0].v);
+    if (S2 < 0.0) {   // counter-clockwise order: interior to the left of every edge
+        const P2 tmp = T[1];
+        T[1] = T[2];
+        T[2] = tmp;
+        S2 = -S2;
+    }
+    const double scale = g.tri_weight / S2;   // deposit = scale * (twice the piece area)
+    const double rl = (double)j - ov;
+    P2 row[6];
+    if (!clip_poly<1, 3>(T, rl, rl + 1.0, row)) return;
+    double rumin = row[0].u, rumax = row[0].u;
+#pragma unroll
+    for (int m = 1; m < 6; ++m) {
+        rumin = fmin(rumin, row[m].u);
+        rumax = fmax(rumax, row[m].u);
+    }
+    const double ga = fmax(floor(rumin), -ou), gb = fmin(floor(rumax), (double)(g.n1 - 1) - ou);
+    if (ga > gb) return;
+    // pixels of this row fully inside the triangle: every corner on the inner
+    // side of each edge (local pixel indices)
+    double fa = -1e300, fb = 1e300;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const P2 P = T[m], Q = T[(m + 1) % 3];
+        const double dx = Q.u - P.u, dy = Q.v - P.v;
+        const double vc = dx > 0.0 ? rl : rl + 1.0;
+        const double base = dx * (vc - P.v);
+        if (dy > 0.0) fb = fmin(fb, floor(P.u - 1.0 + base / dy));
+        else if (dy < 0.0) fa = fmax(fa, ceil(P.u - base / (-dy)));
+        else if (base < 0.0) fa = 1e300;
+    }
+    fa = fmax(fa, ga);
+    fb = fmin(fb, gb);
+    const bool has_full = fa <= fb;
+    const int64_t ia = (int64_t)ga, ib = (int64_t)gb;
+    const int64_t pa = has_full ? (int64_t)fa : ib + 1, pb = has_full ? (int64_t)fb : ib;
+    // boundary pixels: exact clip of the row polygon to the pixel column
+    for (int64_t i = ia; i <= ib; ++i) {
+        if (i == pa && has_full) {
+            i = pb;
+            continue;
+        }
+        const double cl = (double)i;
+        P2 piece[12];
+        if (!clip_poly<0, 6>(row, cl, cl + 1.0, piece)) continue;
+        const double a2 = shoelace2(piece, cl, rl);
+        if (a2 != 0.0) deposit(map, g, i + (int64_t)ou, j, scale * a2);
+    }
+    if (has_full) {
+        double *dr = diff + j * (int64_t)(g.n1 + 1) + (int64_t)ou;
+        unsafeAtomicAdd(dr + pa, 2.0 * scale);
+        unsafeAtomicAdd(dr + pb + 1, -2.0 * scale);
+    }
+}
+
+// map[j][i] += sum_{k <= i} diff[j][k]; one wavefront per pixel row
+__global__ __launch_bounds__(64) void k_diff_rows(MapGeom g, const double *__restrict__ diff, double *__restrict__ map)
+{
+    const int64_t j = blockIdx.x;
+    const int lane = threadIdx.x;
+    const double *dr = diff + j * (int64_t)(g.n1 + 1);
+    double *mr = map + j * (int64_t)g.n1;
+    double carry = 0.0;
+    for (int64_t c = 0; c < g.n1; c += 64) {
+        const int64_t i = c + lane;
+        double v = i < g.n1 ? dr[i] : 0.0;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const double o = __shfl_up(v, d, 64);
+            if (lane >= d) v += o;
+        }
+        v += carry;
+        if (i < g.n1 && v != 0.0) mr[i] += v;
+        carry = __shfl(v, 63, 64);
+    }
 }
 
 }  // namespace
 
 void launch_ipm(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int64_t vb0, const MapGeom &g,
-                double *map, unsigned long long *counters, hipStream_t st)
+                double *map, unsigned long long *counters, BigTri *queue, int64_t queue_cap, hipStream_t st)
 {
     int64_t ncells = (nr1 - 1) * (cb1 - cb0);
     if (ncells <= 0) return;
+    BigQueue q{queue, counters + 4, (unsigned long long)queue_cap};
     hipLaunchKernelGGL(k_ipm, dim3((unsigned)((ncells + 255) / 256)), dim3(256), 0, st, verts, nr1, cb0, ncells, vb0,
-                       g, map, counters);
+                       g, map, counters, q);
+}
+
+void launch_big_rows(int64_t nq, const BigTri *tri, const MapGeom &g, int64_t *rows, hipStream_t st)
+{
+    if (nq > 0) hipLaunchKernelGGL(k_big_rows, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, nq, tri, g, rows);
+}
+
+void launch_big_apportion(int64_t total_rows, int64_t nq, const int64_t *row_off, const BigTri *tri, const MapGeom &g,
+                          double *map, double *diff, hipStream_t st)
+{
+    if (total_rows > 0)
+        hipLaunchKernelGGL(k_big_apportion, dim3((unsigned)((total_rows + 255) / 256)), dim3(256), 0, st, total_rows,
+                           nq, row_off, tri, g, map, diff);
+}
+
+void launch_diff_rows(const MapGeom &g, const double *diff, double *map, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_diff_rows, dim3((unsigned)g.n2), dim3(64), 0, st, g, diff, map);
 }
 
 }  // namespace mlm

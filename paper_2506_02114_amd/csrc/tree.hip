@@ -211,6 +211,22 @@ int64_t scan_total_public(mlm_lens *lens, const int32_t *in, int32_t *out, int64
     return scan_total(lens, in, out, n, st);
 }
 
+// exclusive prefix sum of n int64 values; returns the total
+int64_t scan_total_i64(mlm_lens *lens, const int64_t *in, int64_t *out, int64_t n, hipStream_t st)
+{
+    Workspace &ws = lens->ws;
+    if (n == 0) return 0;
+    size_t tb = 0;
+    MLM_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, in, out, (int)n, st));
+    void *tmp = cub_tmp(ws, tb);
+    MLM_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, in, out, (int)n, st));
+    int64_t *h = static_cast<int64_t *>(pinned(lens, 2 * sizeof(int64_t)));
+    MLM_HIP(hipMemcpyAsync(h, out + n - 1, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    MLM_HIP(hipMemcpyAsync(h + 1, in + n - 1, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    MLM_HIP(hipStreamSynchronize(st));
+    return h[0] + h[1];
+}
+
 void build_tree(mlm_lens *lens, const Region &R, const mlm_map_request &req, Tree &T, hipStream_t st)
 {
     Workspace &ws = lens->ws;
