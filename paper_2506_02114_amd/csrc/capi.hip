@@ -409,12 +409,6 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
     double *wdev = nullptr;
     if (q.w_out) wdev = q.device_out ? q.w_out : static_cast<double *>(ws.wbuf.reserve((size_t)nbuf * sizeof(double2)));
 
-    int64_t qcap = std::min<int64_t>(2 * (int64_t)(rows_per_strip - 1) * (R.nr1 - 1), (int64_t)1 << 24);
-    if (qcap < 1024) qcap = 1024;
-    BigTri *bigq = static_cast<BigTri *>(ws.bigq.reserve((size_t)qcap * sizeof(BigTri)));
-    int64_t *bigrows = static_cast<int64_t *>(ws.bigrows.reserve((size_t)qcap * sizeof(int64_t)));
-    int64_t *bigoff = static_cast<int64_t *>(ws.bigoff.reserve((size_t)qcap * sizeof(int64_t)));
-    unsigned long long *hq = static_cast<unsigned long long *>(pinned(lens, 8 * sizeof(unsigned long long)));
     int64_t n_big = 0, n_big_rows = 0;
 
     double t_shoot = 0.0, t_ipm = 0.0;
@@ -435,17 +429,23 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
         if (fmm) launch_shoot(lens, T, R, lc, g, nt, vb0, verts, w_here, st);
         else launch_shoot_direct(lens, R, lc, g, vb0, vb1, verts, w_here, st);
         int eb = tm.mark();
-        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, cnt + 4, 1);
-        launch_ipm(verts, R.nr1, r0, r1, vb0, g, map, cnt, bigq, qcap, st);
-        MLM_HIP(hipMemcpyAsync(hq, cnt + 4, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-        MLM_HIP(hipStreamSynchronize(st));
-        int64_t nq = std::min<int64_t>((int64_t)hq[0], qcap);
-        if (nq > 0) {
-            launch_big_rows(nq, bigq, g, bigrows, st);
-            int64_t total_rows = scan_total_i64(lens, bigrows, bigoff, nq, st);
-            launch_big_apportion(total_rows, nq, bigoff, bigq, g, map, diff, st);
-            n_big += nq;
-            n_big_rows += total_rows;
+        // IPM: cell pass, then one thread per (triangle, pixel column) for the
+        // ordinary triangles and the row-parallel passes for the large ones
+        const int64_t ncells = (R.nr1 - 1) * (r1 - r0);
+        int32_t *nbig = static_cast<int32_t *>(ws.nbig.reserve((size_t)ncells * sizeof(int32_t)));
+        int64_t *bigoff = static_cast<int64_t *>(ws.bigoff.reserve((size_t)(ncells + 1) * sizeof(int64_t)));
+        launch_ipm(verts, R.nr1, r0, r1, vb0, g, map, cnt, nbig, st);
+        const int64_t nb = scan_i32_to_i64(lens, nbig, bigoff, ncells, st);
+        if (nb > 0) {
+            BigPrep *prep = static_cast<BigPrep *>(ws.bigprep.reserve((size_t)nb * sizeof(BigPrep)));
+            int64_t *rows = static_cast<int64_t *>(ws.bigrows.reserve((size_t)nb * sizeof(int64_t)));
+            launch_big_gather(ncells, bigoff, verts, R.nr1, r0, vb0, g, prep, rows, st);
+            launch_big(nb, prep, rows, g, map, diff, st);
+            if (q.timing) {   // statistics only
+                int64_t *rowoff = static_cast<int64_t *>(ws.rowoff.reserve((size_t)nb * sizeof(int64_t)));
+                n_big_rows += scan_total_i64(lens, rows, rowoff, nb, st);
+            }
+            n_big += nb;
         }
         int ec = tm.mark();
         if (q.w_out && !q.device_out)

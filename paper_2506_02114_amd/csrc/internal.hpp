@@ -90,9 +90,13 @@ struct LensConst {
     int32_t pad;
 };
 
-// a mapped triangle queued for the row-parallel IPM (pixel coordinates)
-struct BigTri {
-    double u0, v0, u1, v1, u2, v2;
+// per-triangle data of the row-parallel IPM: counter-clockwise vertices
+// relative to the integer origin (ou, ov), edge slopes sv = dv/du and
+// su = du/dv, and the deposit per unit of twice the piece area
+struct BigPrep {
+    double u[3], v[3];
+    double sv[3], su[3];
+    double ou, ov, scale;
 };
 
 // map geometry for the IPM, in pixel units
@@ -133,7 +137,7 @@ struct Workspace {
     DevBuf code, level, leaf, slo, shi, block, parent, child0, node_leaf, leaf_node, flags, offs;
     DevBuf ilist, mult, local, ops_m2m, ops_m2l, ops_l2l;
     DevBuf leaves, near, deriv, near_offs;
-    DevBuf tile_off, tile_leaf, verts, map, wbuf, pts, counters, bigq, bigrows, bigoff, diff;
+    DevBuf tile_off, tile_leaf, verts, map, wbuf, pts, counters, items, itemoff, nbig, bigoff, bigprep, bigrows, rowoff, nbnd, nbndoff, diff;
     void *pinned = nullptr;               // small pinned host buffer for read-backs
     size_t pinned_cap = 0;
     int ops_p = -1;                       // order the operator tables were built for
@@ -181,12 +185,14 @@ void launch_deflect_points(mlm_lens *lens, const Tree *T, const LensConst &lc, c
 
 // ipm.hip
 void launch_ipm(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int64_t vb0, const MapGeom &g,
-                double *map, unsigned long long *counters, BigTri *queue, int64_t queue_cap, hipStream_t st);
-void launch_big_rows(int64_t nq, const BigTri *tri, const MapGeom &g, int64_t *rows, hipStream_t st);
-void launch_big_apportion(int64_t total_rows, int64_t nq, const int64_t *row_off, const BigTri *tri,
-                          const MapGeom &g, double *map, double *diff, hipStream_t st);
+                double *map, unsigned long long *counters, int32_t *nbig, hipStream_t st);
+void launch_big_gather(int64_t ncells, const int64_t *boff, const double2 *verts, int64_t nr1, int64_t cb0,
+                       int64_t vb0, const MapGeom &g, BigPrep *prep, int64_t *rows, hipStream_t st);
+void launch_big(int64_t nbig, const BigPrep *prep, const int64_t *rows, const MapGeom &g, double *map, double *diff,
+                hipStream_t st);
 void launch_diff_rows(const MapGeom &g, const double *diff, double *map, hipStream_t st);
 int64_t scan_total_i64(mlm_lens *lens, const int64_t *in, int64_t *out, int64_t n, hipStream_t st);
+int64_t scan_i32_to_i64(mlm_lens *lens, const int32_t *in, int64_t *out, int64_t n, hipStream_t st);
 
 // helpers
 void *pinned(mlm_lens *lens, size_t bytes);

@@ -28,61 +28,50 @@ struct P2 {
     double u, v;
 };
 
-constexpr int64_t BIG_PIXELS = 48;   // bounding-box pixels above which a triangle is queued
+constexpr int64_t BIG_PIXELS = 48;   // bounding-box pixels above which a triangle goes row by row
 
-struct BigQueue {
-    BigTri *tri;
-    unsigned long long *count;
-    unsigned long long cap;
-};
 
-__device__ inline P2 lerp2(P2 P, P2 Q, double t)
-{
-    if (t == 0.0) return P;
-    if (t == 1.0) return Q;
-    return P2{P.u + t * (Q.u - P.u), P.v + t * (Q.v - P.v)};
-}
-
-// part of segment P->Q with lo <= coordinate <= hi (AXIS 0: u, 1: v)
+// Part of segment P->Q with lo <= coordinate <= hi (AXIS 0: u, 1: v).  The
+// segment lies on a line whose other coordinate changes by `slope` per unit of
+// the clipping coordinate, so a crossing is one multiply-add.
 template <int AXIS>
-__device__ inline bool clip_seg(P2 P, P2 Q, double lo, double hi, P2 &E, P2 &X)
+__device__ inline bool clip_seg(P2 P, P2 Q, double lo, double hi, double slope, P2 &E, P2 &X)
 {
     const double p = AXIS ? P.v : P.u, q = AXIS ? Q.v : Q.u;
+    const double po = AXIS ? P.u : P.v;
+    auto at = [&](double c) { return AXIS ? P2{po + (c - p) * slope, c} : P2{c, po + (c - p) * slope}; };
     if (p == q) {
         if (p < lo || p > hi) return false;
         E = P;
         X = Q;
         return true;
     }
-    const double inv = 1.0 / (q - p);
-    const double ta = (lo - p) * inv, tb = (hi - p) * inv;
-    double tin, tout, bin, bout;
     if (q > p) {
-        tin = ta; bin = lo; tout = tb; bout = hi;
+        if (q < lo || p > hi) return false;
+        E = p < lo ? at(lo) : P;
+        X = q > hi ? at(hi) : Q;
     } else {
-        tin = tb; bin = hi; tout = ta; bout = lo;
+        if (p < lo || q > hi) return false;
+        E = p > hi ? at(hi) : P;
+        X = q < lo ? at(lo) : Q;
     }
-    const bool cut_in = tin > 0.0, cut_out = tout < 1.0;
-    if (!cut_in) tin = 0.0;
-    if (!cut_out) tout = 1.0;
-    if (tin > tout) return false;
-    E = lerp2(P, Q, tin);
-    X = lerp2(P, Q, tout);
-    if (cut_in) { if (AXIS) E.v = bin; else E.u = bin; }
-    if (cut_out) { if (AXIS) X.v = bout; else X.u = bout; }
     return true;
 }
 
-// polygon of N slots clipped to a strip -> 2N slots; false if empty
+// polygon of N slots clipped to a strip -> 2N slots; false if empty.
+// slope[k] is edge k's rate of change of the other coordinate per unit of the
+// clipping coordinate.  In the output, edge 2k lies on input edge k and edge
+// 2k+1 on a strip boundary line (or has zero length).
 template <int AXIS, int N>
-__device__ inline bool clip_poly(const P2 (&in)[N], double lo, double hi, P2 (&out)[2 * N])
+__device__ inline bool clip_poly(const P2 (&in)[N], const double (&slope)[N], double lo, double hi,
+                                 P2 (&out)[2 * N])
 {
     P2 E[N], X[N];
     bool ok[N];
     bool any = false;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        ok[k] = clip_seg<AXIS>(in[k], in[(k + 1) % N], lo, hi, E[k], X[k]);
+        ok[k] = clip_seg<AXIS>(in[k], in[(k + 1) % N], lo, hi, slope[k], E[k], X[k]);
         any = any || ok[k];
     }
     if (!any) return false;
@@ -104,6 +93,78 @@ __device__ inline bool clip_poly(const P2 (&in)[N], double lo, double hi, P2 (&o
     return true;
 }
 
+// slopes of the 6 edges of a polygon made by clipping a triangle to a strip,
+// for a clip along the other axis: triangle edge k's slope on edge 2k, zero on
+// the strip-boundary edges 2k+1
+__device__ inline void slopes6(const double (&tri)[3], double (&s6)[6])
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        s6[2 * k] = tri[k];
+        s6[2 * k + 1] = 0.0;
+    }
+}
+
+// edge slopes of a triangle: sv = dv/du (for clips along u), su = du/dv (along v)
+__device__ inline void tri_slopes(const P2 (&T)[3], double (&sv)[3], double (&su)[3])
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double du = T[(k + 1) % 3].u - T[k].u, dv = T[(k + 1) % 3].v - T[k].v;
+        sv[k] = du != 0.0 ? dv / du : 0.0;
+        su[k] = dv != 0.0 ? du / dv : 0.0;
+    }
+}
+
+// integral over t in [0, 1] of max(ua + t (ub - ua), 0); inv = 1 / |ub - ua|
+// (unused when ua and ub have the same sign)
+__device__ inline double clamp_integral(double ua, double ub, double inv)
+{
+    const double m = fmax(ua, ub);
+    const double cross = 0.5 * m * m * inv;
+    return (ua >= 0.0 && ub >= 0.0) ? 0.5 * (ua + ub) : ((ua <= 0.0 && ub <= 0.0) ? 0.0 : cross);
+}
+
+// Pixel areas from the triangle's edges clipped to one strip.  For a strip of
+// pixel rows [v0, v0 + 1] and a polygon traversed counter-clockwise, the area
+// left of the line u = c is  G(c) = -sum_e dv_e * I(c - ua_e, c - ub_e), I the
+// clamp integral above; for a strip of columns and the line v = r, the area
+// below it is  H(r) = sum_e du_e * I(r - va_e, r - vb_e).  A pixel's area is
+// then a difference of two such sums.  (Clockwise triangles give the negated
+// area, matching the sign of their signed area.)
+struct Segs {
+    double a[3], b[3];       // coordinate across the strip at both ends (u for rows, v for columns)
+    double d[3];             // signed extent along the strip (dv for rows, du for columns)
+    double inv[3];           // 1 / |b - a| (0 if equal)
+};
+
+template <int AXIS>
+__device__ inline void strip_segments(const P2 (&T)[3], const double (&slope)[3], double lo, double hi, Segs &S)
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        P2 E, X;
+        if (clip_seg<AXIS>(T[k], T[(k + 1) % 3], lo, hi, slope[k], E, X)) {
+            S.a[k] = AXIS ? E.u : E.v;
+            S.b[k] = AXIS ? X.u : X.v;
+            S.d[k] = AXIS ? X.v - E.v : X.u - E.u;
+        } else {
+            S.a[k] = S.b[k] = S.d[k] = 0.0;
+        }
+        const double w = fabs(S.b[k] - S.a[k]);
+        S.inv[k] = w > 0.0 ? 1.0 / w : 0.0;
+    }
+}
+
+// sum_e d_e * I(c - a_e, c - b_e)
+__device__ inline double strip_cumulative(const Segs &S, double c)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s += S.d[k] * clamp_integral(c - S.a[k], c - S.b[k], S.inv[k]);
+    return s;
+}
+
 // twice the signed area (shoelace), coordinates taken relative to (ou, ov)
 template <int N>
 __device__ inline double shoelace2(const P2 (&p)[N], double ou, double ov)
@@ -123,177 +184,400 @@ __device__ inline void deposit(double *map, const MapGeom &g, int64_t i, int64_t
     unsafeAtomicAdd(map + j * (int64_t)g.n1 + i, val);
 }
 
-// apportion one triangle (pixel coordinates); weight = its image area / pixel area.
-// Triangles whose bounding box within the map exceeds BIG_PIXELS go to the
-// big-triangle queue (unless it is full).
-__device__ void apportion(P2 A, P2 B, P2 C, double weight, const MapGeom &g, double *map,
-                          unsigned long long *counters, BigQueue q)
+// wavefront-level load balancing: a wavefront owns 64 segments (cells, large
+// triangles or rows) with v items each; the exclusive scan of v over the
+// lanes numbers the items, and an item finds its segment by binary lifting
+// over the lanes' scan values (lane shuffles, no global memory)
+__device__ inline int wave_excl_scan(int v, int lane, int &total)
 {
-    if (!(isfinite(A.u) && isfinite(A.v) && isfinite(B.u) && isfinite(B.v) && isfinite(C.u) && isfinite(C.v))) {
-        atomicAdd(counters, 1ull);
-        return;
+    int incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
     }
+    total = __shfl(incl, 63, 64);
+    return incl - v;
+}
+
+// largest lane L with excl(L) <= x (excl non-decreasing over the lanes); the
+// segment of item x has at least one item since excl(L + 1) > x
+__device__ inline int wave_find(int excl, int x)
+{
+    int lo = 0;
+#pragma unroll
+    for (int step = 32; step >= 1; step >>= 1) {
+        const int e = __shfl(excl, lo + step, 64);
+        if (e <= x) lo += step;
+    }
+    return lo;
+}
+
+// Classification of one mapped triangle (pixel coordinates) for the cell pass.
+//   kind 0: nothing to deposit (outside the map, or skipped as non-finite)
+//   kind 1: one deposit (single pixel, or zero area -> its centroid's pixel)
+//   kind 2: `cols` pixel columns, each one work item of the column pass
+//   kind 3: large: goes to the row-parallel pass
+struct TriClass {
+    int kind;
+    int cols;
+    int64_t i0;           // first column inside the map
+    int64_t pi, pj;       // pixel of a kind-1 deposit (or -1: outside)
+};
+
+// twice the signed area of (A, B, C) in coordinates relative to (ou, ov),
+// evaluated as written so every kernel gets the same value
+__device__ inline double twice_area(P2 A, P2 B, P2 C, double ou, double ov)
+{
+#pragma clang fp contract(off)
+    const double au = A.u - ou, av = A.v - ov;
+    return ((B.u - ou) - au) * ((C.v - ov) - av) - ((C.u - ou) - au) * ((B.v - ov) - av);
+}
+
+__device__ inline TriClass classify(P2 A, P2 B, P2 C, const MapGeom &g)
+{
+    TriClass c{0, 0, 0, -1, -1};
+    if (!(isfinite(A.u) && isfinite(A.v) && isfinite(B.u) && isfinite(B.v) && isfinite(C.u) && isfinite(C.v)))
+        return c;
     const double umin = fmin(A.u, fmin(B.u, C.u)), umax = fmax(A.u, fmax(B.u, C.u));
     const double vmin = fmin(A.v, fmin(B.v, C.v)), vmax = fmax(A.v, fmax(B.v, C.v));
     const double fu0 = floor(umin), fu1 = floor(umax), fv0 = floor(vmin), fv1 = floor(vmax);
-    // entirely outside the map
-    if (fu1 < 0.0 || fv1 < 0.0 || fu0 > (double)(g.n1 - 1) || fv0 > (double)(g.n2 - 1)) return;
+    if (fu1 < 0.0 || fv1 < 0.0 || fu0 > (double)(g.n1 - 1) || fv0 > (double)(g.n2 - 1)) return c;
     if (fu0 == fu1 && fv0 == fv1) {
-        deposit(map, g, (int64_t)fu0, (int64_t)fv0, weight);
-        return;
+        c.kind = 1;
+        c.pi = (int64_t)fu0;
+        c.pj = (int64_t)fv0;
+        return c;
     }
-    // local coordinates relative to the bounding box's lower-left pixel corner
-    const P2 T[3] = {P2{A.u - fu0, A.v - fv0}, P2{B.u - fu0, B.v - fv0}, P2{C.u - fu0, C.v - fv0}};
-    const double S2 = (T[1].u - T[0].u) * (T[2].v - T[0].v) - (T[2].u - T[0].u) * (T[1].v - T[0].v);
-    if (S2 == 0.0) {
+    if (twice_area(A, B, C, fu0, fv0) == 0.0) {
         // no source-plane area: the whole image area goes to the centroid's pixel
-        const double cu = (A.u + B.u + C.u) / 3.0, cv = (A.v + B.v + C.v) / 3.0;
-        const double fi = floor(cu), fj = floor(cv);
-        if (fi >= 0.0 && fj >= 0.0 && fi <= (double)(g.n1 - 1) && fj <= (double)(g.n2 - 1))
-            deposit(map, g, (int64_t)fi, (int64_t)fj, weight);
-        return;
+        const double fi = floor((A.u + B.u + C.u) / 3.0), fj = floor((A.v + B.v + C.v) / 3.0);
+        c.kind = 1;
+        if (fi >= 0.0 && fj >= 0.0 && fi <= (double)(g.n1 - 1) && fj <= (double)(g.n2 - 1)) {
+            c.pi = (int64_t)fi;
+            c.pj = (int64_t)fj;
+        }
+        return c;
     }
-    const double scale = weight / S2;
     const int64_t i0 = (int64_t)fmax(fu0, 0.0), i1 = (int64_t)fmin(fu1, (double)(g.n1 - 1));
     const int64_t j0 = (int64_t)fmax(fv0, 0.0), j1 = (int64_t)fmin(fv1, (double)(g.n2 - 1));
     if ((i1 - i0 + 1) * (j1 - j0 + 1) > BIG_PIXELS) {
-        unsigned long long k = atomicAdd(q.count, 1ull);
-        if (k < q.cap) {
-            q.tri[k] = BigTri{A.u, A.v, B.u, B.v, C.u, C.v};
-            return;
-        }
-        atomicAdd(counters + 3, 1ull);   // queue full: apportion here
+        c.kind = 3;
+        return c;
     }
-    for (int64_t i = i0; i <= i1; ++i) {
-        const double cl = (double)i - fu0;
-        P2 col[6];
-        if (!clip_poly<0, 3>(T, cl, cl + 1.0, col)) continue;
-        double cvmin = col[0].v, cvmax = col[0].v;
+    c.kind = 2;
+    c.cols = (int)(i1 - i0 + 1);
+    c.i0 = i0;
+    return c;
+}
+
+__device__ inline void load_cell(const double2 *verts, int64_t nr1, int64_t cb0, int64_t vb0, int64_t cell,
+                                 P2 &v00, P2 &v10, P2 &v11, P2 &v01)
+{
+    const int64_t ncol = nr1 - 1;
+    const int64_t a = cell % ncol, b = cb0 + cell / ncol;
+    const double2 *r0 = verts + (b - vb0) * nr1, *r1 = r0 + nr1;
+    const double2 q00 = r0[a], q10 = r0[a + 1], q01 = r1[a], q11 = r1[a + 1];
+    v00 = P2{q00.x, q00.y};
+    v10 = P2{q10.x, q10.y};
+    v11 = P2{q11.x, q11.y};
+    v01 = P2{q01.x, q01.y};
+}
+
+__device__ inline bool cell_in_one_pixel(P2 v00, P2 v10, P2 v11, P2 v01, const MapGeom &g, int64_t &pi, int64_t &pj)
+{
+    const double fu = floor(v00.u), fv = floor(v00.v);
+    if (!(floor(v10.u) == fu && floor(v11.u) == fu && floor(v01.u) == fu && floor(v10.v) == fv &&
+          floor(v11.v) == fv && floor(v01.v) == fv))
+        return false;
+    pi = pj = -1;
+    if (fu >= 0.0 && fv >= 0.0 && fu <= (double)(g.n1 - 1) && fv <= (double)(g.n2 - 1)) {
+        pi = (int64_t)fu;
+        pj = (int64_t)fv;
+    }
+    return true;
+}
+
+// one pixel column `r` (counted over the cell's triangles that need clipping)
+// of cell `cell`: clip the triangle to the column, then to each pixel row
+__device__ void cell_column(const double2 *verts, int64_t nr1, int64_t cb0, int64_t vb0, int64_t cell, int r,
+                            const MapGeom &g, double *map)
+{
+    P2 v00, v10, v11, v01;
+    load_cell(verts, nr1, cb0, vb0, cell, v00, v10, v11, v01);
+    const TriClass k1 = classify(v00, v10, v11, g);
+    P2 A, B, C;
+    int64_t i0;
+    if (k1.kind == 2 && r < k1.cols) {
+        A = v00; B = v10; C = v11;
+        i0 = k1.i0;
+    } else {
+        if (k1.kind == 2) r -= k1.cols;
+        const TriClass k2 = classify(v00, v11, v01, g);
+        if (k2.kind != 2 || r >= k2.cols) return;   // never: the items were counted from the same values
+        A = v00; B = v11; C = v01;
+        i0 = k2.i0;
+    }
+    const double fu0 = floor(fmin(A.u, fmin(B.u, C.u))), fv0 = floor(fmin(A.v, fmin(B.v, C.v)));
+    const double fv1 = floor(fmax(A.v, fmax(B.v, C.v)));
+    const P2 T[3] = {P2{A.u - fu0, A.v - fv0}, P2{B.u - fu0, B.v - fv0}, P2{C.u - fu0, C.v - fv0}};
+    const double scale = g.tri_weight / twice_area(A, B, C, fu0, fv0);
+    const int64_t j0 = (int64_t)fmax(fv0, 0.0), j1 = (int64_t)fmin(fv1, (double)(g.n2 - 1));
+    const int64_t i = i0 + r;
+    double sv[3], su[3];
+    tri_slopes(T, sv, su);
+    const double cl = (double)i - fu0;
+    Segs S;
+    strip_segments<0>(T, sv, cl, cl + 1.0, S);
+    double cvmin = 1e300, cvmax = -1e300;
 #pragma unroll
-        for (int k = 1; k < 6; ++k) {
-            cvmin = fmin(cvmin, col[k].v);
-            cvmax = fmax(cvmax, col[k].v);
+    for (int k = 0; k < 3; ++k)
+        if (S.d[k] != 0.0 || S.a[k] != S.b[k]) {
+            cvmin = fmin(cvmin, fmin(S.a[k], S.b[k]));
+            cvmax = fmax(cvmax, fmax(S.a[k], S.b[k]));
         }
-        const double gj0 = floor(cvmin), gj1 = floor(cvmax);
-        if (gj0 == gj1) {
-            const int64_t j = (int64_t)gj0 + (int64_t)fv0;
-            if (j >= j0 && j <= j1) deposit(map, g, i, j, scale * shoelace2(col, cl, gj0));
-            continue;
-        }
-        const int64_t ja = (int64_t)fmax(gj0 + fv0, (double)j0), jb = (int64_t)fmin(gj1 + fv0, (double)j1);
-        for (int64_t j = ja; j <= jb; ++j) {
-            const double rl = (double)j - fv0;
-            P2 piece[12];
-            if (!clip_poly<1, 6>(col, rl, rl + 1.0, piece)) continue;
-            const double a2 = shoelace2(piece, cl, rl);
-            if (a2 != 0.0) deposit(map, g, i, j, scale * a2);
-        }
+    if (cvmin > cvmax) return;
+    // area below v = r inside the column; a piece is the difference of two
+    const int64_t ja = (int64_t)fmax(floor(cvmin) + fv0, (double)j0);
+    const int64_t jb = (int64_t)fmin(floor(cvmax) + fv0, (double)j1);
+    double h0 = strip_cumulative(S, (double)ja - fv0);
+    for (int64_t j = ja; j <= jb; ++j) {
+        const double h1 = strip_cumulative(S, (double)(j + 1) - fv0);
+        const double a2 = 2.0 * (h1 - h0);   // twice the piece area, signed like the triangle
+        h0 = h1;
+        if (a2 != 0.0) deposit(map, g, i, j, scale * a2);
     }
 }
 
-// one thread per grid cell of cell rows [cb0, cb1)
+// IPM of the ordinary triangles: one thread per cell for single-pixel
+// deposits and classification (cell (a, b) splits along v00-v11 into
+// T1 = (v00, v10, v11) and T2 = (v00, v11, v01)), then the wavefront's pixel
+// columns spread evenly over its lanes.  Large triangles are only counted here.
 __global__ __launch_bounds__(256) void k_ipm(const double2 *__restrict__ verts, int64_t nr1, int64_t cb0,
                                              int64_t ncells, int64_t vb0, MapGeom g, double *__restrict__ map,
-                                             unsigned long long *__restrict__ counters, BigQueue q)
+                                             unsigned long long *__restrict__ counters, int32_t *__restrict__ nbig)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wave0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+    const int64_t t = wave0 + lane;
+    int cnt = 0;
+    if (t < ncells) {
+        P2 v00, v10, v11, v01;
+        load_cell(verts, nr1, cb0, vb0, t, v00, v10, v11, v01);
+        int64_t pi, pj;
+        int nb = 0;
+        if (cell_in_one_pixel(v00, v10, v11, v01, g, pi, pj)) {
+            if (pi >= 0) deposit(map, g, pi, pj, 2.0 * g.tri_weight);
+        } else {
+            const P2 tri[2][3] = {{v00, v10, v11}, {v00, v11, v01}};
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const P2 A = tri[k][0], B = tri[k][1], C = tri[k][2];
+                const TriClass c = classify(A, B, C, g);
+                if (c.kind == 0) {
+                    if (!(isfinite(A.u) && isfinite(A.v) && isfinite(B.u) && isfinite(B.v) && isfinite(C.u) &&
+                          isfinite(C.v)))
+                        atomicAdd(counters, 1ull);
+                } else if (c.kind == 1) {
+                    if (c.pi >= 0) deposit(map, g, c.pi, c.pj, g.tri_weight);
+                } else if (c.kind == 2) {
+                    cnt += c.cols;
+                } else {
+                    ++nb;
+                }
+            }
+        }
+        nbig[t] = nb;
+    }
+    int total;
+    const int excl = wave_excl_scan(cnt, lane, total);
+    for (int base = 0; base < total; base += 64) {
+        const int item = base + lane;
+        const int L = wave_find(excl, item);
+        const int r = item - __shfl(excl, L, 64);
+        if (item < total) cell_column(verts, nr1, cb0, vb0, wave0 + L, r, g, map);
+    }
+}
+
+// set-up of every large triangle, written at its slot of the exclusive scan
+// of the per-cell counts: integer local origin (inside or at the edge of the
+// map, so nearby pixel boundaries are exact), counter-clockwise local
+// vertices, edge slopes, the deposit scale, and the pixel rows it covers
+__global__ __launch_bounds__(256) void k_big_gather(int64_t ncells, const int64_t *__restrict__ boff,
+                                                    const double2 *__restrict__ verts, int64_t nr1, int64_t cb0,
+                                                    int64_t vb0, MapGeom g, BigPrep *__restrict__ prep,
+                                                    int64_t *__restrict__ rows)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ncells) return;
-    const int64_t ncol = nr1 - 1;
-    const int64_t a = t % ncol, b = cb0 + t / ncol;
-    const double2 *r0 = verts + (b - vb0) * nr1, *r1 = r0 + nr1;
-    const double2 q00 = r0[a], q10 = r0[a + 1], q01 = r1[a], q11 = r1[a + 1];
-    const P2 v00{q00.x, q00.y}, v10{q10.x, q10.y}, v11{q11.x, q11.y}, v01{q01.x, q01.y};
-    // both triangles inside one pixel: one deposit for the cell
-    const double fu = floor(v00.u), fv = floor(v00.v);
-    if (floor(v10.u) == fu && floor(v11.u) == fu && floor(v01.u) == fu && floor(v10.v) == fv &&
-        floor(v11.v) == fv && floor(v01.v) == fv) {
-        if (fu >= 0.0 && fv >= 0.0 && fu <= (double)(g.n1 - 1) && fv <= (double)(g.n2 - 1))
-            deposit(map, g, (int64_t)fu, (int64_t)fv, 2.0 * g.tri_weight);
-        return;
-    }
-    // T1 = (v00, v10, v11), T2 = (v00, v11, v01): split along v00-v11
-    apportion(v00, v10, v11, g.tri_weight, g, map, counters, q);
-    apportion(v00, v11, v01, g.tri_weight, g, map, counters, q);
-}
-
-// pixel rows of each queued triangle inside the map
-__global__ void k_big_rows(int64_t nq, const BigTri *__restrict__ tri, MapGeom g, int64_t *__restrict__ rows)
-{
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nq) return;
-    const BigTri t = tri[k];
-    const double vmin = fmin(t.v0, fmin(t.v1, t.v2)), vmax = fmax(t.v0, fmax(t.v1, t.v2));
-    const double j0 = fmax(floor(vmin), 0.0), j1 = fmin(floor(vmax), (double)(g.n2 - 1));
-    rows[k] = j1 >= j0 ? (int64_t)(j1 - j0) + 1 : 0;
-}
-
-// one (queued triangle, pixel row) per thread
-__global__ __launch_bounds__(256) void k_big_apportion(int64_t total, int64_t nq, const int64_t *__restrict__ row_off,
-                                                       const BigTri *__restrict__ tri, MapGeom g,
-                                                       double *__restrict__ map, double *__restrict__ diff)
-{
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= total) return;
-    const int64_t k = upper_bound_i64<int64_t>(row_off, nq, t) - 1;
-    const BigTri bt = tri[k];
-    const double umin = fmin(bt.u0, fmin(bt.u1, bt.u2)), vmin = fmin(bt.v0, fmin(bt.v1, bt.v2));
-    // integer local origin inside or at the edge of the map: exact pixel boundaries nearby
-    const double ou = fmax(floor(umin), 0.0), ov = fmax(floor(vmin), 0.0);
-    const int64_t j = (int64_t)ov + (t - row_off[k]);
-    P2 T[3] = {P2{bt.u0 - ou, bt.v0 - ov}, P2{bt.u1 - ou, bt.v1 - ov}, P2{bt.u2 - ou, bt.v2 - ov}};
-    double S2 = (T[1].u - T[0].u) * (T[2].v - T[0].v) - (T[2].u - T[0].u) * (T[1].v - T[0].v);
-    if (S2 < 0.0) {   // counter-clockwise order: interior to the left of every edge
-        const P2 tmp = T[1];
-        T[1] = T[2];
-        T[2] = tmp;
-        S2 = -S2;
-    }
-    const double scale = g.tri_weight / S2;   // deposit = scale * (twice the piece area)
-    const double rl = (double)j - ov;
-    P2 row[6];
-    if (!clip_poly<1, 3>(T, rl, rl + 1.0, row)) return;
-    double rumin = row[0].u, rumax = row[0].u;
+    int64_t slot = boff[t];
+    if (boff[t + 1] == slot) return;
+    P2 v00, v10, v11, v01;
+    load_cell(verts, nr1, cb0, vb0, t, v00, v10, v11, v01);
+    const P2 tri[2][3] = {{v00, v10, v11}, {v00, v11, v01}};
+    const int64_t end = boff[t + 1];
+    for (int k = 0; k < 2 && slot < end; ++k) {
+        const P2 A = tri[k][0], B = tri[k][1], C = tri[k][2];
+        if (classify(A, B, C, g).kind != 3) continue;
+        const double umin = fmin(A.u, fmin(B.u, C.u));
+        const double vmin = fmin(A.v, fmin(B.v, C.v)), vmax = fmax(A.v, fmax(B.v, C.v));
+        const double ou = fmax(floor(umin), 0.0), ov = fmax(floor(vmin), 0.0);
+        P2 T[3] = {P2{A.u - ou, A.v - ov}, P2{B.u - ou, B.v - ov}, P2{C.u - ou, C.v - ov}};
+        double S2 = twice_area(A, B, C, ou, ov);
+        if (S2 < 0.0) {   // counter-clockwise: the interior is left of every edge
+            const P2 tmp = T[1];
+            T[1] = T[2];
+            T[2] = tmp;
+            S2 = -S2;
+        }
+        BigPrep bp;
+        double sv[3], su[3];
+        tri_slopes(T, sv, su);
 #pragma unroll
-    for (int m = 1; m < 6; ++m) {
-        rumin = fmin(rumin, row[m].u);
-        rumax = fmax(rumax, row[m].u);
+        for (int m = 0; m < 3; ++m) {
+            bp.u[m] = T[m].u;
+            bp.v[m] = T[m].v;
+            bp.sv[m] = sv[m];
+            bp.su[m] = su[m];
+        }
+        bp.ou = ou;
+        bp.ov = ov;
+        bp.scale = g.tri_weight / S2;
+        prep[slot] = bp;
+        const double j1 = fmin(floor(vmax), (double)(g.n2 - 1));
+        rows[slot] = j1 >= ov ? (int64_t)(j1 - ov) + 1 : 0;
+        ++slot;
     }
-    const double ga = fmax(floor(rumin), -ou), gb = fmin(floor(rumax), (double)(g.n1 - 1) - ou);
-    if (ga > gb) return;
-    // pixels of this row fully inside the triangle: every corner on the inner
-    // side of each edge (local pixel indices)
+}
+
+// The edges of a large triangle clipped to pixel row j (local coordinates),
+// the row's column range [ga, gb] inside the map and the run [pa, pb] of
+// pixels fully inside the triangle (local column indices; pa > pb: none);
+// false if the row holds nothing
+struct RowInfo {
+    Segs S;
+    double rl;
+    int64_t ga, gb, pa, pb;
+};
+
+__device__ inline bool row_info(const BigPrep &bp, int64_t j, const MapGeom &g, RowInfo &ri)
+{
+    const P2 T[3] = {P2{bp.u[0], bp.v[0]}, P2{bp.u[1], bp.v[1]}, P2{bp.u[2], bp.v[2]}};
+    const double su[3] = {bp.su[0], bp.su[1], bp.su[2]};
+    ri.rl = (double)j - bp.ov;
+    const double rl = ri.rl;
+    strip_segments<1>(T, su, rl, rl + 1.0, ri.S);
+    double rumin = 1e300, rumax = -1e300;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        if (ri.S.d[k] != 0.0 || ri.S.a[k] != ri.S.b[k]) {
+            rumin = fmin(rumin, fmin(ri.S.a[k], ri.S.b[k]));
+            rumax = fmax(rumax, fmax(ri.S.a[k], ri.S.b[k]));
+        }
+    if (rumin > rumax) return false;
+    const double ga = fmax(floor(rumin), -bp.ou), gb = fmin(floor(rumax), (double)(g.n1 - 1) - bp.ou);
+    if (ga > gb) return false;
+    // a pixel is fully inside when every corner is on the inner side of each edge
     double fa = -1e300, fb = 1e300;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
         const P2 P = T[m], Q = T[(m + 1) % 3];
         const double dx = Q.u - P.u, dy = Q.v - P.v;
         const double vc = dx > 0.0 ? rl : rl + 1.0;
-        const double base = dx * (vc - P.v);
-        if (dy > 0.0) fb = fmin(fb, floor(P.u - 1.0 + base / dy));
-        else if (dy < 0.0) fa = fmax(fa, ceil(P.u - base / (-dy)));
-        else if (base < 0.0) fa = 1e300;
+        const double off = (vc - P.v) * su[m];   // dx (vc - P.v) / dy
+        if (dy > 0.0) fb = fmin(fb, floor(P.u - 1.0 + off));
+        else if (dy < 0.0) fa = fmax(fa, ceil(P.u + off));
+        else if (dx * (vc - P.v) < 0.0) fa = 1e300;
     }
     fa = fmax(fa, ga);
     fb = fmin(fb, gb);
-    const bool has_full = fa <= fb;
-    const int64_t ia = (int64_t)ga, ib = (int64_t)gb;
-    const int64_t pa = has_full ? (int64_t)fa : ib + 1, pb = has_full ? (int64_t)fb : ib;
-    // boundary pixels: exact clip of the row polygon to the pixel column
-    for (int64_t i = ia; i <= ib; ++i) {
-        if (i == pa && has_full) {
-            i = pb;
-            continue;
-        }
-        const double cl = (double)i;
-        P2 piece[12];
-        if (!clip_poly<0, 6>(row, cl, cl + 1.0, piece)) continue;
-        const double a2 = shoelace2(piece, cl, rl);
-        if (a2 != 0.0) deposit(map, g, i + (int64_t)ou, j, scale * a2);
+    ri.ga = (int64_t)ga;
+    ri.gb = (int64_t)gb;
+    if (fa <= fb) {
+        ri.pa = (int64_t)fa;
+        ri.pb = (int64_t)fb;
+    } else {
+        ri.pa = ri.gb + 1;
+        ri.pb = ri.gb;
     }
-    if (has_full) {
-        double *dr = diff + j * (int64_t)(g.n1 + 1) + (int64_t)ou;
-        unsafeAtomicAdd(dr + pa, 2.0 * scale);
-        unsafeAtomicAdd(dr + pb + 1, -2.0 * scale);
+    return true;
+}
+
+// IPM of the large triangles: a wavefront owns 64 of them; their pixel rows
+// are spread over its lanes (fully covered runs go to the difference buffer),
+// then the boundary pixels of those 64 rows, whose row polygons the lanes
+// share through the wavefront's slots in LDS
+struct RowSlot {
+    Segs S;
+    double ou, scale;
+    int64_t j, ga, pa, pb, gb;
+};
+
+__global__ __launch_bounds__(256) void k_big(int64_t nbig, const BigPrep *__restrict__ prep,
+                                             const int64_t *__restrict__ rows, MapGeom g, double *__restrict__ map,
+                                             double *__restrict__ diff)
+{
+    __shared__ RowSlot slots[256];
+    const int lane = threadIdx.x & 63;
+    const int64_t wave0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+    const int64_t k = wave0 + lane;
+    RowSlot *ws = slots + (threadIdx.x & ~63);
+    const int nrow = k < nbig ? (int)rows[k] : 0;
+    int rtotal;
+    const int rexcl = wave_excl_scan(nrow, lane, rtotal);
+    for (int rbase = 0; rbase < rtotal; rbase += 64) {
+        const int ritem = rbase + lane;
+        const int L = wave_find(rexcl, ritem);
+        const int rr = ritem - __shfl(rexcl, L, 64);
+        int np = 0;
+        if (ritem < rtotal) {
+            const BigPrep bp = prep[wave0 + L];
+            const int64_t j = (int64_t)bp.ov + rr;
+            RowInfo ri;
+            if (row_info(bp, j, g, ri)) {
+                const bool full = ri.pa <= ri.pb;
+                np = (int)(full ? (ri.pa - ri.ga) + (ri.gb - ri.pb) : ri.gb - ri.ga + 1);
+                if (full) {
+                    double *dr = diff + j * (int64_t)(g.n1 + 1) + (int64_t)bp.ou;
+                    unsafeAtomicAdd(dr + ri.pa, 2.0 * bp.scale);
+                    unsafeAtomicAdd(dr + ri.pb + 1, -2.0 * bp.scale);
+                }
+                RowSlot &sl = ws[lane];
+                sl.S = ri.S;
+                sl.ou = bp.ou;
+                sl.scale = bp.scale;
+                sl.j = j;
+                sl.ga = ri.ga;
+                sl.pa = ri.pa;
+                sl.pb = ri.pb;
+                sl.gb = ri.gb;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        int ptotal;
+        const int pexcl = wave_excl_scan(np, lane, ptotal);
+        for (int pbase = 0; pbase < ptotal; pbase += 64) {
+            const int pitem = pbase + lane;
+            const int M = wave_find(pexcl, pitem);
+            const int64_t r = pitem - __shfl(pexcl, M, 64);
+            if (pitem < ptotal) {
+                const RowSlot &sl = ws[M];
+                int64_t i;
+                if (sl.pa <= sl.pb) i = (r < sl.pa - sl.ga) ? sl.ga + r : sl.pb + 1 + (r - (sl.pa - sl.ga));
+                else i = sl.ga + r;
+                if (i >= sl.ga && i <= sl.gb) {
+                    const Segs S = sl.S;
+                    // twice the area: 2 (G(i + 1) - G(i)), G(c) = -sum dv I(c - ua, c - ub)
+                    const double a2 = 2.0 * (strip_cumulative(S, (double)i) - strip_cumulative(S, (double)(i + 1)));
+                    if (a2 != 0.0) deposit(map, g, i + (int64_t)sl.ou, sl.j, sl.scale * a2);
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
@@ -322,26 +606,27 @@ __global__ __launch_bounds__(64) void k_diff_rows(MapGeom g, const double *__res
 }  // namespace
 
 void launch_ipm(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int64_t vb0, const MapGeom &g,
-                double *map, unsigned long long *counters, BigTri *queue, int64_t queue_cap, hipStream_t st)
+                double *map, unsigned long long *counters, int32_t *nbig, hipStream_t st)
 {
     int64_t ncells = (nr1 - 1) * (cb1 - cb0);
     if (ncells <= 0) return;
-    BigQueue q{queue, counters + 4, (unsigned long long)queue_cap};
     hipLaunchKernelGGL(k_ipm, dim3((unsigned)((ncells + 255) / 256)), dim3(256), 0, st, verts, nr1, cb0, ncells, vb0,
-                       g, map, counters, q);
+                       g, map, counters, nbig);
 }
 
-void launch_big_rows(int64_t nq, const BigTri *tri, const MapGeom &g, int64_t *rows, hipStream_t st)
+void launch_big_gather(int64_t ncells, const int64_t *boff, const double2 *verts, int64_t nr1, int64_t cb0,
+                       int64_t vb0, const MapGeom &g, BigPrep *prep, int64_t *rows, hipStream_t st)
 {
-    if (nq > 0) hipLaunchKernelGGL(k_big_rows, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, nq, tri, g, rows);
+    if (ncells > 0)
+        hipLaunchKernelGGL(k_big_gather, dim3((unsigned)((ncells + 255) / 256)), dim3(256), 0, st, ncells, boff, verts,
+                           nr1, cb0, vb0, g, prep, rows);
 }
 
-void launch_big_apportion(int64_t total_rows, int64_t nq, const int64_t *row_off, const BigTri *tri, const MapGeom &g,
-                          double *map, double *diff, hipStream_t st)
+void launch_big(int64_t nbig, const BigPrep *prep, const int64_t *rows, const MapGeom &g, double *map, double *diff,
+                hipStream_t st)
 {
-    if (total_rows > 0)
-        hipLaunchKernelGGL(k_big_apportion, dim3((unsigned)((total_rows + 255) / 256)), dim3(256), 0, st, total_rows,
-                           nq, row_off, tri, g, map, diff);
+    if (nbig > 0)
+        hipLaunchKernelGGL(k_big, dim3((unsigned)((nbig + 255) / 256)), dim3(256), 0, st, nbig, prep, rows, g, map, diff);
 }
 
 void launch_diff_rows(const MapGeom &g, const double *diff, double *map, hipStream_t st)

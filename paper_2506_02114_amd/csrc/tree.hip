@@ -110,6 +110,8 @@ __global__ void k_leaf_index(int64_t nnodes, const int32_t *__restrict__ leaf,
     }
 }
 
+__global__ void k_zero_first(int64_t *p) { p[0] = 0; }
+
 struct LevelRanges {
     int64_t lo[KEY_BITS + 2], hi[KEY_BITS + 2];
 };
@@ -209,6 +211,23 @@ int64_t scan_total(mlm_lens *lens, const int32_t *in, int32_t *out, int64_t n, h
 int64_t scan_total_public(mlm_lens *lens, const int32_t *in, int32_t *out, int64_t n, hipStream_t st)
 {
     return scan_total(lens, in, out, n, st);
+}
+
+// exclusive prefix sum of n int32 counts into n + 1 int64 offsets (the last
+// one is the total, which is returned)
+int64_t scan_i32_to_i64(mlm_lens *lens, const int32_t *in, int64_t *out, int64_t n, hipStream_t st)
+{
+    Workspace &ws = lens->ws;
+    if (n == 0) return 0;
+    size_t tb = 0;
+    MLM_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, tb, in, out + 1, (int)n, st));
+    void *tmp = cub_tmp(ws, tb);
+    hipLaunchKernelGGL(k_zero_first, dim3(1), dim3(1), 0, st, out);
+    MLM_HIP(hipcub::DeviceScan::InclusiveSum(tmp, tb, in, out + 1, (int)n, st));
+    int64_t *h = static_cast<int64_t *>(pinned(lens, sizeof(int64_t)));
+    MLM_HIP(hipMemcpyAsync(h, out + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    MLM_HIP(hipStreamSynchronize(st));
+    return h[0];
 }
 
 // exclusive prefix sum of n int64 values; returns the total
