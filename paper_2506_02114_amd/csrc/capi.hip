@@ -83,6 +83,12 @@ __global__ void k_zero_u64(unsigned long long *p, int n)
     if (threadIdx.x < n) p[threadIdx.x] = 0;
 }
 
+__global__ void k_zero_i32(int32_t *p, int64_t n)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0;
+}
+
 // ray-star pairs and rays of a strip (for the statistics)
 __global__ void k_strip_work(int64_t nleaves, const LeafInfo *__restrict__ lv, unsigned long long *cnt)
 {
@@ -440,7 +446,25 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
             BigPrep *prep = static_cast<BigPrep *>(ws.bigprep.reserve((size_t)nb * sizeof(BigPrep)));
             int64_t *rows = static_cast<int64_t *>(ws.bigrows.reserve((size_t)nb * sizeof(int64_t)));
             launch_big_gather(ncells, bigoff, verts, R.nr1, r0, vb0, g, prep, rows, st);
-            launch_big(nb, prep, rows, g, map, diff, st);
+            const int bh = band_height(g.n1, g.n2);
+            if (bh > 0) {
+                // large triangles by pixel bands: owned rows, LDS accumulation
+                const int32_t nbands = (int32_t)((g.n2 + bh - 1) / bh);
+                int32_t *bcnt = static_cast<int32_t *>(ws.bandcnt.reserve((size_t)nbands * sizeof(int32_t)));
+                unsigned long long *boffs =
+                    static_cast<unsigned long long *>(ws.bandoff.reserve((size_t)(nbands + 1) * sizeof(unsigned long long)));
+                unsigned long long *bcur =
+                    static_cast<unsigned long long *>(ws.bandcur.reserve((size_t)(nbands + 1) * sizeof(unsigned long long)));
+                hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((nbands + 255) / 256)), dim3(256), 0, st, bcnt, nbands);
+                launch_band_count(nb, prep, rows, bh, nbands, bcnt, st);
+                const int64_t nlist = scan_i32_to_u64(lens, bcnt, boffs, nbands, st);
+                int32_t *blist = static_cast<int32_t *>(ws.bandlist.reserve((size_t)(nlist > 0 ? nlist : 1) * sizeof(int32_t)));
+                MLM_HIP(hipMemcpyAsync(bcur, boffs, (size_t)nbands * sizeof(unsigned long long), hipMemcpyDeviceToDevice, st));
+                launch_band_scatter(nb, prep, rows, bh, nbands, bcur, blist, st);
+                launch_band(nbands, boffs, blist, prep, rows, bh, g, map, st);
+            } else {
+                launch_big(nb, prep, rows, g, map, diff, st);
+            }
             if (q.timing) {   // statistics only
                 int64_t *rowoff = static_cast<int64_t *>(ws.rowoff.reserve((size_t)nb * sizeof(int64_t)));
                 n_big_rows += scan_total_i64(lens, rows, rowoff, nb, st);

@@ -137,7 +137,8 @@ struct Workspace {
     DevBuf code, level, leaf, slo, shi, block, parent, child0, node_leaf, leaf_node, flags, offs;
     DevBuf ilist, mult, local, ops_m2m, ops_m2l, ops_l2l;
     DevBuf leaves, near, deriv, near_offs;
-    DevBuf tile_off, tile_leaf, verts, map, wbuf, pts, counters, items, itemoff, nbig, bigoff, bigprep, bigrows, rowoff, nbnd, nbndoff, diff;
+    DevBuf tile_off, tile_leaf, verts, map, wbuf, pts, counters, items, itemoff, nbig, bigoff, bigprep, bigrows, rowoff, nbnd, nbndoff, diff, bandcnt, bandoff,
+        bandcur, bandlist;
     void *pinned = nullptr;               // small pinned host buffer for read-backs
     size_t pinned_cap = 0;
     int ops_p = -1;                       // order the operator tables were built for
@@ -191,6 +192,14 @@ void launch_big_gather(int64_t ncells, const int64_t *boff, const double2 *verts
 void launch_big(int64_t nbig, const BigPrep *prep, const int64_t *rows, const MapGeom &g, double *map, double *diff,
                 hipStream_t st);
 void launch_diff_rows(const MapGeom &g, const double *diff, double *map, hipStream_t st);
+int band_height(int32_t n1, int32_t n2);
+void launch_band_count(int64_t nbig, const BigPrep *prep, const int64_t *rows, int bh, int32_t nbands, int32_t *count,
+                       hipStream_t st);
+void launch_band_scatter(int64_t nbig, const BigPrep *prep, const int64_t *rows, int bh, int32_t nbands,
+                         unsigned long long *cursor, int32_t *list, hipStream_t st);
+void launch_band(int32_t nbands, const unsigned long long *band_off, const int32_t *list, const BigPrep *prep,
+                 const int64_t *rows, int bh, const MapGeom &g, double *map, hipStream_t st);
+int64_t scan_i32_to_u64(mlm_lens *lens, const int32_t *in, unsigned long long *out, int64_t n, hipStream_t st);
 int64_t scan_total_i64(mlm_lens *lens, const int64_t *in, int64_t *out, int64_t n, hipStream_t st);
 int64_t scan_i32_to_i64(mlm_lens *lens, const int32_t *in, int64_t *out, int64_t n, hipStream_t st);
 

@@ -184,6 +184,22 @@ __device__ inline void deposit(double *map, const MapGeom &g, int64_t i, int64_t
     unsafeAtomicAdd(map + j * (int64_t)g.n1 + i, val);
 }
 
+// pixel window of a workgroup in LDS: deposits inside it are summed there and
+// added to the map once per pixel at the end; the rest go straight to the map
+constexpr int WIN = 64;   // window side in pixels (WIN x WIN doubles)
+
+struct Window {
+    double *acc;          // WIN x WIN, row-major
+    int64_t i0, j0;       // map pixel of acc[0]
+};
+
+__device__ inline void deposit_w(const Window &w, double *map, const MapGeom &g, int64_t i, int64_t j, double val)
+{
+    const int64_t di = i - w.i0, dj = j - w.j0;
+    if ((uint64_t)di < (uint64_t)WIN && (uint64_t)dj < (uint64_t)WIN) atomicAdd(w.acc + dj * WIN + di, val);
+    else deposit(map, g, i, j, val);
+}
+
 // wavefront-level load balancing: a wavefront owns 64 segments (cells, large
 // triangles or rows) with v items each; the exclusive scan of v over the
 // lanes numbers the items, and an item finds its segment by binary lifting
@@ -301,7 +317,7 @@ __device__ inline bool cell_in_one_pixel(P2 v00, P2 v10, P2 v11, P2 v01, const M
 // one pixel column `r` (counted over the cell's triangles that need clipping)
 // of cell `cell`: clip the triangle to the column, then to each pixel row
 __device__ void cell_column(const double2 *verts, int64_t nr1, int64_t cb0, int64_t vb0, int64_t cell, int r,
-                            const MapGeom &g, double *map)
+                            const MapGeom &g, double *map, const Window &w)
 {
     P2 v00, v10, v11, v01;
     load_cell(verts, nr1, cb0, vb0, cell, v00, v10, v11, v01);
@@ -345,29 +361,53 @@ __device__ void cell_column(const double2 *verts, int64_t nr1, int64_t cb0, int6
         const double h1 = strip_cumulative(S, (double)(j + 1) - fv0);
         const double a2 = 2.0 * (h1 - h0);   // twice the piece area, signed like the triangle
         h0 = h1;
-        if (a2 != 0.0) deposit(map, g, i, j, scale * a2);
+        if (a2 != 0.0) deposit_w(w, map, g, i, j, scale * a2);
     }
 }
 
-// IPM of the ordinary triangles: one thread per cell for single-pixel
-// deposits and classification (cell (a, b) splits along v00-v11 into
-// T1 = (v00, v10, v11) and T2 = (v00, v11, v01)), then the wavefront's pixel
-// columns spread evenly over its lanes.  Large triangles are only counted here.
+// IPM of the ordinary triangles.  A workgroup takes a tile of 16 x 16 cells
+// (each wavefront 16 x 4): one thread per cell deposits single-pixel
+// triangles and classifies the rest (cell (a, b) splits along v00-v11 into
+// T1 = (v00, v10, v11) and T2 = (v00, v11, v01)); then each wavefront spreads
+// its triangles' pixel columns evenly over its lanes.  A tile of cells maps to
+// a compact patch of the source plane, so deposits are summed in an LDS
+// window around the tile's image first.  Large triangles are only counted.
+constexpr int CT = 16;   // cells per tile side
+
 __global__ __launch_bounds__(256) void k_ipm(const double2 *__restrict__ verts, int64_t nr1, int64_t cb0,
-                                             int64_t ncells, int64_t vb0, MapGeom g, double *__restrict__ map,
+                                             int64_t nrows, int64_t vb0, MapGeom g, double *__restrict__ map,
                                              unsigned long long *__restrict__ counters, int32_t *__restrict__ nbig)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t wave0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63);
-    const int64_t t = wave0 + lane;
+    __shared__ double acc[WIN * WIN];
+    const int64_t ncol = nr1 - 1;
+    const int64_t tiles_a = (ncol + CT - 1) / CT;
+    const int64_t ta = blockIdx.x % tiles_a, tb = blockIdx.x / tiles_a;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t a = ta * CT + (lane & (CT - 1));
+    const int64_t brow = tb * CT + wave * 4 + (lane >> 4);   // cell row within the strip
+    for (int k = threadIdx.x; k < WIN * WIN; k += blockDim.x) acc[k] = 0.0;
+    // window anchored on the image of the tile's centre vertex
+    Window w;
+    w.acc = acc;
+    {
+        const int64_t ca = min(ta * CT + CT / 2, ncol), cb = min(tb * CT + CT / 2, nrows);
+        const double2 c = verts[(cb0 + cb - vb0) * nr1 + ca];
+        const double fu = isfinite(c.x) ? fmin(fmax(floor(c.x), -1e9), 1e9) : 0.0;
+        const double fv = isfinite(c.y) ? fmin(fmax(floor(c.y), -1e9), 1e9) : 0.0;
+        w.i0 = (int64_t)fu - WIN / 2;
+        w.j0 = (int64_t)fv - WIN / 2;
+    }
+    __syncthreads();
     int cnt = 0;
-    if (t < ncells) {
+    int64_t cell = -1;
+    if (a < ncol && brow < nrows) {
+        cell = brow * ncol + a;
         P2 v00, v10, v11, v01;
-        load_cell(verts, nr1, cb0, vb0, t, v00, v10, v11, v01);
+        load_cell(verts, nr1, cb0, vb0, cell, v00, v10, v11, v01);
         int64_t pi, pj;
         int nb = 0;
         if (cell_in_one_pixel(v00, v10, v11, v01, g, pi, pj)) {
-            if (pi >= 0) deposit(map, g, pi, pj, 2.0 * g.tri_weight);
+            if (pi >= 0) deposit_w(w, map, g, pi, pj, 2.0 * g.tri_weight);
         } else {
             const P2 tri[2][3] = {{v00, v10, v11}, {v00, v11, v01}};
 #pragma unroll
@@ -379,7 +419,7 @@ __global__ __launch_bounds__(256) void k_ipm(const double2 *__restrict__ verts, 
                           isfinite(C.v)))
                         atomicAdd(counters, 1ull);
                 } else if (c.kind == 1) {
-                    if (c.pi >= 0) deposit(map, g, c.pi, c.pj, g.tri_weight);
+                    if (c.pi >= 0) deposit_w(w, map, g, c.pi, c.pj, g.tri_weight);
                 } else if (c.kind == 2) {
                     cnt += c.cols;
                 } else {
@@ -387,7 +427,7 @@ __global__ __launch_bounds__(256) void k_ipm(const double2 *__restrict__ verts, 
                 }
             }
         }
-        nbig[t] = nb;
+        nbig[cell] = nb;
     }
     int total;
     const int excl = wave_excl_scan(cnt, lane, total);
@@ -395,7 +435,16 @@ __global__ __launch_bounds__(256) void k_ipm(const double2 *__restrict__ verts, 
         const int item = base + lane;
         const int L = wave_find(excl, item);
         const int r = item - __shfl(excl, L, 64);
-        if (item < total) cell_column(verts, nr1, cb0, vb0, wave0 + L, r, g, map);
+        const int64_t c = __shfl(cell, L, 64);
+        if (item < total) cell_column(verts, nr1, cb0, vb0, c, r, g, map, w);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < WIN * WIN; k += blockDim.x) {
+        const double v = acc[k];
+        if (v != 0.0) {
+            const int64_t i = w.i0 + (k % WIN), j = w.j0 + (k / WIN);
+            deposit(map, g, i, j, v);   // inside the map: only in-map pixels were deposited
+        }
     }
 }
 
@@ -581,6 +630,145 @@ __global__ __launch_bounds__(256) void k_big(int64_t nbig, const BigPrep *__rest
     }
 }
 
+// ---------------------------------------------------------------------------
+// Large triangles by pixel bands.  Every pixel receives hundreds of boundary
+// deposits from the large triangles around star images, and device-wide
+// atomics are the limit, so the work is binned instead: the map's rows are cut
+// into bands of BH full-width rows, each large triangle is listed in every
+// band its rows cross, and one workgroup per band accumulates its pixels in
+// LDS (boundary pixels by LDS atomics, fully covered runs in an LDS
+// difference row), prefix-sums its own rows and adds them to the map.  The
+// band owns those rows, so no device-wide atomic is needed.
+// ---------------------------------------------------------------------------
+constexpr int BAND_THREADS = 512;
+constexpr int64_t BAND_LDS_DOUBLES = 8192;    // band map + difference rows (64 KiB)
+
+__device__ inline void band_range(const BigPrep &bp, int64_t rows, int bh, int64_t &b0, int64_t &b1)
+{
+    const int64_t j0 = (int64_t)bp.ov;
+    b0 = j0 / bh;
+    b1 = (j0 + rows - 1) / bh;
+}
+
+// per band: number of large triangles crossing it (block histogram in LDS)
+__global__ __launch_bounds__(256) void k_band_count(int64_t nbig, const BigPrep *__restrict__ prep,
+                                                    const int64_t *__restrict__ rows, int bh, int32_t nbands,
+                                                    int32_t *__restrict__ count)
+{
+    extern __shared__ int32_t hist[];
+    for (int32_t b = threadIdx.x; b < nbands; b += blockDim.x) hist[b] = 0;
+    __syncthreads();
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nbig && rows[k] > 0) {
+        int64_t b0, b1;
+        band_range(prep[k], rows[k], bh, b0, b1);
+        for (int64_t b = b0; b <= b1; ++b) atomicAdd(&hist[b], 1);
+    }
+    __syncthreads();
+    for (int32_t b = threadIdx.x; b < nbands; b += blockDim.x)
+        if (hist[b]) atomicAdd(count + b, hist[b]);
+}
+
+// triangle indices into their bands' lists: each block reserves one range
+// per band and hands out slots inside it from LDS
+__global__ __launch_bounds__(256) void k_band_scatter(int64_t nbig, const BigPrep *__restrict__ prep,
+                                                      const int64_t *__restrict__ rows, int bh, int32_t nbands,
+                                                      unsigned long long *__restrict__ cursor,
+                                                      int32_t *__restrict__ list)
+{
+    extern __shared__ int32_t sh[];
+    int32_t *hist = sh;
+    unsigned long long *base = reinterpret_cast<unsigned long long *>(sh + ((nbands + 1) & ~1));
+    for (int32_t b = threadIdx.x; b < nbands; b += blockDim.x) hist[b] = 0;
+    __syncthreads();
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t b0 = 0, b1 = -1;
+    if (k < nbig && rows[k] > 0) {
+        band_range(prep[k], rows[k], bh, b0, b1);
+        for (int64_t b = b0; b <= b1; ++b) atomicAdd(&hist[b], 1);
+    }
+    __syncthreads();
+    for (int32_t b = threadIdx.x; b < nbands; b += blockDim.x) {
+        if (hist[b]) base[b] = atomicAdd(cursor + b, (unsigned long long)hist[b]);
+        hist[b] = 0;
+    }
+    __syncthreads();
+    for (int64_t b = b0; b <= b1; ++b) {
+        const int32_t o = atomicAdd(&hist[b], 1);
+        list[base[b] + o] = (int32_t)k;
+    }
+}
+
+// one workgroup per band of bh pixel rows
+__global__ __launch_bounds__(BAND_THREADS) void k_band(const unsigned long long *__restrict__ band_off,
+                                                       const int32_t *__restrict__ list,
+                                                       const BigPrep *__restrict__ prep,
+                                                       const int64_t *__restrict__ rows, int bh, MapGeom g,
+                                                       double *__restrict__ map)
+{
+    extern __shared__ double lds[];
+    const int64_t n1 = g.n1;
+    double *bmap = lds;                    // bh x n1
+    double *bdiff = lds + bh * n1;         // bh x (n1 + 1)
+    const int64_t band = blockIdx.x;
+    const int64_t jb0 = band * bh;
+    const int nrow = (int)min((int64_t)bh, (int64_t)g.n2 - jb0);
+    for (int64_t t = threadIdx.x; t < (int64_t)bh * (2 * n1 + 1); t += blockDim.x) lds[t] = 0.0;
+    __syncthreads();
+    const int64_t r0 = (int64_t)band_off[band], r1 = (int64_t)band_off[band + 1];
+    // items: (listed triangle, row of the band)
+    const int64_t nitems = (r1 - r0) * bh;
+    for (int64_t it = threadIdx.x; it < nitems; it += blockDim.x) {
+        const int64_t k = list[r0 + it / bh];
+        const int rr = (int)(it % bh);
+        if (rr >= nrow) continue;
+        const BigPrep bp = prep[k];
+        const int64_t j = jb0 + rr;
+        if (j < (int64_t)bp.ov || j >= (int64_t)bp.ov + rows[k]) continue;
+        RowInfo ri;
+        if (!row_info(bp, j, g, ri)) continue;
+        const int64_t ou = (int64_t)bp.ou;
+        double *brow = bmap + rr * n1 + ou;
+        for (int64_t i = ri.ga; i <= ri.gb; ++i) {
+            if (i == ri.pa && ri.pa <= ri.pb) {
+                i = ri.pb;
+                continue;
+            }
+            const double a2 = 2.0 * (strip_cumulative(ri.S, (double)i) - strip_cumulative(ri.S, (double)(i + 1)));
+            if (a2 != 0.0) atomicAdd(brow + i, bp.scale * a2);
+        }
+        if (ri.pa <= ri.pb) {
+            double *drow = bdiff + rr * (n1 + 1) + ou;
+            atomicAdd(drow + ri.pa, 2.0 * bp.scale);
+            atomicAdd(drow + ri.pb + 1, -2.0 * bp.scale);
+        }
+    }
+    __syncthreads();
+    // per row: prefix sum of the difference row, plus the boundary deposits
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int rr = wave; rr < nrow; rr += BAND_THREADS / 64) {
+        const double *dr = bdiff + rr * (n1 + 1);
+        const double *br = bmap + rr * n1;
+        double *mr = map + (jb0 + rr) * n1;
+        double carry = 0.0;
+        for (int64_t c = 0; c < n1; c += 64) {
+            const int64_t i = c + lane;
+            double v = i < n1 ? dr[i] : 0.0;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const double o = __shfl_up(v, d, 64);
+                if (lane >= d) v += o;
+            }
+            v += carry;
+            carry = __shfl(v, 63, 64);
+            if (i < n1) {
+                const double add = v + br[i];
+                if (add != 0.0) mr[i] += add;
+            }
+        }
+    }
+}
+
 // map[j][i] += sum_{k <= i} diff[j][k]; one wavefront per pixel row
 __global__ __launch_bounds__(64) void k_diff_rows(MapGeom g, const double *__restrict__ diff, double *__restrict__ map)
 {
@@ -608,10 +796,11 @@ __global__ __launch_bounds__(64) void k_diff_rows(MapGeom g, const double *__res
 void launch_ipm(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int64_t vb0, const MapGeom &g,
                 double *map, unsigned long long *counters, int32_t *nbig, hipStream_t st)
 {
-    int64_t ncells = (nr1 - 1) * (cb1 - cb0);
-    if (ncells <= 0) return;
-    hipLaunchKernelGGL(k_ipm, dim3((unsigned)((ncells + 255) / 256)), dim3(256), 0, st, verts, nr1, cb0, ncells, vb0,
-                       g, map, counters, nbig);
+    const int64_t ncol = nr1 - 1, nrows = cb1 - cb0;
+    if (ncol <= 0 || nrows <= 0) return;
+    const int64_t tiles = ((ncol + CT - 1) / CT) * ((nrows + CT - 1) / CT);
+    hipLaunchKernelGGL(k_ipm, dim3((unsigned)tiles), dim3(256), 0, st, verts, nr1, cb0, nrows, vb0, g, map, counters,
+                       nbig);
 }
 
 void launch_big_gather(int64_t ncells, const int64_t *boff, const double2 *verts, int64_t nr1, int64_t cb0,
@@ -627,6 +816,48 @@ void launch_big(int64_t nbig, const BigPrep *prep, const int64_t *rows, const Ma
 {
     if (nbig > 0)
         hipLaunchKernelGGL(k_big, dim3((unsigned)((nbig + 255) / 256)), dim3(256), 0, st, nbig, prep, rows, g, map, diff);
+}
+
+int band_height(int32_t n1, int32_t n2)
+{
+    int64_t bh = BAND_LDS_DOUBLES / (2 * (int64_t)n1 + 1);
+    if (bh > 16) bh = 16;
+    // 0: the map is too wide for one band per workgroup, or has too many bands
+    // for the binning histograms in LDS
+    if (bh > 0 && (n2 + bh - 1) / bh > 12000) bh = 0;
+    return (int)bh;
+}
+
+void launch_band_count(int64_t nbig, const BigPrep *prep, const int64_t *rows, int bh, int32_t nbands, int32_t *count,
+                       hipStream_t st)
+{
+    if (nbig > 0)
+        hipLaunchKernelGGL(k_band_count, dim3((unsigned)((nbig + 255) / 256)), dim3(256), nbands * sizeof(int32_t), st,
+                           nbig, prep, rows, bh, nbands, count);
+}
+
+void launch_band_scatter(int64_t nbig, const BigPrep *prep, const int64_t *rows, int bh, int32_t nbands,
+                         unsigned long long *cursor, int32_t *list, hipStream_t st)
+{
+    size_t shmem = ((nbands + 1) & ~1) * sizeof(int32_t) + nbands * sizeof(unsigned long long);
+    if (nbig > 0)
+        hipLaunchKernelGGL(k_band_scatter, dim3((unsigned)((nbig + 255) / 256)), dim3(256), shmem, st, nbig, prep, rows,
+                           bh, nbands, cursor, list);
+}
+
+void launch_band(int32_t nbands, const unsigned long long *band_off, const int32_t *list, const BigPrep *prep,
+                 const int64_t *rows, int bh, const MapGeom &g, double *map, hipStream_t st)
+{
+    size_t shmem = (size_t)bh * (2 * (size_t)g.n1 + 1) * sizeof(double);
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_band), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(BAND_LDS_DOUBLES * sizeof(double)));
+        attr_set = true;
+    }
+    if (nbands > 0)
+        hipLaunchKernelGGL(k_band, dim3((unsigned)nbands), dim3(BAND_THREADS), shmem, st, band_off, list, prep, rows, bh,
+                           g, map);
 }
 
 void launch_diff_rows(const MapGeom &g, const double *diff, double *map, hipStream_t st)

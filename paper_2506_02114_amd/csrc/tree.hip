@@ -230,6 +230,12 @@ int64_t scan_i32_to_i64(mlm_lens *lens, const int32_t *in, int64_t *out, int64_t
     return h[0];
 }
 
+// exclusive prefix sum of n int32 counts into n + 1 uint64 offsets; returns the total
+int64_t scan_i32_to_u64(mlm_lens *lens, const int32_t *in, unsigned long long *out, int64_t n, hipStream_t st)
+{
+    return scan_i32_to_i64(lens, in, reinterpret_cast<int64_t *>(out), n, st);
+}
+
 // exclusive prefix sum of n int64 values; returns the total
 int64_t scan_total_i64(mlm_lens *lens, const int64_t *in, int64_t *out, int64_t n, hipStream_t st)
 {
