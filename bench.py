@@ -17,11 +17,24 @@ import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
+IPM_SRC = os.path.join(ROOT, "paper_2506_02114_amd", "csrc", "ipm.hip")
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "rays/sec and maps/hour on 1 MI355X at ≤1e-4 pixel error; plain vs mixed/batched"
 FP64_VECTOR_PEAK_TFLOPS = 78.6          # MI355X FP64 vector, dense
+
+# HBM traffic of one k_band launch on this workload, from two rocprofv3 --pmc
+# passes (FETCH_SIZE, WRITE_SIZE) scaled by the same counters' reading of a
+# plain 1 GiB device copy (--copy-check); valid only for the IPM source it was
+# taken with, identified by its SHA-256 prefix.
+BAND_TRAFFIC = None   # {"fetch_bytes": F, "write_bytes": W, "ipm_sha256": "..."}
+
+
+def file_sha(path: str) -> str:
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def shoot_flops(stats: dict) -> float:
@@ -32,6 +45,29 @@ def shoot_flops(stats: dict) -> float:
     coordinates."""
     p = stats["order"]
     return 10.0 * stats["near_pairs"] + (8.0 * (p - 1) + 26.0) * stats["n_rays"]
+
+
+def band_flops(stats: dict) -> float:
+    """Algorithmic FP64 flops of the per-band IPM kernel for one map:
+    30 per (large triangle, pixel row) item (3 edges clipped to the row, 2
+    crossings x 3 each; for the ~2 edges present: extent, width, inverse and
+    deposit factor, 6 each) and 10 per column difference deposited (one
+    clamp integral 7, the scaled difference 2, the change from the previous
+    column 1)."""
+    return 30.0 * stats["n_band_rows"] + 10.0 * stats["n_band_pieces"]
+
+
+def copy_check() -> None:
+    """A plain device copy of 1 GiB (2^27 doubles), three times: the reference
+    reading for the HBM byte counters."""
+    import torch
+    n = 1 << 27
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}), flush=True)
 
 
 def cpu_baseline(wl, spec, region, nthreads: int) -> dict:
@@ -78,11 +114,15 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-check", action="store_true", help="only run the plain copy used to scale HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the map path has no multi-GPU mode); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_check:
+        copy_check()
+        return
 
     import torch
 
@@ -118,11 +158,20 @@ def main():
     def avg(k):
         return sum(s[k] for s in stats) / len(stats)
 
-    t_shoot, t_ipm = avg("t_shoot_ms"), avg("t_ipm_ms")
+    t_shoot, t_ipm, t_band = avg("t_shoot_ms"), avg("t_ipm_ms"), avg("t_band_ms")
     flops = shoot_flops(stats[0])
     shoot_roof = {"bound": "alu", "achieved": flops / (t_shoot * 1e-3) / 1e12, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                  "unit": "TFLOP/s", "traffic": None, "kernel": "k_shoot"}
+                  "unit": "TFLOP/s", "kernel": "k_shoot", "launch_ms": t_shoot}
     shoot_roof["frac"] = shoot_roof["achieved"] / shoot_roof["peak"]
+    # dominant kernel: the per-band IPM pass (one launch per map on this workload)
+    traffic = None
+    if BAND_TRAFFIC and BAND_TRAFFIC["ipm_sha256"] == file_sha(IPM_SRC):
+        traffic = BAND_TRAFFIC["fetch_bytes"] + BAND_TRAFFIC["write_bytes"]
+    band_roof = {"bound": "alu", "achieved": band_flops(stats[0]) / (t_band * 1e-3) / 1e12,
+                 "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "traffic": traffic, "kernel": "k_band",
+                 "launch_ms": t_band, "launches_per_step": stats[0]["n_ipm_launches"],
+                 "row_items": stats[0]["n_band_rows"], "pieces": stats[0]["n_band_pieces"]}
+    band_roof["frac"] = band_roof["achieved"] / band_roof["peak"]
     line = {
         "metric": METRIC,
         "value": value,
@@ -141,8 +190,9 @@ def main():
                    "rays_per_map": rays, "grid": [region["nr1"], region["nr2"]], "precision": "fp64"},
         "maps_per_hour": 3600.0 / (ms * 1e-3),
         "stages_ms": {"tree": avg("t_tree_ms"), "fmm": avg("t_fmm_ms"), "shoot": t_shoot, "ipm": t_ipm,
-                      "total_device": avg("t_total_ms")},
-        "roofline": shoot_roof,
+                      "ipm_cells": avg("t_cells_ms"), "ipm_band": t_band, "total_device": avg("t_total_ms")},
+        "roofline": band_roof,
+        "roofline_shoot": shoot_roof,
         "tree": {"nodes": stats[0]["n_nodes"], "leaves": stats[0]["n_leaves"], "levels": stats[0]["n_levels"],
                  "near_pairs_per_ray": stats[0]["near_pairs"] / rays},
         "ipm": {"triangles": 2 * stats[0]["n_cells"], "row_path_triangles": stats[0]["n_big"],

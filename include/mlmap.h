@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define MLM_ABI_VERSION 1
+#define MLM_ABI_VERSION 2
 
 typedef enum mlm_status {
     MLM_OK = 0,
@@ -220,6 +220,11 @@ typedef struct mlm_map_stats {
     int32_t n_shoot_launches, n_ipm_launches;
     int64_t n_big;           /* triangles apportioned row by row (large mapped area) */
     int64_t n_big_rows;      /* pixel rows those triangles cover inside the map */
+    /* the following are filled only when req->timing is set */
+    double t_cells_ms;       /* per-cell IPM kernel (ordinary triangles) */
+    double t_band_ms;        /* per-band IPM kernel (large triangles) */
+    int64_t n_band_rows;     /* (large triangle, pixel row) pairs the per-band kernel visits */
+    int64_t n_band_pieces;   /* column differences those rows deposit inside the map */
 } mlm_map_stats;
 
 /*

@@ -73,7 +73,8 @@ class MapStats(C.Structure):
                 ("tri_area", C.c_double), ("t_tree_ms", C.c_double), ("t_fmm_ms", C.c_double),
                 ("t_shoot_ms", C.c_double), ("t_ipm_ms", C.c_double), ("t_total_ms", C.c_double),
                 ("n_shoot_launches", C.c_int32), ("n_ipm_launches", C.c_int32),
-                ("n_big", C.c_int64), ("n_big_rows", C.c_int64)]
+                ("n_big", C.c_int64), ("n_big_rows", C.c_int64), ("t_cells_ms", C.c_double),
+                ("t_band_ms", C.c_double), ("n_band_rows", C.c_int64), ("n_band_pieces", C.c_int64)]
 
 
 class TreeInfo(C.Structure):

@@ -375,8 +375,8 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
     int64_t npix = (int64_t)q.n1 * q.n2;
     double *map = q.device_out ? mu : static_cast<double *>(ws.map.reserve(npix * sizeof(double)));
     fill(map, npix, 0.0, st);
-    // counters: [0] skipped triangles, [1] ray-star pairs, [2] rays, [3] queue
-    // overflows, [4] queued big triangles of the current strip
+    // counters: [0] skipped triangles, [1] ray-star pairs, [2] rays, [3] unused,
+    // [4] band row items, [5] band boundary pieces (the last two if timing)
     unsigned long long *cnt = static_cast<unsigned long long *>(ws.counters.reserve(8 * sizeof(unsigned long long)));
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, cnt, 8);
     int64_t ndiff = (int64_t)q.n2 * (q.n1 + 1);
@@ -417,7 +417,7 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
 
     int64_t n_big = 0, n_big_rows = 0;
 
-    double t_shoot = 0.0, t_ipm = 0.0;
+    double t_shoot = 0.0, t_ipm = 0.0, t_cells = 0.0, t_band = 0.0;
     int64_t tiles = 0;
     int nstrips = 0;
     for (int64_t r0 = cb0; r0 < cb1; ++nstrips) {
@@ -441,6 +441,8 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
         int32_t *nbig = static_cast<int32_t *>(ws.nbig.reserve((size_t)ncells * sizeof(int32_t)));
         int64_t *bigoff = static_cast<int64_t *>(ws.bigoff.reserve((size_t)(ncells + 1) * sizeof(int64_t)));
         launch_ipm(verts, R.nr1, r0, r1, vb0, g, map, cnt, nbig, st);
+        const int e_cells = tm.mark();
+        int e_band0 = -1, e_band1 = -1;
         const int64_t nb = scan_i32_to_i64(lens, nbig, bigoff, ncells, st);
         if (nb > 0) {
             BigPrep *prep = static_cast<BigPrep *>(ws.bigprep.reserve((size_t)nb * sizeof(BigPrep)));
@@ -461,7 +463,9 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
                 int32_t *blist = static_cast<int32_t *>(ws.bandlist.reserve((size_t)(nlist > 0 ? nlist : 1) * sizeof(int32_t)));
                 MLM_HIP(hipMemcpyAsync(bcur, boffs, (size_t)nbands * sizeof(unsigned long long), hipMemcpyDeviceToDevice, st));
                 launch_band_scatter(nb, prep, rows, bh, nbands, bcur, blist, st);
-                launch_band(nbands, boffs, blist, prep, rows, bh, g, map, st);
+                e_band0 = tm.mark();
+                launch_band(nbands, boffs, blist, prep, rows, bh, g, map, q.timing ? cnt + 4 : nullptr, st);
+                e_band1 = tm.mark();
             } else {
                 launch_big(nb, prep, rows, g, map, diff, st);
             }
@@ -478,6 +482,8 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
         MLM_HIP(hipStreamSynchronize(st));
         t_shoot += tm.ms(ea, eb);
         t_ipm += tm.ms(eb, ec);
+        t_cells += tm.ms(eb, e_cells);
+        t_band += tm.ms(e_band0, e_band1);
         tiles += nt;
         r0 = r1;
     }
@@ -508,6 +514,10 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
         S.n_ipm_launches = nstrips;
         S.n_big = n_big;
         S.n_big_rows = n_big_rows;
+        S.t_cells_ms = t_cells;
+        S.t_band_ms = t_band;
+        S.n_band_rows = q.timing ? (int64_t)hc[4] : 0;
+        S.n_band_pieces = q.timing ? (int64_t)hc[5] : 0;
         *stats = S;
     }
     API_END

@@ -91,11 +91,11 @@ struct LensConst {
 };
 
 // per-triangle data of the row-parallel IPM: counter-clockwise vertices
-// relative to the integer origin (ou, ov), edge slopes sv = dv/du and
-// su = du/dv, and the deposit per unit of twice the piece area
+// relative to the integer origin (ou, ov), edge slopes su = du/dv, and the
+// deposit per unit of twice the piece area (96 bytes)
 struct BigPrep {
     double u[3], v[3];
-    double sv[3], su[3];
+    double su[3];
     double ou, ov, scale;
 };
 
@@ -198,7 +198,8 @@ void launch_band_count(int64_t nbig, const BigPrep *prep, const int64_t *rows, i
 void launch_band_scatter(int64_t nbig, const BigPrep *prep, const int64_t *rows, int bh, int32_t nbands,
                          unsigned long long *cursor, int32_t *list, hipStream_t st);
 void launch_band(int32_t nbands, const unsigned long long *band_off, const int32_t *list, const BigPrep *prep,
-                 const int64_t *rows, int bh, const MapGeom &g, double *map, hipStream_t st);
+                 const int64_t *rows, int bh, const MapGeom &g, double *map, unsigned long long *work,
+                 hipStream_t st);
 int64_t scan_i32_to_u64(mlm_lens *lens, const int32_t *in, unsigned long long *out, int64_t n, hipStream_t st);
 int64_t scan_total_i64(mlm_lens *lens, const int64_t *in, int64_t *out, int64_t n, hipStream_t st);
 int64_t scan_i32_to_i64(mlm_lens *lens, const int32_t *in, int64_t *out, int64_t n, hipStream_t st);

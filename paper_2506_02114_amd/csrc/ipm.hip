@@ -486,7 +486,6 @@ __global__ __launch_bounds__(256) void k_big_gather(int64_t ncells, const int64_
         for (int m = 0; m < 3; ++m) {
             bp.u[m] = T[m].u;
             bp.v[m] = T[m].v;
-            bp.sv[m] = sv[m];
             bp.su[m] = su[m];
         }
         bp.ou = ou;
@@ -635,13 +634,12 @@ __global__ __launch_bounds__(256) void k_big(int64_t nbig, const BigPrep *__rest
 // deposits from the large triangles around star images, and device-wide
 // atomics are the limit, so the work is binned instead: the map's rows are cut
 // into bands of BH full-width rows, each large triangle is listed in every
-// band its rows cross, and one workgroup per band accumulates its pixels in
-// LDS (boundary pixels by LDS atomics, fully covered runs in an LDS
-// difference row), prefix-sums its own rows and adds them to the map.  The
-// band owns those rows, so no device-wide atomic is needed.
+// band its rows cross, and one workgroup per band accumulates the column
+// differences of its rows in LDS from the triangles' edges, prefix-sums its
+// own rows and adds them to the map.
 // ---------------------------------------------------------------------------
 constexpr int BAND_THREADS = 512;
-constexpr int64_t BAND_LDS_DOUBLES = 8192;    // band map + difference rows (64 KiB)
+constexpr int64_t BAND_LDS_DOUBLES = 8192;    // band difference rows (64 KiB)
 
 __device__ inline void band_range(const BigPrep &bp, int64_t rows, int bh, int64_t &b0, int64_t &b1)
 {
@@ -699,24 +697,38 @@ __global__ __launch_bounds__(256) void k_band_scatter(int64_t nbig, const BigPre
     }
 }
 
-// one workgroup per band of bh pixel rows
+// One workgroup per band of bh pixel rows; a thread takes one (listed
+// triangle, band row) item at a time.  Within a pixel row the triangle's area
+// left of u = c is G(c) = -sum_e dv_e J_e(c), J_e(c) = I(c - ua_e, c - ub_e)
+// over the edges clipped to the row, so pixel i receives
+// sum_e delta_e(i), delta_e(i) = -dv_e (J_e(i + 1) - J_e(i)).  delta_e is zero
+// left of the edge, equal to -dv_e right of it and varies only over the
+// columns the edge crosses; so the band keeps differences
+// D(i) = delta(i) - delta(i - 1), which an edge changes only at those columns
+// and the one after, and a prefix sum along the row gives the pixel areas
+// (the covered interior costs nothing).  Columns left of the map fold into
+// column 0, those right of it are dropped.  The band owns its rows, so the
+// differences live in LDS and no device-wide atomic is needed.
 __global__ __launch_bounds__(BAND_THREADS) void k_band(const unsigned long long *__restrict__ band_off,
                                                        const int32_t *__restrict__ list,
                                                        const BigPrep *__restrict__ prep,
                                                        const int64_t *__restrict__ rows, int bh, MapGeom g,
-                                                       double *__restrict__ map)
+                                                       double *__restrict__ map, unsigned long long *__restrict__ work)
 {
-    extern __shared__ double lds[];
+    extern __shared__ double bdiff[];      // bh x n1 differences
+    __shared__ unsigned long long wsum[2];
+    if (threadIdx.x < 2) wsum[threadIdx.x] = 0;
+    unsigned long long my_rows = 0, my_pieces = 0;
     const int64_t n1 = g.n1;
-    double *bmap = lds;                    // bh x n1
-    double *bdiff = lds + bh * n1;         // bh x (n1 + 1)
-    const int64_t band = blockIdx.x;
+    // consecutive bands on one XCD (workgroups go round-robin over the 8 XCDs),
+    // so a triangle's set-up read by neighbouring bands stays in that L2
+    const int64_t nb = gridDim.x, per = nb / 8, rem = nb % 8, x = blockIdx.x % 8, idx = blockIdx.x / 8;
+    const int64_t band = x < rem ? x * (per + 1) + idx : rem * (per + 1) + (x - rem) * per + idx;
     const int64_t jb0 = band * bh;
     const int nrow = (int)min((int64_t)bh, (int64_t)g.n2 - jb0);
-    for (int64_t t = threadIdx.x; t < (int64_t)bh * (2 * n1 + 1); t += blockDim.x) lds[t] = 0.0;
+    for (int64_t t = threadIdx.x; t < (int64_t)bh * n1; t += blockDim.x) bdiff[t] = 0.0;
     __syncthreads();
     const int64_t r0 = (int64_t)band_off[band], r1 = (int64_t)band_off[band + 1];
-    // items: (listed triangle, row of the band)
     const int64_t nitems = (r1 - r0) * bh;
     for (int64_t it = threadIdx.x; it < nitems; it += blockDim.x) {
         const int64_t k = list[r0 + it / bh];
@@ -725,30 +737,47 @@ __global__ __launch_bounds__(BAND_THREADS) void k_band(const unsigned long long 
         const BigPrep bp = prep[k];
         const int64_t j = jb0 + rr;
         if (j < (int64_t)bp.ov || j >= (int64_t)bp.ov + rows[k]) continue;
-        RowInfo ri;
-        if (!row_info(bp, j, g, ri)) continue;
+        ++my_rows;
+        const double rl = (double)j - bp.ov;
         const int64_t ou = (int64_t)bp.ou;
-        double *brow = bmap + rr * n1 + ou;
-        for (int64_t i = ri.ga; i <= ri.gb; ++i) {
-            if (i == ri.pa && ri.pa <= ri.pb) {
-                i = ri.pb;
+        double *drow = bdiff + rr * n1 + ou;   // indexed by local column
+        const int64_t cmin = -ou, cmax = n1 - 1 - ou;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const P2 P{bp.u[m], bp.v[m]}, Q{bp.u[(m + 1) % 3], bp.v[(m + 1) % 3]};
+            if (P.v == Q.v) continue;   // no extent along v: contributes nothing
+            P2 E, X;
+            if (!clip_seg<1>(P, Q, rl, rl + 1.0, bp.su[m], E, X)) continue;
+            const double dv = X.v - E.v;
+            if (dv == 0.0) continue;
+            const double ua = E.u, ub = X.u;
+            const double w = fabs(ub - ua), inv = w > 0.0 ? 1.0 / w : 0.0;
+            const int64_t x0 = (int64_t)floor(fmin(ua, ub)), x1 = (int64_t)floor(fmax(ua, ub));
+            const double f = -2.0 * bp.scale * dv;   // deposit for a fully covered difference
+            const int64_t is = max(x0, cmin);
+            if (is > x1) {   // the segment lies left of the map
+                atomicAdd(drow + cmin, f);
+                ++my_pieces;
                 continue;
             }
-            const double a2 = 2.0 * (strip_cumulative(ri.S, (double)i) - strip_cumulative(ri.S, (double)(i + 1)));
-            if (a2 != 0.0) atomicAdd(brow + i, bp.scale * a2);
-        }
-        if (ri.pa <= ri.pb) {
-            double *drow = bdiff + rr * (n1 + 1) + ou;
-            atomicAdd(drow + ri.pa, 2.0 * bp.scale);
-            atomicAdd(drow + ri.pb + 1, -2.0 * bp.scale);
+            double Jc = clamp_integral((double)is - ua, (double)is - ub, inv), prev = 0.0;
+            const int64_t ie = min(x1, cmax);
+            for (int64_t i = is; i <= ie; ++i) {
+                const double Jn = clamp_integral((double)(i + 1) - ua, (double)(i + 1) - ub, inv);
+                const double cur = f * (Jn - Jc);
+                atomicAdd(drow + i, cur - prev);
+                prev = cur;
+                Jc = Jn;
+            }
+            if (x1 + 1 <= cmax) atomicAdd(drow + x1 + 1, f - prev);
+            my_pieces += (unsigned long long)(max(ie - is + 1, (int64_t)0) + (x1 + 1 <= cmax ? 1 : 0));
         }
     }
     __syncthreads();
-    // per row: prefix sum of the difference row, plus the boundary deposits
+    // per row: prefix sum of the differences, added to the map
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int rr = wave; rr < nrow; rr += BAND_THREADS / 64) {
-        const double *dr = bdiff + rr * (n1 + 1);
-        const double *br = bmap + rr * n1;
+        const double *dr = bdiff + rr * n1;
         double *mr = map + (jb0 + rr) * n1;
         double carry = 0.0;
         for (int64_t c = 0; c < n1; c += 64) {
@@ -761,11 +790,14 @@ __global__ __launch_bounds__(BAND_THREADS) void k_band(const unsigned long long 
             }
             v += carry;
             carry = __shfl(v, 63, 64);
-            if (i < n1) {
-                const double add = v + br[i];
-                if (add != 0.0) mr[i] += add;
-            }
+            if (i < n1 && v != 0.0) mr[i] += v;
         }
+    }
+    if (work) {   // work counts for statistics: row items and difference deposits
+        atomicAdd(&wsum[0], my_rows);
+        atomicAdd(&wsum[1], my_pieces);
+        __syncthreads();
+        if (threadIdx.x < 2 && wsum[threadIdx.x]) atomicAdd(work + threadIdx.x, wsum[threadIdx.x]);
     }
 }
 
@@ -820,7 +852,7 @@ void launch_big(int64_t nbig, const BigPrep *prep, const int64_t *rows, const Ma
 
 int band_height(int32_t n1, int32_t n2)
 {
-    int64_t bh = BAND_LDS_DOUBLES / (2 * (int64_t)n1 + 1);
+    int64_t bh = BAND_LDS_DOUBLES / (int64_t)n1;
     if (bh > 16) bh = 16;
     // 0: the map is too wide for one band per workgroup, or has too many bands
     // for the binning histograms in LDS
@@ -846,18 +878,16 @@ void launch_band_scatter(int64_t nbig, const BigPrep *prep, const int64_t *rows,
 }
 
 void launch_band(int32_t nbands, const unsigned long long *band_off, const int32_t *list, const BigPrep *prep,
-                 const int64_t *rows, int bh, const MapGeom &g, double *map, hipStream_t st)
+                 const int64_t *rows, int bh, const MapGeom &g, double *map, unsigned long long *work, hipStream_t st)
 {
-    size_t shmem = (size_t)bh * (2 * (size_t)g.n1 + 1) * sizeof(double);
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_band), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)(BAND_LDS_DOUBLES * sizeof(double)));
-        attr_set = true;
-    }
+    size_t shmem = (size_t)bh * (size_t)g.n1 * sizeof(double);
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_band),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)(BAND_LDS_DOUBLES * sizeof(double)));
+    MLM_HIP(attr);
     if (nbands > 0)
         hipLaunchKernelGGL(k_band, dim3((unsigned)nbands), dim3(BAND_THREADS), shmem, st, band_off, list, prep, rows, bh,
-                           g, map);
+                           g, map, work);
 }
 
 void launch_diff_rows(const MapGeom &g, const double *diff, double *map, hipStream_t st)
