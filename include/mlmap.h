@@ -143,8 +143,16 @@ enum { MLM_METHOD_FMM = 0, MLM_METHOD_DIRECT = 1 };
  *   leaf_max       maximum stars in a node's 3x3 block of same-level
  *                  squares before it is divided (app. C.1), default 32
  *   max_level      deepest tree level, default and maximum 24
- *   precision      MLM_PREC_FP64 (everything in double); MLM_PREC_MIXED is
- *                  reserved and returns MLM_ENOTSUP in this build
+ *   precision      MLM_PREC_FP64 (everything in double) or MLM_PREC_MIXED:
+ *                  multipole and Taylor coefficients (app. C.2), near field,
+ *                  Taylor evaluation and the column pass of the IPM in FP32;
+ *                  grid positions, leaf centres and offsets from them, the
+ *                  macro model, the sheet, triangle set-up, thin triangles
+ *                  (squared extent above 256 x twice the area, the ones
+ *                  folded across caustics), the row-band pass and every
+ *                  pixel sum in FP64 (the paper's single-precision mode,
+ *                  sec. 5, with FP64 kept where caustics need it).  With
+ *                  MLM_METHOD_DIRECT it gives MLM_ENOTSUP.
  *   method         MLM_METHOD_FMM or MLM_METHOD_DIRECT (every star summed
  *                  for every ray; the no-FMM reference of sec. 4)
  *   device_out     != 0: `mu` (and `w_out`) are device pointers
@@ -238,6 +246,47 @@ typedef struct mlm_map_stats {
  * MLM_ENOMEM, MLM_EDEVICE, MLM_ENOTSUP.
  */
 mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_stats *stats);
+
+/*
+ * Batched maps: many lenses and requests in one call, each map as mlm_map
+ * would make it, but with the ray shooting and the IPM of many maps fused
+ * into persistent launches that walk the concatenated work of all maps (so
+ * small maps do not leave the GPU idle).  The per-map tree, FMM and leaf
+ * tables are built first, one map after another; the maps are then taken in
+ * chunks whose grids fit `vertex_budget` vertices at once.
+ *   lenses[i], reqs[i]: map i (distinct lenses: each holds its map's tree
+ *       until the call returns); requests must cover all rows, use the FMM,
+ *       have no w_out and agree in device_out; reqs[0].stream is used.
+ *   mus[i]: n2 x n1 output of map i (host or device per device_out).
+ *   stats: NULL or nmaps per-map statistics (times of the fused stages are
+ *       in `bstats`, not per map).
+ *   opts: NULL for the defaults.
+ *   bstats: NULL or the batch's statistics.
+ * With opts->autotune, each map's leaf size (app. C.1's split threshold,
+ * which trades near-field pairs against tree and expansion work) is chosen
+ * among 8, 16, 32 and 64 by timing tree + FMM + shooting of a sample of the
+ * map's rows for each, and the choice is cached per class of map (precision,
+ * expansion order and rays per star in powers of two) for the process.
+ * Errors: as mlm_map; MLM_EINVAL also for an empty or inconsistent batch.
+ */
+typedef struct mlm_batch_opts {
+    int64_t vertex_budget;   /* vertices held at once, 0: 2^28 (at least the largest map) */
+    int32_t autotune;        /* != 0: choose each map's leaf size by timed trials */
+    int32_t reserved0;
+    int64_t reserved[6];
+} mlm_batch_opts;
+
+typedef struct mlm_batch_stats {
+    int64_t n_maps, n_chunks, n_rays, n_cells, n_big;
+    double t_prep_ms;        /* trees, FMM, leaf tables, tile plans (and tuning) */
+    double t_shoot_ms;       /* fused ray shooting */
+    double t_ipm_ms;         /* fused IPM passes */
+    double t_total_ms;       /* whole call, device time */
+    int64_t reserved[4];
+} mlm_batch_stats;
+
+mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, int32_t nmaps, double *const *mus,
+                         mlm_map_stats *stats, const mlm_batch_opts *opts, mlm_batch_stats *bstats);
 
 /*
  * Source positions w(z) of arbitrary image-plane points through the same

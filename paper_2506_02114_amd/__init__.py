@@ -24,7 +24,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 METHOD_FMM, METHOD_DIRECT = 0, 1
 
 EXPORTED = [
-    "mlm_abi_version", "mlm_status_str", "mlm_last_error", "mlm_lens_create", "mlm_lens_destroy",
+    "mlm_abi_version", "mlm_status_str", "mlm_last_error", "mlm_lens_create", "mlm_lens_destroy", "mlm_map_batch",
     "mlm_lens_get_info", "mlm_map_request_init", "mlm_map_region", "mlm_map", "mlm_deflect",
     "mlm_fmm_export",
 ]
@@ -77,6 +77,17 @@ class MapStats(C.Structure):
                 ("t_band_ms", C.c_double), ("n_band_rows", C.c_int64), ("n_band_pieces", C.c_int64)]
 
 
+class BatchOpts(C.Structure):
+    _fields_ = [("vertex_budget", C.c_int64), ("autotune", C.c_int32), ("reserved0", C.c_int32),
+                ("reserved", C.c_int64 * 6)]
+
+
+class BatchStats(C.Structure):
+    _fields_ = [("n_maps", C.c_int64), ("n_chunks", C.c_int64), ("n_rays", C.c_int64), ("n_cells", C.c_int64),
+                ("n_big", C.c_int64), ("t_prep_ms", C.c_double), ("t_shoot_ms", C.c_double),
+                ("t_ipm_ms", C.c_double), ("t_total_ms", C.c_double), ("reserved", C.c_int64 * 4)]
+
+
 class TreeInfo(C.Structure):
     _fields_ = [("n_nodes", C.c_int64), ("n_leaves", C.c_int64), ("n_levels", C.c_int32),
                 ("order", C.c_int32), ("L0", C.c_double)]
@@ -118,6 +129,9 @@ def _lib():
     L.mlm_deflect.restype = C.c_int
     L.mlm_fmm_export.argtypes = [vp, C.POINTER(MapRequest), C.POINTER(TreeInfo), vp, vp, vp, vp, vp, vp, vp, vp, i64]
     L.mlm_fmm_export.restype = C.c_int
+    L.mlm_map_batch.argtypes = [C.POINTER(vp), C.POINTER(MapRequest), i32, C.POINTER(vp), C.POINTER(MapStats),
+                                C.POINTER(BatchOpts), C.POINTER(BatchStats)]
+    L.mlm_map_batch.restype = C.c_int
     _L = L
     return L
 
@@ -263,3 +277,36 @@ class Lens:
                                      ptr(ns), ptr(blk), ptr(mult), ptr(loc), n))
         return dict(info=_asdict(I), level=level, i=ix, j=iy, leaf=leaf, nstars=ns, block=blk,
                     mult=mult.view(np.complex128).reshape(n, P1), local=loc.view(np.complex128).reshape(n, P1))
+
+
+def map_batch(lenses, requests, outs, stream=None, autotune: bool = False, vertex_budget: int = 0):
+    """Maps of many lenses in one call (mlm_map_batch).  `requests` are dicts
+    of map-request fields, `outs` float64 arrays of (n2, n1): all numpy (host)
+    or all torch tensors on the GPU.  Returns (per-map stats, batch stats)."""
+    n = len(lenses)
+    if not (len(requests) == n == len(outs)) or n == 0:
+        raise ValueError("lenses, requests and outs must have the same non-zero length")
+    device = _is_torch_cuda(outs[0])
+    reqs = (MapRequest * n)()
+    ptrs = (C.c_void_p * n)()
+    hs = (C.c_void_p * n)()
+    for i, (lens, kw, out) in enumerate(zip(lenses, requests, outs)):
+        r = make_request(**kw)
+        if device:
+            import torch
+            assert _is_torch_cuda(out) and out.dtype == torch.float64 and out.is_contiguous()
+            assert out.numel() == r.n1 * r.n2
+            r.device_out = 1
+            r.stream = stream if stream is not None else _current_stream()
+            ptrs[i] = out.data_ptr()
+        else:
+            assert isinstance(out, np.ndarray) and out.dtype == np.float64 and out.flags.c_contiguous
+            assert out.size == r.n1 * r.n2
+            ptrs[i] = out.ctypes.data
+        reqs[i] = r
+        hs[i] = lens._h.value
+    stats = (MapStats * n)()
+    o = BatchOpts(int(vertex_budget), 1 if autotune else 0, 0)
+    b = BatchStats()
+    _check(_lib().mlm_map_batch(hs, reqs, n, ptrs, stats, C.byref(o), C.byref(b)))
+    return [_asdict(s) for s in stats], _asdict(b)

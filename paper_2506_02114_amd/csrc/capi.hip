@@ -4,7 +4,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <set>
+#include <tuple>
 #include <vector>
 
 #include "dev.hpp"
@@ -142,8 +146,10 @@ struct Timer {
 void check_request(const mlm_map_request *q)
 {
     if (!q) fail(MLM_EINVAL, "request is NULL");
-    if (q->precision == MLM_PREC_MIXED) fail(MLM_ENOTSUP, "mixed precision is not available in this build");
-    if (q->precision != MLM_PREC_FP64) fail(MLM_EINVAL, "unknown precision %d", q->precision);
+    if (q->precision != MLM_PREC_FP64 && q->precision != MLM_PREC_MIXED)
+        fail(MLM_EINVAL, "unknown precision %d", q->precision);
+    if (q->precision == MLM_PREC_MIXED && q->method == MLM_METHOD_DIRECT)
+        fail(MLM_ENOTSUP, "the direct-sum method runs in FP64 only");
     if (q->method != MLM_METHOD_FMM && q->method != MLM_METHOD_DIRECT) fail(MLM_EINVAL, "unknown method %d", q->method);
     if (q->order < 0 || q->order > MAX_ORDER) fail(MLM_EINVAL, "order %d outside [0, %d]", q->order, MAX_ORDER);
     if (q->leaf_max < 0 || q->max_level < 0 || q->max_level > KEY_BITS)
@@ -155,6 +161,7 @@ void check_request(const mlm_map_request *q)
 void prepare_fmm(mlm_lens *lens, const Region &R, const mlm_map_request &q, Tree &T, hipStream_t st)
 {
     build_tree(lens, R, q, T, st);
+    T.mixed = q.precision == MLM_PREC_MIXED;
     int p = q.order;
     if (p <= 0) {
         double Lmin = std::ldexp(R.L0, -(T.nlevels - 1));
@@ -165,6 +172,111 @@ void prepare_fmm(mlm_lens *lens, const Region &R, const mlm_map_request &q, Tree
 }
 
 hipStream_t stream_of(const mlm_map_request *q) { return q ? static_cast<hipStream_t>(q->stream) : nullptr; }
+
+__global__ void k_zero_u64n(unsigned long long *p, int64_t n)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0;
+}
+
+// --------------------------------------------------------------------------
+// batched maps
+// --------------------------------------------------------------------------
+
+// device buffers of the fused batch passes (one set per process, on the
+// device of the calls; calls are serialised by `mu`)
+struct BatchWs {
+    std::mutex mu;
+    DevBuf maps, verts, nbig, boff, prep, rows, owner, bcnt, boffs, bcur, blist, counters;
+};
+
+BatchWs &batch_ws()
+{
+    static BatchWs *w = new BatchWs;   // never destroyed: outlives every call, even at exit
+    return *w;
+}
+
+struct MapPlan {
+    mlm_lens *lens = nullptr;
+    mlm_map_request q{};
+    Region R{};
+    Tree T;
+    MapGeom g{};
+    LensConst lc{};
+    double *map = nullptr;
+    int64_t nverts = 0, ncells = 0, ntiles = 0, nctiles = 0, nbands = 0;
+    int32_t bh = 0;
+    int e_tree0 = -1, e_tree1 = -1, e_fmm1 = -1;
+};
+
+MapGeom map_geom(const mlm_map_request &q, const Region &R)
+{
+    MapGeom g;
+    g.ylo1 = q.y1c - q.hw1;
+    g.ylo2 = q.y2c - q.hw2;
+    g.pix1 = R.pix1;
+    g.pix2 = R.pix2;
+    g.n1 = q.n1;
+    g.n2 = q.n2;
+    g.tri_weight = 0.5 * R.d1 * R.d2 / (R.pix1 * R.pix2);
+    return g;
+}
+
+int order_for(const mlm_map_request &q, const Region &R, const Tree &T)
+{
+    if (q.order > 0) return q.order;
+    return auto_order(R.mean_m, R.mean_m2, std::ldexp(R.L0, -(T.nlevels - 1)), q.eps > 0 ? q.eps : 1e-7);
+}
+
+// Leaf-size autotuner: for a map, the split threshold that minimises the
+// estimated time of tree + FMM + shooting, from timed trials on the map's
+// own stars and a sample of its grid rows; cached per class of map.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, int> g_tune_cache;
+
+int tune_leaf_max(mlm_lens *lens, const mlm_map_request &q, const Region &R, hipStream_t st)
+{
+    const double rays = (double)R.nr1 * (double)R.nr2;
+    const int cls = (int)std::floor(std::log2(std::max(1.0, rays / std::max<int64_t>(lens->n, 1))));
+    const auto key = std::make_tuple(q.precision, q.order, cls);
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) return it->second;
+    }
+    const int64_t srows = std::min<int64_t>(R.nr2, std::max<int64_t>(64, R.nr2 / 16));
+    const int64_t vb0 = (R.nr2 - srows) / 2;
+    double2 *verts = static_cast<double2 *>(lens->ws.verts.reserve((size_t)(srows * R.nr1) * sizeof(double2)));
+    const MapGeom g = map_geom(q, R);
+    const LensConst lc = lens_const(lens, R);
+    int best = 32;
+    double best_t = 1e300;
+    for (int cand : {8, 16, 32, 64}) {
+        mlm_map_request qc = q;
+        qc.leaf_max = cand;
+        Timer tm(true, st);
+        const int a = tm.mark();
+        Tree T;
+        build_tree(lens, R, qc, T, st);
+        T.mixed = qc.precision == MLM_PREC_MIXED;
+        run_fmm(lens, T, order_for(qc, R, T), st);
+        build_leaf_tables(lens, T, st);
+        const int b = tm.mark();
+        const int64_t nt = plan_tiles(lens, T, R, vb0, vb0 + srows, st);
+        const int c = tm.mark();
+        launch_shoot(lens, T, R, lc, g, nt, vb0, verts, nullptr, st);
+        const int d = tm.mark();
+        MLM_HIP(hipStreamSynchronize(st));
+        const double est = tm.ms(a, b) + tm.ms(c, d) * (double)R.nr2 / (double)srows;
+        if (est < best_t) {
+            best_t = est;
+            best = cand;
+        }
+    }
+    std::lock_guard<std::mutex> g2(g_tune_mu);
+    g_tune_cache[key] = best;
+    return best;
+}
 
 }  // namespace
 }  // namespace mlm
@@ -388,6 +500,7 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
     int e_tree = -1, e_fmm = -1;
     if (fmm) {
         build_tree(lens, R, q, T, st);
+        T.mixed = q.precision == MLM_PREC_MIXED;
         e_tree = tm.mark();
         int p = q.order;
         if (p <= 0) p = auto_order(R.mean_m, R.mean_m2, std::ldexp(R.L0, -(T.nlevels - 1)), q.eps > 0 ? q.eps : 1e-7);
@@ -440,7 +553,7 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
         const int64_t ncells = (R.nr1 - 1) * (r1 - r0);
         int32_t *nbig = static_cast<int32_t *>(ws.nbig.reserve((size_t)ncells * sizeof(int32_t)));
         int64_t *bigoff = static_cast<int64_t *>(ws.bigoff.reserve((size_t)(ncells + 1) * sizeof(int64_t)));
-        launch_ipm(verts, R.nr1, r0, r1, vb0, g, map, cnt, nbig, st);
+        launch_ipm(verts, R.nr1, r0, r1, vb0, g, map, cnt, nbig, q.precision == MLM_PREC_MIXED, st);
         const int e_cells = tm.mark();
         int e_band0 = -1, e_band1 = -1;
         const int64_t nb = scan_i32_to_i64(lens, nbig, bigoff, ncells, st);
@@ -519,6 +632,197 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
         S.n_band_rows = q.timing ? (int64_t)hc[4] : 0;
         S.n_band_pieces = q.timing ? (int64_t)hc[5] : 0;
         *stats = S;
+    }
+    API_END
+}
+
+mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, int32_t nmaps, double *const *mus,
+                         mlm_map_stats *stats, const mlm_batch_opts *opts, mlm_batch_stats *bstats)
+{
+    API_BEGIN
+    if (!lenses || !reqs || !mus || nmaps <= 0) fail(MLM_EINVAL, "lenses, reqs and mus must hold nmaps >= 1 entries");
+    std::set<mlm_lens *> seen;
+    for (int32_t i = 0; i < nmaps; ++i) {
+        const mlm_map_request &q = reqs[i];
+        if (!lenses[i] || !mus[i]) fail(MLM_EINVAL, "map %d: lens and output must not be NULL", i);
+        if (!seen.insert(lenses[i]).second) fail(MLM_EINVAL, "map %d: every map of a batch needs its own lens", i);
+        check_request(&q);
+        if (q.method != MLM_METHOD_FMM) fail(MLM_EINVAL, "map %d: batched maps use the FMM", i);
+        if (q.row_begin > 0 || q.row_end >= 0) fail(MLM_EINVAL, "map %d: batched maps cover all rows", i);
+        if (q.w_out) fail(MLM_EINVAL, "map %d: batched maps have no w_out", i);
+        if ((q.device_out != 0) != (reqs[0].device_out != 0)) fail(MLM_EINVAL, "map %d: device_out differs", i);
+    }
+    mlm_batch_opts o{};
+    if (opts) o = *opts;
+    hipStream_t st = stream_of(&reqs[0]);
+    // every lens locked, in address order
+    std::vector<std::unique_lock<std::mutex>> locks;
+    for (mlm_lens *l : seen) locks.emplace_back(l->mu);
+    BatchWs &B = batch_ws();
+    std::lock_guard<std::mutex> bguard(B.mu);
+    Timer tm(bstats != nullptr || (stats && reqs[0].timing), st);
+    const int e_start = tm.mark();
+
+    // per map: region, (tuned) tree, FMM, leaf tables and tile plan, all kept
+    // in the map's lens workspace
+    std::vector<MapPlan> P(nmaps);
+    unsigned long long *cnt =
+        static_cast<unsigned long long *>(B.counters.reserve((size_t)nmaps * 8 * sizeof(unsigned long long)));
+    hipLaunchKernelGGL(k_zero_u64n, dim3((unsigned)((nmaps * 8 + 255) / 256)), dim3(256), 0, st, cnt,
+                       (int64_t)nmaps * 8);
+    int64_t max_verts = 0, max_band_lds = 0;
+    for (int32_t i = 0; i < nmaps; ++i) {
+        MapPlan &m = P[i];
+        m.lens = lenses[i];
+        m.q = reqs[i];
+        setup_region(m.lens, &m.q, &m.R);
+        if (m.R.nr1 > INT32_MAX || m.R.nr2 > INT32_MAX) fail(MLM_ERANGE, "map %d: ray grid too large", i);
+        if (o.autotune) m.q.leaf_max = tune_leaf_max(m.lens, m.q, m.R, st);
+        m.e_tree0 = tm.mark();
+        build_tree(m.lens, m.R, m.q, m.T, st);
+        m.T.mixed = m.q.precision == MLM_PREC_MIXED;
+        m.e_tree1 = tm.mark();
+        run_fmm(m.lens, m.T, order_for(m.q, m.R, m.T), st);
+        build_leaf_tables(m.lens, m.T, st);
+        m.e_fmm1 = tm.mark();
+        m.ntiles = plan_tiles(m.lens, m.T, m.R, 0, m.R.nr2, st);
+        m.g = map_geom(m.q, m.R);
+        m.lc = lens_const(m.lens, m.R);
+        const int64_t npix = (int64_t)m.q.n1 * m.q.n2;
+        m.map = m.q.device_out ? mus[i] : static_cast<double *>(m.lens->ws.map.reserve(npix * sizeof(double)));
+        fill(m.map, npix, 0.0, st);
+        m.nverts = m.R.nr1 * m.R.nr2;
+        m.ncells = (m.R.nr1 - 1) * (m.R.nr2 - 1);
+        m.nctiles = ((m.R.nr1 - 1 + 15) / 16) * ((m.R.nr2 - 1 + 15) / 16);
+        m.bh = band_height(m.q.n1, m.q.n2);
+        if (m.bh <= 0) fail(MLM_ENOTSUP, "map %d: %d x %d pixels is too wide for batched row bands", i, m.q.n1, m.q.n2);
+        m.nbands = (m.q.n2 + m.bh - 1) / m.bh;
+        max_verts = std::max(max_verts, m.nverts);
+        max_band_lds = std::max<int64_t>(max_band_lds, (int64_t)m.bh * m.q.n1);
+    }
+    const int e_prep = tm.mark();
+
+    // chunks of consecutive maps that fit the vertex budget: one fused launch
+    // per stage for all maps of a chunk
+    const int64_t budget = std::max<int64_t>(o.vertex_budget > 0 ? o.vertex_budget : (1ll << 28), max_verts);
+    double t_shoot = 0.0, t_ipm = 0.0;
+    int64_t n_chunks = 0, n_big = 0, n_rays = 0, n_cells = 0;
+    std::vector<BatchMap> hm;
+    for (int32_t c0 = 0; c0 < nmaps; ++n_chunks) {
+        int32_t c1 = c0;
+        int64_t sv = 0;
+        while (c1 < nmaps && (c1 == c0 || sv + P[c1].nverts <= budget)) sv += P[c1++].nverts;
+        const int32_t nm = c1 - c0;
+        double2 *verts = static_cast<double2 *>(B.verts.reserve((size_t)sv * sizeof(double2)));
+        hm.assign(nm, BatchMap{});
+        int64_t vo = 0, tl = 0, ctl = 0, cl = 0, bl = 0;
+        for (int32_t k = 0; k < nm; ++k) {
+            const MapPlan &m = P[c0 + k];
+            BatchMap &d = hm[k];
+            d.x0 = m.R.x0;
+            d.y0 = m.R.y0;
+            d.d1 = m.R.d1;
+            d.d2 = m.R.d2;
+            d.nr1 = m.R.nr1;
+            d.nrows = m.R.nr2 - 1;
+            d.lc = m.lc;
+            d.g = m.g;
+            d.tile_leaf = m.lens->ws.tile_leaf.as<int32_t>();
+            d.tile_off = m.lens->ws.tile_off.as<int32_t>();
+            d.leaves = m.T.leaves;
+            d.near = m.T.near;
+            d.deriv = m.T.mixed ? static_cast<const void *>(m.T.deriv_f) : static_cast<const void *>(m.T.deriv);
+            d.verts = verts + vo;
+            d.map = m.map;
+            d.counters = cnt + 8 * (c0 + k);
+            d.tile_lo = tl;
+            d.ctile_lo = ctl;
+            d.cell_lo = cl;
+            d.band_lo = bl;
+            d.bh = m.bh;
+            d.p = m.T.p;
+            d.mixed = m.T.mixed ? 1 : 0;
+            vo += m.nverts;
+            tl += m.ntiles;
+            ctl += m.nctiles;
+            cl += m.ncells;
+            bl += m.nbands;
+        }
+        BatchMap *dmaps = static_cast<BatchMap *>(B.maps.reserve((size_t)nm * sizeof(BatchMap)));
+        MLM_HIP(hipMemcpyAsync(dmaps, hm.data(), (size_t)nm * sizeof(BatchMap), hipMemcpyHostToDevice, st));
+        mlm_lens *scan_lens = P[c0].lens;
+        const int ea = tm.mark();
+        launch_shoot_batch(dmaps, nm, tl, st);
+        const int eb = tm.mark();
+        int32_t *nbig = static_cast<int32_t *>(B.nbig.reserve((size_t)std::max<int64_t>(cl, 1) * sizeof(int32_t)));
+        int64_t *boff = static_cast<int64_t *>(B.boff.reserve((size_t)(cl + 1) * sizeof(int64_t)));
+        launch_ipm_batch(dmaps, nm, ctl, nbig, st);
+        const int64_t nb = scan_i32_to_i64(scan_lens, nbig, boff, cl, st);
+        if (nb > 0) {
+            BigPrep *prep = static_cast<BigPrep *>(B.prep.reserve((size_t)nb * sizeof(BigPrep)));
+            int64_t *rows = static_cast<int64_t *>(B.rows.reserve((size_t)nb * sizeof(int64_t)));
+            int32_t *owner = static_cast<int32_t *>(B.owner.reserve((size_t)nb * sizeof(int32_t)));
+            launch_big_gather_batch(dmaps, nm, cl, boff, prep, rows, owner, st);
+            int32_t *bcnt = static_cast<int32_t *>(B.bcnt.reserve((size_t)bl * sizeof(int32_t)));
+            hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((bl + 255) / 256)), dim3(256), 0, st, bcnt, bl);
+            launch_band_count_batch(dmaps, nb, prep, rows, owner, bcnt, st);
+            unsigned long long *boffs =
+                static_cast<unsigned long long *>(B.boffs.reserve((size_t)(bl + 1) * sizeof(unsigned long long)));
+            const int64_t nlist = scan_i32_to_u64(scan_lens, bcnt, boffs, bl, st);
+            int32_t *blist = static_cast<int32_t *>(B.blist.reserve((size_t)std::max<int64_t>(nlist, 1) * sizeof(int32_t)));
+            unsigned long long *bcur =
+                static_cast<unsigned long long *>(B.bcur.reserve((size_t)bl * sizeof(unsigned long long)));
+            MLM_HIP(hipMemcpyAsync(bcur, boffs, (size_t)bl * sizeof(unsigned long long), hipMemcpyDeviceToDevice, st));
+            launch_band_scatter_batch(dmaps, nb, prep, rows, owner, bcur, blist, st);
+            launch_band_batch(dmaps, nm, bl, boffs, blist, prep, rows, max_band_lds, st);
+        }
+        const int ec = tm.mark();
+        MLM_HIP(hipStreamSynchronize(st));   // the chunk's buffers are reused by the next one
+        t_shoot += tm.ms(ea, eb);
+        t_ipm += tm.ms(eb, ec);
+        n_big += nb;
+        n_rays += vo;
+        n_cells += cl;
+        c0 = c1;
+    }
+    std::vector<unsigned long long> hc((size_t)nmaps * 8);
+    MLM_HIP(hipMemcpyAsync(hc.data(), cnt, hc.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    for (int32_t i = 0; i < nmaps; ++i)
+        if (!P[i].q.device_out)
+            MLM_HIP(hipMemcpyAsync(mus[i], P[i].map, (size_t)P[i].q.n1 * P[i].q.n2 * sizeof(double),
+                                   hipMemcpyDeviceToHost, st));
+    const int e_end = tm.mark();
+    MLM_HIP(hipStreamSynchronize(st));
+    if (stats)
+        for (int32_t i = 0; i < nmaps; ++i) {
+            const MapPlan &m = P[i];
+            mlm_map_stats S{};
+            S.n_rays = m.nverts;
+            S.n_cells = m.ncells;
+            S.n_skipped = (int64_t)hc[8 * i];
+            S.n_nodes = m.T.nnodes;
+            S.n_leaves = m.T.nleaves;
+            S.n_levels = m.T.nlevels;
+            S.order = m.T.p;
+            S.n_tiles = m.ntiles;
+            S.tri_area = 0.5 * m.R.d1 * m.R.d2;
+            S.t_tree_ms = tm.ms(m.e_tree0, m.e_tree1);
+            S.t_fmm_ms = tm.ms(m.e_tree1, m.e_fmm1);
+            S.n_shoot_launches = S.n_ipm_launches = 0;
+            stats[i] = S;
+        }
+    if (bstats) {
+        mlm_batch_stats b{};
+        b.n_maps = nmaps;
+        b.n_chunks = n_chunks;
+        b.n_rays = n_rays;
+        b.n_cells = n_cells;
+        b.n_big = n_big;
+        b.t_prep_ms = tm.ms(e_start, e_prep);
+        b.t_shoot_ms = t_shoot;
+        b.t_ipm_ms = t_ipm;
+        b.t_total_ms = tm.ms(e_start, e_end);
+        *bstats = b;
     }
     API_END
 }
@@ -602,8 +906,21 @@ mlm_status mlm_fmm_export(mlm_lens *lens, const mlm_map_request *req, mlm_tree_i
         if (nstars) nstars[k] = hi[k] - lo[k];
         if (block) block[k] = bk[k];
     }
-    if (mult) MLM_HIP(hipMemcpy(mult, T.mult, N * P1 * sizeof(double2), hipMemcpyDeviceToHost));
-    if (local) MLM_HIP(hipMemcpy(local, T.local, N * P1 * sizeof(double2), hipMemcpyDeviceToHost));
+    if (T.mixed) {   // FP32 coefficients, widened
+        std::vector<float2> h((size_t)(N * P1));
+        for (int which = 0; which < 2; ++which) {
+            double *dst = which ? local : mult;
+            if (!dst) continue;
+            MLM_HIP(hipMemcpy(h.data(), which ? T.local_f : T.mult_f, h.size() * sizeof(float2), hipMemcpyDeviceToHost));
+            for (size_t k = 0; k < h.size(); ++k) {
+                dst[2 * k] = h[k].x;
+                dst[2 * k + 1] = h[k].y;
+            }
+        }
+    } else {
+        if (mult) MLM_HIP(hipMemcpy(mult, T.mult, N * P1 * sizeof(double2), hipMemcpyDeviceToHost));
+        if (local) MLM_HIP(hipMemcpy(local, T.local, N * P1 * sizeof(double2), hipMemcpyDeviceToHost));
+    }
     API_END
 }
 

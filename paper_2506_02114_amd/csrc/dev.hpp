@@ -95,4 +95,44 @@ __device__ inline double2 cpowi(double2 z, int n)
     return r;
 }
 
+// the same on float2, and the complex type of a real type
+__device__ __host__ inline float2 cmul(float2 a, float2 b)
+{
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __host__ inline float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ inline float2 cinv(float2 a)
+{
+    float r = __builtin_amdgcn_rcpf(a.x * a.x + a.y * a.y);
+    return make_float2(a.x * r, -a.y * r);
+}
+__device__ inline float2 cpowi(float2 z, int n)
+{
+    float2 r = make_float2(1.0f, 0.0f);
+    while (n) {
+        if (n & 1) r = cmul(r, z);
+        z = cmul(z, z);
+        n >>= 1;
+    }
+    return r;
+}
+
+template <class R> struct Cx;
+template <> struct Cx<double> {
+    using c2 = double2;
+    using v4 = double4;
+    __device__ __host__ static c2 make(double a, double b) { return make_double2(a, b); }
+    __device__ __host__ static v4 make4(double a, double b, double c) { return make_double4(a, b, c, 0.0); }
+};
+template <> struct Cx<float> {
+    using c2 = float2;
+    using v4 = float4;
+    __device__ __host__ static c2 make(float a, float b) { return make_float2(a, b); }
+    __device__ __host__ static v4 make4(float a, float b, float c) { return make_float4(a, b, c, 0.0f); }
+};
+
+// a / b: FP64 division, or a times the FP32 hardware reciprocal (1 ulp)
+__device__ inline double qdiv(double a, double b) { return a / b; }
+__device__ inline float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
 }  // namespace mlm

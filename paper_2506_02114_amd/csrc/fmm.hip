@@ -111,42 +111,47 @@ __device__ inline void node_geom(uint64_t code, int lev, double L0, double &cx, 
     cy = -L0 + (double)(2 * (int64_t)j + 1) * L;
 }
 
-// upward pass of one level: P2M at leaves, M2M from the four children elsewhere
+// upward pass of one level: P2M at leaves, M2M from the four children
+// elsewhere.  R is the arithmetic type of the coefficients; star offsets from
+// the node centre are always formed in FP64.
+template <class R>
 __global__ void k_upward(int64_t lo, int64_t hi, int lev, int p, double L0, const uint64_t *__restrict__ code,
                          const int32_t *__restrict__ leaf, const int32_t *__restrict__ slo,
                          const int32_t *__restrict__ shi, const int32_t *__restrict__ child0,
                          const double *__restrict__ sx, const double *__restrict__ sy,
-                         const double *__restrict__ sm, const double2 *__restrict__ m2m,
-                         double2 *__restrict__ mult)
+                         const double *__restrict__ sm, const typename Cx<R>::c2 *__restrict__ m2m,
+                         typename Cx<R>::c2 *__restrict__ mult)
 {
+    using C2 = typename Cx<R>::c2;
     const int P1 = p + 1;
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t q = lo + t / P1;
     int k = (int)(t % P1);
     if (q >= hi) return;
-    double2 acc = make_double2(0.0, 0.0);
+    C2 acc = Cx<R>::make(0, 0);
     if (leaf[q]) {
         double cx, cy, L, invL;
         node_geom(code[q], lev, L0, cx, cy, L, invL);
         // a_0 = sum m_i;  a_k = -(1/k) sum m_i zeta_i^k
         for (int32_t s = slo[q]; s < shi[q]; ++s) {
+            const R m = (R)sm[s];
             if (k == 0) {
-                acc.x += sm[s];
+                acc.x += m;
             } else {
-                double2 z = make_double2((sx[s] - cx) * invL, (sy[s] - cy) * invL);
-                double2 zk = cpowi(z, k);
-                acc.x -= sm[s] * zk.x;
-                acc.y -= sm[s] * zk.y;
+                C2 z = Cx<R>::make((R)((sx[s] - cx) * invL), (R)((sy[s] - cy) * invL));
+                C2 zk = cpowi(z, k);
+                acc.x -= m * zk.x;
+                acc.y -= m * zk.y;
             }
         }
-        if (k > 0) acc = cscale(acc, 1.0 / (double)k);
+        if (k > 0) acc = cscale(acc, (R)1 / (R)k);
     } else {
         int32_t c0 = child0[q];
         for (int quad = 0; quad < 4; ++quad) {
-            const double2 *op = m2m + (quad * P1 + k) * P1;
-            const double2 *a = mult + (int64_t)(c0 + quad) * P1;
+            const C2 *op = m2m + (quad * P1 + k) * P1;
+            const C2 *a = mult + (int64_t)(c0 + quad) * P1;
             for (int kk = 0; kk <= k; ++kk) {
-                double2 o = op[kk], v = a[kk];
+                C2 o = op[kk], v = a[kk];
                 acc.x += o.x * v.x - o.y * v.y;
                 acc.y += o.x * v.y + o.y * v.x;
             }
@@ -156,31 +161,33 @@ __global__ void k_upward(int64_t lo, int64_t hi, int lev, int p, double L0, cons
 }
 
 // downward pass of one level (>= 2): Taylor coefficient l of each node
+template <class R>
 __global__ void k_downward(int64_t lo, int64_t hi, int lev, int p, double L0, const uint64_t *__restrict__ code,
                            const int32_t *__restrict__ parent, const IEntry *__restrict__ ilist,
                            const double *__restrict__ sx, const double *__restrict__ sy,
-                           const double *__restrict__ sm, const double2 *__restrict__ m2l,
-                           const double2 *__restrict__ l2l, const double2 *__restrict__ mult,
-                           double2 *__restrict__ local)
+                           const double *__restrict__ sm, const typename Cx<R>::c2 *__restrict__ m2l,
+                           const typename Cx<R>::c2 *__restrict__ l2l, const typename Cx<R>::c2 *__restrict__ mult,
+                           typename Cx<R>::c2 *__restrict__ local)
 {
+    using C2 = typename Cx<R>::c2;
     const int P1 = p + 1;
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t q = lo + t / P1;
     int l = (int)(t % P1);
     if (q >= hi) return;
     if (l == 0) {
-        local[q * P1] = make_double2(0.0, 0.0);   // c_0 only shifts the potential
+        local[q * P1] = Cx<R>::make(0, 0);   // c_0 only shifts the potential
         return;
     }
     uint64_t c = code[q];
-    double2 acc = make_double2(0.0, 0.0);
+    C2 acc = Cx<R>::make(0, 0);
     // L2L from the parent (levels 0 and 1 have no far field)
     if (lev >= 3) {
         int quad = (int)((c & 1ull) | (((c >> 1) & 1ull) << 1));
-        const double2 *op = l2l + (quad * P1 + l) * P1;
-        const double2 *cp = local + (int64_t)parent[q] * P1;
+        const C2 *op = l2l + (quad * P1 + l) * P1;
+        const C2 *cp = local + (int64_t)parent[q] * P1;
         for (int k = l; k <= p; ++k) {
-            double2 o = op[k], v = cp[k];
+            C2 o = op[k], v = cp[k];
             acc.x += o.x * v.x - o.y * v.y;
             acc.y += o.x * v.y + o.y * v.x;
         }
@@ -192,19 +199,19 @@ __global__ void k_downward(int64_t lo, int64_t hi, int lev, int p, double L0, co
         IEntry en = list[e];
         if (en.src >= 0) {
             // M2L
-            const double2 *op = m2l + (en.off * P1 + l) * P1;
-            const double2 *b = mult + (int64_t)en.src * P1;
+            const C2 *op = m2l + (en.off * P1 + l) * P1;
+            const C2 *b = mult + (int64_t)en.src * P1;
             for (int k = 0; k <= p; ++k) {
-                double2 o = op[k], v = b[k];
+                C2 o = op[k], v = b[k];
                 acc.x += o.x * v.x - o.y * v.y;
                 acc.y += o.x * v.y + o.y * v.x;
             }
         } else if (en.src == -1) {
             // P2L: c_l += -m_i / (l zeta_i^l)
             for (int32_t s = en.slo; s < en.shi; ++s) {
-                double2 z = make_double2((sx[s] - cx) * invL, (sy[s] - cy) * invL);
-                double2 w = cpowi(cinv(z), l);
-                double f = -sm[s] / (double)l;
+                C2 z = Cx<R>::make((R)((sx[s] - cx) * invL), (R)((sy[s] - cy) * invL));
+                C2 w = cpowi(cinv(z), l);
+                R f = -(R)sm[s] / (R)l;
                 acc.x += f * w.x;
                 acc.y += f * w.y;
             }
@@ -213,21 +220,24 @@ __global__ void k_downward(int64_t lo, int64_t hi, int lev, int p, double L0, co
     local[q * P1 + l] = acc;
 }
 
-__global__ void k_zero2(double2 *a, int64_t n)
+template <class C2>
+__global__ void k_zero2(C2 *a, int64_t n)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) a[t] = make_double2(0.0, 0.0);
+    if (t < n) a[t] = C2{0, 0};
 }
 
 // per-leaf data for the ray kernels: geometry, derivative of the Taylor
-// series and the stars of the leaf's 3x3 block relative to its centre
+// series (in R) and the stars of the leaf's 3x3 block relative to its centre
+// (FP64 in both modes: a ray's offset from a star is formed from them)
+template <class R>
 __global__ void k_leaf_tables(int64_t nleaves, int p, double L0, const int32_t *__restrict__ leaf_node,
                               const uint64_t *__restrict__ code, const int32_t *__restrict__ level,
                               const int32_t *__restrict__ block, const int32_t *__restrict__ near_offs,
                               const uint64_t *__restrict__ keys, int32_t n, const double *__restrict__ sx,
                               const double *__restrict__ sy, const double *__restrict__ sm,
-                              const double2 *__restrict__ local, LeafInfo *__restrict__ info,
-                              double2 *__restrict__ deriv, double4 *__restrict__ near)
+                              const typename Cx<R>::c2 *__restrict__ local, LeafInfo *__restrict__ info,
+                              typename Cx<R>::c2 *__restrict__ deriv, double4 *__restrict__ near)
 {
     int64_t lf = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (lf >= nleaves) return;
@@ -247,7 +257,7 @@ __global__ void k_leaf_tables(int64_t nleaves, int p, double L0, const int32_t *
     info[lf] = li;
     const int P1 = p + 1;
     // d psi / dz = (1/L) sum_{l>=1} l c_l zeta^(l-1)
-    for (int l = 0; l < p; ++l) deriv[lf * p + l] = cscale(local[(int64_t)q * P1 + l + 1], (double)(l + 1) * invL);
+    for (int l = 0; l < p; ++l) deriv[lf * p + l] = cscale(local[(int64_t)q * P1 + l + 1], (R)((double)(l + 1) * invL));
     uint32_t i = compact_bits(c), j = compact_bits(c >> 1);
     int64_t side = 1ll << lev;
     int sh = 2 * (KEY_BITS - lev);
@@ -271,42 +281,62 @@ __global__ void k_leaf_block(int64_t nleaves, const int32_t *__restrict__ leaf_n
 
 }  // namespace
 
-void run_fmm(mlm_lens *lens, Tree &T, int p, hipStream_t st)
+namespace {
+
+template <class R>
+void upload_ops(DevBuf &buf, const std::vector<double2> &h)
 {
+    using C2 = typename Cx<R>::c2;
+    std::vector<C2> c(h.size());
+    for (size_t k = 0; k < h.size(); ++k) c[k] = Cx<R>::make((R)h[k].x, (R)h[k].y);
+    void *d = buf.reserve(c.size() * sizeof(C2));
+    MLM_HIP(hipMemcpy(d, c.data(), c.size() * sizeof(C2), hipMemcpyHostToDevice));
+}
+
+template <class R>
+void run_fmm_t(mlm_lens *lens, Tree &T, int p, hipStream_t st, typename Cx<R>::c2 *&mult,
+               typename Cx<R>::c2 *&local)
+{
+    using C2 = typename Cx<R>::c2;
     Workspace &ws = lens->ws;
-    if (p < 1 || p > MAX_ORDER) fail(MLM_EINVAL, "expansion order %d outside [1, %d]", p, MAX_ORDER);
-    T.p = p;
     const int P1 = p + 1;
-    if (ws.ops_p != p) {
+    const int key = 2 * p + (sizeof(R) == 4 ? 1 : 0);
+    if (ws.ops_p != key) {
         std::vector<double2> h;
         table_m2m(p, h);
-        void *d = ws.ops_m2m.reserve(h.size() * sizeof(double2));
-        MLM_HIP(hipMemcpy(d, h.data(), h.size() * sizeof(double2), hipMemcpyHostToDevice));
+        upload_ops<R>(ws.ops_m2m, h);
         table_m2l(p, h);
-        d = ws.ops_m2l.reserve(h.size() * sizeof(double2));
-        MLM_HIP(hipMemcpy(d, h.data(), h.size() * sizeof(double2), hipMemcpyHostToDevice));
+        upload_ops<R>(ws.ops_m2l, h);
         table_l2l(p, h);
-        d = ws.ops_l2l.reserve(h.size() * sizeof(double2));
-        MLM_HIP(hipMemcpy(d, h.data(), h.size() * sizeof(double2), hipMemcpyHostToDevice));
-        ws.ops_p = p;
+        upload_ops<R>(ws.ops_l2l, h);
+        ws.ops_p = key;
     }
-    T.mult = static_cast<double2 *>(ws.mult.reserve((size_t)T.nnodes * P1 * sizeof(double2)));
-    T.local = static_cast<double2 *>(ws.local.reserve((size_t)T.nnodes * P1 * sizeof(double2)));
+    mult = static_cast<C2 *>(ws.mult.reserve((size_t)T.nnodes * P1 * sizeof(C2)));
+    local = static_cast<C2 *>(ws.local.reserve((size_t)T.nnodes * P1 * sizeof(C2)));
     // upward
     for (int lev = T.nlevels - 1; lev >= 0; --lev) {
         int64_t lo = T.level_lo[lev], hi = T.level_hi[lev], nt = (hi - lo) * P1;
-        hipLaunchKernelGGL(k_upward, dim3(nblocks(nt)), dim3(BLK), 0, st, lo, hi, lev, p, T.L0, T.code,
-                           T.leaf, T.slo, T.shi, T.child0, T.x, T.y, T.m, ws.ops_m2m.as<double2>(), T.mult);
+        hipLaunchKernelGGL(k_upward<R>, dim3(nblocks(nt)), dim3(BLK), 0, st, lo, hi, lev, p, T.L0, T.code, T.leaf,
+                           T.slo, T.shi, T.child0, T.x, T.y, T.m, ws.ops_m2m.as<C2>(), mult);
     }
     // downward: levels 0, 1 have no far field
     int64_t top = T.nlevels > 2 ? T.level_lo[2] : T.nnodes;
-    hipLaunchKernelGGL(k_zero2, dim3(nblocks(top * P1)), dim3(BLK), 0, st, T.local, top * P1);
+    hipLaunchKernelGGL(k_zero2<C2>, dim3(nblocks(top * P1)), dim3(BLK), 0, st, local, top * P1);
     for (int lev = 2; lev < T.nlevels; ++lev) {
         int64_t lo = T.level_lo[lev], hi = T.level_hi[lev], nt = (hi - lo) * P1;
-        hipLaunchKernelGGL(k_downward, dim3(nblocks(nt)), dim3(BLK), 0, st, lo, hi, lev, p, T.L0, T.code,
-                           T.parent, T.ilist, T.x, T.y, T.m, ws.ops_m2l.as<double2>(),
-                           ws.ops_l2l.as<double2>(), T.mult, T.local);
+        hipLaunchKernelGGL(k_downward<R>, dim3(nblocks(nt)), dim3(BLK), 0, st, lo, hi, lev, p, T.L0, T.code,
+                           T.parent, T.ilist, T.x, T.y, T.m, ws.ops_m2l.as<C2>(), ws.ops_l2l.as<C2>(), mult, local);
     }
+}
+
+}  // namespace
+
+void run_fmm(mlm_lens *lens, Tree &T, int p, hipStream_t st)
+{
+    if (p < 1 || p > MAX_ORDER) fail(MLM_EINVAL, "expansion order %d outside [1, %d]", p, MAX_ORDER);
+    T.p = p;
+    if (T.mixed) run_fmm_t<float>(lens, T, p, st, T.mult_f, T.local_f);
+    else run_fmm_t<double>(lens, T, p, st, T.mult, T.local);
 }
 
 void build_leaf_tables(mlm_lens *lens, Tree &T, hipStream_t st)
@@ -318,11 +348,19 @@ void build_leaf_tables(mlm_lens *lens, Tree &T, hipStream_t st)
     hipLaunchKernelGGL(k_leaf_block, dim3(nblocks(nl)), dim3(BLK), 0, st, nl, T.leaf_node, T.block, cnt);
     T.near_total = scan_total_public(lens, cnt, offs, nl, st);
     T.leaves = static_cast<LeafInfo *>(ws.leaves.reserve(nl * sizeof(LeafInfo)));
-    T.deriv = static_cast<double2 *>(ws.deriv.reserve((size_t)nl * T.p * sizeof(double2)));
-    T.near = static_cast<double4 *>(ws.near.reserve((size_t)(T.near_total > 0 ? T.near_total : 1) * sizeof(double4)));
-    hipLaunchKernelGGL(k_leaf_tables, dim3(nblocks(nl, 64)), dim3(64), 0, st, nl, T.p, T.L0, T.leaf_node, T.code,
-                       T.level, T.block, offs, T.keys, (int32_t)T.n, T.x, T.y, T.m, T.local, T.leaves, T.deriv,
-                       T.near);
+    const size_t nn = (size_t)(T.near_total > 0 ? T.near_total : 1);
+    T.near = static_cast<double4 *>(ws.near.reserve(nn * sizeof(double4)));
+    if (T.mixed) {
+        T.deriv_f = static_cast<float2 *>(ws.deriv.reserve((size_t)nl * T.p * sizeof(float2)));
+        hipLaunchKernelGGL(k_leaf_tables<float>, dim3(nblocks(nl, 64)), dim3(64), 0, st, nl, T.p, T.L0, T.leaf_node,
+                           T.code, T.level, T.block, offs, T.keys, (int32_t)T.n, T.x, T.y, T.m, T.local_f,
+                           T.leaves, T.deriv_f, T.near);
+    } else {
+        T.deriv = static_cast<double2 *>(ws.deriv.reserve((size_t)nl * T.p * sizeof(double2)));
+        hipLaunchKernelGGL(k_leaf_tables<double>, dim3(nblocks(nl, 64)), dim3(64), 0, st, nl, T.p, T.L0,
+                           T.leaf_node, T.code, T.level, T.block, offs, T.keys, (int32_t)T.n, T.x, T.y, T.m, T.local,
+                           T.leaves, T.deriv, T.near);
+    }
 }
 
 }  // namespace mlm

@@ -99,6 +99,14 @@ struct BigPrep {
     double ou, ov, scale;
 };
 
+// ray-grid geometry of a shooting launch
+struct ShootArgs {
+    double x0, y0, d1, d2;
+    int64_t nr1, vb0;
+    int p;
+    int pad;
+};
+
 // map geometry for the IPM, in pixel units
 struct MapGeom {
     double ylo1, ylo2;      // lower-left corner of the map
@@ -106,6 +114,38 @@ struct MapGeom {
     int32_t n1, n2;
     double tri_weight;      // image area of a triangle / pixel area
 };
+
+// one map of a fused batch, as the batch kernels see it (device array, in
+// the order of the maps; the *_lo fields are non-decreasing prefix offsets)
+struct BatchMap {
+    double x0, y0, d1, d2;            // ray grid
+    int64_t nr1, nrows;               // vertices per grid row, cell rows
+    LensConst lc;
+    MapGeom g;
+    const int32_t *tile_leaf, *tile_off;
+    const LeafInfo *leaves;
+    const double4 *near;
+    const void *deriv;                // double2, or float2 if mixed
+    double2 *verts;                   // vertex rows 0 .. nrows of this map
+    double *map;                      // n2 x n1, accumulated into
+    unsigned long long *counters;     // [0] skipped triangles of this map
+    int64_t tile_lo, ctile_lo, cell_lo, band_lo;   // first shoot tile, cell tile, cell, band
+    int32_t bh, p, mixed, pad;
+};
+
+// index of the map whose range [lo, next lo) holds item x (maps with empty
+// ranges are skipped: the last map whose lo <= x)
+template <class T>
+__device__ inline int32_t batch_find(const BatchMap *maps, int32_t nmaps, int64_t x, T BatchMap::*lo)
+{
+    int32_t a = 0, b = nmaps - 1;
+    while (a < b) {
+        const int32_t mid = (a + b + 1) >> 1;
+        if (maps[mid].*lo <= x) a = mid;
+        else b = mid - 1;
+    }
+    return a;
+}
 
 // FMM tree with coefficients (device arrays) and host metadata
 struct Tree {
@@ -125,11 +165,14 @@ struct Tree {
     int32_t *parent = nullptr, *child0 = nullptr, *node_leaf = nullptr;
     int32_t *leaf_node = nullptr;
     IEntry *ilist = nullptr;
+    bool mixed = false;                  // FP32 coefficients and leaf tables (the *_f arrays)
     double2 *mult = nullptr, *local = nullptr;
+    float2 *mult_f = nullptr, *local_f = nullptr;
     // leaf tables
     LeafInfo *leaves = nullptr;
-    double4 *near = nullptr;             // (dx, dy, m, 0) relative to the leaf centre
+    double4 *near = nullptr;             // (dx, dy, m, 0) relative to the leaf centre (both modes)
     double2 *deriv = nullptr;            // [nleaves][p]: (l+1) c_{l+1} / L
+    float2 *deriv_f = nullptr;           // the same in FP32 (mixed mode)
 };
 
 struct Workspace {
@@ -141,7 +184,7 @@ struct Workspace {
         bandcur, bandlist;
     void *pinned = nullptr;               // small pinned host buffer for read-backs
     size_t pinned_cap = 0;
-    int ops_p = -1;                       // order the operator tables were built for
+    int ops_p = -1;                       // 2 x order (+1 for FP32) of the operator tables
     ~Workspace();
 };
 
@@ -181,12 +224,13 @@ void launch_shoot(mlm_lens *lens, const Tree &T, const Region &R, const LensCons
 void launch_shoot_direct(mlm_lens *lens, const Region &R, const LensConst &lc, const MapGeom &g,
                          int64_t vb0, int64_t vb1, double2 *verts, double *w_out,
                          hipStream_t st);
+void launch_shoot_batch(const BatchMap *maps, int32_t nmaps, int64_t ntiles, hipStream_t st);
 void launch_deflect_points(mlm_lens *lens, const Tree *T, const LensConst &lc, const double *z,
                            int64_t n, double *w, hipStream_t st);
 
 // ipm.hip
 void launch_ipm(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int64_t vb0, const MapGeom &g,
-                double *map, unsigned long long *counters, int32_t *nbig, hipStream_t st);
+                double *map, unsigned long long *counters, int32_t *nbig, bool mixed, hipStream_t st);
 void launch_big_gather(int64_t ncells, const int64_t *boff, const double2 *verts, int64_t nr1, int64_t cb0,
                        int64_t vb0, const MapGeom &g, BigPrep *prep, int64_t *rows, hipStream_t st);
 void launch_big(int64_t nbig, const BigPrep *prep, const int64_t *rows, const MapGeom &g, double *map, double *diff,
@@ -200,6 +244,16 @@ void launch_band_scatter(int64_t nbig, const BigPrep *prep, const int64_t *rows,
 void launch_band(int32_t nbands, const unsigned long long *band_off, const int32_t *list, const BigPrep *prep,
                  const int64_t *rows, int bh, const MapGeom &g, double *map, unsigned long long *work,
                  hipStream_t st);
+void launch_ipm_batch(const BatchMap *maps, int32_t nmaps, int64_t nctiles, int32_t *nbig, hipStream_t st);
+void launch_big_gather_batch(const BatchMap *maps, int32_t nmaps, int64_t ncells, const int64_t *boff, BigPrep *prep,
+                             int64_t *rows, int32_t *owner, hipStream_t st);
+void launch_band_count_batch(const BatchMap *maps, int64_t nbig, const BigPrep *prep, const int64_t *rows,
+                             const int32_t *owner, int32_t *count, hipStream_t st);
+void launch_band_scatter_batch(const BatchMap *maps, int64_t nbig, const BigPrep *prep, const int64_t *rows,
+                               const int32_t *owner, unsigned long long *cursor, int32_t *list, hipStream_t st);
+void launch_band_batch(const BatchMap *maps, int32_t nmaps, int64_t nbands, const unsigned long long *band_off,
+                       const int32_t *list, const BigPrep *prep, const int64_t *rows, int64_t lds_doubles,
+                       hipStream_t st);
 int64_t scan_i32_to_u64(mlm_lens *lens, const int32_t *in, unsigned long long *out, int64_t n, hipStream_t st);
 int64_t scan_total_i64(mlm_lens *lens, const int64_t *in, int64_t *out, int64_t n, hipStream_t st);
 int64_t scan_i32_to_i64(mlm_lens *lens, const int32_t *in, int64_t *out, int64_t n, hipStream_t st);

@@ -2,44 +2,45 @@
 // triangles; each mapped triangle's image-plane area is apportioned among the
 // source pixels it covers, in proportion to (triangle n pixel) / triangle.
 //
-// A triangle is cut along pixel columns, and each column piece along pixel
-// rows, as in the paper's column-then-row clipping.  The clipping keeps a
-// fixed number of vertex slots: each polygon edge is clipped to the strip by
-// its parameter interval (Liang-Barsky), and an edge entirely outside the
-// strip is replaced by a repeat of the previous exit point.  For a convex
-// polygon the gaps so closed run along the strip's boundary lines, so the
-// slots trace exactly the clipped polygon, with every index known at compile
-// time (no dynamically indexed arrays, nothing spilled to scratch).
+// Pixel areas come from closed forms instead of explicit polygon clipping:
+// inside a strip of pixel rows (or columns) the triangle's area on one side of
+// a line across the strip is a sum over its edges clipped to the strip of
+// (signed extent) x (integral of a clamped linear function), and the area of
+// a pixel is the difference of two such sums.
 //
-// Triangles next to a star map to huge triangles (the linear interpolation
-// of a singular mapping), covering up to millions of pixels.  Their cost is
-// made proportional to their perimeter instead of their area: they are queued
-// and processed one (triangle, pixel row) per thread; in each row only the
-// pixels on the triangle's boundary are clipped, and the run of fully covered
-// pixels between them is recorded as two entries of a per-row difference
-// buffer, whose prefix sums are added to the map at the end.
+// Ordinary triangles go by pixel columns, one work item per (triangle,
+// column).  Triangles next to a star map to huge triangles (the linear
+// interpolation of a singular mapping), covering up to millions of pixels;
+// their cost is made proportional to their perimeter: they are binned by
+// bands of pixel rows and apportioned through per-row column differences.
+//
+// Every geometric helper is templated on its arithmetic type R: FP64, or FP32
+// in the mixed-precision mode, where coordinates are first made local to the
+// triangle in FP64 and the sums are kept in FP64.
+#include <algorithm>
+
 #include "dev.hpp"
 
 namespace mlm {
 
 namespace {
 
-struct P2 {
-    double u, v;
+template <class R> struct Pt {
+    R u, v;
 };
+using P2 = Pt<double>;
 
 constexpr int64_t BIG_PIXELS = 48;   // bounding-box pixels above which a triangle goes row by row
-
 
 // Part of segment P->Q with lo <= coordinate <= hi (AXIS 0: u, 1: v).  The
 // segment lies on a line whose other coordinate changes by `slope` per unit of
 // the clipping coordinate, so a crossing is one multiply-add.
-template <int AXIS>
-__device__ inline bool clip_seg(P2 P, P2 Q, double lo, double hi, double slope, P2 &E, P2 &X)
+template <int AXIS, class R>
+__device__ inline bool clip_seg(Pt<R> P, Pt<R> Q, R lo, R hi, R slope, Pt<R> &E, Pt<R> &X)
 {
-    const double p = AXIS ? P.v : P.u, q = AXIS ? Q.v : Q.u;
-    const double po = AXIS ? P.u : P.v;
-    auto at = [&](double c) { return AXIS ? P2{po + (c - p) * slope, c} : P2{c, po + (c - p) * slope}; };
+    const R p = AXIS ? P.v : P.u, q = AXIS ? Q.v : Q.u;
+    const R po = AXIS ? P.u : P.v;
+    auto at = [&](R c) { return AXIS ? Pt<R>{po + (c - p) * slope, c} : Pt<R>{c, po + (c - p) * slope}; };
     if (p == q) {
         if (p < lo || p > hi) return false;
         E = P;
@@ -58,71 +59,26 @@ __device__ inline bool clip_seg(P2 P, P2 Q, double lo, double hi, double slope, 
     return true;
 }
 
-// polygon of N slots clipped to a strip -> 2N slots; false if empty.
-// slope[k] is edge k's rate of change of the other coordinate per unit of the
-// clipping coordinate.  In the output, edge 2k lies on input edge k and edge
-// 2k+1 on a strip boundary line (or has zero length).
-template <int AXIS, int N>
-__device__ inline bool clip_poly(const P2 (&in)[N], const double (&slope)[N], double lo, double hi,
-                                 P2 (&out)[2 * N])
-{
-    P2 E[N], X[N];
-    bool ok[N];
-    bool any = false;
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        ok[k] = clip_seg<AXIS>(in[k], in[(k + 1) % N], lo, hi, slope[k], E[k], X[k]);
-        any = any || ok[k];
-    }
-    if (!any) return false;
-    P2 carry = in[0];
-#pragma unroll
-    for (int k = 0; k < N; ++k)
-        if (ok[k]) carry = X[k];     // exit point of the last non-empty edge
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        if (ok[k]) {
-            out[2 * k] = E[k];
-            out[2 * k + 1] = X[k];
-            carry = X[k];
-        } else {
-            out[2 * k] = carry;
-            out[2 * k + 1] = carry;
-        }
-    }
-    return true;
-}
-
-// slopes of the 6 edges of a polygon made by clipping a triangle to a strip,
-// for a clip along the other axis: triangle edge k's slope on edge 2k, zero on
-// the strip-boundary edges 2k+1
-__device__ inline void slopes6(const double (&tri)[3], double (&s6)[6])
-{
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        s6[2 * k] = tri[k];
-        s6[2 * k + 1] = 0.0;
-    }
-}
-
 // edge slopes of a triangle: sv = dv/du (for clips along u), su = du/dv (along v)
-__device__ inline void tri_slopes(const P2 (&T)[3], double (&sv)[3], double (&su)[3])
+template <class R>
+__device__ inline void tri_slopes(const Pt<R> (&T)[3], R (&sv)[3], R (&su)[3])
 {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const double du = T[(k + 1) % 3].u - T[k].u, dv = T[(k + 1) % 3].v - T[k].v;
-        sv[k] = du != 0.0 ? dv / du : 0.0;
-        su[k] = dv != 0.0 ? du / dv : 0.0;
+        const R du = T[(k + 1) % 3].u - T[k].u, dv = T[(k + 1) % 3].v - T[k].v;
+        sv[k] = du != R(0) ? qdiv(dv, du) : R(0);
+        su[k] = dv != R(0) ? qdiv(du, dv) : R(0);
     }
 }
 
 // integral over t in [0, 1] of max(ua + t (ub - ua), 0); inv = 1 / |ub - ua|
 // (unused when ua and ub have the same sign)
-__device__ inline double clamp_integral(double ua, double ub, double inv)
+template <class R>
+__device__ inline R clamp_integral(R ua, R ub, R inv)
 {
-    const double m = fmax(ua, ub);
-    const double cross = 0.5 * m * m * inv;
-    return (ua >= 0.0 && ub >= 0.0) ? 0.5 * (ua + ub) : ((ua <= 0.0 && ub <= 0.0) ? 0.0 : cross);
+    const R m = fmax(ua, ub);
+    const R cross = R(0.5) * m * m * inv;
+    return (ua >= R(0) && ub >= R(0)) ? R(0.5) * (ua + ub) : ((ua <= R(0) && ub <= R(0)) ? R(0) : cross);
 }
 
 // Pixel areas from the triangle's edges clipped to one strip.  For a strip of
@@ -132,52 +88,46 @@ __device__ inline double clamp_integral(double ua, double ub, double inv)
 // below it is  H(r) = sum_e du_e * I(r - va_e, r - vb_e).  A pixel's area is
 // then a difference of two such sums.  (Clockwise triangles give the negated
 // area, matching the sign of their signed area.)
-struct Segs {
-    double a[3], b[3];       // coordinate across the strip at both ends (u for rows, v for columns)
-    double d[3];             // signed extent along the strip (dv for rows, du for columns)
-    double inv[3];           // 1 / |b - a| (0 if equal)
+template <class R> struct SegsT {
+    R a[3], b[3];       // coordinate across the strip at both ends (u for rows, v for columns)
+    R d[3];             // signed extent along the strip (dv for rows, du for columns)
+    R inv[3];           // 1 / |b - a| (0 if equal)
 };
+using Segs = SegsT<double>;
 
-template <int AXIS>
-__device__ inline void strip_segments(const P2 (&T)[3], const double (&slope)[3], double lo, double hi, Segs &S)
+template <int AXIS, class R>
+__device__ inline void strip_segments(const Pt<R> (&T)[3], const R (&slope)[3], R lo, R hi, SegsT<R> &S)
 {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        P2 E, X;
+        Pt<R> E, X;
         if (clip_seg<AXIS>(T[k], T[(k + 1) % 3], lo, hi, slope[k], E, X)) {
             S.a[k] = AXIS ? E.u : E.v;
             S.b[k] = AXIS ? X.u : X.v;
             S.d[k] = AXIS ? X.v - E.v : X.u - E.u;
         } else {
-            S.a[k] = S.b[k] = S.d[k] = 0.0;
+            S.a[k] = S.b[k] = S.d[k] = R(0);
         }
-        const double w = fabs(S.b[k] - S.a[k]);
-        S.inv[k] = w > 0.0 ? 1.0 / w : 0.0;
+        const R w = fabs(S.b[k] - S.a[k]);
+        S.inv[k] = w > R(0) ? qdiv(R(1), w) : R(0);
     }
 }
 
 // sum_e d_e * I(c - a_e, c - b_e)
-__device__ inline double strip_cumulative(const Segs &S, double c)
+template <class R>
+__device__ inline R strip_cumulative(const SegsT<R> &S, R c)
 {
-    double s = 0.0;
+    R s = 0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) s += S.d[k] * clamp_integral(c - S.a[k], c - S.b[k], S.inv[k]);
     return s;
 }
 
-// twice the signed area (shoelace), coordinates taken relative to (ou, ov)
-template <int N>
-__device__ inline double shoelace2(const P2 (&p)[N], double ou, double ov)
-{
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        const double x1 = p[k].u - ou, y1 = p[k].v - ov;
-        const double x2 = p[(k + 1) % N].u - ou, y2 = p[(k + 1) % N].v - ov;
-        s += x1 * y2 - x2 * y1;
-    }
-    return s;
-}
+// Largest ratio of squared extent to twice the area that the FP32 geometry
+// of the mixed mode accepts: its relative area error is about FP32's unit
+// round-off times this ratio (below 2e-5 here).  Thinner triangles, the ones
+// folded across a caustic, are apportioned in FP64.
+constexpr double MIXED_MAX_COND = 256.0;
 
 __device__ inline void deposit(double *map, const MapGeom &g, int64_t i, int64_t j, double val)
 {
@@ -314,8 +264,42 @@ __device__ inline bool cell_in_one_pixel(P2 v00, P2 v10, P2 v11, P2 v01, const M
     return true;
 }
 
+// pixel pieces of one column of a triangle: T in coordinates local to the
+// integer point (fu0, fv0) (formed in FP64), cl = column - fu0; each piece is
+// a difference of the column's cumulative edge sum H at two row lines
+template <class R>
+__device__ inline void column_pieces(const P2 (&Td)[3], double cl, double fv0, int64_t i, int64_t j0, int64_t j1,
+                                     double scale, const MapGeom &g, double *map, const Window &w)
+{
+    const Pt<R> T[3] = {Pt<R>{(R)Td[0].u, (R)Td[0].v}, Pt<R>{(R)Td[1].u, (R)Td[1].v}, Pt<R>{(R)Td[2].u, (R)Td[2].v}};
+    R sv[3], su[3];
+    tri_slopes(T, sv, su);
+    SegsT<R> S;
+    strip_segments<0>(T, sv, (R)cl, (R)(cl + 1.0), S);
+    const R big = sizeof(R) == 4 ? R(3e38f) : R(1e300);
+    R cvmin = big, cvmax = -big;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        if (S.d[k] != R(0) || S.a[k] != S.b[k]) {
+            cvmin = fmin(cvmin, fmin(S.a[k], S.b[k]));
+            cvmax = fmax(cvmax, fmax(S.a[k], S.b[k]));
+        }
+    if (cvmin > cvmax) return;
+    // area below v = r inside the column; a piece is the difference of two
+    const int64_t ja = (int64_t)fmax(floor((double)cvmin) + fv0, (double)j0);
+    const int64_t jb = (int64_t)fmin(floor((double)cvmax) + fv0, (double)j1);
+    R h0 = strip_cumulative(S, (R)((double)ja - fv0));
+    for (int64_t j = ja; j <= jb; ++j) {
+        const R h1 = strip_cumulative(S, (R)((double)(j + 1) - fv0));
+        const double a2 = 2.0 * ((double)h1 - (double)h0);   // twice the piece area, signed like the triangle
+        h0 = h1;
+        if (a2 != 0.0) deposit_w(w, map, g, i, j, scale * a2);
+    }
+}
+
 // one pixel column `r` (counted over the cell's triangles that need clipping)
-// of cell `cell`: clip the triangle to the column, then to each pixel row
+// of cell `cell`
+template <bool MIXED>
 __device__ void cell_column(const double2 *verts, int64_t nr1, int64_t cb0, int64_t vb0, int64_t cell, int r,
                             const MapGeom &g, double *map, const Window &w)
 {
@@ -334,35 +318,23 @@ __device__ void cell_column(const double2 *verts, int64_t nr1, int64_t cb0, int6
         A = v00; B = v11; C = v01;
         i0 = k2.i0;
     }
-    const double fu0 = floor(fmin(A.u, fmin(B.u, C.u))), fv0 = floor(fmin(A.v, fmin(B.v, C.v)));
+    const double umin = fmin(A.u, fmin(B.u, C.u)), vmin = fmin(A.v, fmin(B.v, C.v));
+    const double fu0 = floor(umin), fv0 = floor(vmin);
     const double fv1 = floor(fmax(A.v, fmax(B.v, C.v)));
     const P2 T[3] = {P2{A.u - fu0, A.v - fv0}, P2{B.u - fu0, B.v - fv0}, P2{C.u - fu0, C.v - fv0}};
-    const double scale = g.tri_weight / twice_area(A, B, C, fu0, fv0);
+    const double S2 = twice_area(A, B, C, fu0, fv0);
+    const double scale = g.tri_weight / S2;
     const int64_t j0 = (int64_t)fmax(fv0, 0.0), j1 = (int64_t)fmin(fv1, (double)(g.n2 - 1));
     const int64_t i = i0 + r;
-    double sv[3], su[3];
-    tri_slopes(T, sv, su);
     const double cl = (double)i - fu0;
-    Segs S;
-    strip_segments<0>(T, sv, cl, cl + 1.0, S);
-    double cvmin = 1e300, cvmax = -1e300;
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-        if (S.d[k] != 0.0 || S.a[k] != S.b[k]) {
-            cvmin = fmin(cvmin, fmin(S.a[k], S.b[k]));
-            cvmax = fmax(cvmax, fmax(S.a[k], S.b[k]));
+    if (MIXED) {
+        const double eu = fmax(A.u, fmax(B.u, C.u)) - umin, ev = fmax(A.v, fmax(B.v, C.v)) - vmin;
+        if (eu * eu + ev * ev <= MIXED_MAX_COND * fabs(S2)) {
+            column_pieces<float>(T, cl, fv0, i, j0, j1, scale, g, map, w);
+            return;
         }
-    if (cvmin > cvmax) return;
-    // area below v = r inside the column; a piece is the difference of two
-    const int64_t ja = (int64_t)fmax(floor(cvmin) + fv0, (double)j0);
-    const int64_t jb = (int64_t)fmin(floor(cvmax) + fv0, (double)j1);
-    double h0 = strip_cumulative(S, (double)ja - fv0);
-    for (int64_t j = ja; j <= jb; ++j) {
-        const double h1 = strip_cumulative(S, (double)(j + 1) - fv0);
-        const double a2 = 2.0 * (h1 - h0);   // twice the piece area, signed like the triangle
-        h0 = h1;
-        if (a2 != 0.0) deposit_w(w, map, g, i, j, scale * a2);
     }
+    column_pieces<double>(T, cl, fv0, i, j0, j1, scale, g, map, w);
 }
 
 // IPM of the ordinary triangles.  A workgroup takes a tile of 16 x 16 cells
@@ -374,14 +346,17 @@ __device__ void cell_column(const double2 *verts, int64_t nr1, int64_t cb0, int6
 // window around the tile's image first.  Large triangles are only counted.
 constexpr int CT = 16;   // cells per tile side
 
-__global__ __launch_bounds__(256) void k_ipm(const double2 *__restrict__ verts, int64_t nr1, int64_t cb0,
-                                             int64_t nrows, int64_t vb0, MapGeom g, double *__restrict__ map,
-                                             unsigned long long *__restrict__ counters, int32_t *__restrict__ nbig)
+// cell tile `tile` of a strip (a whole workgroup of 256 threads; acc is its
+// WIN x WIN LDS window)
+template <bool MIXED>
+__device__ inline void ipm_tile(const double2 *__restrict__ verts, int64_t nr1, int64_t cb0, int64_t nrows,
+                                int64_t vb0, const MapGeom &g, double *__restrict__ map,
+                                unsigned long long *__restrict__ counters, int32_t *__restrict__ nbig, int64_t tile,
+                                double *acc)
 {
-    __shared__ double acc[WIN * WIN];
     const int64_t ncol = nr1 - 1;
     const int64_t tiles_a = (ncol + CT - 1) / CT;
-    const int64_t ta = blockIdx.x % tiles_a, tb = blockIdx.x / tiles_a;
+    const int64_t ta = tile % tiles_a, tb = tile / tiles_a;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t a = ta * CT + (lane & (CT - 1));
     const int64_t brow = tb * CT + wave * 4 + (lane >> 4);   // cell row within the strip
@@ -436,7 +411,7 @@ __global__ __launch_bounds__(256) void k_ipm(const double2 *__restrict__ verts, 
         const int L = wave_find(excl, item);
         const int r = item - __shfl(excl, L, 64);
         const int64_t c = __shfl(cell, L, 64);
-        if (item < total) cell_column(verts, nr1, cb0, vb0, c, r, g, map, w);
+        if (item < total) cell_column<MIXED>(verts, nr1, cb0, vb0, c, r, g, map, w);
     }
     __syncthreads();
     for (int k = threadIdx.x; k < WIN * WIN; k += blockDim.x) {
@@ -446,25 +421,47 @@ __global__ __launch_bounds__(256) void k_ipm(const double2 *__restrict__ verts, 
             deposit(map, g, i, j, v);   // inside the map: only in-map pixels were deposited
         }
     }
+    __syncthreads();   // the window may be reused by the workgroup's next tile
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(256) void k_ipm(const double2 *__restrict__ verts, int64_t nr1, int64_t cb0,
+                                             int64_t nrows, int64_t vb0, MapGeom g, double *__restrict__ map,
+                                             unsigned long long *__restrict__ counters, int32_t *__restrict__ nbig)
+{
+    __shared__ double acc[WIN * WIN];
+    ipm_tile<MIXED>(verts, nr1, cb0, nrows, vb0, g, map, counters, nbig, blockIdx.x, acc);
+}
+
+// every cell tile of every map of a fused batch in one persistent launch
+__global__ __launch_bounds__(256) void k_ipm_batch(const BatchMap *__restrict__ maps, int32_t nmaps,
+                                                   int64_t ntiles, int32_t *__restrict__ nbig)
+{
+    __shared__ double acc[WIN * WIN];
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int32_t m = batch_find(maps, nmaps, t, &BatchMap::ctile_lo);
+        const BatchMap &d = maps[m];
+        if (d.mixed)
+            ipm_tile<true>(d.verts, d.nr1, 0, d.nrows, 0, d.g, d.map, d.counters, nbig + d.cell_lo, t - d.ctile_lo,
+                           acc);
+        else
+            ipm_tile<false>(d.verts, d.nr1, 0, d.nrows, 0, d.g, d.map, d.counters, nbig + d.cell_lo, t - d.ctile_lo,
+                            acc);
+    }
 }
 
 // set-up of every large triangle, written at its slot of the exclusive scan
 // of the per-cell counts: integer local origin (inside or at the edge of the
 // map, so nearby pixel boundaries are exact), counter-clockwise local
 // vertices, edge slopes, the deposit scale, and the pixel rows it covers
-__global__ __launch_bounds__(256) void k_big_gather(int64_t ncells, const int64_t *__restrict__ boff,
-                                                    const double2 *__restrict__ verts, int64_t nr1, int64_t cb0,
-                                                    int64_t vb0, MapGeom g, BigPrep *__restrict__ prep,
-                                                    int64_t *__restrict__ rows)
+__device__ inline void gather_cell(int64_t t, int64_t slot, int64_t end, const double2 *__restrict__ verts,
+                                   int64_t nr1, int64_t cb0, int64_t vb0, const MapGeom &g,
+                                   BigPrep *__restrict__ prep, int64_t *__restrict__ rows,
+                                   int32_t *__restrict__ owner, int32_t map_index)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ncells) return;
-    int64_t slot = boff[t];
-    if (boff[t + 1] == slot) return;
     P2 v00, v10, v11, v01;
     load_cell(verts, nr1, cb0, vb0, t, v00, v10, v11, v01);
     const P2 tri[2][3] = {{v00, v10, v11}, {v00, v11, v01}};
-    const int64_t end = boff[t + 1];
     for (int k = 0; k < 2 && slot < end; ++k) {
         const P2 A = tri[k][0], B = tri[k][1], C = tri[k][2];
         if (classify(A, B, C, g).kind != 3) continue;
@@ -494,8 +491,33 @@ __global__ __launch_bounds__(256) void k_big_gather(int64_t ncells, const int64_
         prep[slot] = bp;
         const double j1 = fmin(floor(vmax), (double)(g.n2 - 1));
         rows[slot] = j1 >= ov ? (int64_t)(j1 - ov) + 1 : 0;
+        if (owner) owner[slot] = map_index;
         ++slot;
     }
+}
+
+__global__ __launch_bounds__(256) void k_big_gather(int64_t ncells, const int64_t *__restrict__ boff,
+                                                    const double2 *__restrict__ verts, int64_t nr1, int64_t cb0,
+                                                    int64_t vb0, MapGeom g, BigPrep *__restrict__ prep,
+                                                    int64_t *__restrict__ rows)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ncells || boff[t + 1] == boff[t]) return;
+    gather_cell(t, boff[t], boff[t + 1], verts, nr1, cb0, vb0, g, prep, rows, nullptr, 0);
+}
+
+// the batch's cells: boff is the scan over all maps' cells; owner records
+// each large triangle's map
+__global__ __launch_bounds__(256) void k_big_gather_batch(const BatchMap *__restrict__ maps, int32_t nmaps,
+                                                          int64_t ncells, const int64_t *__restrict__ boff,
+                                                          BigPrep *__restrict__ prep, int64_t *__restrict__ rows,
+                                                          int32_t *__restrict__ owner)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncells || boff[c + 1] == boff[c]) return;
+    const int32_t m = batch_find(maps, nmaps, c, &BatchMap::cell_lo);
+    const BatchMap &d = maps[m];
+    gather_cell(c - d.cell_lo, boff[c], boff[c + 1], d.verts, d.nr1, 0, 0, d.g, prep, rows, owner, m);
 }
 
 // The edges of a large triangle clipped to pixel row j (local coordinates),
@@ -709,26 +731,28 @@ __global__ __launch_bounds__(256) void k_band_scatter(int64_t nbig, const BigPre
 // (the covered interior costs nothing).  Columns left of the map fold into
 // column 0, those right of it are dropped.  The band owns its rows, so the
 // differences live in LDS and no device-wide atomic is needed.
-__global__ __launch_bounds__(BAND_THREADS) void k_band(const unsigned long long *__restrict__ band_off,
-                                                       const int32_t *__restrict__ list,
-                                                       const BigPrep *__restrict__ prep,
-                                                       const int64_t *__restrict__ rows, int bh, MapGeom g,
-                                                       double *__restrict__ map, unsigned long long *__restrict__ work)
+// consecutive bands on one XCD (workgroups go round-robin over the 8 XCDs),
+// so a triangle's set-up read by neighbouring bands stays in that L2
+__device__ inline int64_t xcd_band(int64_t blk, int64_t nb)
 {
-    extern __shared__ double bdiff[];      // bh x n1 differences
-    __shared__ unsigned long long wsum[2];
+    const int64_t per = nb / 8, rem = nb % 8, x = blk % 8, idx = blk / 8;
+    return x < rem ? x * (per + 1) + idx : rem * (per + 1) + (x - rem) * per + idx;
+}
+
+// band `band` of one map: its listed triangles are list[r0, r1); bdiff is
+// the workgroup's LDS (bh x n1 doubles), wsum two LDS counters
+__device__ inline void band_rows(int64_t band, int64_t r0, int64_t r1, const int32_t *__restrict__ list,
+                                 const BigPrep *__restrict__ prep, const int64_t *__restrict__ rows, int bh,
+                                 const MapGeom &g, double *__restrict__ map, unsigned long long *__restrict__ work,
+                                 double *bdiff, unsigned long long *wsum)
+{
     if (threadIdx.x < 2) wsum[threadIdx.x] = 0;
     unsigned long long my_rows = 0, my_pieces = 0;
     const int64_t n1 = g.n1;
-    // consecutive bands on one XCD (workgroups go round-robin over the 8 XCDs),
-    // so a triangle's set-up read by neighbouring bands stays in that L2
-    const int64_t nb = gridDim.x, per = nb / 8, rem = nb % 8, x = blockIdx.x % 8, idx = blockIdx.x / 8;
-    const int64_t band = x < rem ? x * (per + 1) + idx : rem * (per + 1) + (x - rem) * per + idx;
     const int64_t jb0 = band * bh;
     const int nrow = (int)min((int64_t)bh, (int64_t)g.n2 - jb0);
     for (int64_t t = threadIdx.x; t < (int64_t)bh * n1; t += blockDim.x) bdiff[t] = 0.0;
     __syncthreads();
-    const int64_t r0 = (int64_t)band_off[band], r1 = (int64_t)band_off[band + 1];
     const int64_t nitems = (r1 - r0) * bh;
     for (int64_t it = threadIdx.x; it < nitems; it += blockDim.x) {
         const int64_t k = list[r0 + it / bh];
@@ -799,6 +823,67 @@ __global__ __launch_bounds__(BAND_THREADS) void k_band(const unsigned long long 
         __syncthreads();
         if (threadIdx.x < 2 && wsum[threadIdx.x]) atomicAdd(work + threadIdx.x, wsum[threadIdx.x]);
     }
+    __syncthreads();   // the LDS may be reused for the workgroup's next band
+}
+
+__global__ __launch_bounds__(BAND_THREADS) void k_band(const unsigned long long *__restrict__ band_off,
+                                                       const int32_t *__restrict__ list,
+                                                       const BigPrep *__restrict__ prep,
+                                                       const int64_t *__restrict__ rows, int bh, MapGeom g,
+                                                       double *__restrict__ map, unsigned long long *__restrict__ work)
+{
+    extern __shared__ double bdiff[];      // bh x n1 differences
+    __shared__ unsigned long long wsum[2];
+    const int64_t band = xcd_band(blockIdx.x, gridDim.x);
+    band_rows(band, (int64_t)band_off[band], (int64_t)band_off[band + 1], list, prep, rows, bh, g, map, work, bdiff,
+              wsum);
+}
+
+// the bands of every map of a fused batch (band_off and list over the
+// batch's global band numbers)
+__global__ __launch_bounds__(BAND_THREADS) void k_band_batch(const BatchMap *__restrict__ maps, int32_t nmaps,
+                                                             const unsigned long long *__restrict__ band_off,
+                                                             const int32_t *__restrict__ list,
+                                                             const BigPrep *__restrict__ prep,
+                                                             const int64_t *__restrict__ rows)
+{
+    extern __shared__ double bdiff[];
+    __shared__ unsigned long long wsum[2];
+    const int64_t gb = xcd_band(blockIdx.x, gridDim.x);
+    const int32_t m = batch_find(maps, nmaps, gb, &BatchMap::band_lo);
+    const BatchMap &d = maps[m];
+    band_rows(gb - d.band_lo, (int64_t)band_off[gb], (int64_t)band_off[gb + 1], list, prep, rows, d.bh, d.g, d.map,
+              nullptr, bdiff, wsum);
+}
+
+// band binning of a batch's large triangles over global band numbers
+// (device-wide atomics: a batch has too many bands for LDS histograms)
+__global__ __launch_bounds__(256) void k_band_count_batch(const BatchMap *__restrict__ maps, int64_t nbig,
+                                                          const BigPrep *__restrict__ prep,
+                                                          const int64_t *__restrict__ rows,
+                                                          const int32_t *__restrict__ owner, int32_t *__restrict__ count)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nbig || rows[k] <= 0) return;
+    const BatchMap &d = maps[owner[k]];
+    int64_t b0, b1;
+    band_range(prep[k], rows[k], d.bh, b0, b1);
+    for (int64_t b = b0; b <= b1; ++b) atomicAdd(count + d.band_lo + b, 1);
+}
+
+__global__ __launch_bounds__(256) void k_band_scatter_batch(const BatchMap *__restrict__ maps, int64_t nbig,
+                                                            const BigPrep *__restrict__ prep,
+                                                            const int64_t *__restrict__ rows,
+                                                            const int32_t *__restrict__ owner,
+                                                            unsigned long long *__restrict__ cursor,
+                                                            int32_t *__restrict__ list)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nbig || rows[k] <= 0) return;
+    const BatchMap &d = maps[owner[k]];
+    int64_t b0, b1;
+    band_range(prep[k], rows[k], d.bh, b0, b1);
+    for (int64_t b = b0; b <= b1; ++b) list[atomicAdd(cursor + d.band_lo + b, 1ull)] = (int32_t)k;
 }
 
 // map[j][i] += sum_{k <= i} diff[j][k]; one wavefront per pixel row
@@ -826,13 +911,17 @@ __global__ __launch_bounds__(64) void k_diff_rows(MapGeom g, const double *__res
 }  // namespace
 
 void launch_ipm(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int64_t vb0, const MapGeom &g,
-                double *map, unsigned long long *counters, int32_t *nbig, hipStream_t st)
+                double *map, unsigned long long *counters, int32_t *nbig, bool mixed, hipStream_t st)
 {
     const int64_t ncol = nr1 - 1, nrows = cb1 - cb0;
     if (ncol <= 0 || nrows <= 0) return;
     const int64_t tiles = ((ncol + CT - 1) / CT) * ((nrows + CT - 1) / CT);
-    hipLaunchKernelGGL(k_ipm, dim3((unsigned)tiles), dim3(256), 0, st, verts, nr1, cb0, nrows, vb0, g, map, counters,
-                       nbig);
+    if (mixed)
+        hipLaunchKernelGGL(k_ipm<true>, dim3((unsigned)tiles), dim3(256), 0, st, verts, nr1, cb0, nrows, vb0, g, map,
+                           counters, nbig);
+    else
+        hipLaunchKernelGGL(k_ipm<false>, dim3((unsigned)tiles), dim3(256), 0, st, verts, nr1, cb0, nrows, vb0, g, map,
+                           counters, nbig);
 }
 
 void launch_big_gather(int64_t ncells, const int64_t *boff, const double2 *verts, int64_t nr1, int64_t cb0,
@@ -888,6 +977,51 @@ void launch_band(int32_t nbands, const unsigned long long *band_off, const int32
     if (nbands > 0)
         hipLaunchKernelGGL(k_band, dim3((unsigned)nbands), dim3(BAND_THREADS), shmem, st, band_off, list, prep, rows, bh,
                            g, map, work);
+}
+
+void launch_ipm_batch(const BatchMap *maps, int32_t nmaps, int64_t nctiles, int32_t *nbig, hipStream_t st)
+{
+    if (nctiles <= 0) return;
+    const int64_t grid = std::min<int64_t>(nctiles, 256 * 4);   // persistent: 4 workgroups per CU
+    hipLaunchKernelGGL(k_ipm_batch, dim3((unsigned)grid), dim3(256), 0, st, maps, nmaps, nctiles, nbig);
+}
+
+void launch_big_gather_batch(const BatchMap *maps, int32_t nmaps, int64_t ncells, const int64_t *boff, BigPrep *prep,
+                             int64_t *rows, int32_t *owner, hipStream_t st)
+{
+    if (ncells > 0)
+        hipLaunchKernelGGL(k_big_gather_batch, dim3((unsigned)((ncells + 255) / 256)), dim3(256), 0, st, maps, nmaps,
+                           ncells, boff, prep, rows, owner);
+}
+
+void launch_band_count_batch(const BatchMap *maps, int64_t nbig, const BigPrep *prep, const int64_t *rows,
+                             const int32_t *owner, int32_t *count, hipStream_t st)
+{
+    if (nbig > 0)
+        hipLaunchKernelGGL(k_band_count_batch, dim3((unsigned)((nbig + 255) / 256)), dim3(256), 0, st, maps, nbig,
+                           prep, rows, owner, count);
+}
+
+void launch_band_scatter_batch(const BatchMap *maps, int64_t nbig, const BigPrep *prep, const int64_t *rows,
+                               const int32_t *owner, unsigned long long *cursor, int32_t *list, hipStream_t st)
+{
+    if (nbig > 0)
+        hipLaunchKernelGGL(k_band_scatter_batch, dim3((unsigned)((nbig + 255) / 256)), dim3(256), 0, st, maps, nbig,
+                           prep, rows, owner, cursor, list);
+}
+
+void launch_band_batch(const BatchMap *maps, int32_t nmaps, int64_t nbands, const unsigned long long *band_off,
+                       const int32_t *list, const BigPrep *prep, const int64_t *rows, int64_t lds_doubles,
+                       hipStream_t st)
+{
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_band_batch),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)(BAND_LDS_DOUBLES * sizeof(double)));
+    MLM_HIP(attr);
+    if (lds_doubles > BAND_LDS_DOUBLES) fail(MLM_EINVAL, "band of %lld doubles exceeds LDS", (long long)lds_doubles);
+    if (nbands > 0)
+        hipLaunchKernelGGL(k_band_batch, dim3((unsigned)nbands), dim3(BAND_THREADS), (size_t)lds_doubles * sizeof(double),
+                           st, maps, nmaps, band_off, list, prep, rows);
 }
 
 void launch_diff_rows(const MapGeom &g, const double *diff, double *map, hipStream_t st)

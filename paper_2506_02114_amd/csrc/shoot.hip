@@ -7,6 +7,8 @@
 // cut into 8 x 8 tiles; one 64-lane wavefront shoots one tile.  All lanes of a
 // wavefront share the leaf, so the near stars and the Taylor coefficients are
 // wavefront-uniform and are read through the scalar cache into SGPRs.
+#include <algorithm>
+
 #include "dev.hpp"
 
 namespace mlm {
@@ -81,12 +83,6 @@ __global__ void k_tile_leaf(int64_t ntiles, int64_t nleaves, const int32_t *__re
     tile_leaf[t] = (int32_t)(upper_bound_i64<int32_t>(tile_off, nleaves, (int32_t)t) - 1);
 }
 
-struct ShootArgs {
-    double x0, y0, d1, d2;
-    int64_t nr1, vb0;
-    int p;
-    int pad;
-};
 
 __device__ inline void finish_vertex(const LensConst &lc, const MapGeom &g, double x, double y, double ax,
                                      double ay, double &w1, double &w2, double2 &uv)
@@ -104,16 +100,44 @@ __device__ inline void finish_vertex(const LensConst &lc, const MapGeom &g, doub
     uv = make_double2((w1 - g.ylo1) / g.pix1, (w2 - g.ylo2) / g.pix2);
 }
 
-// one wavefront (64 lanes) per 8 x 8 tile
-__global__ __launch_bounds__(64) void k_shoot(ShootArgs sa, LensConst lc, MapGeom g,
-                                              const int32_t *__restrict__ tile_leaf,
-                                              const int32_t *__restrict__ tile_off,
-                                              const LeafInfo *__restrict__ leaves,
-                                              const double4 *__restrict__ near, const double2 *__restrict__ deriv,
-                                              double2 *__restrict__ verts, double2 *__restrict__ w_out)
+// far-field and near-field deflection at offset (dx, dy) from a leaf's
+// centre, in arithmetic type R; the offsets from the leaf centre and from
+// each near star are formed in FP64 (a ray may pass very close to a star)
+template <class R>
+__device__ inline void leaf_alpha(double dx, double dy, const LeafInfo &li, const double4 *__restrict__ ns,
+                                  const typename Cx<R>::c2 *__restrict__ dv, int p, double &ax_out, double &ay_out)
 {
-    const int64_t t = blockIdx.x;
-    const int lane = threadIdx.x;
+    // near field: a_* += m (z - z_i) / |z - z_i|^2
+    R ax = 0, ay = 0;
+    for (int32_t s = 0; s < li.near_cnt; ++s) {
+        const double4 st = ns[s];
+        const R ex = (R)(dx - st.x), ey = (R)(dy - st.y);
+        const R f = qdiv((R)st.z, ex * ex + ey * ey);
+        ax += f * ex;
+        ay += f * ey;
+    }
+    // far field: conj( sum_{l<p} deriv_l zeta^l ), Horner
+    const R zr = (R)(dx * li.invL), zi = (R)(dy * li.invL);
+    R sr = dv[p - 1].x, si = dv[p - 1].y;
+    for (int l = p - 2; l >= 0; --l) {
+        const typename Cx<R>::c2 c = dv[l];
+        const R nr = sr * zr - si * zi + c.x;
+        const R ni = sr * zi + si * zr + c.y;
+        sr = nr;
+        si = ni;
+    }
+    ax_out = (double)ax + (double)sr;
+    ay_out = (double)ay - (double)si;
+}
+
+// shoot tile t of a map (one 64-lane wavefront per 8 x 8 tile)
+template <class R>
+__device__ inline void shoot_tile(const ShootArgs &sa, const LensConst &lc, const MapGeom &g,
+                                  const int32_t *__restrict__ tile_leaf, const int32_t *__restrict__ tile_off,
+                                  const LeafInfo *__restrict__ leaves, const double4 *__restrict__ near,
+                                  const typename Cx<R>::c2 *__restrict__ deriv, double2 *__restrict__ verts,
+                                  double2 *__restrict__ w_out, int64_t t, int lane)
+{
     const int32_t lf = tile_leaf[t];
     const LeafInfo li = leaves[lf];
     const int32_t local = (int32_t)t - tile_off[lf];
@@ -122,32 +146,8 @@ __global__ __launch_bounds__(64) void k_shoot(ShootArgs sa, LensConst lc, MapGeo
     const bool valid = ia < li.na && ib < li.nb;
     const int64_t a = li.a_lo + ia, b = li.b_lo + ib;
     const double x = grid_pos(sa.x0, sa.d1, a), y = grid_pos(sa.y0, sa.d2, b);
-    const double dx = x - li.cx, dy = y - li.cy;
-
-    // near field: a_* += m (z - z_i) / |z - z_i|^2
-    double ax = 0.0, ay = 0.0;
-    const double4 *ns = near + li.near_off;
-    for (int32_t s = 0; s < li.near_cnt; ++s) {
-        const double4 st = ns[s];
-        const double ex = dx - st.x, ey = dy - st.y;
-        const double f = st.z / (ex * ex + ey * ey);
-        ax += f * ex;
-        ay += f * ey;
-    }
-    // far field: conj( sum_{l<p} deriv_l zeta^l ), Horner
-    const double zr = dx * li.invL, zi = dy * li.invL;
-    const double2 *dv = deriv + (int64_t)lf * sa.p;
-    double sr = dv[sa.p - 1].x, si = dv[sa.p - 1].y;
-    for (int l = sa.p - 2; l >= 0; --l) {
-        const double2 c = dv[l];
-        const double nr = sr * zr - si * zi + c.x;
-        const double ni = sr * zi + si * zr + c.y;
-        sr = nr;
-        si = ni;
-    }
-    ax += sr;
-    ay -= si;
-
+    double ax, ay;
+    leaf_alpha<R>(x - li.cx, y - li.cy, li, near + li.near_off, deriv + (int64_t)lf * sa.p, sa.p, ax, ay);
     double w1, w2;
     double2 uv;
     finish_vertex(lc, g, x, y, ax, ay, w1, w2, uv);
@@ -155,6 +155,36 @@ __global__ __launch_bounds__(64) void k_shoot(ShootArgs sa, LensConst lc, MapGeo
         const int64_t o = (b - sa.vb0) * sa.nr1 + a;
         verts[o] = uv;
         if (w_out) w_out[o] = make_double2(w1, w2);
+    }
+}
+
+template <class R>
+__global__ __launch_bounds__(64) void k_shoot(ShootArgs sa, LensConst lc, MapGeom g,
+                                              const int32_t *__restrict__ tile_leaf,
+                                              const int32_t *__restrict__ tile_off,
+                                              const LeafInfo *__restrict__ leaves,
+                                              const double4 *__restrict__ near,
+                                              const typename Cx<R>::c2 *__restrict__ deriv,
+                                              double2 *__restrict__ verts, double2 *__restrict__ w_out)
+{
+    shoot_tile<R>(sa, lc, g, tile_leaf, tile_off, leaves, near, deriv, verts, w_out, blockIdx.x, threadIdx.x);
+}
+
+// the maps of a fused batch: every tile of every map in one persistent launch
+// (each wavefront walks the concatenated tile list with a grid-sized stride)
+__global__ __launch_bounds__(64) void k_shoot_batch(const BatchMap *__restrict__ maps, int32_t nmaps,
+                                                    int64_t ntiles)
+{
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int32_t m = batch_find(maps, nmaps, t, &BatchMap::tile_lo);
+        const BatchMap &d = maps[m];
+        const ShootArgs sa{d.x0, d.y0, d.d1, d.d2, d.nr1, 0, d.p, 0};
+        if (d.mixed)
+            shoot_tile<float>(sa, d.lc, d.g, d.tile_leaf, d.tile_off, d.leaves, d.near,
+                              static_cast<const float2 *>(d.deriv), d.verts, nullptr, t - d.tile_lo, threadIdx.x);
+        else
+            shoot_tile<double>(sa, d.lc, d.g, d.tile_leaf, d.tile_off, d.leaves, d.near,
+                               static_cast<const double2 *>(d.deriv), d.verts, nullptr, t - d.tile_lo, threadIdx.x);
     }
 }
 
@@ -198,11 +228,12 @@ struct LevelRanges {
 };
 
 // w at arbitrary points: leaf by descending the levels, then as k_shoot
+template <class R>
 __global__ void k_deflect_points(int64_t npts, const double2 *__restrict__ z, LevelRanges lr, int nlevels,
                                  double L0, int L0_exp, const uint64_t *__restrict__ code,
                                  const int32_t *__restrict__ leaf, const int32_t *__restrict__ node_leaf,
                                  const LeafInfo *__restrict__ leaves, const double4 *__restrict__ near,
-                                 const double2 *__restrict__ deriv, int p, LensConst lc,
+                                 const typename Cx<R>::c2 *__restrict__ deriv, int p, LensConst lc,
                                  double2 *__restrict__ w)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -225,27 +256,9 @@ __global__ void k_deflect_points(int64_t npts, const double2 *__restrict__ z, Le
         w[t] = make_double2(nan(""), nan(""));
         return;
     }
-    LeafInfo li = leaves[lf];
-    double dx = x - li.cx, dy = y - li.cy;
-    double ax = 0.0, ay = 0.0;
-    for (int32_t s = 0; s < li.near_cnt; ++s) {
-        double4 st = near[li.near_off + s];
-        double ex = dx - st.x, ey = dy - st.y;
-        double f = st.z / (ex * ex + ey * ey);
-        ax += f * ex;
-        ay += f * ey;
-    }
-    double zr = dx * li.invL, zi = dy * li.invL;
-    const double2 *dv = deriv + lf * p;
-    double sr = dv[p - 1].x, si = dv[p - 1].y;
-    for (int l = p - 2; l >= 0; --l) {
-        double nr = sr * zr - si * zi + dv[l].x;
-        double ni = sr * zi + si * zr + dv[l].y;
-        sr = nr;
-        si = ni;
-    }
-    ax += sr;
-    ay -= si;
+    const LeafInfo li = leaves[lf];
+    double ax, ay;
+    leaf_alpha<R>(x - li.cx, y - li.cy, li, near + li.near_off, deriv + lf * p, p, ax, ay);
     MapGeom g{0, 0, 1, 1, 1, 1, 0};
     double w1, w2;
     double2 uv;
@@ -310,9 +323,14 @@ void launch_shoot(mlm_lens *lens, const Tree &T, const Region &R, const LensCons
     if (ntiles <= 0) return;
     Workspace &ws = lens->ws;
     ShootArgs sa{R.x0, R.y0, R.d1, R.d2, R.nr1, vb0, T.p, 0};
-    hipLaunchKernelGGL(k_shoot, dim3((unsigned)ntiles), dim3(64), 0, st, sa, lc, g, ws.tile_leaf.as<int32_t>(),
-                       ws.tile_off.as<int32_t>(), T.leaves, T.near, T.deriv, verts,
-                       reinterpret_cast<double2 *>(w_out));
+    if (T.mixed)
+        hipLaunchKernelGGL(k_shoot<float>, dim3((unsigned)ntiles), dim3(64), 0, st, sa, lc, g,
+                           ws.tile_leaf.as<int32_t>(), ws.tile_off.as<int32_t>(), T.leaves, T.near, T.deriv_f, verts,
+                           reinterpret_cast<double2 *>(w_out));
+    else
+        hipLaunchKernelGGL(k_shoot<double>, dim3((unsigned)ntiles), dim3(64), 0, st, sa, lc, g,
+                           ws.tile_leaf.as<int32_t>(), ws.tile_off.as<int32_t>(), T.leaves, T.near, T.deriv, verts,
+                           reinterpret_cast<double2 *>(w_out));
 }
 
 void launch_shoot_direct(mlm_lens *lens, const Region &R, const LensConst &lc, const MapGeom &g, int64_t vb0,
@@ -323,6 +341,13 @@ void launch_shoot_direct(mlm_lens *lens, const Region &R, const LensConst &lc, c
     ShootArgs sa{R.x0, R.y0, R.d1, R.d2, R.nr1, vb0, 0, 0};
     hipLaunchKernelGGL(k_shoot_direct, dim3(nblocks(nv)), dim3(256), 0, st, sa, lc, g, nv, lens->d_x, lens->d_y,
                        lens->d_m, (int32_t)lens->n, verts, reinterpret_cast<double2 *>(w_out));
+}
+
+void launch_shoot_batch(const BatchMap *maps, int32_t nmaps, int64_t ntiles, hipStream_t st)
+{
+    if (ntiles <= 0) return;
+    const int64_t grid = std::min<int64_t>(ntiles, 256 * 32);   // 32 wavefronts per CU, persistent
+    hipLaunchKernelGGL(k_shoot_batch, dim3((unsigned)grid), dim3(64), 0, st, maps, nmaps, ntiles);
 }
 
 void launch_deflect_points(mlm_lens *lens, const Tree *T, const LensConst &lc, const double *z, int64_t n,
@@ -341,8 +366,13 @@ void launch_deflect_points(mlm_lens *lens, const Tree *T, const LensConst &lc, c
         lr.lo[l] = T->level_lo[l];
         lr.hi[l] = T->level_hi[l];
     }
-    hipLaunchKernelGGL(k_deflect_points, dim3(nblocks(n)), dim3(BLK), 0, st, n, z2, lr, T->nlevels, T->L0,
-                       T->L0_exp, T->code, T->leaf, T->node_leaf, T->leaves, T->near, T->deriv, T->p, lc, w2);
+    if (T->mixed)
+        hipLaunchKernelGGL(k_deflect_points<float>, dim3(nblocks(n)), dim3(BLK), 0, st, n, z2, lr, T->nlevels, T->L0,
+                           T->L0_exp, T->code, T->leaf, T->node_leaf, T->leaves, T->near, T->deriv_f, T->p, lc, w2);
+    else
+        hipLaunchKernelGGL(k_deflect_points<double>, dim3(nblocks(n)), dim3(BLK), 0, st, n, z2, lr, T->nlevels,
+                           T->L0, T->L0_exp, T->code, T->leaf, T->node_leaf, T->leaves, T->near, T->deriv, T->p, lc,
+                           w2);
 }
 
 }  // namespace mlm

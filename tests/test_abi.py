@@ -42,7 +42,8 @@ def test_every_declared_symbol_is_exported(mlm):
 def test_struct_layouts_match_header(mlm):
     structs = {"mlm_lens_params": mlm.LensParams, "mlm_lens_info": mlm.LensInfo,
                "mlm_map_request": mlm.MapRequest, "mlm_region": mlm.Region,
-               "mlm_map_stats": mlm.MapStats, "mlm_tree_info": mlm.TreeInfo}
+               "mlm_map_stats": mlm.MapStats, "mlm_tree_info": mlm.TreeInfo,
+               "mlm_batch_opts": mlm.BatchOpts, "mlm_batch_stats": mlm.BatchStats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mlmap.h"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')

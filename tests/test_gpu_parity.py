@@ -253,9 +253,9 @@ def test_edge_cases(mlm, orc):
     with pytest.raises(mlm.MLMError) as e:
         bad.map(hw1=1.0, hw2=1.0, n1=4, n2=4)
     assert e.value.status == mlm.MLM_EDEGENERATE
-    # mixed precision is not in this build
+    # mixed precision exists for the FMM only
     with pytest.raises(mlm.MLMError) as e:
-        g.map(hw1=1.0, hw2=1.0, n1=4, n2=4, precision="mixed")
+        g.map(hw1=1.0, hw2=1.0, n1=4, n2=4, precision="mixed", method="direct")
     assert e.value.status == mlm.MLM_ENOTSUP
     # bad row range
     with pytest.raises(mlm.MLMError) as e:
