@@ -28,7 +28,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6          # MI355X FP64 vector, dense
 # passes (FETCH_SIZE, WRITE_SIZE) scaled by the same counters' reading of a
 # plain 1 GiB device copy (--copy-check); valid only for the IPM source it was
 # taken with, identified by its SHA-256 prefix.
-BAND_TRAFFIC = None   # {"fetch_bytes": F, "write_bytes": W, "ipm_sha256": "..."}
+BAND_TRAFFIC = {"fetch_bytes": 3024394.44 * 1024 * 2.0, "write_bytes": 31265.63 * 1024 * 1.0,
+                "ipm_sha256": "973be82e0e233e28"}
 
 
 def file_sha(path: str) -> str:

@@ -179,6 +179,16 @@ __global__ void k_zero_u64n(unsigned long long *p, int64_t n)
     if (t < n) p[t] = 0;
 }
 
+// out[m] = boff[maps[m].cell_lo], out[nmaps] = boff[ncells]: where each map's
+// large triangles start in the gathered list
+__global__ void k_map_big_bounds(const BatchMap *maps, int32_t nmaps, int64_t ncells, const int64_t *boff,
+                                 int64_t *out)
+{
+    const int32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < nmaps) out[m] = boff[maps[m].cell_lo];
+    if (m == nmaps) out[m] = boff[ncells];
+}
+
 // --------------------------------------------------------------------------
 // batched maps
 // --------------------------------------------------------------------------
@@ -187,7 +197,7 @@ __global__ void k_zero_u64n(unsigned long long *p, int64_t n)
 // device of the calls; calls are serialised by `mu`)
 struct BatchWs {
     std::mutex mu;
-    DevBuf maps, verts, nbig, boff, prep, rows, owner, bcnt, boffs, bcur, blist, counters;
+    DevBuf maps, verts, nbig, boff, prep, rows, bcnt, boffs, bcur, blist, counters, bounds, slice_map, slice_lo;
 };
 
 BatchWs &batch_ws()
@@ -740,6 +750,7 @@ mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, i
             d.cell_lo = cl;
             d.band_lo = bl;
             d.bh = m.bh;
+            d.nbands = (int32_t)m.nbands;
             d.p = m.T.p;
             d.mixed = m.T.mixed ? 1 : 0;
             vo += m.nverts;
@@ -761,11 +772,36 @@ mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, i
         if (nb > 0) {
             BigPrep *prep = static_cast<BigPrep *>(B.prep.reserve((size_t)nb * sizeof(BigPrep)));
             int64_t *rows = static_cast<int64_t *>(B.rows.reserve((size_t)nb * sizeof(int64_t)));
-            int32_t *owner = static_cast<int32_t *>(B.owner.reserve((size_t)nb * sizeof(int32_t)));
-            launch_big_gather_batch(dmaps, nm, cl, boff, prep, rows, owner, st);
+            launch_big_gather_batch(dmaps, nm, cl, boff, prep, rows, nullptr, st);
+            // each map's slice of the gathered list, cut into workgroup-sized
+            // slices for the binning passes
+            int64_t *bnd = static_cast<int64_t *>(B.bounds.reserve((size_t)(nm + 1) * sizeof(int64_t)));
+            hipLaunchKernelGGL(k_map_big_bounds, dim3((unsigned)((nm + 1 + 255) / 256)), dim3(256), 0, st, dmaps, nm, cl,
+                               boff, bnd);
+            std::vector<int64_t> hb((size_t)nm + 1);
+            MLM_HIP(hipMemcpyAsync(hb.data(), bnd, hb.size() * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+            MLM_HIP(hipStreamSynchronize(st));
+            std::vector<int32_t> smap;
+            std::vector<int64_t> slo;
+            int32_t max_bands = 0;
+            for (int32_t k = 0; k < nm; ++k) {
+                hm[k].big_lo = hb[k];
+                hm[k].big_hi = hb[k + 1];
+                for (int64_t a = hb[k]; a < hb[k + 1]; a += 256) {
+                    smap.push_back(k);
+                    slo.push_back(a);
+                }
+                if (hb[k + 1] > hb[k]) max_bands = std::max(max_bands, hm[k].nbands);
+            }
+            const int64_t ns = (int64_t)smap.size();
+            int32_t *dsm = static_cast<int32_t *>(B.slice_map.reserve((size_t)ns * sizeof(int32_t)));
+            int64_t *dsl = static_cast<int64_t *>(B.slice_lo.reserve((size_t)ns * sizeof(int64_t)));
+            MLM_HIP(hipMemcpyAsync(dsm, smap.data(), (size_t)ns * sizeof(int32_t), hipMemcpyHostToDevice, st));
+            MLM_HIP(hipMemcpyAsync(dsl, slo.data(), (size_t)ns * sizeof(int64_t), hipMemcpyHostToDevice, st));
+            MLM_HIP(hipMemcpyAsync(dmaps, hm.data(), (size_t)nm * sizeof(BatchMap), hipMemcpyHostToDevice, st));
             int32_t *bcnt = static_cast<int32_t *>(B.bcnt.reserve((size_t)bl * sizeof(int32_t)));
             hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((bl + 255) / 256)), dim3(256), 0, st, bcnt, bl);
-            launch_band_count_batch(dmaps, nb, prep, rows, owner, bcnt, st);
+            launch_band_count_batch(dmaps, ns, dsm, dsl, max_bands, prep, rows, bcnt, st);
             unsigned long long *boffs =
                 static_cast<unsigned long long *>(B.boffs.reserve((size_t)(bl + 1) * sizeof(unsigned long long)));
             const int64_t nlist = scan_i32_to_u64(scan_lens, bcnt, boffs, bl, st);
@@ -773,7 +809,8 @@ mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, i
             unsigned long long *bcur =
                 static_cast<unsigned long long *>(B.bcur.reserve((size_t)bl * sizeof(unsigned long long)));
             MLM_HIP(hipMemcpyAsync(bcur, boffs, (size_t)bl * sizeof(unsigned long long), hipMemcpyDeviceToDevice, st));
-            launch_band_scatter_batch(dmaps, nb, prep, rows, owner, bcur, blist, st);
+            launch_band_scatter_batch(dmaps, ns, dsm, dsl, max_bands, prep, rows, bcur, blist, st);
+            MLM_HIP(hipStreamSynchronize(st));   // the host slice tables are released at the end of this block
             launch_band_batch(dmaps, nm, bl, boffs, blist, prep, rows, max_band_lds, st);
         }
         const int ec = tm.mark();

@@ -130,7 +130,8 @@ struct BatchMap {
     double *map;                      // n2 x n1, accumulated into
     unsigned long long *counters;     // [0] skipped triangles of this map
     int64_t tile_lo, ctile_lo, cell_lo, band_lo;   // first shoot tile, cell tile, cell, band
-    int32_t bh, p, mixed, pad;
+    int64_t big_lo, big_hi;           // this map's large triangles in the gathered list
+    int32_t bh, nbands, p, mixed;
 };
 
 // index of the map whose range [lo, next lo) holds item x (maps with empty
@@ -247,10 +248,12 @@ void launch_band(int32_t nbands, const unsigned long long *band_off, const int32
 void launch_ipm_batch(const BatchMap *maps, int32_t nmaps, int64_t nctiles, int32_t *nbig, hipStream_t st);
 void launch_big_gather_batch(const BatchMap *maps, int32_t nmaps, int64_t ncells, const int64_t *boff, BigPrep *prep,
                              int64_t *rows, int32_t *owner, hipStream_t st);
-void launch_band_count_batch(const BatchMap *maps, int64_t nbig, const BigPrep *prep, const int64_t *rows,
-                             const int32_t *owner, int32_t *count, hipStream_t st);
-void launch_band_scatter_batch(const BatchMap *maps, int64_t nbig, const BigPrep *prep, const int64_t *rows,
-                               const int32_t *owner, unsigned long long *cursor, int32_t *list, hipStream_t st);
+void launch_band_count_batch(const BatchMap *maps, int64_t nslices, const int32_t *slice_map, const int64_t *slice_lo,
+                             int32_t max_bands, const BigPrep *prep, const int64_t *rows, int32_t *count,
+                             hipStream_t st);
+void launch_band_scatter_batch(const BatchMap *maps, int64_t nslices, const int32_t *slice_map,
+                               const int64_t *slice_lo, int32_t max_bands, const BigPrep *prep, const int64_t *rows,
+                               unsigned long long *cursor, int32_t *list, hipStream_t st);
 void launch_band_batch(const BatchMap *maps, int32_t nmaps, int64_t nbands, const unsigned long long *band_off,
                        const int32_t *list, const BigPrep *prep, const int64_t *rows, int64_t lds_doubles,
                        hipStream_t st);

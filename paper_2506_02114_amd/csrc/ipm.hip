@@ -433,12 +433,14 @@ __global__ __launch_bounds__(256) void k_ipm(const double2 *__restrict__ verts, 
     ipm_tile<MIXED>(verts, nr1, cb0, nrows, vb0, g, map, counters, nbig, blockIdx.x, acc);
 }
 
-// every cell tile of every map of a fused batch in one persistent launch
+// every cell tile of every map of a fused batch in one launch (one
+// workgroup per tile of the concatenated tile list)
 __global__ __launch_bounds__(256) void k_ipm_batch(const BatchMap *__restrict__ maps, int32_t nmaps,
                                                    int64_t ntiles, int32_t *__restrict__ nbig)
 {
     __shared__ double acc[WIN * WIN];
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    {
+        const int64_t t = blockIdx.x;
         const int32_t m = batch_find(maps, nmaps, t, &BatchMap::ctile_lo);
         const BatchMap &d = maps[m];
         if (d.mixed)
@@ -856,34 +858,65 @@ __global__ __launch_bounds__(BAND_THREADS) void k_band_batch(const BatchMap *__r
               nullptr, bdiff, wsum);
 }
 
-// band binning of a batch's large triangles over global band numbers
-// (device-wide atomics: a batch has too many bands for LDS histograms)
-__global__ __launch_bounds__(256) void k_band_count_batch(const BatchMap *__restrict__ maps, int64_t nbig,
+// band binning of a batch's large triangles.  The triangles of map m are
+// the contiguous range [big_lo, big_hi) of its BatchMap (they were gathered
+// in cell order); slice s of the launch is workgroup-sized and lies inside
+// one map (`slice_map`, `slice_lo`), so a workgroup histograms that map's
+// bands in LDS and issues one device-wide atomic per band it touches.
+__global__ __launch_bounds__(256) void k_band_count_batch(const BatchMap *__restrict__ maps,
+                                                          const int32_t *__restrict__ slice_map,
+                                                          const int64_t *__restrict__ slice_lo,
                                                           const BigPrep *__restrict__ prep,
                                                           const int64_t *__restrict__ rows,
-                                                          const int32_t *__restrict__ owner, int32_t *__restrict__ count)
+                                                          int32_t *__restrict__ count)
 {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nbig || rows[k] <= 0) return;
-    const BatchMap &d = maps[owner[k]];
-    int64_t b0, b1;
-    band_range(prep[k], rows[k], d.bh, b0, b1);
-    for (int64_t b = b0; b <= b1; ++b) atomicAdd(count + d.band_lo + b, 1);
+    extern __shared__ int32_t hist[];
+    const BatchMap &d = maps[slice_map[blockIdx.x]];
+    const int32_t nb = (int32_t)d.nbands;
+    for (int32_t b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0;
+    __syncthreads();
+    const int64_t k = slice_lo[blockIdx.x] + threadIdx.x;
+    if (k < d.big_hi && rows[k] > 0) {
+        int64_t b0, b1;
+        band_range(prep[k], rows[k], d.bh, b0, b1);
+        for (int64_t b = b0; b <= b1; ++b) atomicAdd(&hist[b], 1);
+    }
+    __syncthreads();
+    for (int32_t b = threadIdx.x; b < nb; b += blockDim.x)
+        if (hist[b]) atomicAdd(count + d.band_lo + b, hist[b]);
 }
 
-__global__ __launch_bounds__(256) void k_band_scatter_batch(const BatchMap *__restrict__ maps, int64_t nbig,
+__global__ __launch_bounds__(256) void k_band_scatter_batch(const BatchMap *__restrict__ maps,
+                                                            const int32_t *__restrict__ slice_map,
+                                                            const int64_t *__restrict__ slice_lo,
                                                             const BigPrep *__restrict__ prep,
                                                             const int64_t *__restrict__ rows,
-                                                            const int32_t *__restrict__ owner,
                                                             unsigned long long *__restrict__ cursor,
                                                             int32_t *__restrict__ list)
 {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nbig || rows[k] <= 0) return;
-    const BatchMap &d = maps[owner[k]];
-    int64_t b0, b1;
-    band_range(prep[k], rows[k], d.bh, b0, b1);
-    for (int64_t b = b0; b <= b1; ++b) list[atomicAdd(cursor + d.band_lo + b, 1ull)] = (int32_t)k;
+    extern __shared__ int32_t sh[];
+    const BatchMap &d = maps[slice_map[blockIdx.x]];
+    const int32_t nb = (int32_t)d.nbands;
+    int32_t *hist = sh;
+    unsigned long long *base = reinterpret_cast<unsigned long long *>(sh + ((nb + 1) & ~1));
+    for (int32_t b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0;
+    __syncthreads();
+    const int64_t k = slice_lo[blockIdx.x] + threadIdx.x;
+    int64_t b0 = 0, b1 = -1;
+    if (k < d.big_hi && rows[k] > 0) {
+        band_range(prep[k], rows[k], d.bh, b0, b1);
+        for (int64_t b = b0; b <= b1; ++b) atomicAdd(&hist[b], 1);
+    }
+    __syncthreads();
+    for (int32_t b = threadIdx.x; b < nb; b += blockDim.x) {
+        if (hist[b]) base[b] = atomicAdd(cursor + d.band_lo + b, (unsigned long long)hist[b]);
+        hist[b] = 0;
+    }
+    __syncthreads();
+    for (int64_t b = b0; b <= b1; ++b) {
+        const int32_t o = atomicAdd(&hist[b], 1);
+        list[base[b] + o] = (int32_t)k;
+    }
 }
 
 // map[j][i] += sum_{k <= i} diff[j][k]; one wavefront per pixel row
@@ -982,8 +1015,8 @@ void launch_band(int32_t nbands, const unsigned long long *band_off, const int32
 void launch_ipm_batch(const BatchMap *maps, int32_t nmaps, int64_t nctiles, int32_t *nbig, hipStream_t st)
 {
     if (nctiles <= 0) return;
-    const int64_t grid = std::min<int64_t>(nctiles, 256 * 4);   // persistent: 4 workgroups per CU
-    hipLaunchKernelGGL(k_ipm_batch, dim3((unsigned)grid), dim3(256), 0, st, maps, nmaps, nctiles, nbig);
+    if (nctiles > (int64_t)UINT32_MAX) fail(MLM_ERANGE, "too many cell tiles in one batch chunk");
+    hipLaunchKernelGGL(k_ipm_batch, dim3((unsigned)nctiles), dim3(256), 0, st, maps, nmaps, nctiles, nbig);
 }
 
 void launch_big_gather_batch(const BatchMap *maps, int32_t nmaps, int64_t ncells, const int64_t *boff, BigPrep *prep,
@@ -994,20 +1027,23 @@ void launch_big_gather_batch(const BatchMap *maps, int32_t nmaps, int64_t ncells
                            ncells, boff, prep, rows, owner);
 }
 
-void launch_band_count_batch(const BatchMap *maps, int64_t nbig, const BigPrep *prep, const int64_t *rows,
-                             const int32_t *owner, int32_t *count, hipStream_t st)
+void launch_band_count_batch(const BatchMap *maps, int64_t nslices, const int32_t *slice_map, const int64_t *slice_lo,
+                             int32_t max_bands, const BigPrep *prep, const int64_t *rows, int32_t *count,
+                             hipStream_t st)
 {
-    if (nbig > 0)
-        hipLaunchKernelGGL(k_band_count_batch, dim3((unsigned)((nbig + 255) / 256)), dim3(256), 0, st, maps, nbig,
-                           prep, rows, owner, count);
+    if (nslices > 0)
+        hipLaunchKernelGGL(k_band_count_batch, dim3((unsigned)nslices), dim3(256), (size_t)max_bands * sizeof(int32_t),
+                           st, maps, slice_map, slice_lo, prep, rows, count);
 }
 
-void launch_band_scatter_batch(const BatchMap *maps, int64_t nbig, const BigPrep *prep, const int64_t *rows,
-                               const int32_t *owner, unsigned long long *cursor, int32_t *list, hipStream_t st)
+void launch_band_scatter_batch(const BatchMap *maps, int64_t nslices, const int32_t *slice_map,
+                               const int64_t *slice_lo, int32_t max_bands, const BigPrep *prep, const int64_t *rows,
+                               unsigned long long *cursor, int32_t *list, hipStream_t st)
 {
-    if (nbig > 0)
-        hipLaunchKernelGGL(k_band_scatter_batch, dim3((unsigned)((nbig + 255) / 256)), dim3(256), 0, st, maps, nbig,
-                           prep, rows, owner, cursor, list);
+    const size_t shmem = ((max_bands + 1) & ~1) * sizeof(int32_t) + (size_t)max_bands * sizeof(unsigned long long);
+    if (nslices > 0)
+        hipLaunchKernelGGL(k_band_scatter_batch, dim3((unsigned)nslices), dim3(256), shmem, st, maps, slice_map,
+                           slice_lo, prep, rows, cursor, list);
 }
 
 void launch_band_batch(const BatchMap *maps, int32_t nmaps, int64_t nbands, const unsigned long long *band_off,

@@ -170,12 +170,13 @@ __global__ __launch_bounds__(64) void k_shoot(ShootArgs sa, LensConst lc, MapGeo
     shoot_tile<R>(sa, lc, g, tile_leaf, tile_off, leaves, near, deriv, verts, w_out, blockIdx.x, threadIdx.x);
 }
 
-// the maps of a fused batch: every tile of every map in one persistent launch
-// (each wavefront walks the concatenated tile list with a grid-sized stride)
+// the maps of a fused batch: every tile of every map in one launch (one
+// wavefront per tile of the concatenated tile list)
 __global__ __launch_bounds__(64) void k_shoot_batch(const BatchMap *__restrict__ maps, int32_t nmaps,
                                                     int64_t ntiles)
 {
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    {
+        const int64_t t = blockIdx.x;
         const int32_t m = batch_find(maps, nmaps, t, &BatchMap::tile_lo);
         const BatchMap &d = maps[m];
         const ShootArgs sa{d.x0, d.y0, d.d1, d.d2, d.nr1, 0, d.p, 0};
@@ -346,8 +347,8 @@ void launch_shoot_direct(mlm_lens *lens, const Region &R, const LensConst &lc, c
 void launch_shoot_batch(const BatchMap *maps, int32_t nmaps, int64_t ntiles, hipStream_t st)
 {
     if (ntiles <= 0) return;
-    const int64_t grid = std::min<int64_t>(ntiles, 256 * 32);   // 32 wavefronts per CU, persistent
-    hipLaunchKernelGGL(k_shoot_batch, dim3((unsigned)grid), dim3(64), 0, st, maps, nmaps, ntiles);
+    if (ntiles > (int64_t)UINT32_MAX) fail(MLM_ERANGE, "too many ray tiles in one batch chunk");
+    hipLaunchKernelGGL(k_shoot_batch, dim3((unsigned)ntiles), dim3(64), 0, st, maps, nmaps, ntiles);
 }
 
 void launch_deflect_points(mlm_lens *lens, const Tree *T, const LensConst &lc, const double *z, int64_t n,

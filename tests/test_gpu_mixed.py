@@ -12,14 +12,15 @@ round-off u = 2^-24 and the structure of each sum:
     field's magnitude (p <= 31), then a degree-p Horner and <= 60 near-star
     terms of relative error ~3u with offsets exact to FP64: about 5e-5, so
     1e-4;
-  * maps: the deflection error moves mapped vertices by
-    dw <= 1e-4 max(|a|, 1); a pixel's magnification then moves by at most
-    ~4 dw / pix relative (four pixel sides crossed by displaced edges), which
-    for |a| <~ 10 and pixels >= 0.025 gives the per-pixel bound 1e-2, with
-    p99.9 below 1e-3 and the median (vertices moved by the median deflection
-    error) below 1e-5; the FP32 pieces of well-conditioned triangles add only
-    ~256 u.  These are the errors the single-precision mode is stated with;
-    they are not the FP64 mode's 1e-4.
+  * maps: FP32 translation chains leave the Taylor coefficients with an
+    absolute error of ~64 u times the field they carry, whose size is that
+    of the star disc's field across the region, |a|max ~ kappa_* |z|max + 1;
+    mapped vertices move by dw ~ 64 u |a|max, and a pixel's magnification by
+    at most ~4 dw / pix relative (four pixel sides crossed by displaced
+    edges).  That is the per-pixel bound `_map_bound`; the median pixel, fed
+    by vertices moved by the median error, stays 100 times below it.  These
+    are the errors the single-precision mode is stated with (the paper finds
+    it degrades, sec. 5); they are not the FP64 mode's 1e-4.
 Measured values go to gpurun_out/parity_report_mixed.json.
 """
 import json
@@ -61,6 +62,14 @@ def _pair(mlm, orc, ks, kss, g, sf):
 def _alpha_from_w(ol, orc, zx, zy, wx, wy):
     mx, my = orc.lens_equation(ol, zx, zy, np.zeros_like(zx), np.zeros_like(zy))
     return mx - wx, my - wy
+
+
+U32 = 2.0 ** -24
+
+
+def _map_bound(kappa_star, R):
+    zmax = np.hypot(R.dX1 + abs(R.X1), R.dX2 + abs(R.X2))
+    return 4.0 * 64.0 * U32 * (kappa_star * zmax + 1.0) / min(R.pix1, R.pix2)
 
 
 def test_mixed_coefficients(mlm, orc):
@@ -120,13 +129,14 @@ def test_mixed_map_small(mlm, orc):
     ref = orc.magnification_map(ol, spec, method="fmm", p=20)
     pos = ref.mu > 0
     rel = np.abs(mu[pos] - ref.mu[pos]) / ref.mu[pos]
+    bound = _map_bound(0.3, ref.region)
     _report("map_plain_small", max=float(rel.max()), p999=float(np.quantile(rel, 0.999)),
-            median=float(np.median(rel)))
+            median=float(np.median(rel)), bound=bound)
     assert np.all(np.abs(mu[~pos]) < 1e-12)
-    assert rel.max() < 1e-2 and np.quantile(rel, 0.999) < 1e-3 and np.median(rel) < 1e-5
+    assert rel.max() < bound and np.median(rel) < bound / 100
 
 
-def test_mixed_map_full_size(mlm):
+def test_mixed_map_full_size(mlm, orc):
     """The 1e5-star workload's whole map in mixed precision against the
     oracle's whole FP64 map (stored pixels), and its speed beside FP64."""
     import torch
@@ -155,7 +165,9 @@ def test_mixed_map_full_size(mlm):
     _report("map_plain_large", vs_oracle_max=float(rel.max()), vs_oracle_p999=float(np.quantile(rel, 0.999)),
             vs_oracle_median=float(np.median(rel)), vs_fp64_whole_map_max=float(rel64.max()),
             vs_fp64_whole_map_median=float(np.median(rel64)), ms_fp64=t["fp64"], ms_mixed=t["mixed"])
-    assert rel.max() < 1e-2 and np.quantile(rel, 0.999) < 1e-3 and np.median(rel) < 1e-5
+    R = orc.region(orc.Lens(0.45, 0.0, 0.45, sf.x, sf.y, sf.m), **spec)
+    bound = _map_bound(0.45, R)
+    assert rel.max() < bound and np.median(rel) < bound / 100
 
 
 def test_mixed_high_magnification_map(mlm, orc):
