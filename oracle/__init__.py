@@ -102,6 +102,10 @@ def lib():
         L.orc_tri_pixel_area.argtypes = [_dp, _dp, C.c_long, C.c_long]
         L.orc_tri_pixel_area.restype = C.c_double
         L.orc_ipm_rows.argtypes = [C.POINTER(Region), C.c_long, C.c_long, _dp, _dp, _dp, _dp]
+        L.orc_cell_features.argtypes = [_dp, _dp, _dp]
+        L.orc_refine_cells.argtypes = [C.POINTER(Region), C.c_double, C.c_double, C.c_double, C.c_int, C.c_double,
+                                       C.c_long, _dp, _dp, _dp, C.c_void_p, C.c_long, _lp, _lp, C.c_double,
+                                       C.c_int, C.c_int, C.POINTER(C.c_ubyte), _dp, _lp]
         L.orc_normalise.argtypes = [C.POINTER(Region), _dp, _dp]
         L.orc_shoot_rows.argtypes = [C.POINTER(Region), C.c_double, C.c_double, C.c_double, C.c_int,
                                      C.c_double, C.c_long, _dp, _dp, _dp, C.c_void_p, C.c_long,
@@ -383,3 +387,93 @@ def magnification_map(lens: Lens, spec: dict, method: str = "fmm", p: int = 0,
     lib().orc_normalise(C.byref(R), _d(dep), _d(mu))
     return MapResult(mu.reshape(R.n2, R.n1), R, stats[0], stats[1], stats[2], int(stats[3]),
                      int(stats[4]), (row_lo, row_hi))
+
+
+# ---------------------------------------------------------------------------
+# Cell refinement and its learned stand-in.  The paper apportions every cell
+# as two triangles and does no subdivision (sec. 3.2); the refinement below is
+# the plain test the learned variant is trained on and judged against:
+#   refine a (sub)cell if its mapped ears disagree in orientation (a critical
+#   curve crosses it) or if splitting it 2 x 2 changes its in-map deposits
+#   by more than TAU times its image area (L1 over pixels); a refined cell is
+#   replaced by its four children, tested again down to MAX_DEPTH levels;
+#   cells whose triangles span more than WINDOW pixels are left alone.
+# ---------------------------------------------------------------------------
+REFINE_TAU = 1e-3
+REFINE_MAX_DEPTH = 3
+REFINE_WINDOW = 8
+
+
+def cell_features(u4, v4) -> np.ndarray:
+    """12 features of a mapped cell (corners in the order 00, 10, 11, 01)."""
+    f = np.empty(12)
+    lib().orc_cell_features(_d(_f64(u4)), _d(_f64(v4)), _d(f))
+    return f
+
+
+def refine_cells(R: Region, lens: Lens, cells_a, cells_b, fmm: Optional[FMM] = None, tau: float = REFINE_TAU,
+                 max_depth: int = REFINE_MAX_DEPTH, window: int = REFINE_WINDOW):
+    """Plain refinement of ray-grid cells (a, b): per-cell labels (1: the
+    cell itself is refined), the magnification change of the map (refined
+    minus plain, n2 x n1) and {tested, refined, too large} counts."""
+    ca = np.ascontiguousarray(cells_a, dtype=np.int64)
+    cb = np.ascontiguousarray(cells_b, dtype=np.int64)
+    labels = np.zeros(ca.size, np.uint8)
+    dep = np.zeros(R.n1 * R.n2)
+    st = np.zeros(3, np.int64)
+    lib().orc_refine_cells(C.byref(R), lens.kappa_star, lens.kappa_smooth, lens.gamma, int(lens.sheet),
+                           lens.r_star, lens.n, _d(lens.x), _d(lens.y), _d(lens.m),
+                           fmm.handle if fmm is not None else None, ca.size, ca.ctypes.data_as(_lp),
+                           cb.ctypes.data_as(_lp), tau, max_depth, window,
+                           labels.ctypes.data_as(C.POINTER(C.c_ubyte)), _d(dep), st.ctypes.data_as(_lp))
+    dmu = np.empty_like(dep)
+    lib().orc_normalise(C.byref(R), _d(dep), _d(dmu))
+    return labels, dmu.reshape(R.n2, R.n1), st
+
+
+# The refinement network: 12 -> 64 -> 64 -> 1, ReLU between layers, a logit
+# out; trained with the weighted binary cross-entropy
+#   loss = mean_i [ w+ y_i softplus(-z_i) + (1 - y_i) softplus(z_i) ].
+MLP_SIZES = (12, 64, 64, 1)
+
+
+def mlp_init(seed: int = 0) -> dict:
+    """He-normal weights, zero biases (a fixed, seeded start)."""
+    rng = np.random.default_rng(seed)
+    return dict(W1=rng.normal(0, np.sqrt(2 / 12), (12, 64)), b1=np.zeros(64),
+                W2=rng.normal(0, np.sqrt(2 / 64), (64, 64)), b2=np.zeros(64),
+                W3=rng.normal(0, np.sqrt(2 / 64), 64), b3=np.zeros(1))
+
+
+def mlp_forward(P: dict, X: np.ndarray):
+    """Logits of samples X (n x 12), with the hidden activations."""
+    A1 = X @ P["W1"] + P["b1"]
+    H1 = np.maximum(A1, 0.0)
+    A2 = H1 @ P["W2"] + P["b2"]
+    H2 = np.maximum(A2, 0.0)
+    z = H2 @ P["W3"] + P["b3"][0]
+    return z, (X, A1, H1, A2, H2)
+
+
+def _softplus(x):
+    return np.logaddexp(0.0, x)
+
+
+def mlp_loss_grad(P: dict, X: np.ndarray, y: np.ndarray, pos_weight: float = 1.0):
+    """Loss and its gradient with respect to every parameter (FP64)."""
+    z, (X, A1, H1, A2, H2) = mlp_forward(P, X)
+    y = y.astype(np.float64)
+    n = X.shape[0]
+    loss = np.mean(pos_weight * y * _softplus(-z) + (1 - y) * _softplus(z))
+    sig = 1.0 / (1.0 + np.exp(-z))
+    dz = (pos_weight * y * (sig - 1.0) + (1 - y) * sig) / n
+    G = {}
+    G["W3"] = H2.T @ dz
+    G["b3"] = np.array([dz.sum()])
+    dA2 = np.outer(dz, P["W3"]) * (A2 > 0)
+    G["W2"] = H1.T @ dA2
+    G["b2"] = dA2.sum(axis=0)
+    dA1 = (dA2 @ P["W2"].T) * (A1 > 0)
+    G["W1"] = X.T @ dA1
+    G["b1"] = dA1.sum(axis=0)
+    return loss, G

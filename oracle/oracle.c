@@ -1019,3 +1019,201 @@ void orc_shoot_rows(const orc_region *R, double kappa_star, double kappa_smooth,
     shoot_ctx c = {R, &L, n, sx, sy, sm, F, row_lo, wx, wy};
     parallel_for(row_hi - row_lo, nthreads, shoot_rows, &c);
 }
+
+/* ------------------------------------------------------------------------ */
+/* cell refinement (not in the paper, which does no subdivision, sec. 3.2):  */
+/* the plain test the learned variant is judged against                     */
+/* ------------------------------------------------------------------------ */
+
+static double sgn(double x) { return (x > 0.0) - (x < 0.0); }
+
+/* twice the signed area of (a, b, c) */
+static double area2(double ua, double va, double ub, double vb, double uc, double vc)
+{
+    return (ub - ua) * (vc - va) - (uc - ua) * (vb - va);
+}
+
+/* Features of a mapped cell: corners (u, v) in pixel units in the order
+   00, 10, 11, 01; f[0..7] = sign(d) log(1 + |d|) of each corner's offset
+   from the mean of the four, f[8..11] = signs of the mapped ears at the
+   corners (00: (00, 10, 01); 10: (10, 11, 00); 11: (11, 01, 10);
+   01: (01, 00, 11)), which all agree unless the cell is folded. */
+void orc_cell_features(const double *u4, const double *v4, double *f)
+{
+    double cu = 0.25 * (u4[0] + u4[1] + u4[2] + u4[3]);
+    double cv = 0.25 * (v4[0] + v4[1] + v4[2] + v4[3]);
+    for (int k = 0; k < 4; ++k) {
+        double du = u4[k] - cu, dv = v4[k] - cv;
+        f[2 * k] = sgn(du) * log1p(fabs(du));
+        f[2 * k + 1] = sgn(dv) * log1p(fabs(dv));
+    }
+    for (int k = 0; k < 4; ++k) {
+        int p = (k + 3) % 4, q = (k + 1) % 4;   /* neighbours in the cycle 00, 10, 11, 01 */
+        f[8 + k] = sgn(area2(u4[k], v4[k], u4[q], v4[q], u4[p], v4[p]));
+    }
+}
+
+typedef struct {
+    const orc_region *R;
+    orc_lens L;
+    long n;
+    const double *sx, *sy, *sm;
+    const void *F;
+    double tau;
+    int max_depth, window;
+    double *dmap;              /* image-area deposits of (refined - plain) */
+    long n_tested, n_refined, n_large;
+} refine_ctx;
+
+/* source position of image point (A d1 + x0, B d2 + y0), in pixel units */
+static void refine_shoot(const refine_ctx *c, double A, double B, double *u, double *v)
+{
+    const orc_region *R = c->R;
+    double x = R->x0 + A * R->d1, y = R->y0 + B * R->d2;
+    double ax, ay;
+    if (c->F) orc_fmm_alpha(c->F, 1, &x, &y, &ax, &ay, NULL, 1);
+    else orc_alpha_direct(c->n, c->sx, c->sy, c->sm, 1, &x, &y, &ax, &ay, 1);
+    double wx, wy;
+    lens_equation(&c->L, x, y, ax, ay, &wx, &wy);
+    *u = (wx - (R->y1c - R->hw1)) / R->pix1;
+    *v = (wy - (R->y2c - R->hw2)) / R->pix2;
+}
+
+/* image-area deposit of triangle (u, v) of image area AT into pixel (i, j) */
+static double tri_dep(double AT, const double *u, const double *v, long i, long j)
+{
+    double S = 0.5 * area2(u[0], v[0], u[1], v[1], u[2], v[2]);
+    if (!(S != 0.0) || !isfinite(S)) return 0.0;
+    double a = orc_tri_pixel_area(u, v, i, j);
+    return a == 0.0 ? 0.0 : AT * (a / S);
+}
+
+/* a (sub)cell's two triangles, corners in the order 00, 10, 11, 01 */
+static void cell_tris(const double *u4, const double *v4, double tu[2][3], double tv[2][3])
+{
+    const int t[2][3] = {{0, 1, 2}, {0, 2, 3}};
+    for (int k = 0; k < 2; ++k)
+        for (int m = 0; m < 3; ++m) { tu[k][m] = u4[t[k][m]]; tv[k][m] = v4[t[k][m]]; }
+}
+
+static void add_cell(refine_ctx *c, double AT, const double *u4, const double *v4, double sign)
+{
+    double tu[2][3], tv[2][3];
+    cell_tris(u4, v4, tu, tv);
+    const orc_region *R = c->R;
+    for (int k = 0; k < 2; ++k) {
+        int ok = 1;
+        for (int m = 0; m < 3; ++m) ok &= isfinite(tu[k][m]) && isfinite(tv[k][m]);
+        if (!ok) continue;
+        double umin = fmin(tu[k][0], fmin(tu[k][1], tu[k][2])), umax = fmax(tu[k][0], fmax(tu[k][1], tu[k][2]));
+        double vmin = fmin(tv[k][0], fmin(tv[k][1], tv[k][2])), vmax = fmax(tv[k][0], fmax(tv[k][1], tv[k][2]));
+        long i0 = (long)floor(umin), i1 = (long)floor(umax), j0 = (long)floor(vmin), j1 = (long)floor(vmax);
+        if (i0 < 0) i0 = 0;
+        if (j0 < 0) j0 = 0;
+        if (i1 > R->n1 - 1) i1 = R->n1 - 1;
+        if (j1 > R->n2 - 1) j1 = R->n2 - 1;
+        for (long j = j0; j <= j1; ++j)
+            for (long i = i0; i <= i1; ++i) c->dmap[j * R->n1 + i] += sign * tri_dep(AT, tu[k], tv[k], i, j);
+    }
+}
+
+/* The test of one (sub)cell at depth d (image corners A0 + {0, h} x
+   B0 + {0, h} in grid units, source corners u4, v4):  refine if the mapped
+   ears disagree, or if splitting it 2 x 2 changes its in-map deposits by
+   more than tau times its image area (L1 over the pixels).  Cells whose
+   parent or child triangles span more than `window` pixels along an axis
+   are not refined.  A refined cell is replaced by its four children, each
+   tested again while d + 1 < max_depth.  Deposits of (leaves - cell) go to
+   dmap.  Returns whether the cell was refined. */
+static int refine_rec(refine_ctx *c, double A0, double B0, double h, int d, const double *u4, const double *v4)
+{
+    const orc_region *R = c->R;
+    c->n_tested++;
+    double f[12];
+    orc_cell_features(u4, v4, f);
+    int fold = !(f[8] == f[9] && f[9] == f[10] && f[10] == f[11]);
+    /* children: grid vertices (A0 + {0, h/2, h}, B0 + {0, h/2, h}) */
+    double gu[3][3], gv[3][3];
+    gu[0][0] = u4[0]; gv[0][0] = v4[0];
+    gu[0][2] = u4[1]; gv[0][2] = v4[1];
+    gu[2][2] = u4[2]; gv[2][2] = v4[2];
+    gu[2][0] = u4[3]; gv[2][0] = v4[3];
+    double hh = 0.5 * h;
+    refine_shoot(c, A0 + hh, B0, &gu[0][1], &gv[0][1]);
+    refine_shoot(c, A0, B0 + hh, &gu[1][0], &gv[1][0]);
+    refine_shoot(c, A0 + hh, B0 + hh, &gu[1][1], &gv[1][1]);
+    refine_shoot(c, A0 + h, B0 + hh, &gu[1][2], &gv[1][2]);
+    refine_shoot(c, A0 + hh, B0 + h, &gu[2][1], &gv[2][1]);
+    /* extent of parent and children */
+    double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+    for (int r = 0; r < 3; ++r)
+        for (int s = 0; s < 3; ++s) {
+            umin = fmin(umin, gu[r][s]); umax = fmax(umax, gu[r][s]);
+            vmin = fmin(vmin, gv[r][s]); vmax = fmax(vmax, gv[r][s]);
+        }
+    if (!(umax - umin <= c->window && vmax - vmin <= c->window)) { c->n_large++; return 0; }
+    double AT = 0.5 * (h * R->d1) * (h * R->d2);   /* image area of one parent triangle */
+    int refine = fold;
+    if (!refine) {
+        /* L1 change of the in-map deposits */
+        long i0 = (long)floor(umin), i1 = (long)floor(umax), j0 = (long)floor(vmin), j1 = (long)floor(vmax);
+        if (i0 < 0) i0 = 0;
+        if (j0 < 0) j0 = 0;
+        if (i1 > R->n1 - 1) i1 = R->n1 - 1;
+        if (j1 > R->n2 - 1) j1 = R->n2 - 1;
+        double l1 = 0.0;
+        double pu[2][3], pv[2][3];
+        cell_tris(u4, v4, pu, pv);
+        for (long j = j0; j <= j1; ++j)
+            for (long i = i0; i <= i1; ++i) {
+                double diff = -tri_dep(AT, pu[0], pv[0], i, j) - tri_dep(AT, pu[1], pv[1], i, j);
+                for (int r = 0; r < 2; ++r)
+                    for (int s = 0; s < 2; ++s) {
+                        double cu[4] = {gu[r][s], gu[r][s + 1], gu[r + 1][s + 1], gu[r + 1][s]};
+                        double cv[4] = {gv[r][s], gv[r][s + 1], gv[r + 1][s + 1], gv[r + 1][s]};
+                        double tu[2][3], tv[2][3];
+                        cell_tris(cu, cv, tu, tv);
+                        diff += tri_dep(0.25 * AT, tu[0], tv[0], i, j) + tri_dep(0.25 * AT, tu[1], tv[1], i, j);
+                    }
+                l1 += fabs(diff);
+            }
+        refine = l1 > c->tau * 2.0 * AT;
+    }
+    if (!refine) return 0;
+    c->n_refined++;
+    add_cell(c, AT, u4, v4, -1.0);
+    for (int r = 0; r < 2; ++r)
+        for (int s = 0; s < 2; ++s) {
+            double cu[4] = {gu[r][s], gu[r][s + 1], gu[r + 1][s + 1], gu[r + 1][s]};
+            double cv[4] = {gv[r][s], gv[r][s + 1], gv[r + 1][s + 1], gv[r + 1][s]};
+            double a0 = A0 + s * hh, b0 = B0 + r * hh;
+            add_cell(c, 0.25 * AT, cu, cv, +1.0);   /* a refined child takes this back itself */
+            if (d + 1 < c->max_depth) refine_rec(c, a0, b0, hh, d + 1, cu, cv);
+        }
+    return 1;
+}
+
+/* The plain refinement of cells (a[k], b[k]) of the ray grid: label[k] = 1
+   if the cell itself is refined; dmap (n2 x n1, image-area units, not
+   normalised) receives the refined minus the plain deposits; stats =
+   {tested (sub)cells, refined (sub)cells, skipped as too large}. */
+void orc_refine_cells(const orc_region *R, double kappa_star, double kappa_smooth, double gamma, int sheet,
+                      double r_star, long n, const double *sx, const double *sy, const double *sm, const void *F,
+                      long ncells, const long *ca, const long *cb, double tau, int max_depth, int window,
+                      unsigned char *label, double *dmap, long *stats)
+{
+    refine_ctx c = {R, {kappa_star, kappa_smooth, gamma, sheet, r_star}, n, sx, sy, sm, F, tau, max_depth, window,
+                    dmap, 0, 0, 0};
+    for (long k = 0; k < ncells; ++k) {
+        double u4[4], v4[4];
+        double A = (double)ca[k], B = (double)cb[k];
+        refine_shoot(&c, A, B, &u4[0], &v4[0]);
+        refine_shoot(&c, A + 1.0, B, &u4[1], &v4[1]);
+        refine_shoot(&c, A + 1.0, B + 1.0, &u4[2], &v4[2]);
+        refine_shoot(&c, A, B + 1.0, &u4[3], &v4[3]);
+        label[k] = (unsigned char)(max_depth > 0 ? refine_rec(&c, A, B, 1.0, 0, u4, v4) : 0);
+    }
+    stats[0] += c.n_tested;
+    stats[1] += c.n_refined;
+    stats[2] += c.n_large;
+}
