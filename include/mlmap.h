@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define MLM_ABI_VERSION 2
+#define MLM_ABI_VERSION 3
 
 typedef enum mlm_status {
     MLM_OK = 0,
@@ -122,6 +122,7 @@ mlm_status mlm_lens_get_info(const mlm_lens *lens, mlm_lens_info *out);
 /* ------------------------------------------------------------------------ */
 
 enum { MLM_PREC_FP64 = 0, MLM_PREC_MIXED = 1 };
+enum { MLM_REFINE_NONE = 0, MLM_REFINE_PLAIN = 1, MLM_REFINE_LEARNED = 2 };
 enum { MLM_METHOD_FMM = 0, MLM_METHOD_DIRECT = 1 };
 
 /*
@@ -155,6 +156,17 @@ enum { MLM_METHOD_FMM = 0, MLM_METHOD_DIRECT = 1 };
  *                  MLM_METHOD_DIRECT it gives MLM_ENOTSUP.
  *   method         MLM_METHOD_FMM or MLM_METHOD_DIRECT (every star summed
  *                  for every ray; the no-FMM reference of sec. 4)
+ *   refine         cell refinement after the IPM (the paper apportions
+ *                  each cell as two triangles, sec. 3.2; refinement splits
+ *                  cells where that is coarse): MLM_REFINE_PLAIN tests every
+ *                  cell: refine if the mapped ears disagree in orientation
+ *                  or a 2 x 2 split changes the cell's in-map deposits by
+ *                  more than refine_tau times its image area (L1), children
+ *                  tested again down to refine_depth levels, cells wider
+ *                  than refine_window pixels left alone; MLM_REFINE_LEARNED
+ *                  runs the same test only on the cells `refiner` flags
+ *                  (logit > refine_threshold) and on every folded cell.
+ *                  FP64 with the FMM only (else MLM_ENOTSUP).
  *   device_out     != 0: `mu` (and `w_out`) are device pointers
  *   eps            absolute deflection accuracy for the automatic order,
  *                  default 1e-7
@@ -186,7 +198,12 @@ typedef struct mlm_map_request {
     void *stream;
     double *w_out;
     int32_t timing;
-    int32_t reserved;
+    int32_t refine;            /* MLM_REFINE_NONE, _PLAIN or _LEARNED */
+    int32_t refine_depth;      /* levels of 2 x 2 splitting, 1..4 (default 3) */
+    int32_t refine_window;     /* widest (sub)cell image refined, pixels (default 8) */
+    double refine_tau;         /* L1 threshold over the cell's image area (default 1e-3) */
+    double refine_threshold;   /* logit above which the network flags a cell (default 0) */
+    struct mlm_refiner *refiner;   /* network for MLM_REFINE_LEARNED */
 } mlm_map_request;
 
 void mlm_map_request_init(mlm_map_request *req);
@@ -233,6 +250,11 @@ typedef struct mlm_map_stats {
     double t_band_ms;        /* per-band IPM kernel (large triangles) */
     int64_t n_band_rows;     /* (large triangle, pixel row) pairs the per-band kernel visits */
     int64_t n_band_pieces;   /* column differences those rows deposit inside the map */
+    int64_t n_refine_candidates;   /* cells the refinement test ran on */
+    int64_t n_refined;       /* cells refined (their own test passed) */
+    int64_t n_refine_tests;  /* (sub)cells tested, all depths */
+    int64_t n_refine_large;  /* (sub)cells left alone for their width */
+    double t_refine_ms;      /* features, network and refinement (if timing) */
 } mlm_map_stats;
 
 /*
@@ -287,6 +309,64 @@ typedef struct mlm_batch_stats {
 
 mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, int32_t nmaps, double *const *mus,
                          mlm_map_stats *stats, const mlm_batch_opts *opts, mlm_batch_stats *bstats);
+
+/*
+ * The refinement network (learned variant of the cell refinement, see
+ * mlm_map_request.refine): 12 -> 64 -> 64 -> 1, ReLU, logit out; BF16
+ * weights and activations with FP32 accumulation, FP32 master weights.
+ * Parameters, FP32, MLM_REFINER_PARAMS of them in this order: W1 [12][64],
+ * b1 [64], W2 [64][64], b2 [64], W3 [64], b3; layer l computes
+ * relu(h W_l + b_l).  Features of a cell (corners 00, 10, 11, 01 mapped to
+ * pixel units): sign(d) log(1 + |d|) of each corner's (u, v) offset from
+ * the corner of the pixel holding the four corners' mean (8 values), then
+ * the signs (+1, -1, 0) of the
+ * mapped ears at the corners, ear k = (k, k + 1, k - 1) in that cyclic order.
+ * Loss: mean [ pos_weight y softplus(-z) + (1 - y) softplus(z) ].
+ * The refiner lives on the current device; calls on one refiner must not
+ * overlap.
+ */
+#define MLM_REFINER_PARAMS 5057
+typedef struct mlm_refiner mlm_refiner;
+
+/* params: NULL for He-normal weights drawn with `seed` and zero biases. */
+mlm_status mlm_refiner_create(const float *params, uint64_t seed, mlm_refiner **out);
+void mlm_refiner_destroy(mlm_refiner *r);
+mlm_status mlm_refiner_get_params(mlm_refiner *r, float *params);
+mlm_status mlm_refiner_set_params(mlm_refiner *r, const float *params);
+
+/* Logits of n feature rows (n x 12 floats); host or device pointers. */
+mlm_status mlm_refiner_predict(mlm_refiner *r, const float *feats, int64_t n, float *logits, int32_t device_ptrs,
+                               void *stream);
+
+/* Loss of n labelled rows and its gradient (MLM_REFINER_PARAMS floats),
+ * from the training kernels (one batch of n). */
+mlm_status mlm_refiner_grads(mlm_refiner *r, const float *feats, const uint8_t *labels, int64_t n, float pos_weight,
+                             float *grads, double *loss, int32_t device_ptrs, void *stream);
+
+typedef struct mlm_train_opts {
+    int32_t epochs;          /* default 4 */
+    int32_t batch;           /* samples per step, default 4096 */
+    float lr;                /* Adam step, default 1e-3 */
+    float pos_weight;        /* weight of positive labels, default 1 */
+    uint64_t seed;           /* shuffling */
+    int32_t device_ptrs;     /* feats and labels on the device */
+    int32_t reserved0;
+    void *stream;
+} mlm_train_opts;
+
+void mlm_train_opts_init(mlm_train_opts *o);
+
+/* Adam on the weighted cross-entropy over n labelled rows, `epochs` passes
+ * in seeded random order; loss_per_epoch (host, epochs values) may be NULL. */
+mlm_status mlm_refiner_train(mlm_refiner *r, const mlm_train_opts *opts, const float *feats, const uint8_t *labels,
+                             int64_t n, float *loss_per_epoch);
+
+/* Training samples of a map request: for cells (a, b) of its ray grid
+ * (cells[2k], cells[2k + 1]), the features (n x 12) and the label of the
+ * plain test at the first level (1: refine), from the request's tree
+ * (FP64, FMM).  Host or device pointers per device_ptrs. */
+mlm_status mlm_cell_samples(mlm_lens *lens, const mlm_map_request *req, const int64_t *cells, int64_t n, float *feats,
+                            uint8_t *labels, int32_t device_ptrs);
 
 /*
  * Source positions w(z) of arbitrary image-plane points through the same

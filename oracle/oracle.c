@@ -1035,13 +1035,15 @@ static double area2(double ua, double va, double ub, double vb, double uc, doubl
 
 /* Features of a mapped cell: corners (u, v) in pixel units in the order
    00, 10, 11, 01; f[0..7] = sign(d) log(1 + |d|) of each corner's offset
-   from the mean of the four, f[8..11] = signs of the mapped ears at the
-   corners (00: (00, 10, 01); 10: (10, 11, 00); 11: (11, 01, 10);
-   01: (01, 00, 11)), which all agree unless the cell is folded. */
+   from the corner of the pixel holding the mean of the four (so both the
+   cell's shape and where it falls on the pixel grid show), f[8..11] = signs
+   of the mapped ears at the corners (00: (00, 10, 01); 10: (10, 11, 00);
+   11: (11, 01, 10); 01: (01, 00, 11)), which all agree unless the cell is
+   folded. */
 void orc_cell_features(const double *u4, const double *v4, double *f)
 {
-    double cu = 0.25 * (u4[0] + u4[1] + u4[2] + u4[3]);
-    double cv = 0.25 * (v4[0] + v4[1] + v4[2] + v4[3]);
+    double cu = floor(0.25 * (u4[0] + u4[1] + u4[2] + u4[3]));
+    double cv = floor(0.25 * (v4[0] + v4[1] + v4[2] + v4[3]));
     for (int k = 0; k < 4; ++k) {
         double du = u4[k] - cu, dv = v4[k] - cv;
         f[2 * k] = sgn(du) * log1p(fabs(du));

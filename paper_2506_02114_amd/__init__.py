@@ -21,12 +21,16 @@ LIB_PATH = os.path.join(_HERE, "libmlmap.so")
 MLM_OK, MLM_EINVAL, MLM_EDEGENERATE, MLM_ERANGE, MLM_ENOMEM, MLM_EDEVICE, MLM_ENOTSUP = range(7)
 SHEET_CIRCLE, SHEET_NONE = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
+REFINE_NONE, REFINE_PLAIN, REFINE_LEARNED = 0, 1, 2
+REFINER_PARAMS = 5057
 METHOD_FMM, METHOD_DIRECT = 0, 1
 
 EXPORTED = [
     "mlm_abi_version", "mlm_status_str", "mlm_last_error", "mlm_lens_create", "mlm_lens_destroy", "mlm_map_batch",
     "mlm_lens_get_info", "mlm_map_request_init", "mlm_map_region", "mlm_map", "mlm_deflect",
-    "mlm_fmm_export",
+    "mlm_fmm_export", "mlm_refiner_create", "mlm_refiner_destroy", "mlm_refiner_get_params",
+    "mlm_refiner_set_params", "mlm_refiner_predict", "mlm_refiner_grads", "mlm_train_opts_init",
+    "mlm_refiner_train", "mlm_cell_samples",
 ]
 
 
@@ -55,7 +59,9 @@ class MapRequest(C.Structure):
                 ("max_level", C.c_int32), ("precision", C.c_int32), ("method", C.c_int32),
                 ("device_out", C.c_int32), ("eps", C.c_double), ("row_begin", C.c_int64),
                 ("row_end", C.c_int64), ("stream", C.c_void_p), ("w_out", C.c_void_p),
-                ("timing", C.c_int32), ("reserved", C.c_int32)]
+                ("timing", C.c_int32), ("refine", C.c_int32), ("refine_depth", C.c_int32),
+                ("refine_window", C.c_int32), ("refine_tau", C.c_double), ("refine_threshold", C.c_double),
+                ("refiner", C.c_void_p)]
 
 
 class Region(C.Structure):
@@ -74,7 +80,9 @@ class MapStats(C.Structure):
                 ("t_shoot_ms", C.c_double), ("t_ipm_ms", C.c_double), ("t_total_ms", C.c_double),
                 ("n_shoot_launches", C.c_int32), ("n_ipm_launches", C.c_int32),
                 ("n_big", C.c_int64), ("n_big_rows", C.c_int64), ("t_cells_ms", C.c_double),
-                ("t_band_ms", C.c_double), ("n_band_rows", C.c_int64), ("n_band_pieces", C.c_int64)]
+                ("t_band_ms", C.c_double), ("n_band_rows", C.c_int64), ("n_band_pieces", C.c_int64),
+                ("n_refine_candidates", C.c_int64), ("n_refined", C.c_int64), ("n_refine_tests", C.c_int64),
+                ("n_refine_large", C.c_int64), ("t_refine_ms", C.c_double)]
 
 
 class BatchOpts(C.Structure):
@@ -86,6 +94,11 @@ class BatchStats(C.Structure):
     _fields_ = [("n_maps", C.c_int64), ("n_chunks", C.c_int64), ("n_rays", C.c_int64), ("n_cells", C.c_int64),
                 ("n_big", C.c_int64), ("t_prep_ms", C.c_double), ("t_shoot_ms", C.c_double),
                 ("t_ipm_ms", C.c_double), ("t_total_ms", C.c_double), ("reserved", C.c_int64 * 4)]
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("pos_weight", C.c_float),
+                ("seed", C.c_uint64), ("device_ptrs", C.c_int32), ("reserved0", C.c_int32), ("stream", C.c_void_p)]
 
 
 class TreeInfo(C.Structure):
@@ -132,6 +145,21 @@ def _lib():
     L.mlm_map_batch.argtypes = [C.POINTER(vp), C.POINTER(MapRequest), i32, C.POINTER(vp), C.POINTER(MapStats),
                                 C.POINTER(BatchOpts), C.POINTER(BatchStats)]
     L.mlm_map_batch.restype = C.c_int
+    fp, u8p = C.POINTER(C.c_float), C.POINTER(C.c_uint8)
+    L.mlm_refiner_create.argtypes = [vp, C.c_uint64, C.POINTER(vp)]
+    L.mlm_refiner_destroy.argtypes = [vp]
+    L.mlm_refiner_destroy.restype = None
+    L.mlm_refiner_get_params.argtypes = [vp, vp]
+    L.mlm_refiner_set_params.argtypes = [vp, vp]
+    L.mlm_refiner_predict.argtypes = [vp, vp, i64, vp, i32, vp]
+    L.mlm_refiner_grads.argtypes = [vp, vp, vp, i64, C.c_float, vp, C.POINTER(C.c_double), i32, vp]
+    L.mlm_train_opts_init.argtypes = [C.POINTER(TrainOpts)]
+    L.mlm_train_opts_init.restype = None
+    L.mlm_refiner_train.argtypes = [vp, C.POINTER(TrainOpts), vp, vp, i64, vp]
+    L.mlm_cell_samples.argtypes = [vp, C.POINTER(MapRequest), vp, i64, vp, vp, i32]
+    for f in ("mlm_refiner_create", "mlm_refiner_get_params", "mlm_refiner_set_params", "mlm_refiner_predict",
+              "mlm_refiner_grads", "mlm_refiner_train", "mlm_cell_samples"):
+        getattr(L, f).restype = C.c_int
     _L = L
     return L
 
@@ -154,7 +182,7 @@ def _current_stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-REQUEST_KEYS = {k for k, _ in MapRequest._fields_} - {"stream", "w_out", "device_out", "reserved"}
+REQUEST_KEYS = {k for k, _ in MapRequest._fields_} - {"stream", "w_out", "device_out", "refiner"}
 
 
 def make_request(**kw) -> MapRequest:
@@ -165,6 +193,11 @@ def make_request(**kw) -> MapRequest:
             v = {"fp64": PREC_FP64, "mixed": PREC_MIXED}[v]
         if k == "method" and isinstance(v, str):
             v = {"fmm": METHOD_FMM, "direct": METHOD_DIRECT}[v]
+        if k == "refine" and isinstance(v, str):
+            v = {"none": REFINE_NONE, "plain": REFINE_PLAIN, "learned": REFINE_LEARNED}[v]
+        if k == "refiner":
+            r.refiner = v._h if v is not None else None
+            continue
         if k == "rows":
             if v is not None:
                 r.row_begin, r.row_end = int(v[0]), int(v[1])
@@ -261,6 +294,18 @@ class Lens:
                                   w.ctypes.data_as(C.c_void_p)))
         return w
 
+    def cell_samples(self, cells, **req):
+        """Features (n x 12, float32) and first-level refinement labels of
+        ray-grid cells (n x 2 int64 of (a, b)) of a request."""
+        r = make_request(**req)
+        cells = np.ascontiguousarray(cells, dtype=np.int64).reshape(-1, 2)
+        n = cells.shape[0]
+        feats = np.empty((n, 12), np.float32)
+        labels = np.empty(n, np.uint8)
+        _check(_lib().mlm_cell_samples(self._h, C.byref(r), cells.ctypes.data_as(C.c_void_p), n,
+                                       feats.ctypes.data_as(C.c_void_p), labels.ctypes.data_as(C.c_void_p), 0))
+        return feats, labels
+
     def fmm_export(self, **req) -> dict:
         r = make_request(**req)
         I = TreeInfo()
@@ -310,3 +355,75 @@ def map_batch(lenses, requests, outs, stream=None, autotune: bool = False, verte
     b = BatchStats()
     _check(_lib().mlm_map_batch(hs, reqs, n, ptrs, stats, C.byref(o), C.byref(b)))
     return [_asdict(s) for s in stats], _asdict(b)
+
+
+class Refiner:
+    """The refinement network (mlm_refiner_*): FP32 parameters on the host
+    side as one array of REFINER_PARAMS floats (W1, b1, W2, b2, W3, b3)."""
+
+    def __init__(self, params=None, seed: int = 0):
+        self._h = C.c_void_p()
+        p = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
+        if p is not None:
+            assert p.size == REFINER_PARAMS
+        _check(_lib().mlm_refiner_create(p.ctypes.data_as(C.c_void_p) if p is not None else None, seed,
+                                         C.byref(self._h)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib().mlm_refiner_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def params(self) -> np.ndarray:
+        p = np.empty(REFINER_PARAMS, np.float32)
+        _check(_lib().mlm_refiner_get_params(self._h, p.ctypes.data_as(C.c_void_p)))
+        return p
+
+    @params.setter
+    def params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == REFINER_PARAMS
+        _check(_lib().mlm_refiner_set_params(self._h, p.ctypes.data_as(C.c_void_p)))
+
+    def predict(self, feats) -> np.ndarray:
+        f = np.ascontiguousarray(feats, dtype=np.float32).reshape(-1, 12)
+        out = np.empty(f.shape[0], np.float32)
+        _check(_lib().mlm_refiner_predict(self._h, f.ctypes.data_as(C.c_void_p), f.shape[0],
+                                          out.ctypes.data_as(C.c_void_p), 0, None))
+        return out
+
+    def grads(self, feats, labels, pos_weight: float = 1.0):
+        f = np.ascontiguousarray(feats, dtype=np.float32).reshape(-1, 12)
+        y = np.ascontiguousarray(labels, dtype=np.uint8)
+        g = np.empty(REFINER_PARAMS, np.float32)
+        loss = C.c_double()
+        _check(_lib().mlm_refiner_grads(self._h, f.ctypes.data_as(C.c_void_p), y.ctypes.data_as(C.c_void_p),
+                                        f.shape[0], pos_weight, g.ctypes.data_as(C.c_void_p), C.byref(loss), 0,
+                                        None))
+        return loss.value, g
+
+    def train(self, feats, labels, epochs: int = 4, batch: int = 4096, lr: float = 1e-3, pos_weight: float = 1.0,
+              seed: int = 0):
+        f = np.ascontiguousarray(feats, dtype=np.float32).reshape(-1, 12)
+        y = np.ascontiguousarray(labels, dtype=np.uint8)
+        o = TrainOpts()
+        _lib().mlm_train_opts_init(C.byref(o))
+        o.epochs, o.batch, o.lr, o.pos_weight, o.seed = epochs, batch, lr, pos_weight, seed
+        losses = np.empty(max(epochs, 1), np.float32)
+        _check(_lib().mlm_refiner_train(self._h, C.byref(o), f.ctypes.data_as(C.c_void_p),
+                                        y.ctypes.data_as(C.c_void_p), f.shape[0], losses.ctypes.data_as(C.c_void_p)))
+        return losses[:epochs]
+
+
+def params_to_dict(p) -> dict:
+    """Split a flat parameter array into the named tensors (float64)."""
+    p = np.asarray(p, dtype=np.float64)
+    return dict(W1=p[0:768].reshape(12, 64), b1=p[768:832], W2=p[832:4928].reshape(64, 64), b2=p[4928:4992],
+                W3=p[4992:5056], b3=p[5056:5057])

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <set>
@@ -155,6 +156,15 @@ void check_request(const mlm_map_request *q)
     if (q->leaf_max < 0 || q->max_level < 0 || q->max_level > KEY_BITS)
         fail(MLM_EINVAL, "leaf_max must be >= 0 and max_level in [0, %d]", KEY_BITS);
     if (!(q->eps >= 0) || !std::isfinite(q->eps)) fail(MLM_EINVAL, "eps must be finite and >= 0");
+    if (q->refine < MLM_REFINE_NONE || q->refine > MLM_REFINE_LEARNED) fail(MLM_EINVAL, "unknown refine %d", q->refine);
+    if (q->refine != MLM_REFINE_NONE) {
+        if (q->precision != MLM_PREC_FP64 || q->method != MLM_METHOD_FMM)
+            fail(MLM_ENOTSUP, "cell refinement needs FP64 and the FMM");
+        if (q->refine_depth < 1 || q->refine_depth > 4 || q->refine_window < 1 || !(q->refine_tau >= 0) ||
+            !std::isfinite(q->refine_tau) || !std::isfinite(q->refine_threshold))
+            fail(MLM_EINVAL, "refine_depth in [1, 4], refine_window >= 1, refine_tau >= 0 and finite");
+        if (q->refine == MLM_REFINE_LEARNED && !q->refiner) fail(MLM_EINVAL, "learned refinement needs a refiner");
+    }
 }
 
 // tree + FMM + leaf tables for a request
@@ -348,6 +358,21 @@ void mlm_map_request_init(mlm_map_request *r)
     r->eps = 1e-7;
     r->row_begin = 0;
     r->row_end = -1;
+    r->refine = MLM_REFINE_NONE;
+    r->refine_depth = 3;
+    r->refine_window = 8;
+    r->refine_tau = 1e-3;
+    r->refine_threshold = 0.0;
+}
+
+void mlm_train_opts_init(mlm_train_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->epochs = 4;
+    o->batch = 4096;
+    o->lr = 1e-3f;
+    o->pos_weight = 1.0f;
 }
 
 mlm_status mlm_lens_create(const mlm_lens_params *params, const double *x, const double *y, const double *m,
@@ -538,7 +563,9 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
     double *wdev = nullptr;
     if (q.w_out) wdev = q.device_out ? q.w_out : static_cast<double *>(ws.wbuf.reserve((size_t)nbuf * sizeof(double2)));
 
-    int64_t n_big = 0, n_big_rows = 0;
+    int64_t n_big = 0, n_big_rows = 0, n_cand = 0, n_refined = 0;
+    double t_refine = 0.0;
+    bool refine_stats_zeroed = false;
 
     double t_shoot = 0.0, t_ipm = 0.0, t_cells = 0.0, t_band = 0.0;
     int64_t tiles = 0;
@@ -599,12 +626,49 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
             n_big += nb;
         }
         int ec = tm.mark();
+        if (q.refine != MLM_REFINE_NONE) {
+            // cell refinement of this strip's cells (a + (nr1 - 1) b, b in [r0, r1))
+            const int64_t base = (R.nr1 - 1) * r0;
+            int64_t *cand = static_cast<int64_t *>(ws.rcand.reserve((size_t)ncells * sizeof(int64_t)));
+            int64_t ncand = ncells;
+            if (q.refine == MLM_REFINE_LEARNED) {
+                mlm_refiner *nn = q.refiner;
+                float *feats = static_cast<float *>(ws.rfeat.reserve((size_t)ncells * 12 * sizeof(float)));
+                float *logit = static_cast<float *>(ws.rlogit.reserve((size_t)ncells * sizeof(float)));
+                int32_t *flag = static_cast<int32_t *>(ws.rflag.reserve((size_t)ncells * sizeof(int32_t)));
+                int64_t *pos = static_cast<int64_t *>(ws.rpos.reserve((size_t)(ncells + 1) * sizeof(int64_t)));
+                launch_cell_features(R.nr1, r0, ncells, vb0, verts, feats, st);
+                mlp_predict(feats, ncells, nn->W1b.as<uint16_t>(), nn->W2b.as<uint16_t>(), nn->P.as<float>(), logit, st);
+                launch_select(ncells, feats, logit, (float)q.refine_threshold, flag, st);
+                ncand = scan_i32_to_i64(lens, flag, pos, ncells, st);
+                launch_compact(ncells, flag, pos, base, cand, st);
+            } else {
+                launch_compact(ncells, nullptr, nullptr, base, cand, st);
+            }
+            uint8_t *lab = static_cast<uint8_t *>(ws.rlabel.reserve((size_t)std::max<int64_t>(ncand, 1)));
+            unsigned long long *rst3 = static_cast<unsigned long long *>(ws.rstats.reserve(4 * sizeof(unsigned long long)));
+            if (!refine_stats_zeroed) {
+                hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, rst3, 4);
+                refine_stats_zeroed = true;
+            }
+            launch_refine(T, R, lc, g, q.refine_tau, q.refine_depth, q.refine_window, ncand, cand, R.nr1, vb0, verts, lab,
+                          map, rst3, st);
+            if (ncand > 0) {
+                std::vector<uint8_t> hl((size_t)ncand);
+                MLM_HIP(hipMemcpyAsync(hl.data(), lab, (size_t)ncand, hipMemcpyDeviceToHost, st));
+                MLM_HIP(hipStreamSynchronize(st));
+                for (uint8_t v : hl) n_refined += v;
+            }
+            n_cand += ncand;
+        }
+        int ed = tm.mark();
         if (q.w_out && !q.device_out)
             MLM_HIP(hipMemcpyAsync(q.w_out + 2 * (vb0 - cb0) * R.nr1, wdev, (size_t)(vb1 - vb0) * R.nr1 * 2 * sizeof(double),
                                    hipMemcpyDeviceToHost, st));
         MLM_HIP(hipStreamSynchronize(st));
         t_shoot += tm.ms(ea, eb);
         t_ipm += tm.ms(eb, ec);
+        t_refine += tm.ms(ec, ed);
         t_cells += tm.ms(eb, e_cells);
         t_band += tm.ms(e_band0, e_band1);
         tiles += nt;
@@ -641,6 +705,15 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
         S.t_band_ms = t_band;
         S.n_band_rows = q.timing ? (int64_t)hc[4] : 0;
         S.n_band_pieces = q.timing ? (int64_t)hc[5] : 0;
+        S.n_refine_candidates = n_cand;
+        S.n_refined = n_refined;
+        if (refine_stats_zeroed) {
+            unsigned long long h3[4];
+            MLM_HIP(hipMemcpy(h3, ws.rstats.p, sizeof h3, hipMemcpyDeviceToHost));
+            S.n_refine_tests = (int64_t)h3[0];
+            S.n_refine_large = (int64_t)h3[2];
+        }
+        S.t_refine_ms = t_refine;
         *stats = S;
     }
     API_END
@@ -861,6 +934,240 @@ mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, i
         b.t_total_ms = tm.ms(e_start, e_end);
         *bstats = b;
     }
+    API_END
+}
+
+// ---------------------------------------------------------------------------
+// refinement network
+// ---------------------------------------------------------------------------
+
+static void refiner_upload(mlm_refiner *r, const float *params, hipStream_t st)
+{
+    MLM_HIP(hipMemcpyAsync(r->P.p, params, MLM_REFINER_PARAMS * sizeof(float), hipMemcpyHostToDevice, st));
+    mlp_pack(r->P.as<float>(), r->W1b.as<uint16_t>(), r->W2b.as<uint16_t>(), st);
+    MLM_HIP(hipStreamSynchronize(st));
+}
+
+mlm_status mlm_refiner_create(const float *params, uint64_t seed, mlm_refiner **out)
+{
+    API_BEGIN
+    if (!out) fail(MLM_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    std::unique_ptr<mlm_refiner> r(new mlm_refiner);
+    const size_t nb = (MLM_REFINER_PARAMS + 1) * sizeof(float);
+    r->P.reserve(nb);
+    r->M.reserve(nb);
+    r->V.reserve(nb);
+    r->G.reserve(nb);
+    r->W1b.reserve(16 * 64 * sizeof(uint16_t));
+    r->W2b.reserve(64 * 64 * sizeof(uint16_t));
+    mlp_zero(r->M.as<float>(), MLM_REFINER_PARAMS + 1, nullptr);
+    mlp_zero(r->V.as<float>(), MLM_REFINER_PARAMS + 1, nullptr);
+    mlp_zero(r->G.as<float>(), MLM_REFINER_PARAMS + 1, nullptr);
+    std::vector<float> h(MLM_REFINER_PARAMS, 0.0f);
+    if (params) {
+        std::memcpy(h.data(), params, h.size() * sizeof(float));
+    } else {
+        // He-normal weights from a counter-free Box-Muller over splitmix64
+        uint64_t x = seed;
+        auto next = [&x]() {
+            uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+            z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+            z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+            return (double)((z ^ (z >> 31)) >> 11) * 0x1.0p-53;
+        };
+        auto normal = [&]() {
+            const double u1 = std::max(next(), 1e-300), u2 = next();
+            return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+        };
+        for (int k = 0; k < 768; ++k) h[k] = (float)(normal() * std::sqrt(2.0 / 12));
+        for (int k = 832; k < 4928; ++k) h[k] = (float)(normal() * std::sqrt(2.0 / 64));
+        for (int k = 4992; k < 5056; ++k) h[k] = (float)(normal() * std::sqrt(2.0 / 64));
+    }
+    refiner_upload(r.get(), h.data(), nullptr);
+    *out = r.release();
+    API_END
+}
+
+void mlm_refiner_destroy(mlm_refiner *r) { delete r; }
+
+mlm_status mlm_refiner_get_params(mlm_refiner *r, float *params)
+{
+    API_BEGIN
+    if (!r || !params) fail(MLM_EINVAL, "refiner and params must not be NULL");
+    std::lock_guard<std::mutex> g(r->mu);
+    MLM_HIP(hipMemcpy(params, r->P.p, MLM_REFINER_PARAMS * sizeof(float), hipMemcpyDeviceToHost));
+    API_END
+}
+
+mlm_status mlm_refiner_set_params(mlm_refiner *r, const float *params)
+{
+    API_BEGIN
+    if (!r || !params) fail(MLM_EINVAL, "refiner and params must not be NULL");
+    std::lock_guard<std::mutex> g(r->mu);
+    for (int k = 0; k < MLM_REFINER_PARAMS; ++k)
+        if (!std::isfinite(params[k])) fail(MLM_EINVAL, "parameter %d is not finite", k);
+    refiner_upload(r, params, nullptr);
+    API_END
+}
+
+// device copies of host rows (staging in the refiner's buffers)
+static const float *stage_feats(mlm_refiner *r, const float *feats, int64_t n, int32_t dev, hipStream_t st)
+{
+    if (dev) return feats;
+    float *d = static_cast<float *>(r->feats.reserve((size_t)n * 12 * sizeof(float)));
+    MLM_HIP(hipMemcpyAsync(d, feats, (size_t)n * 12 * sizeof(float), hipMemcpyHostToDevice, st));
+    return d;
+}
+
+mlm_status mlm_refiner_predict(mlm_refiner *r, const float *feats, int64_t n, float *logits, int32_t device_ptrs,
+                               void *stream)
+{
+    API_BEGIN
+    if (!r || n < 0 || (n > 0 && (!feats || !logits))) fail(MLM_EINVAL, "refiner, feats and logits must be given");
+    std::lock_guard<std::mutex> g(r->mu);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (n == 0) return MLM_OK;
+    const float *df = stage_feats(r, feats, n, device_ptrs, st);
+    float *dl = device_ptrs ? logits : static_cast<float *>(r->logits.reserve((size_t)n * sizeof(float)));
+    mlp_predict(df, n, r->W1b.as<uint16_t>(), r->W2b.as<uint16_t>(), r->P.as<float>(), dl, st);
+    if (!device_ptrs) MLM_HIP(hipMemcpyAsync(logits, dl, (size_t)n * sizeof(float), hipMemcpyDeviceToHost, st));
+    MLM_HIP(hipStreamSynchronize(st));
+    API_END
+}
+
+__global__ void k_iota64(int64_t *p, int64_t n)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = t;
+}
+
+// one forward/backward over rows idx[0, n) into r->G (gradient + loss at [NP])
+static void refiner_batch(mlm_refiner *r, const float *df, const uint8_t *dy, const int64_t *didx, int64_t n,
+                          float pos_weight, hipStream_t st)
+{
+    const int64_t nblk = (n + 127) / 128;
+    float *xbuf = static_cast<float *>(r->xbuf.reserve((size_t)nblk * 128 * 12 * sizeof(float)));
+    mlp_train_batch(df, dy, didx, n, r->W1b.as<uint16_t>(), r->W2b.as<uint16_t>(), r->P.as<float>(), pos_weight,
+                    r->G.as<float>(), xbuf, st);
+}
+
+mlm_status mlm_refiner_grads(mlm_refiner *r, const float *feats, const uint8_t *labels, int64_t n, float pos_weight,
+                             float *grads, double *loss, int32_t device_ptrs, void *stream)
+{
+    API_BEGIN
+    if (!r || n <= 0 || !feats || !labels || !grads) fail(MLM_EINVAL, "refiner, rows, labels and grads must be given");
+    if (!(pos_weight > 0) || !std::isfinite(pos_weight)) fail(MLM_EINVAL, "pos_weight must be finite and > 0");
+    std::lock_guard<std::mutex> g(r->mu);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const float *df = stage_feats(r, feats, n, device_ptrs, st);
+    const uint8_t *dy = labels;
+    if (!device_ptrs) {
+        uint8_t *d = static_cast<uint8_t *>(r->labels.reserve((size_t)n));
+        MLM_HIP(hipMemcpyAsync(d, labels, (size_t)n, hipMemcpyHostToDevice, st));
+        dy = d;
+    }
+    int64_t *didx = static_cast<int64_t *>(r->idx.reserve((size_t)n * sizeof(int64_t)));
+    hipLaunchKernelGGL(k_iota64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, didx, n);
+    mlp_zero(r->G.as<float>(), MLM_REFINER_PARAMS + 1, st);
+    refiner_batch(r, df, dy, didx, n, pos_weight, st);
+    std::vector<float> h(MLM_REFINER_PARAMS + 1);
+    MLM_HIP(hipMemcpyAsync(h.data(), r->G.p, h.size() * sizeof(float), hipMemcpyDeviceToHost, st));
+    mlp_zero(r->G.as<float>(), MLM_REFINER_PARAMS + 1, st);
+    MLM_HIP(hipStreamSynchronize(st));
+    std::memcpy(grads, h.data(), MLM_REFINER_PARAMS * sizeof(float));
+    if (loss) *loss = h[MLM_REFINER_PARAMS];
+    API_END
+}
+
+mlm_status mlm_refiner_train(mlm_refiner *r, const mlm_train_opts *opts, const float *feats, const uint8_t *labels,
+                             int64_t n, float *loss_per_epoch)
+{
+    API_BEGIN
+    if (!r || !opts || n <= 0 || !feats || !labels) fail(MLM_EINVAL, "refiner, options and labelled rows must be given");
+    const mlm_train_opts o = *opts;
+    if (o.epochs < 0 || o.batch < 1 || !(o.lr > 0) || !(o.pos_weight > 0)) fail(MLM_EINVAL, "bad training options");
+    std::lock_guard<std::mutex> g(r->mu);
+    hipStream_t st = static_cast<hipStream_t>(o.stream);
+    const float *df = stage_feats(r, feats, n, o.device_ptrs, st);
+    const uint8_t *dy = labels;
+    if (!o.device_ptrs) {
+        uint8_t *d = static_cast<uint8_t *>(r->labels.reserve((size_t)n));
+        MLM_HIP(hipMemcpyAsync(d, labels, (size_t)n, hipMemcpyHostToDevice, st));
+        dy = d;
+    }
+    int64_t *didx = static_cast<int64_t *>(r->idx.reserve((size_t)n * sizeof(int64_t)));
+    std::vector<int64_t> perm((size_t)n);
+    uint64_t x = o.seed ^ 0x5DEECE66Dull;
+    auto next = [&x]() {
+        uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    mlp_zero(r->G.as<float>(), MLM_REFINER_PARAMS + 1, st);
+    for (int32_t e = 0; e < o.epochs; ++e) {
+        for (int64_t k = 0; k < n; ++k) perm[k] = k;
+        for (int64_t k = n - 1; k > 0; --k) std::swap(perm[k], perm[next() % (uint64_t)(k + 1)]);
+        MLM_HIP(hipMemcpyAsync(didx, perm.data(), (size_t)n * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        double loss = 0.0;
+        int64_t steps = 0;
+        for (int64_t b0 = 0; b0 < n; b0 += o.batch) {
+            const int64_t nb = std::min<int64_t>(o.batch, n - b0);
+            refiner_batch(r, df, dy, didx + b0, nb, o.pos_weight, st);
+            float hl = 0.0f;
+            if (loss_per_epoch) MLM_HIP(hipMemcpyAsync(&hl, r->G.as<float>() + MLM_REFINER_PARAMS, sizeof(float),
+                                                       hipMemcpyDeviceToHost, st));
+            mlp_adam(r->P.as<float>(), r->M.as<float>(), r->V.as<float>(), r->G.as<float>(), o.lr, ++r->step, st);
+            mlp_zero(r->G.as<float>() + MLM_REFINER_PARAMS, 1, st);
+            mlp_pack(r->P.as<float>(), r->W1b.as<uint16_t>(), r->W2b.as<uint16_t>(), st);
+            if (loss_per_epoch) {
+                MLM_HIP(hipStreamSynchronize(st));
+                loss += hl * (double)nb;
+            }
+            ++steps;
+        }
+        if (loss_per_epoch) loss_per_epoch[e] = (float)(loss / (double)n);
+        MLM_HIP(hipStreamSynchronize(st));   // perm is reused by the next epoch
+    }
+    MLM_HIP(hipStreamSynchronize(st));
+    API_END
+}
+
+mlm_status mlm_cell_samples(mlm_lens *lens, const mlm_map_request *req, const int64_t *cells, int64_t n, float *feats,
+                            uint8_t *labels, int32_t device_ptrs)
+{
+    API_BEGIN
+    if (!lens || !cells || n <= 0 || (!feats && !labels)) fail(MLM_EINVAL, "lens, cells and an output must be given");
+    check_request(req);
+    if (req->precision != MLM_PREC_FP64 || req->method != MLM_METHOD_FMM)
+        fail(MLM_ENOTSUP, "cell samples need FP64 and the FMM");
+    std::lock_guard<std::mutex> guard(lens->mu);
+    Region R{};
+    setup_region(lens, req, &R);
+    hipStream_t st = stream_of(req);
+    Tree T;
+    prepare_fmm(lens, R, *req, T, st);
+    Workspace &ws = lens->ws;
+    const int64_t *dab = cells;
+    if (!device_ptrs) {
+        int64_t *d = static_cast<int64_t *>(ws.rpos.reserve((size_t)n * 2 * sizeof(int64_t)));
+        MLM_HIP(hipMemcpyAsync(d, cells, (size_t)n * 2 * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        dab = d;
+    }
+    const MapGeom g = map_geom(*req, R);
+    const LensConst lc = lens_const(lens, R);
+    if (feats) {
+        float *df = device_ptrs ? feats : static_cast<float *>(ws.rfeat.reserve((size_t)n * 12 * sizeof(float)));
+        launch_sample_features(T, R, lc, g, n, dab, df, st);
+        if (!device_ptrs) MLM_HIP(hipMemcpyAsync(feats, df, (size_t)n * 12 * sizeof(float), hipMemcpyDeviceToHost, st));
+    }
+    if (labels) {
+        uint8_t *dl = device_ptrs ? labels : static_cast<uint8_t *>(ws.rlabel.reserve((size_t)n));
+        launch_sample_labels(T, R, lc, g, req->refine_tau, req->refine_window, n, dab, dl, st);
+        if (!device_ptrs) MLM_HIP(hipMemcpyAsync(labels, dl, (size_t)n, hipMemcpyDeviceToHost, st));
+    }
+    MLM_HIP(hipStreamSynchronize(st));
     API_END
 }
 

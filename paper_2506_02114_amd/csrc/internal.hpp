@@ -182,7 +182,7 @@ struct Workspace {
     DevBuf ilist, mult, local, ops_m2m, ops_m2l, ops_l2l;
     DevBuf leaves, near, deriv, near_offs;
     DevBuf tile_off, tile_leaf, verts, map, wbuf, pts, counters, items, itemoff, nbig, bigoff, bigprep, bigrows, rowoff, nbnd, nbndoff, diff, bandcnt, bandoff,
-        bandcur, bandlist;
+        bandcur, bandlist, rfeat, rlogit, rflag, rpos, rcand, rlabel, rstats;
     void *pinned = nullptr;               // small pinned host buffer for read-backs
     size_t pinned_cap = 0;
     int ops_p = -1;                       // 2 x order (+1 for FP32) of the operator tables
@@ -198,6 +198,14 @@ struct mlm_lens {
     double *d_x = nullptr, *d_y = nullptr, *d_m = nullptr;
     double mass_sum = 0, mass2_sum = 0, max_abs = 0, r_star = 0;
     mlm::Workspace ws;
+    std::mutex mu;
+};
+
+// refinement network: FP32 master weights, Adam moments, gradient (+ loss),
+// bf16 copies in the kernels' layouts, staging
+struct mlm_refiner {
+    mlm::DevBuf P, M, V, G, W1b, W2b, xbuf, idx, feats, labels, logits;
+    int64_t step = 0;
     std::mutex mu;
 };
 
@@ -260,6 +268,28 @@ void launch_band_batch(const BatchMap *maps, int32_t nmaps, int64_t nbands, cons
 int64_t scan_i32_to_u64(mlm_lens *lens, const int32_t *in, unsigned long long *out, int64_t n, hipStream_t st);
 int64_t scan_total_i64(mlm_lens *lens, const int64_t *in, int64_t *out, int64_t n, hipStream_t st);
 int64_t scan_i32_to_i64(mlm_lens *lens, const int32_t *in, int64_t *out, int64_t n, hipStream_t st);
+
+// refine.hip
+void launch_refine(const Tree &T, const Region &R, const LensConst &lc, const MapGeom &g, double tau, int depth,
+                   int window, int64_t ncand, const int64_t *cand, int64_t nr1, int64_t vb0, const double2 *verts,
+                   uint8_t *label, double *map, unsigned long long *stats, hipStream_t st);
+void launch_cell_features(int64_t nr1, int64_t cb0, int64_t ncells, int64_t vb0, const double2 *verts, float *feats,
+                          hipStream_t st);
+void launch_sample_features(const Tree &T, const Region &R, const LensConst &lc, const MapGeom &g, int64_t n,
+                            const int64_t *ab, float *feats, hipStream_t st);
+void launch_sample_labels(const Tree &T, const Region &R, const LensConst &lc, const MapGeom &g, double tau,
+                          int window, int64_t n, const int64_t *ab, uint8_t *label, hipStream_t st);
+void launch_select(int64_t n, const float *feats, const float *logits, float thr, int32_t *flag, hipStream_t st);
+void launch_compact(int64_t n, const int32_t *flag, const int64_t *pos, int64_t base, int64_t *cand, hipStream_t st);
+
+// mlp.hip
+void mlp_pack(const float *P, uint16_t *W1b, uint16_t *W2b, hipStream_t st);
+void mlp_predict(const float *feats, int64_t n, const uint16_t *W1b, const uint16_t *W2b, const float *P,
+                 float *logits, hipStream_t st);
+void mlp_train_batch(const float *feats, const uint8_t *y, const int64_t *idx, int64_t n, const uint16_t *W1b,
+                     const uint16_t *W2b, const float *P, float pos_weight, float *grad, float *xbuf, hipStream_t st);
+void mlp_adam(float *P, float *M, float *V, float *grad, float lr, int64_t step, hipStream_t st);
+void mlp_zero(float *p, int64_t n, hipStream_t st);
 
 // helpers
 void *pinned(mlm_lens *lens, size_t bytes);

@@ -1,0 +1,317 @@
+// The refinement network: 12 -> 64 -> 64 -> 1 with ReLU between layers and a
+// logit out, BF16 weights and activations on the matrix cores with FP32
+// accumulation (v_mfma_f32_32x32x8_bf16), FP32 master weights and Adam.  The
+// hidden activations feeding the second layer are carried as two bf16 parts
+// (value and residual, two products each): one bf16 rounding there moves
+// pre-activations across the ReLU kink often enough to change gradients by
+// percents, while the rounding of weights and back-propagated gradients
+// costs about 2^-9.
+//
+// Parameters (FP32, 5057): W1 [12][64], b1 [64], W2 [64][64], b2 [64],
+// W3 [64], b3; layer l computes h_l = relu(h_{l-1} W_l + b_l).
+// Loss: mean_i [ w+ y_i softplus(-z_i) + (1 - y_i) softplus(z_i) ].
+//
+// One wavefront takes 32 samples; a workgroup of four wavefronts takes 128.
+// Every product is a 32 x 32 block tile (one MFMA per 8 of the reduced
+// dimension) whose operands are read from LDS or global memory with the
+// strides that make the transposes of the backward pass free.
+#include "dev.hpp"
+
+namespace mlm {
+
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int NP = 5057;
+constexpr int OW1 = 0, OB1 = 768, OW2 = 832, OB2 = 4928, OW3 = 4992, OB3 = 5056;
+constexpr int MB = 128;   // samples per workgroup (4 wavefronts x 32)
+
+// float -> bf16, round to nearest even (finite inputs)
+__device__ inline uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// C (32 x 32 tile) += A (32 x K) B (K x 32); A(m, k) = a[m * sam + k * sak],
+// B(k, n) = b[k * sbk + n * sbn] (bf16); K a multiple of 8.  Operand layout
+// of the instruction: lane l holds A(l % 32, 4 (l / 32) + t) and
+// B(4 (l / 32) + t, l % 32), t < 4.
+__device__ inline f32x16 tile_mma(const uint16_t *a, int sam, int sak, const uint16_t *b, int sbk, int sbn, int K,
+                                  f32x16 acc, int lane)
+{
+    const int r = lane & 31, h = (lane >> 5) * 4;
+    for (int k0 = 0; k0 < K; k0 += 8) {
+        bf16x4 av, bv;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            av[t] = (short)a[r * sam + (k0 + h + t) * sak];
+            bv[t] = (short)b[(k0 + h + t) * sbk + r * sbn];
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// row and column of accumulator element j of lane `lane` in a 32 x 32 tile
+__device__ inline int acc_row(int j, int lane) { return 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3); }
+__device__ inline int acc_col(int lane) { return lane & 31; }
+
+struct WaveLds {
+    uint16_t x[32 * 16];     // inputs, 12 features + 4 zero columns
+    uint16_t h1[32 * 64];    // layer-1 activations, bf16 part
+    uint16_t h1lo[32 * 64];  // and the bf16 residual: h1 + h1lo carries 16 bits
+    float h2[32 * 64];       // layer-2 activations
+    uint16_t d2[32 * 64];    // gradient at layer-2 pre-activations
+    uint16_t d1[32 * 64];    // gradient at layer-1 pre-activations
+    float z[32], dz[32];
+};
+
+// forward pass of the wavefront's 32 samples [s0, s0 + 32) (rows past n
+// are zero); W1b is [16][64] (rows 12..15 zero), W2b [64][64], bf16
+__device__ inline void forward(const float *__restrict__ feats, int64_t s0, int64_t n, const uint16_t *__restrict__ W1b,
+                               const uint16_t *__restrict__ W2b, const float *__restrict__ P, WaveLds &L, int lane)
+{
+    for (int e = lane; e < 32 * 16; e += 64) {
+        const int m = e >> 4, k = e & 15;
+        const int64_t s = s0 + m;
+        L.x[e] = (k < 12 && s < n) ? f2bf(feats[s * 12 + k]) : (uint16_t)0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int nh = 0; nh < 2; ++nh) {
+        f32x16 acc = {};
+        acc = tile_mma(L.x, 16, 1, W1b + nh * 32, 64, 1, 16, acc, lane);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int m = acc_row(j, lane), c = nh * 32 + acc_col(lane);
+            const float h = fmaxf(acc[j] + P[OB1 + c], 0.0f);
+            const uint16_t hi = f2bf(h);
+            L.h1[m * 64 + c] = hi;
+            L.h1lo[m * 64 + c] = f2bf(h - bf2f(hi));
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int nh = 0; nh < 2; ++nh) {
+        f32x16 acc = {};
+        acc = tile_mma(L.h1, 64, 1, W2b + nh * 32, 64, 1, 64, acc, lane);
+        acc = tile_mma(L.h1lo, 64, 1, W2b + nh * 32, 64, 1, 64, acc, lane);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int m = acc_row(j, lane), c = nh * 32 + acc_col(lane);
+            L.h2[m * 64 + c] = fmaxf(acc[j] + P[OB2 + c], 0.0f);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < 32) {
+        float z = P[OB3];
+        for (int c = 0; c < 64; ++c) z += L.h2[lane * 64 + c] * bf2f(f2bf(P[OW3 + c]));
+        L.z[lane] = z;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(256) void k_mlp_predict(const float *__restrict__ feats, int64_t n,
+                                                     const uint16_t *__restrict__ W1b, const uint16_t *__restrict__ W2b,
+                                                     const float *__restrict__ P, float *__restrict__ logits)
+{
+    __shared__ WaveLds lds[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t s0 = (int64_t)blockIdx.x * MB + wave * 32;
+    forward(feats, s0, n, W1b, W2b, P, lds[wave], lane);
+    if (lane < 32 && s0 + lane < n) logits[s0 + lane] = lds[wave].z[lane];
+}
+
+__device__ inline float softplus(float x) { return x > 0.0f ? x + log1pf(expf(-x)) : log1pf(expf(x)); }
+
+// forward and backward of samples idx[s] (s in [0, n)); gradients (FP32)
+// and the loss sum are added to grad[0 .. NP] (grad[NP] = loss); the loss is
+// divided by `norm` (the batch size)
+__global__ __launch_bounds__(256) void k_mlp_train(const float *__restrict__ feats_all, const uint8_t *__restrict__ y_all,
+                                                   const int64_t *__restrict__ idx, int64_t n,
+                                                   const uint16_t *__restrict__ W1b,
+                                                   const uint16_t *__restrict__ W2b, const float *__restrict__ P,
+                                                   float pos_weight, float norm, float *__restrict__ grad,
+                                                   float *__restrict__ xbuf)
+{
+    __shared__ WaveLds lds[4];
+    __shared__ float g[NP + 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int t = threadIdx.x; t <= NP; t += blockDim.x) g[t] = 0.0f;
+    WaveLds &L = lds[wave];
+    const int64_t s0 = (int64_t)blockIdx.x * MB + wave * 32;
+    // gather this wavefront's samples into a contiguous staging area
+    float *xs = xbuf + ((int64_t)blockIdx.x * MB + wave * 32) * 12;
+    for (int e = lane; e < 32 * 12; e += 64) {
+        const int64_t s = s0 + e / 12;
+        xs[e] = s < n ? feats_all[idx[s] * 12 + e % 12] : 0.0f;
+    }
+    __threadfence_block();
+    __syncthreads();
+    forward(xbuf + (int64_t)blockIdx.x * MB * 12, wave * 32, MB, W1b, W2b, P, L, lane);
+    // loss and dL/dz
+    if (lane < 32) {
+        const int64_t s = s0 + lane;
+        float dz = 0.0f, l = 0.0f;
+        if (s < n) {
+            const float z = L.z[lane], y = (float)y_all[idx[s]];
+            const float sg = 1.0f / (1.0f + expf(-z));
+            l = pos_weight * y * softplus(-z) + (1.0f - y) * softplus(z);
+            dz = (pos_weight * y * (sg - 1.0f) + (1.0f - y) * sg) / norm;
+        }
+        L.dz[lane] = dz;
+        atomicAdd(&g[NP], l / norm);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // layer 3: dW3, db3; gradient at layer-2 pre-activations
+    {
+        const int c = lane;   // unit 0..63
+        const float w3 = bf2f(f2bf(P[OW3 + c]));
+        float gw = 0.0f, gb = 0.0f;
+        for (int m = 0; m < 32; ++m) {
+            const float h = L.h2[m * 64 + c], dz = L.dz[m];
+            gw += dz * h;
+            const float d = h > 0.0f ? dz * w3 : 0.0f;
+            gb += d;
+            L.d2[m * 64 + c] = f2bf(d);
+        }
+        atomicAdd(&g[OW3 + c], gw);
+        atomicAdd(&g[OB2 + c], gb);
+        if (lane == 0) {
+            float s = 0.0f;
+            for (int m = 0; m < 32; ++m) s += L.dz[m];
+            atomicAdd(&g[OB3], s);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // dW2 (64 x 64) = h1^T d2: A(i, m) = h1[m][i], B(m, j) = d2[m][j]
+    for (int ih = 0; ih < 2; ++ih)
+        for (int jh = 0; jh < 2; ++jh) {
+            f32x16 acc = {};
+            acc = tile_mma(L.h1 + ih * 32, 1, 64, L.d2 + jh * 32, 64, 1, 32, acc, lane);
+            acc = tile_mma(L.h1lo + ih * 32, 1, 64, L.d2 + jh * 32, 64, 1, 32, acc, lane);
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                atomicAdd(&g[OW2 + (ih * 32 + acc_row(j, lane)) * 64 + jh * 32 + acc_col(lane)], acc[j]);
+        }
+    // gradient at layer-1 pre-activations: (d2 W2^T) masked; A(m, j) = d2[m][j], B(j, i) = W2[i][j]
+    for (int ih = 0; ih < 2; ++ih) {
+        f32x16 acc = {};
+        acc = tile_mma(L.d2, 64, 1, W2b + ih * 32 * 64, 1, 64, 64, acc, lane);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int m = acc_row(j, lane), c = ih * 32 + acc_col(lane);
+            const float d = L.h1[m * 64 + c] != 0 ? acc[j] : 0.0f;   // relu'(pre) = [h1 > 0]
+            L.d1[m * 64 + c] = f2bf(d);
+            atomicAdd(&g[OB1 + c], d);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // dW1 (16 x 64, rows 12.. zero) = x^T d1: A(k, m) = x[m][k] (rows >= 16 read as zero via x's padding)
+    for (int jh = 0; jh < 2; ++jh) {
+        f32x16 acc = {};
+        {
+            const int r = lane & 31, h = (lane >> 5) * 4;
+            for (int k0 = 0; k0 < 32; k0 += 8) {
+                bf16x4 av, bv;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    av[t] = r < 16 ? (short)L.x[(k0 + h + t) * 16 + r] : (short)0;
+                    bv[t] = (short)L.d1[(k0 + h + t) * 64 + jh * 32 + r];
+                }
+                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc, 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int k = acc_row(j, lane);
+            if (k < 12) atomicAdd(&g[OW1 + k * 64 + jh * 32 + acc_col(lane)], acc[j]);
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t <= NP; t += blockDim.x)
+        if (g[t] != 0.0f) atomicAdd(grad + t, g[t]);
+}
+
+// bf16 copies of the weights in the layouts the kernels read
+__global__ void k_mlp_pack(const float *__restrict__ P, uint16_t *__restrict__ W1b, uint16_t *__restrict__ W2b)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < 16 * 64) W1b[t] = t < 12 * 64 ? f2bf(P[OW1 + t]) : (uint16_t)0;
+    if (t < 64 * 64) W2b[t] = f2bf(P[OW2 + t]);
+}
+
+// Adam step (bias-corrected) on the FP32 master weights; clears the gradient
+__global__ void k_adam(float *__restrict__ P, float *__restrict__ M, float *__restrict__ V, float *__restrict__ grad,
+                       float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= NP) return;
+    const float gv = grad[t];
+    const float m = b1 * M[t] + (1.0f - b1) * gv, v = b2 * V[t] + (1.0f - b2) * gv * gv;
+    M[t] = m;
+    V[t] = v;
+    P[t] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+    grad[t] = 0.0f;
+}
+
+__global__ void k_zero_f32(float *p, int64_t n)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0.0f;
+}
+
+}  // namespace
+
+// host launchers (device pointers throughout)
+void mlp_pack(const float *P, uint16_t *W1b, uint16_t *W2b, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mlp_pack, dim3(16), dim3(256), 0, st, P, W1b, W2b);
+}
+
+void mlp_predict(const float *feats, int64_t n, const uint16_t *W1b, const uint16_t *W2b, const float *P,
+                 float *logits, hipStream_t st)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_mlp_predict, dim3((unsigned)((n + MB - 1) / MB)), dim3(256), 0, st, feats, n, W1b, W2b, P,
+                           logits);
+}
+
+void mlp_train_batch(const float *feats, const uint8_t *y, const int64_t *idx, int64_t n, const uint16_t *W1b,
+                     const uint16_t *W2b, const float *P, float pos_weight, float *grad, float *xbuf, hipStream_t st)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_mlp_train, dim3((unsigned)((n + MB - 1) / MB)), dim3(256), 0, st, feats, y, idx, n, W1b,
+                           W2b, P, pos_weight, (float)n, grad, xbuf);
+}
+
+void mlp_adam(float *P, float *M, float *V, float *grad, float lr, int64_t step, hipStream_t st)
+{
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.0f - std::pow(b1, (float)step), c2 = 1.0f - std::pow(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3((NP + 255) / 256), dim3(256), 0, st, P, M, V, grad, lr, b1, b2, 1e-8f, c1, c2);
+}
+
+void mlp_zero(float *p, int64_t n, hipStream_t st)
+{
+    if (n > 0) hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
+}
+
+}  // namespace mlm

@@ -1,0 +1,474 @@
+// Cell refinement and the network that predicts it.
+//
+// The paper apportions each ray-grid cell as two triangles (sec. 3.2); where
+// the mapping is strongly curved (next to a star, across a caustic) that
+// linear interpolation is coarse.  Plain refinement: a (sub)cell is refined
+// if its mapped ears disagree in orientation (a critical curve crosses it) or
+// if splitting it 2 x 2 changes its in-map deposits by more than tau times
+// its image area (L1 over pixels); a refined cell is replaced by its four
+// children, which are tested again down to `max_depth` levels; cells whose
+// triangles span more than `window` pixels are left alone.  The map changes
+// by (deposits of the leaves - deposits of the cell).
+//
+// The learned variant runs the test only on the cells a small network
+// (12 -> 64 -> 64 -> 1, BF16 weights, FP32 accumulation on the matrix cores)
+// flags from each cell's mapped corners and ear signs, plus every folded cell.
+#include <algorithm>
+#include <vector>
+
+#include "shoot_dev.hpp"
+
+namespace mlm {
+
+namespace {
+
+constexpr int RBLK = 64;
+
+__device__ inline double sgn(double x) { return (double)((x > 0.0) - (x < 0.0)); }
+
+// twice the signed area of (a, b, c), evaluated as written
+__device__ inline double area2(double ua, double va, double ub, double vb, double uc, double vc)
+{
+#pragma clang fp contract(off)
+    return (ub - ua) * (vc - va) - (uc - ua) * (vb - va);
+}
+
+// part of polygon (xs, ys) with s (coord - c) >= 0, coord = x (axis 0) or y
+__device__ inline int clip_half(const double *xs, const double *ys, int n, int axis, double c, double s,
+                                double *ox, double *oy)
+{
+    int m = 0;
+    for (int k = 0; k < n; ++k) {
+        const int k1 = k + 1 == n ? 0 : k + 1;
+        const double a = s * ((axis ? ys[k] : xs[k]) - c), b = s * ((axis ? ys[k1] : xs[k1]) - c);
+        if (a >= 0.0) {
+            ox[m] = xs[k];
+            oy[m] = ys[k];
+            ++m;
+        }
+        if ((a >= 0.0) != (b >= 0.0)) {
+            const double t = a / (a - b);
+            ox[m] = xs[k] + t * (xs[k1] - xs[k]);
+            oy[m] = ys[k] + t * (ys[k1] - ys[k]);
+            ++m;
+        }
+    }
+    return m;
+}
+
+// signed area of triangle (u, v) inside pixel (i, j): clipped by the
+// pixel's four sides in coordinates local to its corner, then shoelace
+__device__ inline double tri_pixel_area(const double *u, const double *v, int64_t i, int64_t j)
+{
+    double px[8], py[8], qx[8], qy[8];
+    for (int k = 0; k < 3; ++k) {
+        px[k] = u[k] - (double)i;
+        py[k] = v[k] - (double)j;
+    }
+    int n = clip_half(px, py, 3, 0, 0.0, 1.0, qx, qy);
+    if (n < 3) return 0.0;
+    n = clip_half(qx, qy, n, 0, 1.0, -1.0, px, py);
+    if (n < 3) return 0.0;
+    n = clip_half(px, py, n, 1, 0.0, 1.0, qx, qy);
+    if (n < 3) return 0.0;
+    n = clip_half(qx, qy, n, 1, 1.0, -1.0, px, py);
+    if (n < 3) return 0.0;
+    double s = 0.0;
+    for (int k = 0; k < n; ++k) {
+        const int k1 = k + 1 == n ? 0 : k + 1;
+        s += px[k] * py[k1] - px[k1] * py[k];
+    }
+    return 0.5 * s;
+}
+
+// deposit (magnification units) of a triangle of weight w (image area over
+// pixel area) into pixel (i, j)
+__device__ inline double tri_dep(double w, const double *u, const double *v, int64_t i, int64_t j)
+{
+    const double S = 0.5 * area2(u[0], v[0], u[1], v[1], u[2], v[2]);
+    if (!(S != 0.0) || !isfinite(S)) return 0.0;
+    const double a = tri_pixel_area(u, v, i, j);
+    return a == 0.0 ? 0.0 : w * (a / S);
+}
+
+// 12 features of a mapped cell (corners 00, 10, 11, 01 in pixel units):
+// sign(d) log(1 + |d|) of the corners' offsets from the corner of the pixel
+// holding their mean, then the signs of the mapped ears at the corners
+__device__ inline void cell_features(const double *u4, const double *v4, float *f)
+{
+    const double cu = floor(0.25 * (u4[0] + u4[1] + u4[2] + u4[3]));
+    const double cv = floor(0.25 * (v4[0] + v4[1] + v4[2] + v4[3]));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double du = u4[k] - cu, dv = v4[k] - cv;
+        f[2 * k] = (float)(sgn(du) * log1p(fabs(du)));
+        f[2 * k + 1] = (float)(sgn(dv) * log1p(fabs(dv)));
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int p = (k + 3) & 3, q = (k + 1) & 3;
+        f[8 + k] = (float)sgn(area2(u4[k], v4[k], u4[q], v4[q], u4[p], v4[p]));
+    }
+}
+
+__device__ inline bool folded(const float *f) { return !(f[8] == f[9] && f[9] == f[10] && f[10] == f[11]); }
+
+struct RefineArgs {
+    double x0, y0, d1, d2;
+    LensConst lc;
+    MapGeom g;
+    LevelRanges lr;
+    int nlevels, L0_exp, p;
+    double L0;
+    const uint64_t *code;
+    const int32_t *leaf, *node_leaf;
+    const LeafInfo *leaves;
+    const double4 *near;
+    const double2 *deriv;
+    double tau;
+    int max_depth, window;
+};
+
+// source position (pixel units) of image point (x0 + A d1, y0 + B d2)
+__device__ inline void shoot_uv(const RefineArgs &ra, double A, double B, double &u, double &v)
+{
+    double x, y;
+    {
+#pragma clang fp contract(off)
+        x = ra.x0 + A * ra.d1;
+        y = ra.y0 + B * ra.d2;
+    }
+    const int64_t lf = find_leaf(x, y, ra.lr, ra.nlevels, ra.L0, ra.L0_exp, ra.code, ra.leaf, ra.node_leaf);
+    if (lf < 0) {
+        u = v = nan("");
+        return;
+    }
+    const LeafInfo li = ra.leaves[lf];
+    double ax, ay;
+    leaf_alpha<double>(x - li.cx, y - li.cy, li, ra.near + li.near_off, ra.deriv + lf * ra.p, ra.p, ax, ay);
+    double w1, w2;
+    double2 uv;
+    finish_vertex(ra.lc, ra.g, x, y, ax, ay, w1, w2, uv);
+    u = uv.x;
+    v = uv.y;
+}
+
+// deposits of a (sub)cell's two triangles, times `sign`, into the map
+__device__ inline void add_cell(const RefineArgs &ra, double *map, double w, const double *u4, const double *v4,
+                                double sign)
+{
+    const int t[2][3] = {{0, 1, 2}, {0, 2, 3}};
+    for (int k = 0; k < 2; ++k) {
+        double tu[3], tv[3];
+        bool ok = true;
+        for (int m = 0; m < 3; ++m) {
+            tu[m] = u4[t[k][m]];
+            tv[m] = v4[t[k][m]];
+            ok = ok && isfinite(tu[m]) && isfinite(tv[m]);
+        }
+        if (!ok) continue;
+        const int64_t i0 = max((int64_t)floor(fmin(tu[0], fmin(tu[1], tu[2]))), (int64_t)0);
+        const int64_t i1 = min((int64_t)floor(fmax(tu[0], fmax(tu[1], tu[2]))), (int64_t)ra.g.n1 - 1);
+        const int64_t j0 = max((int64_t)floor(fmin(tv[0], fmin(tv[1], tv[2]))), (int64_t)0);
+        const int64_t j1 = min((int64_t)floor(fmax(tv[0], fmax(tv[1], tv[2]))), (int64_t)ra.g.n2 - 1);
+        for (int64_t j = j0; j <= j1; ++j)
+            for (int64_t i = i0; i <= i1; ++i) {
+                const double d = tri_dep(w, tu, tv, i, j);
+                if (d != 0.0) unsafeAtomicAdd(map + j * (int64_t)ra.g.n1 + i, sign * d);
+            }
+    }
+}
+
+struct SubCell {
+    double A0, B0, h;
+    int d;
+    double u[4], v[4];
+};
+
+constexpr int STACK = 16;   // depth-first: at most 1 + 3 max_depth pending subcells (max_depth <= 4)
+
+// The test of one subcell; fills its 3 x 3 grid of source points (corners
+// from the subcell, five new rays) and returns whether it is refined.
+__device__ inline bool refine_test(const RefineArgs &ra, const SubCell &c, double (&gu)[3][3], double (&gv)[3][3],
+                                   int &too_large)
+{
+    gu[0][0] = c.u[0]; gv[0][0] = c.v[0];
+    gu[0][2] = c.u[1]; gv[0][2] = c.v[1];
+    gu[2][2] = c.u[2]; gv[2][2] = c.v[2];
+    gu[2][0] = c.u[3]; gv[2][0] = c.v[3];
+    const double hh = 0.5 * c.h;
+    shoot_uv(ra, c.A0 + hh, c.B0, gu[0][1], gv[0][1]);
+    shoot_uv(ra, c.A0, c.B0 + hh, gu[1][0], gv[1][0]);
+    shoot_uv(ra, c.A0 + hh, c.B0 + hh, gu[1][1], gv[1][1]);
+    shoot_uv(ra, c.A0 + c.h, c.B0 + hh, gu[1][2], gv[1][2]);
+    shoot_uv(ra, c.A0 + hh, c.B0 + c.h, gu[2][1], gv[2][1]);
+    double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
+    bool finite = true;
+    for (int r = 0; r < 3; ++r)
+        for (int s = 0; s < 3; ++s) {
+            finite = finite && isfinite(gu[r][s]) && isfinite(gv[r][s]);
+            umin = fmin(umin, gu[r][s]);
+            umax = fmax(umax, gu[r][s]);
+            vmin = fmin(vmin, gv[r][s]);
+            vmax = fmax(vmax, gv[r][s]);
+        }
+    if (!finite || !(umax - umin <= ra.window && vmax - vmin <= ra.window)) {
+        too_large = 1;
+        return false;
+    }
+    float f[12];
+    cell_features(c.u, c.v, f);
+    if (folded(f)) return true;
+    const double w = ra.g.tri_weight * c.h * c.h;   // parent triangle weight
+    const int64_t i0 = max((int64_t)floor(umin), (int64_t)0), i1 = min((int64_t)floor(umax), (int64_t)ra.g.n1 - 1);
+    const int64_t j0 = max((int64_t)floor(vmin), (int64_t)0), j1 = min((int64_t)floor(vmax), (int64_t)ra.g.n2 - 1);
+    const double pu[2][3] = {{c.u[0], c.u[1], c.u[2]}, {c.u[0], c.u[2], c.u[3]}};
+    const double pv[2][3] = {{c.v[0], c.v[1], c.v[2]}, {c.v[0], c.v[2], c.v[3]}};
+    double l1 = 0.0;
+    for (int64_t j = j0; j <= j1; ++j)
+        for (int64_t i = i0; i <= i1; ++i) {
+            double diff = -tri_dep(w, pu[0], pv[0], i, j) - tri_dep(w, pu[1], pv[1], i, j);
+            for (int r = 0; r < 2; ++r)
+                for (int s = 0; s < 2; ++s) {
+                    const double cu[2][3] = {{gu[r][s], gu[r][s + 1], gu[r + 1][s + 1]},
+                                             {gu[r][s], gu[r + 1][s + 1], gu[r + 1][s]}};
+                    const double cv[2][3] = {{gv[r][s], gv[r][s + 1], gv[r + 1][s + 1]},
+                                             {gv[r][s], gv[r + 1][s + 1], gv[r + 1][s]}};
+                    diff += tri_dep(0.25 * w, cu[0], cv[0], i, j) + tri_dep(0.25 * w, cu[1], cv[1], i, j);
+                }
+            l1 += fabs(diff);
+        }
+    return l1 > ra.tau * 2.0 * w;
+}
+
+// Refinement of candidate cells (global grid indices ca, cb; corners from
+// the strip's vertices, rows from vb0): label[k] = 1 if the cell itself is
+// refined; the map receives (leaves - cell) deposits when `map` is given.
+// stats: [0] tested subcells, [1] refined subcells, [2] too large.
+__global__ __launch_bounds__(RBLK) void k_refine(RefineArgs ra, int64_t ncand, const int64_t *__restrict__ cand,
+                                                 int64_t nr1, int64_t vb0, const double2 *__restrict__ verts,
+                                                 uint8_t *__restrict__ label, double *__restrict__ map,
+                                                 unsigned long long *__restrict__ stats)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ncand) return;
+    const int64_t cell = cand[k];   // a + (nr1 - 1) b
+    const int64_t a = cell % (nr1 - 1), b = cell / (nr1 - 1);
+    SubCell st[STACK];
+    int top = 0;
+    {
+        SubCell &c = st[top++];
+        c.A0 = (double)a;
+        c.B0 = (double)b;
+        c.h = 1.0;
+        c.d = 0;
+        const double2 *r0 = verts + (b - vb0) * nr1, *r1 = r0 + nr1;
+        const double2 q[4] = {r0[a], r0[a + 1], r1[a + 1], r1[a]};
+        for (int m = 0; m < 4; ++m) {
+            c.u[m] = q[m].x;
+            c.v[m] = q[m].y;
+        }
+    }
+    unsigned long long n_test = 0, n_ref = 0, n_large = 0;
+    uint8_t lab = 0;
+    while (top > 0) {
+        const SubCell c = st[--top];
+        double gu[3][3], gv[3][3];
+        int large = 0;
+        ++n_test;
+        const bool refine = refine_test(ra, c, gu, gv, large);
+        n_large += large;
+        if (c.d == 0) lab = refine ? 1 : 0;
+        if (!refine) continue;
+        ++n_ref;
+        const double w = ra.g.tri_weight * c.h * c.h;
+        if (map) add_cell(ra, map, w, c.u, c.v, -1.0);
+        const double hh = 0.5 * c.h;
+        for (int r = 0; r < 2; ++r)
+            for (int s = 0; s < 2; ++s) {
+                SubCell ch;
+                ch.A0 = c.A0 + s * hh;
+                ch.B0 = c.B0 + r * hh;
+                ch.h = hh;
+                ch.d = c.d + 1;
+                const double cu[4] = {gu[r][s], gu[r][s + 1], gu[r + 1][s + 1], gu[r + 1][s]};
+                const double cv[4] = {gv[r][s], gv[r][s + 1], gv[r + 1][s + 1], gv[r + 1][s]};
+                for (int m = 0; m < 4; ++m) {
+                    ch.u[m] = cu[m];
+                    ch.v[m] = cv[m];
+                }
+                if (map) add_cell(ra, map, 0.25 * w, ch.u, ch.v, +1.0);   // a refined child takes it back itself
+                if (ch.d < ra.max_depth && top < STACK) st[top++] = ch;
+            }
+    }
+    label[k] = lab;
+    if (stats) {
+        atomicAdd(stats, n_test);
+        atomicAdd(stats + 1, n_ref);
+        atomicAdd(stats + 2, n_large);
+    }
+}
+
+// features of every cell of a strip (cells [cb0, cb1) of the grid)
+__global__ __launch_bounds__(256) void k_cell_features(int64_t nr1, int64_t cb0, int64_t ncells, int64_t vb0,
+                                                       const double2 *__restrict__ verts, float *__restrict__ feats)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ncells) return;
+    const int64_t a = t % (nr1 - 1), b = cb0 + t / (nr1 - 1);
+    const double2 *r0 = verts + (b - vb0) * nr1, *r1 = r0 + nr1;
+    const double2 q[4] = {r0[a], r0[a + 1], r1[a + 1], r1[a]};
+    double u4[4], v4[4];
+    for (int m = 0; m < 4; ++m) {
+        u4[m] = q[m].x;
+        v4[m] = q[m].y;
+    }
+    float f[12];
+    if (isfinite(u4[0]) && isfinite(u4[1]) && isfinite(u4[2]) && isfinite(u4[3]) && isfinite(v4[0]) &&
+        isfinite(v4[1]) && isfinite(v4[2]) && isfinite(v4[3]))
+        cell_features(u4, v4, f);
+    else
+        for (int m = 0; m < 12; ++m) f[m] = 0.0f;
+    for (int m = 0; m < 12; ++m) feats[t * 12 + m] = f[m];
+}
+
+// features of arbitrary cells, corners shot on the spot
+__global__ __launch_bounds__(RBLK) void k_sample_features(RefineArgs ra, int64_t n, const int64_t *__restrict__ ab,
+                                                          float *__restrict__ feats)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const double A = (double)ab[2 * t], B = (double)ab[2 * t + 1];
+    double u4[4], v4[4];
+    shoot_uv(ra, A, B, u4[0], v4[0]);
+    shoot_uv(ra, A + 1.0, B, u4[1], v4[1]);
+    shoot_uv(ra, A + 1.0, B + 1.0, u4[2], v4[2]);
+    shoot_uv(ra, A, B + 1.0, u4[3], v4[3]);
+    float f[12];
+    cell_features(u4, v4, f);
+    for (int m = 0; m < 12; ++m) feats[t * 12 + m] = isfinite(f[m]) ? f[m] : 0.0f;
+}
+
+// the refinement test at depth 0 of arbitrary cells (labels only)
+__global__ __launch_bounds__(RBLK) void k_sample_labels(RefineArgs ra, int64_t n, const int64_t *__restrict__ ab,
+                                                        uint8_t *__restrict__ label)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    SubCell c;
+    c.A0 = (double)ab[2 * t];
+    c.B0 = (double)ab[2 * t + 1];
+    c.h = 1.0;
+    c.d = 0;
+    shoot_uv(ra, c.A0, c.B0, c.u[0], c.v[0]);
+    shoot_uv(ra, c.A0 + 1.0, c.B0, c.u[1], c.v[1]);
+    shoot_uv(ra, c.A0 + 1.0, c.B0 + 1.0, c.u[2], c.v[2]);
+    shoot_uv(ra, c.A0, c.B0 + 1.0, c.u[3], c.v[3]);
+    double gu[3][3], gv[3][3];
+    int large = 0;
+    label[t] = refine_test(ra, c, gu, gv, large) ? 1 : 0;
+}
+
+// candidates of the learned variant: flag[t] = network says refine, or the
+// cell is folded; cells whose corners are not finite are never candidates
+__global__ __launch_bounds__(256) void k_select(int64_t n, const float *__restrict__ feats,
+                                                const float *__restrict__ logits, float thr, int32_t *__restrict__ flag)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const float *f = feats + t * 12;
+    flag[t] = (logits[t] > thr || folded(f)) ? 1 : 0;
+}
+
+// cand[pos[t]] = base + t for flagged t (pos: exclusive scan of the flags,
+// pos[t + 1] - pos[t] = flag[t]); with flag == NULL every t
+__global__ __launch_bounds__(256) void k_compact(int64_t n, const int32_t *__restrict__ flag,
+                                                 const int64_t *__restrict__ pos, int64_t base,
+                                                 int64_t *__restrict__ cand)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    if (!flag) cand[t] = base + t;
+    else if (flag[t]) cand[pos[t]] = base + t;
+}
+
+}  // namespace
+
+RefineArgs make_refine_args(const Tree &T, const Region &R, const LensConst &lc, const MapGeom &g, double tau,
+                            int max_depth, int window)
+{
+    RefineArgs ra{};
+    ra.x0 = R.x0;
+    ra.y0 = R.y0;
+    ra.d1 = R.d1;
+    ra.d2 = R.d2;
+    ra.lc = lc;
+    ra.g = g;
+    for (int l = 0; l < T.nlevels; ++l) {
+        ra.lr.lo[l] = T.level_lo[l];
+        ra.lr.hi[l] = T.level_hi[l];
+    }
+    ra.nlevels = T.nlevels;
+    ra.L0_exp = T.L0_exp;
+    ra.p = T.p;
+    ra.L0 = T.L0;
+    ra.code = T.code;
+    ra.leaf = T.leaf;
+    ra.node_leaf = T.node_leaf;
+    ra.leaves = T.leaves;
+    ra.near = T.near;
+    ra.deriv = T.deriv;
+    ra.tau = tau;
+    ra.max_depth = max_depth;
+    ra.window = window;
+    return ra;
+}
+
+void launch_refine(const Tree &T, const Region &R, const LensConst &lc, const MapGeom &g, double tau, int depth,
+                   int window, int64_t ncand, const int64_t *cand, int64_t nr1, int64_t vb0, const double2 *verts,
+                   uint8_t *label, double *map, unsigned long long *stats, hipStream_t st)
+{
+    if (ncand <= 0) return;
+    const RefineArgs ra = make_refine_args(T, R, lc, g, tau, depth, window);
+    hipLaunchKernelGGL(k_refine, dim3((unsigned)((ncand + RBLK - 1) / RBLK)), dim3(RBLK), 0, st, ra, ncand, cand, nr1,
+                       vb0, verts, label, map, stats);
+}
+
+void launch_cell_features(int64_t nr1, int64_t cb0, int64_t ncells, int64_t vb0, const double2 *verts, float *feats,
+                          hipStream_t st)
+{
+    if (ncells > 0)
+        hipLaunchKernelGGL(k_cell_features, dim3((unsigned)((ncells + 255) / 256)), dim3(256), 0, st, nr1, cb0, ncells,
+                           vb0, verts, feats);
+}
+
+void launch_sample_features(const Tree &T, const Region &R, const LensConst &lc, const MapGeom &g, int64_t n,
+                            const int64_t *ab, float *feats, hipStream_t st)
+{
+    if (n <= 0) return;
+    const RefineArgs ra = make_refine_args(T, R, lc, g, 0.0, 1, 1);
+    hipLaunchKernelGGL(k_sample_features, dim3((unsigned)((n + RBLK - 1) / RBLK)), dim3(RBLK), 0, st, ra, n, ab,
+                       feats);
+}
+
+void launch_sample_labels(const Tree &T, const Region &R, const LensConst &lc, const MapGeom &g, double tau,
+                          int window, int64_t n, const int64_t *ab, uint8_t *label, hipStream_t st)
+{
+    if (n <= 0) return;
+    const RefineArgs ra = make_refine_args(T, R, lc, g, tau, 1, window);
+    hipLaunchKernelGGL(k_sample_labels, dim3((unsigned)((n + RBLK - 1) / RBLK)), dim3(RBLK), 0, st, ra, n, ab, label);
+}
+
+void launch_select(int64_t n, const float *feats, const float *logits, float thr, int32_t *flag, hipStream_t st)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_select, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, feats, logits, thr, flag);
+}
+
+void launch_compact(int64_t n, const int32_t *flag, const int64_t *pos, int64_t base, int64_t *cand, hipStream_t st)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_compact, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, flag, pos, base, cand);
+}
+
+}  // namespace mlm

@@ -9,7 +9,7 @@
 // wavefront-uniform and are read through the scalar cache into SGPRs.
 #include <algorithm>
 
-#include "dev.hpp"
+#include "shoot_dev.hpp"
 
 namespace mlm {
 
@@ -19,22 +19,6 @@ namespace {
 
 constexpr int BLK = 256;
 inline unsigned nblocks(int64_t n, int b = BLK) { return (unsigned)((n + b - 1) / b); }
-
-// grid coordinate of vertex a: x0 + a d, evaluated as written (no fused multiply-add)
-__device__ inline double grid_pos(double x0, double d, int64_t a)
-{
-#pragma clang fp contract(off)
-    return x0 + (double)a * d;
-}
-
-// square index of t at level lev (root [-L0, L0)), clamped like the star keys
-__device__ inline int64_t level_cell(double t, double L0, double scale_lev, int lev)
-{
-    double u = floor((t + L0) * scale_lev);
-    double top = (double)((1ll << lev) - 1);
-    u = u < 0.0 ? 0.0 : (u > top ? top : u);
-    return (int64_t)u;
-}
 
 // first a in [lo, hi) whose vertex lies in square index >= target at level lev
 __device__ inline int64_t first_in_cell(double x0, double d, int64_t lo, int64_t hi, double L0, double scale_lev,
@@ -83,52 +67,6 @@ __global__ void k_tile_leaf(int64_t ntiles, int64_t nleaves, const int32_t *__re
     tile_leaf[t] = (int32_t)(upper_bound_i64<int32_t>(tile_off, nleaves, (int32_t)t) - 1);
 }
 
-
-__device__ inline void finish_vertex(const LensConst &lc, const MapGeom &g, double x, double y, double ax,
-                                     double ay, double &w1, double &w2, double2 &uv)
-{
-    // macro model
-    w1 = lc.lam1 * x - ax;
-    w2 = lc.lam2 * y - ay;
-    // compensating sheet: a_s = -k_* z inside R_*, -k_* R_*^2 / conj(z) outside
-    if (lc.sheet) {
-        double r2 = x * x + y * y;
-        double f = (r2 <= lc.r_star2) ? lc.kappa_star : lc.kappa_star * lc.r_star2 / r2;
-        w1 += f * x;
-        w2 += f * y;
-    }
-    uv = make_double2((w1 - g.ylo1) / g.pix1, (w2 - g.ylo2) / g.pix2);
-}
-
-// far-field and near-field deflection at offset (dx, dy) from a leaf's
-// centre, in arithmetic type R; the offsets from the leaf centre and from
-// each near star are formed in FP64 (a ray may pass very close to a star)
-template <class R>
-__device__ inline void leaf_alpha(double dx, double dy, const LeafInfo &li, const double4 *__restrict__ ns,
-                                  const typename Cx<R>::c2 *__restrict__ dv, int p, double &ax_out, double &ay_out)
-{
-    // near field: a_* += m (z - z_i) / |z - z_i|^2
-    R ax = 0, ay = 0;
-    for (int32_t s = 0; s < li.near_cnt; ++s) {
-        const double4 st = ns[s];
-        const R ex = (R)(dx - st.x), ey = (R)(dy - st.y);
-        const R f = qdiv((R)st.z, ex * ex + ey * ey);
-        ax += f * ex;
-        ay += f * ey;
-    }
-    // far field: conj( sum_{l<p} deriv_l zeta^l ), Horner
-    const R zr = (R)(dx * li.invL), zi = (R)(dy * li.invL);
-    R sr = dv[p - 1].x, si = dv[p - 1].y;
-    for (int l = p - 2; l >= 0; --l) {
-        const typename Cx<R>::c2 c = dv[l];
-        const R nr = sr * zr - si * zi + c.x;
-        const R ni = sr * zi + si * zr + c.y;
-        sr = nr;
-        si = ni;
-    }
-    ax_out = (double)ax + (double)sr;
-    ay_out = (double)ay - (double)si;
-}
 
 // shoot tile t of a map (one 64-lane wavefront per 8 x 8 tile)
 template <class R>
@@ -224,10 +162,6 @@ __global__ __launch_bounds__(256) void k_shoot_direct(ShootArgs sa, LensConst lc
     if (w_out) w_out[v] = make_double2(w1, w2);
 }
 
-struct LevelRanges {
-    int64_t lo[KEY_BITS + 2], hi[KEY_BITS + 2];
-};
-
 // w at arbitrary points: leaf by descending the levels, then as k_shoot
 template <class R>
 __global__ void k_deflect_points(int64_t npts, const double2 *__restrict__ z, LevelRanges lr, int nlevels,
@@ -240,19 +174,7 @@ __global__ void k_deflect_points(int64_t npts, const double2 *__restrict__ z, Le
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= npts) return;
     double x = z[t].x, y = z[t].y;
-    int64_t lf = -1;
-    for (int lev = 0; lev < nlevels && lf < 0; ++lev) {
-        double scale = ldexp(1.0, lev - L0_exp);
-        uint64_t c = morton2((uint32_t)level_cell(x, L0, scale, lev), (uint32_t)level_cell(y, L0, scale, lev));
-        int64_t a = lr.lo[lev], b = lr.hi[lev];
-        while (a < b) {
-            int64_t mid = (a + b) >> 1;
-            if (code[mid] < c) a = mid + 1;
-            else b = mid;
-        }
-        if (a >= lr.hi[lev] || code[a] != c) break;
-        if (leaf[a]) lf = node_leaf[a];
-    }
+    const int64_t lf = find_leaf(x, y, lr, nlevels, L0, L0_exp, code, leaf, node_leaf);
     if (lf < 0) {
         w[t] = make_double2(nan(""), nan(""));
         return;

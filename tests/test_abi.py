@@ -43,7 +43,8 @@ def test_struct_layouts_match_header(mlm):
     structs = {"mlm_lens_params": mlm.LensParams, "mlm_lens_info": mlm.LensInfo,
                "mlm_map_request": mlm.MapRequest, "mlm_region": mlm.Region,
                "mlm_map_stats": mlm.MapStats, "mlm_tree_info": mlm.TreeInfo,
-               "mlm_batch_opts": mlm.BatchOpts, "mlm_batch_stats": mlm.BatchStats}
+               "mlm_batch_opts": mlm.BatchOpts, "mlm_batch_stats": mlm.BatchStats,
+               "mlm_train_opts": mlm.TrainOpts}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mlmap.h"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -69,7 +70,7 @@ def test_struct_layouts_match_header(mlm):
 
 def test_version_and_status_strings(mlm):
     lib = mlm.load()
-    assert lib.mlm_abi_version() == 2
+    assert lib.mlm_abi_version() == 3
     assert lib.mlm_status_str(0) == b"MLM_OK"
     assert lib.mlm_status_str(2) == b"MLM_EDEGENERATE"
     assert lib.mlm_status_str(99) == b"MLM_UNKNOWN"
@@ -79,6 +80,7 @@ def test_request_defaults(mlm):
     r = mlm.make_request()
     assert r.rays_per_pixel == 1.0 and r.flux_fraction == 0.01 and r.leaf_max == 32
     assert r.max_level == 24 and r.eps == 1e-7 and r.row_end == -1
+    assert r.refine == 0 and r.refine_depth == 3 and r.refine_window == 8 and r.refine_tau == 1e-3
     with pytest.raises(TypeError):
         mlm.make_request(bogus=1)
 

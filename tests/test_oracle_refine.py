@@ -61,14 +61,18 @@ def test_cell_features(orc):
     u = rng.normal(size=4) * 3
     v = rng.normal(size=4) * 3
     f = orc.cell_features(u, v)
-    # offsets from the mean: unchanged by a translation (up to its rounding)
+    # offsets from the pixel corner: unchanged by a whole-pixel translation
     np.testing.assert_allclose(orc.cell_features(u + 5.0, v - 7.0)[:8], f[:8], rtol=0, atol=1e-14)
+    # ... but not by a fraction of a pixel (the grid phase shows)
+    assert np.abs(orc.cell_features(u + 0.5, v)[:8:2] - f[:8:2]).max() > 0.1
     # a unit square with positive orientation: ears all +1; mirrored: all -1
-    su, sv = np.array([0, 1, 1, 0.0]), np.array([0, 0, 1, 1.0])
+    su, sv = np.array([0, 1, 1, 0.0]) + 0.25, np.array([0, 0, 1, 1.0]) + 0.25
     assert list(orc.cell_features(su, sv)[8:]) == [1, 1, 1, 1]
     assert list(orc.cell_features(su, -sv)[8:]) == [-1, -1, -1, -1]
-    # offsets are log-compressed: corner 00 of the unit square sits at (-1/2, -1/2)
-    assert abs(orc.cell_features(su, sv)[0] + math.log1p(0.5)) < 1e-15
+    # offsets are log-compressed: the mean (0.75, 0.75) lies in pixel (0, 0),
+    # so corner 11 sits at (1.25, 1.25)
+    ff = orc.cell_features(su, sv)
+    assert abs(ff[4] - math.log1p(1.25)) < 1e-15 and abs(ff[0] - math.log1p(0.25)) < 1e-15
     # a folded cell (corner 11 pulled across the diagonal): ears disagree
     fu, fv = np.array([0, 1, 0.2, 0.0]), np.array([0, 0, 0.2, 1.0])
     e = orc.cell_features(fu, fv)[8:]
