@@ -63,26 +63,31 @@ void table_m2m(int p, std::vector<double2> &out)
     }
 }
 
-// M2L, offset (dx, dy) in squares: z0 = 2(dx + i dy) in half-lengths;
-// c_l = z0^-l [-b_0/l + sum_{k=1}^{p} b_k (-z0)^-k C(l+k-1,k-1)], l >= 1
-void table_m2l(int p, std::vector<double2> &out)
+// The M2L operator factorised: with z0 the source-to-target offset (in
+// half-lengths) and b' = b_k (-z0)^-k,
+//   c_l = z0^-l [ sum_{k>=1} C(l+k-1, k-1) b'_k - b_0 / l ],
+// so every offset shares one real matrix P[l-1][k-1] = C(l+k-1, k-1) and
+// differs only by the diagonal scalings S[off][k] = (-z0)^-k (sources) and
+// T[off][l] = z0^-l (targets).  Tables of 32 entries per offset (p <= 31);
+// P is 32 x 32, zero beyond p.
+void table_m2l_factors(int p, std::vector<double2> &S, std::vector<double2> &T, std::vector<double> &P)
 {
-    int P1 = p + 1;
-    out.assign(49 * P1 * P1, make_double2(0, 0));
+    S.assign(49 * 32, make_double2(0, 0));
+    T.assign(49 * 32, make_double2(0, 0));
+    P.assign(32 * 32, 0.0);
     for (int dy = -3; dy <= 3; ++dy)
         for (int dx = -3; dx <= 3; ++dx) {
             if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
             int off = (dx + 3) + 7 * (dy + 3);
             cld z0(2.0L * dx, 2.0L * dy);
-            cld zi = 1.0L / z0, nzi = -1.0L / z0;
-            for (int l = 1; l <= p; ++l) {
-                cld zl = ipow(zi, l);
-                for (int k = 0; k <= p; ++k) {
-                    cld v = (k == 0) ? -zl / (long double)l : zl * ipow(nzi, k) * binom_ld(l + k - 1, k - 1);
-                    out[(off * P1 + l) * P1 + k] = make_double2((double)v.real(), (double)v.imag());
-                }
+            for (int k = 0; k <= p; ++k) {
+                cld sv = ipow(-1.0L / z0, k), tv = ipow(1.0L / z0, k);
+                S[off * 32 + k] = make_double2((double)sv.real(), (double)sv.imag());
+                T[off * 32 + k] = make_double2((double)tv.real(), (double)tv.imag());
             }
         }
+    for (int l = 1; l <= p; ++l)
+        for (int k = 1; k <= p; ++k) P[(l - 1) * 32 + (k - 1)] = (double)binom_ld(l + k - 1, k - 1);
 }
 
 // L2L, child quadrant (qi, qj): delta = child centre - parent centre in parent
@@ -160,61 +165,145 @@ __global__ void k_upward(int64_t lo, int64_t hi, int lev, int p, double L0, cons
     mult[q * P1 + k] = acc;
 }
 
-// downward pass of one level (>= 2): Taylor coefficient l of each node
+// Matrix-core product of the factorised M2L: Y (32 x 64) = P (32 x 32) B
+// (32 x 64), as 16 x 16 x 4 tiles; lane l holds A(l % 16, l / 16) and
+// B(l / 16, l % 16); its four results are D(4 (l / 16) + i, l % 16) for the
+// FP32 instruction and D(4 i + l / 16, l % 16) for the FP64 one (i < 4).
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ inline f64x4 mma16(double a, double b, f64x4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+__device__ inline f32x4 mma16(float a, float b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+template <class R> struct V4T;
+template <> struct V4T<double> {
+    using t = f64x4;
+    __device__ static int row(int i, int g4) { return 4 * i + g4; }
+};
+template <> struct V4T<float> {
+    using t = f32x4;
+    __device__ static int row(int i, int g4) { return 4 * g4 + i; }
+};
+
+template <class R> struct DownLds {
+    R B[32 * 64];          // scaled source coefficients: row k - 1, columns (2 s, 2 s + 1) = (re, im) of source s
+    R Y[32 * 64];          // P B
+    typename Cx<R>::c2 b0[32];
+    int off[32], src[32];
+};
+
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// downward pass of one level (>= 2), one wavefront per node: L2L from the
+// parent (lane l: coefficient l), M2L from the same-level interaction nodes
+// through the factorised operator (the shared real matrix on the matrix
+// cores, the scalings on the vector units), P2L from the stars of
+// interaction squares inside coarser leaves
 template <class R>
-__global__ void k_downward(int64_t lo, int64_t hi, int lev, int p, double L0, const uint64_t *__restrict__ code,
-                           const int32_t *__restrict__ parent, const IEntry *__restrict__ ilist,
-                           const double *__restrict__ sx, const double *__restrict__ sy,
-                           const double *__restrict__ sm, const typename Cx<R>::c2 *__restrict__ m2l,
-                           const typename Cx<R>::c2 *__restrict__ l2l, const typename Cx<R>::c2 *__restrict__ mult,
-                           typename Cx<R>::c2 *__restrict__ local)
+__global__ __launch_bounds__(256) void k_downward(int64_t lo, int64_t hi, int lev, int p, double L0,
+                                                  const uint64_t *__restrict__ code, const int32_t *__restrict__ parent,
+                                                  const IEntry *__restrict__ ilist, const double *__restrict__ sx,
+                                                  const double *__restrict__ sy, const double *__restrict__ sm,
+                                                  const typename Cx<R>::c2 *__restrict__ Sf,
+                                                  const typename Cx<R>::c2 *__restrict__ Tf, const R *__restrict__ Pm,
+                                                  const typename Cx<R>::c2 *__restrict__ l2l,
+                                                  const typename Cx<R>::c2 *__restrict__ mult,
+                                                  typename Cx<R>::c2 *__restrict__ local)
 {
     using C2 = typename Cx<R>::c2;
+    using V4 = typename V4T<R>::t;
+    __shared__ DownLds<R> lds[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t q = lo + (int64_t)blockIdx.x * 4 + wave;
+    if (q >= hi) return;   // wavefront-uniform: the wavefronts share no barrier
+    DownLds<R> &L = lds[wave];
     const int P1 = p + 1;
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t q = lo + t / P1;
-    int l = (int)(t % P1);
-    if (q >= hi) return;
+    const uint64_t c = code[q];
+    // the node's M2L sources into slots 0 .. ns-1 (lanes 0..26 hold the entries)
+    const IEntry *list = ilist + q * NLIST;
+    IEntry en{-2, 0, 0, 0};
+    if (lane < NLIST) en = list[lane];
+    const uint64_t mask = __ballot(lane < NLIST && en.src >= 0);
+    const int ns = __popcll(mask);
+    const int slot = __popcll(mask & ((1ull << lane) - 1ull));
+    if (lane < NLIST && en.src >= 0) {
+        L.off[slot] = en.off;
+        L.src[slot] = en.src;
+        L.b0[slot] = mult[(int64_t)en.src * P1];
+    }
+    wave_sync();
+    // B: b_k (-z0)^-k for k = 1..p (rows k - 1), zero elsewhere up to the tiles used
+    const int ncol = ((2 * ns + 15) / 16) * 16;
+    for (int e = lane; e < 32 * ncol / 2; e += 64) {
+        const int k1 = e % 32, s2 = e / 32;   // row k1 = k - 1, source s2
+        R re = 0, im = 0;
+        if (s2 < ns && k1 < p) {
+            const C2 b = mult[(int64_t)L.src[s2] * P1 + k1 + 1], f = Sf[L.off[s2] * 32 + k1 + 1];
+            re = b.x * f.x - b.y * f.y;
+            im = b.x * f.y + b.y * f.x;
+        }
+        L.B[k1 * 64 + 2 * s2] = re;
+        L.B[k1 * 64 + 2 * s2 + 1] = im;
+    }
+    wave_sync();
+    // Y = P B on the matrix cores
+    const int mt_n = (p + 15) / 16, kt_n = (p + 3) / 4;
+    const int r = lane & 15, g4 = lane >> 4;
+    for (int mt = 0; mt < mt_n; ++mt)
+        for (int nt = 0; nt < ncol / 16; ++nt) {
+            V4 acc = {};
+            for (int ks = 0; ks < kt_n; ++ks) {
+                const R a = Pm[(mt * 16 + r) * 32 + ks * 4 + g4];
+                const R b = L.B[(ks * 4 + g4) * 64 + nt * 16 + r];
+                acc = mma16(a, b, acc);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) L.Y[(mt * 16 + V4T<R>::row(i, g4)) * 64 + nt * 16 + r] = acc[i];
+        }
+    wave_sync();
+    // coefficient l = lane
+    const int l = lane;
+    if (l > p) return;
     if (l == 0) {
         local[q * P1] = Cx<R>::make(0, 0);   // c_0 only shifts the potential
         return;
     }
-    uint64_t c = code[q];
     C2 acc = Cx<R>::make(0, 0);
     // L2L from the parent (levels 0 and 1 have no far field)
     if (lev >= 3) {
-        int quad = (int)((c & 1ull) | (((c >> 1) & 1ull) << 1));
+        const int quad = (int)((c & 1ull) | (((c >> 1) & 1ull) << 1));
         const C2 *op = l2l + (quad * P1 + l) * P1;
         const C2 *cp = local + (int64_t)parent[q] * P1;
         for (int k = l; k <= p; ++k) {
-            C2 o = op[k], v = cp[k];
+            const C2 o = op[k], v = cp[k];
             acc.x += o.x * v.x - o.y * v.y;
             acc.y += o.x * v.y + o.y * v.x;
         }
     }
-    double cx, cy, L, invL;
-    node_geom(c, lev, L0, cx, cy, L, invL);
-    const IEntry *list = ilist + q * NLIST;
+    // M2L: z0^-l (y_l - b_0 / l) per source
+    const R il = (R)1 / (R)l;
+    for (int s2 = 0; s2 < ns; ++s2) {
+        const C2 t = Tf[L.off[s2] * 32 + l];
+        const R yr = L.Y[(l - 1) * 64 + 2 * s2] - L.b0[s2].x * il;
+        const R yi = L.Y[(l - 1) * 64 + 2 * s2 + 1] - L.b0[s2].y * il;
+        acc.x += t.x * yr - t.y * yi;
+        acc.y += t.x * yi + t.y * yr;
+    }
+    // P2L: c_l += -m_i / (l zeta_i^l)
+    double cx, cy, Lh, invL;
+    node_geom(c, lev, L0, cx, cy, Lh, invL);
     for (int e = 0; e < NLIST; ++e) {
-        IEntry en = list[e];
-        if (en.src >= 0) {
-            // M2L
-            const C2 *op = m2l + (en.off * P1 + l) * P1;
-            const C2 *b = mult + (int64_t)en.src * P1;
-            for (int k = 0; k <= p; ++k) {
-                C2 o = op[k], v = b[k];
-                acc.x += o.x * v.x - o.y * v.y;
-                acc.y += o.x * v.y + o.y * v.x;
-            }
-        } else if (en.src == -1) {
-            // P2L: c_l += -m_i / (l zeta_i^l)
-            for (int32_t s = en.slo; s < en.shi; ++s) {
-                C2 z = Cx<R>::make((R)((sx[s] - cx) * invL), (R)((sy[s] - cy) * invL));
-                C2 w = cpowi(cinv(z), l);
-                R f = -(R)sm[s] / (R)l;
-                acc.x += f * w.x;
-                acc.y += f * w.y;
-            }
+        const IEntry ei = list[e];
+        if (ei.src != -1) continue;
+        for (int32_t s = ei.slo; s < ei.shi; ++s) {
+            const C2 z = Cx<R>::make((R)((sx[s] - cx) * invL), (R)((sy[s] - cy) * invL));
+            const C2 w = cpowi(cinv(z), l);
+            const R f = -(R)sm[s] / (R)l;
+            acc.x += f * w.x;
+            acc.y += f * w.y;
         }
     }
     local[q * P1 + l] = acc;
@@ -302,15 +391,28 @@ void run_fmm_t(mlm_lens *lens, Tree &T, int p, hipStream_t st, typename Cx<R>::c
     const int P1 = p + 1;
     const int key = 2 * p + (sizeof(R) == 4 ? 1 : 0);
     if (ws.ops_p != key) {
-        std::vector<double2> h;
+        std::vector<double2> h, S, T;
+        std::vector<double> Pm;
         table_m2m(p, h);
         upload_ops<R>(ws.ops_m2m, h);
-        table_m2l(p, h);
-        upload_ops<R>(ws.ops_m2l, h);
         table_l2l(p, h);
         upload_ops<R>(ws.ops_l2l, h);
+        table_m2l_factors(p, S, T, Pm);
+        // one buffer: S (49 x 32 complex), T (49 x 32 complex), P (32 x 32 real)
+        std::vector<C2> st(2 * 49 * 32);
+        for (size_t k = 0; k < S.size(); ++k) {
+            st[k] = Cx<R>::make((R)S[k].x, (R)S[k].y);
+            st[S.size() + k] = Cx<R>::make((R)T[k].x, (R)T[k].y);
+        }
+        std::vector<R> pr(Pm.size());
+        for (size_t k = 0; k < Pm.size(); ++k) pr[k] = (R)Pm[k];
+        char *d = static_cast<char *>(ws.ops_m2l.reserve(st.size() * sizeof(C2) + pr.size() * sizeof(R)));
+        MLM_HIP(hipMemcpy(d, st.data(), st.size() * sizeof(C2), hipMemcpyHostToDevice));
+        MLM_HIP(hipMemcpy(d + st.size() * sizeof(C2), pr.data(), pr.size() * sizeof(R), hipMemcpyHostToDevice));
         ws.ops_p = key;
     }
+    const C2 *Sf = ws.ops_m2l.as<C2>(), *Tf = Sf + 49 * 32;
+    const R *Pm = reinterpret_cast<const R *>(Sf + 2 * 49 * 32);
     mult = static_cast<C2 *>(ws.mult.reserve((size_t)T.nnodes * P1 * sizeof(C2)));
     local = static_cast<C2 *>(ws.local.reserve((size_t)T.nnodes * P1 * sizeof(C2)));
     // upward
@@ -323,9 +425,9 @@ void run_fmm_t(mlm_lens *lens, Tree &T, int p, hipStream_t st, typename Cx<R>::c
     int64_t top = T.nlevels > 2 ? T.level_lo[2] : T.nnodes;
     hipLaunchKernelGGL(k_zero2<C2>, dim3(nblocks(top * P1)), dim3(BLK), 0, st, local, top * P1);
     for (int lev = 2; lev < T.nlevels; ++lev) {
-        int64_t lo = T.level_lo[lev], hi = T.level_hi[lev], nt = (hi - lo) * P1;
-        hipLaunchKernelGGL(k_downward<R>, dim3(nblocks(nt)), dim3(BLK), 0, st, lo, hi, lev, p, T.L0, T.code,
-                           T.parent, T.ilist, T.x, T.y, T.m, ws.ops_m2l.as<C2>(), ws.ops_l2l.as<C2>(), mult, local);
+        const int64_t lo = T.level_lo[lev], hi = T.level_hi[lev];
+        hipLaunchKernelGGL(k_downward<R>, dim3((unsigned)((hi - lo + 3) / 4)), dim3(256), 0, st, lo, hi, lev, p, T.L0,
+                           T.code, T.parent, T.ilist, T.x, T.y, T.m, Sf, Tf, Pm, ws.ops_l2l.as<C2>(), mult, local);
     }
 }
 
