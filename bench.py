@@ -6,7 +6,10 @@ kappa_* = 0.45, kappa_s = 0, gamma = 0.45, 2000 x 2000 px of half-width 25,
 ray shooting and IPM, with the stars already resident in device memory and
 the map left in device memory.  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-variants]
+
+Beside the headline, `variants` reports the same map in mixed precision and
+the 256-map batched workload (one fused call against 256 single calls).
 """
 from __future__ import annotations
 
@@ -28,8 +31,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6          # MI355X FP64 vector, dense
 # passes (FETCH_SIZE, WRITE_SIZE) scaled by the same counters' reading of a
 # plain 1 GiB device copy (--copy-check); valid only for the IPM source it was
 # taken with, identified by its SHA-256 prefix.
-BAND_TRAFFIC = {"fetch_bytes": 3024394.44 * 1024 * 2.0, "write_bytes": 31265.63 * 1024 * 1.0,
-                "ipm_sha256": "973be82e0e233e28"}
+BAND_TRAFFIC = {"fetch_bytes": 3034635.5 * 1024 * 2.0, "write_bytes": 31265.625 * 1024 * 1.0,
+                "ipm_sha256": "618a91275048ced6"}
 
 
 def file_sha(path: str) -> str:
@@ -56,6 +59,55 @@ def band_flops(stats: dict) -> float:
     clamp integral 7, the scaled difference 2, the change from the previous
     column 1)."""
     return 30.0 * stats["n_band_rows"] + 10.0 * stats["n_band_pieces"]
+
+
+def mixed_variant(lens, spec, out, ref) -> dict:
+    """The same map in the mixed-precision mode: time per map and its
+    per-pixel difference from the FP64 map just made (`ref`)."""
+    import torch
+    lens.map(out=out, precision="mixed", **spec)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(3):
+        _, s = lens.map(out=out, precision="mixed", timing=1, **spec)
+        ts.append(s["t_total_ms"])
+    d = ((out - ref).abs() / ref.clamp_min(1e-300))
+    return {"ms_per_map": sum(ts) / len(ts), "rays_per_s": s["n_rays"] / (sum(ts) / len(ts) * 1e-3),
+            "max_rel_vs_fp64": float(d.max()), "median_rel_vs_fp64": float(d.median())}
+
+
+def batched_variant() -> dict:
+    """The 256-map batched workload (seed 4; kappa, gamma, s and star counts
+    drawn; 1000^2 px, mixed precision): one fused batch call (leaf sizes from
+    the autotuner, cached after a first call) against 256 single-map calls."""
+    import torch
+    import paper_2506_02114_amd as mlm
+    import workloads as W
+    dev = torch.device("cuda:0")
+    lenses, reqs, outs = [], [], []
+    for wl in W.batch_draws(256, seed=4):
+        sf = wl.stars()
+        L = wl.lens
+        lenses.append(mlm.Lens(L.kappa_star, L.kappa_smooth, L.gamma, torch.from_numpy(sf.x).to(dev),
+                               torch.from_numpy(sf.y).to(dev), torch.from_numpy(sf.m).to(dev)))
+        reqs.append(dict(wl.map.asdict(), precision="mixed"))
+        outs.append(torch.empty((wl.map.n2, wl.map.n1), dtype=torch.float64, device=dev))
+    print("[bench] batched: 256 lenses ready", file=sys.stderr, flush=True)
+    mlm.map_batch(lenses, reqs, outs, autotune=True)          # tunes and warms
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, b = mlm.map_batch(lenses, reqs, outs, autotune=True)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for lens, r, o in zip(lenses, reqs, outs):
+        lens.map(out=o, **r)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    print("[bench] batched: done", file=sys.stderr, flush=True)
+    return {"maps": 256, "rays": b["n_rays"], "s_per_batch": t_batch, "rays_per_s": b["n_rays"] / t_batch,
+            "maps_per_hour": 256 * 3600.0 / t_batch, "s_256_single_calls": t_seq, "chunks": b["n_chunks"],
+            "stage_ms": {"prep": b["t_prep_ms"], "shoot": b["t_shoot_ms"], "ipm": b["t_ipm_ms"]}}
 
 
 def copy_check() -> None:
@@ -116,6 +168,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-check", action="store_true", help="only run the plain copy used to scale HBM counters")
+    ap.add_argument("--no-variants", action="store_true", help="skip the mixed-precision and batched measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the map path has no multi-GPU mode); got --gpus {args.gpus}",
@@ -199,6 +252,18 @@ def main():
         "ipm": {"triangles": 2 * stats[0]["n_cells"], "row_path_triangles": stats[0]["n_big"],
                 "row_path_rows": stats[0]["n_big_rows"]},
     }
+    if not args.no_variants:
+        variants = {}
+        ref = out.clone()
+        try:
+            variants["mixed_plain_large"] = mixed_variant(lens, spec, torch.empty_like(out), ref)
+        except Exception as e:   # a variant must not cost the headline line
+            variants["mixed_plain_large"] = {"error": str(e)}
+        try:
+            variants["batched_256"] = batched_variant()
+        except Exception as e:
+            variants["batched_256"] = {"error": str(e)}
+        line["variants"] = variants
     if not args.no_cpu_baseline:
         nthreads = min(16, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), os.cpu_count() or 1)
         line["cpu_baseline"] = cpu_baseline(wl, spec, region, nthreads)

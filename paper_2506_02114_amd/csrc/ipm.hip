@@ -30,7 +30,7 @@ template <class R> struct Pt {
 };
 using P2 = Pt<double>;
 
-constexpr int64_t BIG_PIXELS = 48;   // bounding-box pixels above which a triangle goes row by row
+constexpr int64_t BIG_PIXELS = 192;  // bounding-box pixels above which a triangle goes by row bands
 
 // Part of segment P->Q with lo <= coordinate <= hi (AXIS 0: u, 1: v).  The
 // segment lies on a line whose other coordinate changes by `slope` per unit of
