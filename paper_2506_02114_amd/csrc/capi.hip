@@ -1111,7 +1111,6 @@ mlm_status mlm_refiner_train(mlm_refiner *r, const mlm_train_opts *opts, const f
         for (int64_t k = n - 1; k > 0; --k) std::swap(perm[k], perm[next() % (uint64_t)(k + 1)]);
         MLM_HIP(hipMemcpyAsync(didx, perm.data(), (size_t)n * sizeof(int64_t), hipMemcpyHostToDevice, st));
         double loss = 0.0;
-        int64_t steps = 0;
         for (int64_t b0 = 0; b0 < n; b0 += o.batch) {
             const int64_t nb = std::min<int64_t>(o.batch, n - b0);
             refiner_batch(r, df, dy, didx + b0, nb, o.pos_weight, st);
@@ -1125,7 +1124,6 @@ mlm_status mlm_refiner_train(mlm_refiner *r, const mlm_train_opts *opts, const f
                 MLM_HIP(hipStreamSynchronize(st));
                 loss += hl * (double)nb;
             }
-            ++steps;
         }
         if (loss_per_epoch) loss_per_epoch[e] = (float)(loss / (double)n);
         MLM_HIP(hipStreamSynchronize(st));   // perm is reused by the next epoch

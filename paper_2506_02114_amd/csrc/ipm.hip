@@ -187,6 +187,7 @@ __device__ inline int wave_find(int excl, int x)
 struct TriClass {
     int kind;
     int cols;
+    bool small;           // kind 2 within a 2 x 2 pixel box: apportioned in place, no work items
     int64_t i0;           // first column inside the map
     int64_t pi, pj;       // pixel of a kind-1 deposit (or -1: outside)
 };
@@ -202,7 +203,7 @@ __device__ inline double twice_area(P2 A, P2 B, P2 C, double ou, double ov)
 
 __device__ inline TriClass classify(P2 A, P2 B, P2 C, const MapGeom &g)
 {
-    TriClass c{0, 0, 0, -1, -1};
+    TriClass c{0, 0, false, 0, -1, -1};
     if (!(isfinite(A.u) && isfinite(A.v) && isfinite(B.u) && isfinite(B.v) && isfinite(C.u) && isfinite(C.v)))
         return c;
     const double umin = fmin(A.u, fmin(B.u, C.u)), umax = fmax(A.u, fmax(B.u, C.u));
@@ -233,8 +234,70 @@ __device__ inline TriClass classify(P2 A, P2 B, P2 C, const MapGeom &g)
     }
     c.kind = 2;
     c.cols = (int)(i1 - i0 + 1);
+    c.small = fu1 - fu0 <= 1.0 && fv1 - fv0 <= 1.0;
     c.i0 = i0;
     return c;
+}
+
+// Area (signed like S, the triangle's signed area) of the part of a triangle
+// with coordinates a, b, c along one axis that lies below the line x = 1.  A
+// line leaving one vertex x0 alone on its side cuts off the corner triangle at
+// that vertex; along each edge from x0 the line sits at the fraction
+// t = (1 - x0) / (x - x0), so the corner's area is S t1 t2.
+__device__ inline double part_below(double a, double b, double c, double S)
+{
+    const bool la = a < 1.0, lb = b < 1.0, lc = c < 1.0;
+    const int n = (int)la + (int)lb + (int)lc;
+    const bool split = n == 1 || n == 2;
+    const double x0 = lb == lc ? a : (la == lc ? b : c);   // the lone vertex
+    const double x1 = lb == lc ? b : (la == lc ? c : a);
+    const double x2 = lb == lc ? c : (la == lc ? a : b);
+    const double den = split ? (x1 - x0) * (x2 - x0) : 1.0;
+    const double corner = S * ((1.0 - x0) * (1.0 - x0) / den);
+    return n == 0 ? 0.0 : (n == 3 ? S : (n == 1 ? corner : S - corner));
+}
+
+__device__ inline void put_pixel(const Window &w, double *map, const MapGeom &g, int64_t i, int64_t j, double val)
+{
+    if (val != 0.0 && i >= 0 && j >= 0 && i < g.n1 && j < g.n2) deposit_w(w, map, g, i, j, val);
+}
+
+// A triangle inside a 2 x 2 pixel box (first pixel (fu0, fv0)), apportioned
+// in place: with local coordinates at most the lines u = 1 and v = 1 cross
+// it, and its four pieces follow from the part left of u = 1 (GL), the part
+// below v = 1 (HB) and the part in both (Q).  Q is the corner triangle that
+// u = 1 cuts off, clipped below v = 1 (or HB minus it, when the corner is the
+// right-hand part).  Local coordinates are exact: a double minus a nearby
+// integer.
+__device__ inline void small_triangle(P2 A, P2 B, P2 C, double fu0, double fv0, const MapGeom &g, double *map,
+                                      const Window &w)
+{
+    const P2 a{A.u - fu0, A.v - fv0}, b{B.u - fu0, B.v - fv0}, c{C.u - fu0, C.v - fv0};
+    const double S = 0.5 * twice_area(A, B, C, fu0, fv0);   // never 0: those go to one pixel
+    const double inv = g.tri_weight / S;
+    const bool cu = fmax(a.u, fmax(b.u, c.u)) >= 1.0, cv = fmax(a.v, fmax(b.v, c.v)) >= 1.0;
+    const double HB = cv ? part_below(a.v, b.v, c.v, S) : S;
+    double GL = S, Q = HB;
+    if (cu) {
+        const bool la = a.u < 1.0, lb = b.u < 1.0, lc = c.u < 1.0;
+        const P2 p0 = lb == lc ? a : (la == lc ? b : c);   // alone on its side of u = 1
+        const P2 p1 = lb == lc ? b : (la == lc ? c : a);
+        const P2 p2 = lb == lc ? c : (la == lc ? a : b);
+        const double t1 = (1.0 - p0.u) / (p1.u - p0.u), t2 = (1.0 - p0.u) / (p2.u - p0.u);
+        const double corner = S * t1 * t2;
+        const bool left = p0.u < 1.0;
+        GL = left ? corner : S - corner;
+        Q = GL;
+        if (cv) {
+            const double q = part_below(p0.v, p0.v + t1 * (p1.v - p0.v), p0.v + t2 * (p2.v - p0.v), corner);
+            Q = left ? q : HB - q;
+        }
+    }
+    const int64_t i = (int64_t)fu0, j = (int64_t)fv0;
+    put_pixel(w, map, g, i, j, Q * inv);
+    if (cu) put_pixel(w, map, g, i + 1, j, (HB - Q) * inv);
+    if (cv) put_pixel(w, map, g, i, j + 1, (GL - Q) * inv);
+    if (cu && cv) put_pixel(w, map, g, i + 1, j + 1, ((S - GL) - (HB - Q)) * inv);
 }
 
 __device__ inline void load_cell(const double2 *verts, int64_t nr1, int64_t cb0, int64_t vb0, int64_t cell,
@@ -308,13 +371,14 @@ __device__ void cell_column(const double2 *verts, int64_t nr1, int64_t cb0, int6
     const TriClass k1 = classify(v00, v10, v11, g);
     P2 A, B, C;
     int64_t i0;
-    if (k1.kind == 2 && r < k1.cols) {
+    const int n1 = k1.kind == 2 && !k1.small ? k1.cols : 0;
+    if (r < n1) {
         A = v00; B = v10; C = v11;
         i0 = k1.i0;
     } else {
-        if (k1.kind == 2) r -= k1.cols;
+        r -= n1;
         const TriClass k2 = classify(v00, v11, v01, g);
-        if (k2.kind != 2 || r >= k2.cols) return;   // never: the items were counted from the same values
+        if (k2.kind != 2 || k2.small || r >= k2.cols) return;   // never: the items were counted from the same values
         A = v00; B = v11; C = v01;
         i0 = k2.i0;
     }
@@ -396,7 +460,12 @@ __device__ inline void ipm_tile(const double2 *__restrict__ verts, int64_t nr1, 
                 } else if (c.kind == 1) {
                     if (c.pi >= 0) deposit_w(w, map, g, c.pi, c.pj, g.tri_weight);
                 } else if (c.kind == 2) {
-                    cnt += c.cols;
+                    if (c.small) {
+                        const double fu0 = floor(fmin(A.u, fmin(B.u, C.u))), fv0 = floor(fmin(A.v, fmin(B.v, C.v)));
+                        small_triangle(A, B, C, fu0, fv0, g, map, w);
+                    } else {
+                        cnt += c.cols;
+                    }
                 } else {
                     ++nb;
                 }
