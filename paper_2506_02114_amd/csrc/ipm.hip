@@ -123,6 +123,70 @@ __device__ inline R strip_cumulative(const SegsT<R> &S, R c)
     return s;
 }
 
+// The same for a strip of pixel columns, divide-free: for an edge with slope
+// sv = dv/du clipped to the strip, |b - a| = |sv| |d|, so where the clamped
+// function changes sign d I = sign(d) m^2 / (2 |sv|) = m^2 c / 2 with
+// c = sign(d) |du/dv| fixed per edge.
+template <class R> struct ColSeg {
+    R a, b;             // v at both ends of the clipped edge
+    R d;                // du of the clipped edge
+    R c;                // sign(du) |du/dv| (0 if du = 0)
+};
+template <class R> struct ColSegs {
+    ColSeg<R> e0, e1, e2;
+};
+
+template <class R>
+__device__ inline ColSeg<R> col_seg(Pt<R> P, Pt<R> Q, R lo, R hi, R sv, R su)
+{
+    ColSeg<R> s;
+    Pt<R> E, X;
+    if (clip_seg<0>(P, Q, lo, hi, sv, E, X)) {
+        s.a = E.v;
+        s.b = X.v;
+        s.d = X.u - E.u;
+    } else {
+        s.a = s.b = s.d = R(0);
+    }
+    s.c = s.d > R(0) ? fabs(su) : (s.d < R(0) ? -fabs(su) : R(0));
+    return s;
+}
+
+template <class R>
+__device__ inline void col_segments(const Pt<R> (&T)[3], const R (&sv)[3], const R (&su)[3], R lo, R hi,
+                                    ColSegs<R> &S)
+{
+    S.e0 = col_seg(T[0], T[1], lo, hi, sv[0], su[0]);
+    S.e1 = col_seg(T[1], T[2], lo, hi, sv[1], su[1]);
+    S.e2 = col_seg(T[2], T[0], lo, hi, sv[2], su[2]);
+}
+
+template <class R>
+__device__ inline R col_term(const ColSeg<R> &e, R r)
+{
+    const R ua = r - e.a, ub = r - e.b;
+    const R m = fmax(ua, ub);
+    return (ua >= R(0) && ub >= R(0)) ? R(0.5) * e.d * (ua + ub)
+                                      : ((ua <= R(0) && ub <= R(0)) ? R(0) : R(0.5) * m * m * e.c);
+}
+
+// area below v = r inside the column: sum_e d_e I(r - a_e, r - b_e)
+template <class R>
+__device__ inline R col_cumulative(const ColSegs<R> &S, R r)
+{
+    return col_term(S.e0, r) + col_term(S.e1, r) + col_term(S.e2, r);
+}
+
+// widen [lo, hi] to the v range of a clipped edge (if it has one)
+template <class R>
+__device__ inline void col_range(const ColSeg<R> &e, R &lo, R &hi)
+{
+    if (e.d != R(0) || e.a != e.b) {
+        lo = fmin(lo, fmin(e.a, e.b));
+        hi = fmax(hi, fmax(e.a, e.b));
+    }
+}
+
 // Largest ratio of squared extent to twice the area that the FP32 geometry
 // of the mixed mode accepts: its relative area error is about FP32's unit
 // round-off times this ratio (below 2e-5 here).  Thinner triangles, the ones
@@ -331,74 +395,97 @@ __device__ inline bool cell_in_one_pixel(P2 v00, P2 v10, P2 v11, P2 v01, const M
 // integer point (fu0, fv0) (formed in FP64), cl = column - fu0; each piece is
 // a difference of the column's cumulative edge sum H at two row lines
 template <class R>
-__device__ inline void column_pieces(const P2 (&Td)[3], double cl, double fv0, int64_t i, int64_t j0, int64_t j1,
+__device__ inline void column_pieces(const P2 (&Td)[3], const double (&svd)[3], const double (&sud)[3], double cl, double fv0, int64_t i, int64_t j0, int64_t j1,
                                      double scale, const MapGeom &g, double *map, const Window &w)
 {
     const Pt<R> T[3] = {Pt<R>{(R)Td[0].u, (R)Td[0].v}, Pt<R>{(R)Td[1].u, (R)Td[1].v}, Pt<R>{(R)Td[2].u, (R)Td[2].v}};
-    R sv[3], su[3];
-    tri_slopes(T, sv, su);
-    SegsT<R> S;
-    strip_segments<0>(T, sv, (R)cl, (R)(cl + 1.0), S);
+    const R sv[3] = {(R)svd[0], (R)svd[1], (R)svd[2]};
+    const R su[3] = {(R)sud[0], (R)sud[1], (R)sud[2]};
+    ColSegs<R> S;
+    col_segments(T, sv, su, (R)cl, (R)(cl + 1.0), S);
     const R big = sizeof(R) == 4 ? R(3e38f) : R(1e300);
     R cvmin = big, cvmax = -big;
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-        if (S.d[k] != R(0) || S.a[k] != S.b[k]) {
-            cvmin = fmin(cvmin, fmin(S.a[k], S.b[k]));
-            cvmax = fmax(cvmax, fmax(S.a[k], S.b[k]));
-        }
+    col_range(S.e0, cvmin, cvmax);
+    col_range(S.e1, cvmin, cvmax);
+    col_range(S.e2, cvmin, cvmax);
     if (cvmin > cvmax) return;
     // area below v = r inside the column; a piece is the difference of two
     const int64_t ja = (int64_t)fmax(floor((double)cvmin) + fv0, (double)j0);
     const int64_t jb = (int64_t)fmin(floor((double)cvmax) + fv0, (double)j1);
-    R h0 = strip_cumulative(S, (R)((double)ja - fv0));
+    R h0 = col_cumulative(S, (R)((double)ja - fv0));
     for (int64_t j = ja; j <= jb; ++j) {
-        const R h1 = strip_cumulative(S, (R)((double)(j + 1) - fv0));
+        const R h1 = col_cumulative(S, (R)((double)(j + 1) - fv0));
         const double a2 = 2.0 * ((double)h1 - (double)h0);   // twice the piece area, signed like the triangle
         h0 = h1;
         if (a2 != 0.0) deposit_w(w, map, g, i, j, scale * a2);
     }
 }
 
-// one pixel column `r` (counted over the cell's triangles that need clipping)
-// of cell `cell`
-template <bool MIXED>
-__device__ void cell_column(const double2 *verts, int64_t nr1, int64_t cb0, int64_t vb0, int64_t cell, int r,
-                            const MapGeom &g, double *map, const Window &w)
+// What a pixel column of a medium triangle needs, computed once per triangle
+// by the thread that classified it and read by the threads that take its
+// columns (through cross-lane reads, so no cell is loaded twice).
+struct ColSetup {
+    P2 T[3];              // vertices local to (fu0, fv0)
+    double sv[3];         // edge slopes dv/du
+    double su[3];         // and du/dv
+    double scale;         // tri_weight / (twice the signed area)
+    double fu0, fv0;      // floor of the box's lower-left corner
+    int i0, j0, j1;       // first in-map column; in-map rows
+    int fp32;             // mixed mode: conditioned well enough for FP32 geometry
+};
+
+__device__ inline ColSetup col_setup(P2 A, P2 B, P2 C, int64_t i0, const MapGeom &g, bool mixed)
 {
-    P2 v00, v10, v11, v01;
-    load_cell(verts, nr1, cb0, vb0, cell, v00, v10, v11, v01);
-    const TriClass k1 = classify(v00, v10, v11, g);
-    P2 A, B, C;
-    int64_t i0;
-    const int n1 = k1.kind == 2 && !k1.small ? k1.cols : 0;
-    if (r < n1) {
-        A = v00; B = v10; C = v11;
-        i0 = k1.i0;
-    } else {
-        r -= n1;
-        const TriClass k2 = classify(v00, v11, v01, g);
-        if (k2.kind != 2 || k2.small || r >= k2.cols) return;   // never: the items were counted from the same values
-        A = v00; B = v11; C = v01;
-        i0 = k2.i0;
-    }
+    ColSetup c;
     const double umin = fmin(A.u, fmin(B.u, C.u)), vmin = fmin(A.v, fmin(B.v, C.v));
-    const double fu0 = floor(umin), fv0 = floor(vmin);
-    const double fv1 = floor(fmax(A.v, fmax(B.v, C.v)));
-    const P2 T[3] = {P2{A.u - fu0, A.v - fv0}, P2{B.u - fu0, B.v - fv0}, P2{C.u - fu0, C.v - fv0}};
-    const double S2 = twice_area(A, B, C, fu0, fv0);
-    const double scale = g.tri_weight / S2;
-    const int64_t j0 = (int64_t)fmax(fv0, 0.0), j1 = (int64_t)fmin(fv1, (double)(g.n2 - 1));
-    const int64_t i = i0 + r;
-    const double cl = (double)i - fu0;
-    if (MIXED) {
-        const double eu = fmax(A.u, fmax(B.u, C.u)) - umin, ev = fmax(A.v, fmax(B.v, C.v)) - vmin;
-        if (eu * eu + ev * ev <= MIXED_MAX_COND * fabs(S2)) {
-            column_pieces<float>(T, cl, fv0, i, j0, j1, scale, g, map, w);
-            return;
-        }
+    const double umax = fmax(A.u, fmax(B.u, C.u)), vmax = fmax(A.v, fmax(B.v, C.v));
+    c.fu0 = floor(umin);
+    c.fv0 = floor(vmin);
+    c.T[0] = P2{A.u - c.fu0, A.v - c.fv0};
+    c.T[1] = P2{B.u - c.fu0, B.v - c.fv0};
+    c.T[2] = P2{C.u - c.fu0, C.v - c.fv0};
+    tri_slopes(c.T, c.sv, c.su);
+    const double S2 = twice_area(A, B, C, c.fu0, c.fv0);
+    c.scale = g.tri_weight / S2;
+    c.i0 = (int)i0;
+    c.j0 = (int)fmax(c.fv0, 0.0);
+    c.j1 = (int)fmin(floor(vmax), (double)(g.n2 - 1));
+    const double eu = umax - umin, ev = vmax - vmin;
+    c.fp32 = mixed && eu * eu + ev * ev <= MIXED_MAX_COND * fabs(S2);
+    return c;
+}
+
+__device__ inline ColSetup shfl_setup(const ColSetup &s, int L)
+{
+    ColSetup c;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        c.T[k].u = __shfl(s.T[k].u, L, 64);
+        c.T[k].v = __shfl(s.T[k].v, L, 64);
+        c.sv[k] = __shfl(s.sv[k], L, 64);
+        c.su[k] = __shfl(s.su[k], L, 64);
     }
-    column_pieces<double>(T, cl, fv0, i, j0, j1, scale, g, map, w);
+    c.scale = __shfl(s.scale, L, 64);
+    c.fu0 = __shfl(s.fu0, L, 64);
+    c.fv0 = __shfl(s.fv0, L, 64);
+    c.i0 = __shfl(s.i0, L, 64);
+    c.j0 = __shfl(s.j0, L, 64);
+    c.j1 = __shfl(s.j1, L, 64);
+    c.fp32 = __shfl(s.fp32, L, 64);
+    return c;
+}
+
+// pixel column i0 + r of the triangle set up in `c`
+template <bool MIXED>
+__device__ inline void setup_column(const ColSetup &c, int r, const MapGeom &g, double *map, const Window &w)
+{
+    const int64_t i = (int64_t)c.i0 + r;
+    const double cl = (double)i - c.fu0;
+    if (MIXED && c.fp32) {
+        column_pieces<float>(c.T, c.sv, c.su, cl, c.fv0, i, c.j0, c.j1, c.scale, g, map, w);
+        return;
+    }
+    column_pieces<double>(c.T, c.sv, c.su, cl, c.fv0, i, c.j0, c.j1, c.scale, g, map, w);
 }
 
 // IPM of the ordinary triangles.  A workgroup takes a tile of 16 x 16 cells
@@ -437,11 +524,11 @@ __device__ inline void ipm_tile(const double2 *__restrict__ verts, int64_t nr1, 
         w.j0 = (int64_t)fv - WIN / 2;
     }
     __syncthreads();
-    int cnt = 0;
-    int64_t cell = -1;
+    int mcols[2] = {0, 0};      // pixel columns of each medium triangle of the cell (0: none)
+    int64_t mi0[2] = {0, 0};
+    P2 v00{0.0, 0.0}, v10{0.0, 0.0}, v11{0.0, 0.0}, v01{0.0, 0.0};
     if (a < ncol && brow < nrows) {
-        cell = brow * ncol + a;
-        P2 v00, v10, v11, v01;
+        const int64_t cell = brow * ncol + a;
         load_cell(verts, nr1, cb0, vb0, cell, v00, v10, v11, v01);
         int64_t pi, pj;
         int nb = 0;
@@ -464,7 +551,8 @@ __device__ inline void ipm_tile(const double2 *__restrict__ verts, int64_t nr1, 
                         const double fu0 = floor(fmin(A.u, fmin(B.u, C.u))), fv0 = floor(fmin(A.v, fmin(B.v, C.v)));
                         small_triangle(A, B, C, fu0, fv0, g, map, w);
                     } else {
-                        cnt += c.cols;
+                        mcols[k] = c.cols;
+                        mi0[k] = c.i0;
                     }
                 } else {
                     ++nb;
@@ -473,14 +561,22 @@ __device__ inline void ipm_tile(const double2 *__restrict__ verts, int64_t nr1, 
         }
         nbig[cell] = nb;
     }
-    int total;
-    const int excl = wave_excl_scan(cnt, lane, total);
-    for (int base = 0; base < total; base += 64) {
-        const int item = base + lane;
-        const int L = wave_find(excl, item);
-        const int r = item - __shfl(excl, L, 64);
-        const int64_t c = __shfl(cell, L, 64);
-        if (item < total) cell_column<MIXED>(verts, nr1, cb0, vb0, c, r, g, map, w);
+    // the medium triangles' pixel columns, spread evenly over the wavefront's
+    // lanes: first triangle of every cell, then the second
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        int total;
+        const int excl = wave_excl_scan(mcols[k], lane, total);
+        if (total == 0) continue;
+        ColSetup own{};
+        if (mcols[k] > 0) own = k == 0 ? col_setup(v00, v10, v11, mi0[k], g, MIXED) : col_setup(v00, v11, v01, mi0[k], g, MIXED);
+        for (int base = 0; base < total; base += 64) {
+            const int item = base + lane;
+            const int L = wave_find(excl, item);
+            const int r = item - __shfl(excl, L, 64);
+            const ColSetup c = shfl_setup(own, L);
+            if (item < total) setup_column<MIXED>(c, r, g, map, w);
+        }
     }
     __syncthreads();
     for (int k = threadIdx.x; k < WIN * WIN; k += blockDim.x) {
