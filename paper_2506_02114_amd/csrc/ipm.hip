@@ -193,9 +193,9 @@ __device__ inline void col_range(const ColSeg<R> &e, R &lo, R &hi)
 // folded across a caustic, are apportioned in FP64.
 constexpr double MIXED_MAX_COND = 256.0;
 
-__device__ inline void deposit(double *map, const MapGeom &g, int64_t i, int64_t j, double val)
+__device__ inline void deposit(double *map, const MapGeom &g, int i, int j, double val)
 {
-    unsafeAtomicAdd(map + j * (int64_t)g.n1 + i, val);
+    unsafeAtomicAdd(map + (int64_t)j * g.n1 + i, val);
 }
 
 // pixel window of a workgroup in LDS: deposits inside it are summed there and
@@ -204,13 +204,13 @@ constexpr int WIN = 64;   // window side in pixels (WIN x WIN doubles)
 
 struct Window {
     double *acc;          // WIN x WIN, row-major
-    int64_t i0, j0;       // map pixel of acc[0]
+    int i0, j0;           // map pixel of acc[0]
 };
 
-__device__ inline void deposit_w(const Window &w, double *map, const MapGeom &g, int64_t i, int64_t j, double val)
+__device__ inline void deposit_w(const Window &w, double *map, const MapGeom &g, int i, int j, double val)
 {
-    const int64_t di = i - w.i0, dj = j - w.j0;
-    if ((uint64_t)di < (uint64_t)WIN && (uint64_t)dj < (uint64_t)WIN) atomicAdd(w.acc + dj * WIN + di, val);
+    const int di = i - w.i0, dj = j - w.j0;
+    if ((unsigned)di < (unsigned)WIN && (unsigned)dj < (unsigned)WIN) atomicAdd(w.acc + dj * WIN + di, val);
     else deposit(map, g, i, j, val);
 }
 
@@ -252,8 +252,8 @@ struct TriClass {
     int kind;
     int cols;
     bool small;           // kind 2 within a 2 x 2 pixel box: apportioned in place, no work items
-    int64_t i0;           // first column inside the map
-    int64_t pi, pj;       // pixel of a kind-1 deposit (or -1: outside)
+    int i0;               // first column inside the map
+    int pi, pj;           // pixel of a kind-1 deposit (or -1: outside)
 };
 
 // twice the signed area of (A, B, C) in coordinates relative to (ou, ov),
@@ -276,8 +276,8 @@ __device__ inline TriClass classify(P2 A, P2 B, P2 C, const MapGeom &g)
     if (fu1 < 0.0 || fv1 < 0.0 || fu0 > (double)(g.n1 - 1) || fv0 > (double)(g.n2 - 1)) return c;
     if (fu0 == fu1 && fv0 == fv1) {
         c.kind = 1;
-        c.pi = (int64_t)fu0;
-        c.pj = (int64_t)fv0;
+        c.pi = (int)fu0;
+        c.pj = (int)fv0;
         return c;
     }
     if (twice_area(A, B, C, fu0, fv0) == 0.0) {
@@ -285,14 +285,14 @@ __device__ inline TriClass classify(P2 A, P2 B, P2 C, const MapGeom &g)
         const double fi = floor((A.u + B.u + C.u) / 3.0), fj = floor((A.v + B.v + C.v) / 3.0);
         c.kind = 1;
         if (fi >= 0.0 && fj >= 0.0 && fi <= (double)(g.n1 - 1) && fj <= (double)(g.n2 - 1)) {
-            c.pi = (int64_t)fi;
-            c.pj = (int64_t)fj;
+            c.pi = (int)fi;
+            c.pj = (int)fj;
         }
         return c;
     }
-    const int64_t i0 = (int64_t)fmax(fu0, 0.0), i1 = (int64_t)fmin(fu1, (double)(g.n1 - 1));
-    const int64_t j0 = (int64_t)fmax(fv0, 0.0), j1 = (int64_t)fmin(fv1, (double)(g.n2 - 1));
-    if ((i1 - i0 + 1) * (j1 - j0 + 1) > BIG_PIXELS) {
+    const int i0 = (int)fmax(fu0, 0.0), i1 = (int)fmin(fu1, (double)(g.n1 - 1));
+    const int j0 = (int)fmax(fv0, 0.0), j1 = (int)fmin(fv1, (double)(g.n2 - 1));
+    if ((int64_t)(i1 - i0 + 1) * (j1 - j0 + 1) > BIG_PIXELS) {
         c.kind = 3;
         return c;
     }
@@ -321,7 +321,7 @@ __device__ inline double part_below(double a, double b, double c, double S)
     return n == 0 ? 0.0 : (n == 3 ? S : (n == 1 ? corner : S - corner));
 }
 
-__device__ inline void put_pixel(const Window &w, double *map, const MapGeom &g, int64_t i, int64_t j, double val)
+__device__ inline void put_pixel(const Window &w, double *map, const MapGeom &g, int i, int j, double val)
 {
     if (val != 0.0 && i >= 0 && j >= 0 && i < g.n1 && j < g.n2) deposit_w(w, map, g, i, j, val);
 }
@@ -357,7 +357,7 @@ __device__ inline void small_triangle(P2 A, P2 B, P2 C, double fu0, double fv0, 
             Q = left ? q : HB - q;
         }
     }
-    const int64_t i = (int64_t)fu0, j = (int64_t)fv0;
+    const int i = (int)fu0, j = (int)fv0;   // at least -1: the box meets the map
     put_pixel(w, map, g, i, j, Q * inv);
     if (cu) put_pixel(w, map, g, i + 1, j, (HB - Q) * inv);
     if (cv) put_pixel(w, map, g, i, j + 1, (GL - Q) * inv);
@@ -377,7 +377,7 @@ __device__ inline void load_cell(const double2 *verts, int64_t nr1, int64_t cb0,
     v01 = P2{q01.x, q01.y};
 }
 
-__device__ inline bool cell_in_one_pixel(P2 v00, P2 v10, P2 v11, P2 v01, const MapGeom &g, int64_t &pi, int64_t &pj)
+__device__ inline bool cell_in_one_pixel(P2 v00, P2 v10, P2 v11, P2 v01, const MapGeom &g, int &pi, int &pj)
 {
     const double fu = floor(v00.u), fv = floor(v00.v);
     if (!(floor(v10.u) == fu && floor(v11.u) == fu && floor(v01.u) == fu && floor(v10.v) == fv &&
@@ -385,8 +385,8 @@ __device__ inline bool cell_in_one_pixel(P2 v00, P2 v10, P2 v11, P2 v01, const M
         return false;
     pi = pj = -1;
     if (fu >= 0.0 && fv >= 0.0 && fu <= (double)(g.n1 - 1) && fv <= (double)(g.n2 - 1)) {
-        pi = (int64_t)fu;
-        pj = (int64_t)fv;
+        pi = (int)fu;
+        pj = (int)fv;
     }
     return true;
 }
@@ -395,7 +395,7 @@ __device__ inline bool cell_in_one_pixel(P2 v00, P2 v10, P2 v11, P2 v01, const M
 // integer point (fu0, fv0) (formed in FP64), cl = column - fu0; each piece is
 // a difference of the column's cumulative edge sum H at two row lines
 template <class R>
-__device__ inline void column_pieces(const P2 (&Td)[3], const double (&svd)[3], const double (&sud)[3], double cl, double fv0, int64_t i, int64_t j0, int64_t j1,
+__device__ inline void column_pieces(const P2 (&Td)[3], const double (&svd)[3], const double (&sud)[3], double cl, double fv0, int i, int j0, int j1,
                                      double scale, const MapGeom &g, double *map, const Window &w)
 {
     const Pt<R> T[3] = {Pt<R>{(R)Td[0].u, (R)Td[0].v}, Pt<R>{(R)Td[1].u, (R)Td[1].v}, Pt<R>{(R)Td[2].u, (R)Td[2].v}};
@@ -410,10 +410,11 @@ __device__ inline void column_pieces(const P2 (&Td)[3], const double (&svd)[3], 
     col_range(S.e2, cvmin, cvmax);
     if (cvmin > cvmax) return;
     // area below v = r inside the column; a piece is the difference of two
-    const int64_t ja = (int64_t)fmax(floor((double)cvmin) + fv0, (double)j0);
-    const int64_t jb = (int64_t)fmin(floor((double)cvmax) + fv0, (double)j1);
+    // rows of the column's pieces, clamped to the triangle's in-map rows
+    const int ja = (int)fmin(fmax(floor((double)cvmin) + fv0, (double)j0), (double)j1 + 1.0);
+    const int jb = (int)fmax(fmin(floor((double)cvmax) + fv0, (double)j1), (double)j0 - 1.0);
     R h0 = col_cumulative(S, (R)((double)ja - fv0));
-    for (int64_t j = ja; j <= jb; ++j) {
+    for (int j = ja; j <= jb; ++j) {
         const R h1 = col_cumulative(S, (R)((double)(j + 1) - fv0));
         const double a2 = 2.0 * ((double)h1 - (double)h0);   // twice the piece area, signed like the triangle
         h0 = h1;
@@ -434,7 +435,7 @@ struct ColSetup {
     int fp32;             // mixed mode: conditioned well enough for FP32 geometry
 };
 
-__device__ inline ColSetup col_setup(P2 A, P2 B, P2 C, int64_t i0, const MapGeom &g, bool mixed)
+__device__ inline ColSetup col_setup(P2 A, P2 B, P2 C, int i0, const MapGeom &g, bool mixed)
 {
     ColSetup c;
     const double umin = fmin(A.u, fmin(B.u, C.u)), vmin = fmin(A.v, fmin(B.v, C.v));
@@ -479,7 +480,7 @@ __device__ inline ColSetup shfl_setup(const ColSetup &s, int L)
 template <bool MIXED>
 __device__ inline void setup_column(const ColSetup &c, int r, const MapGeom &g, double *map, const Window &w)
 {
-    const int64_t i = (int64_t)c.i0 + r;
+    const int i = c.i0 + r;
     const double cl = (double)i - c.fu0;
     if (MIXED && c.fp32) {
         column_pieces<float>(c.T, c.sv, c.su, cl, c.fv0, i, c.j0, c.j1, c.scale, g, map, w);
@@ -520,17 +521,17 @@ __device__ inline void ipm_tile(const double2 *__restrict__ verts, int64_t nr1, 
         const double2 c = verts[(cb0 + cb - vb0) * nr1 + ca];
         const double fu = isfinite(c.x) ? fmin(fmax(floor(c.x), -1e9), 1e9) : 0.0;
         const double fv = isfinite(c.y) ? fmin(fmax(floor(c.y), -1e9), 1e9) : 0.0;
-        w.i0 = (int64_t)fu - WIN / 2;
-        w.j0 = (int64_t)fv - WIN / 2;
+        w.i0 = (int)fu - WIN / 2;
+        w.j0 = (int)fv - WIN / 2;
     }
     __syncthreads();
     int mcols[2] = {0, 0};      // pixel columns of each medium triangle of the cell (0: none)
-    int64_t mi0[2] = {0, 0};
+    int mi0[2] = {0, 0};
     P2 v00{0.0, 0.0}, v10{0.0, 0.0}, v11{0.0, 0.0}, v01{0.0, 0.0};
     if (a < ncol && brow < nrows) {
         const int64_t cell = brow * ncol + a;
         load_cell(verts, nr1, cb0, vb0, cell, v00, v10, v11, v01);
-        int64_t pi, pj;
+        int pi, pj;
         int nb = 0;
         if (cell_in_one_pixel(v00, v10, v11, v01, g, pi, pj)) {
             if (pi >= 0) deposit_w(w, map, g, pi, pj, 2.0 * g.tri_weight);
@@ -582,7 +583,7 @@ __device__ inline void ipm_tile(const double2 *__restrict__ verts, int64_t nr1, 
     for (int k = threadIdx.x; k < WIN * WIN; k += blockDim.x) {
         const double v = acc[k];
         if (v != 0.0) {
-            const int64_t i = w.i0 + (k % WIN), j = w.j0 + (k / WIN);
+            const int i = w.i0 + (k % WIN), j = w.j0 + (k / WIN);
             deposit(map, g, i, j, v);   // inside the map: only in-map pixels were deposited
         }
     }
@@ -808,7 +809,7 @@ __global__ __launch_bounds__(256) void k_big(int64_t nbig, const BigPrep *__rest
                     const Segs S = sl.S;
                     // twice the area: 2 (G(i + 1) - G(i)), G(c) = -sum dv I(c - ua, c - ub)
                     const double a2 = 2.0 * (strip_cumulative(S, (double)i) - strip_cumulative(S, (double)(i + 1)));
-                    if (a2 != 0.0) deposit(map, g, i + (int64_t)sl.ou, sl.j, sl.scale * a2);
+                    if (a2 != 0.0) deposit(map, g, (int)(i + (int64_t)sl.ou), (int)sl.j, sl.scale * a2);   // in the map
                 }
             }
         }
@@ -930,9 +931,9 @@ __device__ inline void band_rows(int64_t band, int64_t r0, int64_t r1, const int
         if (j < (int64_t)bp.ov || j >= (int64_t)bp.ov + rows[k]) continue;
         ++my_rows;
         const double rl = (double)j - bp.ov;
-        const int64_t ou = (int64_t)bp.ou;
+        const int ou = (int)bp.ou;             // in [0, n1]
         double *drow = bdiff + rr * n1 + ou;   // indexed by local column
-        const int64_t cmin = -ou, cmax = n1 - 1 - ou;
+        const int cmin = -ou, cmax = (int)n1 - 1 - ou;
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
             const P2 P{bp.u[m], bp.v[m]}, Q{bp.u[(m + 1) % 3], bp.v[(m + 1) % 3]};
@@ -943,17 +944,22 @@ __device__ inline void band_rows(int64_t band, int64_t r0, int64_t r1, const int
             if (dv == 0.0) continue;
             const double ua = E.u, ub = X.u;
             const double w = fabs(ub - ua), inv = w > 0.0 ? 1.0 / w : 0.0;
-            const int64_t x0 = (int64_t)floor(fmin(ua, ub)), x1 = (int64_t)floor(fmax(ua, ub));
+            // first and last column of the clipped edge, clamped to one
+            // column beyond the map on either side (which changes nothing
+            // below) so they fit 32 bits
+            const double lo = (double)cmin - 1.0, hi = (double)cmax + 1.0;
+            const int x0 = (int)fmin(fmax(floor(fmin(ua, ub)), lo), hi);
+            const int x1 = (int)fmin(fmax(floor(fmax(ua, ub)), lo), hi);
             const double f = -2.0 * bp.scale * dv;   // deposit for a fully covered difference
-            const int64_t is = max(x0, cmin);
+            const int is = max(x0, cmin);
             if (is > x1) {   // the segment lies left of the map
                 atomicAdd(drow + cmin, f);
                 ++my_pieces;
                 continue;
             }
             double Jc = clamp_integral((double)is - ua, (double)is - ub, inv), prev = 0.0;
-            const int64_t ie = min(x1, cmax);
-            for (int64_t i = is; i <= ie; ++i) {
+            const int ie = min(x1, cmax);
+            for (int i = is; i <= ie; ++i) {
                 const double Jn = clamp_integral((double)(i + 1) - ua, (double)(i + 1) - ub, inv);
                 const double cur = f * (Jn - Jc);
                 atomicAdd(drow + i, cur - prev);
@@ -961,7 +967,7 @@ __device__ inline void band_rows(int64_t band, int64_t r0, int64_t r1, const int
                 Jc = Jn;
             }
             if (x1 + 1 <= cmax) atomicAdd(drow + x1 + 1, f - prev);
-            my_pieces += (unsigned long long)(max(ie - is + 1, (int64_t)0) + (x1 + 1 <= cmax ? 1 : 0));
+            my_pieces += (unsigned long long)(max(ie - is + 1, 0) + (x1 + 1 <= cmax ? 1 : 0));
         }
     }
     __syncthreads();
