@@ -128,9 +128,10 @@ __device__ inline R strip_cumulative(const SegsT<R> &S, R c)
 // function changes sign d I = sign(d) m^2 / (2 |sv|) = m^2 c / 2 with
 // c = sign(d) |du/dv| fixed per edge.
 template <class R> struct ColSeg {
-    R a, b;             // v at both ends of the clipped edge
+    R lo, hi;           // v range of the clipped edge
     R d;                // du of the clipped edge
     R c;                // sign(du) |du/dv| (0 if du = 0)
+    bool any;           // the edge crosses the column with some extent
 };
 template <class R> struct ColSegs {
     ColSeg<R> e0, e1, e2;
@@ -142,12 +143,13 @@ __device__ inline ColSeg<R> col_seg(Pt<R> P, Pt<R> Q, R lo, R hi, R sv, R su)
     ColSeg<R> s;
     Pt<R> E, X;
     if (clip_seg<0>(P, Q, lo, hi, sv, E, X)) {
-        s.a = E.v;
-        s.b = X.v;
+        s.lo = fmin(E.v, X.v);
+        s.hi = fmax(E.v, X.v);
         s.d = X.u - E.u;
     } else {
-        s.a = s.b = s.d = R(0);
+        s.lo = s.hi = s.d = R(0);
     }
+    s.any = s.d != R(0) || s.lo != s.hi;
     s.c = s.d > R(0) ? fabs(su) : (s.d < R(0) ? -fabs(su) : R(0));
     return s;
 }
@@ -161,13 +163,16 @@ __device__ inline void col_segments(const Pt<R> (&T)[3], const R (&sv)[3], const
     S.e2 = col_seg(T[2], T[0], lo, hi, sv[2], su[2]);
 }
 
+// d I(r - a, r - b) without case branches: below the edge's v range the
+// crossing form (r - lo)^2 c / 2 is 0 once r - lo is clamped at 0; above it
+// the linear form applies
 template <class R>
 __device__ inline R col_term(const ColSeg<R> &e, R r)
 {
-    const R ua = r - e.a, ub = r - e.b;
-    const R m = fmax(ua, ub);
-    return (ua >= R(0) && ub >= R(0)) ? R(0.5) * e.d * (ua + ub)
-                                      : ((ua <= R(0) && ub <= R(0)) ? R(0) : R(0.5) * m * m * e.c);
+    const R t = fmax(r - e.lo, R(0));
+    const R cross = R(0.5) * t * t * e.c;
+    const R full = R(0.5) * e.d * ((r - e.lo) + (r - e.hi));
+    return r >= e.hi ? full : cross;
 }
 
 // area below v = r inside the column: sum_e d_e I(r - a_e, r - b_e)
@@ -181,9 +186,9 @@ __device__ inline R col_cumulative(const ColSegs<R> &S, R r)
 template <class R>
 __device__ inline void col_range(const ColSeg<R> &e, R &lo, R &hi)
 {
-    if (e.d != R(0) || e.a != e.b) {
-        lo = fmin(lo, fmin(e.a, e.b));
-        hi = fmax(hi, fmax(e.a, e.b));
+    if (e.any) {
+        lo = fmin(lo, e.lo);
+        hi = fmax(hi, e.hi);
     }
 }
 
@@ -957,17 +962,31 @@ __device__ inline void band_rows(int64_t band, int64_t r0, int64_t r1, const int
                 ++my_pieces;
                 continue;
             }
-            double Jc = clamp_integral((double)is - ua, (double)is - ub, inv), prev = 0.0;
-            const int ie = min(x1, cmax);
-            for (int i = is; i <= ie; ++i) {
-                const double Jn = clamp_integral((double)(i + 1) - ua, (double)(i + 1) - ub, inv);
+            // the clamp integral J(x) at column boundaries x: 0 up to x0, the
+            // crossing form (x - umin)^2 / (2 w) up to x1, the linear form
+            // at x1 + 1 (past the edge), so the walk needs no case tests
+            const double umin = fmin(ua, ub), hinv = 0.5 * inv;
+            auto cross = [&](int x) {
+                const double t = (double)x - umin;
+                return hinv * t * t;
+            };
+            double Jc = is > x0 ? cross(is) : 0.0, prev = 0.0;
+            const int iend = min(x1 - 1, cmax);
+            for (int i = is; i <= iend; ++i) {
+                const double Jn = cross(i + 1);
                 const double cur = f * (Jn - Jc);
                 atomicAdd(drow + i, cur - prev);
                 prev = cur;
                 Jc = Jn;
             }
-            if (x1 + 1 <= cmax) atomicAdd(drow + x1 + 1, f - prev);
-            my_pieces += (unsigned long long)(max(ie - is + 1, 0) + (x1 + 1 <= cmax ? 1 : 0));
+            if (x1 <= cmax) {
+                const double Jn = 0.5 * (((double)(x1 + 1) - ua) + ((double)(x1 + 1) - ub));
+                const double cur = f * (Jn - Jc);
+                atomicAdd(drow + x1, cur - prev);
+                prev = cur;
+                if (x1 + 1 <= cmax) atomicAdd(drow + x1 + 1, f - prev);
+            }
+            my_pieces += (unsigned long long)(max(min(x1, cmax) - is + 1, 0) + (x1 + 1 <= cmax ? 1 : 0));
         }
     }
     __syncthreads();
