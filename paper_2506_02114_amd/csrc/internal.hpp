@@ -91,12 +91,15 @@ struct LensConst {
 };
 
 // per-triangle data of the row-parallel IPM: counter-clockwise vertices
-// relative to the integer origin (ou, ov), edge slopes su = du/dv, and the
-// deposit per unit of twice the piece area (96 bytes)
+// relative to the integer origin (ou, ov), edge slopes su = du/dv, the
+// deposit per unit of twice the piece area, and per edge the factor of the
+// squared distance past the edge's first column in its row term,
+// -scale sign(dv) |dv/du| (0 for edges with du = 0) (120 bytes)
 struct BigPrep {
     double u[3], v[3];
     double su[3];
     double ou, ov, scale;
+    double kc[3];
 };
 
 // ray-grid geometry of a shooting launch

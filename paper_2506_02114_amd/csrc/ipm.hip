@@ -661,6 +661,11 @@ __device__ inline void gather_cell(int64_t t, int64_t slot, int64_t end, const d
         bp.ou = ou;
         bp.ov = ov;
         bp.scale = g.tri_weight / S2;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const double dv = T[m == 2 ? 0 : m + 1].v - T[m].v;
+            bp.kc[m] = dv > 0.0 ? -bp.scale * fabs(sv[m]) : (dv < 0.0 ? bp.scale * fabs(sv[m]) : 0.0);
+        }
         prep[slot] = bp;
         const double j1 = fmin(floor(vmax), (double)(g.n2 - 1));
         rows[slot] = j1 >= ov ? (int64_t)(j1 - ov) + 1 : 0;
@@ -948,7 +953,6 @@ __device__ inline void band_rows(int64_t band, int64_t r0, int64_t r1, const int
             const double dv = X.v - E.v;
             if (dv == 0.0) continue;
             const double ua = E.u, ub = X.u;
-            const double w = fabs(ub - ua), inv = w > 0.0 ? 1.0 / w : 0.0;
             // first and last column of the clipped edge, clamped to one
             // column beyond the map on either side (which changes nothing
             // below) so they fit 32 bits
@@ -962,26 +966,28 @@ __device__ inline void band_rows(int64_t band, int64_t r0, int64_t r1, const int
                 ++my_pieces;
                 continue;
             }
-            // the clamp integral J(x) at column boundaries x: 0 up to x0, the
-            // crossing form (x - umin)^2 / (2 w) up to x1, the linear form
-            // at x1 + 1 (past the edge), so the walk needs no case tests
-            const double umin = fmin(ua, ub), hinv = 0.5 * inv;
+            // f J(x) at column boundaries x, J the clamp integral over the
+            // clipped edge of width w: 0 up to x0, the crossing form
+            // f (x - umin)^2 / (2 w) = kc (x - umin)^2 up to x1 (f / w is
+            // fixed along the edge), the linear form at x1 + 1 (past the
+            // edge), so the walk needs neither case tests nor a division
+            const double umin = fmin(ua, ub), kc = bp.kc[m];
             auto cross = [&](int x) {
                 const double t = (double)x - umin;
-                return hinv * t * t;
+                return kc * t * t;
             };
             double Jc = is > x0 ? cross(is) : 0.0, prev = 0.0;
             const int iend = min(x1 - 1, cmax);
             for (int i = is; i <= iend; ++i) {
                 const double Jn = cross(i + 1);
-                const double cur = f * (Jn - Jc);
+                const double cur = Jn - Jc;
                 atomicAdd(drow + i, cur - prev);
                 prev = cur;
                 Jc = Jn;
             }
             if (x1 <= cmax) {
-                const double Jn = 0.5 * (((double)(x1 + 1) - ua) + ((double)(x1 + 1) - ub));
-                const double cur = f * (Jn - Jc);
+                const double Jn = f * (0.5 * (((double)(x1 + 1) - ua) + ((double)(x1 + 1) - ub)));
+                const double cur = Jn - Jc;
                 atomicAdd(drow + x1, cur - prev);
                 prev = cur;
                 if (x1 + 1 <= cmax) atomicAdd(drow + x1 + 1, f - prev);
