@@ -117,6 +117,35 @@ __device__ inline float2 cpowi(float2 z, int n)
     return r;
 }
 
+// wavefront-level load balancing: a wavefront owns 64 segments (cells, large
+// triangles or rows) with v items each; the exclusive scan of v over the
+// lanes numbers the items, and an item finds its segment by binary lifting
+// over the lanes' scan values (lane shuffles, no global memory)
+__device__ inline int wave_excl_scan(int v, int lane, int &total)
+{
+    int incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+    }
+    total = __shfl(incl, 63, 64);
+    return incl - v;
+}
+
+// largest lane L with excl(L) <= x (excl non-decreasing over the lanes); the
+// segment of item x has at least one item since excl(L + 1) > x
+__device__ inline int wave_find(int excl, int x)
+{
+    int lo = 0;
+#pragma unroll
+    for (int step = 32; step >= 1; step >>= 1) {
+        const int e = __shfl(excl, lo + step, 64);
+        if (e <= x) lo += step;
+    }
+    return lo;
+}
+
 template <class R> struct Cx;
 template <> struct Cx<double> {
     using c2 = double2;

@@ -263,6 +263,43 @@ __global__ __launch_bounds__(256) void k_downward(int64_t lo, int64_t hi, int le
 #pragma unroll
             for (int i = 0; i < 4; ++i) L.Y[(mt * 16 + V4T<R>::row(i, g4)) * 64 + nt * 16 + r] = acc[i];
         }
+    // P2L from the stars of interaction squares that are not nodes (parts of
+    // coarser leaves): c_l += -m / (l zeta^l).  Lanes take the stars, the
+    // powers zeta^-l follow by one product per order, and each order's sum
+    // over the wavefront lands in lane l.
+    double cx, cy, Lh, invL;
+    node_geom(c, lev, L0, cx, cy, Lh, invL);
+    C2 p2l = Cx<R>::make(0, 0);
+    {
+        const int cnt = (lane < NLIST && en.src == -1) ? en.shi - en.slo : 0;
+        int total;
+        const int excl = wave_excl_scan(cnt, lane, total);
+        for (int base = 0; base < total; base += 64) {
+            const int item = base + lane;
+            const int E = wave_find(excl, item);
+            const int s = __shfl(en.slo, E, 64) + item - __shfl(excl, E, 64);
+            C2 w = Cx<R>::make(0, 0);
+            R mq = 0;
+            if (item < total) {
+                w = cinv(Cx<R>::make((R)((sx[s] - cx) * invL), (R)((sy[s] - cy) * invL)));
+                mq = -(R)sm[s];
+            }
+            C2 t = cscale(w, mq);   // -m zeta^-1
+            for (int k = 1; k <= p; ++k) {
+                R vx = t.x, vy = t.y;
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) {
+                    vx += __shfl_xor(vx, o, 64);
+                    vy += __shfl_xor(vy, o, 64);
+                }
+                if (lane == k) {
+                    p2l.x += vx;
+                    p2l.y += vy;
+                }
+                t = cmul(t, w);
+            }
+        }
+    }
     wave_sync();
     // coefficient l = lane
     const int l = lane;
@@ -292,20 +329,8 @@ __global__ __launch_bounds__(256) void k_downward(int64_t lo, int64_t hi, int le
         acc.x += t.x * yr - t.y * yi;
         acc.y += t.x * yi + t.y * yr;
     }
-    // P2L: c_l += -m_i / (l zeta_i^l)
-    double cx, cy, Lh, invL;
-    node_geom(c, lev, L0, cx, cy, Lh, invL);
-    for (int e = 0; e < NLIST; ++e) {
-        const IEntry ei = list[e];
-        if (ei.src != -1) continue;
-        for (int32_t s = ei.slo; s < ei.shi; ++s) {
-            const C2 z = Cx<R>::make((R)((sx[s] - cx) * invL), (R)((sy[s] - cy) * invL));
-            const C2 w = cpowi(cinv(z), l);
-            const R f = -(R)sm[s] / (R)l;
-            acc.x += f * w.x;
-            acc.y += f * w.y;
-        }
-    }
+    acc.x += p2l.x * il;
+    acc.y += p2l.y * il;
     local[q * P1 + l] = acc;
 }
 
