@@ -184,8 +184,8 @@ template <> struct V4T<float> {
 };
 
 template <class R> struct DownLds {
-    R B[32 * 64];          // scaled source coefficients: row k - 1, columns (2 s, 2 s + 1) = (re, im) of source s
-    R Y[32 * 64];          // P B
+    R B[32 * 64];          // scaled source coefficients: row k - 1, columns (2 s, 2 s + 1) = (re, im) of
+                           // source s; then, in place, P B
     typename Cx<R>::c2 b0[32];
     int off[32], src[32];
 };
@@ -203,7 +203,7 @@ __device__ inline void wave_sync()
 // cores, the scalings on the vector units), P2L from the stars of
 // interaction squares inside coarser leaves
 template <class R>
-__global__ __launch_bounds__(256) void k_downward(int64_t lo, int64_t hi, int lev, int p, double L0,
+__global__ __launch_bounds__(64) void k_downward(int64_t lo, int64_t hi, int lev, int p, double L0,
                                                   const uint64_t *__restrict__ code, const int32_t *__restrict__ parent,
                                                   const IEntry *__restrict__ ilist, const double *__restrict__ sx,
                                                   const double *__restrict__ sy, const double *__restrict__ sm,
@@ -215,11 +215,10 @@ __global__ __launch_bounds__(256) void k_downward(int64_t lo, int64_t hi, int le
 {
     using C2 = typename Cx<R>::c2;
     using V4 = typename V4T<R>::t;
-    __shared__ DownLds<R> lds[4];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t q = lo + (int64_t)blockIdx.x * 4 + wave;
-    if (q >= hi) return;   // wavefront-uniform: the wavefronts share no barrier
-    DownLds<R> &L = lds[wave];
+    __shared__ DownLds<R> L;   // one wavefront per workgroup and node
+    const int lane = threadIdx.x;
+    const int64_t q = lo + (int64_t)blockIdx.x;
+    if (q >= hi) return;
     const int P1 = p + 1;
     const uint64_t c = code[q];
     // the node's M2L sources into slots 0 .. ns-1 (lanes 0..26 hold the entries)
@@ -249,20 +248,24 @@ __global__ __launch_bounds__(256) void k_downward(int64_t lo, int64_t hi, int le
         L.B[k1 * 64 + 2 * s2 + 1] = im;
     }
     wave_sync();
-    // Y = P B on the matrix cores
+    // Y = P B on the matrix cores, in place: a 16-column block of B is read
+    // whole (both 16-row tiles of P) before Y's block overwrites it
     const int mt_n = (p + 15) / 16, kt_n = (p + 3) / 4;
     const int r = lane & 15, g4 = lane >> 4;
-    for (int mt = 0; mt < mt_n; ++mt)
-        for (int nt = 0; nt < ncol / 16; ++nt) {
-            V4 acc = {};
-            for (int ks = 0; ks < kt_n; ++ks) {
-                const R a = Pm[(mt * 16 + r) * 32 + ks * 4 + g4];
-                const R b = L.B[(ks * 4 + g4) * 64 + nt * 16 + r];
-                acc = mma16(a, b, acc);
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) L.Y[(mt * 16 + V4T<R>::row(i, g4)) * 64 + nt * 16 + r] = acc[i];
+    for (int nt = 0; nt < ncol / 16; ++nt) {
+        V4 acc0 = {}, acc1 = {};
+        for (int ks = 0; ks < kt_n; ++ks) {
+            const R b = L.B[(ks * 4 + g4) * 64 + nt * 16 + r];
+            acc0 = mma16(Pm[r * 32 + ks * 4 + g4], b, acc0);
+            if (mt_n > 1) acc1 = mma16(Pm[(16 + r) * 32 + ks * 4 + g4], b, acc1);
         }
+        wave_sync();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            L.B[V4T<R>::row(i, g4) * 64 + nt * 16 + r] = acc0[i];
+            if (mt_n > 1) L.B[(16 + V4T<R>::row(i, g4)) * 64 + nt * 16 + r] = acc1[i];
+        }
+    }
     // P2L from the stars of interaction squares that are not nodes (parts of
     // coarser leaves): c_l += -m / (l zeta^l).  Lanes take the stars, the
     // powers zeta^-l follow by one product per order, and each order's sum
@@ -324,8 +327,8 @@ __global__ __launch_bounds__(256) void k_downward(int64_t lo, int64_t hi, int le
     const R il = (R)1 / (R)l;
     for (int s2 = 0; s2 < ns; ++s2) {
         const C2 t = Tf[L.off[s2] * 32 + l];
-        const R yr = L.Y[(l - 1) * 64 + 2 * s2] - L.b0[s2].x * il;
-        const R yi = L.Y[(l - 1) * 64 + 2 * s2 + 1] - L.b0[s2].y * il;
+        const R yr = L.B[(l - 1) * 64 + 2 * s2] - L.b0[s2].x * il;
+        const R yi = L.B[(l - 1) * 64 + 2 * s2 + 1] - L.b0[s2].y * il;
         acc.x += t.x * yr - t.y * yi;
         acc.y += t.x * yi + t.y * yr;
     }
@@ -451,7 +454,7 @@ void run_fmm_t(mlm_lens *lens, Tree &T, int p, hipStream_t st, typename Cx<R>::c
     hipLaunchKernelGGL(k_zero2<C2>, dim3(nblocks(top * P1)), dim3(BLK), 0, st, local, top * P1);
     for (int lev = 2; lev < T.nlevels; ++lev) {
         const int64_t lo = T.level_lo[lev], hi = T.level_hi[lev];
-        hipLaunchKernelGGL(k_downward<R>, dim3((unsigned)((hi - lo + 3) / 4)), dim3(256), 0, st, lo, hi, lev, p, T.L0,
+        hipLaunchKernelGGL(k_downward<R>, dim3((unsigned)(hi - lo)), dim3(64), 0, st, lo, hi, lev, p, T.L0,
                            T.code, T.parent, T.ilist, T.x, T.y, T.m, Sf, Tf, Pm, ws.ops_l2l.as<C2>(), mult, local);
     }
 }
