@@ -181,7 +181,7 @@ struct Tree {
 
 struct Workspace {
     DevBuf keys_in, keys, idx_in, idx, sx, sy, sm, cub_tmp;
-    DevBuf code, level, leaf, slo, shi, block, parent, child0, node_leaf, leaf_node, flags, offs;
+    DevBuf code, level, leaf, slo, shi, block, parent, child0, coll, node_leaf, leaf_node, flags, offs;
     DevBuf ilist, mult, local, ops_m2m, ops_m2l, ops_l2l;
     DevBuf leaves, near, deriv, near_offs;
     DevBuf tile_off, tile_leaf, verts, map, wbuf, pts, counters, items, itemoff, nbig, bigoff, bigprep, bigrows, rowoff, nbnd, nbndoff, diff, bandcnt, bandoff,

@@ -4,8 +4,12 @@
 // so the stars of any square of any level are one contiguous range of the
 // sorted array.  The tree is then built level by level from the root: a node
 // is divided into four children when the stars of its 3x3 block of
-// same-level squares (the node and its neighbours) exceed nmax.  Counting the
-// block needs only binary searches in the sorted keys.
+// same-level squares (the node and its neighbours) exceed nmax.  A divided
+// node always gets all four children, so every square of a level inside the
+// root is a node or lies inside a leaf of a coarser level; each node keeps its
+// 3x3 neighbourhood as such references ("colleagues"), found from its
+// parent's in O(1), and the block count and the interaction lists follow
+// from them without searching the whole key array.
 #include <hipcub/hipcub.hpp>
 
 #include "dev.hpp"
@@ -46,27 +50,86 @@ __global__ void k_root(uint64_t *code, int32_t *level, int32_t *parent)
     parent[0] = -1;
 }
 
-// star range of the node's square and the star count of its 3x3 block
-__global__ void k_level(int64_t lo, int64_t hi, int lev, int lmax, int nmax,
-                        const uint64_t *__restrict__ code, const uint64_t *__restrict__ keys, int32_t n,
-                        int32_t *__restrict__ slo, int32_t *__restrict__ shi, int32_t *__restrict__ block,
-                        int32_t *__restrict__ split)
+// star range of each node's square: a sub-range of its parent's
+__global__ void k_level(int64_t lo, int64_t hi, int lev, const uint64_t *__restrict__ code,
+                        const int32_t *__restrict__ parent, const uint64_t *__restrict__ keys, int32_t n,
+                        int32_t *__restrict__ slo, int32_t *__restrict__ shi)
 {
-    int64_t q = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t q = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= hi) return;
-    uint64_t c = code[q];
-    uint32_t i = compact_bits(c), j = compact_bits(c >> 1);
-    int sh = 2 * (KEY_BITS - lev);
-    slo[q] = lower_bound_u64(keys, n, c << sh);
-    shi[q] = lower_bound_u64(keys, n, (c + 1) << sh);
-    int64_t side = 1ll << lev;
+    if (lev == 0) {
+        slo[q] = 0;
+        shi[q] = n;
+        return;
+    }
+    const uint64_t c = code[q];
+    const int sh = 2 * (KEY_BITS - lev);
+    const int32_t pq = parent[q], a = slo[pq], b = shi[pq];
+    const int32_t s0 = a + lower_bound_u64(keys + a, b - a, c << sh);
+    slo[q] = s0;
+    shi[q] = s0 + lower_bound_u64(keys + s0, b - s0, (c + 1) << sh);
+}
+
+// A colleague reference: >= 0 a node of the same level, -1 nothing (outside
+// the root), <= -2 the leaf -(ref + 2) of a coarser level containing the square.
+// Stars of square `sc` (level shift sh) inside the reference's range.
+__device__ inline void ref_stars(int32_t ref, uint64_t sc, int sh, const int32_t *__restrict__ slo,
+                                 const int32_t *__restrict__ shi, const uint64_t *__restrict__ keys, int32_t &s0,
+                                 int32_t &s1)
+{
+    s0 = s1 = 0;
+    if (ref >= 0) {
+        s0 = slo[ref];
+        s1 = shi[ref];
+    } else if (ref <= -2) {
+        const int32_t L = -ref - 2, a = slo[L], b = shi[L];
+        s0 = a + lower_bound_u64(keys + a, b - a, sc << sh);
+        s1 = s0 + lower_bound_u64(keys + s0, b - s0, (sc + 1) << sh);
+    }
+}
+
+// square (a, b) of level lev, one of the children of the parent-level
+// reference pc: its own reference
+__device__ inline int32_t child_ref(int32_t pc, uint32_t a, uint32_t b, const int32_t *__restrict__ child0)
+{
+    if (pc == -1) return -1;
+    if (pc <= -2) return pc;
+    const int32_t c0 = child0[pc];
+    return c0 >= 0 ? c0 + (int32_t)((a & 1u) | ((b & 1u) << 1)) : -(pc + 2);
+}
+
+// colleagues of each node (from its parent's), the star count of its 3x3
+// block and whether it is divided
+__global__ void k_block(int64_t lo, int64_t hi, int lev, int lmax, int nmax, const uint64_t *__restrict__ code,
+                        const int32_t *__restrict__ parent, const int32_t *__restrict__ child0,
+                        const int32_t *__restrict__ slo, const int32_t *__restrict__ shi,
+                        const uint64_t *__restrict__ keys, int32_t *__restrict__ coll,
+                        int32_t *__restrict__ block, int32_t *__restrict__ split)
+{
+    const int64_t q = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= hi) return;
+    const uint64_t c = code[q];
+    const int64_t i = compact_bits(c), j = compact_bits(c >> 1), side = 1ll << lev;
+    const int sh = 2 * (KEY_BITS - lev);
+    const int32_t pq = lev > 0 ? parent[q] : -1;
     int32_t blk = 0;
     for (int dj = -1; dj <= 1; ++dj)
         for (int di = -1; di <= 1; ++di) {
-            int64_t a = (int64_t)i + di, b = (int64_t)j + dj;
-            if (a < 0 || b < 0 || a >= side || b >= side) continue;
-            uint64_t cc = morton2((uint32_t)a, (uint32_t)b);
-            blk += lower_bound_u64(keys, n, (cc + 1) << sh) - lower_bound_u64(keys, n, cc << sh);
+            const int64_t a = i + di, b = j + dj;
+            int32_t ref = -1;
+            if (a >= 0 && b >= 0 && a < side && b < side) {
+                if (lev == 0) {
+                    ref = (int32_t)q;
+                } else {
+                    const int k = (int)((b >> 1) - (j >> 1) + 1) * 3 + (int)((a >> 1) - (i >> 1) + 1);
+                    ref = child_ref(coll[(int64_t)pq * 9 + k], (uint32_t)a, (uint32_t)b, child0);
+                }
+            }
+            coll[q * 9 + (dj + 1) * 3 + (di + 1)] = ref;
+            int32_t s0, s1;
+            ref_stars(ref, morton2((uint32_t)(a < 0 ? 0 : a), (uint32_t)(b < 0 ? 0 : b)), sh, slo, shi, keys, s0,
+                      s1);
+            blk += s1 - s0;
         }
     block[q] = blk;
     split[q - lo] = (blk > nmax && lev < lmax) ? 1 : 0;
@@ -112,63 +175,52 @@ __global__ void k_leaf_index(int64_t nnodes, const int32_t *__restrict__ leaf,
 
 __global__ void k_zero_first(int64_t *p) { p[0] = 0; }
 
-struct LevelRanges {
-    int64_t lo[KEY_BITS + 2], hi[KEY_BITS + 2];
-};
-
-__device__ inline int64_t find_code(const uint64_t *code, int64_t lo, int64_t hi, uint64_t v)
-{
-    int64_t a = lo, b = hi;
-    while (a < b) {
-        int64_t mid = (a + b) >> 1;
-        if (code[mid] < v) a = mid + 1;
-        else b = mid;
-    }
-    return (a < hi && code[a] == v) ? a : -1;
-}
-
 // interaction squares of every node of level >= 2: the children of the
-// parent's 3x3 block that are outside the node's own 3x3 block (27 of them)
-__global__ void k_ilist(int64_t lo, int64_t hi, LevelRanges lr, const uint64_t *__restrict__ code,
-                        const int32_t *__restrict__ level, const uint64_t *__restrict__ keys,
-                        int32_t n, IEntry *__restrict__ list)
+// parent's 3x3 block that are outside the node's own 3x3 block (27 of them),
+// read from the parent's colleagues: a node (M2L), a part of a leaf (P2L from
+// its stars in the square) or nothing
+__global__ void k_ilist(int64_t lo, int64_t hi, const uint64_t *__restrict__ code,
+                        const int32_t *__restrict__ level, const int32_t *__restrict__ parent,
+                        const int32_t *__restrict__ child0, const int32_t *__restrict__ slo,
+                        const int32_t *__restrict__ shi, const uint64_t *__restrict__ keys,
+                        const int32_t *__restrict__ coll, IEntry *__restrict__ list)
 {
-    int64_t q = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t q = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= hi) return;
-    int lev = level[q];
-    uint64_t c = code[q];
-    int64_t i = compact_bits(c), j = compact_bits(c >> 1);
-    int64_t pi = i >> 1, pj = j >> 1, side = 1ll << lev;
-    int sh = 2 * (KEY_BITS - lev);
+    const int lev = level[q];
+    const uint64_t c = code[q];
+    const int64_t i = compact_bits(c), j = compact_bits(c >> 1);
+    const int64_t pi = i >> 1, pj = j >> 1;
+    const int sh = 2 * (KEY_BITS - lev);
+    const int32_t *pc = coll + (int64_t)parent[q] * 9;
     int e = 0;
-    for (int64_t qj = pj - 1; qj <= pj + 1; ++qj)
-        for (int64_t qi = pi - 1; qi <= pi + 1; ++qi)
+    for (int qj = -1; qj <= 1; ++qj)
+        for (int qi = -1; qi <= 1; ++qi) {
+            const int32_t pref = pc[(qj + 1) * 3 + (qi + 1)];
             for (int cj = 0; cj < 2; ++cj)
                 for (int ci = 0; ci < 2; ++ci) {
-                    int64_t si = 2 * qi + ci, sj = 2 * qj + cj;
-                    int64_t dx = si - i, dy = sj - j;
+                    const int64_t si = 2 * (pi + qi) + ci, sj = 2 * (pj + qj) + cj;
+                    const int64_t dx = si - i, dy = sj - j;
                     if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) continue;
                     IEntry en;
                     en.off = (int32_t)((dx + 3) + 7 * (dy + 3));
                     en.src = -2;
                     en.slo = en.shi = 0;
-                    if (si >= 0 && sj >= 0 && si < side && sj < side) {
-                        uint64_t sc = morton2((uint32_t)si, (uint32_t)sj);
-                        int64_t s = find_code(code, lr.lo[lev], lr.hi[lev], sc);
-                        if (s >= 0) {
-                            en.src = (int32_t)s;
-                        } else {
-                            int32_t a = lower_bound_u64(keys, n, sc << sh);
-                            int32_t b = lower_bound_u64(keys, n, (sc + 1) << sh);
-                            if (b > a) {
-                                en.src = -1;
-                                en.slo = a;
-                                en.shi = b;
-                            }
+                    const int32_t ref = child_ref(pref, (uint32_t)si, (uint32_t)sj, child0);
+                    if (ref >= 0) {
+                        en.src = ref;
+                    } else if (ref <= -2) {
+                        int32_t s0, s1;
+                        ref_stars(ref, morton2((uint32_t)si, (uint32_t)sj), sh, slo, shi, keys, s0, s1);
+                        if (s1 > s0) {
+                            en.src = -1;
+                            en.slo = s0;
+                            en.shi = s1;
                         }
                     }
                     list[(q - lo) * NLIST + e++] = en;
                 }
+        }
 }
 
 template <class T>
@@ -288,6 +340,7 @@ void build_tree(mlm_lens *lens, const Region &R, const mlm_map_request &req, Tre
     T.level_lo.assign(1, 0);
     T.level_hi.assign(1, 1);
     size_t used = 0;
+    int32_t *coll = nullptr;   // 9 colleague references per node
     auto ensure = [&](size_t need) {
         T.code = grow_keep<uint64_t>(ws.code, used, need, st);
         T.level = grow_keep<int32_t>(ws.level, used, need, st);
@@ -297,6 +350,7 @@ void build_tree(mlm_lens *lens, const Region &R, const mlm_map_request &req, Tre
         T.block = grow_keep<int32_t>(ws.block, used, need, st);
         T.parent = grow_keep<int32_t>(ws.parent, used, need, st);
         T.child0 = grow_keep<int32_t>(ws.child0, used, need, st);
+        coll = grow_keep<int32_t>(ws.coll, 9 * used, 9 * need, st);
     };
     ensure(1024);
     hipLaunchKernelGGL(k_root, dim3(1), dim3(1), 0, st, T.code, T.level, T.parent);
@@ -305,8 +359,10 @@ void build_tree(mlm_lens *lens, const Region &R, const mlm_map_request &req, Tre
         int64_t lo = T.level_lo[lev], hi = T.level_hi[lev], nl = hi - lo;
         int32_t *flags = static_cast<int32_t *>(ws.flags.reserve(nl * 4));
         int32_t *offs = static_cast<int32_t *>(ws.offs.reserve(nl * 4));
-        hipLaunchKernelGGL(k_level, dim3(nblocks(nl)), dim3(BLK), 0, st, lo, hi, lev, T.lmax, T.nmax,
-                           T.code, T.keys, n, T.slo, T.shi, T.block, flags);
+        hipLaunchKernelGGL(k_level, dim3(nblocks(nl)), dim3(BLK), 0, st, lo, hi, lev, T.code, T.parent, T.keys, n,
+                           T.slo, T.shi);
+        hipLaunchKernelGGL(k_block, dim3(nblocks(nl)), dim3(BLK), 0, st, lo, hi, lev, T.lmax, T.nmax, T.code,
+                           T.parent, T.child0, T.slo, T.shi, T.keys, coll, T.block, flags);
         int64_t nsplit = scan_total(lens, flags, offs, nl, st);
         if (hi + 4 * nsplit > (int64_t)INT32_MAX) fail(MLM_ERANGE, "tree too large");
         ensure((size_t)(hi + 4 * nsplit));
@@ -333,14 +389,9 @@ void build_tree(mlm_lens *lens, const Region &R, const mlm_map_request &req, Tre
     // 4. interaction lists of the nodes of levels >= 2
     T.ilist = static_cast<IEntry *>(ws.ilist.reserve((size_t)T.nnodes * NLIST * sizeof(IEntry)));
     if (T.nlevels > 2) {
-        LevelRanges lr{};
-        for (int l = 0; l < T.nlevels; ++l) {
-            lr.lo[l] = T.level_lo[l];
-            lr.hi[l] = T.level_hi[l];
-        }
         int64_t lo = T.level_lo[2], hi = T.nnodes;
-        hipLaunchKernelGGL(k_ilist, dim3(nblocks(hi - lo)), dim3(BLK), 0, st, lo, hi, lr, T.code,
-                           T.level, T.keys, n, T.ilist + lo * NLIST);
+        hipLaunchKernelGGL(k_ilist, dim3(nblocks(hi - lo)), dim3(BLK), 0, st, lo, hi, T.code, T.level, T.parent,
+                           T.child0, T.slo, T.shi, T.keys, coll, T.ilist + lo * NLIST);
     }
 }
 
