@@ -27,12 +27,14 @@ if ROOT not in sys.path:
 METRIC = "rays/sec and maps/hour on 1 MI355X at ≤1e-4 pixel error; plain vs mixed/batched"
 FP64_VECTOR_PEAK_TFLOPS = 78.6          # MI355X FP64 vector, dense
 
-# HBM traffic of one k_band launch on this workload, from two rocprofv3 --pmc
-# passes (FETCH_SIZE, WRITE_SIZE) scaled by the same counters' reading of a
-# plain 1 GiB device copy (--copy-check); valid only for the IPM source it was
+# HBM traffic of one launch of each IPM kernel on this workload, from two
+# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), scaled by
+# the same counters' reading of a plain 1 GiB device copy (--copy-check):
+# FETCH_SIZE x 2.0, WRITE_SIZE x 1.0.  Valid only for the IPM source they were
 # taken with, identified by its SHA-256 prefix.
-BAND_TRAFFIC = {"fetch_bytes": 3034635.5 * 1024 * 2.0, "write_bytes": 31265.625 * 1024 * 1.0,
-                "ipm_sha256": "618a91275048ced6"}
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+IPM_TRAFFIC = {"ipm_sha256": "5d5f852261b04c2f",                     # (fetch KiB, write KiB)
+               "k_ipm": (719966.5625, 4497661.09375), "k_band": (2260970.1875, 31250.0)}
 
 
 def file_sha(path: str) -> str:
@@ -54,11 +56,24 @@ def shoot_flops(stats: dict) -> float:
 def band_flops(stats: dict) -> float:
     """Algorithmic FP64 flops of the per-band IPM kernel for one map:
     30 per (large triangle, pixel row) item (3 edges clipped to the row, 2
-    crossings x 3 each; for the ~2 edges present: extent, width, inverse and
-    deposit factor, 6 each) and 10 per column difference deposited (one
-    clamp integral 7, the scaled difference 2, the change from the previous
-    column 1)."""
-    return 30.0 * stats["n_band_rows"] + 10.0 * stats["n_band_pieces"]
+    crossings x 3 each; for the ~2 edges present: extent, first and last
+    column and deposit factor, 6 each) and 6 per column difference deposited
+    (the squared distance 2 and its factor 1, the difference of two terms 1,
+    the change from the previous column 1, the column boundary 1)."""
+    return 30.0 * stats["n_band_rows"] + 6.0 * stats["n_band_pieces"]
+
+
+def cells_flops(stats: dict) -> float:
+    """Algorithmic FP64 flops of the per-cell IPM kernel for one map: 18 per
+    cell (twice the signed area of both triangles, 9 each), 55 per triangle
+    inside a 2 x 2 pixel box (local coordinates 6, area 9, weight 1, the part
+    below v = 1 7, the corner cut by u = 1 and the part left of it 8, the
+    corner's vertices and its part below v = 1 16, four pieces 8), 21 per
+    (triangle, pixel column) item (3 edges clipped to the column, 7 each) and
+    29 per pixel piece (the area below the next row line from 3 clipped
+    edges, 26; the piece and its deposit, 3)."""
+    return (18.0 * stats["n_cells"] + 55.0 * stats["n_small"] + 21.0 * stats["n_col_items"]
+            + 29.0 * stats["n_col_pieces"])
 
 
 def mixed_variant(lens, spec, out, ref) -> dict:
@@ -206,6 +221,9 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / args.steps
+    # one more map, untimed, for the IPM kernels' work counts (timing 2)
+    _, counts = lens.map(out=out, timing=2, **spec)
+    torch.cuda.synchronize()
     rays = stats[0]["n_rays"]
     value = rays / (ms * 1e-3)
 
@@ -217,15 +235,27 @@ def main():
     shoot_roof = {"bound": "alu", "achieved": flops / (t_shoot * 1e-3) / 1e12, "peak": FP64_VECTOR_PEAK_TFLOPS,
                   "unit": "TFLOP/s", "kernel": "k_shoot", "launch_ms": t_shoot}
     shoot_roof["frac"] = shoot_roof["achieved"] / shoot_roof["peak"]
-    # dominant kernel: the per-band IPM pass (one launch per map on this workload)
-    traffic = None
-    if BAND_TRAFFIC and BAND_TRAFFIC["ipm_sha256"] == file_sha(IPM_SRC):
-        traffic = BAND_TRAFFIC["fetch_bytes"] + BAND_TRAFFIC["write_bytes"]
-    band_roof = {"bound": "alu", "achieved": band_flops(stats[0]) / (t_band * 1e-3) / 1e12,
-                 "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "traffic": traffic, "kernel": "k_band",
+    # the two IPM kernels (one launch each per map on this workload); the
+    # headline roofline is the one that takes longer
+    fresh = IPM_TRAFFIC["ipm_sha256"] == file_sha(IPM_SRC)
+
+    def traffic(kernel):
+        t = IPM_TRAFFIC.get(kernel) if fresh else None
+        return None if t is None else (t[0] * FETCH_SCALE + t[1] * WRITE_SCALE) * 1024.0
+
+    t_cells = avg("t_cells_ms")
+    cells_roof = {"bound": "alu", "achieved": cells_flops(counts) / (t_cells * 1e-3) / 1e12,
+                  "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "traffic": traffic("k_ipm"), "kernel": "k_ipm",
+                  "launch_ms": t_cells, "launches_per_step": stats[0]["n_ipm_launches"],
+                  "cells": counts["n_cells"], "small_triangles": counts["n_small"],
+                  "column_items": counts["n_col_items"], "pieces": counts["n_col_pieces"]}
+    cells_roof["frac"] = cells_roof["achieved"] / cells_roof["peak"]
+    band_roof = {"bound": "alu", "achieved": band_flops(counts) / (t_band * 1e-3) / 1e12,
+                 "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "traffic": traffic("k_band"), "kernel": "k_band",
                  "launch_ms": t_band, "launches_per_step": stats[0]["n_ipm_launches"],
-                 "row_items": stats[0]["n_band_rows"], "pieces": stats[0]["n_band_pieces"]}
+                 "row_items": counts["n_band_rows"], "pieces": counts["n_band_pieces"]}
     band_roof["frac"] = band_roof["achieved"] / band_roof["peak"]
+    roof, other = (cells_roof, band_roof) if t_cells >= t_band else (band_roof, cells_roof)
     line = {
         "metric": METRIC,
         "value": value,
@@ -245,12 +275,13 @@ def main():
         "maps_per_hour": 3600.0 / (ms * 1e-3),
         "stages_ms": {"tree": avg("t_tree_ms"), "fmm": avg("t_fmm_ms"), "shoot": t_shoot, "ipm": t_ipm,
                       "ipm_cells": avg("t_cells_ms"), "ipm_band": t_band, "total_device": avg("t_total_ms")},
-        "roofline": band_roof,
+        "roofline": roof,
+        "roofline_" + other["kernel"]: other,
         "roofline_shoot": shoot_roof,
         "tree": {"nodes": stats[0]["n_nodes"], "leaves": stats[0]["n_leaves"], "levels": stats[0]["n_levels"],
                  "near_pairs_per_ray": stats[0]["near_pairs"] / rays},
         "ipm": {"triangles": 2 * stats[0]["n_cells"], "row_path_triangles": stats[0]["n_big"],
-                "row_path_rows": stats[0]["n_big_rows"]},
+                "row_path_rows": counts["n_big_rows"]},
     }
     if not args.no_variants:
         variants = {}

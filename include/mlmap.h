@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define MLM_ABI_VERSION 3
+#define MLM_ABI_VERSION 4
 
 typedef enum mlm_status {
     MLM_OK = 0,
@@ -178,7 +178,10 @@ enum { MLM_METHOD_FMM = 0, MLM_METHOD_DIRECT = 1 };
  *   w_out          optional: receives the mapped source positions (y1, y2)
  *                  of the vertex rows row_begin .. row_end (inclusive),
  *                  nray1 per row, interleaved doubles (2 * nr1 * rows).
- *   timing         != 0: record device times of each stage into the stats
+ *   timing         1: record device times of each stage into the stats;
+ *                  2: also count the IPM kernels' work (n_big_rows,
+ *                  n_band_rows, n_band_pieces, n_small, n_col_items,
+ *                  n_col_pieces), which adds a little device work
  */
 typedef struct mlm_map_request {
     double y1c, y2c, hw1, hw2;
@@ -244,8 +247,8 @@ typedef struct mlm_map_stats {
     double t_total_ms;       /* whole call, device time */
     int32_t n_shoot_launches, n_ipm_launches;
     int64_t n_big;           /* triangles apportioned row by row (large mapped area) */
-    int64_t n_big_rows;      /* pixel rows those triangles cover inside the map */
-    /* the following are filled only when req->timing is set */
+    int64_t n_big_rows;      /* pixel rows those triangles cover inside the map (if timing 2) */
+    /* the following are filled only when req->timing is set (counts: timing 2) */
     double t_cells_ms;       /* per-cell IPM kernel (ordinary triangles) */
     double t_band_ms;        /* per-band IPM kernel (large triangles) */
     int64_t n_band_rows;     /* (large triangle, pixel row) pairs the per-band kernel visits */
@@ -255,6 +258,9 @@ typedef struct mlm_map_stats {
     int64_t n_refine_tests;  /* (sub)cells tested, all depths */
     int64_t n_refine_large;  /* (sub)cells left alone for their width */
     double t_refine_ms;      /* features, network and refinement (if timing) */
+    int64_t n_small;         /* triangles within 2 x 2 pixels, apportioned in place (if timing) */
+    int64_t n_col_items;     /* (triangle, pixel column) items of the cell pass (if timing) */
+    int64_t n_col_pieces;    /* pixel pieces those columns evaluate (if timing) */
 } mlm_map_stats;
 
 /*

@@ -82,7 +82,8 @@ class MapStats(C.Structure):
                 ("n_big", C.c_int64), ("n_big_rows", C.c_int64), ("t_cells_ms", C.c_double),
                 ("t_band_ms", C.c_double), ("n_band_rows", C.c_int64), ("n_band_pieces", C.c_int64),
                 ("n_refine_candidates", C.c_int64), ("n_refined", C.c_int64), ("n_refine_tests", C.c_int64),
-                ("n_refine_large", C.c_int64), ("t_refine_ms", C.c_double)]
+                ("n_refine_large", C.c_int64), ("t_refine_ms", C.c_double),
+                ("n_small", C.c_int64), ("n_col_items", C.c_int64), ("n_col_pieces", C.c_int64)]
 
 
 class BatchOpts(C.Structure):

@@ -523,9 +523,12 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
     double *map = q.device_out ? mu : static_cast<double *>(ws.map.reserve(npix * sizeof(double)));
     fill(map, npix, 0.0, st);
     // counters: [0] skipped triangles, [1] ray-star pairs, [2] rays, [3] unused,
-    // [4] band row items, [5] band boundary pieces (the last two if timing)
-    unsigned long long *cnt = static_cast<unsigned long long *>(ws.counters.reserve(8 * sizeof(unsigned long long)));
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, cnt, 8);
+    // [4] band row items, [5] band boundary pieces (if timing), then (if
+    // timing) WORK_SLOTS partial sums each of small triangles, column items
+    // and column pieces
+    constexpr int NCNT = 8 + 3 * WORK_SLOTS;
+    unsigned long long *cnt = static_cast<unsigned long long *>(ws.counters.reserve(NCNT * sizeof(unsigned long long)));
+    hipLaunchKernelGGL(k_zero_u64n, dim3((NCNT + 255) / 256), dim3(256), 0, st, cnt, (int64_t)NCNT);
     int64_t ndiff = (int64_t)q.n2 * (q.n1 + 1);
     double *diff = static_cast<double *>(ws.diff.reserve(ndiff * sizeof(double)));
     fill(diff, ndiff, 0.0, st);
@@ -590,7 +593,8 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
         const int64_t ncells = (R.nr1 - 1) * (r1 - r0);
         int32_t *nbig = static_cast<int32_t *>(ws.nbig.reserve((size_t)ncells * sizeof(int32_t)));
         int64_t *bigoff = static_cast<int64_t *>(ws.bigoff.reserve((size_t)(ncells + 1) * sizeof(int64_t)));
-        launch_ipm(verts, R.nr1, r0, r1, vb0, g, map, cnt, nbig, q.precision == MLM_PREC_MIXED, st);
+        launch_ipm(verts, R.nr1, r0, r1, vb0, g, map, cnt, nbig, q.precision == MLM_PREC_MIXED,
+                   q.timing >= 2 ? cnt + 8 : nullptr, st);
         const int e_cells = tm.mark();
         int e_band0 = -1, e_band1 = -1;
         const int64_t nb = scan_i32_to_i64(lens, nbig, bigoff, ncells, st);
@@ -614,12 +618,12 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
                 MLM_HIP(hipMemcpyAsync(bcur, boffs, (size_t)nbands * sizeof(unsigned long long), hipMemcpyDeviceToDevice, st));
                 launch_band_scatter(nb, prep, rows, bh, nbands, bcur, blist, st);
                 e_band0 = tm.mark();
-                launch_band(nbands, boffs, blist, prep, rows, bh, g, map, q.timing ? cnt + 4 : nullptr, st);
+                launch_band(nbands, boffs, blist, prep, rows, bh, g, map, q.timing >= 2 ? cnt + 4 : nullptr, st);
                 e_band1 = tm.mark();
             } else {
                 launch_big(nb, prep, rows, g, map, diff, st);
             }
-            if (q.timing) {   // statistics only
+            if (q.timing >= 2) {   // statistics only
                 int64_t *rowoff = static_cast<int64_t *>(ws.rowoff.reserve((size_t)nb * sizeof(int64_t)));
                 n_big_rows += scan_total_i64(lens, rows, rowoff, nb, st);
             }
@@ -676,8 +680,8 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
     }
     launch_diff_rows(g, diff, map, st);
     if (!q.device_out) MLM_HIP(hipMemcpyAsync(mu, map, npix * sizeof(double), hipMemcpyDeviceToHost, st));
-    unsigned long long *hc = static_cast<unsigned long long *>(pinned(lens, 8 * sizeof(unsigned long long)));
-    MLM_HIP(hipMemcpyAsync(hc, cnt, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    unsigned long long *hc = static_cast<unsigned long long *>(pinned(lens, NCNT * sizeof(unsigned long long)));
+    MLM_HIP(hipMemcpyAsync(hc, cnt, NCNT * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     int e_end = tm.mark();
     MLM_HIP(hipStreamSynchronize(st));
     if (stats) {
@@ -703,8 +707,13 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
         S.n_big_rows = n_big_rows;
         S.t_cells_ms = t_cells;
         S.t_band_ms = t_band;
-        S.n_band_rows = q.timing ? (int64_t)hc[4] : 0;
-        S.n_band_pieces = q.timing ? (int64_t)hc[5] : 0;
+        S.n_band_rows = q.timing >= 2 ? (int64_t)hc[4] : 0;
+        S.n_band_pieces = q.timing >= 2 ? (int64_t)hc[5] : 0;
+        int64_t wsum[3] = {0, 0, 0};
+        for (int k = 0; k < 3 * WORK_SLOTS; ++k) wsum[k / WORK_SLOTS] += (int64_t)hc[8 + k];
+        S.n_small = wsum[0];
+        S.n_col_items = wsum[1];
+        S.n_col_pieces = wsum[2];
         S.n_refine_candidates = n_cand;
         S.n_refined = n_refined;
         if (refine_stats_zeroed) {

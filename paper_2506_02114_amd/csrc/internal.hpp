@@ -241,8 +241,12 @@ void launch_deflect_points(mlm_lens *lens, const Tree *T, const LensConst &lc, c
                            int64_t n, double *w, hipStream_t st);
 
 // ipm.hip
+// work counts of the per-cell IPM kernel (statistics): WORK_SLOTS partial sums
+// per count, so that the wavefronts' additions rarely meet at one address
+constexpr int WORK_SLOTS = 256;
 void launch_ipm(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int64_t vb0, const MapGeom &g,
-                double *map, unsigned long long *counters, int32_t *nbig, bool mixed, hipStream_t st);
+                double *map, unsigned long long *counters, int32_t *nbig, bool mixed, unsigned long long *work,
+                hipStream_t st);
 void launch_big_gather(int64_t ncells, const int64_t *boff, const double2 *verts, int64_t nr1, int64_t cb0,
                        int64_t vb0, const MapGeom &g, BigPrep *prep, int64_t *rows, hipStream_t st);
 void launch_big(int64_t nbig, const BigPrep *prep, const int64_t *rows, const MapGeom &g, double *map, double *diff,

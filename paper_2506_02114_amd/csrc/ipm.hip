@@ -371,7 +371,7 @@ __device__ inline bool cell_in_one_pixel(P2 v00, P2 v10, P2 v11, P2 v01, const M
 // integer point (fu0, fv0) (formed in FP64), cl = column - fu0; each piece is
 // a difference of the column's cumulative edge sum H at two row lines
 template <class R>
-__device__ inline void column_pieces(const P2 (&Td)[3], const double (&svd)[3], const double (&sud)[3], double cl, double fv0, int i, int j0, int j1,
+__device__ inline int column_pieces(const P2 (&Td)[3], const double (&svd)[3], const double (&sud)[3], double cl, double fv0, int i, int j0, int j1,
                                      double scale, const MapGeom &g, double *map, const Window &w)
 {
     const Pt<R> T[3] = {Pt<R>{(R)Td[0].u, (R)Td[0].v}, Pt<R>{(R)Td[1].u, (R)Td[1].v}, Pt<R>{(R)Td[2].u, (R)Td[2].v}};
@@ -384,7 +384,7 @@ __device__ inline void column_pieces(const P2 (&Td)[3], const double (&svd)[3], 
     col_range(S.e0, cvmin, cvmax);
     col_range(S.e1, cvmin, cvmax);
     col_range(S.e2, cvmin, cvmax);
-    if (cvmin > cvmax) return;
+    if (cvmin > cvmax) return 0;
     // area below v = r inside the column; a piece is the difference of two
     // rows of the column's pieces, clamped to the triangle's in-map rows
     const int ja = (int)fmin(fmax(floor((double)cvmin) + fv0, (double)j0), (double)j1 + 1.0);
@@ -396,6 +396,7 @@ __device__ inline void column_pieces(const P2 (&Td)[3], const double (&svd)[3], 
         h0 = h1;
         if (a2 != 0.0) deposit_w(w, map, g, i, j, scale * a2);
     }
+    return jb >= ja ? jb - ja + 1 : 0;
 }
 
 // What a pixel column of a medium triangle needs, computed once per triangle
@@ -454,15 +455,12 @@ __device__ inline ColSetup shfl_setup(const ColSetup &s, int L)
 
 // pixel column i0 + r of the triangle set up in `c`
 template <bool MIXED>
-__device__ inline void setup_column(const ColSetup &c, int r, const MapGeom &g, double *map, const Window &w)
+__device__ inline int setup_column(const ColSetup &c, int r, const MapGeom &g, double *map, const Window &w)
 {
     const int i = c.i0 + r;
     const double cl = (double)i - c.fu0;
-    if (MIXED && c.fp32) {
-        column_pieces<float>(c.T, c.sv, c.su, cl, c.fv0, i, c.j0, c.j1, c.scale, g, map, w);
-        return;
-    }
-    column_pieces<double>(c.T, c.sv, c.su, cl, c.fv0, i, c.j0, c.j1, c.scale, g, map, w);
+    if (MIXED && c.fp32) return column_pieces<float>(c.T, c.sv, c.su, cl, c.fv0, i, c.j0, c.j1, c.scale, g, map, w);
+    return column_pieces<double>(c.T, c.sv, c.su, cl, c.fv0, i, c.j0, c.j1, c.scale, g, map, w);
 }
 
 // IPM of the ordinary triangles.  A workgroup takes a tile of 16 x 16 cells
@@ -480,7 +478,7 @@ template <bool MIXED>
 __device__ inline void ipm_tile(const double2 *__restrict__ verts, int64_t nr1, int64_t cb0, int64_t nrows,
                                 int64_t vb0, const MapGeom &g, double *__restrict__ map,
                                 unsigned long long *__restrict__ counters, int32_t *__restrict__ nbig, int64_t tile,
-                                double *acc)
+                                double *acc, unsigned long long *__restrict__ work)
 {
     const int64_t ncol = nr1 - 1;
     const int64_t tiles_a = (ncol + CT - 1) / CT;
@@ -501,6 +499,7 @@ __device__ inline void ipm_tile(const double2 *__restrict__ verts, int64_t nr1, 
         w.j0 = (int)fv - WIN / 2;
     }
     __syncthreads();
+    unsigned n_small = 0, n_items = 0, n_pieces = 0;   // work counts (statistics)
     int mcols[2] = {0, 0};      // pixel columns of each medium triangle of the cell (0: none)
     int mi0[2] = {0, 0};
     P2 v00{0.0, 0.0}, v10{0.0, 0.0}, v11{0.0, 0.0}, v01{0.0, 0.0};
@@ -527,6 +526,7 @@ __device__ inline void ipm_tile(const double2 *__restrict__ verts, int64_t nr1, 
                     if (c.small) {
                         const double fu0 = floor(fmin(A.u, fmin(B.u, C.u))), fv0 = floor(fmin(A.v, fmin(B.v, C.v)));
                         small_triangle(A, B, C, fu0, fv0, g, map, w);
+                        ++n_small;
                     } else {
                         mcols[k] = c.cols;
                         mi0[k] = c.i0;
@@ -552,7 +552,19 @@ __device__ inline void ipm_tile(const double2 *__restrict__ verts, int64_t nr1, 
             const int L = wave_find(excl, item);
             const int r = item - __shfl(excl, L, 64);
             const ColSetup c = shfl_setup(own, L);
-            if (item < total) setup_column<MIXED>(c, r, g, map, w);
+            if (item < total) {
+                n_pieces += (unsigned)setup_column<MIXED>(c, r, g, map, w);
+                ++n_items;
+            }
+        }
+    }
+    if (work) {   // one sum per wavefront and count, spread over WORK_SLOTS slots per count
+        unsigned v[3] = {n_small, n_items, n_pieces};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+            if (lane == 0 && v[k]) atomicAdd(work + k * WORK_SLOTS + (tile & (WORK_SLOTS - 1)), (unsigned long long)v[k]);
         }
     }
     __syncthreads();
@@ -569,10 +581,11 @@ __device__ inline void ipm_tile(const double2 *__restrict__ verts, int64_t nr1, 
 template <bool MIXED>
 __global__ __launch_bounds__(256) void k_ipm(const double2 *__restrict__ verts, int64_t nr1, int64_t cb0,
                                              int64_t nrows, int64_t vb0, MapGeom g, double *__restrict__ map,
-                                             unsigned long long *__restrict__ counters, int32_t *__restrict__ nbig)
+                                             unsigned long long *__restrict__ counters, int32_t *__restrict__ nbig,
+                                             unsigned long long *__restrict__ work)
 {
     __shared__ double acc[WIN * WIN];
-    ipm_tile<MIXED>(verts, nr1, cb0, nrows, vb0, g, map, counters, nbig, blockIdx.x, acc);
+    ipm_tile<MIXED>(verts, nr1, cb0, nrows, vb0, g, map, counters, nbig, blockIdx.x, acc, work);
 }
 
 // every cell tile of every map of a fused batch in one launch (one
@@ -587,10 +600,10 @@ __global__ __launch_bounds__(256) void k_ipm_batch(const BatchMap *__restrict__ 
         const BatchMap &d = maps[m];
         if (d.mixed)
             ipm_tile<true>(d.verts, d.nr1, 0, d.nrows, 0, d.g, d.map, d.counters, nbig + d.cell_lo, t - d.ctile_lo,
-                           acc);
+                           acc, nullptr);
         else
             ipm_tile<false>(d.verts, d.nr1, 0, d.nrows, 0, d.g, d.map, d.counters, nbig + d.cell_lo, t - d.ctile_lo,
-                            acc);
+                            acc, nullptr);
     }
 }
 
@@ -1111,17 +1124,18 @@ __global__ __launch_bounds__(64) void k_diff_rows(MapGeom g, const double *__res
 }  // namespace
 
 void launch_ipm(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int64_t vb0, const MapGeom &g,
-                double *map, unsigned long long *counters, int32_t *nbig, bool mixed, hipStream_t st)
+                double *map, unsigned long long *counters, int32_t *nbig, bool mixed, unsigned long long *work,
+                hipStream_t st)
 {
     const int64_t ncol = nr1 - 1, nrows = cb1 - cb0;
     if (ncol <= 0 || nrows <= 0) return;
     const int64_t tiles = ((ncol + CT - 1) / CT) * ((nrows + CT - 1) / CT);
     if (mixed)
         hipLaunchKernelGGL(k_ipm<true>, dim3((unsigned)tiles), dim3(256), 0, st, verts, nr1, cb0, nrows, vb0, g, map,
-                           counters, nbig);
+                           counters, nbig, work);
     else
         hipLaunchKernelGGL(k_ipm<false>, dim3((unsigned)tiles), dim3(256), 0, st, verts, nr1, cb0, nrows, vb0, g, map,
-                           counters, nbig);
+                           counters, nbig, work);
 }
 
 void launch_big_gather(int64_t ncells, const int64_t *boff, const double2 *verts, int64_t nr1, int64_t cb0,

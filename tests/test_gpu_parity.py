@@ -172,6 +172,32 @@ def test_map_small_matches_oracle(mlm, orc):
     assert mu.sum() * ref.region.pix1 * ref.region.pix2 == pytest.approx(ref.dep_total, rel=1e-9)
 
 
+def test_timing_levels_and_work_counts(mlm):
+    """timing 0, 1 and 2 make the same map; only timing 2 fills the IPM
+    kernels' work counts, which obey their definitions' bounds."""
+    wl = W.config("plain_small")
+    sf = wl.stars()
+    gl = mlm.Lens(0.3, 0.0, 0.3, sf.x, sf.y, sf.m)
+    spec = _spec(wl, order=20)
+    maps, stats = [], []
+    for t in (0, 1, 2):
+        mu, st = gl.map(timing=t, **spec)
+        maps.append(mu)
+        stats.append(st)
+    for mu in maps[1:]:
+        pos = maps[0] > 0
+        assert np.all(mu[~pos] == 0.0)
+        assert np.abs(mu[pos] - maps[0][pos]).max() <= 1e-12 * maps[0][pos].max()
+    s1, s2 = stats[1], stats[2]
+    assert s1["t_cells_ms"] > 0 and s1["n_small"] == s1["n_col_items"] == s1["n_col_pieces"] == 0
+    assert s1["n_band_rows"] == 0
+    assert 0 < s2["n_small"] <= 2 * s2["n_cells"]
+    assert 0 < s2["n_col_items"] <= s2["n_col_pieces"]
+    assert s2["n_big_rows"] >= s2["n_big"] and s2["n_band_pieces"] >= 0
+    _report("work_counts_plain_small", cells=s2["n_cells"], small=s2["n_small"], items=s2["n_col_items"],
+            pieces=s2["n_col_pieces"], big=s2["n_big"], band_rows=s2["n_band_rows"])
+
+
 def test_map_device_output_and_stream(mlm, orc):
     import torch
     wl = W.config("plain_small")
