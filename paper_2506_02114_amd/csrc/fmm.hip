@@ -183,8 +183,11 @@ template <> struct V4T<float> {
     __device__ static int row(int i, int g4) { return 4 * g4 + i; }
 };
 
+// row stride of the LDS matrix: one element more than its 64 columns, so the
+// 32 rows of a column fall in different banks
+constexpr int BRS = 65;
 template <class R> struct DownLds {
-    R B[32 * 64];          // scaled source coefficients: row k - 1, columns (2 s, 2 s + 1) = (re, im) of
+    R B[32 * BRS];         // scaled source coefficients: row k - 1, columns (2 s, 2 s + 1) = (re, im) of
                            // source s; then, in place, P B
     typename Cx<R>::c2 b0[32];
     int off[32], src[32];
@@ -244,8 +247,8 @@ __global__ __launch_bounds__(64) void k_downward(int64_t lo, int64_t hi, int lev
             re = b.x * f.x - b.y * f.y;
             im = b.x * f.y + b.y * f.x;
         }
-        L.B[k1 * 64 + 2 * s2] = re;
-        L.B[k1 * 64 + 2 * s2 + 1] = im;
+        L.B[k1 * BRS + 2 * s2] = re;
+        L.B[k1 * BRS + 2 * s2 + 1] = im;
     }
     wave_sync();
     // Y = P B on the matrix cores, in place: a 16-column block of B is read
@@ -255,15 +258,15 @@ __global__ __launch_bounds__(64) void k_downward(int64_t lo, int64_t hi, int lev
     for (int nt = 0; nt < ncol / 16; ++nt) {
         V4 acc0 = {}, acc1 = {};
         for (int ks = 0; ks < kt_n; ++ks) {
-            const R b = L.B[(ks * 4 + g4) * 64 + nt * 16 + r];
+            const R b = L.B[(ks * 4 + g4) * BRS + nt * 16 + r];
             acc0 = mma16(Pm[r * 32 + ks * 4 + g4], b, acc0);
             if (mt_n > 1) acc1 = mma16(Pm[(16 + r) * 32 + ks * 4 + g4], b, acc1);
         }
         wave_sync();
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            L.B[V4T<R>::row(i, g4) * 64 + nt * 16 + r] = acc0[i];
-            if (mt_n > 1) L.B[(16 + V4T<R>::row(i, g4)) * 64 + nt * 16 + r] = acc1[i];
+            L.B[V4T<R>::row(i, g4) * BRS + nt * 16 + r] = acc0[i];
+            if (mt_n > 1) L.B[(16 + V4T<R>::row(i, g4)) * BRS + nt * 16 + r] = acc1[i];
         }
     }
     // P2L from the stars of interaction squares that are not nodes (parts of
@@ -327,8 +330,8 @@ __global__ __launch_bounds__(64) void k_downward(int64_t lo, int64_t hi, int lev
     const R il = (R)1 / (R)l;
     for (int s2 = 0; s2 < ns; ++s2) {
         const C2 t = Tf[L.off[s2] * 32 + l];
-        const R yr = L.B[(l - 1) * 64 + 2 * s2] - L.b0[s2].x * il;
-        const R yi = L.B[(l - 1) * 64 + 2 * s2 + 1] - L.b0[s2].y * il;
+        const R yr = L.B[(l - 1) * BRS + 2 * s2] - L.b0[s2].x * il;
+        const R yi = L.B[(l - 1) * BRS + 2 * s2 + 1] - L.b0[s2].y * il;
         acc.x += t.x * yr - t.y * yi;
         acc.y += t.x * yi + t.y * yr;
     }
