@@ -298,6 +298,13 @@ int tune_leaf_max(mlm_lens *lens, const mlm_map_request &q, const Region &R, hip
     return best;
 }
 
+// p[t] = t
+__global__ void k_iota64(int64_t *p, int64_t n)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = t;
+}
+
 }  // namespace
 }  // namespace mlm
 
@@ -1043,12 +1050,6 @@ mlm_status mlm_refiner_predict(mlm_refiner *r, const float *feats, int64_t n, fl
     if (!device_ptrs) MLM_HIP(hipMemcpyAsync(logits, dl, (size_t)n * sizeof(float), hipMemcpyDeviceToHost, st));
     MLM_HIP(hipStreamSynchronize(st));
     API_END
-}
-
-__global__ void k_iota64(int64_t *p, int64_t n)
-{
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) p[t] = t;
 }
 
 // one forward/backward over rows idx[0, n) into r->G (gradient + loss at [NP])
