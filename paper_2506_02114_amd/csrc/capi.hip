@@ -1,5 +1,6 @@
 // C ABI of the library and the orchestration of a map.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -9,6 +10,7 @@
 #include <mutex>
 #include <new>
 #include <set>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -205,9 +207,13 @@ __global__ void k_map_big_bounds(const BatchMap *maps, int32_t nmaps, int64_t nc
 
 // device buffers of the fused batch passes (one set per process, on the
 // device of the calls; calls are serialised by `mu`)
+// host threads (each with a stream of its own) that prepare a batch's maps
+constexpr int PREP_THREADS = 4;
+
 struct BatchWs {
     std::mutex mu;
     DevBuf maps, verts, nbig, boff, prep, rows, bcnt, boffs, bcur, blist, counters, bounds, slice_map, slice_lo;
+    hipStream_t prep_st[PREP_THREADS] = {};   // created on first use, default priority
 };
 
 BatchWs &batch_ws()
@@ -226,6 +232,7 @@ struct MapPlan {
     double *map = nullptr;
     int64_t nverts = 0, ncells = 0, ntiles = 0, nctiles = 0, nbands = 0;
     int32_t bh = 0;
+    Timer *tm = nullptr;   // the preparing thread's timer, and its marks
     int e_tree0 = -1, e_tree1 = -1, e_fmm1 = -1;
 };
 
@@ -769,33 +776,73 @@ mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, i
         static_cast<unsigned long long *>(B.counters.reserve((size_t)nmaps * 8 * sizeof(unsigned long long)));
     hipLaunchKernelGGL(k_zero_u64n, dim3((unsigned)((nmaps * 8 + 255) / 256)), dim3(256), 0, st, cnt,
                        (int64_t)nmaps * 8);
+    // A tree is built level by level with a host read of each level's size,
+    // so one stream would idle between levels: PREP_THREADS host threads
+    // take the maps in turn, each on a stream of its own that first waits for
+    // the caller's stream.
+    for (hipStream_t &ps : B.prep_st)
+        if (!ps) MLM_HIP(hipStreamCreateWithFlags(&ps, hipStreamNonBlocking));
+    hipEvent_t go;
+    MLM_HIP(hipEventCreateWithFlags(&go, hipEventDisableTiming));
+    MLM_HIP(hipEventRecord(go, st));
+    std::vector<std::unique_ptr<Timer>> ptm;
+    for (int t = 0; t < PREP_THREADS; ++t) ptm.emplace_back(new Timer(tm.on, B.prep_st[t]));
+    std::atomic<int32_t> next{0};
+    std::atomic<bool> failed{false};
+    std::exception_ptr err;
+    std::mutex err_mu;
+    auto prep_worker = [&](int t) {
+        const hipStream_t ps = B.prep_st[t];
+        Timer &pt = *ptm[t];
+        try {
+            MLM_HIP(hipStreamWaitEvent(ps, go, 0));
+            for (int32_t i = next++; i < nmaps && !failed; i = next++) {
+                MapPlan &m = P[i];
+                m.lens = lenses[i];
+                m.q = reqs[i];
+                setup_region(m.lens, &m.q, &m.R);
+                if (m.R.nr1 > INT32_MAX || m.R.nr2 > INT32_MAX) fail(MLM_ERANGE, "map %d: ray grid too large", i);
+                if (o.autotune) m.q.leaf_max = tune_leaf_max(m.lens, m.q, m.R, ps);
+                m.tm = &pt;
+                m.e_tree0 = pt.mark();
+                build_tree(m.lens, m.R, m.q, m.T, ps);
+                m.T.mixed = m.q.precision == MLM_PREC_MIXED;
+                m.e_tree1 = pt.mark();
+                run_fmm(m.lens, m.T, order_for(m.q, m.R, m.T), ps);
+                build_leaf_tables(m.lens, m.T, ps);
+                m.e_fmm1 = pt.mark();
+                m.ntiles = plan_tiles(m.lens, m.T, m.R, 0, m.R.nr2, ps);
+                m.g = map_geom(m.q, m.R);
+                m.lc = lens_const(m.lens, m.R);
+                const int64_t npix = (int64_t)m.q.n1 * m.q.n2;
+                m.map = m.q.device_out ? mus[i] : static_cast<double *>(m.lens->ws.map.reserve(npix * sizeof(double)));
+                fill(m.map, npix, 0.0, ps);
+                m.nverts = m.R.nr1 * m.R.nr2;
+                m.ncells = (m.R.nr1 - 1) * (m.R.nr2 - 1);
+                m.nctiles = ((m.R.nr1 - 1 + 15) / 16) * ((m.R.nr2 - 1 + 15) / 16);
+                m.bh = band_height(m.q.n1, m.q.n2);
+                if (m.bh <= 0)
+                    fail(MLM_ENOTSUP, "map %d: %d x %d pixels is too wide for batched row bands", i, m.q.n1, m.q.n2);
+                m.nbands = (m.q.n2 + m.bh - 1) / m.bh;
+            }
+            MLM_HIP(hipStreamSynchronize(ps));
+        } catch (...) {
+            failed = true;
+            (void)hipStreamSynchronize(ps);
+            std::lock_guard<std::mutex> g(err_mu);
+            if (!err) err = std::current_exception();
+        }
+    };
+    {
+        std::vector<std::thread> pool;
+        for (int t = 1; t < PREP_THREADS; ++t) pool.emplace_back(prep_worker, t);
+        prep_worker(0);
+        for (std::thread &th : pool) th.join();
+    }
+    (void)hipEventDestroy(go);
+    if (err) std::rethrow_exception(err);
     int64_t max_verts = 0, max_band_lds = 0;
-    for (int32_t i = 0; i < nmaps; ++i) {
-        MapPlan &m = P[i];
-        m.lens = lenses[i];
-        m.q = reqs[i];
-        setup_region(m.lens, &m.q, &m.R);
-        if (m.R.nr1 > INT32_MAX || m.R.nr2 > INT32_MAX) fail(MLM_ERANGE, "map %d: ray grid too large", i);
-        if (o.autotune) m.q.leaf_max = tune_leaf_max(m.lens, m.q, m.R, st);
-        m.e_tree0 = tm.mark();
-        build_tree(m.lens, m.R, m.q, m.T, st);
-        m.T.mixed = m.q.precision == MLM_PREC_MIXED;
-        m.e_tree1 = tm.mark();
-        run_fmm(m.lens, m.T, order_for(m.q, m.R, m.T), st);
-        build_leaf_tables(m.lens, m.T, st);
-        m.e_fmm1 = tm.mark();
-        m.ntiles = plan_tiles(m.lens, m.T, m.R, 0, m.R.nr2, st);
-        m.g = map_geom(m.q, m.R);
-        m.lc = lens_const(m.lens, m.R);
-        const int64_t npix = (int64_t)m.q.n1 * m.q.n2;
-        m.map = m.q.device_out ? mus[i] : static_cast<double *>(m.lens->ws.map.reserve(npix * sizeof(double)));
-        fill(m.map, npix, 0.0, st);
-        m.nverts = m.R.nr1 * m.R.nr2;
-        m.ncells = (m.R.nr1 - 1) * (m.R.nr2 - 1);
-        m.nctiles = ((m.R.nr1 - 1 + 15) / 16) * ((m.R.nr2 - 1 + 15) / 16);
-        m.bh = band_height(m.q.n1, m.q.n2);
-        if (m.bh <= 0) fail(MLM_ENOTSUP, "map %d: %d x %d pixels is too wide for batched row bands", i, m.q.n1, m.q.n2);
-        m.nbands = (m.q.n2 + m.bh - 1) / m.bh;
+    for (const MapPlan &m : P) {
         max_verts = std::max(max_verts, m.nverts);
         max_band_lds = std::max<int64_t>(max_band_lds, (int64_t)m.bh * m.q.n1);
     }
@@ -932,8 +979,8 @@ mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, i
             S.order = m.T.p;
             S.n_tiles = m.ntiles;
             S.tri_area = 0.5 * m.R.d1 * m.R.d2;
-            S.t_tree_ms = tm.ms(m.e_tree0, m.e_tree1);
-            S.t_fmm_ms = tm.ms(m.e_tree1, m.e_fmm1);
+            S.t_tree_ms = m.tm ? m.tm->ms(m.e_tree0, m.e_tree1) : 0.0;
+            S.t_fmm_ms = m.tm ? m.tm->ms(m.e_tree1, m.e_fmm1) : 0.0;
             S.n_shoot_launches = S.n_ipm_launches = 0;
             stats[i] = S;
         }
