@@ -134,6 +134,17 @@ def test_batch_errors(mlm):
     with pytest.raises(mlm.MLMError) as e:
         mlm.map_batch([l for l, _ in lenses], [dict(reqs[0], method="direct"), reqs[1]], outs)
     assert e.value.status == mlm.MLM_EINVAL
+    # a map too wide for the row bands fails while the maps are prepared
+    # (on a preparing thread): the error reaches the caller and the batch
+    # machinery stays usable
+    wide = dict(reqs[1], n1=9000, n2=4, hw1=4.5, hw2=0.002)
+    with pytest.raises(mlm.MLMError) as e:
+        mlm.map_batch([l for l, _ in lenses], [reqs[0], wide], [outs[0], np.empty((4, 9000))])
+    assert e.value.status == mlm.MLM_ENOTSUP
+    stats, b = mlm.map_batch([l for l, _ in lenses], reqs, outs)
+    ref, _ = _single(lenses[1][0], reqs[1])
+    pos = ref > 0
+    assert (np.abs(outs[1][pos] - ref[pos]) / ref[pos]).max() < 1e-11
 
 
 def test_batched_workload_draws(mlm, orc):
