@@ -208,7 +208,7 @@ __global__ void k_map_big_bounds(const BatchMap *maps, int32_t nmaps, int64_t nc
 // device buffers of the fused batch passes (one set per process, on the
 // device of the calls; calls are serialised by `mu`)
 // host threads (each with a stream of its own) that prepare a batch's maps
-constexpr int PREP_THREADS = 4;
+constexpr int PREP_THREADS = 8;
 
 struct BatchWs {
     std::mutex mu;
