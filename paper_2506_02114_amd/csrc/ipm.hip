@@ -901,6 +901,18 @@ __device__ inline int64_t xcd_band(int64_t blk, int64_t nb)
     return x < rem ? x * (per + 1) + idx : rem * (per + 1) + (x - rem) * per + idx;
 }
 
+// edge P->Q clipped to the pixel row rl <= v <= rl + 1 (su = du/dv): the u of
+// its ends and its extent dv; false if it has none in the row (an edge with
+// P.v = Q.v included).  Ends inside the row keep their exact u.
+__device__ inline bool row_clip(P2 P, P2 Q, double rl, double su, double &ua, double &ub, double &dv)
+{
+    const double ev = fmin(fmax(P.v, rl), rl + 1.0), xv = fmin(fmax(Q.v, rl), rl + 1.0);
+    ua = ev == P.v ? P.u : P.u + (ev - P.v) * su;
+    ub = xv == Q.v ? Q.u : P.u + (xv - P.v) * su;
+    dv = xv - ev;
+    return dv != 0.0;
+}
+
 // band `band` of one map: its listed triangles are list[r0, r1); bdiff is
 // the workgroup's LDS (bh x n1 doubles), wsum two LDS counters
 __device__ inline void band_rows(int64_t band, int64_t r0, int64_t r1, const int32_t *__restrict__ list,
@@ -915,28 +927,27 @@ __device__ inline void band_rows(int64_t band, int64_t r0, int64_t r1, const int
     const int nrow = (int)min((int64_t)bh, (int64_t)g.n2 - jb0);
     for (int64_t t = threadIdx.x; t < (int64_t)bh * n1; t += blockDim.x) bdiff[t] = 0.0;
     __syncthreads();
-    const int64_t nitems = (r1 - r0) * bh;
-    for (int64_t it = threadIdx.x; it < nitems; it += blockDim.x) {
-        const int64_t k = list[r0 + it / bh];
-        const int rr = (int)(it % bh);
-        if (rr >= nrow) continue;
+    // items (listed triangle, row of the band); bh is a power of two that
+    // divides the workgroup, so a thread keeps its row
+    const int lg = __builtin_ctz((unsigned)bh);
+    const int rr = (int)threadIdx.x & (bh - 1);
+    const int nlist = (int)(r1 - r0);
+    for (int li = (int)threadIdx.x >> lg; li < nlist; li += (int)blockDim.x >> lg) {
+        if (rr >= nrow) break;
+        const int64_t k = list[r0 + li];
         const BigPrep bp = prep[k];
-        const int64_t j = jb0 + rr;
-        if (j < (int64_t)bp.ov || j >= (int64_t)bp.ov + rows[k]) continue;
+        const int j = (int)jb0 + rr, ov = (int)bp.ov;   // ov in [0, n2)
+        if (j < ov || j - ov >= rows[k]) continue;
         ++my_rows;
-        const double rl = (double)j - bp.ov;
+        const double rl = (double)(j - ov);
         const int ou = (int)bp.ou;             // in [0, n1]
         double *drow = bdiff + rr * n1 + ou;   // indexed by local column
         const int cmin = -ou, cmax = (int)n1 - 1 - ou;
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
             const P2 P{bp.u[m], bp.v[m]}, Q{bp.u[(m + 1) % 3], bp.v[(m + 1) % 3]};
-            if (P.v == Q.v) continue;   // no extent along v: contributes nothing
-            P2 E, X;
-            if (!clip_seg<1>(P, Q, rl, rl + 1.0, bp.su[m], E, X)) continue;
-            const double dv = X.v - E.v;
-            if (dv == 0.0) continue;
-            const double ua = E.u, ub = X.u;
+            double ua, ub, dv;
+            if (!row_clip(P, Q, rl, bp.su[m], ua, ub, dv)) continue;
             // first and last column of the clipped edge, clamped to one
             // column beyond the map on either side (which changes nothing
             // below) so they fit 32 bits
@@ -1155,8 +1166,10 @@ void launch_big(int64_t nbig, const BigPrep *prep, const int64_t *rows, const Ma
 
 int band_height(int32_t n1, int32_t n2)
 {
-    int64_t bh = BAND_LDS_DOUBLES / (int64_t)n1;
-    if (bh > 16) bh = 16;
+    // a power of two (at most 16, so it divides the workgroup), as many rows
+    // of the map as the LDS holds
+    int64_t bh = 16;
+    while (bh > 0 && bh * n1 > BAND_LDS_DOUBLES) bh >>= 1;
     // 0: the map is too wide for one band per workgroup, or has too many bands
     // for the binning histograms in LDS
     if (bh > 0 && (n2 + bh - 1) / bh > 12000) bh = 0;
