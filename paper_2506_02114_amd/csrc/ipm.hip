@@ -137,19 +137,20 @@ template <class R> struct ColSegs {
     ColSeg<R> e0, e1, e2;
 };
 
+// edge P->Q clipped to the column lo <= u <= hi, without branches: its ends
+// are clamped into the column (an end inside keeps its exact v); an edge that
+// misses the column clamps to a single point
 template <class R>
 __device__ inline ColSeg<R> col_seg(Pt<R> P, Pt<R> Q, R lo, R hi, R sv, R su)
 {
     ColSeg<R> s;
-    Pt<R> E, X;
-    if (clip_seg<0>(P, Q, lo, hi, sv, E, X)) {
-        s.lo = fmin(E.v, X.v);
-        s.hi = fmax(E.v, X.v);
-        s.d = X.u - E.u;
-    } else {
-        s.lo = s.hi = s.d = R(0);
-    }
-    s.any = s.d != R(0) || s.lo != s.hi;
+    const R eu = fmin(fmax(P.u, lo), hi), xu = fmin(fmax(Q.u, lo), hi);
+    const R ev = eu == P.u ? P.v : P.v + (eu - P.u) * sv;
+    const R xv = xu == Q.u ? Q.v : P.v + (xu - P.u) * sv;
+    s.d = xu - eu;
+    s.any = s.d != R(0) || ev != xv;
+    s.lo = s.any ? fmin(ev, xv) : R(0);
+    s.hi = s.any ? fmax(ev, xv) : R(0);
     s.c = s.d > R(0) ? fabs(su) : (s.d < R(0) ? -fabs(su) : R(0));
     return s;
 }
