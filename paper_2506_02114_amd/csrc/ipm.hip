@@ -201,7 +201,10 @@ constexpr double MIXED_MAX_COND = 256.0;
 
 __device__ inline void deposit(double *map, const MapGeom &g, int i, int j, double val)
 {
-    unsafeAtomicAdd(map + (int64_t)j * g.n1 + i, val);
+    // the map is global memory (also when its pointer was read from a batch
+    // descriptor, where the compiler could not tell): a global, not a flat, atomic
+    auto *gm = (__attribute__((address_space(1))) double *)map;
+    __hip_atomic_fetch_add(gm + (int64_t)j * g.n1 + i, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // pixel window of a workgroup in LDS: deposits inside it are summed there and
@@ -216,8 +219,13 @@ struct Window {
 __device__ inline void deposit_w(const Window &w, double *map, const MapGeom &g, int i, int j, double val)
 {
     const int di = i - w.i0, dj = j - w.j0;
-    if ((unsigned)di < (unsigned)WIN && (unsigned)dj < (unsigned)WIN) atomicAdd(w.acc + dj * WIN + di, val);
-    else deposit(map, g, i, j, val);
+    if ((unsigned)di < (unsigned)WIN && (unsigned)dj < (unsigned)WIN)
+        // workgroup scope: kept apart from the device-scope map deposit, so the
+        // two are not merged into one generic (flat) atomic and this one stays
+        // an LDS atomic
+        __hip_atomic_fetch_add(w.acc + dj * WIN + di, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    else
+        deposit(map, g, i, j, val);
 }
 
 // Classification of one mapped triangle (pixel coordinates) for the cell pass.
@@ -476,7 +484,7 @@ constexpr int CT = 16;   // cells per tile side
 // cell tile `tile` of a strip (a whole workgroup of 256 threads; acc is its
 // WIN x WIN LDS window)
 template <bool MIXED>
-__device__ inline void ipm_tile(const double2 *__restrict__ verts, int64_t nr1, int64_t cb0, int64_t nrows,
+__device__ __forceinline__ void ipm_tile(const double2 *__restrict__ verts, int64_t nr1, int64_t cb0, int64_t nrows,
                                 int64_t vb0, const MapGeom &g, double *__restrict__ map,
                                 unsigned long long *__restrict__ counters, int32_t *__restrict__ nbig, int64_t tile,
                                 double *acc, unsigned long long *__restrict__ work)
