@@ -349,17 +349,26 @@ __device__ inline void small_triangle(P2 A, P2 B, P2 C, double fu0, double fv0, 
     if (cu && cv) put_pixel(w, map, g, i + 1, j + 1, ((S - GL) - (HB - Q)) * inv);
 }
 
+// the corners of the cell in column a of vertex row r (counted in `verts`);
+// the vertices are global memory (also when their pointer was read from a
+// batch descriptor)
+__device__ inline void load_cell_at(const double2 *verts, int64_t nr1, int64_t r, int64_t a, P2 &v00, P2 &v10,
+                                    P2 &v11, P2 &v01)
+{
+    using GD = const __attribute__((address_space(1))) double;
+    GD *r0 = (GD *)verts + 2 * (r * nr1 + a), *r1 = r0 + 2 * nr1;
+    v00 = P2{r0[0], r0[1]};
+    v10 = P2{r0[2], r0[3]};
+    v11 = P2{r1[2], r1[3]};
+    v01 = P2{r1[0], r1[1]};
+}
+
 __device__ inline void load_cell(const double2 *verts, int64_t nr1, int64_t cb0, int64_t vb0, int64_t cell,
                                  P2 &v00, P2 &v10, P2 &v11, P2 &v01)
 {
     const int64_t ncol = nr1 - 1;
     const int64_t a = cell % ncol, b = cb0 + cell / ncol;
-    const double2 *r0 = verts + (b - vb0) * nr1, *r1 = r0 + nr1;
-    const double2 q00 = r0[a], q10 = r0[a + 1], q01 = r1[a], q11 = r1[a + 1];
-    v00 = P2{q00.x, q00.y};
-    v10 = P2{q10.x, q10.y};
-    v11 = P2{q11.x, q11.y};
-    v01 = P2{q01.x, q01.y};
+    load_cell_at(verts, nr1, b - vb0, a, v00, v10, v11, v01);
 }
 
 __device__ inline bool cell_in_one_pixel(P2 v00, P2 v10, P2 v11, P2 v01, const MapGeom &g, int &pi, int &pj)
@@ -514,7 +523,7 @@ __device__ __forceinline__ void ipm_tile(const double2 *__restrict__ verts, int6
     P2 v00{0.0, 0.0}, v10{0.0, 0.0}, v11{0.0, 0.0}, v01{0.0, 0.0};
     if (a < ncol && brow < nrows) {
         const int64_t cell = brow * ncol + a;
-        load_cell(verts, nr1, cb0, vb0, cell, v00, v10, v11, v01);
+        load_cell_at(verts, nr1, cb0 + brow - vb0, a, v00, v10, v11, v01);
         int pi, pj;
         int nb = 0;
         if (cell_in_one_pixel(v00, v10, v11, v01, g, pi, pj)) {
