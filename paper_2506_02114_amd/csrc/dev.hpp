@@ -162,6 +162,19 @@ template <> struct Cx<float> {
 
 // a / b: FP64 division, or a times the FP32 hardware reciprocal (1 ulp)
 __device__ inline double qdiv(double a, double b) { return a / b; }
+
+// a / b for the near-field sum: the hardware reciprocal estimate refined by
+// two Newton steps y <- y + y (1 - b y) (each doubles the correct bits), then
+// one product; within a few ulp of the correctly rounded quotient, and
+// non-finite (as the quotient) when b is 0
+__device__ inline double near_div(double a, double b)
+{
+    double y = __builtin_amdgcn_rcp(b);
+    y = fma(fma(-b, y, 1.0), y, y);
+    y = fma(fma(-b, y, 1.0), y, y);
+    return a * y;
+}
+__device__ inline float near_div(float a, float b) { return qdiv(a, b); }
 __device__ inline float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
 }  // namespace mlm

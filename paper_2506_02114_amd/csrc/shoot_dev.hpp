@@ -51,7 +51,7 @@ __device__ inline void leaf_alpha(double dx, double dy, const LeafInfo &li, cons
     for (int32_t s = 0; s < li.near_cnt; ++s) {
         const double4 st = ns[s];
         const R ex = (R)(dx - st.x), ey = (R)(dy - st.y);
-        const R f = qdiv((R)st.z, ex * ex + ey * ey);
+        const R f = near_div((R)st.z, ex * ex + ey * ey);
         ax += f * ex;
         ay += f * ey;
     }
