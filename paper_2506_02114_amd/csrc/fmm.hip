@@ -238,9 +238,11 @@ __global__ __launch_bounds__(64) void k_downward(int64_t lo, int64_t hi, int lev
     }
     wave_sync();
     // B: b_k (-z0)^-k for k = 1..p (rows k - 1), zero elsewhere up to the tiles used
+    // (only the rows the products read: 16 for p <= 16, else 32)
     const int ncol = ((2 * ns + 15) / 16) * 16;
-    for (int e = lane; e < 32 * ncol / 2; e += 64) {
-        const int k1 = e % 32, s2 = e / 32;   // row k1 = k - 1, source s2
+    const int lgr = p <= 16 ? 4 : 5;
+    for (int e = lane; e < (ncol / 2) << lgr; e += 64) {
+        const int k1 = e & ((1 << lgr) - 1), s2 = e >> lgr;   // row k1 = k - 1, source s2
         R re = 0, im = 0;
         if (s2 < ns && k1 < p) {
             const C2 b = mult[(int64_t)L.src[s2] * P1 + k1 + 1], f = Sf[L.off[s2] * 32 + k1 + 1];
