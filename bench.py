@@ -33,8 +33,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6          # MI355X FP64 vector, dense
 # FETCH_SIZE x 2.0, WRITE_SIZE x 1.0.  Valid only for the IPM source they were
 # taken with, identified by its SHA-256 prefix.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
-IPM_TRAFFIC = {"ipm_sha256": "5d5f852261b04c2f",                     # (fetch KiB, write KiB)
-               "k_ipm": (719966.5625, 4497661.09375), "k_band": (2260970.1875, 31250.0)}
+IPM_TRAFFIC = {"ipm_sha256": "535a60fbece3f4bf",                     # (fetch KiB, write KiB)
+               "k_ipm": (719940.5625, 4497660.59375), "k_band": (2344886.1875, 31250.0)}
 
 
 def file_sha(path: str) -> str:
