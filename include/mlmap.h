@@ -356,8 +356,10 @@ typedef struct mlm_train_opts {
     float pos_weight;        /* weight of positive labels, default 1 */
     uint64_t seed;           /* shuffling */
     int32_t device_ptrs;     /* feats and labels on the device */
-    int32_t reserved0;
-    void *stream;
+    int32_t graph;           /* 1 (default): an epoch's steps are captured once in a
+                                HIP graph and replayed per epoch; 0: launched one by one */
+    void *stream;            /* the training runs on a stream of the refiner's own,
+                                after the work already queued on this one */
 } mlm_train_opts;
 
 void mlm_train_opts_init(mlm_train_opts *o);

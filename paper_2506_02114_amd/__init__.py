@@ -99,7 +99,7 @@ class BatchStats(C.Structure):
 
 class TrainOpts(C.Structure):
     _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("pos_weight", C.c_float),
-                ("seed", C.c_uint64), ("device_ptrs", C.c_int32), ("reserved0", C.c_int32), ("stream", C.c_void_p)]
+                ("seed", C.c_uint64), ("device_ptrs", C.c_int32), ("graph", C.c_int32), ("stream", C.c_void_p)]
 
 
 class TreeInfo(C.Structure):
@@ -411,12 +411,13 @@ class Refiner:
         return loss.value, g
 
     def train(self, feats, labels, epochs: int = 4, batch: int = 4096, lr: float = 1e-3, pos_weight: float = 1.0,
-              seed: int = 0):
+              seed: int = 0, graph: bool = True):
         f = np.ascontiguousarray(feats, dtype=np.float32).reshape(-1, 12)
         y = np.ascontiguousarray(labels, dtype=np.uint8)
         o = TrainOpts()
         _lib().mlm_train_opts_init(C.byref(o))
         o.epochs, o.batch, o.lr, o.pos_weight, o.seed = epochs, batch, lr, pos_weight, seed
+        o.graph = 1 if graph else 0
         losses = np.empty(max(epochs, 1), np.float32)
         _check(_lib().mlm_refiner_train(self._h, C.byref(o), f.ctypes.data_as(C.c_void_p),
                                         y.ctypes.data_as(C.c_void_p), f.shape[0], losses.ctypes.data_as(C.c_void_p)))

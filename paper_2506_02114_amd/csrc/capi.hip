@@ -387,6 +387,7 @@ void mlm_train_opts_init(mlm_train_opts *o)
     o->batch = 4096;
     o->lr = 1e-3f;
     o->pos_weight = 1.0f;
+    o->graph = 1;
 }
 
 mlm_status mlm_lens_create(const mlm_lens_params *params, const double *x, const double *y, const double *m,
@@ -1024,6 +1025,9 @@ mlm_status mlm_refiner_create(const float *params, uint64_t seed, mlm_refiner **
     r->G.reserve(nb);
     r->W1b.reserve(16 * 64 * sizeof(uint16_t));
     r->W2b.reserve(64 * 64 * sizeof(uint16_t));
+    r->tstep.reserve(sizeof(int64_t));
+    r->lacc.reserve(sizeof(double));
+    mlp_step_reset(r->tstep.as<int64_t>(), r->lacc.as<double>(), true, nullptr);
     mlp_zero(r->M.as<float>(), MLM_REFINER_PARAMS + 1, nullptr);
     mlp_zero(r->V.as<float>(), MLM_REFINER_PARAMS + 1, nullptr);
     mlp_zero(r->G.as<float>(), MLM_REFINER_PARAMS + 1, nullptr);
@@ -1162,30 +1166,66 @@ mlm_status mlm_refiner_train(mlm_refiner *r, const mlm_train_opts *opts, const f
         z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
         return z ^ (z >> 31);
     };
-    mlp_zero(r->G.as<float>(), MLM_REFINER_PARAMS + 1, st);
-    for (int32_t e = 0; e < o.epochs; ++e) {
-        for (int64_t k = 0; k < n; ++k) perm[k] = k;
-        for (int64_t k = n - 1; k > 0; --k) std::swap(perm[k], perm[next() % (uint64_t)(k + 1)]);
-        MLM_HIP(hipMemcpyAsync(didx, perm.data(), (size_t)n * sizeof(int64_t), hipMemcpyHostToDevice, st));
-        double loss = 0.0;
+    // the training runs on the refiner's own stream (a graph cannot be
+    // captured on the null stream), after the caller's stream
+    if (!r->gst) MLM_HIP(hipStreamCreateWithFlags(&r->gst, hipStreamNonBlocking));
+    const hipStream_t ts = r->gst;
+    hipEvent_t ready;
+    MLM_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    MLM_HIP(hipEventRecord(ready, st));
+    MLM_HIP(hipStreamWaitEvent(ts, ready, 0));
+    (void)hipEventDestroy(ready);
+    r->xbuf.reserve((size_t)((std::min<int64_t>(o.batch, n) + 127) / 128) * 128 * 12 * sizeof(float));
+    float *G = r->G.as<float>();
+    int64_t *tstep = r->tstep.as<int64_t>();
+    double *lacc = r->lacc.as<double>();
+    mlp_zero(G, MLM_REFINER_PARAMS + 1, ts);
+    // one epoch's steps over the permutation in didx: the same kernels with the
+    // same arguments every epoch (the permutation is rewritten in place, the
+    // step count and the loss sum live on the device)
+    auto epoch_steps = [&]() {
         for (int64_t b0 = 0; b0 < n; b0 += o.batch) {
             const int64_t nb = std::min<int64_t>(o.batch, n - b0);
-            refiner_batch(r, df, dy, didx + b0, nb, o.pos_weight, st);
-            float hl = 0.0f;
-            if (loss_per_epoch) MLM_HIP(hipMemcpyAsync(&hl, r->G.as<float>() + MLM_REFINER_PARAMS, sizeof(float),
-                                                       hipMemcpyDeviceToHost, st));
-            mlp_adam(r->P.as<float>(), r->M.as<float>(), r->V.as<float>(), r->G.as<float>(), o.lr, ++r->step, st);
-            mlp_zero(r->G.as<float>() + MLM_REFINER_PARAMS, 1, st);
-            mlp_pack(r->P.as<float>(), r->W1b.as<uint16_t>(), r->W2b.as<uint16_t>(), st);
-            if (loss_per_epoch) {
-                MLM_HIP(hipStreamSynchronize(st));
-                loss += hl * (double)nb;
-            }
+            refiner_batch(r, df, dy, didx + b0, nb, o.pos_weight, ts);
+            mlp_adam(r->P.as<float>(), r->M.as<float>(), r->V.as<float>(), G, o.lr, tstep, ts);
+            mlp_step_end(G, tstep, lacc, (float)nb, ts);
+            mlp_pack(r->P.as<float>(), r->W1b.as<uint16_t>(), r->W2b.as<uint16_t>(), ts);
         }
-        if (loss_per_epoch) loss_per_epoch[e] = (float)(loss / (double)n);
-        MLM_HIP(hipStreamSynchronize(st));   // perm is reused by the next epoch
+    };
+    hipGraphExec_t ge = nullptr;
+    if (o.graph && o.epochs > 0) {
+        hipGraph_t gr = nullptr;
+        MLM_HIP(hipStreamBeginCapture(ts, hipStreamCaptureModeThreadLocal));
+        try {
+            epoch_steps();
+        } catch (...) {
+            if (hipStreamEndCapture(ts, &gr) == hipSuccess && gr) (void)hipGraphDestroy(gr);
+            throw;
+        }
+        MLM_HIP(hipStreamEndCapture(ts, &gr));
+        const hipError_t ie = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        MLM_HIP(ie);
     }
-    MLM_HIP(hipStreamSynchronize(st));
+    try {
+        for (int32_t e = 0; e < o.epochs; ++e) {
+            for (int64_t k = 0; k < n; ++k) perm[k] = k;
+            for (int64_t k = n - 1; k > 0; --k) std::swap(perm[k], perm[next() % (uint64_t)(k + 1)]);
+            MLM_HIP(hipMemcpyAsync(didx, perm.data(), (size_t)n * sizeof(int64_t), hipMemcpyHostToDevice, ts));
+            mlp_step_reset(tstep, lacc, false, ts);
+            if (ge) MLM_HIP(hipGraphLaunch(ge, ts));
+            else epoch_steps();
+            double hl = 0.0;
+            if (loss_per_epoch) MLM_HIP(hipMemcpyAsync(&hl, lacc, sizeof(double), hipMemcpyDeviceToHost, ts));
+            MLM_HIP(hipStreamSynchronize(ts));   // perm (and hl) are reused by the next epoch
+            if (loss_per_epoch) loss_per_epoch[e] = (float)(hl / (double)n);
+        }
+    } catch (...) {
+        if (ge) (void)hipGraphExecDestroy(ge);
+        throw;
+    }
+    if (ge) MLM_HIP(hipGraphExecDestroy(ge));
+    MLM_HIP(hipStreamSynchronize(ts));
     API_END
 }
 

@@ -208,8 +208,14 @@ struct mlm_lens {
 // bf16 copies in the kernels' layouts, staging
 struct mlm_refiner {
     mlm::DevBuf P, M, V, G, W1b, W2b, xbuf, idx, feats, labels, logits;
-    int64_t step = 0;
+    mlm::DevBuf tstep;     // Adam steps taken (int64, on the device: read by the step kernels)
+    mlm::DevBuf lacc;      // loss summed over an epoch's rows (double)
+    hipStream_t gst = nullptr;   // training stream (graph capture needs a stream of its own)
     std::mutex mu;
+    ~mlm_refiner()
+    {
+        if (gst) (void)hipStreamDestroy(gst);
+    }
 };
 
 namespace mlm {
@@ -295,8 +301,10 @@ void mlp_predict(const float *feats, int64_t n, const uint16_t *W1b, const uint1
                  float *logits, hipStream_t st);
 void mlp_train_batch(const float *feats, const uint8_t *y, const int64_t *idx, int64_t n, const uint16_t *W1b,
                      const uint16_t *W2b, const float *P, float pos_weight, float *grad, float *xbuf, hipStream_t st);
-void mlp_adam(float *P, float *M, float *V, float *grad, float lr, int64_t step, hipStream_t st);
+void mlp_adam(float *P, float *M, float *V, float *grad, float lr, const int64_t *tstep, hipStream_t st);
+void mlp_step_end(float *G, int64_t *tstep, double *lacc, float nb, hipStream_t st);
 void mlp_zero(float *p, int64_t n, hipStream_t st);
+void mlp_step_reset(int64_t *tstep, double *lacc, bool steps, hipStream_t st);
 
 // helpers
 void *pinned(mlm_lens *lens, size_t bytes);

@@ -258,18 +258,41 @@ __global__ void k_mlp_pack(const float *__restrict__ P, uint16_t *__restrict__ W
     if (t < 64 * 64) W2b[t] = f2bf(P[OW2 + t]);
 }
 
-// Adam step (bias-corrected) on the FP32 master weights; clears the gradient
+// Adam step (bias-corrected) on the FP32 master weights; clears the gradient.
+// The step number is read from the device (steps taken + 1), so a captured
+// sequence of steps replays with the right corrections.
 __global__ void k_adam(float *__restrict__ P, float *__restrict__ M, float *__restrict__ V, float *__restrict__ grad,
-                       float lr, float b1, float b2, float eps, float c1, float c2)
+                       float lr, float b1, float b2, float eps, const int64_t *__restrict__ tstep)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= NP) return;
+    const float s = (float)(tstep[0] + 1);
+    const float c1 = 1.0f - powf(b1, s), c2 = 1.0f - powf(b2, s);
     const float gv = grad[t];
     const float m = b1 * M[t] + (1.0f - b1) * gv, v = b2 * V[t] + (1.0f - b2) * gv * gv;
     M[t] = m;
     V[t] = v;
     P[t] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
     grad[t] = 0.0f;
+}
+
+// after a step: counts it, adds the batch's loss (the mean over its nb rows,
+// in G[NP]) times nb to the epoch's sum, and clears it
+__global__ void k_step_end(float *__restrict__ G, int64_t *__restrict__ tstep, double *__restrict__ lacc, float nb)
+{
+    if (threadIdx.x == 0) {
+        *lacc += (double)G[NP] * (double)nb;
+        G[NP] = 0.0f;
+        *tstep += 1;
+    }
+}
+
+__global__ void k_step_reset(int64_t *__restrict__ tstep, double *__restrict__ lacc, int steps)
+{
+    if (threadIdx.x == 0) {
+        if (steps) *tstep = 0;
+        *lacc = 0.0;
+    }
 }
 
 __global__ void k_zero_f32(float *p, int64_t n)
@@ -302,11 +325,19 @@ void mlp_train_batch(const float *feats, const uint8_t *y, const int64_t *idx, i
                            W2b, P, pos_weight, (float)n, grad, xbuf);
 }
 
-void mlp_adam(float *P, float *M, float *V, float *grad, float lr, int64_t step, hipStream_t st)
+void mlp_adam(float *P, float *M, float *V, float *grad, float lr, const int64_t *tstep, hipStream_t st)
 {
-    const float b1 = 0.9f, b2 = 0.999f;
-    const float c1 = 1.0f - std::pow(b1, (float)step), c2 = 1.0f - std::pow(b2, (float)step);
-    hipLaunchKernelGGL(k_adam, dim3((NP + 255) / 256), dim3(256), 0, st, P, M, V, grad, lr, b1, b2, 1e-8f, c1, c2);
+    hipLaunchKernelGGL(k_adam, dim3((NP + 255) / 256), dim3(256), 0, st, P, M, V, grad, lr, 0.9f, 0.999f, 1e-8f, tstep);
+}
+
+void mlp_step_end(float *G, int64_t *tstep, double *lacc, float nb, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, st, G, tstep, lacc, nb);
+}
+
+void mlp_step_reset(int64_t *tstep, double *lacc, bool steps, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_step_reset, dim3(1), dim3(64), 0, st, tstep, lacc, steps ? 1 : 0);
 }
 
 void mlp_zero(float *p, int64_t n, hipStream_t st)
