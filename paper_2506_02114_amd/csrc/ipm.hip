@@ -8,11 +8,14 @@
 // (signed extent) x (integral of a clamped linear function), and the area of
 // a pixel is the difference of two such sums.
 //
-// Ordinary triangles go by pixel columns, one work item per (triangle,
-// column).  Triangles next to a star map to huge triangles (the linear
-// interpolation of a singular mapping), covering up to millions of pixels;
-// their cost is made proportional to their perimeter: they are binned by
-// bands of pixel rows and apportioned through per-row column differences.
+// A triangle inside one pixel is one deposit; one inside a 2 x 2 pixel box
+// is apportioned in place from the areas of the corner triangles that the
+// pixel lines cut off; other ordinary triangles go by pixel columns, one work
+// item per (triangle, column).  Triangles next to a star map to huge
+// triangles (the linear interpolation of a singular mapping), covering up to
+// millions of pixels; their cost is made proportional to their perimeter:
+// they are binned by bands of pixel rows and apportioned through per-row
+// column differences.
 //
 // Every geometric helper is templated on its arithmetic type R: FP64, or FP32
 // in the mixed-precision mode, where coordinates are first made local to the
@@ -231,7 +234,8 @@ __device__ inline void deposit_w(const Window &w, double *map, const MapGeom &g,
 // Classification of one mapped triangle (pixel coordinates) for the cell pass.
 //   kind 0: nothing to deposit (outside the map, or skipped as non-finite)
 //   kind 1: one deposit (single pixel, or zero area -> its centroid's pixel)
-//   kind 2: `cols` pixel columns, each one work item of the column pass
+//   kind 2: within a 2 x 2 pixel box (`small`), apportioned in place; else
+//           `cols` pixel columns, each one work item of the column pass
 //   kind 3: large: goes to the row-parallel pass
 struct TriClass {
     int kind;
