@@ -198,6 +198,26 @@ def test_timing_levels_and_work_counts(mlm):
             pieces=s2["n_col_pieces"], big=s2["n_big"], band_rows=s2["n_band_rows"])
 
 
+@pytest.mark.parametrize("n1", [5000, 9000])
+def test_wide_maps_match_oracle(mlm, orc, n1):
+    """Maps wider than the row bands' usual shape: 5000 px gives one-row
+    bands, 9000 px (more than an LDS row of doubles) takes the per-triangle
+    row kernel with global column differences.  A coarse ray grid makes
+    every triangle large, so these paths carry the whole map."""
+    wl = W.config("plain_small")
+    sf = wl.stars()
+    gl, ol = _pair(mlm, orc, 0.3, 0.0, 0.3, sf)
+    pix = 0.001
+    spec = dict(hw1=0.5 * n1 * pix, hw2=1.5 * pix, n1=n1, n2=3, nray1=150, nray2=160, order=16)
+    mu, st = gl.map(timing=2, **spec)
+    ref = orc.magnification_map(ol, spec, method="fmm", p=16)
+    rel, zok = _rel_map_err(mu, ref.mu)
+    _report(f"map_wide_{n1}_vs_oracle_fmm", max=float(rel.max()), median=float(np.median(rel)), big=st["n_big"],
+            band_rows=st["n_band_rows"])
+    assert st["n_big"] > 0 and zok and rel.max() < 1e-9
+    assert mu.sum() * pix * pix == pytest.approx(ref.dep_total, rel=1e-9)
+
+
 def test_map_device_output_and_stream(mlm, orc):
     import torch
     wl = W.config("plain_small")
