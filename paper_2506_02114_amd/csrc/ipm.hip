@@ -854,21 +854,53 @@ __device__ inline void band_range(const BigPrep &bp, int64_t rows, int bh, int64
     b1 = (j0 + rows - 1) / bh;
 }
 
+// Per-band counts of a workgroup's triangles from their band ranges [b0, b1]:
+// each adds +1 at b0 and -1 past b1 in `hist` (nb + 1 entries, zeroed), and
+// a prefix sum over the bands turns that in place into the counts (O(1)
+// updates per triangle instead of one per band).  The sum runs over
+// contiguous chunks of bands, one per thread, chained by a scan of the chunk
+// totals (`part`: one entry per wavefront).  Called by the whole workgroup;
+// synchronises before and after.
+__device__ inline void band_diff_to_counts(int32_t *hist, int32_t nb, int32_t *part)
+{
+    __syncthreads();
+    const int nt = (int)blockDim.x, t = (int)threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int chunk = (nb + nt - 1) / nt, c0 = min(t * chunk, (int)nb), c1 = min(c0 + chunk, (int)nb);
+    int sum = 0;
+    for (int b = c0; b < c1; ++b) sum += hist[b];
+    int total;
+    const int excl = wave_excl_scan(sum, lane, total);
+    if (lane == 0) part[wave] = total;
+    __syncthreads();
+    int run = excl;
+    for (int w = 0; w < wave; ++w) run += part[w];
+    for (int b = c0; b < c1; ++b) {
+        run += hist[b];
+        hist[b] = run;
+    }
+    __syncthreads();
+}
+
+// LDS words of a band histogram with its scan totals (256 threads), rounded
+// up to whole 8-byte words
+__host__ __device__ inline size_t band_hist_words(int64_t nb) { return (size_t)((nb + 1 + 4 + 1) & ~1); }
+
 // per band: number of large triangles crossing it (block histogram in LDS)
 __global__ __launch_bounds__(256) void k_band_count(int64_t nbig, const BigPrep *__restrict__ prep,
                                                     const int64_t *__restrict__ rows, int bh, int32_t nbands,
                                                     int32_t *__restrict__ count)
 {
-    extern __shared__ int32_t hist[];
-    for (int32_t b = threadIdx.x; b < nbands; b += blockDim.x) hist[b] = 0;
+    extern __shared__ int32_t hist[];   // nbands + 1 entries, then 4 chunk-scan totals
+    for (int32_t b = threadIdx.x; b <= nbands; b += blockDim.x) hist[b] = 0;
     __syncthreads();
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < nbig && rows[k] > 0) {
         int64_t b0, b1;
         band_range(prep[k], rows[k], bh, b0, b1);
-        for (int64_t b = b0; b <= b1; ++b) atomicAdd(&hist[b], 1);
+        atomicAdd(&hist[b0], 1);
+        atomicAdd(&hist[b1 + 1], -1);
     }
-    __syncthreads();
+    band_diff_to_counts(hist, nbands, hist + nbands + 1);
     for (int32_t b = threadIdx.x; b < nbands; b += blockDim.x)
         if (hist[b]) atomicAdd(count + b, hist[b]);
 }
@@ -882,16 +914,17 @@ __global__ __launch_bounds__(256) void k_band_scatter(int64_t nbig, const BigPre
 {
     extern __shared__ int32_t sh[];
     int32_t *hist = sh;
-    unsigned long long *base = reinterpret_cast<unsigned long long *>(sh + ((nbands + 1) & ~1));
-    for (int32_t b = threadIdx.x; b < nbands; b += blockDim.x) hist[b] = 0;
+    unsigned long long *base = reinterpret_cast<unsigned long long *>(sh + band_hist_words(nbands));
+    for (int32_t b = threadIdx.x; b <= nbands; b += blockDim.x) hist[b] = 0;
     __syncthreads();
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t b0 = 0, b1 = -1;
     if (k < nbig && rows[k] > 0) {
         band_range(prep[k], rows[k], bh, b0, b1);
-        for (int64_t b = b0; b <= b1; ++b) atomicAdd(&hist[b], 1);
+        atomicAdd(&hist[b0], 1);
+        atomicAdd(&hist[b1 + 1], -1);
     }
-    __syncthreads();
+    band_diff_to_counts(hist, nbands, hist + nbands + 1);
     for (int32_t b = threadIdx.x; b < nbands; b += blockDim.x) {
         if (hist[b]) base[b] = atomicAdd(cursor + b, (unsigned long long)hist[b]);
         hist[b] = 0;
@@ -1083,18 +1116,19 @@ __global__ __launch_bounds__(256) void k_band_count_batch(const BatchMap *__rest
                                                           const int64_t *__restrict__ rows,
                                                           int32_t *__restrict__ count)
 {
-    extern __shared__ int32_t hist[];
+    extern __shared__ int32_t hist[];   // nb + 1 entries, then 4 chunk-scan totals
     const BatchMap &d = maps[slice_map[blockIdx.x]];
     const int32_t nb = (int32_t)d.nbands;
-    for (int32_t b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0;
+    for (int32_t b = threadIdx.x; b <= nb; b += blockDim.x) hist[b] = 0;
     __syncthreads();
     const int64_t k = slice_lo[blockIdx.x] + threadIdx.x;
     if (k < d.big_hi && rows[k] > 0) {
         int64_t b0, b1;
         band_range(prep[k], rows[k], d.bh, b0, b1);
-        for (int64_t b = b0; b <= b1; ++b) atomicAdd(&hist[b], 1);
+        atomicAdd(&hist[b0], 1);
+        atomicAdd(&hist[b1 + 1], -1);
     }
-    __syncthreads();
+    band_diff_to_counts(hist, nb, hist + nb + 1);
     for (int32_t b = threadIdx.x; b < nb; b += blockDim.x)
         if (hist[b]) atomicAdd(count + d.band_lo + b, hist[b]);
 }
@@ -1111,16 +1145,17 @@ __global__ __launch_bounds__(256) void k_band_scatter_batch(const BatchMap *__re
     const BatchMap &d = maps[slice_map[blockIdx.x]];
     const int32_t nb = (int32_t)d.nbands;
     int32_t *hist = sh;
-    unsigned long long *base = reinterpret_cast<unsigned long long *>(sh + ((nb + 1) & ~1));
-    for (int32_t b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0;
+    unsigned long long *base = reinterpret_cast<unsigned long long *>(sh + band_hist_words(nb));
+    for (int32_t b = threadIdx.x; b <= nb; b += blockDim.x) hist[b] = 0;
     __syncthreads();
     const int64_t k = slice_lo[blockIdx.x] + threadIdx.x;
     int64_t b0 = 0, b1 = -1;
     if (k < d.big_hi && rows[k] > 0) {
         band_range(prep[k], rows[k], d.bh, b0, b1);
-        for (int64_t b = b0; b <= b1; ++b) atomicAdd(&hist[b], 1);
+        atomicAdd(&hist[b0], 1);
+        atomicAdd(&hist[b1 + 1], -1);
     }
-    __syncthreads();
+    band_diff_to_counts(hist, nb, hist + nb + 1);
     for (int32_t b = threadIdx.x; b < nb; b += blockDim.x) {
         if (hist[b]) base[b] = atomicAdd(cursor + d.band_lo + b, (unsigned long long)hist[b]);
         hist[b] = 0;
@@ -1202,14 +1237,14 @@ void launch_band_count(int64_t nbig, const BigPrep *prep, const int64_t *rows, i
                        hipStream_t st)
 {
     if (nbig > 0)
-        hipLaunchKernelGGL(k_band_count, dim3((unsigned)((nbig + 255) / 256)), dim3(256), nbands * sizeof(int32_t), st,
-                           nbig, prep, rows, bh, nbands, count);
+        hipLaunchKernelGGL(k_band_count, dim3((unsigned)((nbig + 255) / 256)), dim3(256),
+                           band_hist_words(nbands) * sizeof(int32_t), st, nbig, prep, rows, bh, nbands, count);
 }
 
 void launch_band_scatter(int64_t nbig, const BigPrep *prep, const int64_t *rows, int bh, int32_t nbands,
                          unsigned long long *cursor, int32_t *list, hipStream_t st)
 {
-    size_t shmem = ((nbands + 1) & ~1) * sizeof(int32_t) + nbands * sizeof(unsigned long long);
+    size_t shmem = band_hist_words(nbands) * sizeof(int32_t) + nbands * sizeof(unsigned long long);
     if (nbig > 0)
         hipLaunchKernelGGL(k_band_scatter, dim3((unsigned)((nbig + 255) / 256)), dim3(256), shmem, st, nbig, prep, rows,
                            bh, nbands, cursor, list);
@@ -1248,15 +1283,16 @@ void launch_band_count_batch(const BatchMap *maps, int64_t nslices, const int32_
                              hipStream_t st)
 {
     if (nslices > 0)
-        hipLaunchKernelGGL(k_band_count_batch, dim3((unsigned)nslices), dim3(256), (size_t)max_bands * sizeof(int32_t),
-                           st, maps, slice_map, slice_lo, prep, rows, count);
+        hipLaunchKernelGGL(k_band_count_batch, dim3((unsigned)nslices), dim3(256),
+                           band_hist_words(max_bands) * sizeof(int32_t), st, maps, slice_map, slice_lo, prep, rows,
+                           count);
 }
 
 void launch_band_scatter_batch(const BatchMap *maps, int64_t nslices, const int32_t *slice_map,
                                const int64_t *slice_lo, int32_t max_bands, const BigPrep *prep, const int64_t *rows,
                                unsigned long long *cursor, int32_t *list, hipStream_t st)
 {
-    const size_t shmem = ((max_bands + 1) & ~1) * sizeof(int32_t) + (size_t)max_bands * sizeof(unsigned long long);
+    const size_t shmem = band_hist_words(max_bands) * sizeof(int32_t) + (size_t)max_bands * sizeof(unsigned long long);
     if (nslices > 0)
         hipLaunchKernelGGL(k_band_scatter_batch, dim3((unsigned)nslices), dim3(256), shmem, st, maps, slice_map,
                            slice_lo, prep, rows, cursor, list);
