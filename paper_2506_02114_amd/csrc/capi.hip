@@ -212,7 +212,7 @@ constexpr int PREP_THREADS = 8;
 
 struct BatchWs {
     std::mutex mu;
-    DevBuf maps, verts, nbig, boff, prep, rows, bcnt, boffs, bcur, blist, counters, bounds, slice_map, slice_lo;
+    DevBuf maps, verts, nbig, boff, prep, rows, row0, bcnt, boffs, bcur, blist, counters, bounds, slice_map, slice_lo;
     hipStream_t prep_st[PREP_THREADS] = {};   // created on first use, default priority
 };
 
@@ -616,7 +616,8 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
         if (nb > 0) {
             BigPrep *prep = static_cast<BigPrep *>(ws.bigprep.reserve((size_t)nb * sizeof(BigPrep)));
             int64_t *rows = static_cast<int64_t *>(ws.bigrows.reserve((size_t)nb * sizeof(int64_t)));
-            launch_big_gather(ncells, bigoff, verts, R.nr1, r0, vb0, g, prep, rows, st);
+            int32_t *row0 = static_cast<int32_t *>(ws.bigrow0.reserve((size_t)nb * sizeof(int32_t)));
+            launch_big_gather(ncells, bigoff, verts, R.nr1, r0, vb0, g, prep, rows, row0, st);
             const int bh = band_height(g.n1, g.n2);
             if (bh > 0) {
                 // large triangles by pixel bands: owned rows, LDS accumulation
@@ -627,11 +628,11 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
                 unsigned long long *bcur =
                     static_cast<unsigned long long *>(ws.bandcur.reserve((size_t)(nbands + 1) * sizeof(unsigned long long)));
                 hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((nbands + 255) / 256)), dim3(256), 0, st, bcnt, nbands);
-                launch_band_count(nb, prep, rows, bh, nbands, bcnt, st);
+                launch_band_count(nb, row0, rows, bh, nbands, bcnt, st);
                 const int64_t nlist = scan_i32_to_u64(lens, bcnt, boffs, nbands, st);
                 int32_t *blist = static_cast<int32_t *>(ws.bandlist.reserve((size_t)(nlist > 0 ? nlist : 1) * sizeof(int32_t)));
                 MLM_HIP(hipMemcpyAsync(bcur, boffs, (size_t)nbands * sizeof(unsigned long long), hipMemcpyDeviceToDevice, st));
-                launch_band_scatter(nb, prep, rows, bh, nbands, bcur, blist, st);
+                launch_band_scatter(nb, row0, rows, bh, nbands, bcur, blist, st);
                 e_band0 = tm.mark();
                 launch_band(nbands, boffs, blist, prep, rows, bh, g, map, q.timing >= 2 ? cnt + 4 : nullptr, st);
                 e_band1 = tm.mark();
@@ -909,7 +910,8 @@ mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, i
         if (nb > 0) {
             BigPrep *prep = static_cast<BigPrep *>(B.prep.reserve((size_t)nb * sizeof(BigPrep)));
             int64_t *rows = static_cast<int64_t *>(B.rows.reserve((size_t)nb * sizeof(int64_t)));
-            launch_big_gather_batch(dmaps, nm, cl, boff, prep, rows, nullptr, st);
+            int32_t *row0 = static_cast<int32_t *>(B.row0.reserve((size_t)nb * sizeof(int32_t)));
+            launch_big_gather_batch(dmaps, nm, cl, boff, prep, rows, row0, st);
             // each map's slice of the gathered list, cut into workgroup-sized
             // slices for the binning passes
             int64_t *bnd = static_cast<int64_t *>(B.bounds.reserve((size_t)(nm + 1) * sizeof(int64_t)));
@@ -924,7 +926,7 @@ mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, i
             for (int32_t k = 0; k < nm; ++k) {
                 hm[k].big_lo = hb[k];
                 hm[k].big_hi = hb[k + 1];
-                for (int64_t a = hb[k]; a < hb[k + 1]; a += 256) {
+                for (int64_t a = hb[k]; a < hb[k + 1]; a += BIN_TRIS) {
                     smap.push_back(k);
                     slo.push_back(a);
                 }
@@ -938,7 +940,7 @@ mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, i
             MLM_HIP(hipMemcpyAsync(dmaps, hm.data(), (size_t)nm * sizeof(BatchMap), hipMemcpyHostToDevice, st));
             int32_t *bcnt = static_cast<int32_t *>(B.bcnt.reserve((size_t)bl * sizeof(int32_t)));
             hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((bl + 255) / 256)), dim3(256), 0, st, bcnt, bl);
-            launch_band_count_batch(dmaps, ns, dsm, dsl, max_bands, prep, rows, bcnt, st);
+            launch_band_count_batch(dmaps, ns, dsm, dsl, max_bands, row0, rows, bcnt, st);
             unsigned long long *boffs =
                 static_cast<unsigned long long *>(B.boffs.reserve((size_t)(bl + 1) * sizeof(unsigned long long)));
             const int64_t nlist = scan_i32_to_u64(scan_lens, bcnt, boffs, bl, st);
@@ -946,7 +948,7 @@ mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, i
             unsigned long long *bcur =
                 static_cast<unsigned long long *>(B.bcur.reserve((size_t)bl * sizeof(unsigned long long)));
             MLM_HIP(hipMemcpyAsync(bcur, boffs, (size_t)bl * sizeof(unsigned long long), hipMemcpyDeviceToDevice, st));
-            launch_band_scatter_batch(dmaps, ns, dsm, dsl, max_bands, prep, rows, bcur, blist, st);
+            launch_band_scatter_batch(dmaps, ns, dsm, dsl, max_bands, row0, rows, bcur, blist, st);
             MLM_HIP(hipStreamSynchronize(st));   // the host slice tables are released at the end of this block
             launch_band_batch(dmaps, nm, bl, boffs, blist, prep, rows, max_band_lds, st);
         }

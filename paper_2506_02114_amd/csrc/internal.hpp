@@ -184,7 +184,7 @@ struct Workspace {
     DevBuf code, level, leaf, slo, shi, block, parent, child0, coll, node_leaf, leaf_node, flags, offs;
     DevBuf ilist, mult, local, ops_m2m, ops_m2l, ops_l2l;
     DevBuf leaves, near, deriv, near_offs;
-    DevBuf tile_off, tile_leaf, verts, map, wbuf, pts, counters, items, itemoff, nbig, bigoff, bigprep, bigrows, rowoff, nbnd, nbndoff, diff, bandcnt, bandoff,
+    DevBuf tile_off, tile_leaf, verts, map, wbuf, pts, counters, items, itemoff, nbig, bigoff, bigprep, bigrows, bigrow0, rowoff, nbnd, nbndoff, diff, bandcnt, bandoff,
         bandcur, bandlist, rfeat, rlogit, rflag, rpos, rcand, rlabel, rstats;
     void *pinned = nullptr;               // small pinned host buffer for read-backs
     size_t pinned_cap = 0;
@@ -250,30 +250,33 @@ void launch_deflect_points(mlm_lens *lens, const Tree *T, const LensConst &lc, c
 // work counts of the per-cell IPM kernel (statistics): WORK_SLOTS partial sums
 // per count, so that the wavefronts' additions rarely meet at one address
 constexpr int WORK_SLOTS = 256;
+// large triangles per workgroup of the band binning passes (and per slice of
+// a batch map's list of them)
+constexpr int64_t BIN_TRIS = 2048;
 void launch_ipm(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int64_t vb0, const MapGeom &g,
                 double *map, unsigned long long *counters, int32_t *nbig, bool mixed, unsigned long long *work,
                 hipStream_t st);
 void launch_big_gather(int64_t ncells, const int64_t *boff, const double2 *verts, int64_t nr1, int64_t cb0,
-                       int64_t vb0, const MapGeom &g, BigPrep *prep, int64_t *rows, hipStream_t st);
+                       int64_t vb0, const MapGeom &g, BigPrep *prep, int64_t *rows, int32_t *row0, hipStream_t st);
 void launch_big(int64_t nbig, const BigPrep *prep, const int64_t *rows, const MapGeom &g, double *map, double *diff,
                 hipStream_t st);
 void launch_diff_rows(const MapGeom &g, const double *diff, double *map, hipStream_t st);
 int band_height(int32_t n1, int32_t n2);
-void launch_band_count(int64_t nbig, const BigPrep *prep, const int64_t *rows, int bh, int32_t nbands, int32_t *count,
+void launch_band_count(int64_t nbig, const int32_t *row0, const int64_t *rows, int bh, int32_t nbands, int32_t *count,
                        hipStream_t st);
-void launch_band_scatter(int64_t nbig, const BigPrep *prep, const int64_t *rows, int bh, int32_t nbands,
+void launch_band_scatter(int64_t nbig, const int32_t *row0, const int64_t *rows, int bh, int32_t nbands,
                          unsigned long long *cursor, int32_t *list, hipStream_t st);
 void launch_band(int32_t nbands, const unsigned long long *band_off, const int32_t *list, const BigPrep *prep,
                  const int64_t *rows, int bh, const MapGeom &g, double *map, unsigned long long *work,
                  hipStream_t st);
 void launch_ipm_batch(const BatchMap *maps, int32_t nmaps, int64_t nctiles, int32_t *nbig, hipStream_t st);
 void launch_big_gather_batch(const BatchMap *maps, int32_t nmaps, int64_t ncells, const int64_t *boff, BigPrep *prep,
-                             int64_t *rows, int32_t *owner, hipStream_t st);
+                             int64_t *rows, int32_t *row0, hipStream_t st);
 void launch_band_count_batch(const BatchMap *maps, int64_t nslices, const int32_t *slice_map, const int64_t *slice_lo,
-                             int32_t max_bands, const BigPrep *prep, const int64_t *rows, int32_t *count,
+                             int32_t max_bands, const int32_t *row0, const int64_t *rows, int32_t *count,
                              hipStream_t st);
 void launch_band_scatter_batch(const BatchMap *maps, int64_t nslices, const int32_t *slice_map,
-                               const int64_t *slice_lo, int32_t max_bands, const BigPrep *prep, const int64_t *rows,
+                               const int64_t *slice_lo, int32_t max_bands, const int32_t *row0, const int64_t *rows,
                                unsigned long long *cursor, int32_t *list, hipStream_t st);
 void launch_band_batch(const BatchMap *maps, int32_t nmaps, int64_t nbands, const unsigned long long *band_off,
                        const int32_t *list, const BigPrep *prep, const int64_t *rows, int64_t lds_doubles,

@@ -633,10 +633,12 @@ __global__ __launch_bounds__(256) void k_ipm_batch(const BatchMap *__restrict__ 
 // of the per-cell counts: integer local origin (inside or at the edge of the
 // map, so nearby pixel boundaries are exact), counter-clockwise local
 // vertices, edge slopes, the deposit scale, and the pixel rows it covers
+// (their count in rows[], the first in row0[]: compact copies for the
+// binning passes, which need nothing else)
 __device__ inline void gather_cell(int64_t t, int64_t slot, int64_t end, const double2 *__restrict__ verts,
                                    int64_t nr1, int64_t cb0, int64_t vb0, const MapGeom &g,
                                    BigPrep *__restrict__ prep, int64_t *__restrict__ rows,
-                                   int32_t *__restrict__ owner, int32_t map_index)
+                                   int32_t *__restrict__ row0)
 {
     P2 v00, v10, v11, v01;
     load_cell(verts, nr1, cb0, vb0, t, v00, v10, v11, v01);
@@ -675,7 +677,7 @@ __device__ inline void gather_cell(int64_t t, int64_t slot, int64_t end, const d
         prep[slot] = bp;
         const double j1 = fmin(floor(vmax), (double)(g.n2 - 1));
         rows[slot] = j1 >= ov ? (int64_t)(j1 - ov) + 1 : 0;
-        if (owner) owner[slot] = map_index;
+        row0[slot] = (int32_t)ov;
         ++slot;
     }
 }
@@ -683,25 +685,24 @@ __device__ inline void gather_cell(int64_t t, int64_t slot, int64_t end, const d
 __global__ __launch_bounds__(256) void k_big_gather(int64_t ncells, const int64_t *__restrict__ boff,
                                                     const double2 *__restrict__ verts, int64_t nr1, int64_t cb0,
                                                     int64_t vb0, MapGeom g, BigPrep *__restrict__ prep,
-                                                    int64_t *__restrict__ rows)
+                                                    int64_t *__restrict__ rows, int32_t *__restrict__ row0)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ncells || boff[t + 1] == boff[t]) return;
-    gather_cell(t, boff[t], boff[t + 1], verts, nr1, cb0, vb0, g, prep, rows, nullptr, 0);
+    gather_cell(t, boff[t], boff[t + 1], verts, nr1, cb0, vb0, g, prep, rows, row0);
 }
 
-// the batch's cells: boff is the scan over all maps' cells; owner records
-// each large triangle's map
+// the batch's cells: boff is the scan over all maps' cells
 __global__ __launch_bounds__(256) void k_big_gather_batch(const BatchMap *__restrict__ maps, int32_t nmaps,
                                                           int64_t ncells, const int64_t *__restrict__ boff,
                                                           BigPrep *__restrict__ prep, int64_t *__restrict__ rows,
-                                                          int32_t *__restrict__ owner)
+                                                          int32_t *__restrict__ row0)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncells || boff[c + 1] == boff[c]) return;
     const int32_t m = batch_find(maps, nmaps, c, &BatchMap::cell_lo);
     const BatchMap &d = maps[m];
-    gather_cell(c - d.cell_lo, boff[c], boff[c + 1], d.verts, d.nr1, 0, 0, d.g, prep, rows, owner, m);
+    gather_cell(c - d.cell_lo, boff[c], boff[c + 1], d.verts, d.nr1, 0, 0, d.g, prep, rows, row0);
 }
 
 // The edges of a large triangle clipped to pixel row j (local coordinates),
@@ -847,9 +848,8 @@ __global__ __launch_bounds__(256) void k_big(int64_t nbig, const BigPrep *__rest
 constexpr int BAND_THREADS = 512;
 constexpr int64_t BAND_LDS_DOUBLES = 8192;    // band difference rows (64 KiB)
 
-__device__ inline void band_range(const BigPrep &bp, int64_t rows, int bh, int64_t &b0, int64_t &b1)
+__device__ inline void band_range(int64_t j0, int64_t rows, int bh, int64_t &b0, int64_t &b1)
 {
-    const int64_t j0 = (int64_t)bp.ov;
     b0 = j0 / bh;
     b1 = (j0 + rows - 1) / bh;
 }
@@ -885,55 +885,85 @@ __device__ inline void band_diff_to_counts(int32_t *hist, int32_t nb, int32_t *p
 // up to whole 8-byte words
 __host__ __device__ inline size_t band_hist_words(int64_t nb) { return (size_t)((nb + 1 + 4 + 1) & ~1); }
 
-// per band: number of large triangles crossing it (block histogram in LDS)
-__global__ __launch_bounds__(256) void k_band_count(int64_t nbig, const BigPrep *__restrict__ prep,
-                                                    const int64_t *__restrict__ rows, int bh, int32_t nbands,
-                                                    int32_t *__restrict__ count)
+// Binning of the large triangles into bands.  A workgroup takes BIN_TRIS
+// consecutive ones, [lo, hi) of one map, so that each device-wide update of a
+// band's total or cursor serves many triangles (with one triangle per thread
+// those updates, all on the few hundred band entries, were the cost).
+// bin_count adds the workgroup's per-band counts to count[] (hist: LDS of
+// band_hist_words(nb) words).
+__device__ inline void bin_count(int64_t lo, int64_t hi, const int32_t *__restrict__ row0,
+                                 const int64_t *__restrict__ rows, int bh, int32_t nb, int32_t *hist,
+                                 int32_t *__restrict__ count)
 {
-    extern __shared__ int32_t hist[];   // nbands + 1 entries, then 4 chunk-scan totals
-    for (int32_t b = threadIdx.x; b <= nbands; b += blockDim.x) hist[b] = 0;
+    for (int32_t b = threadIdx.x; b <= nb; b += blockDim.x) hist[b] = 0;
     __syncthreads();
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < nbig && rows[k] > 0) {
+    for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+        const int64_t n = rows[k];
+        if (n <= 0) continue;
         int64_t b0, b1;
-        band_range(prep[k], rows[k], bh, b0, b1);
+        band_range(row0[k], n, bh, b0, b1);
         atomicAdd(&hist[b0], 1);
         atomicAdd(&hist[b1 + 1], -1);
     }
-    band_diff_to_counts(hist, nbands, hist + nbands + 1);
-    for (int32_t b = threadIdx.x; b < nbands; b += blockDim.x)
+    band_diff_to_counts(hist, nb, hist + nb + 1);
+    for (int32_t b = threadIdx.x; b < nb; b += blockDim.x)
         if (hist[b]) atomicAdd(count + b, hist[b]);
 }
 
-// triangle indices into their bands' lists: each block reserves one range
-// per band and hands out slots inside it from LDS
-__global__ __launch_bounds__(256) void k_band_scatter(int64_t nbig, const BigPrep *__restrict__ prep,
+// triangle indices into their bands' lists: the workgroup reserves one range
+// per band from cursor[] and hands out slots inside it from LDS (sh:
+// band_hist_words(nb) words, then nb 8-byte range starts)
+__device__ inline void bin_scatter(int64_t lo, int64_t hi, const int32_t *__restrict__ row0,
+                                   const int64_t *__restrict__ rows, int bh, int32_t nb, int32_t *sh,
+                                   unsigned long long *__restrict__ cursor, int32_t *__restrict__ list)
+{
+    int32_t *hist = sh;
+    unsigned long long *base = reinterpret_cast<unsigned long long *>(sh + band_hist_words(nb));
+    for (int32_t b = threadIdx.x; b <= nb; b += blockDim.x) hist[b] = 0;
+    __syncthreads();
+    for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+        const int64_t n = rows[k];
+        if (n <= 0) continue;
+        int64_t b0, b1;
+        band_range(row0[k], n, bh, b0, b1);
+        atomicAdd(&hist[b0], 1);
+        atomicAdd(&hist[b1 + 1], -1);
+    }
+    band_diff_to_counts(hist, nb, hist + nb + 1);
+    for (int32_t b = threadIdx.x; b < nb; b += blockDim.x) {
+        if (hist[b]) base[b] = atomicAdd(cursor + b, (unsigned long long)hist[b]);
+        hist[b] = 0;
+    }
+    __syncthreads();
+    for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+        const int64_t n = rows[k];
+        if (n <= 0) continue;
+        int64_t b0, b1;
+        band_range(row0[k], n, bh, b0, b1);
+        for (int64_t b = b0; b <= b1; ++b) {
+            const int32_t o = atomicAdd(&hist[b], 1);
+            list[base[b] + o] = (int32_t)k;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_band_count(int64_t nbig, const int32_t *__restrict__ row0,
+                                                    const int64_t *__restrict__ rows, int bh, int32_t nbands,
+                                                    int32_t *__restrict__ count)
+{
+    extern __shared__ int32_t hist[];
+    const int64_t lo = (int64_t)blockIdx.x * BIN_TRIS;
+    bin_count(lo, min(lo + BIN_TRIS, nbig), row0, rows, bh, nbands, hist, count);
+}
+
+__global__ __launch_bounds__(256) void k_band_scatter(int64_t nbig, const int32_t *__restrict__ row0,
                                                       const int64_t *__restrict__ rows, int bh, int32_t nbands,
                                                       unsigned long long *__restrict__ cursor,
                                                       int32_t *__restrict__ list)
 {
     extern __shared__ int32_t sh[];
-    int32_t *hist = sh;
-    unsigned long long *base = reinterpret_cast<unsigned long long *>(sh + band_hist_words(nbands));
-    for (int32_t b = threadIdx.x; b <= nbands; b += blockDim.x) hist[b] = 0;
-    __syncthreads();
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t b0 = 0, b1 = -1;
-    if (k < nbig && rows[k] > 0) {
-        band_range(prep[k], rows[k], bh, b0, b1);
-        atomicAdd(&hist[b0], 1);
-        atomicAdd(&hist[b1 + 1], -1);
-    }
-    band_diff_to_counts(hist, nbands, hist + nbands + 1);
-    for (int32_t b = threadIdx.x; b < nbands; b += blockDim.x) {
-        if (hist[b]) base[b] = atomicAdd(cursor + b, (unsigned long long)hist[b]);
-        hist[b] = 0;
-    }
-    __syncthreads();
-    for (int64_t b = b0; b <= b1; ++b) {
-        const int32_t o = atomicAdd(&hist[b], 1);
-        list[base[b] + o] = (int32_t)k;
-    }
+    const int64_t lo = (int64_t)blockIdx.x * BIN_TRIS;
+    bin_scatter(lo, min(lo + BIN_TRIS, nbig), row0, rows, bh, nbands, sh, cursor, list);
 }
 
 // One workgroup per band of bh pixel rows; a thread takes one (listed
@@ -1106,65 +1136,34 @@ __global__ __launch_bounds__(BAND_THREADS) void k_band_batch(const BatchMap *__r
 
 // band binning of a batch's large triangles.  The triangles of map m are
 // the contiguous range [big_lo, big_hi) of its BatchMap (they were gathered
-// in cell order); slice s of the launch is workgroup-sized and lies inside
-// one map (`slice_map`, `slice_lo`), so a workgroup histograms that map's
-// bands in LDS and issues one device-wide atomic per band it touches.
+// in cell order); slice s of the launch holds up to BIN_TRIS of them and lies
+// inside one map (`slice_map`, `slice_lo`), so a workgroup histograms that
+// map's bands in LDS and issues one device-wide atomic per band it touches.
 __global__ __launch_bounds__(256) void k_band_count_batch(const BatchMap *__restrict__ maps,
                                                           const int32_t *__restrict__ slice_map,
                                                           const int64_t *__restrict__ slice_lo,
-                                                          const BigPrep *__restrict__ prep,
+                                                          const int32_t *__restrict__ row0,
                                                           const int64_t *__restrict__ rows,
                                                           int32_t *__restrict__ count)
 {
-    extern __shared__ int32_t hist[];   // nb + 1 entries, then 4 chunk-scan totals
+    extern __shared__ int32_t hist[];
     const BatchMap &d = maps[slice_map[blockIdx.x]];
-    const int32_t nb = (int32_t)d.nbands;
-    for (int32_t b = threadIdx.x; b <= nb; b += blockDim.x) hist[b] = 0;
-    __syncthreads();
-    const int64_t k = slice_lo[blockIdx.x] + threadIdx.x;
-    if (k < d.big_hi && rows[k] > 0) {
-        int64_t b0, b1;
-        band_range(prep[k], rows[k], d.bh, b0, b1);
-        atomicAdd(&hist[b0], 1);
-        atomicAdd(&hist[b1 + 1], -1);
-    }
-    band_diff_to_counts(hist, nb, hist + nb + 1);
-    for (int32_t b = threadIdx.x; b < nb; b += blockDim.x)
-        if (hist[b]) atomicAdd(count + d.band_lo + b, hist[b]);
+    const int64_t lo = slice_lo[blockIdx.x];
+    bin_count(lo, min(lo + BIN_TRIS, d.big_hi), row0, rows, d.bh, (int32_t)d.nbands, hist, count + d.band_lo);
 }
 
 __global__ __launch_bounds__(256) void k_band_scatter_batch(const BatchMap *__restrict__ maps,
                                                             const int32_t *__restrict__ slice_map,
                                                             const int64_t *__restrict__ slice_lo,
-                                                            const BigPrep *__restrict__ prep,
+                                                            const int32_t *__restrict__ row0,
                                                             const int64_t *__restrict__ rows,
                                                             unsigned long long *__restrict__ cursor,
                                                             int32_t *__restrict__ list)
 {
     extern __shared__ int32_t sh[];
     const BatchMap &d = maps[slice_map[blockIdx.x]];
-    const int32_t nb = (int32_t)d.nbands;
-    int32_t *hist = sh;
-    unsigned long long *base = reinterpret_cast<unsigned long long *>(sh + band_hist_words(nb));
-    for (int32_t b = threadIdx.x; b <= nb; b += blockDim.x) hist[b] = 0;
-    __syncthreads();
-    const int64_t k = slice_lo[blockIdx.x] + threadIdx.x;
-    int64_t b0 = 0, b1 = -1;
-    if (k < d.big_hi && rows[k] > 0) {
-        band_range(prep[k], rows[k], d.bh, b0, b1);
-        atomicAdd(&hist[b0], 1);
-        atomicAdd(&hist[b1 + 1], -1);
-    }
-    band_diff_to_counts(hist, nb, hist + nb + 1);
-    for (int32_t b = threadIdx.x; b < nb; b += blockDim.x) {
-        if (hist[b]) base[b] = atomicAdd(cursor + d.band_lo + b, (unsigned long long)hist[b]);
-        hist[b] = 0;
-    }
-    __syncthreads();
-    for (int64_t b = b0; b <= b1; ++b) {
-        const int32_t o = atomicAdd(&hist[b], 1);
-        list[base[b] + o] = (int32_t)k;
-    }
+    const int64_t lo = slice_lo[blockIdx.x];
+    bin_scatter(lo, min(lo + BIN_TRIS, d.big_hi), row0, rows, d.bh, (int32_t)d.nbands, sh, cursor + d.band_lo, list);
 }
 
 // map[j][i] += sum_{k <= i} diff[j][k]; one wavefront per pixel row
@@ -1207,11 +1206,11 @@ void launch_ipm(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int
 }
 
 void launch_big_gather(int64_t ncells, const int64_t *boff, const double2 *verts, int64_t nr1, int64_t cb0,
-                       int64_t vb0, const MapGeom &g, BigPrep *prep, int64_t *rows, hipStream_t st)
+                       int64_t vb0, const MapGeom &g, BigPrep *prep, int64_t *rows, int32_t *row0, hipStream_t st)
 {
     if (ncells > 0)
         hipLaunchKernelGGL(k_big_gather, dim3((unsigned)((ncells + 255) / 256)), dim3(256), 0, st, ncells, boff, verts,
-                           nr1, cb0, vb0, g, prep, rows);
+                           nr1, cb0, vb0, g, prep, rows, row0);
 }
 
 void launch_big(int64_t nbig, const BigPrep *prep, const int64_t *rows, const MapGeom &g, double *map, double *diff,
@@ -1233,20 +1232,20 @@ int band_height(int32_t n1, int32_t n2)
     return (int)bh;
 }
 
-void launch_band_count(int64_t nbig, const BigPrep *prep, const int64_t *rows, int bh, int32_t nbands, int32_t *count,
+void launch_band_count(int64_t nbig, const int32_t *row0, const int64_t *rows, int bh, int32_t nbands, int32_t *count,
                        hipStream_t st)
 {
     if (nbig > 0)
-        hipLaunchKernelGGL(k_band_count, dim3((unsigned)((nbig + 255) / 256)), dim3(256),
-                           band_hist_words(nbands) * sizeof(int32_t), st, nbig, prep, rows, bh, nbands, count);
+        hipLaunchKernelGGL(k_band_count, dim3((unsigned)((nbig + BIN_TRIS - 1) / BIN_TRIS)), dim3(256),
+                           band_hist_words(nbands) * sizeof(int32_t), st, nbig, row0, rows, bh, nbands, count);
 }
 
-void launch_band_scatter(int64_t nbig, const BigPrep *prep, const int64_t *rows, int bh, int32_t nbands,
+void launch_band_scatter(int64_t nbig, const int32_t *row0, const int64_t *rows, int bh, int32_t nbands,
                          unsigned long long *cursor, int32_t *list, hipStream_t st)
 {
     size_t shmem = band_hist_words(nbands) * sizeof(int32_t) + nbands * sizeof(unsigned long long);
     if (nbig > 0)
-        hipLaunchKernelGGL(k_band_scatter, dim3((unsigned)((nbig + 255) / 256)), dim3(256), shmem, st, nbig, prep, rows,
+        hipLaunchKernelGGL(k_band_scatter, dim3((unsigned)((nbig + BIN_TRIS - 1) / BIN_TRIS)), dim3(256), shmem, st, nbig, row0, rows,
                            bh, nbands, cursor, list);
 }
 
@@ -1271,31 +1270,31 @@ void launch_ipm_batch(const BatchMap *maps, int32_t nmaps, int64_t nctiles, int3
 }
 
 void launch_big_gather_batch(const BatchMap *maps, int32_t nmaps, int64_t ncells, const int64_t *boff, BigPrep *prep,
-                             int64_t *rows, int32_t *owner, hipStream_t st)
+                             int64_t *rows, int32_t *row0, hipStream_t st)
 {
     if (ncells > 0)
         hipLaunchKernelGGL(k_big_gather_batch, dim3((unsigned)((ncells + 255) / 256)), dim3(256), 0, st, maps, nmaps,
-                           ncells, boff, prep, rows, owner);
+                           ncells, boff, prep, rows, row0);
 }
 
 void launch_band_count_batch(const BatchMap *maps, int64_t nslices, const int32_t *slice_map, const int64_t *slice_lo,
-                             int32_t max_bands, const BigPrep *prep, const int64_t *rows, int32_t *count,
+                             int32_t max_bands, const int32_t *row0, const int64_t *rows, int32_t *count,
                              hipStream_t st)
 {
     if (nslices > 0)
         hipLaunchKernelGGL(k_band_count_batch, dim3((unsigned)nslices), dim3(256),
-                           band_hist_words(max_bands) * sizeof(int32_t), st, maps, slice_map, slice_lo, prep, rows,
+                           band_hist_words(max_bands) * sizeof(int32_t), st, maps, slice_map, slice_lo, row0, rows,
                            count);
 }
 
 void launch_band_scatter_batch(const BatchMap *maps, int64_t nslices, const int32_t *slice_map,
-                               const int64_t *slice_lo, int32_t max_bands, const BigPrep *prep, const int64_t *rows,
+                               const int64_t *slice_lo, int32_t max_bands, const int32_t *row0, const int64_t *rows,
                                unsigned long long *cursor, int32_t *list, hipStream_t st)
 {
     const size_t shmem = band_hist_words(max_bands) * sizeof(int32_t) + (size_t)max_bands * sizeof(unsigned long long);
     if (nslices > 0)
         hipLaunchKernelGGL(k_band_scatter_batch, dim3((unsigned)nslices), dim3(256), shmem, st, maps, slice_map,
-                           slice_lo, prep, rows, cursor, list);
+                           slice_lo, row0, rows, cursor, list);
 }
 
 void launch_band_batch(const BatchMap *maps, int32_t nmaps, int64_t nbands, const unsigned long long *band_off,
