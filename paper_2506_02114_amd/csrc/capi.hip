@@ -191,14 +191,14 @@ __global__ void k_zero_u64n(unsigned long long *p, int64_t n)
     if (t < n) p[t] = 0;
 }
 
-// out[m] = boff[maps[m].cell_lo], out[nmaps] = boff[ncells]: where each map's
-// large triangles start in the gathered list
-__global__ void k_map_big_bounds(const BatchMap *maps, int32_t nmaps, int64_t ncells, const int64_t *boff,
+// out[m] = toff[maps[m].ctile_lo], out[nmaps] = toff[ntiles]: where each
+// map's large triangles start in the gathered list
+__global__ void k_map_big_bounds(const BatchMap *maps, int32_t nmaps, int64_t ntiles, const int64_t *toff,
                                  int64_t *out)
 {
     const int32_t m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m < nmaps) out[m] = boff[maps[m].cell_lo];
-    if (m == nmaps) out[m] = boff[ncells];
+    if (m < nmaps) out[m] = toff[maps[m].ctile_lo];
+    if (m == nmaps) out[m] = toff[ntiles];
 }
 
 // --------------------------------------------------------------------------
@@ -212,7 +212,7 @@ constexpr int PREP_THREADS = 8;
 
 struct BatchWs {
     std::mutex mu;
-    DevBuf maps, verts, nbig, boff, prep, rows, row0, bcnt, boffs, bcur, blist, counters, bounds, slice_map, slice_lo;
+    DevBuf maps, verts, tbig, toff, prep, rows, row0, bcnt, boffs, bcur, blist, counters, bounds, slice_map, slice_lo;
     hipStream_t prep_st[PREP_THREADS] = {};   // created on first use, default priority
 };
 
@@ -606,18 +606,20 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
         // IPM: cell pass, then one thread per (triangle, pixel column) for the
         // ordinary triangles and the row-parallel passes for the large ones
         const int64_t ncells = (R.nr1 - 1) * (r1 - r0);
-        int32_t *nbig = static_cast<int32_t *>(ws.nbig.reserve((size_t)ncells * sizeof(int32_t)));
-        int64_t *bigoff = static_cast<int64_t *>(ws.bigoff.reserve((size_t)(ncells + 1) * sizeof(int64_t)));
-        launch_ipm(verts, R.nr1, r0, r1, vb0, g, map, cnt, nbig, q.precision == MLM_PREC_MIXED,
+        const int64_t ntl = ipm_tile_count(R.nr1, r1 - r0);
+        int32_t *tbig = static_cast<int32_t *>(ws.tbig.reserve((size_t)std::max<int64_t>(ntl, 1) * sizeof(int32_t)));
+        int64_t *toff = static_cast<int64_t *>(ws.tbigoff.reserve((size_t)(ntl + 1) * sizeof(int64_t)));
+        if (ntl > 0) hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((ntl + 255) / 256)), dim3(256), 0, st, tbig, ntl);
+        launch_ipm(verts, R.nr1, r0, r1, vb0, g, map, cnt, tbig, q.precision == MLM_PREC_MIXED,
                    q.timing >= 2 ? cnt + 8 : nullptr, st);
         const int e_cells = tm.mark();
         int e_band0 = -1, e_band1 = -1;
-        const int64_t nb = scan_i32_to_i64(lens, nbig, bigoff, ncells, st);
+        const int64_t nb = scan_i32_to_i64(lens, tbig, toff, ntl, st);
         if (nb > 0) {
             BigPrep *prep = static_cast<BigPrep *>(ws.bigprep.reserve((size_t)nb * sizeof(BigPrep)));
             int64_t *rows = static_cast<int64_t *>(ws.bigrows.reserve((size_t)nb * sizeof(int64_t)));
             int32_t *row0 = static_cast<int32_t *>(ws.bigrow0.reserve((size_t)nb * sizeof(int32_t)));
-            launch_big_gather(ncells, bigoff, verts, R.nr1, r0, vb0, g, prep, rows, row0, st);
+            launch_big_gather(verts, R.nr1, r0, r1, vb0, g, toff, prep, rows, row0, st);
             const int bh = band_height(g.n1, g.n2);
             if (bh > 0) {
                 // large triangles by pixel bands: owned rows, LDS accumulation
@@ -903,20 +905,21 @@ mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, i
         const int ea = tm.mark();
         launch_shoot_batch(dmaps, nm, tl, st);
         const int eb = tm.mark();
-        int32_t *nbig = static_cast<int32_t *>(B.nbig.reserve((size_t)std::max<int64_t>(cl, 1) * sizeof(int32_t)));
-        int64_t *boff = static_cast<int64_t *>(B.boff.reserve((size_t)(cl + 1) * sizeof(int64_t)));
-        launch_ipm_batch(dmaps, nm, ctl, nbig, st);
-        const int64_t nb = scan_i32_to_i64(scan_lens, nbig, boff, cl, st);
+        int32_t *tbig = static_cast<int32_t *>(B.tbig.reserve((size_t)std::max<int64_t>(ctl, 1) * sizeof(int32_t)));
+        int64_t *toff = static_cast<int64_t *>(B.toff.reserve((size_t)(ctl + 1) * sizeof(int64_t)));
+        if (ctl > 0) hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((ctl + 255) / 256)), dim3(256), 0, st, tbig, ctl);
+        launch_ipm_batch(dmaps, nm, ctl, tbig, st);
+        const int64_t nb = scan_i32_to_i64(scan_lens, tbig, toff, ctl, st);
         if (nb > 0) {
             BigPrep *prep = static_cast<BigPrep *>(B.prep.reserve((size_t)nb * sizeof(BigPrep)));
             int64_t *rows = static_cast<int64_t *>(B.rows.reserve((size_t)nb * sizeof(int64_t)));
             int32_t *row0 = static_cast<int32_t *>(B.row0.reserve((size_t)nb * sizeof(int32_t)));
-            launch_big_gather_batch(dmaps, nm, cl, boff, prep, rows, row0, st);
+            launch_big_gather_batch(dmaps, nm, ctl, toff, prep, rows, row0, st);
             // each map's slice of the gathered list, cut into workgroup-sized
             // slices for the binning passes
             int64_t *bnd = static_cast<int64_t *>(B.bounds.reserve((size_t)(nm + 1) * sizeof(int64_t)));
-            hipLaunchKernelGGL(k_map_big_bounds, dim3((unsigned)((nm + 1 + 255) / 256)), dim3(256), 0, st, dmaps, nm, cl,
-                               boff, bnd);
+            hipLaunchKernelGGL(k_map_big_bounds, dim3((unsigned)((nm + 1 + 255) / 256)), dim3(256), 0, st, dmaps, nm, ctl,
+                               toff, bnd);
             std::vector<int64_t> hb((size_t)nm + 1);
             MLM_HIP(hipMemcpyAsync(hb.data(), bnd, hb.size() * sizeof(int64_t), hipMemcpyDeviceToHost, st));
             MLM_HIP(hipStreamSynchronize(st));

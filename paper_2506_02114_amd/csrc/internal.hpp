@@ -184,7 +184,7 @@ struct Workspace {
     DevBuf code, level, leaf, slo, shi, block, parent, child0, coll, node_leaf, leaf_node, flags, offs;
     DevBuf ilist, mult, local, ops_m2m, ops_m2l, ops_l2l;
     DevBuf leaves, near, deriv, near_offs;
-    DevBuf tile_off, tile_leaf, verts, map, wbuf, pts, counters, items, itemoff, nbig, bigoff, bigprep, bigrows, bigrow0, rowoff, nbnd, nbndoff, diff, bandcnt, bandoff,
+    DevBuf tile_off, tile_leaf, verts, map, wbuf, pts, counters, items, itemoff, tbig, tbigoff, bigprep, bigrows, bigrow0, rowoff, nbnd, nbndoff, diff, bandcnt, bandoff,
         bandcur, bandlist, rfeat, rlogit, rflag, rpos, rcand, rlabel, rstats;
     void *pinned = nullptr;               // small pinned host buffer for read-backs
     size_t pinned_cap = 0;
@@ -253,11 +253,14 @@ constexpr int WORK_SLOTS = 256;
 // large triangles per workgroup of the band binning passes (and per slice of
 // a batch map's list of them)
 constexpr int64_t BIN_TRIS = 2048;
+// cell tiles of the cell pass over cell rows [cb0, cb0 + nrows): one workgroup and one
+// large-triangle count each
+int64_t ipm_tile_count(int64_t nr1, int64_t nrows);
 void launch_ipm(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int64_t vb0, const MapGeom &g,
-                double *map, unsigned long long *counters, int32_t *nbig, bool mixed, unsigned long long *work,
+                double *map, unsigned long long *counters, int32_t *tile_big, bool mixed, unsigned long long *work,
                 hipStream_t st);
-void launch_big_gather(int64_t ncells, const int64_t *boff, const double2 *verts, int64_t nr1, int64_t cb0,
-                       int64_t vb0, const MapGeom &g, BigPrep *prep, int64_t *rows, int32_t *row0, hipStream_t st);
+void launch_big_gather(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int64_t vb0, const MapGeom &g,
+                       const int64_t *tile_off, BigPrep *prep, int64_t *rows, int32_t *row0, hipStream_t st);
 void launch_big(int64_t nbig, const BigPrep *prep, const int64_t *rows, const MapGeom &g, double *map, double *diff,
                 hipStream_t st);
 void launch_diff_rows(const MapGeom &g, const double *diff, double *map, hipStream_t st);
@@ -269,9 +272,9 @@ void launch_band_scatter(int64_t nbig, const int32_t *row0, const int64_t *rows,
 void launch_band(int32_t nbands, const unsigned long long *band_off, const int32_t *list, const BigPrep *prep,
                  const int64_t *rows, int bh, const MapGeom &g, double *map, unsigned long long *work,
                  hipStream_t st);
-void launch_ipm_batch(const BatchMap *maps, int32_t nmaps, int64_t nctiles, int32_t *nbig, hipStream_t st);
-void launch_big_gather_batch(const BatchMap *maps, int32_t nmaps, int64_t ncells, const int64_t *boff, BigPrep *prep,
-                             int64_t *rows, int32_t *row0, hipStream_t st);
+void launch_ipm_batch(const BatchMap *maps, int32_t nmaps, int64_t nctiles, int32_t *tile_big, hipStream_t st);
+void launch_big_gather_batch(const BatchMap *maps, int32_t nmaps, int64_t nctiles, const int64_t *tile_off,
+                             BigPrep *prep, int64_t *rows, int32_t *row0, hipStream_t st);
 void launch_band_count_batch(const BatchMap *maps, int64_t nslices, const int32_t *slice_map, const int64_t *slice_lo,
                              int32_t max_bands, const int32_t *row0, const int64_t *rows, int32_t *count,
                              hipStream_t st);

@@ -367,14 +367,6 @@ __device__ inline void load_cell_at(const double2 *verts, int64_t nr1, int64_t r
     v01 = P2{r1[0], r1[1]};
 }
 
-__device__ inline void load_cell(const double2 *verts, int64_t nr1, int64_t cb0, int64_t vb0, int64_t cell,
-                                 P2 &v00, P2 &v10, P2 &v11, P2 &v01)
-{
-    const int64_t ncol = nr1 - 1;
-    const int64_t a = cell % ncol, b = cb0 + cell / ncol;
-    load_cell_at(verts, nr1, b - vb0, a, v00, v10, v11, v01);
-}
-
 __device__ inline bool cell_in_one_pixel(P2 v00, P2 v10, P2 v11, P2 v01, const MapGeom &g, int &pi, int &pj)
 {
     const double fu = floor(v00.u), fv = floor(v00.v);
@@ -499,7 +491,7 @@ constexpr int CT = 16;   // cells per tile side
 template <bool MIXED>
 __device__ __forceinline__ void ipm_tile(const double2 *__restrict__ verts, int64_t nr1, int64_t cb0, int64_t nrows,
                                 int64_t vb0, const MapGeom &g, double *__restrict__ map,
-                                unsigned long long *__restrict__ counters, int32_t *__restrict__ nbig, int64_t tile,
+                                unsigned long long *__restrict__ counters, int32_t *__restrict__ tile_big, int64_t tile,
                                 double *acc, unsigned long long *__restrict__ work)
 {
     const int64_t ncol = nr1 - 1;
@@ -525,11 +517,10 @@ __device__ __forceinline__ void ipm_tile(const double2 *__restrict__ verts, int6
     int mcols[2] = {0, 0};      // pixel columns of each medium triangle of the cell (0: none)
     int mi0[2] = {0, 0};
     P2 v00{0.0, 0.0}, v10{0.0, 0.0}, v11{0.0, 0.0}, v01{0.0, 0.0};
+    int nb = 0;   // large triangles of the cell
     if (a < ncol && brow < nrows) {
-        const int64_t cell = brow * ncol + a;
         load_cell_at(verts, nr1, cb0 + brow - vb0, a, v00, v10, v11, v01);
         int pi, pj;
-        int nb = 0;
         if (cell_in_one_pixel(v00, v10, v11, v01, g, pi, pj)) {
             if (pi >= 0) deposit_w(w, map, g, pi, pj, 2.0 * g.tri_weight);
         } else {
@@ -558,7 +549,12 @@ __device__ __forceinline__ void ipm_tile(const double2 *__restrict__ verts, int6
                 }
             }
         }
-        nbig[cell] = nb;
+    }
+    {   // the tile's count of large triangles (tile_big is zeroed beforehand)
+        int s = nb;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+        if (lane == 0 && s) atomicAdd(tile_big + tile, s);
     }
     // the medium triangles' pixel columns, spread evenly over the wavefront's
     // lanes: first triangle of every cell, then the second
@@ -603,17 +599,17 @@ __device__ __forceinline__ void ipm_tile(const double2 *__restrict__ verts, int6
 template <bool MIXED>
 __global__ __launch_bounds__(256) void k_ipm(const double2 *__restrict__ verts, int64_t nr1, int64_t cb0,
                                              int64_t nrows, int64_t vb0, MapGeom g, double *__restrict__ map,
-                                             unsigned long long *__restrict__ counters, int32_t *__restrict__ nbig,
+                                             unsigned long long *__restrict__ counters, int32_t *__restrict__ tile_big,
                                              unsigned long long *__restrict__ work)
 {
     __shared__ double acc[WIN * WIN];
-    ipm_tile<MIXED>(verts, nr1, cb0, nrows, vb0, g, map, counters, nbig, blockIdx.x, acc, work);
+    ipm_tile<MIXED>(verts, nr1, cb0, nrows, vb0, g, map, counters, tile_big, blockIdx.x, acc, work);
 }
 
 // every cell tile of every map of a fused batch in one launch (one
 // workgroup per tile of the concatenated tile list)
 __global__ __launch_bounds__(256) void k_ipm_batch(const BatchMap *__restrict__ maps, int32_t nmaps,
-                                                   int64_t ntiles, int32_t *__restrict__ nbig)
+                                                   int64_t ntiles, int32_t *__restrict__ tile_big)
 {
     __shared__ double acc[WIN * WIN];
     {
@@ -621,31 +617,37 @@ __global__ __launch_bounds__(256) void k_ipm_batch(const BatchMap *__restrict__ 
         const int32_t m = batch_find(maps, nmaps, t, &BatchMap::ctile_lo);
         const BatchMap &d = maps[m];
         if (d.mixed)
-            ipm_tile<true>(d.verts, d.nr1, 0, d.nrows, 0, d.g, d.map, d.counters, nbig + d.cell_lo, t - d.ctile_lo,
+            ipm_tile<true>(d.verts, d.nr1, 0, d.nrows, 0, d.g, d.map, d.counters, tile_big + d.ctile_lo, t - d.ctile_lo,
                            acc, nullptr);
         else
-            ipm_tile<false>(d.verts, d.nr1, 0, d.nrows, 0, d.g, d.map, d.counters, nbig + d.cell_lo, t - d.ctile_lo,
+            ipm_tile<false>(d.verts, d.nr1, 0, d.nrows, 0, d.g, d.map, d.counters, tile_big + d.ctile_lo, t - d.ctile_lo,
                             acc, nullptr);
     }
 }
 
-// set-up of every large triangle, written at its slot of the exclusive scan
-// of the per-cell counts: integer local origin (inside or at the edge of the
-// map, so nearby pixel boundaries are exact), counter-clockwise local
-// vertices, edge slopes, the deposit scale, and the pixel rows it covers
-// (their count in rows[], the first in row0[]: compact copies for the
-// binning passes, which need nothing else)
-__device__ inline void gather_cell(int64_t t, int64_t slot, int64_t end, const double2 *__restrict__ verts,
-                                   int64_t nr1, int64_t cb0, int64_t vb0, const MapGeom &g,
-                                   BigPrep *__restrict__ prep, int64_t *__restrict__ rows,
+// which of the cell's two triangles are large (bit k: triangle k), with the
+// cell pass's classification: none if the cell lies in one pixel
+__device__ inline int cell_big_mask(P2 v00, P2 v10, P2 v11, P2 v01, const MapGeom &g)
+{
+    int pi, pj;
+    if (cell_in_one_pixel(v00, v10, v11, v01, g, pi, pj)) return 0;
+    return (classify(v00, v10, v11, g).kind == 3 ? 1 : 0) | (classify(v00, v11, v01, g).kind == 3 ? 2 : 0);
+}
+
+// set-up of the cell's large triangles (`mask`), written to slots [slot,
+// end): integer local origin (inside or at the edge of the map, so nearby
+// pixel boundaries are exact), counter-clockwise local vertices, edge slopes,
+// the deposit scale, and the pixel rows it covers (their count in rows[], the
+// first in row0[]: compact copies for the binning passes, which need nothing
+// else)
+__device__ inline void gather_cell(P2 v00, P2 v10, P2 v11, P2 v01, int mask, int64_t slot, int64_t end,
+                                   const MapGeom &g, BigPrep *__restrict__ prep, int64_t *__restrict__ rows,
                                    int32_t *__restrict__ row0)
 {
-    P2 v00, v10, v11, v01;
-    load_cell(verts, nr1, cb0, vb0, t, v00, v10, v11, v01);
     const P2 tri[2][3] = {{v00, v10, v11}, {v00, v11, v01}};
     for (int k = 0; k < 2 && slot < end; ++k) {
+        if (!(mask >> k & 1)) continue;
         const P2 A = tri[k][0], B = tri[k][1], C = tri[k][2];
-        if (classify(A, B, C, g).kind != 3) continue;
         const double umin = fmin(A.u, fmin(B.u, C.u));
         const double vmin = fmin(A.v, fmin(B.v, C.v)), vmax = fmax(A.v, fmax(B.v, C.v));
         const double ou = fmax(floor(umin), 0.0), ov = fmax(floor(vmin), 0.0);
@@ -682,27 +684,67 @@ __device__ inline void gather_cell(int64_t t, int64_t slot, int64_t end, const d
     }
 }
 
-__global__ __launch_bounds__(256) void k_big_gather(int64_t ncells, const int64_t *__restrict__ boff,
-                                                    const double2 *__restrict__ verts, int64_t nr1, int64_t cb0,
-                                                    int64_t vb0, MapGeom g, BigPrep *__restrict__ prep,
-                                                    int64_t *__restrict__ rows, int32_t *__restrict__ row0)
+// The large triangles of one cell tile (one workgroup of 256 threads, the
+// cells over the threads as in the cell pass), written in thread order to
+// [lo, hi), the tile's range from the scan of the cell pass's per-tile counts.
+// Slots of that range this pass does not fill (none, as both passes classify
+// alike) are left as triangles without rows.
+__device__ inline void gather_tile(const double2 *__restrict__ verts, int64_t nr1, int64_t cb0, int64_t nrows,
+                                   int64_t vb0, const MapGeom &g, int64_t tile, int64_t lo, int64_t hi,
+                                   BigPrep *__restrict__ prep, int64_t *__restrict__ rows,
+                                   int32_t *__restrict__ row0, int32_t *wsum)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ncells || boff[t + 1] == boff[t]) return;
-    gather_cell(t, boff[t], boff[t + 1], verts, nr1, cb0, vb0, g, prep, rows, row0);
+    const int64_t ncol = nr1 - 1;
+    const int64_t tiles_a = (ncol + CT - 1) / CT;
+    const int64_t ta = tile % tiles_a, tb = tile / tiles_a;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t a = ta * CT + (lane & (CT - 1));
+    const int64_t brow = tb * CT + wave * 4 + (lane >> 4);
+    P2 v00{0.0, 0.0}, v10{0.0, 0.0}, v11{0.0, 0.0}, v01{0.0, 0.0};
+    int mask = 0;
+    if (a < ncol && brow < nrows) {
+        load_cell_at(verts, nr1, cb0 + brow - vb0, a, v00, v10, v11, v01);
+        mask = cell_big_mask(v00, v10, v11, v01, g);
+    }
+    const int nb = (mask & 1) + (mask >> 1);
+    int total;
+    const int excl = wave_excl_scan(nb, lane, total);
+    if (lane == 0) wsum[wave] = total;
+    __syncthreads();
+    int64_t slot = lo + excl, found = 0;
+    for (int w = 0; w < 4; ++w) {
+        if (w < wave) slot += wsum[w];
+        found += wsum[w];
+    }
+    if (mask) gather_cell(v00, v10, v11, v01, mask, slot, min(slot + nb, hi), g, prep, rows, row0);
+    for (int64_t s = lo + found + threadIdx.x; s < hi; s += blockDim.x) {
+        rows[s] = 0;
+        row0[s] = 0;
+    }
 }
 
-// the batch's cells: boff is the scan over all maps' cells
+__global__ __launch_bounds__(256) void k_big_gather(const double2 *__restrict__ verts, int64_t nr1, int64_t cb0,
+                                                    int64_t nrows, int64_t vb0, MapGeom g,
+                                                    const int64_t *__restrict__ tile_off, BigPrep *__restrict__ prep,
+                                                    int64_t *__restrict__ rows, int32_t *__restrict__ row0)
+{
+    __shared__ int32_t wsum[4];
+    const int64_t t = blockIdx.x, lo = tile_off[t], hi = tile_off[t + 1];
+    if (lo == hi) return;   // the whole workgroup
+    gather_tile(verts, nr1, cb0, nrows, vb0, g, t, lo, hi, prep, rows, row0, wsum);
+}
+
+// the batch's cell tiles: tile_off is the scan over all maps' tiles
 __global__ __launch_bounds__(256) void k_big_gather_batch(const BatchMap *__restrict__ maps, int32_t nmaps,
-                                                          int64_t ncells, const int64_t *__restrict__ boff,
+                                                          const int64_t *__restrict__ tile_off,
                                                           BigPrep *__restrict__ prep, int64_t *__restrict__ rows,
                                                           int32_t *__restrict__ row0)
 {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncells || boff[c + 1] == boff[c]) return;
-    const int32_t m = batch_find(maps, nmaps, c, &BatchMap::cell_lo);
-    const BatchMap &d = maps[m];
-    gather_cell(c - d.cell_lo, boff[c], boff[c + 1], d.verts, d.nr1, 0, 0, d.g, prep, rows, row0);
+    __shared__ int32_t wsum[4];
+    const int64_t t = blockIdx.x, lo = tile_off[t], hi = tile_off[t + 1];
+    if (lo == hi) return;   // the whole workgroup
+    const BatchMap &d = maps[batch_find(maps, nmaps, t, &BatchMap::ctile_lo)];
+    gather_tile(d.verts, d.nr1, 0, d.nrows, 0, d.g, t - d.ctile_lo, lo, hi, prep, rows, row0, wsum);
 }
 
 // The edges of a large triangle clipped to pixel row j (local coordinates),
@@ -1191,26 +1233,33 @@ __global__ __launch_bounds__(64) void k_diff_rows(MapGeom g, const double *__res
 }  // namespace
 
 void launch_ipm(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int64_t vb0, const MapGeom &g,
-                double *map, unsigned long long *counters, int32_t *nbig, bool mixed, unsigned long long *work,
+                double *map, unsigned long long *counters, int32_t *tile_big, bool mixed, unsigned long long *work,
                 hipStream_t st)
 {
-    const int64_t ncol = nr1 - 1, nrows = cb1 - cb0;
-    if (ncol <= 0 || nrows <= 0) return;
-    const int64_t tiles = ((ncol + CT - 1) / CT) * ((nrows + CT - 1) / CT);
+    const int64_t nrows = cb1 - cb0, tiles = ipm_tile_count(nr1, nrows);
+    if (tiles <= 0) return;
     if (mixed)
         hipLaunchKernelGGL(k_ipm<true>, dim3((unsigned)tiles), dim3(256), 0, st, verts, nr1, cb0, nrows, vb0, g, map,
-                           counters, nbig, work);
+                           counters, tile_big, work);
     else
         hipLaunchKernelGGL(k_ipm<false>, dim3((unsigned)tiles), dim3(256), 0, st, verts, nr1, cb0, nrows, vb0, g, map,
-                           counters, nbig, work);
+                           counters, tile_big, work);
 }
 
-void launch_big_gather(int64_t ncells, const int64_t *boff, const double2 *verts, int64_t nr1, int64_t cb0,
-                       int64_t vb0, const MapGeom &g, BigPrep *prep, int64_t *rows, int32_t *row0, hipStream_t st)
+int64_t ipm_tile_count(int64_t nr1, int64_t nrows)
 {
-    if (ncells > 0)
-        hipLaunchKernelGGL(k_big_gather, dim3((unsigned)((ncells + 255) / 256)), dim3(256), 0, st, ncells, boff, verts,
-                           nr1, cb0, vb0, g, prep, rows, row0);
+    const int64_t ncol = nr1 - 1;
+    if (ncol <= 0 || nrows <= 0) return 0;
+    return ((ncol + CT - 1) / CT) * ((nrows + CT - 1) / CT);
+}
+
+void launch_big_gather(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int64_t vb0, const MapGeom &g,
+                       const int64_t *tile_off, BigPrep *prep, int64_t *rows, int32_t *row0, hipStream_t st)
+{
+    const int64_t tiles = ipm_tile_count(nr1, cb1 - cb0);
+    if (tiles > 0)
+        hipLaunchKernelGGL(k_big_gather, dim3((unsigned)tiles), dim3(256), 0, st, verts, nr1, cb0, cb1 - cb0, vb0, g,
+                           tile_off, prep, rows, row0);
 }
 
 void launch_big(int64_t nbig, const BigPrep *prep, const int64_t *rows, const MapGeom &g, double *map, double *diff,
@@ -1262,19 +1311,19 @@ void launch_band(int32_t nbands, const unsigned long long *band_off, const int32
                            g, map, work);
 }
 
-void launch_ipm_batch(const BatchMap *maps, int32_t nmaps, int64_t nctiles, int32_t *nbig, hipStream_t st)
+void launch_ipm_batch(const BatchMap *maps, int32_t nmaps, int64_t nctiles, int32_t *tile_big, hipStream_t st)
 {
     if (nctiles <= 0) return;
     if (nctiles > (int64_t)UINT32_MAX) fail(MLM_ERANGE, "too many cell tiles in one batch chunk");
-    hipLaunchKernelGGL(k_ipm_batch, dim3((unsigned)nctiles), dim3(256), 0, st, maps, nmaps, nctiles, nbig);
+    hipLaunchKernelGGL(k_ipm_batch, dim3((unsigned)nctiles), dim3(256), 0, st, maps, nmaps, nctiles, tile_big);
 }
 
-void launch_big_gather_batch(const BatchMap *maps, int32_t nmaps, int64_t ncells, const int64_t *boff, BigPrep *prep,
-                             int64_t *rows, int32_t *row0, hipStream_t st)
+void launch_big_gather_batch(const BatchMap *maps, int32_t nmaps, int64_t nctiles, const int64_t *tile_off,
+                             BigPrep *prep, int64_t *rows, int32_t *row0, hipStream_t st)
 {
-    if (ncells > 0)
-        hipLaunchKernelGGL(k_big_gather_batch, dim3((unsigned)((ncells + 255) / 256)), dim3(256), 0, st, maps, nmaps,
-                           ncells, boff, prep, rows, row0);
+    if (nctiles > 0)
+        hipLaunchKernelGGL(k_big_gather_batch, dim3((unsigned)nctiles), dim3(256), 0, st, maps, nmaps, tile_off, prep,
+                           rows, row0);
 }
 
 void launch_band_count_batch(const BatchMap *maps, int64_t nslices, const int32_t *slice_map, const int64_t *slice_lo,
