@@ -1269,6 +1269,22 @@ void launch_big(int64_t nbig, const BigPrep *prep, const int64_t *rows, const Ma
         hipLaunchKernelGGL(k_big, dim3((unsigned)((nbig + 255) / 256)), dim3(256), 0, st, nbig, prep, rows, g, map, diff);
 }
 
+// LDS bytes of the scatter pass's workgroup for nb bands (the largest of the
+// binning passes): the histogram with its scan totals, then one 8-byte range
+// start per band
+static size_t bin_lds_bytes(int64_t nb) { return band_hist_words(nb) * sizeof(int32_t) + (size_t)nb * 8; }
+
+// the LDS a workgroup may be given on the current device (64 KiB if the
+// device does not say)
+static size_t lds_per_workgroup()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        v <= 0)
+        v = 65536;
+    return (size_t)v;
+}
+
 int band_height(int32_t n1, int32_t n2)
 {
     // a power of two (at most 16, so it divides the workgroup), as many rows
@@ -1277,25 +1293,30 @@ int band_height(int32_t n1, int32_t n2)
     while (bh > 0 && bh * n1 > BAND_LDS_DOUBLES) bh >>= 1;
     // 0: the map is too wide for one band per workgroup, or has too many bands
     // for the binning histograms in LDS
-    if (bh > 0 && (n2 + bh - 1) / bh > 12000) bh = 0;
+    static const size_t lds = lds_per_workgroup();
+    if (bh > 0 && bin_lds_bytes((n2 + bh - 1) / bh) > lds) bh = 0;
     return (int)bh;
 }
 
 void launch_band_count(int64_t nbig, const int32_t *row0, const int64_t *rows, int bh, int32_t nbands, int32_t *count,
                        hipStream_t st)
 {
+    (void)hipGetLastError();   // clear what earlier calls left, so the check below sees this launch
     if (nbig > 0)
         hipLaunchKernelGGL(k_band_count, dim3((unsigned)((nbig + BIN_TRIS - 1) / BIN_TRIS)), dim3(256),
                            band_hist_words(nbands) * sizeof(int32_t), st, nbig, row0, rows, bh, nbands, count);
+    MLM_HIP(hipGetLastError());   // a refused launch leaves the band lists unset: fail here
 }
 
 void launch_band_scatter(int64_t nbig, const int32_t *row0, const int64_t *rows, int bh, int32_t nbands,
                          unsigned long long *cursor, int32_t *list, hipStream_t st)
 {
-    size_t shmem = band_hist_words(nbands) * sizeof(int32_t) + nbands * sizeof(unsigned long long);
+    const size_t shmem = bin_lds_bytes(nbands);
+    (void)hipGetLastError();   // clear what earlier calls left, so the check below sees this launch
     if (nbig > 0)
         hipLaunchKernelGGL(k_band_scatter, dim3((unsigned)((nbig + BIN_TRIS - 1) / BIN_TRIS)), dim3(256), shmem, st, nbig, row0, rows,
                            bh, nbands, cursor, list);
+    MLM_HIP(hipGetLastError());
 }
 
 void launch_band(int32_t nbands, const unsigned long long *band_off, const int32_t *list, const BigPrep *prep,
@@ -1330,20 +1351,24 @@ void launch_band_count_batch(const BatchMap *maps, int64_t nslices, const int32_
                              int32_t max_bands, const int32_t *row0, const int64_t *rows, int32_t *count,
                              hipStream_t st)
 {
+    (void)hipGetLastError();   // clear what earlier calls left, so the check below sees this launch
     if (nslices > 0)
         hipLaunchKernelGGL(k_band_count_batch, dim3((unsigned)nslices), dim3(256),
                            band_hist_words(max_bands) * sizeof(int32_t), st, maps, slice_map, slice_lo, row0, rows,
                            count);
+    MLM_HIP(hipGetLastError());
 }
 
 void launch_band_scatter_batch(const BatchMap *maps, int64_t nslices, const int32_t *slice_map,
                                const int64_t *slice_lo, int32_t max_bands, const int32_t *row0, const int64_t *rows,
                                unsigned long long *cursor, int32_t *list, hipStream_t st)
 {
-    const size_t shmem = band_hist_words(max_bands) * sizeof(int32_t) + (size_t)max_bands * sizeof(unsigned long long);
+    const size_t shmem = bin_lds_bytes(max_bands);
+    (void)hipGetLastError();   // clear what earlier calls left, so the check below sees this launch
     if (nslices > 0)
         hipLaunchKernelGGL(k_band_scatter_batch, dim3((unsigned)nslices), dim3(256), shmem, st, maps, slice_map,
                            slice_lo, row0, rows, cursor, list);
+    MLM_HIP(hipGetLastError());
 }
 
 void launch_band_batch(const BatchMap *maps, int32_t nmaps, int64_t nbands, const unsigned long long *band_off,

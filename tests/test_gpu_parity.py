@@ -218,6 +218,35 @@ def test_wide_maps_match_oracle(mlm, orc, n1):
     assert mu.sum() * pix * pix == pytest.approx(ref.dep_total, rel=1e-9)
 
 
+GOLDEN_TALL = os.path.join(os.path.dirname(__file__), "golden", "tall_map_pixels.npz")
+
+
+def test_tall_map_many_bands(mlm, orc):
+    """6000 one-row bands (5000 x 6000 px): more bands than the binning
+    passes can index in 64 KiB of LDS.  Where the device gives a workgroup
+    more, the band path runs with it, else the per-triangle row kernel; either
+    way the map matches the oracle's (every pixel row's sum and 22000 sampled
+    pixels, stored by tests/golden/make_tall_map_pixels.py)."""
+    gold = np.load(GOLDEN_TALL)
+    n1, n2, pix = int(gold["n1"]), int(gold["n2"]), float(gold["pix"])
+    sf = W.config("plain_small").stars()
+    gl, _ = _pair(mlm, orc, 0.3, 0.0, 0.3, sf)
+    spec = dict(hw1=0.5 * n1 * pix, hw2=0.5 * n2 * pix, n1=n1, n2=n2, nray1=int(gold["nray1"]),
+                nray2=int(gold["nray2"]), order=int(gold["order"]))
+    mu, st = gl.map(timing=2, **spec)
+    assert mu.shape == (n2, n1) and np.all(np.isfinite(mu))
+    rel, zok = _rel_map_err(mu.ravel()[gold["index"]], gold["mu"])
+    rs = mu.sum(axis=1)
+    ref_rs = gold["row_sum"]
+    pos = ref_rs > 0
+    rel_rows = np.abs(rs[pos] - ref_rs[pos]) / ref_rs[pos]
+    _report("map_tall_6000_bands_vs_oracle_fmm", max=float(rel.max()), rows_max=float(rel_rows.max()),
+            big=st["n_big"], band_rows=st["n_band_rows"], path="bands" if st["n_band_rows"] > 0 else "rows")
+    assert st["n_big"] > 0 and zok and rel.max() < 1e-9
+    assert rel_rows.max() < 1e-9 and np.all(np.abs(rs[~pos]) < 1e-9)
+    assert mu.sum() * pix * pix == pytest.approx(float(gold["dep_total"]), rel=1e-9)
+
+
 def test_map_device_output_and_stream(mlm, orc):
     import torch
     wl = W.config("plain_small")
