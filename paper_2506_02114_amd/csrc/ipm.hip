@@ -483,7 +483,8 @@ __device__ inline int setup_column(const ColSetup &c, int r, const MapGeom &g, d
 // T1 = (v00, v10, v11) and T2 = (v00, v11, v01)); then each wavefront spreads
 // its triangles' pixel columns evenly over its lanes.  A tile of cells maps to
 // a compact patch of the source plane, so deposits are summed in an LDS
-// window around the tile's image first.  Large triangles are only counted.
+// window around the tile's image first.  Large triangles are only counted:
+// one total per tile, for the gather pass.
 constexpr int CT = 16;   // cells per tile side
 
 // cell tile `tile` of a strip (a whole workgroup of 256 threads; acc is its
