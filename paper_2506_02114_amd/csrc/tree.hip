@@ -242,6 +242,25 @@ T *grow_keep(DevBuf &b, size_t used_elems, size_t need_elems, hipStream_t st)
 
 void *cub_tmp(Workspace &ws, size_t bytes) { return ws.cub_tmp.reserve(bytes ? bytes : 1); }
 
+// a scan's total read back to the host: a one-wavefront kernel stores it
+// straight into pinned host memory (one small launch where two copies were);
+// exclusive scans pass the last input (total = out[n - 1] + in[n - 1]),
+// inclusive ones none (total = out[n - 1])
+template <class T>
+__global__ void k_scan_total(const T *in, const T *out, int64_t n, int64_t *host)
+{
+    if (threadIdx.x == 0) host[0] = (int64_t)out[n - 1] + (in ? (int64_t)in[n - 1] : 0);
+}
+
+template <class T>
+int64_t read_total(mlm_lens *lens, const T *in, const T *out, int64_t n, hipStream_t st)
+{
+    int64_t *h = static_cast<int64_t *>(pinned(lens, sizeof(int64_t)));
+    hipLaunchKernelGGL(k_scan_total<T>, dim3(1), dim3(64), 0, st, in, out, n, h);
+    MLM_HIP(hipStreamSynchronize(st));
+    return h[0];
+}
+
 // exclusive prefix sum of n int32 flags; returns the total
 int64_t scan_total(mlm_lens *lens, const int32_t *in, int32_t *out, int64_t n, hipStream_t st)
 {
@@ -251,11 +270,7 @@ int64_t scan_total(mlm_lens *lens, const int32_t *in, int32_t *out, int64_t n, h
     MLM_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, in, out, (int)n, st));
     void *tmp = cub_tmp(ws, tb);
     MLM_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, in, out, (int)n, st));
-    int32_t *h = static_cast<int32_t *>(pinned(lens, 2 * sizeof(int32_t)));
-    MLM_HIP(hipMemcpyAsync(h, out + n - 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    MLM_HIP(hipMemcpyAsync(h + 1, in + n - 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    MLM_HIP(hipStreamSynchronize(st));
-    return (int64_t)h[0] + h[1];
+    return read_total<int32_t>(lens, in, out, n, st);
 }
 
 }  // namespace
@@ -276,10 +291,7 @@ int64_t scan_i32_to_i64(mlm_lens *lens, const int32_t *in, int64_t *out, int64_t
     void *tmp = cub_tmp(ws, tb);
     hipLaunchKernelGGL(k_zero_first, dim3(1), dim3(1), 0, st, out);
     MLM_HIP(hipcub::DeviceScan::InclusiveSum(tmp, tb, in, out + 1, (int)n, st));
-    int64_t *h = static_cast<int64_t *>(pinned(lens, sizeof(int64_t)));
-    MLM_HIP(hipMemcpyAsync(h, out + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    MLM_HIP(hipStreamSynchronize(st));
-    return h[0];
+    return read_total<int64_t>(lens, nullptr, out + 1, n, st);
 }
 
 // exclusive prefix sum of n int32 counts into n + 1 uint64 offsets; returns the total
@@ -297,11 +309,7 @@ int64_t scan_total_i64(mlm_lens *lens, const int64_t *in, int64_t *out, int64_t 
     MLM_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, in, out, (int)n, st));
     void *tmp = cub_tmp(ws, tb);
     MLM_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, in, out, (int)n, st));
-    int64_t *h = static_cast<int64_t *>(pinned(lens, 2 * sizeof(int64_t)));
-    MLM_HIP(hipMemcpyAsync(h, out + n - 1, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    MLM_HIP(hipMemcpyAsync(h + 1, in + n - 1, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    MLM_HIP(hipStreamSynchronize(st));
-    return h[0] + h[1];
+    return read_total<int64_t>(lens, in, out, n, st);
 }
 
 void build_tree(mlm_lens *lens, const Region &R, const mlm_map_request &req, Tree &T, hipStream_t st)
