@@ -295,7 +295,10 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
  * among 8, 16, 32 and 64 by timing tree + FMM + shooting of a sample of the
  * map's rows for each, and the choice is cached per class of map (precision,
  * expansion order and rays per star in powers of two) for the process.
- * Errors: as mlm_map; MLM_EINVAL also for an empty or inconsistent batch.
+ * Errors: as mlm_map; MLM_EINVAL also for an empty or inconsistent batch;
+ * MLM_ENOTSUP for a map the fused row bands cannot hold: more than 8192
+ * pixels per row, or more bands (of 1 to 16 pixel rows) than a workgroup's
+ * LDS can index (about 13 600 on MI355X).  mlm_map takes such maps.
  */
 typedef struct mlm_batch_opts {
     int64_t vertex_budget;   /* vertices held at once, 0: 2^28 (at least the largest map) */
