@@ -84,6 +84,32 @@ def test_batch_equals_single_maps(mlm, orc):
     assert rel.max() < 1e-9
 
 
+def test_batch_tall_map_many_bands(mlm):
+    """A 5000 x 6000 px map (6000 one-row bands, more than 64 KiB of LDS can
+    bin) batched with two small maps: the fused binning passes run with the
+    larger LDS the device gives a workgroup, and every map equals its single
+    call (the tall map's single call is pinned to the oracle in the parity
+    tests)."""
+    lenses, reqs = _small_batch(mlm, n_maps=2)
+    sf = W.config("plain_small").stars()
+    tall = mlm.Lens(0.3, 0.0, 0.3, sf.x, sf.y, sf.m)
+    pix = 0.001
+    treq = dict(hw1=0.5 * 5000 * pix, hw2=0.5 * 6000 * pix, n1=5000, n2=6000, nray1=100, nray2=120, order=16)
+    ls = [lenses[0][0], tall, lenses[1][0]]
+    rs = [reqs[0], treq, reqs[1]]
+    outs = [np.empty((r["n2"], r["n1"])) for r in rs]
+    stats, b = mlm.map_batch(ls, rs, outs)
+    assert b["n_maps"] == 3 and b["n_big"] > 0
+    worst = 0.0
+    for lens, r, mu in zip(ls, rs, outs):
+        ref, _ = _single(lens, r)
+        pos = ref > 0
+        assert np.all(np.abs(mu[~pos]) < 1e-12)
+        worst = max(worst, float((np.abs(mu[pos] - ref[pos]) / ref[pos]).max()))
+    _report("batch_tall_map_vs_single", max_rel=worst, bands=6000)
+    assert worst < 1e-11
+
+
 def test_batch_chunks_and_device_outputs(mlm):
     import torch
     lenses, reqs = _small_batch(mlm)
