@@ -1101,12 +1101,21 @@ __device__ inline void band_rows(int64_t band, int64_t r0, int64_t r1, const int
             };
             double Jc = is > x0 ? cross(is) : 0.0, prev = 0.0;
             const int iend = min(x1 - 1, cmax);
-            for (int i = is; i <= iend; ++i) {
-                const double Jn = cross(i + 1);
-                const double cur = Jn - Jc;
-                atomicAdd(drow + i, cur - prev);
-                prev = cur;
-                Jc = Jn;
+            if (is <= iend) {
+                // differences of the crossing form: cur(i) = J(i + 1) - J(i);
+                // past the first two columns consecutive ones differ by the
+                // constant 2 kc, which is all those columns receive
+                const double J1 = cross(is + 1);
+                prev = J1 - Jc;
+                atomicAdd(drow + is, prev);
+                if (is + 1 <= iend) {
+                    const double J2 = cross(is + 2);
+                    atomicAdd(drow + is + 1, (J2 - J1) - prev);
+                    const double d2 = 2.0 * kc;
+                    for (int i = is + 2; i <= iend; ++i) atomicAdd(drow + i, d2);
+                    prev = iend == is + 1 ? J2 - J1 : cross(iend + 1) - cross(iend);
+                }
+                Jc = cross(iend + 1);
             }
             if (x1 <= cmax) {
                 const double Jn = f * (0.5 * (((double)(x1 + 1) - ua) + ((double)(x1 + 1) - ub)));
