@@ -34,8 +34,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6          # MI355X FP64 vector, dense
 # FETCH_SIZE x 2.0, WRITE_SIZE x 1.0.  Valid only for the IPM source they were
 # taken with, identified by its SHA-256 prefix.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
-IPM_TRAFFIC = {"ipm_sha256": "79215a1bbdbee7ce",                     # (fetch KiB, write KiB)
-               "k_ipm": (719914.0625, 4175274.65625), "k_band": (1579512.0625, 31250.0)}
+IPM_TRAFFIC = {"ipm_sha256": "a8e4288d3ca909d0",                     # (fetch KiB, write KiB)
+               "k_ipm": (719914.5, 4175274.65625), "k_band": (1486720.8125, 31250.0)}
 
 
 def file_sha(path: str) -> str:

@@ -1102,18 +1102,19 @@ __device__ inline void band_rows(int64_t band, int64_t r0, int64_t r1, const int
             double Jc = is > x0 ? cross(is) : 0.0, prev = 0.0;
             const int iend = min(x1 - 1, cmax);
             if (is <= iend) {
-                // differences of the crossing form: cur(i) = J(i + 1) - J(i);
-                // past the first two columns consecutive ones differ by the
-                // constant 2 kc, which is all those columns receive
+                // differences of the crossing form, cur(i) = J(i + 1) - J(i),
+                // are kc (2 (i - umin) + 1) past the edge's first column, so
+                // consecutive ones differ by the constant 2 kc: all the
+                // columns past the first two receive
                 const double J1 = cross(is + 1);
                 prev = J1 - Jc;
                 atomicAdd(drow + is, prev);
                 if (is + 1 <= iend) {
-                    const double J2 = cross(is + 2);
-                    atomicAdd(drow + is + 1, (J2 - J1) - prev);
                     const double d2 = 2.0 * kc;
+                    const double c1 = kc * (2.0 * ((double)(is + 1) - umin) + 1.0);
+                    atomicAdd(drow + is + 1, c1 - prev);
                     for (int i = is + 2; i <= iend; ++i) atomicAdd(drow + i, d2);
-                    prev = iend == is + 1 ? J2 - J1 : cross(iend + 1) - cross(iend);
+                    prev = kc * (2.0 * ((double)iend - umin) + 1.0);
                 }
                 Jc = cross(iend + 1);
             }
