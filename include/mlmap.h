@@ -145,14 +145,17 @@ enum { MLM_METHOD_FMM = 0, MLM_METHOD_DIRECT = 1 };
  *                  squares before it is divided (app. C.1), default 32
  *   max_level      deepest tree level, default and maximum 24
  *   precision      MLM_PREC_FP64 (everything in double) or MLM_PREC_MIXED:
- *                  multipole and Taylor coefficients (app. C.2), near field,
- *                  Taylor evaluation and the column pass of the IPM in FP32;
- *                  grid positions, leaf centres and offsets from them, the
- *                  macro model, the sheet, triangle set-up, thin triangles
- *                  (squared extent above 256 x twice the area, the ones
- *                  folded across caustics), the row-band pass and every
- *                  pixel sum in FP64 (the paper's single-precision mode,
- *                  sec. 5, with FP64 kept where caustics need it).  With
+ *                  the near field, the Taylor series' variation across a
+ *                  leaf (its terms l >= 1 in the leaf's local coordinate)
+ *                  and the column pass of the IPM in FP32; the multipole
+ *                  and Taylor coefficients (app. C.2), the far field at
+ *                  each leaf centre, grid positions, leaf centres and
+ *                  offsets from them, the macro model, the sheet, triangle
+ *                  set-up, thin triangles (squared extent above 256 x
+ *                  twice the area, the ones folded across caustics), the
+ *                  row-band pass and every pixel sum in FP64 (the paper's
+ *                  single-precision mode, sec. 5, with FP64 kept where the
+ *                  field's magnitude or caustics need it).  With
  *                  MLM_METHOD_DIRECT it gives MLM_ENOTSUP.
  *   method         MLM_METHOD_FMM or MLM_METHOD_DIRECT (every star summed
  *                  for every ray; the no-FMM reference of sec. 4)

@@ -20,6 +20,10 @@ namespace mlm {
 
 namespace {
 thread_local std::string g_last_error;
+// Device and pinned-host allocations and frees of the library's growing
+// buffers are made one at a time, process-wide: a batch prepares its maps on
+// several host threads at once.
+std::mutex g_alloc_mu;
 }
 
 void fail(mlm_status st, const char *fmt, ...)
@@ -35,6 +39,7 @@ void fail(mlm_status st, const char *fmt, ...)
 void *DevBuf::reserve(size_t bytes)
 {
     if (p && bytes <= cap) return p;
+    std::lock_guard<std::mutex> g(g_alloc_mu);
     if (p) {
         MLM_HIP(hipDeviceSynchronize());   // the old buffer may still be in use by queued work
         MLM_HIP(hipFree(p));
@@ -48,22 +53,48 @@ void *DevBuf::reserve(size_t bytes)
     return p;
 }
 
+void *DevBuf::grow_keep(size_t keep, size_t bytes, hipStream_t st)
+{
+    if (bytes <= cap) return p;
+    size_t c = cap ? cap : 4096;
+    while (c < bytes) c *= 2;
+    void *q = nullptr;
+    {
+        std::lock_guard<std::mutex> g(g_alloc_mu);
+        MLM_HIP(hipMalloc(&q, c));
+    }
+    if (p && keep) MLM_HIP(hipMemcpyAsync(q, p, keep, hipMemcpyDeviceToDevice, st));
+    MLM_HIP(hipStreamSynchronize(st));
+    if (p) {
+        std::lock_guard<std::mutex> g(g_alloc_mu);
+        MLM_HIP(hipFree(p));
+    }
+    p = q;
+    cap = c;
+    return p;
+}
+
 void DevBuf::release()
 {
-    if (p) (void)hipFree(p);
+    if (!p) return;
+    std::lock_guard<std::mutex> g(g_alloc_mu);
+    (void)hipFree(p);
     p = nullptr;
     cap = 0;
 }
 
 Workspace::~Workspace()
 {
-    if (pinned) (void)hipHostFree(pinned);
+    if (!pinned) return;
+    std::lock_guard<std::mutex> g(g_alloc_mu);
+    (void)hipHostFree(pinned);
 }
 
 void *pinned(mlm_lens *lens, size_t bytes)
 {
     Workspace &ws = lens->ws;
     if (ws.pinned && bytes <= ws.pinned_cap) return ws.pinned;
+    std::lock_guard<std::mutex> g(g_alloc_mu);
     if (ws.pinned) {
         MLM_HIP(hipDeviceSynchronize());
         MLM_HIP(hipHostFree(ws.pinned));
@@ -257,7 +288,8 @@ int order_for(const mlm_map_request &q, const Region &R, const Tree &T)
 
 // Leaf-size autotuner: for a map, the split threshold that minimises the
 // estimated time of tree + FMM + shooting, from timed trials on the map's
-// own stars and a sample of its grid rows; cached per class of map.
+// own stars and a sample of its grid rows; cached per class of map.  The
+// batch call tunes every class before its preparing threads start.
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int>, int> g_tune_cache;
 
@@ -516,12 +548,14 @@ mlm_status mlm_map_region(const mlm_lens *lens, const mlm_map_request *req, mlm_
     API_END
 }
 
-mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_stats *stats)
+}  // extern "C"
+
+namespace mlm {
+namespace {
+
+// one map (the body of mlm_map); the lens is locked
+void map_impl(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_stats *stats)
 {
-    API_BEGIN
-    if (!lens || !mu) fail(MLM_EINVAL, "lens and mu must not be NULL");
-    check_request(req);
-    std::lock_guard<std::mutex> guard(lens->mu);
     const mlm_map_request &q = *req;
     Region R{};
     setup_region(lens, req, &R);
@@ -544,9 +578,14 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
     constexpr int NCNT = 8 + 3 * WORK_SLOTS;
     unsigned long long *cnt = static_cast<unsigned long long *>(ws.counters.reserve(NCNT * sizeof(unsigned long long)));
     hipLaunchKernelGGL(k_zero_u64n, dim3((NCNT + 255) / 256), dim3(256), 0, st, cnt, (int64_t)NCNT);
-    int64_t ndiff = (int64_t)q.n2 * (q.n1 + 1);
-    double *diff = static_cast<double *>(ws.diff.reserve(ndiff * sizeof(double)));
-    fill(diff, ndiff, 0.0, st);
+    // column differences of the per-triangle row kernel, for maps too wide
+    // for row bands
+    double *diff = nullptr;
+    if (band_height(q.n1, q.n2) <= 0) {
+        const int64_t ndiff = (int64_t)q.n2 * (q.n1 + 1);
+        diff = static_cast<double *>(ws.diff.reserve(ndiff * sizeof(double)));
+        fill(diff, ndiff, 0.0, st);
+    }
 
     Tree T;
     const bool fmm = q.method == MLM_METHOD_FMM;
@@ -696,7 +735,7 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
         tiles += nt;
         r0 = r1;
     }
-    launch_diff_rows(g, diff, map, st);
+    if (diff) launch_diff_rows(g, diff, map, st);
     if (!q.device_out) MLM_HIP(hipMemcpyAsync(mu, map, npix * sizeof(double), hipMemcpyDeviceToHost, st));
     unsigned long long *hc = static_cast<unsigned long long *>(pinned(lens, NCNT * sizeof(unsigned long long)));
     MLM_HIP(hipMemcpyAsync(hc, cnt, NCNT * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
@@ -743,6 +782,20 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
         S.t_refine_ms = t_refine;
         *stats = S;
     }
+}
+
+}  // namespace
+}  // namespace mlm
+
+extern "C" {
+
+mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_stats *stats)
+{
+    API_BEGIN
+    if (!lens || !mu) fail(MLM_EINVAL, "lens and mu must not be NULL");
+    check_request(req);
+    std::lock_guard<std::mutex> guard(lens->mu);
+    map_impl(lens, req, mu, stats);
     API_END
 }
 
@@ -780,6 +833,17 @@ mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, i
         static_cast<unsigned long long *>(B.counters.reserve((size_t)nmaps * 8 * sizeof(unsigned long long)));
     hipLaunchKernelGGL(k_zero_u64n, dim3((unsigned)((nmaps * 8 + 255) / 256)), dim3(256), 0, st, cnt,
                        (int64_t)nmaps * 8);
+    // Leaf sizes are tuned first, one class of map at a time on the caller's
+    // stream while nothing else runs, so the trials are timed on an idle
+    // device and each class is tuned once; the preparing threads then find
+    // every class in the cache.
+    if (o.autotune)
+        for (int32_t i = 0; i < nmaps; ++i) {
+            mlm_map_request qi = reqs[i];
+            Region Ri{};
+            setup_region(lenses[i], &qi, &Ri);
+            (void)tune_leaf_max(lenses[i], qi, Ri, st);
+        }
     // A tree is built level by level with a host read of each level's size,
     // so one stream would idle between levels: PREP_THREADS host threads
     // take the maps in turn, each on a stream of its own that first waits for
@@ -1350,21 +1414,8 @@ mlm_status mlm_fmm_export(mlm_lens *lens, const mlm_map_request *req, mlm_tree_i
         if (nstars) nstars[k] = hi[k] - lo[k];
         if (block) block[k] = bk[k];
     }
-    if (T.mixed) {   // FP32 coefficients, widened
-        std::vector<float2> h((size_t)(N * P1));
-        for (int which = 0; which < 2; ++which) {
-            double *dst = which ? local : mult;
-            if (!dst) continue;
-            MLM_HIP(hipMemcpy(h.data(), which ? T.local_f : T.mult_f, h.size() * sizeof(float2), hipMemcpyDeviceToHost));
-            for (size_t k = 0; k < h.size(); ++k) {
-                dst[2 * k] = h[k].x;
-                dst[2 * k + 1] = h[k].y;
-            }
-        }
-    } else {
-        if (mult) MLM_HIP(hipMemcpy(mult, T.mult, N * P1 * sizeof(double2), hipMemcpyDeviceToHost));
-        if (local) MLM_HIP(hipMemcpy(local, T.local, N * P1 * sizeof(double2), hipMemcpyDeviceToHost));
-    }
+    if (mult) MLM_HIP(hipMemcpy(mult, T.mult, N * P1 * sizeof(double2), hipMemcpyDeviceToHost));
+    if (local) MLM_HIP(hipMemcpy(local, T.local, N * P1 * sizeof(double2), hipMemcpyDeviceToHost));
     API_END
 }
 

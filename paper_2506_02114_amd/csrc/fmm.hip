@@ -166,21 +166,15 @@ __global__ void k_upward(int64_t lo, int64_t hi, int lev, int p, double L0, cons
 }
 
 // Matrix-core product of the factorised M2L: Y (32 x 64) = P (32 x 32) B
-// (32 x 64), as 16 x 16 x 4 tiles; lane l holds A(l % 16, l / 16) and
-// B(l / 16, l % 16); its four results are D(4 (l / 16) + i, l % 16) for the
-// FP32 instruction and D(4 i + l / 16, l % 16) for the FP64 one (i < 4).
+// (32 x 64), as 16 x 16 x 4 FP64 tiles; lane l holds A(l % 16, l / 16) and
+// B(l / 16, l % 16); its four results are D(4 i + l / 16, l % 16), i < 4.
+// (The coefficient passes run in FP64 in both precision modes.)
 typedef double f64x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 __device__ inline f64x4 mma16(double a, double b, f64x4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-__device__ inline f32x4 mma16(float a, float b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 template <class R> struct V4T;
 template <> struct V4T<double> {
     using t = f64x4;
     __device__ static int row(int i, int g4) { return 4 * i + g4; }
-};
-template <> struct V4T<float> {
-    using t = f32x4;
-    __device__ static int row(int i, int g4) { return 4 * g4 + i; }
 };
 
 // row stride of the LDS matrix: one element more than its 64 columns, so the
@@ -349,16 +343,17 @@ __global__ void k_zero2(C2 *a, int64_t n)
     if (t < n) a[t] = C2{0, 0};
 }
 
-// per-leaf data for the ray kernels: geometry, derivative of the Taylor
-// series (in R) and the stars of the leaf's 3x3 block relative to its centre
-// (FP64 in both modes: a ray's offset from a star is formed from them)
+// per-leaf data for the ray kernels: geometry, the far field at the centre
+// (FP64), derivative of the Taylor series (rounded to R) and the stars of the
+// leaf's 3x3 block relative to its centre (FP64 in both modes: a ray's offset
+// from a star is formed from them)
 template <class R>
 __global__ void k_leaf_tables(int64_t nleaves, int p, double L0, const int32_t *__restrict__ leaf_node,
                               const uint64_t *__restrict__ code, const int32_t *__restrict__ level,
                               const int32_t *__restrict__ block, const int32_t *__restrict__ near_offs,
                               const uint64_t *__restrict__ keys, int32_t n, const double *__restrict__ sx,
                               const double *__restrict__ sy, const double *__restrict__ sm,
-                              const typename Cx<R>::c2 *__restrict__ local, LeafInfo *__restrict__ info,
+                              const double2 *__restrict__ local, LeafInfo *__restrict__ info,
                               typename Cx<R>::c2 *__restrict__ deriv, double4 *__restrict__ near)
 {
     int64_t lf = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -376,10 +371,17 @@ __global__ void k_leaf_tables(int64_t nleaves, int p, double L0, const int32_t *
     li.near_off = near_offs[lf];
     li.near_cnt = block[q];
     li.a_lo = li.na = li.b_lo = li.nb = li.ntx = li.pad = 0;
-    info[lf] = li;
     const int P1 = p + 1;
-    // d psi / dz = (1/L) sum_{l>=1} l c_l zeta^(l-1)
-    for (int l = 0; l < p; ++l) deriv[lf * p + l] = cscale(local[(int64_t)q * P1 + l + 1], (R)((double)(l + 1) * invL));
+    // d psi / dz = (1/L) sum_{l>=1} l c_l zeta^(l-1); its value at the centre
+    // (l = 1) is the whole field of the far stars, kept in FP64
+    const double2 d0 = cscale(local[(int64_t)q * P1 + 1], invL);
+    li.f0x = d0.x;
+    li.f0y = d0.y;
+    info[lf] = li;
+    for (int l = 0; l < p; ++l) {
+        const double2 d = cscale(local[(int64_t)q * P1 + l + 1], (double)(l + 1) * invL);
+        deriv[lf * p + l] = Cx<R>::make((R)d.x, (R)d.y);
+    }
     uint32_t i = compact_bits(c), j = compact_bits(c >> 1);
     int64_t side = 1ll << lev;
     int sh = 2 * (KEY_BITS - lev);
@@ -422,7 +424,7 @@ void run_fmm_t(mlm_lens *lens, Tree &T, int p, hipStream_t st, typename Cx<R>::c
     using C2 = typename Cx<R>::c2;
     Workspace &ws = lens->ws;
     const int P1 = p + 1;
-    const int key = 2 * p + (sizeof(R) == 4 ? 1 : 0);
+    const int key = p;
     if (ws.ops_p != key) {
         std::vector<double2> h, S, T;
         std::vector<double> Pm;
@@ -470,8 +472,10 @@ void run_fmm(mlm_lens *lens, Tree &T, int p, hipStream_t st)
 {
     if (p < 1 || p > MAX_ORDER) fail(MLM_EINVAL, "expansion order %d outside [1, %d]", p, MAX_ORDER);
     T.p = p;
-    if (T.mixed) run_fmm_t<float>(lens, T, p, st, T.mult_f, T.local_f);
-    else run_fmm_t<double>(lens, T, p, st, T.mult, T.local);
+    // FP64 in both modes: the low-order Taylor coefficients carry the field of
+    // the whole star disc (about kappa_* |z|), far above what FP32 translation
+    // chains could hold to a fraction of a pixel
+    run_fmm_t<double>(lens, T, p, st, T.mult, T.local);
 }
 
 void build_leaf_tables(mlm_lens *lens, Tree &T, hipStream_t st)
@@ -488,7 +492,7 @@ void build_leaf_tables(mlm_lens *lens, Tree &T, hipStream_t st)
     if (T.mixed) {
         T.deriv_f = static_cast<float2 *>(ws.deriv.reserve((size_t)nl * T.p * sizeof(float2)));
         hipLaunchKernelGGL(k_leaf_tables<float>, dim3(nblocks(nl, 64)), dim3(64), 0, st, nl, T.p, T.L0, T.leaf_node,
-                           T.code, T.level, T.block, offs, T.keys, (int32_t)T.n, T.x, T.y, T.m, T.local_f,
+                           T.code, T.level, T.block, offs, T.keys, (int32_t)T.n, T.x, T.y, T.m, T.local,
                            T.leaves, T.deriv_f, T.near);
     } else {
         T.deriv = static_cast<double2 *>(ws.deriv.reserve((size_t)nl * T.p * sizeof(double2)));

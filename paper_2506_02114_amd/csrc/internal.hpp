@@ -37,6 +37,8 @@ struct DevBuf {
     void *p = nullptr;
     size_t cap = 0;
     void *reserve(size_t bytes);  // contents are not preserved when it grows
+    // grows keeping the first `keep` bytes (copied on `st`)
+    void *grow_keep(size_t keep, size_t bytes, hipStream_t st);
     void release();
     ~DevBuf() { release(); }
     template <class T> T *as() const { return static_cast<T *>(p); }
@@ -67,6 +69,7 @@ struct LeafInfo {
     int32_t a_lo, na;     // grid columns [a_lo, a_lo + na) inside the leaf
     int32_t b_lo, nb;     // grid rows [b_lo, b_lo + nb) inside the leaf
     int32_t ntx, pad;     // tiles per tile-row
+    double f0x, f0y;      // far field at the centre, d_0 = c_1 / L (FP64 in both modes)
 };
 
 // shooting region and ray grid
@@ -169,14 +172,14 @@ struct Tree {
     int32_t *parent = nullptr, *child0 = nullptr, *node_leaf = nullptr;
     int32_t *leaf_node = nullptr;
     IEntry *ilist = nullptr;
-    bool mixed = false;                  // FP32 coefficients and leaf tables (the *_f arrays)
-    double2 *mult = nullptr, *local = nullptr;
-    float2 *mult_f = nullptr, *local_f = nullptr;
+    bool mixed = false;                  // FP32 Taylor evaluation (deriv_f) and near field
+    double2 *mult = nullptr, *local = nullptr;   // FP64 in both modes
     // leaf tables
     LeafInfo *leaves = nullptr;
     double4 *near = nullptr;             // (dx, dy, m, 0) relative to the leaf centre (both modes)
     double2 *deriv = nullptr;            // [nleaves][p]: (l+1) c_{l+1} / L
-    float2 *deriv_f = nullptr;           // the same in FP32 (mixed mode)
+    float2 *deriv_f = nullptr;           // the same rounded to FP32 (mixed mode; entry 0 unused:
+                                         // the leaf's f0x, f0y carry it in FP64)
 };
 
 struct Workspace {
@@ -188,7 +191,7 @@ struct Workspace {
         bandcur, bandlist, rfeat, rlogit, rflag, rpos, rcand, rlabel, rstats;
     void *pinned = nullptr;               // small pinned host buffer for read-backs
     size_t pinned_cap = 0;
-    int ops_p = -1;                       // 2 x order (+1 for FP32) of the operator tables
+    int ops_p = -1;                       // expansion order of the operator tables
     ~Workspace();
 };
 

@@ -227,12 +227,15 @@ int64_t plan_tiles(mlm_lens *lens, Tree &T, const Region &R, int64_t vb0, int64_
 {
     Workspace &ws = lens->ws;
     int64_t nl = T.nleaves;
+    // every vertex lies in exactly one leaf and every tile holds at least one
+    // vertex, so the tiles number at most the vertices: bounding those keeps
+    // the int32 counts and their scan from overflowing
+    if ((vb1 - vb0) * R.nr1 > (int64_t)INT32_MAX) fail(MLM_ERANGE, "more than 2^31 vertices in one shooting plan");
     int32_t *cnt = static_cast<int32_t *>(ws.flags.reserve(nl * 4));
     int32_t *off = static_cast<int32_t *>(ws.tile_off.reserve(nl * 4));
     hipLaunchKernelGGL(k_tile_counts, dim3(nblocks(nl)), dim3(BLK), 0, st, nl, T.leaf_node, T.code, T.level, T.L0,
                        T.L0_exp, R.x0, R.d1, R.nr1, R.y0, R.d2, vb0, vb1, T.leaves, cnt);
     int64_t ntiles = scan_total_public(lens, cnt, off, nl, st);
-    if (ntiles > (int64_t)INT32_MAX) fail(MLM_ERANGE, "too many ray tiles in one strip");
     if (ntiles > 0) {
         int32_t *tl = static_cast<int32_t *>(ws.tile_leaf.reserve(ntiles * 4));
         hipLaunchKernelGGL(k_tile_leaf, dim3(nblocks(ntiles)), dim3(BLK), 0, st, ntiles, nl, off, tl);

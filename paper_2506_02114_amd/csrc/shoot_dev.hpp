@@ -41,7 +41,11 @@ __device__ inline void finish_vertex(const LensConst &lc, const MapGeom &g, doub
 
 // far-field and near-field deflection at offset (dx, dy) from a leaf's
 // centre, in arithmetic type R; the offsets from the leaf centre and from
-// each near star are formed in FP64 (a ray may pass very close to a star)
+// each near star are formed in FP64 (a ray may pass very close to a star).
+// In FP32 the Taylor series is split: its value at the centre (the field of
+// every far star, as large as kappa_* |z|) is the leaf's FP64 f0, and FP32
+// carries only the variation across the leaf, zeta sum_{l>=1} d_l zeta^(l-1),
+// which is of the size of the field's derivative times the leaf's half-length
 template <class R>
 __device__ inline void leaf_alpha(double dx, double dy, const LeafInfo &li, const double4 *__restrict__ ns,
                                   const typename Cx<R>::c2 *__restrict__ dv, int p, double &ax_out, double &ay_out)
@@ -57,16 +61,34 @@ __device__ inline void leaf_alpha(double dx, double dy, const LeafInfo &li, cons
     }
     // far field: conj( sum_{l<p} deriv_l zeta^l ), Horner
     const R zr = (R)(dx * li.invL), zi = (R)(dy * li.invL);
-    R sr = dv[p - 1].x, si = dv[p - 1].y;
-    for (int l = p - 2; l >= 0; --l) {
-        const typename Cx<R>::c2 c = dv[l];
-        const R nr = sr * zr - si * zi + c.x;
-        const R ni = sr * zi + si * zr + c.y;
-        sr = nr;
-        si = ni;
+    if constexpr (sizeof(R) == sizeof(double)) {
+        R sr = dv[p - 1].x, si = dv[p - 1].y;
+        for (int l = p - 2; l >= 0; --l) {
+            const typename Cx<R>::c2 c = dv[l];
+            const R nr = sr * zr - si * zi + c.x;
+            const R ni = sr * zi + si * zr + c.y;
+            sr = nr;
+            si = ni;
+        }
+        ax_out = (double)ax + (double)sr;
+        ay_out = (double)ay - (double)si;
+    } else {
+        R vr = 0, vi = 0;   // zeta sum_{l>=1} d_l zeta^(l-1)
+        if (p >= 2) {
+            R sr = dv[p - 1].x, si = dv[p - 1].y;
+            for (int l = p - 2; l >= 1; --l) {
+                const typename Cx<R>::c2 c = dv[l];
+                const R nr = sr * zr - si * zi + c.x;
+                const R ni = sr * zi + si * zr + c.y;
+                sr = nr;
+                si = ni;
+            }
+            vr = sr * zr - si * zi;
+            vi = sr * zi + si * zr;
+        }
+        ax_out = (double)ax + (li.f0x + (double)vr);
+        ay_out = (double)ay - (li.f0y + (double)vi);
     }
-    ax_out = (double)ax + (double)sr;
-    ay_out = (double)ay - (double)si;
 }
 
 struct LevelRanges {

@@ -226,18 +226,7 @@ __global__ void k_ilist(int64_t lo, int64_t hi, const uint64_t *__restrict__ cod
 template <class T>
 T *grow_keep(DevBuf &b, size_t used_elems, size_t need_elems, hipStream_t st)
 {
-    size_t need = need_elems * sizeof(T);
-    if (need <= b.cap) return b.as<T>();
-    size_t cap = b.cap ? b.cap : 4096;
-    while (cap < need) cap *= 2;
-    void *p = nullptr;
-    MLM_HIP(hipMalloc(&p, cap));
-    if (b.p && used_elems) MLM_HIP(hipMemcpyAsync(p, b.p, used_elems * sizeof(T), hipMemcpyDeviceToDevice, st));
-    MLM_HIP(hipStreamSynchronize(st));
-    if (b.p) MLM_HIP(hipFree(b.p));
-    b.p = p;
-    b.cap = cap;
-    return static_cast<T *>(p);
+    return static_cast<T *>(b.grow_keep(used_elems * sizeof(T), need_elems * sizeof(T), st));
 }
 
 void *cub_tmp(Workspace &ws, size_t bytes) { return ws.cub_tmp.reserve(bytes ? bytes : 1); }

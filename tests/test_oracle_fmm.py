@@ -77,14 +77,6 @@ def _multipole(zs, ms, centre, L, p):
     return a
 
 
-def _multipole_grad(a, centre, L, z):
-    zeta = (z - centre) / L
-    g = a[0] / zeta
-    for k in range(1, len(a)):
-        g = g - k * a[k] * zeta ** (-k - 1)
-    return g / L
-
-
 def _local_grad(c, centre, L, z):
     zeta = (z - centre) / L
     d = np.zeros_like(zeta)
@@ -97,20 +89,68 @@ def _rand_square(rng, n, centre, L):
     return centre + L * (rng.uniform(-1, 1, n) + 1j * rng.uniform(-1, 1, n))
 
 
+def _square_members(x, y, L0, level, i, j, halo=0):
+    """Stars in the square (level, i, j) of the root [-L0, L0)^2, or in its
+    (2 halo + 1)^2 block of same-level squares."""
+    ci, cj = _cell(x, L0, level), _cell(y, L0, level)
+    return (np.abs(ci - i) <= halo) & (np.abs(cj - j) <= halo)
+
+
 def test_p2m_converges_to_direct_sum(orc):
-    rng = np.random.default_rng(3)
-    zs = _rand_square(rng, 20, 0.3 + 0.1j, 0.5)
-    ms = rng.uniform(0.1, 1.0, 20)
-    z = 0.3 + 0.1j + 0.5 * 4.0 * np.exp(1j * np.linspace(0, 2 * np.pi, 50, endpoint=False))
-    exact = (ms[None, :] / (z[:, None] - zs[None, :])).sum(1)
+    """The oracle's multipole expansion of a leaf (P2M, appendix C.2),
+    evaluated far outside the leaf, converges to the direct sum over the
+    leaf's own stars, with error shrinking like (sqrt2 / dist)^p."""
+    sf = W.star_field(400, 0.3, "salpeter", seed=31)
+    lens = orc.Lens(0.3, 0.0, 0.3, sf.x, sf.y, sf.m)
+    L0 = 2.0 ** math.ceil(math.log2(np.abs(np.r_[sf.x, sf.y]).max() * 1.0001))
     errs = []
     for p in (5, 10, 20, 30):
-        a = _multipole(zs, ms, 0.3 + 0.1j, 0.5, p)
-        errs.append(np.abs(_multipole_grad(a, 0.3 + 0.1j, 0.5, z) - exact).max())
-    # truncation error decays at least like (sqrt2/4)^p
+        F = orc.FMM(lens, L0, p, nmax=8)
+        nd = F.nodes()
+        cand = np.flatnonzero((nd["leaf"] == 1) & (nd["nstars"] >= 3) & (nd["level"] >= 2))
+        q = int(cand[0])
+        lev, i, j = int(nd["level"][q]), int(nd["i"][q]), int(nd["j"][q])
+        L = L0 / 2 ** lev
+        cen = complex(-L0 + (2 * i + 1) * L, -L0 + (2 * j + 1) * L)
+        inside = _square_members(sf.x, sf.y, L0, lev, i, j)
+        assert inside.sum() == nd["nstars"][q]
+        zs = sf.x[inside] + 1j * sf.y[inside]
+        z = cen + 4.0 * L * np.exp(1j * np.linspace(0, 2 * np.pi, 50, endpoint=False))
+        exact = (sf.m[inside][None, :] / (z[:, None] - zs[None, :])).sum(1)
+        got = F.eval_multipole(q, z.real, z.imag)
+        errs.append(np.abs(got - exact).max() / sf.m[inside].sum() * L)
     for e, p in zip(errs, (5, 10, 20, 30)):
-        assert e < 50 * (math.sqrt(2) / 4) ** p * ms.sum()
+        assert e < 4 * (math.sqrt(2) / 4) ** p
     assert errs[-1] < 1e-12
+
+
+def test_local_expansion_is_far_field(orc):
+    """A leaf's Taylor series (appendix C.2, from M2L, P2L and L2L) evaluated
+    inside the leaf converges to the direct sum over every star outside the
+    leaf's 3x3 block of same-level squares (the far stars)."""
+    sf = W.star_field(3000, 0.3, "salpeter", seed=32)
+    lens = orc.Lens(0.3, 0.0, 0.3, sf.x, sf.y, sf.m)
+    L0 = 2.0 ** math.ceil(math.log2(np.abs(np.r_[sf.x, sf.y]).max() * 1.0001))
+    rng = np.random.default_rng(33)
+    prev = None
+    for p in (8, 16, 30):
+        F = orc.FMM(lens, L0, p)
+        nd = F.nodes()
+        leaves = np.flatnonzero((nd["leaf"] == 1) & (nd["level"] >= 3))
+        worst = 0.0
+        for q in leaves[:: max(1, leaves.size // 12)]:
+            lev, i, j = int(nd["level"][q]), int(nd["i"][q]), int(nd["j"][q])
+            L = L0 / 2 ** lev
+            cen = complex(-L0 + (2 * i + 1) * L, -L0 + (2 * j + 1) * L)
+            far = ~_square_members(sf.x, sf.y, L0, lev, i, j, halo=1)
+            z = cen + L * (rng.uniform(-1, 1, 20) + 1j * rng.uniform(-1, 1, 20))
+            exact = (sf.m[far][None, :] / (z[:, None] - (sf.x[far] + 1j * sf.y[far])[None, :])).sum(1)
+            got = F.eval_local(q, z.real, z.imag)
+            worst = max(worst, np.abs(got - exact).max() / max(np.abs(exact).max(), 1.0))
+        if prev is not None:
+            assert worst < prev / 10
+        prev = worst
+    assert prev < 1e-9
 
 
 @pytest.mark.parametrize("qi,qj", [(0, 0), (1, 0), (0, 1), (1, 1)])
