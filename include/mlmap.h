@@ -279,6 +279,30 @@ typedef struct mlm_map_stats {
 mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_stats *stats);
 
 /*
+ * mlm_map without device allocation, for callers that cannot allocate (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, result and errors as mlm_map; every buffer the
+ * map needs beyond the lens, `mu` and `w_out` (the tree, coefficients, leaf
+ * tables, vertex strips, IPM work lists, and `mu`'s device copy when it goes
+ * to the host) is carved from a static device array of
+ * MLM_NOALLOC_SCRATCH_MIB MiB that the library holds on each device it runs
+ * on until the process ends; no hipMalloc, hipFree or pinned host
+ * allocation is made (small host-side bookkeeping uses the C++ heap).
+ *   - Calls on one device share its array and are serialised by a lock of
+ *     the library's (a call returns after its work has completed); processes
+ *     each have their own array.
+ *   - The vertex strip is sized to what the array holds, so large grids run
+ *     in more strips than under mlm_map.
+ *   - MLM_ERANGE when the map cannot fit: at entry, if the sorted stars (48
+ *     bytes each), two vertex rows and the host-bound map copy already
+ *     exceed the array; later, if data-dependent lists (large triangles,
+ *     row bands) exhaust it.  mlm_map takes such maps.
+ *   - MLM_ENOTSUP for cell refinement.
+ */
+#define MLM_NOALLOC_SCRATCH_MIB 64
+mlm_status mlm_map_noalloc(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_stats *stats);
+
+/*
  * Batched maps: many lenses and requests in one call, each map as mlm_map
  * would make it, but with the ray shooting and the IPM of many maps fused
  * into persistent launches that walk the concatenated work of all maps (so

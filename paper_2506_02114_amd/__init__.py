@@ -30,7 +30,7 @@ EXPORTED = [
     "mlm_lens_get_info", "mlm_map_request_init", "mlm_map_region", "mlm_map", "mlm_deflect",
     "mlm_fmm_export", "mlm_refiner_create", "mlm_refiner_destroy", "mlm_refiner_get_params",
     "mlm_refiner_set_params", "mlm_refiner_predict", "mlm_refiner_grads", "mlm_train_opts_init",
-    "mlm_refiner_train", "mlm_cell_samples",
+    "mlm_refiner_train", "mlm_cell_samples", "mlm_map_noalloc",
 ]
 
 
@@ -139,6 +139,8 @@ def _lib():
     L.mlm_map_region.restype = C.c_int
     L.mlm_map.argtypes = [vp, C.POINTER(MapRequest), vp, C.POINTER(MapStats)]
     L.mlm_map.restype = C.c_int
+    L.mlm_map_noalloc.argtypes = [vp, C.POINTER(MapRequest), vp, C.POINTER(MapStats)]
+    L.mlm_map_noalloc.restype = C.c_int
     L.mlm_deflect.argtypes = [vp, C.POINTER(MapRequest), vp, i64, vp]
     L.mlm_deflect.restype = C.c_int
     L.mlm_fmm_export.argtypes = [vp, C.POINTER(MapRequest), C.POINTER(TreeInfo), vp, vp, vp, vp, vp, vp, vp, vp, i64]
@@ -251,9 +253,11 @@ class Lens:
         _check(_lib().mlm_map_region(self._h, C.byref(r), C.byref(R)))
         return _asdict(R)
 
-    def map(self, out=None, w_out=None, stream=None, **req):
+    def map(self, out=None, w_out=None, stream=None, noalloc: bool = False, **req):
         """Magnification map, (n2, n1) row-major.  `out` may be a float64 torch
-        tensor on the GPU (the map stays on the device) or None (host numpy)."""
+        tensor on the GPU (the map stays on the device) or None (host numpy).
+        noalloc: through mlm_map_noalloc (scratch from the library's static
+        device array, no device allocation)."""
         r = make_request(**req)
         device = out is not None and _is_torch_cuda(out)
         if out is None:
@@ -274,7 +278,8 @@ class Lens:
                 assert isinstance(w_out, np.ndarray) and w_out.dtype == np.float64 and w_out.flags.c_contiguous
                 r.w_out = w_out.ctypes.data_as(C.c_void_p)
         s = MapStats()
-        _check(_lib().mlm_map(self._h, C.byref(r), ptr, C.byref(s)))
+        fn = _lib().mlm_map_noalloc if noalloc else _lib().mlm_map
+        _check(fn(self._h, C.byref(r), ptr, C.byref(s)))
         return out, _asdict(s)
 
     def deflect(self, z, stream=None, **req):

@@ -36,8 +36,48 @@ void fail(mlm_status st, const char *fmt, ...)
     throw Error{st, buf};
 }
 
+Arena *&thread_arena()
+{
+    static thread_local Arena *a = nullptr;
+    return a;
+}
+
+void *Arena::take(size_t bytes)
+{
+    const size_t b = (bytes + 255) & ~(size_t)255;
+    if (b > cap - used)
+        fail(MLM_ERANGE, "the scratch array of %zu MiB is exhausted (%zu bytes more needed); mlm_map takes this map",
+             cap >> 20, b - (cap - used));
+    void *q = base + used;
+    used += b;
+    return q;
+}
+
+void *Arena::reserve(DevBuf &b, size_t bytes)
+{
+    if (owns(b.p) && bytes <= b.cap) return b.p;
+    if (!owns(b.p)) {
+        if (nsaved == MAX_BUFS) fail(MLM_ERANGE, "too many scratch buffers");
+        saved[nsaved++] = Saved{&b, b.p, b.cap};
+    }
+    b.p = take(bytes);
+    b.cap = (bytes + 255) & ~(size_t)255;
+    return b.p;
+}
+
+void Arena::restore()
+{
+    while (nsaved > 0) {
+        const Saved &s = saved[--nsaved];
+        s.buf->p = s.p;
+        s.buf->cap = s.cap;
+    }
+    used = 0;
+}
+
 void *DevBuf::reserve(size_t bytes)
 {
+    if (Arena *a = thread_arena()) return a->reserve(*this, bytes);
     if (p && bytes <= cap) return p;
     std::lock_guard<std::mutex> g(g_alloc_mu);
     if (p) {
@@ -55,10 +95,21 @@ void *DevBuf::reserve(size_t bytes)
 
 void *DevBuf::grow_keep(size_t keep, size_t bytes, hipStream_t st)
 {
-    if (bytes <= cap) return p;
+    if (bytes <= cap && (!thread_arena() || thread_arena()->owns(p))) return p;
     size_t c = cap ? cap : 4096;
     while (c < bytes) c *= 2;
     void *q = nullptr;
+    if (Arena *a = thread_arena()) {
+        q = a->take(c);
+        if (p && keep) MLM_HIP(hipMemcpyAsync(q, p, keep, hipMemcpyDeviceToDevice, st));
+        if (!a->owns(p)) {
+            if (a->nsaved == Arena::MAX_BUFS) fail(MLM_ERANGE, "too many scratch buffers");
+            a->saved[a->nsaved++] = Arena::Saved{this, p, cap};
+        }
+        p = q;
+        cap = c;
+        return p;
+    }
     {
         std::lock_guard<std::mutex> g(g_alloc_mu);
         MLM_HIP(hipMalloc(&q, c));
@@ -553,7 +604,7 @@ mlm_status mlm_map_region(const mlm_lens *lens, const mlm_map_request *req, mlm_
 namespace mlm {
 namespace {
 
-// one map (the body of mlm_map); the lens is locked
+// one map (the body of mlm_map and of mlm_map_noalloc); the lens is locked
 void map_impl(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_stats *stats)
 {
     const mlm_map_request &q = *req;
@@ -612,6 +663,12 @@ void map_impl(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_st
     LensConst lc = lens_const(lens, R);
 
     int64_t rows_per_strip = STRIP_VERTS / R.nr1;
+    if (Arena *a = thread_arena()) {
+        // inside a scratch arena the vertex strip takes at most a quarter of
+        // what is left; the rest serves the IPM's per-strip buffers
+        const int64_t fit = (int64_t)((a->cap - a->used) / 4 / (sizeof(double2) * (size_t)R.nr1));
+        rows_per_strip = std::min(rows_per_strip, fit);
+    }
     if (rows_per_strip < 2) rows_per_strip = 2;
     int64_t nbuf = rows_per_strip * R.nr1;
     int64_t vrows = cb1 - cb0 + 1;
@@ -737,7 +794,9 @@ void map_impl(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_st
     }
     if (diff) launch_diff_rows(g, diff, map, st);
     if (!q.device_out) MLM_HIP(hipMemcpyAsync(mu, map, npix * sizeof(double), hipMemcpyDeviceToHost, st));
-    unsigned long long *hc = static_cast<unsigned long long *>(pinned(lens, NCNT * sizeof(unsigned long long)));
+    unsigned long long hc_local[NCNT];
+    unsigned long long *hc =
+        thread_arena() ? hc_local : static_cast<unsigned long long *>(pinned(lens, NCNT * sizeof(unsigned long long)));
     MLM_HIP(hipMemcpyAsync(hc, cnt, NCNT * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     int e_end = tm.mark();
     MLM_HIP(hipStreamSynchronize(st));
@@ -795,6 +854,88 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
     if (!lens || !mu) fail(MLM_EINVAL, "lens and mu must not be NULL");
     check_request(req);
     std::lock_guard<std::mutex> guard(lens->mu);
+    map_impl(lens, req, mu, stats);
+    API_END
+}
+
+}  // extern "C"
+
+namespace mlm {
+namespace {
+
+// The scratch array of mlm_map_noalloc: one per device the library runs on,
+// held until the process ends.  In host code its name is only a stand-in;
+// the device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t SCRATCH_BYTES = (size_t)MLM_NOALLOC_SCRATCH_MIB << 20;
+__device__ __align__(256) char scratch[SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu[MAX_DEVICES];   // one call at a time per device
+char *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of this device's scratch array (the device is current).
+char *scratch_on(int dev)
+{
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        MLM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = static_cast<char *>(ptr);
+    }
+    return g_scratch_ptr[dev];
+}
+
+// installs an arena over the scratch for the duration of a call; on the way
+// out (also after an error) the stream is drained, so no kernel of this call
+// still reads the scratch, and the lens's own buffers are put back
+struct ArenaScope {
+    Arena &a;
+    Workspace &ws;
+    hipStream_t st;
+    int ops_p;
+    ArenaScope(Arena &a_, Workspace &ws_, hipStream_t st_) : a(a_), ws(ws_), st(st_), ops_p(ws_.ops_p)
+    {
+        thread_arena() = &a;
+    }
+    ~ArenaScope()
+    {
+        (void)hipStreamSynchronize(st);
+        thread_arena() = nullptr;
+        a.restore();
+        ws.ops_p = ops_p;   // operator tables uploaded into the scratch are gone
+    }
+};
+
+}  // namespace
+}  // namespace mlm
+
+extern "C" {
+
+mlm_status mlm_map_noalloc(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_stats *stats)
+{
+    API_BEGIN
+    if (!lens || !mu) fail(MLM_EINVAL, "lens and mu must not be NULL");
+    check_request(req);
+    if (req->refine != MLM_REFINE_NONE) fail(MLM_ENOTSUP, "mlm_map_noalloc does not refine cells");
+    int dev = 0;
+    MLM_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) fail(MLM_ERANGE, "device %d beyond the library's %d", dev, MAX_DEVICES);
+    // sizes known before any device work: the sorted stars and their keys
+    // (48 bytes a star), two vertex rows, the map if it goes to the host,
+    // and the column differences of maps too wide for row bands
+    Region R{};
+    setup_region(lens, req, &R);
+    const double need = 48.0 * (double)lens->n + 2.0 * 16.0 * (double)R.nr1 +
+                        (req->device_out ? 0.0 : 8.0 * (double)req->n1 * (double)req->n2) +
+                        (band_height(req->n1, req->n2) <= 0 ? 8.0 * (double)req->n2 * (double)(req->n1 + 1) : 0.0);
+    if (need > (double)SCRATCH_BYTES)
+        fail(MLM_ERANGE, "the map needs at least %.0f MiB of scratch, more than the %zu MiB of mlm_map_noalloc",
+             need / 1048576.0, SCRATCH_BYTES >> 20);
+    std::lock_guard<std::mutex> sguard(g_scratch_mu[dev]);
+    std::lock_guard<std::mutex> guard(lens->mu);
+    Arena a;
+    a.base = scratch_on(dev);
+    a.cap = SCRATCH_BYTES;
+    ArenaScope scope(a, lens->ws, stream_of(req));
     map_impl(lens, req, mu, stats);
     API_END
 }

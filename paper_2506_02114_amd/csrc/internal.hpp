@@ -44,6 +44,32 @@ struct DevBuf {
     template <class T> T *as() const { return static_cast<T *>(p); }
 };
 
+// Scratch arena of the entry point that allocates nothing.  While one is
+// installed on the calling thread, DevBuf::reserve and grow_keep hand out
+// slices of it instead of device allocations (a slice is reused while it is
+// large enough; nothing is freed), and every buffer it replaced is put back
+// when the arena is removed.  Exhausting it is MLM_ERANGE.
+struct Arena {
+    static constexpr int MAX_BUFS = 128;
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+    struct Saved {
+        DevBuf *buf;
+        void *p;
+        size_t cap;
+    } saved[MAX_BUFS];
+    int nsaved = 0;
+    bool owns(const void *q) const
+    {
+        return q && static_cast<const char *>(q) >= base && static_cast<const char *>(q) < base + cap;
+    }
+    void *take(size_t bytes);
+    void *reserve(DevBuf &b, size_t bytes);
+    void restore();
+};
+// the arena installed on this thread, or nullptr
+Arena *&thread_arena();
+
 // ---------------------------------------------------------------------------
 // constants of the tree
 // ---------------------------------------------------------------------------

@@ -244,6 +244,16 @@ __global__ void k_scan_total(const T *in, const T *out, int64_t n, int64_t *host
 template <class T>
 int64_t read_total(mlm_lens *lens, const T *in, const T *out, int64_t n, hipStream_t st)
 {
+    if (Arena *a = thread_arena()) {
+        // no pinned buffer inside a scratch arena: the total goes to a
+        // scratch slot and is copied to the host
+        int64_t *d = static_cast<int64_t *>(a->take(sizeof(int64_t)));
+        int64_t v = 0;
+        hipLaunchKernelGGL(k_scan_total<T>, dim3(1), dim3(64), 0, st, in, out, n, d);
+        MLM_HIP(hipMemcpyAsync(&v, d, sizeof v, hipMemcpyDeviceToHost, st));
+        MLM_HIP(hipStreamSynchronize(st));
+        return v;
+    }
     int64_t *h = static_cast<int64_t *>(pinned(lens, sizeof(int64_t)));
     hipLaunchKernelGGL(k_scan_total<T>, dim3(1), dim3(64), 0, st, in, out, n, h);
     MLM_HIP(hipStreamSynchronize(st));
