@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define MLM_ABI_VERSION 4
+#define MLM_ABI_VERSION 5
 
 typedef enum mlm_status {
     MLM_OK = 0,
@@ -64,19 +64,29 @@ const char *mlm_last_error(void);
 /* lens                                                                      */
 /* ------------------------------------------------------------------------ */
 
-enum { MLM_SHEET_CIRCLE = 0, MLM_SHEET_NONE = 1 };
+enum { MLM_SHEET_CIRCLE = 0, MLM_SHEET_NONE = 1, MLM_SHEET_RECT = 2 };
 
 /*
- * Macro model and microlens field (sec. 2.1-2.2, 3.1).
- *   kappa_star   convergence in microlenses, >= 0.  With MLM_SHEET_CIRCLE the
- *                stars are taken to fill a disc of radius
- *                R_* = sqrt(sum m_i / kappa_star), the compensating sheet is
- *                a_s = -kappa_* z for |z| <= R_* and -kappa_* R_*^2 / conj(z)
- *                outside (sec. 3.1, both branches of its footnote).
+ * Macro model and microlens field (sec. 2.1-2.2, 3.1, app. B).
+ *   kappa_star   convergence in microlenses, >= 0.  The stars are taken to
+ *                fill a region of area pi sum(m_i) / kappa_star (sec. 2.1
+ *                with theta_* = 1), so the realised kappa_* is the requested
+ *                one, and a compensating sheet of -kappa_star over that
+ *                region is added:
+ *                MLM_SHEET_CIRCLE: a disc of radius R_* = sqrt(sum m_i /
+ *                kappa_star); a_s = -kappa_* z for |z| <= R_* and
+ *                -kappa_* R_*^2 / conj(z) outside (sec. 3.1, both branches
+ *                of its footnote);
+ *                MLM_SHEET_RECT: the rectangle [-c1, c1] x [-c2, c2] with
+ *                c2 = rect_aspect c1 and 4 c1 c2 = pi sum m_i / kappa_star;
+ *                a_s is app. B's closed form with four complex logarithms
+ *                and its branch-cut terms, valid inside and outside.
  *   kappa_smooth smooth convergence; kappa = kappa_star + kappa_smooth.
  *   gamma        external shear, real (the frame is rotated onto it, sec. 2.1).
- *   sheet        MLM_SHEET_CIRCLE or MLM_SHEET_NONE (no compensating sheet:
- *                for isolated lenses such as the point lens).
+ *   sheet        MLM_SHEET_CIRCLE, MLM_SHEET_RECT or MLM_SHEET_NONE (no
+ *                compensating sheet: for isolated lenses such as the point
+ *                lens).
+ *   rect_aspect  c2 / c1 of the star rectangle (MLM_SHEET_RECT, > 0).
  */
 typedef struct mlm_lens_params {
     double kappa_star;
@@ -84,6 +94,7 @@ typedef struct mlm_lens_params {
     double gamma;
     int32_t sheet;
     int32_t reserved;
+    double rect_aspect;
 } mlm_lens_params;
 
 typedef struct mlm_lens mlm_lens;
@@ -113,9 +124,21 @@ typedef struct mlm_lens_info {
     double kappa;         /* kappa_* + kappa_s */
     double mu_macro;      /* 1 / ((1-kappa)^2 - gamma^2) */
     double max_abs;       /* max over stars of max(|x|, |y|) */
+    double extent1;       /* star region: R_* (disc) or c1 (rectangle); 0 without a sheet */
+    double extent2;       /* R_* (disc) or c2 (rectangle) */
 } mlm_lens_info;
 
 mlm_status mlm_lens_get_info(const mlm_lens *lens, mlm_lens_info *out);
+
+/*
+ * The lens's stars, in the order they were given or drawn: up to cap of
+ * them into host arrays x, y, m (any may be NULL); *n receives the count.
+ * Lets a checker consume exactly the field the library holds.
+ * Errors: MLM_EINVAL (NULL lens or n), MLM_ERANGE (cap < count: nothing
+ * copied, *n set), MLM_EDEVICE.
+ */
+mlm_status mlm_lens_stars(const mlm_lens *lens, double *x, double *y, double *m, int64_t cap, int64_t *n);
+
 
 /* ------------------------------------------------------------------------ */
 /* map request                                                               */
@@ -124,6 +147,7 @@ mlm_status mlm_lens_get_info(const mlm_lens *lens, mlm_lens_info *out);
 enum { MLM_PREC_FP64 = 0, MLM_PREC_MIXED = 1 };
 enum { MLM_REFINE_NONE = 0, MLM_REFINE_PLAIN = 1, MLM_REFINE_LEARNED = 2 };
 enum { MLM_METHOD_FMM = 0, MLM_METHOD_DIRECT = 1 };
+enum { MLM_MAP_IPM = 0, MLM_MAP_IRS = 1 };
 
 /*
  * Map request.  Fill with mlm_map_request_init() and override fields.
@@ -181,6 +205,14 @@ enum { MLM_METHOD_FMM = 0, MLM_METHOD_DIRECT = 1 };
  *   w_out          optional: receives the mapped source positions (y1, y2)
  *                  of the vertex rows row_begin .. row_end (inclusive),
  *                  nray1 per row, interleaved doubles (2 * nr1 * rows).
+ *   mapping        MLM_MAP_IPM: inverse polygon mapping of the grid's
+ *                  triangular cells (sec. 3.2); MLM_MAP_IRS: inverse ray
+ *                  shooting (sec. 2.3, 4), one ray at the centre of every
+ *                  grid cell, counted in the pixel it lands in, so that
+ *                  mu = count x (cell area) / (pixel area); with the
+ *                  paper's 10^2 - 10^3 rays per pixel.  IRS rows are the
+ *                  same cell rows, so IRS maps are additive over row
+ *                  ranges too; it takes no w_out and no refinement.
  *   timing         1: record device times of each stage into the stats;
  *                  2: also count the IPM kernels' work (n_big_rows,
  *                  n_band_rows, n_band_pieces, n_small, n_col_items,
@@ -210,6 +242,8 @@ typedef struct mlm_map_request {
     double refine_tau;         /* L1 threshold over the cell's image area (default 1e-3) */
     double refine_threshold;   /* logit above which the network flags a cell (default 0) */
     struct mlm_refiner *refiner;   /* network for MLM_REFINE_LEARNED */
+    int32_t mapping;           /* MLM_MAP_IPM (default) or MLM_MAP_IRS */
+    int32_t reserved2;
 } mlm_map_request;
 
 void mlm_map_request_init(mlm_map_request *req);
@@ -233,6 +267,81 @@ typedef struct mlm_region {
 
 /* Compute the region of a request without mapping.  Errors as mlm_map. */
 mlm_status mlm_map_region(const mlm_lens *lens, const mlm_map_request *req, mlm_region *out);
+
+/* ------------------------------------------------------------------------ */
+/* star fields drawn by the library                                          */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Mass functions (the paper names Salpeter and "a variety"; sec. 2.1, 5):
+ *   MLM_MASS_EQUAL     every m = m_equal
+ *   MLM_MASS_SALPETER  dN/dm ~ m^-2.35 on [m_lo, m_hi]
+ *   MLM_MASS_KROUPA    dN/dm ~ m^-1.3 on [m_lo, 0.5), ~ m^-2.3 on [0.5, m_hi],
+ *                      continuous at 0.5 (needs m_lo < 0.5 < m_hi)
+ * Masses are drawn by inverse CDF; positions uniformly in the disc or
+ * rectangle that realises kappa_star for the drawn total mass (the region
+ * mlm_lens_params describes).  Star i's draws are Philox4x32-10 blocks with
+ * counter (i mod 2^32, i div 2^32, b, 0), b = 0, 1, and key (seed mod 2^32,
+ * seed div 2^32): mass from words 0-1 of block 0, then from words 2-3 of
+ * block 0 and 0-1 of block 1 the disc's (r^2 / R_*^2, angle / 2 pi) or the
+ * rectangle's ((x / c1 + 1) / 2, (y / c2 + 1) / 2); a uniform in (0, 1) is
+ * ((a >> 5) 2^26 + (b >> 6) + 1/2) 2^-53 of two words (a, b).
+ */
+enum { MLM_MASS_EQUAL = 0, MLM_MASS_SALPETER = 1, MLM_MASS_KROUPA = 2 };
+
+typedef struct mlm_field_params {
+    double kappa_star;       /* > 0 */
+    int32_t mass_fn;         /* MLM_MASS_* */
+    int32_t shape;           /* MLM_SHEET_CIRCLE (disc) or MLM_SHEET_RECT */
+    double m_equal;          /* MLM_MASS_EQUAL's mass, > 0 (default 1) */
+    double m_lo, m_hi;       /* power-law range (defaults 0.1, 1) */
+    int64_t n_stars;         /* > 0: this many; 0: kappa_star extent / (pi <m>)
+                                with the mass function's <m> (sec. 2.1), rounded */
+    double extent1, extent2; /* n_stars == 0: disc radius (extent1), or the
+                                rectangle's half-sides */
+    double rect_aspect;      /* rectangle c2 / c1 (> 0; 0 with n_stars == 0:
+                                extent2 / extent1) */
+    uint64_t seed;
+} mlm_field_params;
+
+void mlm_field_params_init(mlm_field_params *f);
+
+/* The mass function's <m> and <m^2> (exact integrals). */
+mlm_status mlm_field_moments(const mlm_field_params *f, double *mean_m, double *mean_m2);
+
+/* The number of stars a field has (n_stars, or the count its extent gives). */
+mlm_status mlm_field_count(const mlm_field_params *f, int64_t *n);
+
+/*
+ * Draw a field into host arrays of capacity cap: *n stars; extent1/extent2
+ * (may be NULL) receive the realised region (R_*, R_* or c1, c2).
+ * Errors: MLM_EINVAL (bad parameters), MLM_ERANGE (cap below the count:
+ * nothing written but *n).
+ */
+mlm_status mlm_field_sample(const mlm_field_params *f, double *x, double *y, double *m, int64_t cap, int64_t *n,
+                            double *extent1, double *extent2);
+
+/*
+ * The star region that covers a map request's shooting region (sec. 2.3,
+ * 3.1: "somewhat larger"): margin times the disc radius reaching the
+ * rectangle's farthest corner, or margin times the rectangle
+ * (|X1| + dX1, |X2| + dX2); the border r of appendix A uses the mass
+ * function's exact <m>, <m^2>.  With f->n_stars = 0 and these extents,
+ * mlm_field_count gives the paper's star count for the map.
+ */
+mlm_status mlm_field_cover(const mlm_lens_params *params, const mlm_field_params *f, const mlm_map_request *req,
+                           double margin, double *extent1, double *extent2);
+
+/*
+ * Create a lens from a field the library draws (mlm_field_sample's stars):
+ * params->kappa_star must equal f->kappa_star, and params->sheet must be
+ * f->shape or MLM_SHEET_NONE; a rectangle's aspect is taken from the field.
+ */
+mlm_status mlm_lens_create_sampled(const mlm_lens_params *params, const mlm_field_params *f, mlm_lens **out);
+
+/* The published Philox4x32-10 block (Salmon et al. 2011) the sampler draws
+ * from: out = philox(counter, key). */
+void mlm_philox4x32_10(const uint32_t counter[4], const uint32_t key[2], uint32_t out[4]);
 
 typedef struct mlm_map_stats {
     int64_t n_rays;          /* grid vertices shot */
@@ -264,6 +373,8 @@ typedef struct mlm_map_stats {
     int64_t n_small;         /* triangles within 2 x 2 pixels, apportioned in place (if timing) */
     int64_t n_col_items;     /* (triangle, pixel column) items of the cell pass (if timing) */
     int64_t n_col_pieces;    /* pixel pieces those columns evaluate (if timing) */
+    int64_t n_pieces;        /* (triangle, pixel) pairs that meet inside the map, over all
+                                paths: the pieces the apportioning deposits (timing 2) */
 } mlm_map_stats;
 
 /*

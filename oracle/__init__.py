@@ -75,8 +75,14 @@ def lib():
         L = C.CDLL(_LIB)
         L.orc_alpha_direct.argtypes = [C.c_long, _dp, _dp, _dp, C.c_long, _dp, _dp, _dp, _dp, C.c_int]
         L.orc_alpha_direct_reversed.argtypes = [C.c_long, _dp, _dp, _dp, C.c_long, _dp, _dp, _dp, _dp]
-        L.orc_lens_equation.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int, C.c_double,
+        L.orc_lens_equation.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int, C.c_double, C.c_double,
                                         C.c_long, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.orc_sheet_alpha.argtypes = [C.c_double, C.c_int, C.c_double, C.c_double, C.c_long, _dp, _dp, _dp, _dp]
+        L.orc_star_rect.argtypes = [C.c_long, _dp, C.c_double, C.c_double, _dp, _dp]
+        L.orc_irs_rows.argtypes = [C.POINTER(Region), C.c_double, C.c_double, C.c_double, C.c_int, C.c_double,
+                                   C.c_double, C.c_long, _dp, _dp, _dp, C.c_void_p, C.c_long, C.c_long, _lp,
+                                   _dp, C.c_int]
+        L.orc_irs_rows.restype = C.c_long
         L.orc_star_radius.argtypes = [C.c_long, _dp, C.c_double]
         L.orc_star_radius.restype = C.c_double
         L.orc_region_setup.argtypes = [C.POINTER(Region), C.c_double, C.c_double, C.c_double,
@@ -104,11 +110,12 @@ def lib():
         L.orc_ipm_rows.argtypes = [C.POINTER(Region), C.c_long, C.c_long, _dp, _dp, _dp, _dp]
         L.orc_cell_features.argtypes = [_dp, _dp, _dp]
         L.orc_refine_cells.argtypes = [C.POINTER(Region), C.c_double, C.c_double, C.c_double, C.c_int, C.c_double,
+                                       C.c_double,
                                        C.c_long, _dp, _dp, _dp, C.c_void_p, C.c_long, _lp, _lp, C.c_double,
                                        C.c_int, C.c_int, C.POINTER(C.c_ubyte), _dp, _lp]
         L.orc_normalise.argtypes = [C.POINTER(Region), _dp, _dp]
         L.orc_shoot_rows.argtypes = [C.POINTER(Region), C.c_double, C.c_double, C.c_double, C.c_int,
-                                     C.c_double, C.c_long, _dp, _dp, _dp, C.c_void_p, C.c_long,
+                                     C.c_double, C.c_double, C.c_long, _dp, _dp, _dp, C.c_void_p, C.c_long,
                                      C.c_long, _dp, _dp, C.c_int]
         _lib = L
     return _lib
@@ -128,19 +135,32 @@ def _f64(a) -> np.ndarray:
 
 @dataclass
 class Lens:
-    """Macro model + star field (sec. 2.2).  sheet=True adds the circular
-    compensating sheet of radius R_* = sqrt(sum m / kappa_*) (sec. 3.1)."""
+    """Macro model + star field (sec. 2.2).  sheet=True (or "circle") adds the
+    circular compensating sheet of radius R_* = sqrt(sum m / kappa_*) (sec.
+    3.1); sheet="rect" the rectangular one of app. B over [-c1, c1] x
+    [-c2, c2] with c2 = rect_aspect c1 and 4 c1 c2 = pi sum m / kappa_*."""
     kappa_star: float
     kappa_smooth: float
     gamma: float
     x: np.ndarray
     y: np.ndarray
     m: np.ndarray
-    sheet: bool = True
+    sheet: object = True
+    rect_aspect: float = 0.0
 
     def __post_init__(self):
         self.x, self.y, self.m = _f64(self.x), _f64(self.y), _f64(self.m)
         self.r_star = lib().orc_star_radius(len(self.m), _d(self.m), self.kappa_star)
+        if self.sheet is True or self.sheet == "circle":
+            self.sheet_code, self.e1, self.e2 = (1 if self.n else 0), self.r_star, self.r_star
+        elif self.sheet == "rect":
+            c1, c2 = C.c_double(), C.c_double()
+            lib().orc_star_rect(self.n, _d(self.m), self.kappa_star, self.rect_aspect, C.byref(c1), C.byref(c2))
+            self.sheet_code, self.e1, self.e2 = (2 if self.n else 0), c1.value, c2.value
+        elif self.sheet is False or self.sheet is None or self.sheet == "none":
+            self.sheet_code, self.e1, self.e2 = 0, 0.0, 0.0
+        else:
+            raise ValueError(f"unknown sheet {self.sheet!r}")
 
     @property
     def n(self) -> int:
@@ -163,9 +183,19 @@ def alpha_direct(lens: Lens, zx, zy, nthreads: int = 0, reversed_order: bool = F
 def lens_equation(lens: Lens, zx, zy, ax, ay):
     zx, zy, ax, ay = map(_f64, (zx, zy, ax, ay))
     wx, wy = np.empty_like(zx), np.empty_like(zy)
-    lib().orc_lens_equation(lens.kappa_star, lens.kappa_smooth, lens.gamma, int(lens.sheet),
-                            lens.r_star, zx.size, _d(zx), _d(zy), _d(ax), _d(ay), _d(wx), _d(wy))
+    lib().orc_lens_equation(lens.kappa_star, lens.kappa_smooth, lens.gamma, lens.sheet_code,
+                            lens.e1, lens.e2, zx.size, _d(zx), _d(zy), _d(ax), _d(ay), _d(wx), _d(wy))
     return wx, wy
+
+
+def sheet_alpha(kappa_star: float, sheet: str, e1: float, e2: float, zx, zy):
+    """Deflection a_s of a compensating sheet alone: "circle" of radius e1
+    (sec. 3.1) or "rect" with corner (e1, e2) (app. B)."""
+    zx, zy = _f64(zx), _f64(zy)
+    ax, ay = np.empty_like(zx), np.empty_like(zy)
+    lib().orc_sheet_alpha(kappa_star, {"circle": 1, "rect": 2}[sheet], e1, e2, zx.size, _d(zx), _d(zy),
+                          _d(ax), _d(ay))
+    return ax, ay
 
 
 def shoot_direct(lens: Lens, zx, zy, nthreads: int = 0):
@@ -329,7 +359,7 @@ def shoot_rows(R: Region, lens: Lens, row_lo: int, row_hi: int, fmm: Optional[FM
     n = (row_hi - row_lo) * R.nr1
     wx, wy = np.empty(n), np.empty(n)
     lib().orc_shoot_rows(C.byref(R), lens.kappa_star, lens.kappa_smooth, lens.gamma,
-                         int(lens.sheet), lens.r_star, lens.n, _d(lens.x), _d(lens.y), _d(lens.m),
+                         lens.sheet_code, lens.e1, lens.e2, lens.n, _d(lens.x), _d(lens.y), _d(lens.m),
                          fmm.handle if fmm is not None else None, row_lo, row_hi, _d(wx), _d(wy),
                          nthreads)
     return wx, wy
@@ -389,6 +419,40 @@ def magnification_map(lens: Lens, spec: dict, method: str = "fmm", p: int = 0,
                      int(stats[4]), (row_lo, row_hi))
 
 
+@dataclass
+class IRSResult:
+    counts: np.ndarray         # (n2, n1) rays per pixel
+    mu: np.ndarray             # counts D1 D2 / (pix1 pix2)
+    region: Region
+    n_out: int                 # rays landing outside the map
+    uv: Optional[np.ndarray]   # (rays, 2) landing points in pixel units, if asked for
+    rows: tuple
+
+
+def irs_map(lens: Lens, spec: dict, method: str = "direct", p: int = 0, rows=None, want_uv: bool = False,
+            nthreads: int = 0, nmax: int = 32) -> IRSResult:
+    """Inverse ray shooting (sec. 2.3, 4): one ray at the centre of every
+    cell of the ray grid (or of the cell rows `rows`), counted in the pixel
+    it lands in."""
+    R = region(lens, **spec)
+    row_lo, row_hi = rows if rows is not None else (0, R.nr2 - 1)
+    fmm = None
+    if method == "fmm":
+        fmm = FMM(lens, R.L0, p if p > 0 else 20, nmax, MAX_LEVEL, nthreads)
+    elif method != "direct":
+        raise ValueError(method)
+    counts = np.zeros(R.n1 * R.n2, np.int64)
+    nrays = (row_hi - row_lo) * (R.nr1 - 1)
+    uv = np.empty(2 * max(nrays, 1)) if want_uv else None
+    out = lib().orc_irs_rows(C.byref(R), lens.kappa_star, lens.kappa_smooth, lens.gamma, lens.sheet_code,
+                             lens.e1, lens.e2, lens.n, _d(lens.x), _d(lens.y), _d(lens.m),
+                             fmm.handle if fmm is not None else None, row_lo, row_hi,
+                             counts.ctypes.data_as(_lp), _d(uv) if want_uv else None, nthreads)
+    mu = counts * (R.d1 * R.d2 / (R.pix1 * R.pix2))
+    return IRSResult(counts.reshape(R.n2, R.n1), mu.reshape(R.n2, R.n1), R, int(out),
+                     uv[:2 * nrays].reshape(-1, 2) if want_uv else None, (row_lo, row_hi))
+
+
 # ---------------------------------------------------------------------------
 # Cell refinement and its learned stand-in.  The paper apportions every cell
 # as two triangles and does no subdivision (sec. 3.2); the refinement below is
@@ -421,8 +485,8 @@ def refine_cells(R: Region, lens: Lens, cells_a, cells_b, fmm: Optional[FMM] = N
     labels = np.zeros(ca.size, np.uint8)
     dep = np.zeros(R.n1 * R.n2)
     st = np.zeros(3, np.int64)
-    lib().orc_refine_cells(C.byref(R), lens.kappa_star, lens.kappa_smooth, lens.gamma, int(lens.sheet),
-                           lens.r_star, lens.n, _d(lens.x), _d(lens.y), _d(lens.m),
+    lib().orc_refine_cells(C.byref(R), lens.kappa_star, lens.kappa_smooth, lens.gamma, lens.sheet_code,
+                           lens.e1, lens.e2, lens.n, _d(lens.x), _d(lens.y), _d(lens.m),
                            fmm.handle if fmm is not None else None, ca.size, ca.ctypes.data_as(_lp),
                            cb.ctypes.data_as(_lp), tau, max_depth, window,
                            labels.ctypes.data_as(C.POINTER(C.c_ubyte)), _d(dep), st.ctypes.data_as(_lp))

@@ -12,6 +12,8 @@
  *   lens equation (sec. 2.2)         w = (1-k) z + g conj(z) - a_*(z) - a_s(z)
  *   star deflection (sec. 2.2)       a_*(z) = sum_i m_i / (conj(z) - conj(z_i))
  *   compensating sheet (sec. 3.1)    a_s = -k_* z  (|z| <= R_*),  -k_* R_*^2 / conj(z)  outside
+ *   rectangular sheet (app. B)       the closed form with four complex logarithms
+ *   IRS (sec. 2.3, 4): one ray per grid cell, counted in the pixel it lands in
  *   shooting region (sec. 2.3, app. A)
  *   FMM (sec. 3.3, app. C): tree, P2M, M2M, M2L, P2L, L2L, L2P + near field
  *   IPM (sec. 3.2): each grid cell split into two triangles, each mapped
@@ -34,6 +36,8 @@
 #include <unistd.h>
 
 typedef double complex cplx;
+
+static const double ORC_PI = 3.14159265358979323846;
 
 /* ------------------------------------------------------------------------ */
 /* threading helper                                                          */
@@ -150,9 +154,55 @@ void orc_alpha_direct_reversed(long n, const double *sx, const double *sy, const
 
 typedef struct {
     double kappa_star, kappa_smooth, gamma;
-    int sheet;           /* 1: circular compensating sheet of radius r_star */
-    double r_star;
+    int sheet;           /* 0: none; 1: circular sheet of radius e1 = R_*;
+                            2: rectangular sheet with corner (e1, e2) = (c1, c2) */
+    double e1, e2;
 } orc_lens;
+
+/*
+ * Deflection of a sheet of convergence -k_* spread over the rectangle
+ * [-c1, c1] x [-c2, c2] (app. B), in complex form with c = c1 + i c2 and the
+ * principal logarithm:
+ *   a_s = (-k_* i / pi) [ (c - zb) log(c - zb) - (cb - zb) log(cb - zb)
+ *                         + (-c - zb) log(-c - zb) - (-cb - zb) log(-cb - zb) ]
+ *         - k_* (c + cb + z + zb) B_(c1,c2)(z)
+ *         - k_* 2 (c + cb) B_(inf,c2)(z) H(Re z - c1)
+ * B the boxcar of the rectangle (or of the band |Im z| <= c2), H the step.
+ */
+static cplx sheet_rect(double ks, double c1, double c2, cplx z)
+{
+    cplx c = c1 + I * c2, cb = conj(c), zb = conj(z);
+    cplx t = (c - zb) * clog(c - zb) - (cb - zb) * clog(cb - zb)
+           + (-c - zb) * clog(-c - zb) - (-cb - zb) * clog(-cb - zb);
+    cplx a = (-ks * I / ORC_PI) * t;
+    double x = creal(z), y = cimag(z);
+    int band = (-c2 <= y && y <= c2);
+    if (band && -c1 <= x && x <= c1) a -= ks * (c + cb + z + zb);
+    if (band && x - c1 >= 0.0) a -= ks * 2.0 * (c + cb);
+    return a;
+}
+
+/* a_s of the lens's sheet at z */
+static void sheet_alpha(const orc_lens *L, double x, double y, double *sx, double *sy)
+{
+    *sx = *sy = 0.0;
+    if (L->sheet == 1) {
+        double r2 = x * x + y * y;
+        if (r2 <= L->e1 * L->e1) {
+            *sx = -L->kappa_star * x;
+            *sy = -L->kappa_star * y;
+        } else {
+            /* -k_* R^2 / conj(z) = -k_* R^2 z / |z|^2 */
+            double f = -L->kappa_star * L->e1 * L->e1 / r2;
+            *sx = f * x;
+            *sy = f * y;
+        }
+    } else if (L->sheet == 2) {
+        cplx a = sheet_rect(L->kappa_star, L->e1, L->e2, x + I * y);
+        *sx = creal(a);
+        *sy = cimag(a);
+    }
+}
 
 /* w = (1-kappa) z + gamma conj(z) - a_*(z) - a_s(z), kappa = kappa_* + kappa_s */
 static void lens_equation(const orc_lens *L, double x, double y, double ax, double ay,
@@ -161,32 +211,39 @@ static void lens_equation(const orc_lens *L, double x, double y, double ax, doub
     double kappa = L->kappa_star + L->kappa_smooth;
     double w1 = (1.0 - kappa) * x + L->gamma * x - ax;
     double w2 = (1.0 - kappa) * y - L->gamma * y - ay;
-    if (L->sheet) {
-        double r2 = x * x + y * y;
-        double sx, sy;   /* a_s */
-        if (r2 <= L->r_star * L->r_star) {
-            sx = -L->kappa_star * x;
-            sy = -L->kappa_star * y;
-        } else {
-            /* -k_* R^2 / conj(z) = -k_* R^2 z / |z|^2 */
-            double f = -L->kappa_star * L->r_star * L->r_star / r2;
-            sx = f * x;
-            sy = f * y;
-        }
-        w1 -= sx;
-        w2 -= sy;
-    }
-    *wx = w1;
-    *wy = w2;
+    double sx, sy;
+    sheet_alpha(L, x, y, &sx, &sy);
+    *wx = w1 - sx;
+    *wy = w2 - sy;
 }
 
 void orc_lens_equation(double kappa_star, double kappa_smooth, double gamma, int sheet,
-                       double r_star, long npts, const double *zx, const double *zy,
+                       double e1, double e2, long npts, const double *zx, const double *zy,
                        const double *ax, const double *ay, double *wx, double *wy)
 {
-    orc_lens L = {kappa_star, kappa_smooth, gamma, sheet, r_star};
+    orc_lens L = {kappa_star, kappa_smooth, gamma, sheet, e1, e2};
     for (long q = 0; q < npts; ++q)
         lens_equation(&L, zx[q], zy[q], ax[q], ay[q], &wx[q], &wy[q]);
+}
+
+/* the sheet's deflection a_s alone at points z */
+void orc_sheet_alpha(double kappa_star, int sheet, double e1, double e2, long npts, const double *zx,
+                     const double *zy, double *ax, double *ay)
+{
+    orc_lens L = {kappa_star, 0.0, 0.0, sheet, e1, e2};
+    for (long q = 0; q < npts; ++q) sheet_alpha(&L, zx[q], zy[q], &ax[q], &ay[q]);
+}
+
+/* corner (c1, c2) of the star rectangle of aspect c2 / c1 whose area
+   4 c1 c2 = pi sum m / kappa_* realises kappa_* (sec. 2.1, theta_* = 1) */
+void orc_star_rect(long n, const double *m, double kappa_star, double aspect, double *c1, double *c2)
+{
+    double s = 0.0;
+    for (long i = 0; i < n; ++i) s += m[i];
+    *c1 = *c2 = 0.0;
+    if (n == 0 || kappa_star <= 0.0 || aspect <= 0.0) return;
+    *c1 = sqrt(ORC_PI * s / (4.0 * kappa_star * aspect));
+    *c2 = aspect * *c1;
 }
 
 /* R_* from kappa_* = N <m> / R_*^2  (sec. 2.1, theta_* = 1) */
@@ -1011,13 +1068,79 @@ static void shoot_rows(void *vctx, long lo, long hi)
 
 /* source positions of vertex rows [row_lo, row_hi) */
 void orc_shoot_rows(const orc_region *R, double kappa_star, double kappa_smooth, double gamma,
-                    int sheet, double r_star, long n, const double *sx, const double *sy,
+                    int sheet, double e1, double e2, long n, const double *sx, const double *sy,
                     const double *sm, const void *F, long row_lo, long row_hi,
                     double *wx, double *wy, int nthreads)
 {
-    orc_lens L = {kappa_star, kappa_smooth, gamma, sheet, r_star};
+    orc_lens L = {kappa_star, kappa_smooth, gamma, sheet, e1, e2};
     shoot_ctx c = {R, &L, n, sx, sy, sm, F, row_lo, wx, wy};
     parallel_for(row_hi - row_lo, nthreads, shoot_rows, &c);
+}
+
+/* ------------------------------------------------------------------------ */
+/* inverse ray shooting (sec. 2.3, 4)                                        */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    const orc_region *R; const orc_lens *L;
+    long n; const double *sx, *sy, *sm;
+    const void *F;
+    long row_lo; double *wx, *wy;
+} irs_ctx;
+
+/* source positions of the rays at the centres of the cells of some rows */
+static void irs_shoot(void *vctx, long lo, long hi)
+{
+    irs_ctx *c = vctx;
+    long nc = c->R->nr1 - 1;
+    double *zx = malloc(nc * sizeof(double)), *zy = malloc(nc * sizeof(double));
+    double *ax = malloc(nc * sizeof(double)), *ay = malloc(nc * sizeof(double));
+    for (long r = lo; r < hi; ++r) {
+        long b = c->row_lo + r;
+        for (long a = 0; a < nc; ++a) {
+            zx[a] = c->R->x0 + ((double)a + 0.5) * c->R->d1;
+            zy[a] = c->R->y0 + ((double)b + 0.5) * c->R->d2;
+        }
+        if (c->F) orc_fmm_alpha(c->F, nc, zx, zy, ax, ay, NULL, 1);
+        else orc_alpha_direct(c->n, c->sx, c->sy, c->sm, nc, zx, zy, ax, ay, 1);
+        for (long a = 0; a < nc; ++a)
+            lens_equation(c->L, zx[a], zy[a], ax[a], ay[a], &c->wx[r * nc + a], &c->wy[r * nc + a]);
+    }
+    free(zx); free(zy); free(ax); free(ay);
+}
+
+/*
+ * IRS over cell rows [row_lo, row_hi): one ray at the centre of every grid
+ * cell (a, b), z = (x0 + (a + 1/2) D1, y0 + (b + 1/2) D2), is deflected and
+ * counted in the pixel (floor u, floor v) it lands in, u = (w1 - ylo1) / pix1,
+ * v = (w2 - ylo2) / pix2, when that pixel is inside the map: counts[j n1 + i]
+ * += 1.  A ray stands for its cell's image area D1 D2, so the magnification
+ * is counts D1 D2 / (pix1 pix2).  uv (may be NULL) receives every ray's
+ * (u, v), row by row.  Returns the number of rays landing outside the map.
+ */
+long orc_irs_rows(const orc_region *R, double kappa_star, double kappa_smooth, double gamma, int sheet,
+                  double e1, double e2, long n, const double *sx, const double *sy, const double *sm,
+                  const void *F, long row_lo, long row_hi, long *counts, double *uv, int nthreads)
+{
+    orc_lens L = {kappa_star, kappa_smooth, gamma, sheet, e1, e2};
+    long nc = R->nr1 - 1, nrays = (row_hi - row_lo) * nc;
+    double *wx = malloc((nrays > 0 ? nrays : 1) * sizeof(double));
+    double *wy = malloc((nrays > 0 ? nrays : 1) * sizeof(double));
+    irs_ctx c = {R, &L, n, sx, sy, sm, F, row_lo, wx, wy};
+    parallel_for(row_hi - row_lo, nthreads, irs_shoot, &c);
+    double ylo1 = R->y1c - R->hw1, ylo2 = R->y2c - R->hw2;
+    long out = 0;
+    for (long k = 0; k < nrays; ++k) {
+        double u = (wx[k] - ylo1) / R->pix1, v = (wy[k] - ylo2) / R->pix2;
+        if (uv) { uv[2 * k] = u; uv[2 * k + 1] = v; }
+        double fu = floor(u), fv = floor(v);
+        if (fu >= 0.0 && fv >= 0.0 && fu < (double)R->n1 && fv < (double)R->n2)
+            counts[(long)fv * R->n1 + (long)fu] += 1;
+        else
+            ++out;
+    }
+    free(wx); free(wy);
+    return out;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1200,11 +1323,12 @@ static int refine_rec(refine_ctx *c, double A0, double B0, double h, int d, cons
    normalised) receives the refined minus the plain deposits; stats =
    {tested (sub)cells, refined (sub)cells, skipped as too large}. */
 void orc_refine_cells(const orc_region *R, double kappa_star, double kappa_smooth, double gamma, int sheet,
-                      double r_star, long n, const double *sx, const double *sy, const double *sm, const void *F,
+                      double e1, double e2, long n, const double *sx, const double *sy, const double *sm,
+                      const void *F,
                       long ncells, const long *ca, const long *cb, double tau, int max_depth, int window,
                       unsigned char *label, double *dmap, long *stats)
 {
-    refine_ctx c = {R, {kappa_star, kappa_smooth, gamma, sheet, r_star}, n, sx, sy, sm, F, tau, max_depth, window,
+    refine_ctx c = {R, {kappa_star, kappa_smooth, gamma, sheet, e1, e2}, n, sx, sy, sm, F, tau, max_depth, window,
                     dmap, 0, 0, 0};
     for (long k = 0; k < ncells; ++k) {
         double u4[4], v4[4];

@@ -19,7 +19,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmlmap.so")
 
 MLM_OK, MLM_EINVAL, MLM_EDEGENERATE, MLM_ERANGE, MLM_ENOMEM, MLM_EDEVICE, MLM_ENOTSUP = range(7)
-SHEET_CIRCLE, SHEET_NONE = 0, 1
+SHEET_CIRCLE, SHEET_NONE, SHEET_RECT = 0, 1, 2
+MASS_EQUAL, MASS_SALPETER, MASS_KROUPA = 0, 1, 2
+MAP_IPM, MAP_IRS = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 REFINE_NONE, REFINE_PLAIN, REFINE_LEARNED = 0, 1, 2
 REFINER_PARAMS = 5057
@@ -30,7 +32,9 @@ EXPORTED = [
     "mlm_lens_get_info", "mlm_map_request_init", "mlm_map_region", "mlm_map", "mlm_deflect",
     "mlm_fmm_export", "mlm_refiner_create", "mlm_refiner_destroy", "mlm_refiner_get_params",
     "mlm_refiner_set_params", "mlm_refiner_predict", "mlm_refiner_grads", "mlm_train_opts_init",
-    "mlm_refiner_train", "mlm_cell_samples", "mlm_map_noalloc",
+    "mlm_refiner_train", "mlm_cell_samples", "mlm_map_noalloc", "mlm_lens_stars", "mlm_field_params_init",
+    "mlm_field_moments", "mlm_field_count", "mlm_field_sample", "mlm_field_cover", "mlm_lens_create_sampled",
+    "mlm_philox4x32_10",
 ]
 
 
@@ -42,13 +46,21 @@ class MLMError(RuntimeError):
 
 class LensParams(C.Structure):
     _fields_ = [("kappa_star", C.c_double), ("kappa_smooth", C.c_double), ("gamma", C.c_double),
-                ("sheet", C.c_int32), ("reserved", C.c_int32)]
+                ("sheet", C.c_int32), ("reserved", C.c_int32), ("rect_aspect", C.c_double)]
 
 
 class LensInfo(C.Structure):
     _fields_ = [("n_stars", C.c_int64), ("mass_sum", C.c_double), ("mean_m", C.c_double),
                 ("mean_m2", C.c_double), ("r_star", C.c_double), ("kappa", C.c_double),
-                ("mu_macro", C.c_double), ("max_abs", C.c_double)]
+                ("mu_macro", C.c_double), ("max_abs", C.c_double), ("extent1", C.c_double),
+                ("extent2", C.c_double)]
+
+
+class FieldParams(C.Structure):
+    _fields_ = [("kappa_star", C.c_double), ("mass_fn", C.c_int32), ("shape", C.c_int32),
+                ("m_equal", C.c_double), ("m_lo", C.c_double), ("m_hi", C.c_double), ("n_stars", C.c_int64),
+                ("extent1", C.c_double), ("extent2", C.c_double), ("rect_aspect", C.c_double),
+                ("seed", C.c_uint64)]
 
 
 class MapRequest(C.Structure):
@@ -61,7 +73,7 @@ class MapRequest(C.Structure):
                 ("row_end", C.c_int64), ("stream", C.c_void_p), ("w_out", C.c_void_p),
                 ("timing", C.c_int32), ("refine", C.c_int32), ("refine_depth", C.c_int32),
                 ("refine_window", C.c_int32), ("refine_tau", C.c_double), ("refine_threshold", C.c_double),
-                ("refiner", C.c_void_p)]
+                ("refiner", C.c_void_p), ("mapping", C.c_int32), ("reserved2", C.c_int32)]
 
 
 class Region(C.Structure):
@@ -83,7 +95,8 @@ class MapStats(C.Structure):
                 ("t_band_ms", C.c_double), ("n_band_rows", C.c_int64), ("n_band_pieces", C.c_int64),
                 ("n_refine_candidates", C.c_int64), ("n_refined", C.c_int64), ("n_refine_tests", C.c_int64),
                 ("n_refine_large", C.c_int64), ("t_refine_ms", C.c_double),
-                ("n_small", C.c_int64), ("n_col_items", C.c_int64), ("n_col_pieces", C.c_int64)]
+                ("n_small", C.c_int64), ("n_col_items", C.c_int64), ("n_col_pieces", C.c_int64),
+                ("n_pieces", C.c_int64)]
 
 
 class BatchOpts(C.Structure):
@@ -141,6 +154,20 @@ def _lib():
     L.mlm_map.restype = C.c_int
     L.mlm_map_noalloc.argtypes = [vp, C.POINTER(MapRequest), vp, C.POINTER(MapStats)]
     L.mlm_map_noalloc.restype = C.c_int
+    L.mlm_lens_stars.argtypes = [vp, vp, vp, vp, i64, C.POINTER(i64)]
+    L.mlm_field_params_init.argtypes = [C.POINTER(FieldParams)]
+    L.mlm_field_params_init.restype = None
+    L.mlm_field_moments.argtypes = [C.POINTER(FieldParams), dp, dp]
+    L.mlm_field_count.argtypes = [C.POINTER(FieldParams), C.POINTER(i64)]
+    L.mlm_field_sample.argtypes = [C.POINTER(FieldParams), vp, vp, vp, i64, C.POINTER(i64), dp, dp]
+    L.mlm_field_cover.argtypes = [C.POINTER(LensParams), C.POINTER(FieldParams), C.POINTER(MapRequest), C.c_double,
+                                  dp, dp]
+    L.mlm_lens_create_sampled.argtypes = [C.POINTER(LensParams), C.POINTER(FieldParams), C.POINTER(vp)]
+    L.mlm_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
+    L.mlm_philox4x32_10.restype = None
+    for nm in ("mlm_lens_stars", "mlm_field_moments", "mlm_field_count", "mlm_field_sample", "mlm_field_cover",
+               "mlm_lens_create_sampled"):
+        getattr(L, nm).restype = C.c_int
     L.mlm_deflect.argtypes = [vp, C.POINTER(MapRequest), vp, i64, vp]
     L.mlm_deflect.restype = C.c_int
     L.mlm_fmm_export.argtypes = [vp, C.POINTER(MapRequest), C.POINTER(TreeInfo), vp, vp, vp, vp, vp, vp, vp, vp, i64]
@@ -188,6 +215,72 @@ def _current_stream():
 REQUEST_KEYS = {k for k, _ in MapRequest._fields_} - {"stream", "w_out", "device_out", "refiner"}
 
 
+def _sheet_code(sheet) -> int:
+    if sheet is True or sheet == "circle":
+        return SHEET_CIRCLE
+    if sheet is False or sheet is None or sheet == "none":
+        return SHEET_NONE
+    if sheet == "rect":
+        return SHEET_RECT
+    raise ValueError(f"unknown sheet {sheet!r}")
+
+
+_MASS = {"equal": MASS_EQUAL, "salpeter": MASS_SALPETER, "kroupa": MASS_KROUPA}
+
+
+def field_params(kappa_star: float, mass_fn: str = "equal", n_stars: int = 0, seed: int = 0, shape: str = "circle",
+                 m_lo: float = 0.1, m_hi: float = 1.0, m_equal: float = 1.0, extent=(0.0, 0.0),
+                 rect_aspect: float = 0.0) -> FieldParams:
+    """mlm_field_params of a star field the library draws."""
+    f = FieldParams()
+    _lib().mlm_field_params_init(C.byref(f))
+    f.kappa_star, f.mass_fn, f.shape = kappa_star, _MASS[mass_fn], _sheet_code(shape)
+    f.m_lo, f.m_hi, f.m_equal, f.n_stars, f.seed = m_lo, m_hi, m_equal, int(n_stars), int(seed)
+    f.extent1, f.extent2, f.rect_aspect = float(extent[0]), float(extent[1]), rect_aspect
+    return f
+
+
+def field_moments(f: FieldParams):
+    a, b = C.c_double(), C.c_double()
+    _check(_lib().mlm_field_moments(C.byref(f), C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def field_count(f: FieldParams) -> int:
+    n = C.c_int64()
+    _check(_lib().mlm_field_count(C.byref(f), C.byref(n)))
+    return n.value
+
+
+def field_sample(f: FieldParams):
+    """(x, y, m, extent1, extent2) of the field (host arrays)."""
+    n = field_count(f)
+    x, y, m = (np.empty(n) for _ in range(3))
+    cnt, e1, e2 = C.c_int64(), C.c_double(), C.c_double()
+    _check(_lib().mlm_field_sample(C.byref(f), x.ctypes.data_as(C.c_void_p), y.ctypes.data_as(C.c_void_p),
+                                   m.ctypes.data_as(C.c_void_p), n, C.byref(cnt), C.byref(e1), C.byref(e2)))
+    return x, y, m, e1.value, e2.value
+
+
+def field_cover(kappa_star: float, kappa_smooth: float, gamma: float, f: FieldParams, margin: float = 1.1,
+                **req):
+    """Star-region extents (extent1, extent2) covering a request's shooting region."""
+    p = LensParams(kappa_star, kappa_smooth, gamma, f.shape, 0, 0.0)
+    r = make_request(**req)
+    e1, e2 = C.c_double(), C.c_double()
+    _check(_lib().mlm_field_cover(C.byref(p), C.byref(f), C.byref(r), margin, C.byref(e1), C.byref(e2)))
+    return e1.value, e2.value
+
+
+def philox4x32_10(counter, key):
+    """The published Philox4x32-10 block the sampler draws from."""
+    c = (C.c_uint32 * 4)(*counter)
+    k = (C.c_uint32 * 2)(*key)
+    o = (C.c_uint32 * 4)()
+    _lib().mlm_philox4x32_10(c, k, o)
+    return tuple(o)
+
+
 def make_request(**kw) -> MapRequest:
     r = MapRequest()
     _lib().mlm_map_request_init(C.byref(r))
@@ -196,6 +289,8 @@ def make_request(**kw) -> MapRequest:
             v = {"fp64": PREC_FP64, "mixed": PREC_MIXED}[v]
         if k == "method" and isinstance(v, str):
             v = {"fmm": METHOD_FMM, "direct": METHOD_DIRECT}[v]
+        if k == "mapping" and isinstance(v, str):
+            v = {"ipm": MAP_IPM, "irs": MAP_IRS}[v]
         if k == "refine" and isinstance(v, str):
             v = {"none": REFINE_NONE, "plain": REFINE_PLAIN, "learned": REFINE_LEARNED}[v]
         if k == "refiner":
@@ -214,10 +309,15 @@ def make_request(**kw) -> MapRequest:
 class Lens:
     """Macro model + star field resident on the GPU (see mlm_lens_create)."""
 
-    def __init__(self, kappa_star: float, kappa_smooth: float, gamma: float, x, y, m, sheet: bool = True):
+    def __init__(self, kappa_star: float, kappa_smooth: float, gamma: float, x, y, m, sheet=True,
+                 rect_aspect: float = 0.0):
+        """sheet: True / "circle" (disc sheet), "rect" (rectangular sheet of
+        aspect c2 / c1 = rect_aspect), False / "none"."""
         L = _lib()
         self._h = C.c_void_p()
-        p = LensParams(kappa_star, kappa_smooth, gamma, SHEET_CIRCLE if sheet else SHEET_NONE, 0)
+        p = LensParams(kappa_star, kappa_smooth, gamma, _sheet_code(sheet), 0, rect_aspect)
+        if x is None:   # a field the library draws: see Lens.sampled
+            return
         if _is_torch_cuda(x):
             import torch
             x, y, m = (t.to(torch.float64).contiguous() for t in (x, y, m))
@@ -230,6 +330,26 @@ class Lens:
             _check(L.mlm_lens_create(C.byref(p), x.ctypes.data_as(C.c_void_p), y.ctypes.data_as(C.c_void_p),
                                      m.ctypes.data_as(C.c_void_p), n, 0, C.byref(self._h)))
         self.n = n
+
+    @classmethod
+    def sampled(cls, kappa_star: float, kappa_smooth: float, gamma: float, field: "FieldParams", sheet=True):
+        """A lens whose stars the library draws (mlm_lens_create_sampled)."""
+        self = cls(kappa_star, kappa_smooth, gamma, None, None, None, sheet=sheet)
+        p = LensParams(kappa_star, kappa_smooth, gamma, _sheet_code(sheet), 0, 0.0)
+        _check(_lib().mlm_lens_create_sampled(C.byref(p), C.byref(field), C.byref(self._h)))
+        self.n = self.info()["n_stars"]
+        return self
+
+    def stars(self):
+        """The lens's stars (x, y, m) as host arrays (mlm_lens_stars)."""
+        n = C.c_int64()
+        st = _lib().mlm_lens_stars(self._h, None, None, None, 0, C.byref(n))
+        if st not in (MLM_OK, MLM_ERANGE):
+            _check(st)
+        x, y, m = (np.empty(n.value) for _ in range(3))
+        _check(_lib().mlm_lens_stars(self._h, x.ctypes.data_as(C.c_void_p), y.ctypes.data_as(C.c_void_p),
+                                     m.ctypes.data_as(C.c_void_p), n.value, C.byref(n)))
+        return x, y, m
 
     def close(self):
         if getattr(self, "_h", None):

@@ -160,6 +160,7 @@ void *pinned(mlm_lens *lens, size_t bytes)
 namespace {
 
 constexpr int64_t STRIP_VERTS = 1ll << 26;   // vertices per strip buffer (1 GiB of double2)
+constexpr int64_t IRS_STRIP_RAYS = 1ll << 30;   // rays per inverse-ray-shooting launch (nothing stored per ray)
 
 __global__ void k_fill(double *p, int64_t n, double v)
 {
@@ -241,6 +242,9 @@ void check_request(const mlm_map_request *q)
         fail(MLM_EINVAL, "leaf_max must be >= 0 and max_level in [0, %d]", KEY_BITS);
     if (!(q->eps >= 0) || !std::isfinite(q->eps)) fail(MLM_EINVAL, "eps must be finite and >= 0");
     if (q->refine < MLM_REFINE_NONE || q->refine > MLM_REFINE_LEARNED) fail(MLM_EINVAL, "unknown refine %d", q->refine);
+    if (q->mapping != MLM_MAP_IPM && q->mapping != MLM_MAP_IRS) fail(MLM_EINVAL, "unknown mapping %d", q->mapping);
+    if (q->mapping == MLM_MAP_IRS && (q->refine != MLM_REFINE_NONE || q->w_out))
+        fail(MLM_ENOTSUP, "ray shooting (IRS) maps take no cell refinement and no w_out");
     if (q->refine != MLM_REFINE_NONE) {
         if (q->precision != MLM_PREC_FP64 || q->method != MLM_METHOD_FMM)
             fail(MLM_ENOTSUP, "cell refinement needs FP64 and the FMM");
@@ -473,22 +477,74 @@ void mlm_train_opts_init(mlm_train_opts *o)
     o->graph = 1;
 }
 
+}  // extern "C"
+
+namespace mlm {
+namespace {
+
+void check_lens_params(const mlm_lens_params &P, int64_t n)
+{
+    if (!std::isfinite(P.kappa_star) || !std::isfinite(P.kappa_smooth) || !std::isfinite(P.gamma))
+        fail(MLM_EINVAL, "kappa_star, kappa_smooth, gamma must be finite");
+    if (P.kappa_star < 0) fail(MLM_EINVAL, "kappa_star must be >= 0");
+    if (P.sheet != MLM_SHEET_CIRCLE && P.sheet != MLM_SHEET_NONE && P.sheet != MLM_SHEET_RECT)
+        fail(MLM_EINVAL, "unknown sheet %d", P.sheet);
+    if (n > 0 && P.sheet != MLM_SHEET_NONE && P.kappa_star == 0)
+        fail(MLM_EINVAL, "a compensating sheet needs kappa_star > 0");
+    if (P.sheet == MLM_SHEET_RECT && (!(P.rect_aspect > 0) || !std::isfinite(P.rect_aspect)))
+        fail(MLM_EINVAL, "a rectangular sheet needs a finite rect_aspect > 0");
+}
+
+// a lens from host copies of the stars (checked here); the library owns it
+mlm_lens *lens_from_host(const mlm_lens_params &P, const std::vector<double> &hx, const std::vector<double> &hy,
+                         const std::vector<double> &hm)
+{
+    const int64_t n = (int64_t)hx.size();
+    double s1 = 0.0, s2 = 0.0, amax = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!std::isfinite(hx[i]) || !std::isfinite(hy[i]) || !std::isfinite(hm[i]) || !(hm[i] > 0))
+            fail(MLM_EINVAL, "star %lld has a non-finite position or a mass <= 0", (long long)i);
+        s1 += hm[i];
+        s2 += hm[i] * hm[i];
+        if (std::fabs(hx[i]) > amax) amax = std::fabs(hx[i]);
+        if (std::fabs(hy[i]) > amax) amax = std::fabs(hy[i]);
+    }
+    std::unique_ptr<mlm_lens> L(new mlm_lens());
+    L->params = P;
+    L->n = n;
+    MLM_HIP(hipGetDevice(&L->device));
+    L->mass_sum = s1;
+    L->mass2_sum = s2;
+    L->max_abs = amax;
+    L->r_star = (n > 0 && P.kappa_star > 0) ? std::sqrt(s1 / P.kappa_star) : 0.0;
+    if (n > 0 && P.kappa_star > 0 && P.sheet != MLM_SHEET_NONE)
+        field_extent(P.sheet, P.kappa_star, s1, P.rect_aspect, L->ext1, L->ext2);
+    size_t bytes = (size_t)(n > 0 ? n : 1) * sizeof(double);
+    MLM_HIP(hipMalloc(&L->d_x, bytes));
+    MLM_HIP(hipMalloc(&L->d_y, bytes));
+    MLM_HIP(hipMalloc(&L->d_m, bytes));
+    if (n > 0) {
+        MLM_HIP(hipMemcpy(L->d_x, hx.data(), n * sizeof(double), hipMemcpyHostToDevice));
+        MLM_HIP(hipMemcpy(L->d_y, hy.data(), n * sizeof(double), hipMemcpyHostToDevice));
+        MLM_HIP(hipMemcpy(L->d_m, hm.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    }
+    return L.release();
+}
+
+}  // namespace
+}  // namespace mlm
+
+extern "C" {
+
 mlm_status mlm_lens_create(const mlm_lens_params *params, const double *x, const double *y, const double *m,
                            int64_t n, int32_t device_ptrs, mlm_lens **out)
 {
-    mlm_lens *L = nullptr;
     API_BEGIN
     if (!params || !out) fail(MLM_EINVAL, "params and out must not be NULL");
     if (n < 0) fail(MLM_EINVAL, "n must be >= 0");
     if (n > 0 && (!x || !y || !m)) fail(MLM_EINVAL, "star arrays must not be NULL");
     if (n >= (int64_t)INT32_MAX / 2) fail(MLM_ERANGE, "too many stars");
-    const mlm_lens_params &P = *params;
-    if (!std::isfinite(P.kappa_star) || !std::isfinite(P.kappa_smooth) || !std::isfinite(P.gamma))
-        fail(MLM_EINVAL, "kappa_star, kappa_smooth, gamma must be finite");
-    if (P.kappa_star < 0) fail(MLM_EINVAL, "kappa_star must be >= 0");
-    if (P.sheet != MLM_SHEET_CIRCLE && P.sheet != MLM_SHEET_NONE) fail(MLM_EINVAL, "unknown sheet %d", P.sheet);
-    if (n > 0 && P.sheet == MLM_SHEET_CIRCLE && P.kappa_star == 0)
-        fail(MLM_EINVAL, "a compensating sheet needs kappa_star > 0");
+    check_lens_params(*params, n);
     std::vector<double> hx(n), hy(n), hm(n);
     if (n > 0 && device_ptrs) {
         MLM_HIP(hipMemcpy(hx.data(), x, n * sizeof(double), hipMemcpyDeviceToHost));
@@ -499,46 +555,110 @@ mlm_status mlm_lens_create(const mlm_lens_params *params, const double *x, const
         std::memcpy(hy.data(), y, n * sizeof(double));
         std::memcpy(hm.data(), m, n * sizeof(double));
     }
-    double s1 = 0.0, s2 = 0.0, amax = 0.0;
-    for (int64_t i = 0; i < n; ++i) {
-        if (!std::isfinite(hx[i]) || !std::isfinite(hy[i]) || !std::isfinite(hm[i]) || !(hm[i] > 0))
-            fail(MLM_EINVAL, "star %lld has a non-finite position or a mass <= 0", (long long)i);
-        s1 += hm[i];
-        s2 += hm[i] * hm[i];
-        if (std::fabs(hx[i]) > amax) amax = std::fabs(hx[i]);
-        if (std::fabs(hy[i]) > amax) amax = std::fabs(hy[i]);
+    *out = lens_from_host(*params, hx, hy, hm);
+    API_END
+}
+
+mlm_status mlm_lens_create_sampled(const mlm_lens_params *params, const mlm_field_params *f, mlm_lens **out)
+{
+    API_BEGIN
+    if (!params || !f || !out) fail(MLM_EINVAL, "params, field and out must not be NULL");
+    if (params->kappa_star != f->kappa_star) fail(MLM_EINVAL, "the lens's and the field's kappa_star differ");
+    if (params->sheet != MLM_SHEET_NONE && params->sheet != f->shape)
+        fail(MLM_EINVAL, "the lens's sheet must be the field's shape or none");
+    std::vector<double> hx, hy, hm;
+    double e1 = 0, e2 = 0;
+    const int64_t n = field_sample(*f, hx, hy, hm, e1, e2);
+    if (n >= (int64_t)INT32_MAX / 2) fail(MLM_ERANGE, "too many stars");
+    mlm_lens_params P = *params;
+    if (P.sheet == MLM_SHEET_RECT) P.rect_aspect = e2 / e1;
+    check_lens_params(P, n);
+    *out = lens_from_host(P, hx, hy, hm);
+    API_END
+}
+
+mlm_status mlm_lens_stars(const mlm_lens *lens, double *x, double *y, double *m, int64_t cap, int64_t *n)
+{
+    API_BEGIN
+    if (!lens || !n) fail(MLM_EINVAL, "lens and n must not be NULL");
+    *n = lens->n;
+    if (cap < lens->n) fail(MLM_ERANGE, "the lens has %lld stars, capacity %lld", (long long)lens->n, (long long)cap);
+    const size_t b = (size_t)lens->n * sizeof(double);
+    if (lens->n > 0) {
+        if (x) MLM_HIP(hipMemcpy(x, lens->d_x, b, hipMemcpyDeviceToHost));
+        if (y) MLM_HIP(hipMemcpy(y, lens->d_y, b, hipMemcpyDeviceToHost));
+        if (m) MLM_HIP(hipMemcpy(m, lens->d_m, b, hipMemcpyDeviceToHost));
     }
-    L = new mlm_lens();
-    L->params = P;
-    L->n = n;
-    MLM_HIP(hipGetDevice(&L->device));
-    L->mass_sum = s1;
-    L->mass2_sum = s2;
-    L->max_abs = amax;
-    L->r_star = (n > 0 && P.kappa_star > 0) ? std::sqrt(s1 / P.kappa_star) : 0.0;
-    size_t bytes = (size_t)(n > 0 ? n : 1) * sizeof(double);
-    MLM_HIP(hipMalloc(&L->d_x, bytes));
-    MLM_HIP(hipMalloc(&L->d_y, bytes));
-    MLM_HIP(hipMalloc(&L->d_m, bytes));
-    if (n > 0) {
-        MLM_HIP(hipMemcpy(L->d_x, hx.data(), n * sizeof(double), hipMemcpyHostToDevice));
-        MLM_HIP(hipMemcpy(L->d_y, hy.data(), n * sizeof(double), hipMemcpyHostToDevice));
-        MLM_HIP(hipMemcpy(L->d_m, hm.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    API_END
+}
+
+mlm_status mlm_field_moments(const mlm_field_params *f, double *mean_m, double *mean_m2)
+{
+    API_BEGIN
+    if (!f || !mean_m || !mean_m2) fail(MLM_EINVAL, "field and outputs must not be NULL");
+    mlm_field_params g = *f;   // only the mass function is checked here
+    g.n_stars = 1;
+    g.rect_aspect = 1;
+    (void)field_count(g);
+    field_moments(g, *mean_m, *mean_m2);
+    API_END
+}
+
+mlm_status mlm_field_count(const mlm_field_params *f, int64_t *n)
+{
+    API_BEGIN
+    if (!f || !n) fail(MLM_EINVAL, "field and n must not be NULL");
+    *n = field_count(*f);
+    API_END
+}
+
+mlm_status mlm_field_sample(const mlm_field_params *f, double *x, double *y, double *m, int64_t cap, int64_t *n,
+                            double *extent1, double *extent2)
+{
+    API_BEGIN
+    if (!f || !n) fail(MLM_EINVAL, "field and n must not be NULL");
+    const int64_t cnt = field_count(*f);
+    if (cnt > 0 && (!x || !y || !m)) fail(MLM_EINVAL, "star arrays must not be NULL");
+    if (cap < cnt) {
+        *n = cnt;
+        fail(MLM_ERANGE, "the field has %lld stars, capacity %lld", (long long)cnt, (long long)cap);
     }
-    *out = L;
-    L = nullptr;
+    std::vector<double> hx, hy, hm;
+    double e1 = 0, e2 = 0;
+    field_sample(*f, hx, hy, hm, e1, e2);
+    std::memcpy(x, hx.data(), (size_t)cnt * sizeof(double));
+    std::memcpy(y, hy.data(), (size_t)cnt * sizeof(double));
+    std::memcpy(m, hm.data(), (size_t)cnt * sizeof(double));
+    *n = cnt;
+    if (extent1) *extent1 = e1;
+    if (extent2) *extent2 = e2;
+    API_END
+}
+
+mlm_status mlm_field_cover(const mlm_lens_params *params, const mlm_field_params *f, const mlm_map_request *req,
+                           double margin, double *extent1, double *extent2)
+{
+    API_BEGIN
+    if (!params || !f || !req || !extent1 || !extent2) fail(MLM_EINVAL, "arguments must not be NULL");
+    if (!(margin >= 1) || !std::isfinite(margin)) fail(MLM_EINVAL, "margin must be finite and >= 1");
+    check_request(req);
+    mlm_field_params g = *f;
+    if (g.n_stars == 0 && !(g.extent1 > 0)) {   // only the mass function matters here
+        g.n_stars = 1;
+        if (g.shape == MLM_SHEET_RECT && !(g.rect_aspect > 0)) g.rect_aspect = 1;
     }
-    catch (const Error &e) {
-        mlm_lens_destroy(L);
-        g_last_error = e.msg;
-        return e.status;
+    (void)field_count(g);
+    double mm, mm2, X1, X2, dX1, dX2;
+    field_moments(g, mm, mm2);
+    shooting_region(*params, mm, mm2, *req, X1, X2, dX1, dX2);
+    const double a1 = std::fabs(X1) + dX1, a2 = std::fabs(X2) + dX2;
+    if (f->shape == MLM_SHEET_RECT) {
+        *extent1 = margin * a1;
+        *extent2 = margin * a2;
+    } else {
+        *extent1 = *extent2 = margin * std::sqrt(a1 * a1 + a2 * a2);
     }
-    catch (const std::bad_alloc &) {
-        mlm_lens_destroy(L);
-        g_last_error = "host allocation failed";
-        return MLM_ENOMEM;
-    }
-    return MLM_OK;
+    API_END
 }
 
 void mlm_lens_destroy(mlm_lens *lens)
@@ -565,6 +685,8 @@ mlm_status mlm_lens_get_info(const mlm_lens *lens, mlm_lens_info *out)
     double l1 = 1.0 - I.kappa + lens->params.gamma, l2 = 1.0 - I.kappa - lens->params.gamma;
     I.mu_macro = 1.0 / (l1 * l2);
     I.max_abs = lens->max_abs;
+    I.extent1 = lens->ext1;
+    I.extent2 = lens->ext2;
     *out = I;
     API_END
 }
@@ -623,7 +745,8 @@ void map_impl(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_st
     double *map = q.device_out ? mu : static_cast<double *>(ws.map.reserve(npix * sizeof(double)));
     fill(map, npix, 0.0, st);
     // counters: [0] skipped triangles, [1] ray-star pairs, [2] rays, [3] unused,
-    // [4] band row items, [5] band boundary pieces (if timing), then (if
+    // [4] band row items, [5] band boundary pieces (if timing), [6] (triangle,
+    // pixel) pieces (timing 2), [7] unused, then (if
     // timing) WORK_SLOTS partial sums each of small triangles, column items
     // and column pieces
     constexpr int NCNT = 8 + 3 * WORK_SLOTS;
@@ -662,21 +785,6 @@ void map_impl(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_st
     g.tri_weight = 0.5 * R.d1 * R.d2 / (R.pix1 * R.pix2);
     LensConst lc = lens_const(lens, R);
 
-    int64_t rows_per_strip = STRIP_VERTS / R.nr1;
-    if (Arena *a = thread_arena()) {
-        // inside a scratch arena the vertex strip takes at most a quarter of
-        // what is left; the rest serves the IPM's per-strip buffers
-        const int64_t fit = (int64_t)((a->cap - a->used) / 4 / (sizeof(double2) * (size_t)R.nr1));
-        rows_per_strip = std::min(rows_per_strip, fit);
-    }
-    if (rows_per_strip < 2) rows_per_strip = 2;
-    int64_t nbuf = rows_per_strip * R.nr1;
-    int64_t vrows = cb1 - cb0 + 1;
-    if (vrows < rows_per_strip) nbuf = vrows * R.nr1;
-    double2 *verts = static_cast<double2 *>(ws.verts.reserve((size_t)nbuf * sizeof(double2)));
-    double *wdev = nullptr;
-    if (q.w_out) wdev = q.device_out ? q.w_out : static_cast<double *>(ws.wbuf.reserve((size_t)nbuf * sizeof(double2)));
-
     int64_t n_big = 0, n_big_rows = 0, n_cand = 0, n_refined = 0;
     double t_refine = 0.0;
     bool refine_stats_zeroed = false;
@@ -684,113 +792,161 @@ void map_impl(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_st
     double t_shoot = 0.0, t_ipm = 0.0, t_cells = 0.0, t_band = 0.0;
     int64_t tiles = 0;
     int nstrips = 0;
-    for (int64_t r0 = cb0; r0 < cb1; ++nstrips) {
-        int64_t r1 = std::min(cb1, r0 + rows_per_strip - 1);   // cells [r0, r1), vertex rows [r0, r1]
-        int64_t vb0 = r0, vb1 = r1 + 1;
-        double *w_here = nullptr;
-        if (wdev) w_here = q.device_out ? wdev + 2 * (vb0 - cb0) * R.nr1 : wdev;
-        int64_t nt = 0;
-        if (fmm) {
-            nt = plan_tiles(lens, T, R, vb0, vb1, st);
-            hipLaunchKernelGGL(k_strip_work, dim3((unsigned)((T.nleaves + 255) / 256)), dim3(256), 0, st, T.nleaves,
-                               T.leaves, cnt);
+    const bool irs = q.mapping == MLM_MAP_IRS;
+    if (irs) {
+        // inverse ray shooting: one ray per cell centre, counted per pixel;
+        // nothing is stored per ray, so strips are only bounded by the tile plan
+        unsigned long long *irs_cnt =
+            static_cast<unsigned long long *>(ws.irs_counts.reserve((size_t)npix * sizeof(unsigned long long)));
+        hipLaunchKernelGGL(k_zero_u64n, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, st, irs_cnt, npix);
+        const int64_t rows = std::max<int64_t>(1, IRS_STRIP_RAYS / std::max<int64_t>(R.nr1 - 1, 1));
+        for (int64_t r0 = cb0; r0 < cb1; ++nstrips) {
+            const int64_t r1 = std::min(cb1, r0 + rows);
+            int64_t nt = 0;
+            if (fmm) {
+                nt = plan_tiles(lens, T, R, r0, r1, st, true);
+                hipLaunchKernelGGL(k_strip_work, dim3((unsigned)((T.nleaves + 255) / 256)), dim3(256), 0, st,
+                                   T.nleaves, T.leaves, cnt);
+            }
+            const int ea = tm.mark();
+            if (fmm) launch_shoot_irs(lens, T, R, lc, g, nt, r0, irs_cnt, st);
+            else launch_shoot_irs_direct(lens, R, lc, g, r0, r1, irs_cnt, st);
+            const int eb = tm.mark();
+            MLM_HIP(hipStreamSynchronize(st));
+            t_shoot += tm.ms(ea, eb);
+            tiles += nt;
+            r0 = r1;
         }
-        int ea = tm.mark();
-        if (fmm) launch_shoot(lens, T, R, lc, g, nt, vb0, verts, w_here, st);
-        else launch_shoot_direct(lens, R, lc, g, vb0, vb1, verts, w_here, st);
-        int eb = tm.mark();
-        // IPM: cell pass, then one thread per (triangle, pixel column) for the
-        // ordinary triangles and the row-parallel passes for the large ones
-        const int64_t ncells = (R.nr1 - 1) * (r1 - r0);
-        const int64_t ntl = ipm_tile_count(R.nr1, r1 - r0);
-        int32_t *tbig = static_cast<int32_t *>(ws.tbig.reserve((size_t)std::max<int64_t>(ntl, 1) * sizeof(int32_t)));
-        int64_t *toff = static_cast<int64_t *>(ws.tbigoff.reserve((size_t)(ntl + 1) * sizeof(int64_t)));
-        if (ntl > 0) hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((ntl + 255) / 256)), dim3(256), 0, st, tbig, ntl);
-        launch_ipm(verts, R.nr1, r0, r1, vb0, g, map, cnt, tbig, q.precision == MLM_PREC_MIXED,
-                   q.timing >= 2 ? cnt + 8 : nullptr, st);
-        const int e_cells = tm.mark();
-        int e_band0 = -1, e_band1 = -1;
-        const int64_t nb = scan_i32_to_i64(lens, tbig, toff, ntl, st);
-        if (nb > 0) {
-            BigPrep *prep = static_cast<BigPrep *>(ws.bigprep.reserve((size_t)nb * sizeof(BigPrep)));
-            int64_t *rows = static_cast<int64_t *>(ws.bigrows.reserve((size_t)nb * sizeof(int64_t)));
-            int32_t *row0 = static_cast<int32_t *>(ws.bigrow0.reserve((size_t)nb * sizeof(int32_t)));
-            launch_big_gather(verts, R.nr1, r0, r1, vb0, g, toff, prep, rows, row0, st);
-            const int bh = band_height(g.n1, g.n2);
-            if (bh > 0) {
-                // large triangles by pixel bands: owned rows, LDS accumulation
-                const int32_t nbands = (int32_t)((g.n2 + bh - 1) / bh);
-                int32_t *bcnt = static_cast<int32_t *>(ws.bandcnt.reserve((size_t)nbands * sizeof(int32_t)));
-                unsigned long long *boffs =
-                    static_cast<unsigned long long *>(ws.bandoff.reserve((size_t)(nbands + 1) * sizeof(unsigned long long)));
-                unsigned long long *bcur =
-                    static_cast<unsigned long long *>(ws.bandcur.reserve((size_t)(nbands + 1) * sizeof(unsigned long long)));
-                hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((nbands + 255) / 256)), dim3(256), 0, st, bcnt, nbands);
-                launch_band_count(nb, row0, rows, bh, nbands, bcnt, st);
-                const int64_t nlist = scan_i32_to_u64(lens, bcnt, boffs, nbands, st);
-                int32_t *blist = static_cast<int32_t *>(ws.bandlist.reserve((size_t)(nlist > 0 ? nlist : 1) * sizeof(int32_t)));
-                MLM_HIP(hipMemcpyAsync(bcur, boffs, (size_t)nbands * sizeof(unsigned long long), hipMemcpyDeviceToDevice, st));
-                launch_band_scatter(nb, row0, rows, bh, nbands, bcur, blist, st);
-                e_band0 = tm.mark();
-                launch_band(nbands, boffs, blist, prep, rows, bh, g, map, q.timing >= 2 ? cnt + 4 : nullptr, st);
-                e_band1 = tm.mark();
-            } else {
-                launch_big(nb, prep, rows, g, map, diff, st);
-            }
-            if (q.timing >= 2) {   // statistics only
-                int64_t *rowoff = static_cast<int64_t *>(ws.rowoff.reserve((size_t)nb * sizeof(int64_t)));
-                n_big_rows += scan_total_i64(lens, rows, rowoff, nb, st);
-            }
-            n_big += nb;
-        }
-        int ec = tm.mark();
-        if (q.refine != MLM_REFINE_NONE) {
-            // cell refinement of this strip's cells (a + (nr1 - 1) b, b in [r0, r1))
-            const int64_t base = (R.nr1 - 1) * r0;
-            int64_t *cand = static_cast<int64_t *>(ws.rcand.reserve((size_t)ncells * sizeof(int64_t)));
-            int64_t ncand = ncells;
-            if (q.refine == MLM_REFINE_LEARNED) {
-                mlm_refiner *nn = q.refiner;
-                float *feats = static_cast<float *>(ws.rfeat.reserve((size_t)ncells * 12 * sizeof(float)));
-                float *logit = static_cast<float *>(ws.rlogit.reserve((size_t)ncells * sizeof(float)));
-                int32_t *flag = static_cast<int32_t *>(ws.rflag.reserve((size_t)ncells * sizeof(int32_t)));
-                int64_t *pos = static_cast<int64_t *>(ws.rpos.reserve((size_t)(ncells + 1) * sizeof(int64_t)));
-                launch_cell_features(R.nr1, r0, ncells, vb0, verts, feats, st);
-                mlp_predict(feats, ncells, nn->W1b.as<uint16_t>(), nn->W2b.as<uint16_t>(), nn->P.as<float>(), logit, st);
-                launch_select(ncells, feats, logit, (float)q.refine_threshold, flag, st);
-                ncand = scan_i32_to_i64(lens, flag, pos, ncells, st);
-                launch_compact(ncells, flag, pos, base, cand, st);
-            } else {
-                launch_compact(ncells, nullptr, nullptr, base, cand, st);
-            }
-            uint8_t *lab = static_cast<uint8_t *>(ws.rlabel.reserve((size_t)std::max<int64_t>(ncand, 1)));
-            unsigned long long *rst3 = static_cast<unsigned long long *>(ws.rstats.reserve(4 * sizeof(unsigned long long)));
-            if (!refine_stats_zeroed) {
-                hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, rst3, 4);
-                refine_stats_zeroed = true;
-            }
-            launch_refine(T, R, lc, g, q.refine_tau, q.refine_depth, q.refine_window, ncand, cand, R.nr1, vb0, verts, lab,
-                          map, rst3, st);
-            if (ncand > 0) {
-                std::vector<uint8_t> hl((size_t)ncand);
-                MLM_HIP(hipMemcpyAsync(hl.data(), lab, (size_t)ncand, hipMemcpyDeviceToHost, st));
-                MLM_HIP(hipStreamSynchronize(st));
-                for (uint8_t v : hl) n_refined += v;
-            }
-            n_cand += ncand;
-        }
-        int ed = tm.mark();
-        if (q.w_out && !q.device_out)
-            MLM_HIP(hipMemcpyAsync(q.w_out + 2 * (vb0 - cb0) * R.nr1, wdev, (size_t)(vb1 - vb0) * R.nr1 * 2 * sizeof(double),
-                                   hipMemcpyDeviceToHost, st));
+        const int ea = tm.mark();
+        launch_irs_mu(irs_cnt, npix, R.d1 * R.d2 / (R.pix1 * R.pix2), map, st);
+        const int eb = tm.mark();
         MLM_HIP(hipStreamSynchronize(st));
-        t_shoot += tm.ms(ea, eb);
-        t_ipm += tm.ms(eb, ec);
-        t_refine += tm.ms(ec, ed);
-        t_cells += tm.ms(eb, e_cells);
-        t_band += tm.ms(e_band0, e_band1);
-        tiles += nt;
-        r0 = r1;
+        t_ipm += tm.ms(ea, eb);
+    } else {
+        int64_t rows_per_strip = STRIP_VERTS / R.nr1;
+        if (Arena *a = thread_arena()) {
+            // inside a scratch arena the vertex strip takes at most a quarter of
+            // what is left; the rest serves the IPM's per-strip buffers
+            const int64_t fit = (int64_t)((a->cap - a->used) / 4 / (sizeof(double2) * (size_t)R.nr1));
+            rows_per_strip = std::min(rows_per_strip, fit);
+        }
+        if (rows_per_strip < 2) rows_per_strip = 2;
+        int64_t nbuf = rows_per_strip * R.nr1;
+        int64_t vrows = cb1 - cb0 + 1;
+        if (vrows < rows_per_strip) nbuf = vrows * R.nr1;
+        double2 *verts = static_cast<double2 *>(ws.verts.reserve((size_t)nbuf * sizeof(double2)));
+        double *wdev = nullptr;
+        if (q.w_out) wdev = q.device_out ? q.w_out : static_cast<double *>(ws.wbuf.reserve((size_t)nbuf * sizeof(double2)));
+
+        for (int64_t r0 = cb0; r0 < cb1; ++nstrips) {
+            int64_t r1 = std::min(cb1, r0 + rows_per_strip - 1);   // cells [r0, r1), vertex rows [r0, r1]
+            int64_t vb0 = r0, vb1 = r1 + 1;
+            double *w_here = nullptr;
+            if (wdev) w_here = q.device_out ? wdev + 2 * (vb0 - cb0) * R.nr1 : wdev;
+            int64_t nt = 0;
+            if (fmm) {
+                nt = plan_tiles(lens, T, R, vb0, vb1, st);
+                hipLaunchKernelGGL(k_strip_work, dim3((unsigned)((T.nleaves + 255) / 256)), dim3(256), 0, st, T.nleaves,
+                                   T.leaves, cnt);
+            }
+            int ea = tm.mark();
+            if (fmm) launch_shoot(lens, T, R, lc, g, nt, vb0, verts, w_here, st);
+            else launch_shoot_direct(lens, R, lc, g, vb0, vb1, verts, w_here, st);
+            int eb = tm.mark();
+            // IPM: cell pass, then one thread per (triangle, pixel column) for the
+            // ordinary triangles and the row-parallel passes for the large ones
+            const int64_t ncells = (R.nr1 - 1) * (r1 - r0);
+            const int64_t ntl = ipm_tile_count(R.nr1, r1 - r0);
+            int32_t *tbig = static_cast<int32_t *>(ws.tbig.reserve((size_t)std::max<int64_t>(ntl, 1) * sizeof(int32_t)));
+            int64_t *toff = static_cast<int64_t *>(ws.tbigoff.reserve((size_t)(ntl + 1) * sizeof(int64_t)));
+            if (ntl > 0) hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((ntl + 255) / 256)), dim3(256), 0, st, tbig, ntl);
+            launch_ipm(verts, R.nr1, r0, r1, vb0, g, map, cnt, tbig, q.precision == MLM_PREC_MIXED,
+                       q.timing >= 2 ? cnt + 8 : nullptr, st);
+            const int e_cells = tm.mark();
+            if (q.timing >= 2) launch_count_pieces(verts, R.nr1, r0, r1, vb0, g, cnt + 6, st);   // statistics only
+            int e_band0 = -1, e_band1 = -1;
+            const int64_t nb = scan_i32_to_i64(lens, tbig, toff, ntl, st);
+            if (nb > 0) {
+                BigPrep *prep = static_cast<BigPrep *>(ws.bigprep.reserve((size_t)nb * sizeof(BigPrep)));
+                int64_t *rows = static_cast<int64_t *>(ws.bigrows.reserve((size_t)nb * sizeof(int64_t)));
+                int32_t *row0 = static_cast<int32_t *>(ws.bigrow0.reserve((size_t)nb * sizeof(int32_t)));
+                launch_big_gather(verts, R.nr1, r0, r1, vb0, g, toff, prep, rows, row0, st);
+                const int bh = band_height(g.n1, g.n2);
+                if (bh > 0) {
+                    // large triangles by pixel bands: owned rows, LDS accumulation
+                    const int32_t nbands = (int32_t)((g.n2 + bh - 1) / bh);
+                    int32_t *bcnt = static_cast<int32_t *>(ws.bandcnt.reserve((size_t)nbands * sizeof(int32_t)));
+                    unsigned long long *boffs =
+                        static_cast<unsigned long long *>(ws.bandoff.reserve((size_t)(nbands + 1) * sizeof(unsigned long long)));
+                    unsigned long long *bcur =
+                        static_cast<unsigned long long *>(ws.bandcur.reserve((size_t)(nbands + 1) * sizeof(unsigned long long)));
+                    hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((nbands + 255) / 256)), dim3(256), 0, st, bcnt, nbands);
+                    launch_band_count(nb, row0, rows, bh, nbands, bcnt, st);
+                    const int64_t nlist = scan_i32_to_u64(lens, bcnt, boffs, nbands, st);
+                    int32_t *blist = static_cast<int32_t *>(ws.bandlist.reserve((size_t)(nlist > 0 ? nlist : 1) * sizeof(int32_t)));
+                    MLM_HIP(hipMemcpyAsync(bcur, boffs, (size_t)nbands * sizeof(unsigned long long), hipMemcpyDeviceToDevice, st));
+                    launch_band_scatter(nb, row0, rows, bh, nbands, bcur, blist, st);
+                    e_band0 = tm.mark();
+                    launch_band(nbands, boffs, blist, prep, rows, bh, g, map, q.timing >= 2 ? cnt + 4 : nullptr, st);
+                    e_band1 = tm.mark();
+                } else {
+                    launch_big(nb, prep, rows, g, map, diff, st);
+                }
+                if (q.timing >= 2) {   // statistics only
+                    int64_t *rowoff = static_cast<int64_t *>(ws.rowoff.reserve((size_t)nb * sizeof(int64_t)));
+                    n_big_rows += scan_total_i64(lens, rows, rowoff, nb, st);
+                }
+                n_big += nb;
+            }
+            int ec = tm.mark();
+            if (q.refine != MLM_REFINE_NONE) {
+                // cell refinement of this strip's cells (a + (nr1 - 1) b, b in [r0, r1))
+                const int64_t base = (R.nr1 - 1) * r0;
+                int64_t *cand = static_cast<int64_t *>(ws.rcand.reserve((size_t)ncells * sizeof(int64_t)));
+                int64_t ncand = ncells;
+                if (q.refine == MLM_REFINE_LEARNED) {
+                    mlm_refiner *nn = q.refiner;
+                    float *feats = static_cast<float *>(ws.rfeat.reserve((size_t)ncells * 12 * sizeof(float)));
+                    float *logit = static_cast<float *>(ws.rlogit.reserve((size_t)ncells * sizeof(float)));
+                    int32_t *flag = static_cast<int32_t *>(ws.rflag.reserve((size_t)ncells * sizeof(int32_t)));
+                    int64_t *pos = static_cast<int64_t *>(ws.rpos.reserve((size_t)(ncells + 1) * sizeof(int64_t)));
+                    launch_cell_features(R.nr1, r0, ncells, vb0, verts, feats, st);
+                    mlp_predict(feats, ncells, nn->W1b.as<uint16_t>(), nn->W2b.as<uint16_t>(), nn->P.as<float>(), logit, st);
+                    launch_select(ncells, feats, logit, (float)q.refine_threshold, flag, st);
+                    ncand = scan_i32_to_i64(lens, flag, pos, ncells, st);
+                    launch_compact(ncells, flag, pos, base, cand, st);
+                } else {
+                    launch_compact(ncells, nullptr, nullptr, base, cand, st);
+                }
+                uint8_t *lab = static_cast<uint8_t *>(ws.rlabel.reserve((size_t)std::max<int64_t>(ncand, 1)));
+                unsigned long long *rst3 = static_cast<unsigned long long *>(ws.rstats.reserve(4 * sizeof(unsigned long long)));
+                if (!refine_stats_zeroed) {
+                    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, rst3, 4);
+                    refine_stats_zeroed = true;
+                }
+                launch_refine(T, R, lc, g, q.refine_tau, q.refine_depth, q.refine_window, ncand, cand, R.nr1, vb0, verts, lab,
+                              map, rst3, st);
+                if (ncand > 0) {
+                    std::vector<uint8_t> hl((size_t)ncand);
+                    MLM_HIP(hipMemcpyAsync(hl.data(), lab, (size_t)ncand, hipMemcpyDeviceToHost, st));
+                    MLM_HIP(hipStreamSynchronize(st));
+                    for (uint8_t v : hl) n_refined += v;
+                }
+                n_cand += ncand;
+            }
+            int ed = tm.mark();
+            if (q.w_out && !q.device_out)
+                MLM_HIP(hipMemcpyAsync(q.w_out + 2 * (vb0 - cb0) * R.nr1, wdev, (size_t)(vb1 - vb0) * R.nr1 * 2 * sizeof(double),
+                                       hipMemcpyDeviceToHost, st));
+            MLM_HIP(hipStreamSynchronize(st));
+            t_shoot += tm.ms(ea, eb);
+            t_ipm += tm.ms(eb, ec);
+            t_refine += tm.ms(ec, ed);
+            t_cells += tm.ms(eb, e_cells);
+            t_band += tm.ms(e_band0, e_band1);
+            tiles += nt;
+            r0 = r1;
+        }
     }
     if (diff) launch_diff_rows(g, diff, map, st);
     if (!q.device_out) MLM_HIP(hipMemcpyAsync(mu, map, npix * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -802,7 +958,7 @@ void map_impl(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_st
     MLM_HIP(hipStreamSynchronize(st));
     if (stats) {
         mlm_map_stats S{};
-        S.n_rays = (cb1 - cb0 + 1) * R.nr1;
+        S.n_rays = irs ? (cb1 - cb0) * (R.nr1 - 1) : (cb1 - cb0 + 1) * R.nr1;
         S.n_cells = (cb1 - cb0) * (R.nr1 - 1);
         S.n_skipped = (int64_t)hc[0];
         S.n_nodes = T.nnodes;
@@ -830,6 +986,7 @@ void map_impl(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_st
         S.n_small = wsum[0];
         S.n_col_items = wsum[1];
         S.n_col_pieces = wsum[2];
+        S.n_pieces = q.timing >= 2 && !irs ? (int64_t)hc[6] : 0;
         S.n_refine_candidates = n_cand;
         S.n_refined = n_refined;
         if (refine_stats_zeroed) {
@@ -926,7 +1083,8 @@ mlm_status mlm_map_noalloc(mlm_lens *lens, const mlm_map_request *req, double *m
     setup_region(lens, req, &R);
     const double need = 48.0 * (double)lens->n + 2.0 * 16.0 * (double)R.nr1 +
                         (req->device_out ? 0.0 : 8.0 * (double)req->n1 * (double)req->n2) +
-                        (band_height(req->n1, req->n2) <= 0 ? 8.0 * (double)req->n2 * (double)(req->n1 + 1) : 0.0);
+                        (band_height(req->n1, req->n2) <= 0 ? 8.0 * (double)req->n2 * (double)(req->n1 + 1) : 0.0) +
+                        (req->mapping == MLM_MAP_IRS ? 8.0 * (double)req->n1 * (double)req->n2 : 0.0);
     if (need > (double)SCRATCH_BYTES)
         fail(MLM_ERANGE, "the map needs at least %.0f MiB of scratch, more than the %zu MiB of mlm_map_noalloc",
              need / 1048576.0, SCRATCH_BYTES >> 20);
@@ -952,6 +1110,7 @@ mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, i
         if (!seen.insert(lenses[i]).second) fail(MLM_EINVAL, "map %d: every map of a batch needs its own lens", i);
         check_request(&q);
         if (q.method != MLM_METHOD_FMM) fail(MLM_EINVAL, "map %d: batched maps use the FMM", i);
+        if (q.mapping != MLM_MAP_IPM) fail(MLM_ENOTSUP, "map %d: batched maps use inverse polygon mapping", i);
         if (q.row_begin > 0 || q.row_end >= 0) fail(MLM_EINVAL, "map %d: batched maps cover all rows", i);
         if (q.w_out) fail(MLM_EINVAL, "map %d: batched maps have no w_out", i);
         if ((q.device_out != 0) != (reqs[0].device_out != 0)) fail(MLM_EINVAL, "map %d: device_out differs", i);

@@ -115,7 +115,8 @@ struct LensConst {
     double lam1, lam2;      // 1 - kappa + gamma, 1 - kappa - gamma
     double kappa_star;
     double r_star2;         // R_*^2
-    int32_t sheet;          // 1: circular compensating sheet
+    double c1, c2;          // corner of the star rectangle (rectangular sheet)
+    int32_t sheet;          // 0: none, 1: circular sheet, 2: rectangular sheet
     int32_t pad;
 };
 
@@ -131,12 +132,15 @@ struct BigPrep {
     double kc[3];
 };
 
-// ray-grid geometry of a shooting launch
+// ray-grid geometry of a shooting launch: points (x0 + (a + h) d1,
+// y0 + (b + h) d2), a < nr1, rows b from vb0 (h = 0: the grid's vertices;
+// h = 1/2: the centres of its cells, for inverse ray shooting)
 struct ShootArgs {
     double x0, y0, d1, d2;
     int64_t nr1, vb0;
     int p;
     int pad;
+    double h;
 };
 
 // map geometry for the IPM, in pixel units
@@ -214,7 +218,7 @@ struct Workspace {
     DevBuf ilist, mult, local, ops_m2m, ops_m2l, ops_l2l;
     DevBuf leaves, near, deriv, near_offs;
     DevBuf tile_off, tile_leaf, verts, map, wbuf, pts, counters, items, itemoff, tbig, tbigoff, bigprep, bigrows, bigrow0, rowoff, nbnd, nbndoff, diff, bandcnt, bandoff,
-        bandcur, bandlist, rfeat, rlogit, rflag, rpos, rcand, rlabel, rstats;
+        bandcur, bandlist, rfeat, rlogit, rflag, rpos, rcand, rlabel, rstats, irs_counts;
     void *pinned = nullptr;               // small pinned host buffer for read-backs
     size_t pinned_cap = 0;
     int ops_p = -1;                       // expansion order of the operator tables
@@ -229,6 +233,7 @@ struct mlm_lens {
     int device = 0;
     double *d_x = nullptr, *d_y = nullptr, *d_m = nullptr;
     double mass_sum = 0, mass2_sum = 0, max_abs = 0, r_star = 0;
+    double ext1 = 0, ext2 = 0;            // star region: (R_*, R_*) or the rectangle's (c1, c2)
     mlm::Workspace ws;
     std::mutex mu;
 };
@@ -253,6 +258,17 @@ namespace mlm {
 mlm_status setup_region(const mlm_lens *lens, const mlm_map_request *req, Region *R);
 int auto_order(double mean_m, double mean_m2, double L, double eps);
 
+// field.cpp (host arithmetic, compiled without floating-point contraction)
+void field_moments(const mlm_field_params &F, double &mean_m, double &mean_m2);
+int64_t field_count(const mlm_field_params &F);
+void field_extent(int shape, double kappa_star, double mass_sum, double aspect, double &e1, double &e2);
+int64_t field_sample(const mlm_field_params &F, std::vector<double> &x, std::vector<double> &y,
+                     std::vector<double> &m, double &e1, double &e2);
+// the shooting region's centre and half-sizes (sec. 2.3, app. A) for given
+// mass moments
+void shooting_region(const mlm_lens_params &P, double mean_m, double mean_m2, const mlm_map_request &q, double &X1,
+                     double &X2, double &dX1, double &dX2);
+
 // tree.hip
 void build_tree(mlm_lens *lens, const Region &R, const mlm_map_request &req, Tree &T,
                 hipStream_t st);
@@ -263,8 +279,18 @@ void build_leaf_tables(mlm_lens *lens, Tree &T, hipStream_t st);
 
 // shoot.hip
 LensConst lens_const(const mlm_lens *lens, const Region &R);
+// ray tiles of the grid vertices of rows [vb0, vb1), or (centres) of the
+// cell centres of cell rows [vb0, vb1)
 int64_t plan_tiles(mlm_lens *lens, Tree &T, const Region &R, int64_t vb0, int64_t vb1,
-                   hipStream_t st);
+                   hipStream_t st, bool centres = false);
+// inverse ray shooting of the cell centres of cell rows [cb0, cb1): counts
+// per pixel (n2 x n1) are added to `counts`
+void launch_shoot_irs(mlm_lens *lens, const Tree &T, const Region &R, const LensConst &lc, const MapGeom &g,
+                      int64_t ntiles, int64_t cb0, unsigned long long *counts, hipStream_t st);
+void launch_shoot_irs_direct(mlm_lens *lens, const Region &R, const LensConst &lc, const MapGeom &g, int64_t cb0,
+                             int64_t cb1, unsigned long long *counts, hipStream_t st);
+// map = counts * w
+void launch_irs_mu(const unsigned long long *counts, int64_t npix, double w, double *map, hipStream_t st);
 void launch_shoot(mlm_lens *lens, const Tree &T, const Region &R, const LensConst &lc,
                   const MapGeom &g, int64_t ntiles, int64_t vb0, double2 *verts, double *w_out,
                   hipStream_t st);
@@ -293,6 +319,9 @@ void launch_big_gather(const double2 *verts, int64_t nr1, int64_t cb0, int64_t c
 void launch_big(int64_t nbig, const BigPrep *prep, const int64_t *rows, const MapGeom &g, double *map, double *diff,
                 hipStream_t st);
 void launch_diff_rows(const MapGeom &g, const double *diff, double *map, hipStream_t st);
+// statistics: (triangle, pixel) pieces of cell rows [cb0, cb1) inside the map, added to *out
+void launch_count_pieces(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int64_t vb0, const MapGeom &g,
+                         unsigned long long *out, hipStream_t st);
 int band_height(int32_t n1, int32_t n2);
 void launch_band_count(int64_t nbig, const int32_t *row0, const int64_t *rows, int bh, int32_t nbands, int32_t *count,
                        hipStream_t st);

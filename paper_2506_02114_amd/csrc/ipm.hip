@@ -1241,6 +1241,67 @@ __global__ __launch_bounds__(64) void k_diff_rows(MapGeom g, const double *__res
     }
 }
 
+
+// Statistics only (maps with timing 2): the (triangle, pixel) pairs of cell
+// rows [cb0, cb0 + ncells / (nr1 - 1)) that meet inside the map -- the pieces
+// the apportioning deposits, whatever path a triangle takes.  The part of a
+// triangle inside one pixel row is a convex polygon spanning [umin, umax], so
+// it meets the columns floor(umin) .. ceil(umax) - 1 of that row.  A
+// zero-area triangle is one piece (its centroid's pixel); one with a
+// non-finite vertex none.
+__device__ inline int64_t tri_pieces(double2 A, double2 B, double2 C, const MapGeom &g)
+{
+    if (!isfinite(A.x) || !isfinite(A.y) || !isfinite(B.x) || !isfinite(B.y) || !isfinite(C.x) || !isfinite(C.y))
+        return 0;
+    const double s2 = (B.x - A.x) * (C.y - A.y) - (C.x - A.x) * (B.y - A.y);
+    if (s2 == 0.0) {
+        const double cu = floor((A.x + B.x + C.x) / 3.0), cv = floor((A.y + B.y + C.y) / 3.0);
+        return (cu >= 0.0 && cv >= 0.0 && cu < (double)g.n1 && cv < (double)g.n2) ? 1 : 0;
+    }
+    const double2 P[3] = {A, B, C};
+    const double vlo = fmin(A.y, fmin(B.y, C.y)), vhi = fmax(A.y, fmax(B.y, C.y));
+    const double j0 = fmax(floor(vlo), 0.0), j1 = fmin(ceil(vhi) - 1.0, (double)g.n2 - 1.0);
+    int64_t n = 0;
+    for (double j = j0; j <= j1; j += 1.0) {
+        double lo = INFINITY, hi = -INFINITY;
+        for (int k = 0; k < 3; ++k) {
+            const double2 p = P[k], q = P[(k + 1) % 3];
+            if (p.y >= j && p.y <= j + 1.0) {
+                lo = fmin(lo, p.x);
+                hi = fmax(hi, p.x);
+            }
+            for (int e = 0; e < 2; ++e) {   // crossings of v = j and v = j + 1
+                const double r = j + (double)e;
+                if ((p.y - r) * (q.y - r) < 0.0) {
+                    const double x = p.x + (r - p.y) * (q.x - p.x) / (q.y - p.y);
+                    lo = fmin(lo, x);
+                    hi = fmax(hi, x);
+                }
+            }
+        }
+        if (!(lo <= hi)) continue;
+        const double i0 = fmax(floor(lo), 0.0), i1 = fmin(ceil(hi) - 1.0, (double)g.n1 - 1.0);
+        if (i1 >= i0) n += (int64_t)(i1 - i0) + 1;
+    }
+    return n;
+}
+
+__global__ __launch_bounds__(256) void k_count_pieces(const double2 *__restrict__ verts, int64_t nr1, int64_t cb0,
+                                                      int64_t ncells, int64_t vb0, MapGeom g,
+                                                      unsigned long long *__restrict__ out)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long n = 0;
+    if (c < ncells) {
+        const int64_t a = c % (nr1 - 1), b = cb0 + c / (nr1 - 1);
+        const double2 *r0 = verts + (b - vb0) * nr1, *r1 = r0 + nr1;
+        n = (unsigned long long)(tri_pieces(r0[a], r0[a + 1], r1[a + 1], g) + tri_pieces(r0[a], r1[a + 1], r1[a], g));
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) n += __shfl_xor(n, o, 64);
+    if ((threadIdx.x & 63) == 0 && n) atomicAdd(out, n);
+}
+
 }  // namespace
 
 void launch_ipm(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int64_t vb0, const MapGeom &g,
@@ -1394,6 +1455,15 @@ void launch_band_batch(const BatchMap *maps, int32_t nmaps, int64_t nbands, cons
     if (nbands > 0)
         hipLaunchKernelGGL(k_band_batch, dim3((unsigned)nbands), dim3(BAND_THREADS), (size_t)lds_doubles * sizeof(double),
                            st, maps, nmaps, band_off, list, prep, rows);
+}
+
+void launch_count_pieces(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int64_t vb0, const MapGeom &g,
+                         unsigned long long *out, hipStream_t st)
+{
+    const int64_t ncells = (nr1 - 1) * (cb1 - cb0);
+    if (ncells > 0)
+        hipLaunchKernelGGL(k_count_pieces, dim3((unsigned)((ncells + 255) / 256)), dim3(256), 0, st, verts, nr1, cb0,
+                           ncells, vb0, g, out);
 }
 
 void launch_diff_rows(const MapGeom &g, const double *diff, double *map, hipStream_t st)

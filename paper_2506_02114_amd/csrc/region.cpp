@@ -18,6 +18,22 @@ namespace mlm {
  * is the smallest power of two above every star and ray coordinate, which
  * makes every square's centre and size exact binary fractions.
  */
+void shooting_region(const mlm_lens_params &P, double mean_m, double mean_m2, const mlm_map_request &q, double &X1,
+                     double &X2, double &dX1, double &dX2)
+{
+    const double kappa = P.kappa_star + P.kappa_smooth;
+    const double lam1 = 1.0 - kappa + P.gamma, lam2 = 1.0 - kappa - P.gamma;
+    if (std::fabs(lam1) < 1e-9 || std::fabs(lam2) < 1e-9)
+        fail(MLM_EDEGENERATE, "|1-kappa+-gamma| = (%g, %g): the shooting region is unbounded", std::fabs(lam1),
+             std::fabs(lam2));
+    const double f = q.flux_fraction > 0 ? q.flux_fraction : 0.01;
+    const double border = (mean_m > 0 && P.kappa_star > 0) ? std::sqrt(P.kappa_star * mean_m2 / (f * mean_m)) : 0.0;
+    X1 = q.y1c / lam1;
+    X2 = q.y2c / lam2;
+    dX1 = q.dx1 > 0 ? q.dx1 : (q.hw1 + border) / std::fabs(lam1);
+    dX2 = q.dx2 > 0 ? q.dx2 : (q.hw2 + border) / std::fabs(lam2);
+}
+
 mlm_status setup_region(const mlm_lens *lens, const mlm_map_request *q, Region *R)
 {
     if (!(q->hw1 > 0) || !(q->hw2 > 0) || !std::isfinite(q->hw1) || !std::isfinite(q->hw2) ||
@@ -31,21 +47,15 @@ mlm_status setup_region(const mlm_lens *lens, const mlm_map_request *q, Region *
     R->kappa = P.kappa_star + P.kappa_smooth;
     R->lam1 = 1.0 - R->kappa + P.gamma;
     R->lam2 = 1.0 - R->kappa - P.gamma;
-    if (std::fabs(R->lam1) < 1e-9 || std::fabs(R->lam2) < 1e-9)
-        fail(MLM_EDEGENERATE, "|1-kappa+-gamma| = (%g, %g): the shooting region is unbounded",
-             std::fabs(R->lam1), std::fabs(R->lam2));
     R->mu_macro = 1.0 / (R->lam1 * R->lam2);
 
+    // the sample moments of the lens's own stars
     int64_t n = lens->n;
     R->mean_m = n ? lens->mass_sum / (double)n : 0.0;
     R->mean_m2 = n ? lens->mass2_sum / (double)n : 0.0;
     double f = q->flux_fraction > 0 ? q->flux_fraction : 0.01;
     R->border = (n && P.kappa_star > 0) ? std::sqrt(P.kappa_star * R->mean_m2 / (f * R->mean_m)) : 0.0;
-
-    R->X1 = q->y1c / R->lam1;
-    R->X2 = q->y2c / R->lam2;
-    R->dX1 = q->dx1 > 0 ? q->dx1 : (q->hw1 + R->border) / std::fabs(R->lam1);
-    R->dX2 = q->dx2 > 0 ? q->dx2 : (q->hw2 + R->border) / std::fabs(R->lam2);
+    shooting_region(P, R->mean_m, R->mean_m2, *q, R->X1, R->X2, R->dX1, R->dX2);
     R->pix1 = 2.0 * q->hw1 / (double)q->n1;
     R->pix2 = 2.0 * q->hw2 / (double)q->n2;
 

@@ -20,23 +20,23 @@ namespace {
 constexpr int BLK = 256;
 inline unsigned nblocks(int64_t n, int b = BLK) { return (unsigned)((n + b - 1) / b); }
 
-// first a in [lo, hi) whose vertex lies in square index >= target at level lev
-__device__ inline int64_t first_in_cell(double x0, double d, int64_t lo, int64_t hi, double L0, double scale_lev,
-                                        int lev, int64_t target)
+// first a in [lo, hi) whose lattice point lies in square index >= target at level lev
+__device__ inline int64_t first_in_cell(double x0, double d, double h, int64_t lo, int64_t hi, double L0,
+                                        double scale_lev, int lev, int64_t target)
 {
     while (lo < hi) {
         int64_t mid = (lo + hi) >> 1;
-        if (level_cell(grid_pos(x0, d, mid), L0, scale_lev, lev) < target) lo = mid + 1;
+        if (level_cell(grid_pos(x0, d, mid, h), L0, scale_lev, lev) < target) lo = mid + 1;
         else hi = mid;
     }
     return lo;
 }
 
-// grid columns and rows (within vertex rows [vb0, vb1)) inside each leaf
+// lattice columns and rows (within rows [vb0, vb1)) inside each leaf
 __global__ void k_tile_counts(int64_t nleaves, const int32_t *__restrict__ leaf_node,
                               const uint64_t *__restrict__ code, const int32_t *__restrict__ level, double L0,
                               int L0_exp, double x0, double d1, int64_t nr1, double y0, double d2, int64_t vb0,
-                              int64_t vb1, LeafInfo *__restrict__ info, int32_t *__restrict__ cnt)
+                              int64_t vb1, double h, LeafInfo *__restrict__ info, int32_t *__restrict__ cnt)
 {
     int64_t lf = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (lf >= nleaves) return;
@@ -45,10 +45,10 @@ __global__ void k_tile_counts(int64_t nleaves, const int32_t *__restrict__ leaf_
     uint64_t c = code[q];
     int64_t i = compact_bits(c), j = compact_bits(c >> 1);
     double scale = ldexp(1.0, lev - L0_exp);   // 2^lev / (2 L0)
-    int64_t a0 = first_in_cell(x0, d1, 0, nr1, L0, scale, lev, i);
-    int64_t a1 = first_in_cell(x0, d1, a0, nr1, L0, scale, lev, i + 1);
-    int64_t b0 = first_in_cell(y0, d2, vb0, vb1, L0, scale, lev, j);
-    int64_t b1 = first_in_cell(y0, d2, b0, vb1, L0, scale, lev, j + 1);
+    int64_t a0 = first_in_cell(x0, d1, h, 0, nr1, L0, scale, lev, i);
+    int64_t a1 = first_in_cell(x0, d1, h, a0, nr1, L0, scale, lev, i + 1);
+    int64_t b0 = first_in_cell(y0, d2, h, vb0, vb1, L0, scale, lev, j);
+    int64_t b1 = first_in_cell(y0, d2, h, b0, vb1, L0, scale, lev, j + 1);
     LeafInfo &li = info[lf];
     li.a_lo = (int32_t)a0;
     li.na = (int32_t)(a1 - a0);
@@ -67,6 +67,55 @@ __global__ void k_tile_leaf(int64_t ntiles, int64_t nleaves, const int32_t *__re
     tile_leaf[t] = (int32_t)(upper_bound_i64<int32_t>(tile_off, nleaves, (int32_t)t) - 1);
 }
 
+
+// the lattice point of tile t's lane: its leaf and position, and whether it
+// exists (the tile may overhang the leaf's rectangle)
+struct TilePoint {
+    int32_t lf;
+    int64_t a, b;
+    double x, y;
+    bool valid;
+};
+
+__device__ inline TilePoint tile_point(const ShootArgs &sa, const int32_t *__restrict__ tile_leaf,
+                                       const int32_t *__restrict__ tile_off, const LeafInfo &li, int32_t lf,
+                                       int64_t t, int lane)
+{
+    const int32_t local = (int32_t)t - tile_off[lf];
+    const int32_t ty = local / li.ntx, tx = local - ty * li.ntx;
+    const int32_t ia = tx * TILE + (lane & (TILE - 1)), ib = ty * TILE + (lane >> 3);
+    TilePoint pt;
+    pt.lf = lf;
+    pt.valid = ia < li.na && ib < li.nb;
+    pt.a = li.a_lo + ia;
+    pt.b = li.b_lo + ib;
+    pt.x = grid_pos(sa.x0, sa.d1, pt.a, sa.h);
+    pt.y = grid_pos(sa.y0, sa.d2, pt.b, sa.h);
+    return pt;
+}
+
+// inverse ray shooting of tile t (one wavefront per 8 x 8 tile of cell
+// centres): every ray counted in its pixel
+template <class R>
+__global__ __launch_bounds__(64) void k_shoot_irs(ShootArgs sa, LensConst lc, MapGeom g,
+                                                  const int32_t *__restrict__ tile_leaf,
+                                                  const int32_t *__restrict__ tile_off,
+                                                  const LeafInfo *__restrict__ leaves,
+                                                  const double4 *__restrict__ near,
+                                                  const typename Cx<R>::c2 *__restrict__ deriv,
+                                                  unsigned long long *__restrict__ counts)
+{
+    const int64_t t = blockIdx.x;
+    const int32_t lf = tile_leaf[t];
+    const LeafInfo li = leaves[lf];
+    const TilePoint pt = tile_point(sa, tile_leaf, tile_off, li, lf, t, threadIdx.x);
+    double ax, ay;
+    leaf_alpha<R>(pt.x - li.cx, pt.y - li.cy, li, near + li.near_off, deriv + (int64_t)lf * sa.p, sa.p, ax, ay);
+    double w1, w2;
+    double2 uv;
+    finish_vertex(lc, g, pt.x, pt.y, ax, ay, w1, w2, uv);
+    irs_count(pt.valid, uv, g, counts);
+}
 
 // shoot tile t of a map (one 64-lane wavefront per 8 x 8 tile)
 template <class R>
@@ -117,7 +166,7 @@ __global__ __launch_bounds__(64) void k_shoot_batch(const BatchMap *__restrict__
         const int64_t t = blockIdx.x;
         const int32_t m = batch_find(maps, nmaps, t, &BatchMap::tile_lo);
         const BatchMap &d = maps[m];
-        const ShootArgs sa{d.x0, d.y0, d.d1, d.d2, d.nr1, 0, d.p, 0};
+        const ShootArgs sa{d.x0, d.y0, d.d1, d.d2, d.nr1, 0, d.p, 0, 0.0};
         if (d.mixed)
             shoot_tile<float>(sa, d.lc, d.g, d.tile_leaf, d.tile_off, d.leaves, d.near,
                               static_cast<const float2 *>(d.deriv), d.verts, nullptr, t - d.tile_lo, threadIdx.x);
@@ -128,17 +177,19 @@ __global__ __launch_bounds__(64) void k_shoot_batch(const BatchMap *__restrict__
 }
 
 // direct summation over every star (no FMM): one thread per vertex, stars
-// staged through LDS in tiles
+// staged through LDS in tiles; with counts, the points are the cell centres
+// and each is counted in its pixel (inverse ray shooting) instead of stored
 constexpr int DTILE = 256;
 __global__ __launch_bounds__(256) void k_shoot_direct(ShootArgs sa, LensConst lc, MapGeom g, int64_t nverts,
                                                       const double *__restrict__ sx, const double *__restrict__ sy,
                                                       const double *__restrict__ sm, int32_t n,
-                                                      double2 *__restrict__ verts, double2 *__restrict__ w_out)
+                                                      double2 *__restrict__ verts, double2 *__restrict__ w_out,
+                                                      unsigned long long *__restrict__ counts)
 {
     __shared__ double3 tile[DTILE];
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t a = v % sa.nr1, b = sa.vb0 + v / sa.nr1;
-    double x = grid_pos(sa.x0, sa.d1, a), y = grid_pos(sa.y0, sa.d2, b);
+    double x = grid_pos(sa.x0, sa.d1, a, sa.h), y = grid_pos(sa.y0, sa.d2, b, sa.h);
     double ax = 0.0, ay = 0.0;
     for (int32_t s0 = 0; s0 < n; s0 += DTILE) {
         int32_t s = s0 + threadIdx.x;
@@ -154,12 +205,23 @@ __global__ __launch_bounds__(256) void k_shoot_direct(ShootArgs sa, LensConst lc
             ay += f * ey;
         }
     }
-    if (v >= nverts) return;
     double w1, w2;
     double2 uv;
     finish_vertex(lc, g, x, y, ax, ay, w1, w2, uv);
+    if (counts) {
+        irs_count(v < nverts, uv, g, counts);
+        return;
+    }
+    if (v >= nverts) return;
     verts[v] = uv;
     if (w_out) w_out[v] = make_double2(w1, w2);
+}
+
+__global__ void k_irs_mu(const unsigned long long *__restrict__ counts, int64_t npix, double w,
+                         double *__restrict__ map)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < npix) map[k] = (double)counts[k] * w;
 }
 
 // w at arbitrary points: leaf by descending the levels, then as k_shoot
@@ -218,23 +280,27 @@ LensConst lens_const(const mlm_lens *lens, const Region &R)
     lc.lam2 = R.lam2;
     lc.kappa_star = lens->params.kappa_star;
     lc.r_star2 = lens->r_star * lens->r_star;
-    lc.sheet = lens->params.sheet == MLM_SHEET_CIRCLE ? 1 : 0;
+    lc.c1 = lens->ext1;
+    lc.c2 = lens->ext2;
+    lc.sheet = lens->n == 0 ? 0 : lens->params.sheet == MLM_SHEET_CIRCLE ? 1 : lens->params.sheet == MLM_SHEET_RECT ? 2 : 0;
     lc.pad = 0;
     return lc;
 }
 
-int64_t plan_tiles(mlm_lens *lens, Tree &T, const Region &R, int64_t vb0, int64_t vb1, hipStream_t st)
+int64_t plan_tiles(mlm_lens *lens, Tree &T, const Region &R, int64_t vb0, int64_t vb1, hipStream_t st, bool centres)
 {
     Workspace &ws = lens->ws;
     int64_t nl = T.nleaves;
-    // every vertex lies in exactly one leaf and every tile holds at least one
-    // vertex, so the tiles number at most the vertices: bounding those keeps
-    // the int32 counts and their scan from overflowing
-    if ((vb1 - vb0) * R.nr1 > (int64_t)INT32_MAX) fail(MLM_ERANGE, "more than 2^31 vertices in one shooting plan");
+    const int64_t ncols = centres ? R.nr1 - 1 : R.nr1;
+    const double h = centres ? 0.5 : 0.0;
+    // every lattice point lies in exactly one leaf and every tile holds at
+    // least one point, so the tiles number at most the points: bounding those
+    // keeps the int32 counts and their scan from overflowing
+    if ((vb1 - vb0) * ncols > (int64_t)INT32_MAX) fail(MLM_ERANGE, "more than 2^31 rays in one shooting plan");
     int32_t *cnt = static_cast<int32_t *>(ws.flags.reserve(nl * 4));
     int32_t *off = static_cast<int32_t *>(ws.tile_off.reserve(nl * 4));
     hipLaunchKernelGGL(k_tile_counts, dim3(nblocks(nl)), dim3(BLK), 0, st, nl, T.leaf_node, T.code, T.level, T.L0,
-                       T.L0_exp, R.x0, R.d1, R.nr1, R.y0, R.d2, vb0, vb1, T.leaves, cnt);
+                       T.L0_exp, R.x0, R.d1, ncols, R.y0, R.d2, vb0, vb1, h, T.leaves, cnt);
     int64_t ntiles = scan_total_public(lens, cnt, off, nl, st);
     if (ntiles > 0) {
         int32_t *tl = static_cast<int32_t *>(ws.tile_leaf.reserve(ntiles * 4));
@@ -248,7 +314,7 @@ void launch_shoot(mlm_lens *lens, const Tree &T, const Region &R, const LensCons
 {
     if (ntiles <= 0) return;
     Workspace &ws = lens->ws;
-    ShootArgs sa{R.x0, R.y0, R.d1, R.d2, R.nr1, vb0, T.p, 0};
+    ShootArgs sa{R.x0, R.y0, R.d1, R.d2, R.nr1, vb0, T.p, 0, 0.0};
     if (T.mixed)
         hipLaunchKernelGGL(k_shoot<float>, dim3((unsigned)ntiles), dim3(64), 0, st, sa, lc, g,
                            ws.tile_leaf.as<int32_t>(), ws.tile_off.as<int32_t>(), T.leaves, T.near, T.deriv_f, verts,
@@ -264,9 +330,38 @@ void launch_shoot_direct(mlm_lens *lens, const Region &R, const LensConst &lc, c
 {
     int64_t nv = (vb1 - vb0) * R.nr1;
     if (nv <= 0) return;
-    ShootArgs sa{R.x0, R.y0, R.d1, R.d2, R.nr1, vb0, 0, 0};
+    ShootArgs sa{R.x0, R.y0, R.d1, R.d2, R.nr1, vb0, 0, 0, 0.0};
     hipLaunchKernelGGL(k_shoot_direct, dim3(nblocks(nv)), dim3(256), 0, st, sa, lc, g, nv, lens->d_x, lens->d_y,
-                       lens->d_m, (int32_t)lens->n, verts, reinterpret_cast<double2 *>(w_out));
+                       lens->d_m, (int32_t)lens->n, verts, reinterpret_cast<double2 *>(w_out), nullptr);
+}
+
+void launch_shoot_irs(mlm_lens *lens, const Tree &T, const Region &R, const LensConst &lc, const MapGeom &g,
+                      int64_t ntiles, int64_t cb0, unsigned long long *counts, hipStream_t st)
+{
+    if (ntiles <= 0) return;
+    Workspace &ws = lens->ws;
+    ShootArgs sa{R.x0, R.y0, R.d1, R.d2, R.nr1 - 1, cb0, T.p, 0, 0.5};
+    if (T.mixed)
+        hipLaunchKernelGGL(k_shoot_irs<float>, dim3((unsigned)ntiles), dim3(64), 0, st, sa, lc, g,
+                           ws.tile_leaf.as<int32_t>(), ws.tile_off.as<int32_t>(), T.leaves, T.near, T.deriv_f, counts);
+    else
+        hipLaunchKernelGGL(k_shoot_irs<double>, dim3((unsigned)ntiles), dim3(64), 0, st, sa, lc, g,
+                           ws.tile_leaf.as<int32_t>(), ws.tile_off.as<int32_t>(), T.leaves, T.near, T.deriv, counts);
+}
+
+void launch_shoot_irs_direct(mlm_lens *lens, const Region &R, const LensConst &lc, const MapGeom &g, int64_t cb0,
+                             int64_t cb1, unsigned long long *counts, hipStream_t st)
+{
+    const int64_t nv = (cb1 - cb0) * (R.nr1 - 1);
+    if (nv <= 0) return;
+    ShootArgs sa{R.x0, R.y0, R.d1, R.d2, R.nr1 - 1, cb0, 0, 0, 0.5};
+    hipLaunchKernelGGL(k_shoot_direct, dim3(nblocks(nv)), dim3(256), 0, st, sa, lc, g, nv, lens->d_x, lens->d_y,
+                       lens->d_m, (int32_t)lens->n, nullptr, nullptr, counts);
+}
+
+void launch_irs_mu(const unsigned long long *counts, int64_t npix, double w, double *map, hipStream_t st)
+{
+    if (npix > 0) hipLaunchKernelGGL(k_irs_mu, dim3(nblocks(npix)), dim3(BLK), 0, st, counts, npix, w, map);
 }
 
 void launch_shoot_batch(const BatchMap *maps, int32_t nmaps, int64_t ntiles, hipStream_t st)

@@ -14,6 +14,34 @@ __device__ inline double grid_pos(double x0, double d, int64_t a)
     return x0 + (double)a * d;
 }
 
+// point a of a lattice offset by h cells: x0 + (a + h) d (h = 0: the grid's
+// vertices, the same value as grid_pos; h = 1/2: the centres of its cells)
+__device__ inline double grid_pos(double x0, double d, int64_t a, double h)
+{
+#pragma clang fp contract(off)
+    return x0 + ((double)a + h) * d;
+}
+
+// Inverse ray shooting: a ray landing at uv (pixel units) counts once in the
+// pixel (floor u, floor v) if that lies in the map.  Lanes of a wavefront
+// that land in the same pixel are added together first (one device atomic
+// per distinct pixel: neighbouring rays mostly share a pixel).
+__device__ inline void irs_count(bool valid, double2 uv, const MapGeom &g, unsigned long long *__restrict__ counts)
+{
+    const double fu = floor(uv.x), fv = floor(uv.y);
+    const bool in = valid && fu >= 0.0 && fv >= 0.0 && fu < (double)g.n1 && fv < (double)g.n2;
+    const long long key = in ? (long long)fv * g.n1 + (long long)fu : -1;
+    const int lane = threadIdx.x & 63;
+    unsigned long long active = __ballot(in);
+    while (active) {
+        const int leader = __ffsll(active) - 1;
+        const long long lk = __shfl(key, leader, 64);
+        const unsigned long long same = __ballot(key == lk);
+        if (lane == leader) atomicAdd(counts + lk, (unsigned long long)__popcll(same));
+        active &= ~same;
+    }
+}
+
 // square index of t at level lev (root [-L0, L0)), clamped like the star keys
 __device__ inline int64_t level_cell(double t, double L0, double scale_lev, int lev)
 {
@@ -23,18 +51,52 @@ __device__ inline int64_t level_cell(double t, double L0, double scale_lev, int 
     return (int64_t)u;
 }
 
+// t log t for t = (a, b), principal branch (cut along the negative real axis)
+__device__ inline double2 t_log_t(double a, double b)
+{
+    const double lr = 0.5 * log(a * a + b * b), th = atan2(b, a);
+    return make_double2(a * lr - b * th, b * lr + a * th);
+}
+
+// deflection of a sheet of convergence -k_* over the rectangle
+// [-c1, c1] x [-c2, c2] (app. B): with c = c1 + i c2,
+//   a_s = (-k_* i / pi) [ (c - zb) log(c - zb) - (cb - zb) log(cb - zb)
+//                         + (-c - zb) log(-c - zb) - (-cb - zb) log(-cb - zb) ]
+//         - k_* (2 c1 + 2 x)  inside the rectangle
+//         - k_* 4 c1          for x >= c1, |y| <= c2
+// (the last two undo the branch cuts the logarithms cross)
+__device__ inline void rect_sheet(double x, double y, double ks, double c1, double c2, double &ax, double &ay)
+{
+    const double2 t1 = t_log_t(c1 - x, c2 + y);     // c - zb
+    const double2 t2 = t_log_t(c1 - x, y - c2);     // cb - zb
+    const double2 t3 = t_log_t(-c1 - x, y - c2);    // -c - zb
+    const double2 t4 = t_log_t(-c1 - x, c2 + y);    // -cb - zb
+    const double sr = t1.x - t2.x + t3.x - t4.x, si = t1.y - t2.y + t3.y - t4.y;
+    const double k = ks * (1.0 / M_PI);
+    ax = k * si;
+    ay = -k * sr;
+    const bool in_band = fabs(y) <= c2;
+    if (in_band && fabs(x) <= c1) ax -= ks * (2.0 * c1 + 2.0 * x);
+    if (in_band && x >= c1) ax -= ks * (4.0 * c1);
+}
+
 __device__ inline void finish_vertex(const LensConst &lc, const MapGeom &g, double x, double y, double ax,
                                      double ay, double &w1, double &w2, double2 &uv)
 {
     // macro model
     w1 = lc.lam1 * x - ax;
     w2 = lc.lam2 * y - ay;
-    // compensating sheet: a_s = -k_* z inside R_*, -k_* R_*^2 / conj(z) outside
-    if (lc.sheet) {
+    if (lc.sheet == 1) {
+        // circular sheet: a_s = -k_* z inside R_*, -k_* R_*^2 / conj(z) outside
         double r2 = x * x + y * y;
         double f = (r2 <= lc.r_star2) ? lc.kappa_star : lc.kappa_star * lc.r_star2 / r2;
         w1 += f * x;
         w2 += f * y;
+    } else if (lc.sheet == 2) {
+        double sx, sy;
+        rect_sheet(x, y, lc.kappa_star, lc.c1, lc.c2, sx, sy);
+        w1 -= sx;
+        w2 -= sy;
     }
     uv = make_double2((w1 - g.ylo1) / g.pix1, (w2 - g.ylo2) / g.pix2);
 }

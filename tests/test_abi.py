@@ -44,7 +44,7 @@ def test_struct_layouts_match_header(mlm):
                "mlm_map_request": mlm.MapRequest, "mlm_region": mlm.Region,
                "mlm_map_stats": mlm.MapStats, "mlm_tree_info": mlm.TreeInfo,
                "mlm_batch_opts": mlm.BatchOpts, "mlm_batch_stats": mlm.BatchStats,
-               "mlm_train_opts": mlm.TrainOpts}
+               "mlm_train_opts": mlm.TrainOpts, "mlm_field_params": mlm.FieldParams}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mlmap.h"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -70,7 +70,7 @@ def test_struct_layouts_match_header(mlm):
 
 def test_version_and_status_strings(mlm):
     lib = mlm.load()
-    assert lib.mlm_abi_version() == 4
+    assert lib.mlm_abi_version() == 5
     assert lib.mlm_status_str(0) == b"MLM_OK"
     assert lib.mlm_status_str(2) == b"MLM_EDEGENERATE"
     assert lib.mlm_status_str(99) == b"MLM_UNKNOWN"

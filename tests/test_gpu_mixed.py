@@ -1,27 +1,30 @@
-"""Mixed-precision mode (FP32 expansions, near field, Taylor evaluation and
-column pass; FP64 positions, offsets, macro model, thin triangles, row bands
-and pixel sums) against the FP64 oracle (needs an MI355X).
+"""Mixed-precision mode against the FP64 oracle and the FP64 map (needs an
+MI355X).  In this mode the near field, the Taylor series' variation across a
+leaf (its l >= 1 terms in the leaf's coordinate) and the column pass of
+well-conditioned triangles run in FP32; the FMM coefficients, each leaf's
+far field at its centre, positions, offsets, the macro model, the sheet,
+thin triangles, the row bands and every pixel sum stay FP64.
 
 The paper gives no error bound for its single-precision mode (sec. 5 reports
-that it degrades near caustics), so the bounds here follow from FP32's unit
-round-off u = 2^-24 and the structure of each sum:
-  * coefficients: each of the <= 25 translations adds ~(p + 1) products of
-    bounded terms, so 1e-5 of the node's largest coefficient;
-  * deflection (|da| / max(|a|, theta_*)): the Taylor coefficients pass
-    through up to 16 levels of translations, each adding ~(p + 1) u of the
-    field's magnitude (p <= 31), then a degree-p Horner and <= 60 near-star
-    terms of relative error ~3u with offsets exact to FP64: about 5e-5, so
-    1e-4;
-  * maps: FP32 translation chains leave the Taylor coefficients with an
-    absolute error of ~64 u times the field they carry, whose size is that
-    of the star disc's field across the region, |a|max ~ kappa_* |z|max + 1;
-    mapped vertices move by dw ~ 64 u |a|max, and a pixel's magnification by
-    at most ~4 dw / pix relative (four pixel sides crossed by displaced
-    edges).  That is the per-pixel bound `_map_bound`; the median pixel, fed
-    by vertices moved by the median error, stays 100 times below it.  These
-    are the errors the single-precision mode is stated with (the paper finds
-    it degrades, sec. 5); they are not the FP64 mode's 1e-4.
-Measured values go to gpurun_out/parity_report_mixed.json.
+that it degrades near caustics).  The bounds here follow from FP32's unit
+round-off u = 2^-24 and the size of what FP32 carries:
+  * a vertex moves by delta <= ~10 u S / pix pixels, S = sum over its near
+    stars of m / r plus sum_l |d_l| 2^(l/2) of its leaf's Taylor variation
+    (a few to a few tens of theta_*): delta ~ 1e-6 px typically, up to
+    ~1e-4 px for rays grazing a star;
+  * a pixel away from caustics changes by at most ~4 delta relative (its
+    four sides, each crossed by displaced cell edges): so the median pixel
+    sits near 1e-6 and the p99.9 below the benchmark spec's 1e-4, which is
+    asserted; the median is held to 1e-5;
+  * caustic pixels amplify delta by their magnification gradient (the
+    paper's sec. 5 observation), so the maximum is stated and only bounded
+    loosely: 1e-3 on the two plain maps, 1e-2 on the high-magnification one
+    (mu_macro ~ -1168).
+A regression that puts the field's magnitude back into FP32 (about
+kappa_* |z| ~ 100, i.e. ~1e-5 theta_* of absolute error) fails all three.
+The coefficients are FP64 in both modes, so they match the oracle's like the
+FP64 mode's (1e-11).  Measured values go to
+gpurun_out/parity_report_mixed.json.
 """
 import json
 import os
@@ -64,12 +67,16 @@ def _alpha_from_w(ol, orc, zx, zy, wx, wy):
     return mx - wx, my - wy
 
 
-U32 = 2.0 ** -24
+P999_BOUND = 1e-4      # the per-pixel target, at the 99.9th percentile
+MEDIAN_BOUND = 1e-5
+MAX_BOUND_PLAIN = 1e-3
+MAX_BOUND_HIGHMAG = 1e-2
 
 
-def _map_bound(kappa_star, R):
-    zmax = np.hypot(R.dX1 + abs(R.X1), R.dX2 + abs(R.X2))
-    return 4.0 * 64.0 * U32 * (kappa_star * zmax + 1.0) / min(R.pix1, R.pix2)
+def _assert_map(rel, max_bound, what):
+    assert np.quantile(rel, 0.999) < P999_BOUND, what
+    assert np.median(rel) < MEDIAN_BOUND, what
+    assert rel.max() < max_bound, what
 
 
 def test_mixed_coefficients(mlm, orc):
@@ -95,7 +102,7 @@ def test_mixed_coefficients(mlm, orc):
     ea = np.abs(ex["mult"] - oa) / sa
     ec = np.abs(ex["local"][:, 1:] - oc[:, 1:]) / sc
     _report("coeffs_plain_small", max_mult=float(ea.max()), max_local=float(ec.max()))
-    assert ea.max() < 1e-5 and ec.max() < 1e-5
+    assert ea.max() < 1e-11 and ec.max() < 1e-11
 
 
 def test_mixed_deflection(mlm, orc):
@@ -117,7 +124,9 @@ def test_mixed_deflection(mlm, orc):
     e = np.abs((gx - ax) + 1j * (gy - ay)) / np.maximum(np.abs(ax + 1j * ay), 1.0)
     _report("deflect_plain_small_p20", vs_direct_max=float(e.max()), p999=float(np.quantile(e, 0.999)),
             median=float(np.median(e)))
-    assert e.max() < 1e-4
+    # the FP32 parts carry at most a few tens of theta_* (relative error
+    # ~10 u of that), and the order-20 truncation adds ~1e-8
+    assert e.max() < 1e-5
 
 
 def test_mixed_map_small(mlm, orc):
@@ -129,11 +138,10 @@ def test_mixed_map_small(mlm, orc):
     ref = orc.magnification_map(ol, spec, method="fmm", p=20)
     pos = ref.mu > 0
     rel = np.abs(mu[pos] - ref.mu[pos]) / ref.mu[pos]
-    bound = _map_bound(0.3, ref.region)
     _report("map_plain_small", max=float(rel.max()), p999=float(np.quantile(rel, 0.999)),
-            median=float(np.median(rel)), bound=bound)
+            median=float(np.median(rel)))
     assert np.all(np.abs(mu[~pos]) < 1e-12)
-    assert rel.max() < bound and np.median(rel) < bound / 100
+    _assert_map(rel, MAX_BOUND_PLAIN, "plain_small vs oracle")
 
 
 def test_mixed_map_full_size(mlm, orc):
@@ -161,13 +169,15 @@ def test_mixed_map_full_size(mlm, orc):
     got = mu.ravel()[gold["index"]]
     rel = np.abs(got - ref) / ref
     m64 = ref64.cpu().numpy()
-    rel64 = np.abs(mu - m64) / m64
+    pos64 = m64 > 0
+    assert np.all(mu[~pos64] == 0)
+    rel64 = np.abs(mu[pos64] - m64[pos64]) / m64[pos64]
     _report("map_plain_large", vs_oracle_max=float(rel.max()), vs_oracle_p999=float(np.quantile(rel, 0.999)),
             vs_oracle_median=float(np.median(rel)), vs_fp64_whole_map_max=float(rel64.max()),
+            vs_fp64_whole_map_p999=float(np.quantile(rel64, 0.999)),
             vs_fp64_whole_map_median=float(np.median(rel64)), ms_fp64=t["fp64"], ms_mixed=t["mixed"])
-    R = orc.region(orc.Lens(0.45, 0.0, 0.45, sf.x, sf.y, sf.m), **spec)
-    bound = _map_bound(0.45, R)
-    assert rel.max() < bound and np.median(rel) < bound / 100
+    _assert_map(rel, MAX_BOUND_PLAIN, "plain_large stored pixels vs oracle")
+    _assert_map(rel64, MAX_BOUND_PLAIN, "plain_large whole map vs FP64")
 
 
 def test_mixed_high_magnification_map(mlm, orc):
@@ -201,8 +211,9 @@ def test_mixed_high_magnification_map(mlm, orc):
             median=float(np.median(rel)), mean_mu_fp64=float(b.mean()), mean_mu_mixed=float(a.mean()),
             ms_fp64=s64["t_total_ms"], ms_mixed=s32["t_total_ms"], rays=s64["n_rays"], order=s64["order"])
     # the paper's observation (sec. 5): single precision degrades at high
-    # magnification; the error is stated, the bound only catches breakage
-    assert abs(a.mean() - b.mean()) < 1e-3 * b.mean() and np.median(rel) < 1e-3
+    # magnification; here the caustic pixels are the maximum
+    assert abs(a.mean() - b.mean()) < 1e-6 * b.mean()
+    _assert_map(rel, MAX_BOUND_HIGHMAG, "high-magnification map vs FP64")
     # sampled rays of both modes against the exact direct sum
     rng = np.random.default_rng(33)
     ns = 4000
@@ -215,7 +226,7 @@ def test_mixed_high_magnification_map(mlm, orc):
         gx, gy = _alpha_from_w(ol, orc, zx, zy, w[:, 0], w[:, 1])
         errs[prec] = float((np.abs((gx - ax) + 1j * (gy - ay)) / np.maximum(np.abs(ax + 1j * ay), 1.0)).max())
     _report("deflect_high_magnification_vs_direct", fp64=errs["fp64"], mixed=errs["mixed"], n=ns)
-    assert errs["fp64"] < 1e-6 and errs["mixed"] < 1e-4
+    assert errs["fp64"] < 1e-6 and errs["mixed"] < 1e-5
     # the FP64 map's middle strip against the oracle (pixels below 1e-6 of a
     # partial map held to an absolute bound, as for the 1e5-star strip)
     r0 = R.nr2 // 2 - 2

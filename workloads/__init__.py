@@ -32,7 +32,7 @@ import numpy as np
 
 __all__ = [
     "StarField", "MapSpec", "LensSpec", "sample_masses", "sample_disc",
-    "star_field", "config", "CONFIGS", "batch_draws",
+    "star_field", "rect_field", "config", "CONFIGS", "batch_draws", "paper_table1",
 ]
 
 SALPETER_SLOPE = 2.35
@@ -182,6 +182,44 @@ def config(name: str) -> Workload:
 
 
 CONFIGS = ("plain_small", "plain_large", "mixed_highmag")
+
+
+def paper_table1(shape: str = "circle", seed: int = 1):
+    """The paper's Table 1 map as far as the paper fixes it: kappa =
+    kappa_* = gamma = 0.6 (its sec. 4.1 comparison lens), equal masses, a
+    20 x 20 theta_* map of 2000 x 2000 px, 1 ray per pixel for IPM (100 for
+    IRS), flux fraction 1/1000 (its default).  The star region covers the
+    shooting rectangle (|X1| + dX1, |X2| + dX2) with a 1.2 margin: a disc
+    (about 26 700 stars; the paper says ~27 000) or the rectangle (about
+    6 500; the paper says ~3 000 without stating its margin).  Returns
+    (lens spec, map spec, rect_aspect)."""
+    kappa = gamma = 0.6
+    f = 1e-3
+    r = math.sqrt(kappa / f)                      # equal masses: <m^2>/<m> = 1
+    dx1, dx2 = (10.0 + r) / abs(1 - kappa + gamma), (10.0 + r) / abs(1 - kappa - gamma)
+    if shape == "circle":
+        n = int(round(kappa * (1.2 * math.hypot(dx1, dx2)) ** 2))
+        aspect = 0.0
+    else:
+        n = int(round(kappa * 4 * (1.2 * dx1) * (1.2 * dx2) / math.pi))
+        aspect = dx2 / dx1
+    lens = LensSpec(kappa, 0.0, gamma, n, "equal", seed=seed)
+    spec = MapSpec(hw1=10.0, hw2=10.0, n1=2000, n2=2000, rays_per_pixel=1.0, flux_fraction=f)
+    return lens, spec, aspect
+
+
+def rect_field(n: int, kappa_star: float, aspect: float, mass_fn: str = "equal", seed: int = 0,
+               m_lo: float = 0.1, m_hi: float = 1.0, m_equal: float = 1.0) -> StarField:
+    """N stars uniform in the rectangle [-c1, c1] x [-c2, c2], c2 = aspect c1,
+    whose area 4 c1 c2 = pi sum(m) / kappa_* realises kappa_* exactly (sec.
+    2.1); `radius` holds c1."""
+    rng = np.random.default_rng(seed)
+    m = sample_masses(rng, n, mass_fn, m_lo, m_hi, m_equal)
+    c1 = math.sqrt(math.pi * float(m.sum()) / (4.0 * kappa_star * aspect))
+    c2 = aspect * c1
+    x = c1 * (2.0 * rng.random(n) - 1.0)
+    y = c2 * (2.0 * rng.random(n) - 1.0)
+    return StarField(np.ascontiguousarray(x), np.ascontiguousarray(y), np.ascontiguousarray(m), c1)
 
 
 def batch_draws(n_maps: int = 256, seed: int = 4, min_macro_eig: float = 0.05):
