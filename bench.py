@@ -8,9 +8,14 @@ the map left in device memory.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-variants]
 
-Beside the headline, `variants` reports the same map in mixed precision, the
-256-map batched workload (one fused call against 256 single calls), and the
-paper's Table 1 map (context: the paper's time is for other hardware).
+Beside the headline, `variants` reports the same map in mixed precision
+(with its per-pixel error against FP64), the 256-map batched workload (one
+fused call against 256 single calls, and their differences), the paper's
+Table 1 maps (IPM and IRS, circular and rectangular star regions; context:
+the paper's times are for other hardware) and the high-magnification
+workload in FP64 and mixed precision.  `cpu_baseline` times the oracle on the
+host and states the FMM's method-level error on a strip of the map against
+the exact direct sum.
 """
 from __future__ import annotations
 
@@ -77,6 +82,17 @@ def cells_flops(stats: dict) -> float:
             + 29.0 * stats["n_col_pieces"])
 
 
+def rel_errors(a, b) -> dict:
+    """max, p99.9 and median of |a - b| / b over the pixels with b > 0 (torch
+    tensors on the device), and whether the rest agree exactly."""
+    import torch
+    pos = b > 0
+    d = ((a[pos] - b[pos]).abs() / b[pos]).double()
+    q = torch.quantile(d[torch.randperm(d.numel(), device=d.device)[:1 << 24]], 0.999) if d.numel() else d.sum()
+    return {"max": float(d.max()), "p999": float(q), "median": float(d.median()),
+            "zero_pixels_agree": bool((a[~pos] == b[~pos]).all())}
+
+
 def mixed_variant(lens, spec, out, ref) -> dict:
     """The same map in the mixed-precision mode: time per map and its
     per-pixel difference from the FP64 map just made (`ref`)."""
@@ -87,15 +103,52 @@ def mixed_variant(lens, spec, out, ref) -> dict:
     for _ in range(3):
         _, s = lens.map(out=out, precision="mixed", timing=1, **spec)
         ts.append(s["t_total_ms"])
-    d = ((out - ref).abs() / ref.clamp_min(1e-300))
-    return {"ms_per_map": sum(ts) / len(ts), "rays_per_s": s["n_rays"] / (sum(ts) / len(ts) * 1e-3),
-            "max_rel_vs_fp64": float(d.max()), "median_rel_vs_fp64": float(d.median())}
+    ms = sum(ts) / len(ts)
+    return {"ms_per_map": ms, "rays_per_s": s["n_rays"] / (ms * 1e-3), "maps_per_hour": 3600.0 / (ms * 1e-3),
+            "vs_fp64": rel_errors(out, ref)}
+
+
+def highmag_variant() -> dict:
+    """The high-magnification workload (1e6 Salpeter stars, kappa_* = 0.01,
+    kappa_s = 0.82, gamma = 0.1725, 4000^2 px of half-width 10, 1 ray per
+    pixel: 2.1e10 rays) in FP64 and mixed precision, with the mixed map's
+    per-pixel error against the FP64 map."""
+    import torch
+    import paper_2506_02114_amd as mlm
+    import workloads as W
+    wl = W.config("mixed_highmag")
+    sf = wl.stars()
+    L = wl.lens
+    dev = torch.device("cuda:0")
+    lens = mlm.Lens(L.kappa_star, L.kappa_smooth, L.gamma, torch.from_numpy(sf.x).to(dev),
+                    torch.from_numpy(sf.y).to(dev), torch.from_numpy(sf.m).to(dev))
+    spec = wl.map.asdict()
+    m64 = torch.empty((spec["n2"], spec["n1"]), dtype=torch.float64, device=dev)
+    m32 = torch.empty_like(m64)
+    out = {}
+    for prec, m in (("fp64", m64), ("mixed", m32)):
+        _, s = lens.map(out=m, precision=prec, timing=1, **spec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, s = lens.map(out=m, precision=prec, timing=1, **spec)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        out[prec] = {"s_per_map": sec, "rays_per_s": s["n_rays"] / sec, "maps_per_hour": 3600.0 / sec,
+                     "stages_ms": {"tree": s["t_tree_ms"], "fmm": s["t_fmm_ms"], "shoot": s["t_shoot_ms"],
+                                   "ipm": s["t_ipm_ms"]}}
+        print(f"[bench] high magnification {prec}: {sec:.3f} s", file=sys.stderr, flush=True)
+    out["rays"] = s["n_rays"]
+    out["order"] = s["order"]
+    out["mixed_vs_fp64"] = rel_errors(m32, m64)
+    return out
 
 
 def batched_variant() -> dict:
     """The 256-map batched workload (seed 4; kappa, gamma, s and star counts
     drawn; 1000^2 px, mixed precision): one fused batch call (leaf sizes from
-    the autotuner, cached after a first call) against 256 single-map calls."""
+    the autotuner, cached after a first call) against 256 single-map calls,
+    with the largest difference between the fused and the single maps, and
+    one batched (mixed) map against an FP64 map of the same lens."""
     import torch
     import paper_2506_02114_amd as mlm
     import workloads as W
@@ -115,50 +168,70 @@ def batched_variant() -> dict:
     _, b = mlm.map_batch(lenses, reqs, outs, autotune=True)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
+    fused = [o.clone() for o in outs]
     t0 = time.perf_counter()
     for lens, r, o in zip(lenses, reqs, outs):
         lens.map(out=o, **r)
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
+    worst = 0.0
+    for f, o in zip(fused, outs):
+        pos = o > 0
+        worst = max(worst, float(((f[pos] - o[pos]).abs() / o[pos]).max()) if bool(pos.any()) else 0.0)
+        assert bool((f[~pos] == 0).all())
+    # the largest map of the batch, batched in mixed precision, against FP64
+    k = max(range(256), key=lambda i: lenses[i].n)
+    ref = torch.empty_like(outs[k])
+    lenses[k].map(out=ref, **dict(reqs[k], precision="fp64"))
+    torch.cuda.synchronize()
     print("[bench] batched: done", file=sys.stderr, flush=True)
     return {"maps": 256, "rays": b["n_rays"], "s_per_batch": t_batch, "rays_per_s": b["n_rays"] / t_batch,
             "maps_per_hour": 256 * 3600.0 / t_batch, "s_256_single_calls": t_seq, "chunks": b["n_chunks"],
-            "stage_ms": {"prep": b["t_prep_ms"], "shoot": b["t_shoot_ms"], "ipm": b["t_ipm_ms"]}}
+            "stage_ms": {"prep": b["t_prep_ms"], "shoot": b["t_shoot_ms"], "ipm": b["t_ipm_ms"]},
+            "fused_vs_single_max_rel": worst,
+            "largest_map_mixed_vs_fp64": dict(rel_errors(fused[k], ref), stars=lenses[k].n)}
 
 
 def paper_table1_variant() -> dict:
-    """The paper's Table 1 map (IPM + FMM, circular star region), as far as
-    the paper fixes it: kappa = kappa_* = gamma = 0.6 (its sec. 4.1
-    comparison lens), equal masses, a 20 x 20 theta_* map of 2000 x 2000 px,
-    1 ray per pixel, flux fraction 1/1000 (its default).  The star disc
-    covers the shooting region with a 1.2 margin, about 26 700 stars (the
-    paper says ~27 000).  The paper's 0.763 s was measured on an NVIDIA A100
-    80 GB: context for the same map on other hardware, not a target."""
-    import math
+    """The paper's Table 1 map with the FMM, as far as the paper fixes it:
+    kappa = kappa_* = gamma = 0.6 (its sec. 4.1 comparison lens), equal
+    masses, a 20 x 20 theta_* map of 2000 x 2000 px, flux fraction 1/1000
+    (its default), IPM at 1 ray per pixel and IRS at 100, stars in a disc or
+    a rectangle covering the shooting region with a 1.2 margin.  The paper's
+    times were measured on an NVIDIA A100 80 GB: context for the same maps on
+    other hardware, not a target."""
     import torch
     import paper_2506_02114_amd as mlm
     import workloads as W
-    kappa = gamma = 0.6
-    f = 1e-3
-    r = math.sqrt(kappa / f)                      # equal masses: <m^2>/<m> = 1
-    dx1, dx2 = (10.0 + r) / abs(1 - kappa + gamma), (10.0 + r) / abs(1 - kappa - gamma)
-    n = int(round(kappa * (1.2 * math.hypot(dx1, dx2)) ** 2))
-    sf = W.star_field(n, kappa, "equal", seed=1)
+    paper = {("ipm", "circle"): 0.763, ("ipm", "rect"): 0.839, ("irs", "circle"): 0.748, ("irs", "rect"): 2.141}
     dev = torch.device("cuda:0")
-    lens = mlm.Lens(kappa, 0.0, gamma, torch.from_numpy(sf.x).to(dev), torch.from_numpy(sf.y).to(dev),
-                    torch.from_numpy(sf.m).to(dev))
-    spec = dict(hw1=10.0, hw2=10.0, n1=2000, n2=2000, rays_per_pixel=1.0, flux_fraction=f)
     out = torch.empty((2000, 2000), dtype=torch.float64, device=dev)
-    lens.map(out=out, **spec)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(3):
-        _, st = lens.map(out=out, **spec)
-    torch.cuda.synchronize()
-    s_map = (time.perf_counter() - t0) / 3
-    return {"stars": n, "rays": st["n_rays"], "order": st["order"], "s_per_map": s_map,
-            "rays_per_s": st["n_rays"] / s_map, "paper_s_per_map": 0.763, "paper_hardware": "NVIDIA A100 80 GB",
-            "paper_over_this": 0.763 / s_map, "precision": "fp64"}
+    res = {}
+    for shape in ("circle", "rect"):
+        L, mspec, aspect = W.paper_table1(shape)
+        if shape == "circle":
+            sf = W.star_field(L.n_stars, L.kappa_star, "equal", seed=L.seed)
+            lens = mlm.Lens(L.kappa_star, 0.0, L.gamma, sf.x, sf.y, sf.m)
+        else:
+            sf = W.rect_field(L.n_stars, L.kappa_star, aspect, "equal", seed=L.seed)
+            lens = mlm.Lens(L.kappa_star, 0.0, L.gamma, sf.x, sf.y, sf.m, sheet="rect", rect_aspect=aspect)
+        for mapping, rho in (("ipm", 1.0), ("irs", 100.0)):
+            spec = dict(mspec.asdict(), rays_per_pixel=rho, mapping=mapping)
+            lens.map(out=out, **spec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(2):
+                _, st = lens.map(out=out, **spec)
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t0) / 2
+            res[f"{mapping}_{shape}"] = {"stars": L.n_stars, "rays": st["n_rays"], "order": st["order"],
+                                         "s_per_map": sec, "rays_per_s": st["n_rays"] / sec,
+                                         "paper_s_per_map": paper[(mapping, shape)],
+                                         "paper_over_this": paper[(mapping, shape)] / sec}
+            print(f"[bench] table 1 {mapping} {shape}: {sec:.4f} s", file=sys.stderr, flush=True)
+    res["paper_hardware"] = "NVIDIA A100 80 GB"
+    res["precision"] = "fp64"
+    return res
 
 
 def copy_check() -> None:
@@ -174,13 +247,32 @@ def copy_check() -> None:
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}), flush=True)
 
 
-def cpu_baseline(wl, spec, region, nthreads: int) -> dict:
-    """The oracle (plain FP64 C, FMM + per-pixel IPM) on a bounded sample of the
-    same map: its full FMM build plus a strip of ray rows through the middle
-    of the grid, extrapolated to all rows."""
+def host_cpu() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, spec, nthreads: int, gpu_strip=None) -> dict:
+    """The oracle (plain FP64 C, FMM + per-pixel IPM), rebuilt -O3
+    -march=native for this host, on a bounded sample of the same map: its
+    full FMM build, then strips of cell rows through the middle of the grid,
+    shot and apportioned by `nthreads` workers (each strip on one thread, its
+    own deposit array), extrapolated to all rows.  With gpu_strip = (rows,
+    map of those rows from the GPU), also the method-level error: the same
+    rows mapped with the exact direct sum against the GPU's FMM strip."""
+    import tempfile
+    from concurrent.futures import ThreadPoolExecutor
+
     import numpy as np
     import oracle
 
+    tmp = tempfile.mkdtemp(prefix="oracle_native_")
+    oracle.use_native_build(tmp)
     sf = wl.stars()
     L = wl.lens
     ol = oracle.Lens(L.kappa_star, L.kappa_smooth, L.gamma, sf.x, sf.y, sf.m)
@@ -188,28 +280,50 @@ def cpu_baseline(wl, spec, region, nthreads: int) -> dict:
     t0 = time.perf_counter()
     F = oracle.FMM(ol, R.L0, spec["order"], nthreads=nthreads)
     t_build = time.perf_counter() - t0
-    rows = 64
-    r0 = R.nr2 // 2 - rows // 2
-    dep = np.zeros(R.n1 * R.n2)
-    st = np.zeros(5)
-    t0 = time.perf_counter()
+    strip = 16
+    times = {"shoot": 0.0, "ipm": 0.0}
+
+    def work(b):
+        dep = np.zeros(R.n1 * R.n2)
+        st = np.zeros(5)
+        a = time.perf_counter()
+        wx, wy = oracle.shoot_rows(R, ol, b, b + strip + 1, F, 1)
+        m = time.perf_counter()
+        oracle.ipm_rows(R, b, b + strip, wx, wy, dep, st)
+        e = time.perf_counter()
+        return m - a, e - m
+
+    r0 = R.nr2 // 2 - 8 * strip * nthreads // 2
     done = 0
-    while done < rows or time.perf_counter() - t0 < 8.0:
-        b = r0 + done
-        if b + 16 >= R.nr2:
-            break
-        wx, wy = oracle.shoot_rows(R, ol, b, b + 17, F, nthreads)
-        oracle.ipm_rows(R, b, b + 16, wx, wy, dep, st)
-        done += 16
-        if time.perf_counter() - t0 > 20.0:
-            break
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(nthreads) as ex:
+        while time.perf_counter() - t0 < 12.0 and r0 + done + strip * nthreads < R.nr2 - 1:
+            starts = [r0 + done + k * strip for k in range(nthreads)]
+            for ts, ti in ex.map(work, starts):
+                times["shoot"] += ts
+                times["ipm"] += ti
+            done += strip * nthreads
     t_rows = time.perf_counter() - t0
     t_full = t_build + t_rows * (R.nr2 - 1) / done
     rays = R.nr1 * R.nr2
-    return {"value": rays / t_full, "unit": "rays/s", "cores": nthreads, "kind": "oracle",
-            "sample": f"oracle FMM build ({t_build:.1f} s, p={spec['order']}) + {done} of {R.nr2 - 1} cell rows "
-                      f"shot and apportioned ({t_rows:.1f} s), extrapolated to the full map "
-                      f"({t_full:.0f} s for {rays} rays)"}
+    out = {"value": rays / t_full, "unit": "rays/s", "cores": nthreads, "kind": "oracle",
+           "sample": f"oracle rebuilt -O3 -march=native on this host ({host_cpu()}, nproc {os.cpu_count()}, "
+                     f"{nthreads} threads used: the box's CPU share for one GPU): FMM build {t_build:.1f} s (p="
+                     f"{spec['order']}) + {done} of {R.nr2 - 1} cell rows shot and apportioned in {t_rows:.1f} s, "
+                     f"extrapolated to the full map ({t_full:.0f} s for {rays} rays)",
+           "shoot_us_per_ray_thread": times["shoot"] / (done * R.nr1) * 1e6,
+           "ipm_us_per_triangle_thread": times["ipm"] / (done * 2 * (R.nr1 - 1)) * 1e6}
+    if gpu_strip is not None:
+        (a, b), gmu = gpu_strip
+        t0 = time.perf_counter()
+        ref = oracle.magnification_map(ol, spec, method="direct", rows=(a, b), nthreads=nthreads)
+        big = ref.mu >= 1e-6
+        rel = np.abs(gmu[big] - ref.mu[big]) / ref.mu[big]
+        out["fmm_p20_vs_direct_strip"] = {"rows": [a, b], "pixels": int(big.sum()), "max_rel": float(rel.max()),
+                                          "median_rel": float(np.median(rel)),
+                                          "max_abs_below_1e-6": float(np.abs(gmu[~big] - ref.mu[~big]).max()),
+                                          "s_direct": time.perf_counter() - t0}
+    return out
 
 
 def main():
@@ -292,6 +406,14 @@ def main():
                  "row_items": counts["n_band_rows"], "pieces": counts["n_band_pieces"]}
     band_roof["frac"] = band_roof["achieved"] / band_roof["peak"]
     roof, other = (cells_roof, band_roof) if t_cells >= t_band else (band_roof, cells_roof)
+    # the IPM stage priced by the survey's model: 25 flops per (triangle,
+    # pixel) piece and 30 per triangle, over the whole stage's time
+    survey_flops = 25.0 * counts["n_pieces"] + 30.0 * 2.0 * counts["n_cells"]
+    ipm_survey = {"bound": "alu", "model": "25 flops per (triangle, pixel) piece + 30 per triangle",
+                  "achieved": survey_flops / (t_ipm * 1e-3) / 1e12, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                  "unit": "TFLOP/s", "stage_ms": t_ipm, "pieces": counts["n_pieces"],
+                  "triangles": 2 * counts["n_cells"]}
+    ipm_survey["frac"] = ipm_survey["achieved"] / ipm_survey["peak"]
     line = {
         "metric": METRIC,
         "value": value,
@@ -314,6 +436,7 @@ def main():
         "roofline": roof,
         "roofline_" + other["kernel"]: other,
         "roofline_shoot": shoot_roof,
+        "roofline_ipm_stage_survey_model": ipm_survey,
         "tree": {"nodes": stats[0]["n_nodes"], "leaves": stats[0]["n_leaves"], "levels": stats[0]["n_levels"],
                  "near_pairs_per_ray": stats[0]["near_pairs"] / rays},
         "ipm": {"triangles": 2 * stats[0]["n_cells"], "row_path_triangles": stats[0]["n_big"],
@@ -334,10 +457,18 @@ def main():
             variants["paper_table1"] = paper_table1_variant()
         except Exception as e:
             variants["paper_table1"] = {"error": str(e)}
+        try:
+            variants["high_magnification"] = highmag_variant()
+        except Exception as e:
+            variants["high_magnification"] = {"error": str(e)}
         line["variants"] = variants
     if not args.no_cpu_baseline:
+        # the machine's CPU share for one GPU is 16 threads
         nthreads = min(16, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), os.cpu_count() or 1)
-        line["cpu_baseline"] = cpu_baseline(wl, spec, region, nthreads)
+        mid = region["nr2"] // 2
+        rows = (mid - 4, mid + 4)
+        gstrip, _ = lens.map(rows=rows, **spec)
+        line["cpu_baseline"] = cpu_baseline(wl, spec, nthreads, gpu_strip=(rows, gstrip))
     print(json.dumps(line), flush=True)
 
 

@@ -414,6 +414,32 @@ mlm_status mlm_map(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_m
 mlm_status mlm_map_noalloc(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_stats *stats);
 
 /*
+ * Products of a map (sec. 4.1, 5: light curves and magnification
+ * histograms, the quantities the paper compares maps by).  `req` is the
+ * request that made the map: its pixel geometry (y1c, y2c, hw1, hw2, n1,
+ * n2), where the buffers live (device_out: device pointers, else host) and
+ * its stream.
+ *
+ * Light curve of a point source moving along a straight track: mu at npts
+ * points evenly spaced from (y1a, y2a) to (y1b, y2b), both ends included,
+ * by bilinear interpolation between pixel centres (within half a pixel of
+ * the map's edge the nearest row or column is repeated); NaN at points
+ * outside the map.  out: npts doubles.
+ */
+mlm_status mlm_light_curve(const mlm_map_request *req, const double *mu, double y1a, double y2a, double y1b,
+                           double y2b, int64_t npts, double *out);
+
+/*
+ * Histogram of log10(mu) over the map's n1 x n2 pixels: counts[0] holds the
+ * pixels with mu <= 0 or log10(mu) < lo, counts[1 + b] those in
+ * [lo + b w, lo + (b + 1) w) with w = (hi - lo) / nbins, counts[nbins + 1]
+ * those at or above hi (and NaN).  counts: nbins + 2 int64 (host or device
+ * per req->device_out).  Errors: MLM_EINVAL for nbins < 1 or hi <= lo.
+ */
+mlm_status mlm_histogram(const mlm_map_request *req, const double *mu, double lo, double hi, int32_t nbins,
+                         int64_t *counts);
+
+/*
  * Batched maps: many lenses and requests in one call, each map as mlm_map
  * would make it, but with the ray shooting and the IPM of many maps fused
  * into persistent launches that walk the concatenated work of all maps (so

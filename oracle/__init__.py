@@ -16,6 +16,7 @@ Nothing here is shared with, or calls into, the HIP library.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 from dataclasses import dataclass
@@ -38,6 +39,19 @@ def build(force: bool = True) -> str:
         subprocess.run(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"], check=True)
         os.replace(tmp, _LIB)
     return _LIB
+
+
+def use_native_build(directory: str) -> str:
+    """Compile the same source with -O3 -march=native for the host it runs
+    on, into `directory`, and load that build instead (the CPU baseline's
+    timing build; the arithmetic is the same, contraction stays off)."""
+    global _lib
+    path = os.path.join(directory, "liboracle_native.so")
+    flags = ["-O3", "-march=native"] + [f for f in CFLAGS if f != "-O2"]
+    subprocess.run(["gcc", *flags, _SRC, "-o", path, "-lm"], check=True)
+    _lib = None
+    lib(path)
+    return path
 
 
 _lib = None
@@ -67,12 +81,14 @@ class Region(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-def lib():
+def lib(path: Optional[str] = None):
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        L = C.CDLL(_LIB)
+        if path is None:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+            path = _LIB
+        L = C.CDLL(path)
         L.orc_alpha_direct.argtypes = [C.c_long, _dp, _dp, _dp, C.c_long, _dp, _dp, _dp, _dp, C.c_int]
         L.orc_alpha_direct_reversed.argtypes = [C.c_long, _dp, _dp, _dp, C.c_long, _dp, _dp, _dp, _dp]
         L.orc_lens_equation.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int, C.c_double, C.c_double,
@@ -541,3 +557,55 @@ def mlp_loss_grad(P: dict, X: np.ndarray, y: np.ndarray, pos_weight: float = 1.0
     G["W1"] = X.T @ dA1
     G["b1"] = dA1.sum(axis=0)
     return loss, G
+
+
+# ---------------------------------------------------------------------------
+# Products of a map (sec. 4.1, 5): light curves and magnification histograms
+# ---------------------------------------------------------------------------
+
+def light_curve(mu: np.ndarray, spec: dict, start, end, npts: int) -> np.ndarray:
+    """mu of a point source at npts points evenly spaced from start to end
+    (source-plane coordinates, both ends included), interpolated bilinearly
+    between pixel centres: pixel (i, j) is centred at
+    (y1c - hw1 + (i + 1/2) pix1, y2c - hw2 + (j + 1/2) pix2); within half a
+    pixel of the map's edge the nearest row or column is repeated; NaN
+    outside the map.  Plain loops over the points."""
+    n2, n1 = mu.shape
+    hw1, hw2 = spec["hw1"], spec["hw2"]
+    y1c, y2c = spec.get("y1c", 0.0), spec.get("y2c", 0.0)
+    pix1, pix2 = 2.0 * hw1 / n1, 2.0 * hw2 / n2
+    out = np.empty(npts)
+    for k in range(npts):
+        f = k / (npts - 1) if npts > 1 else 0.0
+        y1 = start[0] + f * (end[0] - start[0])
+        y2 = start[1] + f * (end[1] - start[1])
+        u = (y1 - (y1c - hw1)) / pix1
+        v = (y2 - (y2c - hw2)) / pix2
+        if not (0.0 <= u <= n1 and 0.0 <= v <= n2):
+            out[k] = math.nan
+            continue
+        s = min(max(u - 0.5, 0.0), n1 - 1.0)
+        t = min(max(v - 0.5, 0.0), n2 - 1.0)
+        i0, j0 = min(int(math.floor(s)), n1 - 1), min(int(math.floor(t)), n2 - 1)
+        i1, j1 = min(i0 + 1, n1 - 1), min(j0 + 1, n2 - 1)
+        fs, ft = s - i0, t - j0
+        out[k] = ((1 - ft) * ((1 - fs) * mu[j0, i0] + fs * mu[j0, i1])
+                  + ft * ((1 - fs) * mu[j1, i0] + fs * mu[j1, i1]))
+    return out
+
+
+def histogram(mu: np.ndarray, lo: float, hi: float, nbins: int) -> np.ndarray:
+    """Counts of log10(mu): [0] mu <= 0 or log10(mu) < lo, [1 + b] the bin
+    [lo + b w, lo + (b + 1) w), w = (hi - lo) / nbins, [nbins + 1] at or above
+    hi or NaN; a value's bin is floor((log10(mu) - lo) nbins / (hi - lo))."""
+    out = np.zeros(nbins + 2, np.int64)
+    scale = nbins / (hi - lo)
+    for m in np.asarray(mu, np.float64).ravel():
+        if math.isnan(m):
+            out[nbins + 1] += 1
+        elif m <= 0:
+            out[0] += 1
+        else:
+            x = (math.log10(m) - lo) * scale
+            out[0 if x < 0 else (nbins + 1 if x >= nbins else 1 + int(x))] += 1
+    return out

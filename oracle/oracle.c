@@ -872,7 +872,7 @@ long orc_fmm_sorted_stars(const void *vF, double *x, double *y, double *m)
 void orc_op_m2m(int p, const double *a_ri, double z0x, double z0y, double *b_ri)
 {
     orc_fmm F; memset(&F, 0, sizeof F); F.p = p; binomials(F.binom);
-    cplx a[32], b[32];
+    cplx a[32] = {0}, b[32] = {0};
     for (int k = 0; k <= p; ++k) { a[k] = a_ri[2 * k] + I * a_ri[2 * k + 1]; b[k] = 0; }
     m2m_add(&F, a, z0x + I * z0y, b);
     for (int k = 0; k <= p; ++k) { b_ri[2 * k] = creal(b[k]); b_ri[2 * k + 1] = cimag(b[k]); }
@@ -881,7 +881,7 @@ void orc_op_m2m(int p, const double *a_ri, double z0x, double z0y, double *b_ri)
 void orc_op_m2l(int p, const double *b_ri, double z0x, double z0y, double *c_ri)
 {
     orc_fmm F; memset(&F, 0, sizeof F); F.p = p; binomials(F.binom);
-    cplx b[32], c[32];
+    cplx b[32] = {0}, c[32] = {0};
     for (int k = 0; k <= p; ++k) { b[k] = b_ri[2 * k] + I * b_ri[2 * k + 1]; c[k] = 0; }
     m2l_add(&F, b, z0x + I * z0y, c);
     for (int k = 0; k <= p; ++k) { c_ri[2 * k] = creal(c[k]); c_ri[2 * k + 1] = cimag(c[k]); }
@@ -890,7 +890,7 @@ void orc_op_m2l(int p, const double *b_ri, double z0x, double z0y, double *c_ri)
 void orc_op_l2l(int p, const double *c_ri, double z0x, double z0y, double *d_ri)
 {
     orc_fmm F; memset(&F, 0, sizeof F); F.p = p; binomials(F.binom);
-    cplx c[32], d[32];
+    cplx c[32] = {0}, d[32] = {0};
     for (int k = 0; k <= p; ++k) { c[k] = c_ri[2 * k] + I * c_ri[2 * k + 1]; d[k] = 0; }
     l2l_add(&F, c, z0x + I * z0y, d);
     for (int k = 0; k <= p; ++k) { d_ri[2 * k] = creal(d[k]); d_ri[2 * k + 1] = cimag(d[k]); }

@@ -34,7 +34,7 @@ EXPORTED = [
     "mlm_refiner_set_params", "mlm_refiner_predict", "mlm_refiner_grads", "mlm_train_opts_init",
     "mlm_refiner_train", "mlm_cell_samples", "mlm_map_noalloc", "mlm_lens_stars", "mlm_field_params_init",
     "mlm_field_moments", "mlm_field_count", "mlm_field_sample", "mlm_field_cover", "mlm_lens_create_sampled",
-    "mlm_philox4x32_10",
+    "mlm_philox4x32_10", "mlm_light_curve", "mlm_histogram",
 ]
 
 
@@ -165,8 +165,11 @@ def _lib():
     L.mlm_lens_create_sampled.argtypes = [C.POINTER(LensParams), C.POINTER(FieldParams), C.POINTER(vp)]
     L.mlm_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
     L.mlm_philox4x32_10.restype = None
+    L.mlm_light_curve.argtypes = [C.POINTER(MapRequest), vp, C.c_double, C.c_double, C.c_double, C.c_double, i64,
+                                  vp]
+    L.mlm_histogram.argtypes = [C.POINTER(MapRequest), vp, C.c_double, C.c_double, i32, vp]
     for nm in ("mlm_lens_stars", "mlm_field_moments", "mlm_field_count", "mlm_field_sample", "mlm_field_cover",
-               "mlm_lens_create_sampled"):
+               "mlm_lens_create_sampled", "mlm_light_curve", "mlm_histogram"):
         getattr(L, nm).restype = C.c_int
     L.mlm_deflect.argtypes = [vp, C.POINTER(MapRequest), vp, i64, vp]
     L.mlm_deflect.restype = C.c_int
@@ -270,6 +273,51 @@ def field_cover(kappa_star: float, kappa_smooth: float, gamma: float, f: FieldPa
     e1, e2 = C.c_double(), C.c_double()
     _check(_lib().mlm_field_cover(C.byref(p), C.byref(f), C.byref(r), margin, C.byref(e1), C.byref(e2)))
     return e1.value, e2.value
+
+
+def _map_args(mu, req: dict):
+    r = make_request(**req)
+    if _is_torch_cuda(mu):
+        import torch
+        assert mu.dtype == torch.float64 and mu.is_contiguous() and mu.numel() == r.n1 * r.n2
+        r.device_out = 1
+        r.stream = _current_stream()
+        return r, C.c_void_p(mu.data_ptr()), True
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    assert mu.size == r.n1 * r.n2
+    return r, mu, False
+
+
+def light_curve(mu, start, end, npts: int, **req):
+    """mu along the straight track start -> end (source-plane points), npts
+    samples (mlm_light_curve).  mu: the map (numpy, or a torch tensor on the
+    GPU, which gives a torch result); req: the map's request fields."""
+    r, m, dev = _map_args(mu, req)
+    if dev:
+        import torch
+        out = torch.empty(npts, dtype=torch.float64, device=mu.device)
+        _check(_lib().mlm_light_curve(C.byref(r), m, start[0], start[1], end[0], end[1], npts,
+                                      C.c_void_p(out.data_ptr())))
+        return out
+    out = np.empty(npts)
+    _check(_lib().mlm_light_curve(C.byref(r), m.ctypes.data_as(C.c_void_p), start[0], start[1], end[0], end[1],
+                                  npts, out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def histogram(mu, lo: float, hi: float, nbins: int, **req):
+    """Counts of log10(mu) in nbins bins on [lo, hi), with the underflow
+    (mu <= 0 included) first and the overflow last (mlm_histogram)."""
+    r, m, dev = _map_args(mu, req)
+    if dev:
+        import torch
+        out = torch.empty(nbins + 2, dtype=torch.int64, device=mu.device)
+        _check(_lib().mlm_histogram(C.byref(r), m, lo, hi, nbins, C.c_void_p(out.data_ptr())))
+        return out
+    out = np.empty(nbins + 2, np.int64)
+    _check(_lib().mlm_histogram(C.byref(r), m.ctypes.data_as(C.c_void_p), lo, hi, nbins,
+                                out.ctypes.data_as(C.c_void_p)))
+    return out
 
 
 def philox4x32_10(counter, key):

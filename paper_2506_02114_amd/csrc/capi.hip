@@ -1098,6 +1098,98 @@ mlm_status mlm_map_noalloc(mlm_lens *lens, const mlm_map_request *req, double *m
     API_END
 }
 
+}  // extern "C"
+
+namespace mlm {
+namespace {
+
+// the pixel geometry of a request (no lens needed)
+MapGeom request_geom(const mlm_map_request *q)
+{
+    if (!(q->hw1 > 0) || !(q->hw2 > 0) || !std::isfinite(q->hw1) || !std::isfinite(q->hw2) || q->n1 <= 0 ||
+        q->n2 <= 0 || !std::isfinite(q->y1c) || !std::isfinite(q->y2c))
+        fail(MLM_EINVAL, "map centre/half-widths must be finite, half-widths > 0, pixels >= 1");
+    MapGeom g{};
+    g.ylo1 = q->y1c - q->hw1;
+    g.ylo2 = q->y2c - q->hw2;
+    g.pix1 = 2.0 * q->hw1 / (double)q->n1;
+    g.pix2 = 2.0 * q->hw2 / (double)q->n2;
+    g.n1 = q->n1;
+    g.n2 = q->n2;
+    return g;
+}
+
+// device buffers of the product calls (one set per process, serialised)
+struct ProductWs {
+    std::mutex mu;
+    DevBuf map, out;
+};
+
+ProductWs &product_ws()
+{
+    static ProductWs *w = new ProductWs;   // never destroyed: outlives every call
+    return *w;
+}
+
+}  // namespace
+}  // namespace mlm
+
+extern "C" {
+
+mlm_status mlm_light_curve(const mlm_map_request *req, const double *mu, double y1a, double y2a, double y1b,
+                           double y2b, int64_t npts, double *out)
+{
+    API_BEGIN
+    if (!req || !mu || (npts > 0 && !out) || npts < 0) fail(MLM_EINVAL, "request, map and output must be given");
+    if (!std::isfinite(y1a) || !std::isfinite(y2a) || !std::isfinite(y1b) || !std::isfinite(y2b))
+        fail(MLM_EINVAL, "the track's ends must be finite");
+    const MapGeom g = request_geom(req);
+    hipStream_t st = stream_of(req);
+    if (npts == 0) return MLM_OK;
+    if (req->device_out) {
+        launch_light_curve(mu, g, y1a, y2a, y1b, y2b, npts, out, st);
+        MLM_HIP(hipStreamSynchronize(st));
+        return MLM_OK;
+    }
+    ProductWs &P = product_ws();
+    std::lock_guard<std::mutex> guard(P.mu);
+    const size_t npix = (size_t)g.n1 * (size_t)g.n2;
+    double *dm = static_cast<double *>(P.map.reserve(npix * sizeof(double)));
+    double *dout = static_cast<double *>(P.out.reserve((size_t)npts * sizeof(double)));
+    MLM_HIP(hipMemcpyAsync(dm, mu, npix * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_light_curve(dm, g, y1a, y2a, y1b, y2b, npts, dout, st);
+    MLM_HIP(hipMemcpyAsync(out, dout, (size_t)npts * sizeof(double), hipMemcpyDeviceToHost, st));
+    MLM_HIP(hipStreamSynchronize(st));
+    API_END
+}
+
+mlm_status mlm_histogram(const mlm_map_request *req, const double *mu, double lo, double hi, int32_t nbins,
+                         int64_t *counts)
+{
+    API_BEGIN
+    if (!req || !mu || !counts) fail(MLM_EINVAL, "request, map and counts must be given");
+    if (nbins < 1 || !(hi > lo) || !std::isfinite(lo) || !std::isfinite(hi))
+        fail(MLM_EINVAL, "need nbins >= 1 and finite lo < hi");
+    const MapGeom g = request_geom(req);
+    hipStream_t st = stream_of(req);
+    const int64_t npix = (int64_t)g.n1 * g.n2;
+    if (req->device_out) {
+        launch_histogram(mu, npix, lo, hi, nbins, reinterpret_cast<unsigned long long *>(counts), st);
+        MLM_HIP(hipStreamSynchronize(st));
+        return MLM_OK;
+    }
+    ProductWs &P = product_ws();
+    std::lock_guard<std::mutex> guard(P.mu);
+    double *dm = static_cast<double *>(P.map.reserve((size_t)npix * sizeof(double)));
+    unsigned long long *dc =
+        static_cast<unsigned long long *>(P.out.reserve((size_t)(nbins + 2) * sizeof(unsigned long long)));
+    MLM_HIP(hipMemcpyAsync(dm, mu, (size_t)npix * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_histogram(dm, npix, lo, hi, nbins, dc, st);
+    MLM_HIP(hipMemcpyAsync(counts, dc, (size_t)(nbins + 2) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    MLM_HIP(hipStreamSynchronize(st));
+    API_END
+}
+
 mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, int32_t nmaps, double *const *mus,
                          mlm_map_stats *stats, const mlm_batch_opts *opts, mlm_batch_stats *bstats)
 {

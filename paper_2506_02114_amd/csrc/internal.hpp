@@ -346,6 +346,12 @@ int64_t scan_i32_to_u64(mlm_lens *lens, const int32_t *in, unsigned long long *o
 int64_t scan_total_i64(mlm_lens *lens, const int64_t *in, int64_t *out, int64_t n, hipStream_t st);
 int64_t scan_i32_to_i64(mlm_lens *lens, const int32_t *in, int64_t *out, int64_t n, hipStream_t st);
 
+// products.hip
+void launch_light_curve(const double *mu, const MapGeom &g, double y1a, double y2a, double y1b, double y2b,
+                        int64_t npts, double *out, hipStream_t st);
+void launch_histogram(const double *mu, int64_t npix, double lo, double hi, int nbins, unsigned long long *counts,
+                      hipStream_t st);
+
 // refine.hip
 void launch_refine(const Tree &T, const Region &R, const LensConst &lc, const MapGeom &g, double tau, int depth,
                    int window, int64_t ncand, const int64_t *cand, int64_t nr1, int64_t vb0, const double2 *verts,

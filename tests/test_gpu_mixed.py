@@ -214,6 +214,19 @@ def test_mixed_high_magnification_map(mlm, orc):
     # magnification; here the caustic pixels are the maximum
     assert abs(a.mean() - b.mean()) < 1e-6 * b.mean()
     _assert_map(rel, MAX_BOUND_HIGHMAG, "high-magnification map vs FP64")
+    # the products sec. 5 compares the precisions by: light curves across the
+    # map and the distribution of log10 mu
+    lc = {}
+    for name, (p0, p1) in {"row": ((-10.0, 0.0025), (10.0, 0.0025)), "diagonal": ((-9.99, -9.9), (9.9, 9.99)),
+                           "column": ((0.0025, -10.0), (0.0025, 10.0))}.items():
+        c32 = mlm.light_curve(m32, p0, p1, 8001, **spec).cpu().numpy()
+        c64 = mlm.light_curve(m64, p0, p1, 8001, **spec).cpu().numpy()
+        lc[name] = float(np.max(np.abs(c32 - c64) / c64))
+    h32 = mlm.histogram(m32, 1.0, 5.0, 400, **spec).cpu().numpy()
+    h64 = mlm.histogram(m64, 1.0, 5.0, 400, **spec).cpu().numpy()
+    hist_l1 = float(np.abs(h32 - h64).sum() / h64.sum())
+    _report("high_magnification_products_mixed_vs_fp64", light_curve_max_rel=lc, histogram_l1=hist_l1)
+    assert max(lc.values()) < MAX_BOUND_HIGHMAG and hist_l1 < 1e-3
     # sampled rays of both modes against the exact direct sum
     rng = np.random.default_rng(33)
     ns = 4000
