@@ -263,3 +263,85 @@ def test_learned_refinement_gain(mlm, orc):
     assert recall > 0.95
     assert e_learned < 0.2 * e_plain      # most of the refinement's correction is kept
     assert t_learned < t_full             # for less work than testing every cell
+
+
+def test_learned_refinement_at_workload_size(mlm):
+    """The learned workload at its stated size: 1e7 labelled cells, half from
+    ten draws of the 1e5-star plain lens type (seeds 2001-2010, its 2000^2 px
+    map) and half from ten draws of the 1e6-star high-magnification type
+    (seeds 3001-3010, its 4000^2 px map), sampled uniformly from each ray
+    grid; the network trained on them by the library's kernels; then a fresh
+    high-magnification field (seed 3999) mapped over 16 384 cell rows through
+    the middle of its grid (2.0e8 cells) with no refinement, with full
+    refinement (every cell tested) and with the learned one."""
+    import torch
+    dev = torch.device("cuda")
+    rng = np.random.default_rng(5)
+    feats, labels, domain = [], [], []
+    t0 = time.time()
+    for kind, seeds in (("plain_large", range(2001, 2011)), ("mixed_highmag", range(3001, 3011))):
+        wl = W.config(kind)
+        L = wl.lens
+        spec = dict(wl.map.asdict(), order=16)
+        for seed in seeds:
+            sf = W.star_field(L.n_stars, L.kappa_star, L.mass_fn, seed=seed, m_lo=L.m_lo, m_hi=L.m_hi)
+            gl = mlm.Lens(L.kappa_star, L.kappa_smooth, L.gamma, torch.from_numpy(sf.x).to(dev),
+                          torch.from_numpy(sf.y).to(dev), torch.from_numpy(sf.m).to(dev))
+            R = gl.region(**spec)
+            cells = np.stack([rng.integers(0, R["nr1"] - 1, 500_000), rng.integers(0, R["nr2"] - 1, 500_000)], 1)
+            f, y = gl.cell_samples(cells, **spec)
+            feats.append(f)
+            labels.append(y)
+            domain.append(np.full(len(y), 0 if kind == "plain_large" else 1, np.int8))
+            gl.close()
+        print(f"[refine] {kind}: 5e6 cells labelled, {time.time() - t0:.0f} s", flush=True)
+    X, y, dom = np.concatenate(feats), np.concatenate(labels), np.concatenate(domain)
+    del feats, labels
+    perm = rng.permutation(len(y))
+    X, y, dom = X[perm], y[perm], dom[perm]
+    ntr = len(y) - 500_000
+    pw = float(min((1 - y.mean()) / max(y.mean(), 1e-6), 20.0))
+    net = mlm.Refiner(seed=7)
+    t1 = time.time()
+    losses = net.train(X[:ntr], y[:ntr], epochs=6, batch=8192, lr=2e-3, pos_weight=pw, seed=2)
+    t_train = time.time() - t1
+    print(f"[refine] trained on {ntr} cells in {t_train:.1f} s", flush=True)
+    zv, yv, dv = net.predict(X[ntr:]), y[ntr:], dom[ntr:]
+    folded = np.array([len(set(r)) > 1 for r in X[ntr:, 8:]])
+    thr = min(float(np.quantile(zv[(yv == 1) & ~folded & (dv == d)], 0.02)) for d in (0, 1))
+    flag = (zv > thr) | folded
+    recall = float(flag[yv == 1].mean())
+    precision = float(yv[flag].mean())
+    # the fresh high-magnification field, a 16 384-row strip of its map
+    wl = W.config("mixed_highmag")
+    L = wl.lens
+    sf = W.star_field(L.n_stars, L.kappa_star, L.mass_fn, seed=3999, m_lo=L.m_lo, m_hi=L.m_hi)
+    gl = mlm.Lens(L.kappa_star, L.kappa_smooth, L.gamma, torch.from_numpy(sf.x).to(dev),
+                  torch.from_numpy(sf.y).to(dev), torch.from_numpy(sf.m).to(dev))
+    spec = dict(wl.map.asdict(), order=16)
+    R = gl.region(**spec)
+    mid = R["nr2"] // 2
+    rows = (mid - 8192, mid + 8192)
+    out = {k: torch.empty((spec["n2"], spec["n1"]), dtype=torch.float64, device=dev)
+           for k in ("none", "plain", "learned")}
+    stats = {}
+    for mode in ("none", "plain", "learned"):
+        kw = dict(refine=mode, refiner=net, refine_threshold=thr) if mode == "learned" else dict(refine=mode)
+        _, stats[mode] = gl.map(out=out[mode], rows=rows, timing=1, **spec, **kw)
+        print(f"[refine] strip, refine={mode}: {stats[mode]['t_total_ms']:.0f} ms", flush=True)
+    torch.cuda.synchronize()
+    plain, full, learned = (out[k] for k in ("none", "plain", "learned"))
+    norm = float(full.abs().sum())
+    e_plain = float((plain - full).abs().sum()) / norm
+    e_learned = float((learned - full).abs().sum()) / norm
+    t_full, t_learned = stats["plain"]["t_refine_ms"], stats["learned"]["t_refine_ms"]
+    _report("learned_gain_at_size", cells_trained=ntr, train_s=t_train, label_s=t1 - t0,
+            train_losses=[float(v) for v in losses], positives=float(y.mean()), threshold=thr,
+            heldout_recall=recall, heldout_precision=precision, eval_cells=stats["learned"]["n_cells"],
+            l1_plain_vs_full=e_plain, l1_learned_vs_full=e_learned, t_refine_full_ms=t_full,
+            t_refine_learned_ms=t_learned, candidates=stats["learned"]["n_refine_candidates"],
+            refined_full=stats["plain"]["n_refined"], refined_learned=stats["learned"]["n_refined"],
+            t_map_ms={k: v["t_total_ms"] for k, v in stats.items()})
+    assert recall > 0.95
+    assert e_learned < 0.2 * e_plain
+    assert t_learned < t_full
