@@ -234,6 +234,75 @@ def paper_table1_variant() -> dict:
     return res
 
 
+def learned_variant() -> dict:
+    """The learned refinement (a small network flags the cells worth the
+    refinement test): cells of two fields of the 1e5-star lens type and two
+    of the high-magnification type (8e3 and 2e4 stars, 1e5 sampled cells
+    each) labelled by the plain refinement test on the device, the network
+    trained on them by the library's kernels, then a fresh
+    high-magnification field (2e4 stars, seed 3999, 400^2 px of half-width
+    1) mapped with no refinement, with every cell tested, and with the
+    flagged cells only: times, flags and map differences."""
+    import numpy as np
+    import torch
+    import paper_2506_02114_amd as mlm
+    import workloads as W
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(2001)
+    feats, labels, domain = [], [], []
+    t0 = time.perf_counter()
+    for ks, kss, g, mf, lo, hi, seed, n, hw in ((0.45, 0.0, 0.45, "kroupa", 0.08, 1.5, 2001, 8000, 4.0),
+                                                 (0.45, 0.0, 0.45, "kroupa", 0.08, 1.5, 2002, 8000, 4.0),
+                                                 (0.01, 0.82, 0.1725, "salpeter", 0.1, 1.0, 3001, 20000, 1.0),
+                                                 (0.01, 0.82, 0.1725, "salpeter", 0.1, 1.0, 3002, 20000, 1.0)):
+        sf = W.star_field(n, ks, mf, seed=seed, m_lo=lo, m_hi=hi)
+        gl = mlm.Lens(ks, kss, g, sf.x, sf.y, sf.m)
+        spec = dict(hw1=hw, hw2=hw, n1=400, n2=400, order=16)
+        R = gl.region(**spec)
+        cells = np.stack([rng.integers(0, R["nr1"] - 1, 100000), rng.integers(0, R["nr2"] - 1, 100000)], 1)
+        f, y = gl.cell_samples(cells, **spec)
+        feats.append(f)
+        labels.append(y)
+        domain.append(np.full(len(y), 0 if ks > 0.1 else 1))
+        gl.close()
+    t_label = time.perf_counter() - t0
+    X, y, dom = np.concatenate(feats), np.concatenate(labels), np.concatenate(domain)
+    perm = rng.permutation(len(y))
+    X, y, dom = X[perm], y[perm], dom[perm]
+    ntr = int(0.8 * len(y))
+    pw = float(min((1 - y.mean()) / max(y.mean(), 1e-6), 20.0))
+    net = mlm.Refiner(seed=7)
+    t0 = time.perf_counter()
+    net.train(X[:ntr], y[:ntr], epochs=20, batch=4096, lr=2e-3, pos_weight=pw, seed=2)
+    t_train = time.perf_counter() - t0
+    zv, yv, dv = net.predict(X[ntr:]), y[ntr:], dom[ntr:]
+    folded = np.array([len(set(r)) > 1 for r in X[ntr:, 8:]])
+    thr = min(float(np.quantile(zv[(yv == 1) & ~folded & (dv == d)], 0.02)) for d in (0, 1))
+    flag = (zv > thr) | folded
+    sf = W.star_field(20000, 0.01, "salpeter", seed=3999, m_lo=0.1, m_hi=1.0)
+    gl = mlm.Lens(0.01, 0.82, 0.1725, torch.from_numpy(sf.x).to(dev), torch.from_numpy(sf.y).to(dev),
+                  torch.from_numpy(sf.m).to(dev))
+    spec = dict(hw1=1.0, hw2=1.0, n1=400, n2=400, order=16)
+    out = {k: torch.empty((400, 400), dtype=torch.float64, device=dev) for k in ("none", "plain", "learned")}
+    st = {}
+    for mode in ("none", "plain", "learned"):
+        kw = dict(refine=mode, refiner=net, refine_threshold=thr) if mode == "learned" else dict(refine=mode)
+        gl.map(out=out[mode], **spec, **kw)
+        _, st[mode] = gl.map(out=out[mode], timing=1, **spec, **kw)
+        print(f"[bench] learned refinement: refine={mode} {st[mode]['t_total_ms']:.1f} ms", file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    full = out["plain"]
+    norm = float(full.abs().sum())
+    return {"cells_per_map": st["none"]["n_cells"], "label_s": t_label, "train_s": t_train, "train_cells": ntr,
+            "heldout_recall": float(flag[yv == 1].mean()), "heldout_precision": float(yv[flag].mean()),
+            "ms_per_map": {k: v["t_total_ms"] for k, v in st.items()},
+            "refine_ms": {k: st[k]["t_refine_ms"] for k in ("plain", "learned")},
+            "cells_tested": {k: st[k]["n_refine_candidates"] for k in ("plain", "learned")},
+            "cells_refined": {k: st[k]["n_refined"] for k in ("plain", "learned")},
+            "l1_vs_full_refinement": {k: float((out[k] - full).abs().sum()) / norm for k in ("none", "learned")}}
+
+
 def copy_check() -> None:
     """A plain device copy of 1 GiB (2^27 doubles), three times: the reference
     reading for the HBM byte counters."""
@@ -334,6 +403,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-check", action="store_true", help="only run the plain copy used to scale HBM counters")
     ap.add_argument("--no-variants", action="store_true", help="skip the mixed-precision and batched measurements")
+    ap.add_argument("--only", choices=["mixed", "batched", "table1", "highmag", "learned"],
+                    help="run one variant alone (for profiling) and print it as the JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the map path has no multi-GPU mode); got --gpus {args.gpus}",
@@ -347,6 +418,16 @@ def main():
 
     import paper_2506_02114_amd as mlm
     import workloads as W
+
+    if args.only:
+        torch.cuda.set_device(0)
+        fn = {"batched": batched_variant, "table1": paper_table1_variant, "highmag": highmag_variant,
+              "learned": learned_variant}.get(args.only)
+        if fn is None:
+            print("--only mixed runs with the headline map: use the default run", file=sys.stderr)
+            sys.exit(2)
+        print(json.dumps({"variant": args.only, **fn()}), flush=True)
+        return
 
     wl = W.config("plain_large")
     spec = wl.map.asdict()
@@ -461,6 +542,10 @@ def main():
             variants["high_magnification"] = highmag_variant()
         except Exception as e:
             variants["high_magnification"] = {"error": str(e)}
+        try:
+            variants["learned_refinement"] = learned_variant()
+        except Exception as e:
+            variants["learned_refinement"] = {"error": str(e)}
         line["variants"] = variants
     if not args.no_cpu_baseline:
         # the machine's CPU share for one GPU is 16 threads

@@ -27,7 +27,7 @@ DEVICE = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "
           "-munsafe-fp-atomics"]
 HOST_ONLY = ["-ffp-contract=off"]
 
-SOURCES = ["capi.hip", "tree.hip", "fmm.hip", "shoot.hip", "ipm.hip", "refine.hip", "mlp.hip", "region.cpp", "field.cpp", "products.hip"]
+SOURCES = ["capi.hip", "tree.hip", "scan.hip", "fmm.hip", "shoot.hip", "ipm.hip", "refine.hip", "mlp.hip", "region.cpp", "field.cpp", "products.hip"]
 
 
 def _compile(src: str) -> str:

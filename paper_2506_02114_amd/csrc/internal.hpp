@@ -213,7 +213,7 @@ struct Tree {
 };
 
 struct Workspace {
-    DevBuf keys_in, keys, idx_in, idx, sx, sy, sm, cub_tmp;
+    DevBuf keys_in, keys, idx_in, idx, sx, sy, sm, scan_tmp;
     DevBuf code, level, leaf, slo, shi, block, parent, child0, coll, node_leaf, leaf_node, flags, offs;
     DevBuf ilist, mult, local, ops_m2m, ops_m2l, ops_l2l;
     DevBuf leaves, near, deriv, near_offs;
@@ -343,6 +343,21 @@ void launch_band_batch(const BatchMap *maps, int32_t nmaps, int64_t nbands, cons
                        const int32_t *list, const BigPrep *prep, const int64_t *rows, int64_t lds_doubles,
                        hipStream_t st);
 int64_t scan_i32_to_u64(mlm_lens *lens, const int32_t *in, unsigned long long *out, int64_t n, hipStream_t st);
+
+// scan.hip: device-wide prefix sums (tmp: scan_tmp_bytes(n)); the total is
+// stored to total_dev and/or total_host when they are given
+size_t scan_tmp_bytes(int64_t n);
+void dev_scan_i32(const int32_t *in, int32_t *out, int64_t n, bool inclusive, void *tmp, int64_t *total_dev,
+                  int64_t *total_host, hipStream_t st);
+void dev_scan_i32_i64(const int32_t *in, int64_t *out, int64_t n, bool inclusive, void *tmp, int64_t *total_dev,
+                      int64_t *total_host, hipStream_t st);
+void dev_scan_i64(const int64_t *in, int64_t *out, int64_t n, bool inclusive, void *tmp, int64_t *total_dev,
+                  int64_t *total_host, hipStream_t st);
+// stable radix sort of (key, value) pairs by key bits [0, bits); the result
+// ends in kout/vout, kin/vin are overwritten (tmp: radix_sort_tmp_bytes(n))
+size_t radix_sort_tmp_bytes(int64_t n);
+void radix_sort_pairs(uint64_t *kin, int32_t *vin, uint64_t *kout, int32_t *vout, int64_t n, int bits, void *tmp,
+                      hipStream_t st);
 int64_t scan_total_i64(mlm_lens *lens, const int64_t *in, int64_t *out, int64_t n, hipStream_t st);
 int64_t scan_i32_to_i64(mlm_lens *lens, const int32_t *in, int64_t *out, int64_t n, hipStream_t st);
 

@@ -62,6 +62,19 @@ __device__ inline bool clip_seg(Pt<R> P, Pt<R> Q, R lo, R hi, R slope, Pt<R> &E,
     return true;
 }
 
+// a / b for slopes and weights: the hardware reciprocal estimate, two Newton
+// steps and a corrected product (within an ulp or two of the rounded
+// quotient, for finite normal b); FP32: the reciprocal times a
+__device__ inline double fdiv(double a, double b)
+{
+    double y = __builtin_amdgcn_rcp(b);
+    y = fma(fma(-b, y, 1.0), y, y);
+    y = fma(fma(-b, y, 1.0), y, y);
+    const double r = a * y;
+    return fma(fma(-b, r, a), y, r);
+}
+__device__ inline float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
 // edge slopes of a triangle: sv = dv/du (for clips along u), su = du/dv (along v)
 template <class R>
 __device__ inline void tri_slopes(const Pt<R> (&T)[3], R (&sv)[3], R (&su)[3])
@@ -69,8 +82,8 @@ __device__ inline void tri_slopes(const Pt<R> (&T)[3], R (&sv)[3], R (&su)[3])
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const R du = T[(k + 1) % 3].u - T[k].u, dv = T[(k + 1) % 3].v - T[k].v;
-        sv[k] = du != R(0) ? qdiv(dv, du) : R(0);
-        su[k] = dv != R(0) ? qdiv(du, dv) : R(0);
+        sv[k] = du != R(0) ? fdiv(dv, du) : R(0);
+        su[k] = dv != R(0) ? fdiv(du, dv) : R(0);
     }
 }
 
@@ -128,12 +141,13 @@ __device__ inline R strip_cumulative(const SegsT<R> &S, R c)
 
 // The same for a strip of pixel columns, divide-free: for an edge with slope
 // sv = dv/du clipped to the strip, |b - a| = |sv| |d|, so where the clamped
-// function changes sign d I = sign(d) m^2 / (2 |sv|) = m^2 c / 2 with
-// c = sign(d) |du/dv| fixed per edge.
+// function changes sign d I = sign(d) m^2 / (2 |sv|) = m^2 c with
+// c = sign(d) |du/dv| / 2 fixed per edge.
 template <class R> struct ColSeg {
     R lo, hi;           // v range of the clipped edge
+    R mid;              // (lo + hi) / 2
     R d;                // du of the clipped edge
-    R c;                // sign(du) |du/dv| (0 if du = 0)
+    R c;                // sign(du) |du/dv| / 2 (0 if du = 0)
     bool any;           // the edge crosses the column with some extent
 };
 template <class R> struct ColSegs {
@@ -154,7 +168,8 @@ __device__ inline ColSeg<R> col_seg(Pt<R> P, Pt<R> Q, R lo, R hi, R sv, R su)
     s.any = s.d != R(0) || ev != xv;
     s.lo = s.any ? fmin(ev, xv) : R(0);
     s.hi = s.any ? fmax(ev, xv) : R(0);
-    s.c = s.d > R(0) ? fabs(su) : (s.d < R(0) ? -fabs(su) : R(0));
+    s.mid = R(0.5) * (s.lo + s.hi);
+    s.c = s.d > R(0) ? R(0.5) * fabs(su) : (s.d < R(0) ? R(-0.5) * fabs(su) : R(0));
     return s;
 }
 
@@ -168,14 +183,14 @@ __device__ inline void col_segments(const Pt<R> (&T)[3], const R (&sv)[3], const
 }
 
 // d I(r - a, r - b) without case branches: below the edge's v range the
-// crossing form (r - lo)^2 c / 2 is 0 once r - lo is clamped at 0; above it
-// the linear form applies
+// crossing form (r - lo)^2 c is 0 once r - lo is clamped at 0; above it the
+// linear form d (r - (lo + hi) / 2) applies
 template <class R>
 __device__ inline R col_term(const ColSeg<R> &e, R r)
 {
     const R t = fmax(r - e.lo, R(0));
-    const R cross = R(0.5) * t * t * e.c;
-    const R full = R(0.5) * e.d * ((r - e.lo) + (r - e.hi));
+    const R cross = t * t * e.c;
+    const R full = e.d * (r - e.mid);
     return r >= e.hi ? full : cross;
 }
 
@@ -438,7 +453,7 @@ __device__ inline ColSetup col_setup(P2 A, P2 B, P2 C, int i0, const MapGeom &g,
     c.T[2] = P2{C.u - c.fu0, C.v - c.fv0};
     tri_slopes(c.T, c.sv, c.su);
     const double S2 = twice_area(A, B, C, c.fu0, c.fv0);
-    c.scale = g.tri_weight / S2;
+    c.scale = fdiv(g.tri_weight, S2);
     c.i0 = (int)i0;
     c.j0 = (int)fmax(c.fv0, 0.0);
     c.j1 = (int)fmin(floor(vmax), (double)(g.n2 - 1));

@@ -15,6 +15,8 @@
 // Every product is a 32 x 32 block tile (one MFMA per 8 of the reduced
 // dimension) whose operands are read from LDS or global memory with the
 // strides that make the transposes of the backward pass free.
+#include <algorithm>
+
 #include "dev.hpp"
 
 namespace mlm {
@@ -122,15 +124,118 @@ __device__ inline void forward(const float *__restrict__ feats, int64_t s0, int6
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Inference only: the weights are staged once per workgroup in LDS, rows of
+// every operand are stored so that the four consecutive values of the
+// reduced dimension that a lane feeds one MFMA are one 8-byte LDS read, and
+// each wavefront loops over tiles of 32 samples (a grid sized to the device,
+// not to the samples).  Same arithmetic as `forward` (bf16 inputs, two-part
+// bf16 hidden layer, FP32 accumulation); the final 64-term sum runs in
+// another order.
+constexpr int PS = 68;    // padded row stride (bf16) of the 64-wide operands: 136 B, so rows fall in other banks
+constexpr int XS = 20;    // and of the 16-wide input rows: 40 B
+
+struct PredictLds {
+    uint16_t w1t[64 * XS];   // W1 transposed: w1t[n][k] = W1[k][n], k < 16
+    uint16_t w2t[64 * PS];   // W2 transposed: w2t[n][k] = W2[k][n]
+    float b1[64], b2[64], w3[64];
+    struct Wave {
+        uint16_t x[32 * XS];   // the tile's inputs, 12 features + 4 zero columns
+        uint16_t h1[32 * PS];  // layer-1 activations, bf16 part (then the layer-3 partial sums)
+        uint16_t h1lo[32 * PS];
+    } w[4];
+};
+
+// C (32 x 32) += A (32 x K) B (K x 32), A(m, k) = a[m * sa + k], B(k, n) =
+// bt[n * sb + k] (bf16 in LDS, rows 8-byte aligned): one 8-byte read per
+// operand and MFMA
+__device__ inline f32x16 tile_mma_rows(const uint16_t *a, int sa, const uint16_t *bt, int sb, int K, f32x16 acc,
+                                       int lane)
+{
+    const int r = lane & 31, h = (lane >> 5) * 4;
+    for (int k0 = 0; k0 < K; k0 += 8) {
+        const bf16x4 av = *reinterpret_cast<const bf16x4 *>(a + r * sa + k0 + h);
+        const bf16x4 bv = *reinterpret_cast<const bf16x4 *>(bt + r * sb + k0 + h);
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
 __global__ __launch_bounds__(256) void k_mlp_predict(const float *__restrict__ feats, int64_t n,
                                                      const uint16_t *__restrict__ W1b, const uint16_t *__restrict__ W2b,
                                                      const float *__restrict__ P, float *__restrict__ logits)
 {
-    __shared__ WaveLds lds[4];
+    __shared__ PredictLds S;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t s0 = (int64_t)blockIdx.x * MB + wave * 32;
-    forward(feats, s0, n, W1b, W2b, P, lds[wave], lane);
-    if (lane < 32 && s0 + lane < n) logits[s0 + lane] = lds[wave].z[lane];
+    for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+        const int k = e >> 6, c = e & 63;   // W2b[k][c]
+        S.w2t[c * PS + k] = W2b[e];
+        if (k < 16) S.w1t[c * XS + k] = W1b[e];
+    }
+    if (threadIdx.x < 64) {
+        S.b1[threadIdx.x] = P[OB1 + threadIdx.x];
+        S.b2[threadIdx.x] = P[OB2 + threadIdx.x];
+        S.w3[threadIdx.x] = bf2f(f2bf(P[OW3 + threadIdx.x]));
+    }
+    const float b3 = P[OB3];
+    __syncthreads();
+    PredictLds::Wave &L = S.w[wave];
+    const int64_t ntiles = (n + 31) / 32, nwaves = (int64_t)gridDim.x * 4;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntiles; tile += nwaves) {
+        const int64_t s0 = tile * 32;
+        for (int e = lane; e < 32 * 16; e += 64) {
+            const int m = e >> 4, k = e & 15;
+            const int64_t s = s0 + m;
+            L.x[m * XS + k] = (k < 12 && s < n) ? f2bf(feats[s * 12 + k]) : (uint16_t)0;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int nh = 0; nh < 2; ++nh) {
+            f32x16 acc = {};
+            acc = tile_mma_rows(L.x, XS, S.w1t + nh * 32 * XS, XS, 16, acc, lane);
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int m = acc_row(j, lane), c = nh * 32 + acc_col(lane);
+                const float h = fmaxf(acc[j] + S.b1[c], 0.0f);
+                const uint16_t hi = f2bf(h);
+                L.h1[m * PS + c] = hi;
+                L.h1lo[m * PS + c] = f2bf(h - bf2f(hi));
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // layer 2 and each lane's share of layer 3: sum over its two columns
+        float part[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) part[j] = 0.0f;
+        for (int nh = 0; nh < 2; ++nh) {
+            f32x16 acc = {};
+            acc = tile_mma_rows(L.h1, PS, S.w2t + nh * 32 * PS, PS, 64, acc, lane);
+            acc = tile_mma_rows(L.h1lo, PS, S.w2t + nh * 32 * PS, PS, 64, acc, lane);
+            const int c = nh * 32 + acc_col(lane);
+#pragma unroll
+            for (int j = 0; j < 16; ++j) part[j] += fmaxf(acc[j] + S.b2[c], 0.0f) * S.w3[c];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // the 32 partial sums of each sample, through LDS (h1 is free now)
+        float *zb = reinterpret_cast<float *>(L.h1);   // [32 samples][32 lanes]
+#pragma unroll
+        for (int j = 0; j < 16; ++j) zb[acc_row(j, lane) * 32 + acc_col(lane)] = part[j];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane < 32 && s0 + lane < n) {
+            float z = b3;
+            for (int q = 0; q < 32; ++q) z += zb[lane * 32 + ((q + lane) & 31)];
+            logits[s0 + lane] = z;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
 }
 
 __device__ inline float softplus(float x) { return x > 0.0f ? x + log1pf(expf(-x)) : log1pf(expf(x)); }
@@ -312,9 +417,11 @@ void mlp_pack(const float *P, uint16_t *W1b, uint16_t *W2b, hipStream_t st)
 void mlp_predict(const float *feats, int64_t n, const uint16_t *W1b, const uint16_t *W2b, const float *P,
                  float *logits, hipStream_t st)
 {
-    if (n > 0)
-        hipLaunchKernelGGL(k_mlp_predict, dim3((unsigned)((n + MB - 1) / MB)), dim3(256), 0, st, feats, n, W1b, W2b, P,
-                           logits);
+    // a grid the device holds at once (three workgroups per CU at this LDS
+    // size), each wavefront looping over tiles of 32 samples
+    const int64_t tiles = (n + 31) / 32;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, 256 * 3 * 4));
+    if (n > 0) hipLaunchKernelGGL(k_mlp_predict, dim3(grid), dim3(256), 0, st, feats, n, W1b, W2b, P, logits);
 }
 
 void mlp_train_batch(const float *feats, const uint8_t *y, const int64_t *idx, int64_t n, const uint16_t *W1b,

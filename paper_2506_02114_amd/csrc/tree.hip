@@ -10,8 +10,6 @@
 // 3x3 neighbourhood as such references ("colleagues"), found from its
 // parent's in O(1), and the block count and the interaction lists follow
 // from them without searching the whole key array.
-#include <hipcub/hipcub.hpp>
-
 #include "dev.hpp"
 
 namespace mlm {
@@ -229,47 +227,38 @@ T *grow_keep(DevBuf &b, size_t used_elems, size_t need_elems, hipStream_t st)
     return static_cast<T *>(b.grow_keep(used_elems * sizeof(T), need_elems * sizeof(T), st));
 }
 
-void *cub_tmp(Workspace &ws, size_t bytes) { return ws.cub_tmp.reserve(bytes ? bytes : 1); }
+void *scan_tmp(Workspace &ws, size_t bytes) { return ws.scan_tmp.reserve(bytes ? bytes : 1); }
 
-// a scan's total read back to the host: a one-wavefront kernel stores it
-// straight into pinned host memory (one small launch where two copies were);
-// exclusive scans pass the last input (total = out[n - 1] + in[n - 1]),
-// inclusive ones none (total = out[n - 1])
-template <class T>
-__global__ void k_scan_total(const T *in, const T *out, int64_t n, int64_t *host)
+// A scan's total, read back to the host: the scan stores it straight into
+// pinned host memory (inside a scratch arena, which has no pinned buffer, into
+// a scratch slot that is copied), and the stream is synchronised.
+struct TotalSlot {
+    int64_t *dev = nullptr, *host = nullptr;
+};
+
+TotalSlot total_slot(mlm_lens *lens)
 {
-    if (threadIdx.x == 0) host[0] = (int64_t)out[n - 1] + (in ? (int64_t)in[n - 1] : 0);
+    TotalSlot t;
+    if (Arena *a = thread_arena()) t.dev = static_cast<int64_t *>(a->take(sizeof(int64_t)));
+    else t.host = static_cast<int64_t *>(pinned(lens, sizeof(int64_t)));
+    return t;
 }
 
-template <class T>
-int64_t read_total(mlm_lens *lens, const T *in, const T *out, int64_t n, hipStream_t st)
+int64_t read_total(const TotalSlot &t, hipStream_t st)
 {
-    if (Arena *a = thread_arena()) {
-        // no pinned buffer inside a scratch arena: the total goes to a
-        // scratch slot and is copied to the host
-        int64_t *d = static_cast<int64_t *>(a->take(sizeof(int64_t)));
-        int64_t v = 0;
-        hipLaunchKernelGGL(k_scan_total<T>, dim3(1), dim3(64), 0, st, in, out, n, d);
-        MLM_HIP(hipMemcpyAsync(&v, d, sizeof v, hipMemcpyDeviceToHost, st));
-        MLM_HIP(hipStreamSynchronize(st));
-        return v;
-    }
-    int64_t *h = static_cast<int64_t *>(pinned(lens, sizeof(int64_t)));
-    hipLaunchKernelGGL(k_scan_total<T>, dim3(1), dim3(64), 0, st, in, out, n, h);
+    int64_t v = 0;
+    if (t.dev) MLM_HIP(hipMemcpyAsync(&v, t.dev, sizeof v, hipMemcpyDeviceToHost, st));
     MLM_HIP(hipStreamSynchronize(st));
-    return h[0];
+    return t.dev ? v : t.host[0];
 }
 
 // exclusive prefix sum of n int32 flags; returns the total
 int64_t scan_total(mlm_lens *lens, const int32_t *in, int32_t *out, int64_t n, hipStream_t st)
 {
-    Workspace &ws = lens->ws;
     if (n == 0) return 0;
-    size_t tb = 0;
-    MLM_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, in, out, (int)n, st));
-    void *tmp = cub_tmp(ws, tb);
-    MLM_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, in, out, (int)n, st));
-    return read_total<int32_t>(lens, in, out, n, st);
+    const TotalSlot t = total_slot(lens);
+    dev_scan_i32(in, out, n, false, scan_tmp(lens->ws, scan_tmp_bytes(n)), t.dev, t.host, st);
+    return read_total(t, st);
 }
 
 }  // namespace
@@ -283,14 +272,11 @@ int64_t scan_total_public(mlm_lens *lens, const int32_t *in, int32_t *out, int64
 // one is the total, which is returned)
 int64_t scan_i32_to_i64(mlm_lens *lens, const int32_t *in, int64_t *out, int64_t n, hipStream_t st)
 {
-    Workspace &ws = lens->ws;
     if (n == 0) return 0;
-    size_t tb = 0;
-    MLM_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, tb, in, out + 1, (int)n, st));
-    void *tmp = cub_tmp(ws, tb);
+    const TotalSlot t = total_slot(lens);
     hipLaunchKernelGGL(k_zero_first, dim3(1), dim3(1), 0, st, out);
-    MLM_HIP(hipcub::DeviceScan::InclusiveSum(tmp, tb, in, out + 1, (int)n, st));
-    return read_total<int64_t>(lens, nullptr, out + 1, n, st);
+    dev_scan_i32_i64(in, out + 1, n, true, scan_tmp(lens->ws, scan_tmp_bytes(n)), t.dev, t.host, st);
+    return read_total(t, st);
 }
 
 // exclusive prefix sum of n int32 counts into n + 1 uint64 offsets; returns the total
@@ -302,13 +288,10 @@ int64_t scan_i32_to_u64(mlm_lens *lens, const int32_t *in, unsigned long long *o
 // exclusive prefix sum of n int64 values; returns the total
 int64_t scan_total_i64(mlm_lens *lens, const int64_t *in, int64_t *out, int64_t n, hipStream_t st)
 {
-    Workspace &ws = lens->ws;
     if (n == 0) return 0;
-    size_t tb = 0;
-    MLM_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, in, out, (int)n, st));
-    void *tmp = cub_tmp(ws, tb);
-    MLM_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, in, out, (int)n, st));
-    return read_total<int64_t>(lens, in, out, n, st);
+    const TotalSlot t = total_slot(lens);
+    dev_scan_i64(in, out, n, false, scan_tmp(lens->ws, scan_tmp_bytes(n)), t.dev, t.host, st);
+    return read_total(t, st);
 }
 
 void build_tree(mlm_lens *lens, const Region &R, const mlm_map_request &req, Tree &T, hipStream_t st)
@@ -335,10 +318,7 @@ void build_tree(mlm_lens *lens, const Region &R, const mlm_map_request &req, Tre
         double scale = std::ldexp(1.0, KEY_BITS - R.L0_exp);   // 2^24 / (2 L0)
         hipLaunchKernelGGL(k_keys, dim3(nblocks(n)), dim3(BLK), 0, st, lens->d_x, lens->d_y, n, R.L0,
                            scale, kin, iin);
-        size_t tb = 0;
-        MLM_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, kin, kout, iin, iout, n, 0, 2 * KEY_BITS, st));
-        void *tmp = cub_tmp(ws, tb);
-        MLM_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, kin, kout, iin, iout, n, 0, 2 * KEY_BITS, st));
+        radix_sort_pairs(kin, iin, kout, iout, n, 2 * KEY_BITS, scan_tmp(ws, radix_sort_tmp_bytes(n)), st);
         hipLaunchKernelGGL(k_gather, dim3(nblocks(n)), dim3(BLK), 0, st, iout, lens->d_x, lens->d_y,
                            lens->d_m, n, T.x, T.y, T.m);
     }
