@@ -243,7 +243,9 @@ typedef struct mlm_map_request {
     double refine_threshold;   /* logit above which the network flags a cell (default 0) */
     struct mlm_refiner *refiner;   /* network for MLM_REFINE_LEARNED */
     int32_t mapping;           /* MLM_MAP_IPM (default) or MLM_MAP_IRS */
-    int32_t reserved2;
+    int32_t one_stream;        /* 0 (default): the large-triangle passes of the IPM run on a
+                                  second stream of the lens beside the cell pass (fork and join
+                                  through events on req->stream); 1: every kernel on req->stream */
 } mlm_map_request;
 
 void mlm_map_request_init(mlm_map_request *req);

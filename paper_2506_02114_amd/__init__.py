@@ -73,7 +73,7 @@ class MapRequest(C.Structure):
                 ("row_end", C.c_int64), ("stream", C.c_void_p), ("w_out", C.c_void_p),
                 ("timing", C.c_int32), ("refine", C.c_int32), ("refine_depth", C.c_int32),
                 ("refine_window", C.c_int32), ("refine_tau", C.c_double), ("refine_threshold", C.c_double),
-                ("refiner", C.c_void_p), ("mapping", C.c_int32), ("reserved2", C.c_int32)]
+                ("refiner", C.c_void_p), ("mapping", C.c_int32), ("one_stream", C.c_int32)]
 
 
 class Region(C.Structure):

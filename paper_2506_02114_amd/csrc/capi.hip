@@ -136,6 +136,9 @@ void DevBuf::release()
 
 Workspace::~Workspace()
 {
+    if (side) (void)hipStreamDestroy(side);
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
     if (!pinned) return;
     std::lock_guard<std::mutex> g(g_alloc_mu);
     (void)hipHostFree(pinned);
@@ -207,12 +210,13 @@ struct Timer {
     hipStream_t st;
     std::vector<hipEvent_t> ev;
     Timer(bool on_, hipStream_t st_) : on(on_), st(st_) {}
-    int mark()
+    int mark() { return mark_on(st); }
+    int mark_on(hipStream_t s)
     {
         if (!on) return -1;
         hipEvent_t e;
         MLM_HIP(hipEventCreate(&e));
-        MLM_HIP(hipEventRecord(e, st));
+        MLM_HIP(hipEventRecord(e, s));
         ev.push_back(e);
         return (int)ev.size() - 1;
     }
@@ -853,25 +857,42 @@ void map_impl(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_st
             if (fmm) launch_shoot(lens, T, R, lc, g, nt, vb0, verts, w_here, st);
             else launch_shoot_direct(lens, R, lc, g, vb0, vb1, verts, w_here, st);
             int eb = tm.mark();
-            // IPM: cell pass, then one thread per (triangle, pixel column) for the
-            // ordinary triangles and the row-parallel passes for the large ones
+            // IPM: the cell pass apportions the ordinary triangles; the large ones
+            // are counted per cell tile, gathered, binned by pixel bands and
+            // apportioned band by band.  With row bands and a second stream (the
+            // default) that chain runs beside the cell pass: it counts the large
+            // triangles itself and adds its band rows to the map atomically.
             const int64_t ncells = (R.nr1 - 1) * (r1 - r0);
             const int64_t ntl = ipm_tile_count(R.nr1, r1 - r0);
+            const int bh = band_height(g.n1, g.n2);
+            const bool overlap = bh > 0 && !q.one_stream && !thread_arena();
+            hipStream_t bst = st;   // stream of the large-triangle chain
+            if (overlap) {
+                if (!ws.side) MLM_HIP(hipStreamCreateWithFlags(&ws.side, hipStreamNonBlocking));
+                if (!ws.fork) MLM_HIP(hipEventCreateWithFlags(&ws.fork, hipEventDisableTiming));
+                if (!ws.join) MLM_HIP(hipEventCreateWithFlags(&ws.join, hipEventDisableTiming));
+                bst = ws.side;
+                MLM_HIP(hipEventRecord(ws.fork, st));
+                MLM_HIP(hipStreamWaitEvent(bst, ws.fork, 0));
+            }
             int32_t *tbig = static_cast<int32_t *>(ws.tbig.reserve((size_t)std::max<int64_t>(ntl, 1) * sizeof(int32_t)));
             int64_t *toff = static_cast<int64_t *>(ws.tbigoff.reserve((size_t)(ntl + 1) * sizeof(int64_t)));
-            if (ntl > 0) hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((ntl + 255) / 256)), dim3(256), 0, st, tbig, ntl);
-            launch_ipm(verts, R.nr1, r0, r1, vb0, g, map, cnt, tbig, q.precision == MLM_PREC_MIXED,
+            if (overlap) {
+                launch_big_count(verts, R.nr1, r0, r1, vb0, g, tbig, bst);
+            } else if (ntl > 0) {
+                hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((ntl + 255) / 256)), dim3(256), 0, st, tbig, ntl);
+            }
+            const int e_cells0 = tm.mark();
+            launch_ipm(verts, R.nr1, r0, r1, vb0, g, map, cnt, overlap ? nullptr : tbig, q.precision == MLM_PREC_MIXED,
                        q.timing >= 2 ? cnt + 8 : nullptr, st);
             const int e_cells = tm.mark();
-            if (q.timing >= 2) launch_count_pieces(verts, R.nr1, r0, r1, vb0, g, cnt + 6, st);   // statistics only
             int e_band0 = -1, e_band1 = -1;
-            const int64_t nb = scan_i32_to_i64(lens, tbig, toff, ntl, st);
+            const int64_t nb = scan_i32_to_i64(lens, tbig, toff, ntl, bst);
             if (nb > 0) {
                 BigPrep *prep = static_cast<BigPrep *>(ws.bigprep.reserve((size_t)nb * sizeof(BigPrep)));
                 int64_t *rows = static_cast<int64_t *>(ws.bigrows.reserve((size_t)nb * sizeof(int64_t)));
                 int32_t *row0 = static_cast<int32_t *>(ws.bigrow0.reserve((size_t)nb * sizeof(int32_t)));
-                launch_big_gather(verts, R.nr1, r0, r1, vb0, g, toff, prep, rows, row0, st);
-                const int bh = band_height(g.n1, g.n2);
+                launch_big_gather(verts, R.nr1, r0, r1, vb0, g, toff, prep, rows, row0, bst);
                 if (bh > 0) {
                     // large triangles by pixel bands: owned rows, LDS accumulation
                     const int32_t nbands = (int32_t)((g.n2 + bh - 1) / bh);
@@ -880,24 +901,30 @@ void map_impl(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_st
                         static_cast<unsigned long long *>(ws.bandoff.reserve((size_t)(nbands + 1) * sizeof(unsigned long long)));
                     unsigned long long *bcur =
                         static_cast<unsigned long long *>(ws.bandcur.reserve((size_t)(nbands + 1) * sizeof(unsigned long long)));
-                    hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((nbands + 255) / 256)), dim3(256), 0, st, bcnt, nbands);
-                    launch_band_count(nb, row0, rows, bh, nbands, bcnt, st);
-                    const int64_t nlist = scan_i32_to_u64(lens, bcnt, boffs, nbands, st);
+                    hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((nbands + 255) / 256)), dim3(256), 0, bst, bcnt, nbands);
+                    launch_band_count(nb, row0, rows, bh, nbands, bcnt, bst);
+                    const int64_t nlist = scan_i32_to_u64(lens, bcnt, boffs, nbands, bst);
                     int32_t *blist = static_cast<int32_t *>(ws.bandlist.reserve((size_t)(nlist > 0 ? nlist : 1) * sizeof(int32_t)));
-                    MLM_HIP(hipMemcpyAsync(bcur, boffs, (size_t)nbands * sizeof(unsigned long long), hipMemcpyDeviceToDevice, st));
-                    launch_band_scatter(nb, row0, rows, bh, nbands, bcur, blist, st);
-                    e_band0 = tm.mark();
-                    launch_band(nbands, boffs, blist, prep, rows, bh, g, map, q.timing >= 2 ? cnt + 4 : nullptr, st);
-                    e_band1 = tm.mark();
+                    MLM_HIP(hipMemcpyAsync(bcur, boffs, (size_t)nbands * sizeof(unsigned long long), hipMemcpyDeviceToDevice, bst));
+                    launch_band_scatter(nb, row0, rows, bh, nbands, bcur, blist, bst);
+                    e_band0 = tm.mark_on(bst);
+                    launch_band(nbands, boffs, blist, prep, rows, bh, g, map, q.timing >= 2 ? cnt + 4 : nullptr, overlap,
+                                bst);
+                    e_band1 = tm.mark_on(bst);
                 } else {
                     launch_big(nb, prep, rows, g, map, diff, st);
                 }
                 if (q.timing >= 2) {   // statistics only
                     int64_t *rowoff = static_cast<int64_t *>(ws.rowoff.reserve((size_t)nb * sizeof(int64_t)));
-                    n_big_rows += scan_total_i64(lens, rows, rowoff, nb, st);
+                    n_big_rows += scan_total_i64(lens, rows, rowoff, nb, bst);
                 }
                 n_big += nb;
             }
+            if (overlap) {   // the map waits for both streams
+                MLM_HIP(hipEventRecord(ws.join, bst));
+                MLM_HIP(hipStreamWaitEvent(st, ws.join, 0));
+            }
+            if (q.timing >= 2) launch_count_pieces(verts, R.nr1, r0, r1, vb0, g, cnt + 6, st);   // statistics only
             int ec = tm.mark();
             if (q.refine != MLM_REFINE_NONE) {
                 // cell refinement of this strip's cells (a + (nr1 - 1) b, b in [r0, r1))
@@ -924,13 +951,26 @@ void map_impl(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_st
                     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, rst3, 4);
                     refine_stats_zeroed = true;
                 }
-                launch_refine(T, R, lc, g, q.refine_tau, q.refine_depth, q.refine_window, ncand, cand, R.nr1, vb0, verts, lab,
-                              map, rst3, st);
-                if (ncand > 0) {
-                    std::vector<uint8_t> hl((size_t)ncand);
-                    MLM_HIP(hipMemcpyAsync(hl.data(), lab, (size_t)ncand, hipMemcpyDeviceToHost, st));
-                    MLM_HIP(hipStreamSynchronize(st));
-                    for (uint8_t v : hl) n_refined += v;
+                // level by level: test every item of a level, number the refined
+                // ones by a scan, expand them into the next level's subcells
+                const size_t sub = refine_subcell_bytes();
+                int64_t nlev = ncand;
+                const void *list = nullptr;   // level 0: the candidate cells themselves
+                DevBuf *next = &ws.rsub0;
+                for (int d = 0; d < q.refine_depth && nlev > 0; ++d) {
+                    int32_t *flag = static_cast<int32_t *>(ws.rtflag.reserve((size_t)nlev * sizeof(int32_t)));
+                    int64_t *pos = static_cast<int64_t *>(ws.rtpos.reserve((size_t)(nlev + 1) * sizeof(int64_t)));
+                    launch_refine_test(T, R, lc, g, q.refine_tau, q.refine_depth, q.refine_window, nlev, cand, list,
+                                       R.nr1, vb0, verts, flag, d == 0 ? lab : nullptr, rst3, st);
+                    const int64_t nref = scan_i32_to_i64(lens, flag, pos, nlev, st);
+                    if (d == 0) n_refined += nref;
+                    if (nref == 0) break;
+                    void *out = next->reserve((size_t)(4 * nref) * sub);
+                    launch_refine_expand(T, R, lc, g, q.refine_tau, q.refine_depth, q.refine_window, nlev, cand, list,
+                                         R.nr1, vb0, verts, flag, pos, map, out, st);
+                    list = out;
+                    nlev = 4 * nref;
+                    next = next == &ws.rsub0 ? &ws.rsub1 : &ws.rsub0;
                 }
                 n_cand += ncand;
             }
@@ -942,7 +982,7 @@ void map_impl(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_st
             t_shoot += tm.ms(ea, eb);
             t_ipm += tm.ms(eb, ec);
             t_refine += tm.ms(ec, ed);
-            t_cells += tm.ms(eb, e_cells);
+            t_cells += tm.ms(e_cells0, e_cells);
             t_band += tm.ms(e_band0, e_band1);
             tiles += nt;
             r0 = r1;

@@ -218,7 +218,9 @@ struct Workspace {
     DevBuf ilist, mult, local, ops_m2m, ops_m2l, ops_l2l;
     DevBuf leaves, near, deriv, near_offs;
     DevBuf tile_off, tile_leaf, verts, map, wbuf, pts, counters, items, itemoff, tbig, tbigoff, bigprep, bigrows, bigrow0, rowoff, nbnd, nbndoff, diff, bandcnt, bandoff,
-        bandcur, bandlist, rfeat, rlogit, rflag, rpos, rcand, rlabel, rstats, irs_counts;
+        bandcur, bandlist, rfeat, rlogit, rflag, rpos, rcand, rlabel, rstats, irs_counts, rtflag, rtpos, rsub0, rsub1;
+    hipStream_t side = nullptr;           // second stream of a map: the large-triangle passes beside the cell pass
+    hipEvent_t fork = nullptr, join = nullptr;
     void *pinned = nullptr;               // small pinned host buffer for read-backs
     size_t pinned_cap = 0;
     int ops_p = -1;                       // expansion order of the operator tables
@@ -329,7 +331,9 @@ void launch_band_scatter(int64_t nbig, const int32_t *row0, const int64_t *rows,
                          unsigned long long *cursor, int32_t *list, hipStream_t st);
 void launch_band(int32_t nbands, const unsigned long long *band_off, const int32_t *list, const BigPrep *prep,
                  const int64_t *rows, int bh, const MapGeom &g, double *map, unsigned long long *work,
-                 hipStream_t st);
+                 bool atomic_flush, hipStream_t st);
+void launch_big_count(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int64_t vb0, const MapGeom &g,
+                      int32_t *tile_big, hipStream_t st);
 void launch_ipm_batch(const BatchMap *maps, int32_t nmaps, int64_t nctiles, int32_t *tile_big, hipStream_t st);
 void launch_big_gather_batch(const BatchMap *maps, int32_t nmaps, int64_t nctiles, const int64_t *tile_off,
                              BigPrep *prep, int64_t *rows, int32_t *row0, hipStream_t st);
@@ -368,9 +372,14 @@ void launch_histogram(const double *mu, int64_t npix, double lo, double hi, int 
                       hipStream_t st);
 
 // refine.hip
-void launch_refine(const Tree &T, const Region &R, const LensConst &lc, const MapGeom &g, double tau, int depth,
-                   int window, int64_t ncand, const int64_t *cand, int64_t nr1, int64_t vb0, const double2 *verts,
-                   uint8_t *label, double *map, unsigned long long *stats, hipStream_t st);
+size_t refine_subcell_bytes();
+void launch_refine_test(const Tree &T, const Region &R, const LensConst &lc, const MapGeom &g, double tau, int depth,
+                        int window, int64_t n, const int64_t *cand, const void *list, int64_t nr1, int64_t vb0,
+                        const double2 *verts, int32_t *flag, uint8_t *label, unsigned long long *stats, hipStream_t st);
+void launch_refine_expand(const Tree &T, const Region &R, const LensConst &lc, const MapGeom &g, double tau, int depth,
+                          int window, int64_t n, const int64_t *cand, const void *list, int64_t nr1, int64_t vb0,
+                          const double2 *verts, const int32_t *flag, const int64_t *pos, double *map, void *out,
+                          hipStream_t st);
 void launch_cell_features(int64_t nr1, int64_t cb0, int64_t ncells, int64_t vb0, const double2 *verts, float *feats,
                           hipStream_t st);
 void launch_sample_features(const Tree &T, const Region &R, const LensConst &lc, const MapGeom &g, int64_t n,

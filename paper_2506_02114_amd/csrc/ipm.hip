@@ -566,7 +566,7 @@ __device__ __forceinline__ void ipm_tile(const double2 *__restrict__ verts, int6
             }
         }
     }
-    {   // the tile's count of large triangles (tile_big is zeroed beforehand)
+    if (tile_big) {   // the tile's count of large triangles (tile_big is zeroed beforehand)
         int s = nb;
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
@@ -737,6 +737,35 @@ __device__ inline void gather_tile(const double2 *__restrict__ verts, int64_t nr
         rows[s] = 0;
         row0[s] = 0;
     }
+}
+
+// The number of large triangles of every cell tile (the cell pass's
+// classification, cells over the threads as there), stored per tile: what the
+// gather needs, without the cell pass, so the large-triangle passes can run
+// beside it.
+__global__ __launch_bounds__(256) void k_big_count(const double2 *__restrict__ verts, int64_t nr1, int64_t cb0,
+                                                   int64_t nrows, int64_t vb0, MapGeom g, int32_t *__restrict__ tile_big)
+{
+    __shared__ int32_t wsum[4];
+    const int64_t tile = blockIdx.x;
+    const int64_t ncol = nr1 - 1;
+    const int64_t tiles_a = (ncol + CT - 1) / CT;
+    const int64_t ta = tile % tiles_a, tb = tile / tiles_a;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t a = ta * CT + (lane & (CT - 1));
+    const int64_t brow = tb * CT + wave * 4 + (lane >> 4);
+    int nb = 0;
+    if (a < ncol && brow < nrows) {
+        P2 v00, v10, v11, v01;
+        load_cell_at(verts, nr1, cb0 + brow - vb0, a, v00, v10, v11, v01);
+        const int mask = cell_big_mask(v00, v10, v11, v01, g);
+        nb = (mask & 1) + (mask >> 1);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) nb += __shfl_xor(nb, o, 64);
+    if (lane == 0) wsum[wave] = nb;
+    __syncthreads();
+    if (threadIdx.x == 0) tile_big[tile] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
 __global__ __launch_bounds__(256) void k_big_gather(const double2 *__restrict__ verts, int64_t nr1, int64_t cb0,
@@ -1061,7 +1090,7 @@ __device__ inline bool row_clip(P2 P, P2 Q, double rl, double su, double &ua, do
 __device__ inline void band_rows(int64_t band, int64_t r0, int64_t r1, const int32_t *__restrict__ list,
                                  const BigPrep *__restrict__ prep, const int64_t *__restrict__ rows, int bh,
                                  const MapGeom &g, double *__restrict__ map, unsigned long long *__restrict__ work,
-                                 double *bdiff, unsigned long long *wsum)
+                                 double *bdiff, unsigned long long *wsum, bool atomic_flush)
 {
     if (threadIdx.x < 2) wsum[threadIdx.x] = 0;
     unsigned long long my_rows = 0, my_pieces = 0;
@@ -1160,7 +1189,10 @@ __device__ inline void band_rows(int64_t band, int64_t r0, int64_t r1, const int
             }
             v += carry;
             carry = __shfl(v, 63, 64);
-            if (i < n1 && v != 0.0) mr[i] += v;
+            if (i < n1 && v != 0.0) {
+                if (atomic_flush) unsafeAtomicAdd(mr + i, v);   // the cell pass may be adding to these rows
+                else mr[i] += v;
+            }
         }
     }
     if (work) {   // work counts for statistics: row items and difference deposits
@@ -1176,13 +1208,14 @@ __global__ __launch_bounds__(BAND_THREADS) void k_band(const unsigned long long 
                                                        const int32_t *__restrict__ list,
                                                        const BigPrep *__restrict__ prep,
                                                        const int64_t *__restrict__ rows, int bh, MapGeom g,
-                                                       double *__restrict__ map, unsigned long long *__restrict__ work)
+                                                       double *__restrict__ map, unsigned long long *__restrict__ work,
+                                                       int atomic_flush)
 {
     extern __shared__ double bdiff[];      // bh x n1 differences
     __shared__ unsigned long long wsum[2];
     const int64_t band = xcd_band(blockIdx.x, gridDim.x);
     band_rows(band, (int64_t)band_off[band], (int64_t)band_off[band + 1], list, prep, rows, bh, g, map, work, bdiff,
-              wsum);
+              wsum, atomic_flush != 0);
 }
 
 // the bands of every map of a fused batch (band_off and list over the
@@ -1199,7 +1232,7 @@ __global__ __launch_bounds__(BAND_THREADS) void k_band_batch(const BatchMap *__r
     const int32_t m = batch_find(maps, nmaps, gb, &BatchMap::band_lo);
     const BatchMap &d = maps[m];
     band_rows(gb - d.band_lo, (int64_t)band_off[gb], (int64_t)band_off[gb + 1], list, prep, rows, d.bh, d.g, d.map,
-              nullptr, bdiff, wsum);
+              nullptr, bdiff, wsum, false);
 }
 
 // band binning of a batch's large triangles.  The triangles of map m are
@@ -1349,6 +1382,15 @@ void launch_big_gather(const double2 *verts, int64_t nr1, int64_t cb0, int64_t c
                            tile_off, prep, rows, row0);
 }
 
+void launch_big_count(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int64_t vb0, const MapGeom &g,
+                      int32_t *tile_big, hipStream_t st)
+{
+    const int64_t tiles = ipm_tile_count(nr1, cb1 - cb0);
+    if (tiles > 0)
+        hipLaunchKernelGGL(k_big_count, dim3((unsigned)tiles), dim3(256), 0, st, verts, nr1, cb0, cb1 - cb0, vb0, g,
+                           tile_big);
+}
+
 void launch_big(int64_t nbig, const BigPrep *prep, const int64_t *rows, const MapGeom &g, double *map, double *diff,
                 hipStream_t st)
 {
@@ -1407,7 +1449,8 @@ void launch_band_scatter(int64_t nbig, const int32_t *row0, const int64_t *rows,
 }
 
 void launch_band(int32_t nbands, const unsigned long long *band_off, const int32_t *list, const BigPrep *prep,
-                 const int64_t *rows, int bh, const MapGeom &g, double *map, unsigned long long *work, hipStream_t st)
+                 const int64_t *rows, int bh, const MapGeom &g, double *map, unsigned long long *work,
+                 bool atomic_flush, hipStream_t st)
 {
     size_t shmem = (size_t)bh * (size_t)g.n1 * sizeof(double);
     static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_band),
@@ -1416,7 +1459,7 @@ void launch_band(int32_t nbands, const unsigned long long *band_off, const int32
     MLM_HIP(attr);
     if (nbands > 0)
         hipLaunchKernelGGL(k_band, dim3((unsigned)nbands), dim3(BAND_THREADS), shmem, st, band_off, list, prep, rows, bh,
-                           g, map, work);
+                           g, map, work, atomic_flush ? 1 : 0);
 }
 
 void launch_ipm_batch(const BatchMap *maps, int32_t nmaps, int64_t nctiles, int32_t *tile_big, hipStream_t st)

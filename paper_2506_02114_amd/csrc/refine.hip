@@ -185,12 +185,10 @@ struct SubCell {
     double u[4], v[4];
 };
 
-constexpr int STACK = 16;   // depth-first: at most 1 + 3 max_depth pending subcells (max_depth <= 4)
-
 // The test of one subcell; fills its 3 x 3 grid of source points (corners
 // from the subcell, five new rays) and returns whether it is refined.
-__device__ inline bool refine_test(const RefineArgs &ra, const SubCell &c, double (&gu)[3][3], double (&gv)[3][3],
-                                   int &too_large)
+// the subcell's 3 x 3 grid of source points: its corners and five new rays
+__device__ inline void fill_grid(const RefineArgs &ra, const SubCell &c, double (&gu)[3][3], double (&gv)[3][3])
 {
     gu[0][0] = c.u[0]; gv[0][0] = c.v[0];
     gu[0][2] = c.u[1]; gv[0][2] = c.v[1];
@@ -202,6 +200,12 @@ __device__ inline bool refine_test(const RefineArgs &ra, const SubCell &c, doubl
     shoot_uv(ra, c.A0 + hh, c.B0 + hh, gu[1][1], gv[1][1]);
     shoot_uv(ra, c.A0 + c.h, c.B0 + hh, gu[1][2], gv[1][2]);
     shoot_uv(ra, c.A0 + hh, c.B0 + c.h, gu[2][1], gv[2][1]);
+}
+
+__device__ inline bool refine_test(const RefineArgs &ra, const SubCell &c, double (&gu)[3][3], double (&gv)[3][3],
+                                   int &too_large)
+{
+    fill_grid(ra, c, gu, gv);
     double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
     bool finite = true;
     for (int r = 0; r < 3; ++r)
@@ -241,72 +245,99 @@ __device__ inline bool refine_test(const RefineArgs &ra, const SubCell &c, doubl
     return l1 > ra.tau * 2.0 * w;
 }
 
-// Refinement of candidate cells (global grid indices ca, cb; corners from
-// the strip's vertices, rows from vb0): label[k] = 1 if the cell itself is
-// refined; the map receives (leaves - cell) deposits when `map` is given.
-// stats: [0] tested subcells, [1] refined subcells, [2] too large.
-__global__ __launch_bounds__(RBLK) void k_refine(RefineArgs ra, int64_t ncand, const int64_t *__restrict__ cand,
-                                                 int64_t nr1, int64_t vb0, const double2 *__restrict__ verts,
-                                                 uint8_t *__restrict__ label, double *__restrict__ map,
-                                                 unsigned long long *__restrict__ stats)
+// Refinement level by level (breadth first): every (sub)cell of a level is
+// one thread of k_refine_test, which only decides; the few refined ones are
+// numbered by a scan and expanded by k_refine_expand, which moves their
+// deposits to their four children and lists the children for the next
+// level.  Lanes of a wavefront so do equal work, where one thread walking a
+// cell's whole subtree kept the other lanes waiting.
+//
+// A level's items are either candidate cells (cand: a + (nr1 - 1) b, corners
+// from the strip's vertices) or a list of subcells.
+__device__ inline SubCell level_item(int64_t t, const int64_t *__restrict__ cand, const SubCell *__restrict__ list,
+                                     int64_t nr1, int64_t vb0, const double2 *__restrict__ verts)
 {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= ncand) return;
-    const int64_t cell = cand[k];   // a + (nr1 - 1) b
+    if (list) return list[t];
+    SubCell c;
+    const int64_t cell = cand[t];
     const int64_t a = cell % (nr1 - 1), b = cell / (nr1 - 1);
-    SubCell st[STACK];
-    int top = 0;
-    {
-        SubCell &c = st[top++];
-        c.A0 = (double)a;
-        c.B0 = (double)b;
-        c.h = 1.0;
-        c.d = 0;
-        const double2 *r0 = verts + (b - vb0) * nr1, *r1 = r0 + nr1;
-        const double2 q[4] = {r0[a], r0[a + 1], r1[a + 1], r1[a]};
-        for (int m = 0; m < 4; ++m) {
-            c.u[m] = q[m].x;
-            c.v[m] = q[m].y;
+    c.A0 = (double)a;
+    c.B0 = (double)b;
+    c.h = 1.0;
+    c.d = 0;
+    const double2 *r0 = verts + (b - vb0) * nr1, *r1 = r0 + nr1;
+    const double2 q[4] = {r0[a], r0[a + 1], r1[a + 1], r1[a]};
+    for (int m = 0; m < 4; ++m) {
+        c.u[m] = q[m].x;
+        c.v[m] = q[m].y;
+    }
+    return c;
+}
+
+// flag[t] = the item is refined (and label[t] too, for candidate cells);
+// stats: [0] tested, [1] refined, [2] too large (one atomic per wavefront each)
+__global__ __launch_bounds__(RBLK) void k_refine_test(RefineArgs ra, int64_t n, const int64_t *__restrict__ cand,
+                                                      const SubCell *__restrict__ list, int64_t nr1, int64_t vb0,
+                                                      const double2 *__restrict__ verts, int32_t *__restrict__ flag,
+                                                      uint8_t *__restrict__ label,
+                                                      unsigned long long *__restrict__ stats)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int refine = 0, large = 0, tested = 0;
+    if (t < n) {
+        const SubCell c = level_item(t, cand, list, nr1, vb0, verts);
+        double gu[3][3], gv[3][3];
+        refine = refine_test(ra, c, gu, gv, large) ? 1 : 0;
+        tested = 1;
+        flag[t] = refine;
+        if (label) label[t] = (uint8_t)refine;
+    }
+    if (stats) {
+        int v[3] = {tested, refine, large};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+            if ((threadIdx.x & 63) == 0 && v[k]) atomicAdd(stats + k, (unsigned long long)v[k]);
         }
     }
-    unsigned long long n_test = 0, n_ref = 0, n_large = 0;
-    uint8_t lab = 0;
-    while (top > 0) {
-        const SubCell c = st[--top];
-        double gu[3][3], gv[3][3];
-        int large = 0;
-        ++n_test;
-        const bool refine = refine_test(ra, c, gu, gv, large);
-        n_large += large;
-        if (c.d == 0) lab = refine ? 1 : 0;
-        if (!refine) continue;
-        ++n_ref;
-        const double w = ra.g.tri_weight * c.h * c.h;
-        if (map) add_cell(ra, map, w, c.u, c.v, -1.0);
-        const double hh = 0.5 * c.h;
-        for (int r = 0; r < 2; ++r)
-            for (int s = 0; s < 2; ++s) {
-                SubCell ch;
-                ch.A0 = c.A0 + s * hh;
-                ch.B0 = c.B0 + r * hh;
-                ch.h = hh;
-                ch.d = c.d + 1;
-                const double cu[4] = {gu[r][s], gu[r][s + 1], gu[r + 1][s + 1], gu[r + 1][s]};
-                const double cv[4] = {gv[r][s], gv[r][s + 1], gv[r + 1][s + 1], gv[r + 1][s]};
-                for (int m = 0; m < 4; ++m) {
-                    ch.u[m] = cu[m];
-                    ch.v[m] = cv[m];
-                }
-                if (map) add_cell(ra, map, 0.25 * w, ch.u, ch.v, +1.0);   // a refined child takes it back itself
-                if (ch.d < ra.max_depth && top < STACK) st[top++] = ch;
+}
+
+// the refined items (flag[t]; pos: exclusive scan of the flags): the map
+// loses the item's deposits and gains its four children's, and the children
+// are written to out[4 pos[t] .. 4 pos[t] + 3]
+__global__ __launch_bounds__(RBLK) void k_refine_expand(RefineArgs ra, int64_t n, const int64_t *__restrict__ cand,
+                                                        const SubCell *__restrict__ list, int64_t nr1, int64_t vb0,
+                                                        const double2 *__restrict__ verts,
+                                                        const int32_t *__restrict__ flag,
+                                                        const int64_t *__restrict__ pos, double *__restrict__ map,
+                                                        SubCell *__restrict__ out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n || !flag[t]) return;
+    const SubCell c = level_item(t, cand, list, nr1, vb0, verts);
+    double gu[3][3], gv[3][3];
+    fill_grid(ra, c, gu, gv);
+    const double w = ra.g.tri_weight * c.h * c.h;
+    if (map) add_cell(ra, map, w, c.u, c.v, -1.0);
+    const double hh = 0.5 * c.h;
+    SubCell *dst = out + 4 * pos[t];
+    for (int r = 0; r < 2; ++r)
+        for (int s = 0; s < 2; ++s) {
+            SubCell ch;
+            ch.A0 = c.A0 + s * hh;
+            ch.B0 = c.B0 + r * hh;
+            ch.h = hh;
+            ch.d = c.d + 1;
+            const double cu[4] = {gu[r][s], gu[r][s + 1], gu[r + 1][s + 1], gu[r + 1][s]};
+            const double cv[4] = {gv[r][s], gv[r][s + 1], gv[r + 1][s + 1], gv[r + 1][s]};
+            for (int m = 0; m < 4; ++m) {
+                ch.u[m] = cu[m];
+                ch.v[m] = cv[m];
             }
-    }
-    label[k] = lab;
-    if (stats) {
-        atomicAdd(stats, n_test);
-        atomicAdd(stats + 1, n_ref);
-        atomicAdd(stats + 2, n_large);
-    }
+            if (map) add_cell(ra, map, 0.25 * w, ch.u, ch.v, +1.0);   // a refined child takes it back itself
+            dst[2 * r + s] = ch;
+        }
 }
 
 // features of every cell of a strip (cells [cb0, cb1) of the grid)
@@ -424,14 +455,28 @@ RefineArgs make_refine_args(const Tree &T, const Region &R, const LensConst &lc,
     return ra;
 }
 
-void launch_refine(const Tree &T, const Region &R, const LensConst &lc, const MapGeom &g, double tau, int depth,
-                   int window, int64_t ncand, const int64_t *cand, int64_t nr1, int64_t vb0, const double2 *verts,
-                   uint8_t *label, double *map, unsigned long long *stats, hipStream_t st)
+size_t refine_subcell_bytes() { return sizeof(SubCell); }
+
+void launch_refine_test(const Tree &T, const Region &R, const LensConst &lc, const MapGeom &g, double tau, int depth,
+                        int window, int64_t n, const int64_t *cand, const void *list, int64_t nr1, int64_t vb0,
+                        const double2 *verts, int32_t *flag, uint8_t *label, unsigned long long *stats, hipStream_t st)
 {
-    if (ncand <= 0) return;
+    if (n <= 0) return;
     const RefineArgs ra = make_refine_args(T, R, lc, g, tau, depth, window);
-    hipLaunchKernelGGL(k_refine, dim3((unsigned)((ncand + RBLK - 1) / RBLK)), dim3(RBLK), 0, st, ra, ncand, cand, nr1,
-                       vb0, verts, label, map, stats);
+    hipLaunchKernelGGL(k_refine_test, dim3((unsigned)((n + RBLK - 1) / RBLK)), dim3(RBLK), 0, st, ra, n, cand,
+                       static_cast<const SubCell *>(list), nr1, vb0, verts, flag, label, stats);
+}
+
+void launch_refine_expand(const Tree &T, const Region &R, const LensConst &lc, const MapGeom &g, double tau, int depth,
+                          int window, int64_t n, const int64_t *cand, const void *list, int64_t nr1, int64_t vb0,
+                          const double2 *verts, const int32_t *flag, const int64_t *pos, double *map, void *out,
+                          hipStream_t st)
+{
+    if (n <= 0) return;
+    const RefineArgs ra = make_refine_args(T, R, lc, g, tau, depth, window);
+    hipLaunchKernelGGL(k_refine_expand, dim3((unsigned)((n + RBLK - 1) / RBLK)), dim3(RBLK), 0, st, ra, n, cand,
+                       static_cast<const SubCell *>(list), nr1, vb0, verts, flag, pos, map,
+                       static_cast<SubCell *>(out));
 }
 
 void launch_cell_features(int64_t nr1, int64_t cb0, int64_t ncells, int64_t vb0, const double2 *verts, float *feats,

@@ -247,6 +247,48 @@ def test_tall_map_many_bands(mlm, orc):
     assert mu.sum() * pix * pix == pytest.approx(float(gold["dep_total"]), rel=1e-9)
 
 
+def test_large_triangle_chain_beside_cell_pass(mlm, orc):
+    """The large-triangle passes run on a second stream beside the cell pass
+    by default (band rows added atomically); with one_stream every kernel
+    runs on the request's stream.  The two agree to rounding (only the order
+    of the atomic sums differs), on the small workload with a caller's stream
+    and on the 1e5-star workload's map, and the default matches the oracle."""
+    import torch
+    wl = W.config("plain_small")
+    sf = wl.stars()
+    gl, ol = _pair(mlm, orc, 0.3, 0.0, 0.3, sf)
+    spec = _spec(wl, order=20)
+    ref = orc.magnification_map(ol, spec, method="fmm", p=20)
+    out = torch.empty((256, 256), dtype=torch.float64, device="cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        _, st2 = gl.map(out=out, **spec)
+    s.synchronize()
+    two = out.cpu().numpy()
+    one, st1 = gl.map(one_stream=1, **spec)
+    assert st1["n_big"] == st2["n_big"] > 0
+    rel, zok = _rel_map_err(two, one)
+    assert zok and rel.max() < 1e-12
+    rel, zok = _rel_map_err(two, ref.mu)
+    assert zok and rel.max() < 1e-9
+    big = W.config("plain_large")
+    sfb = big.stars()
+    L = big.lens
+    glb = mlm.Lens(L.kappa_star, L.kappa_smooth, L.gamma, torch.from_numpy(sfb.x).cuda(), torch.from_numpy(sfb.y).cuda(),
+                   torch.from_numpy(sfb.m).cuda())
+    specb = big.map.asdict()
+    a = torch.empty((specb["n2"], specb["n1"]), dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    _, sa = glb.map(out=a, timing=1, **specb)
+    _, sb = glb.map(out=b, timing=1, one_stream=1, **specb)
+    torch.cuda.synchronize()
+    pos = b > 0
+    worst = float(((a[pos] - b[pos]).abs() / b[pos]).max())
+    _report("two_streams_vs_one", max_rel=worst, ms_two=sa["t_total_ms"], ms_one=sb["t_total_ms"],
+            ipm_ms_two=sa["t_ipm_ms"], ipm_ms_one=sb["t_ipm_ms"])
+    assert bool((a[~pos].abs() < 1e-12).all()) and worst < 1e-10
+
+
 def test_map_device_output_and_stream(mlm, orc):
     import torch
     wl = W.config("plain_small")
