@@ -68,6 +68,7 @@ class Region(C.Structure):
         ("nray1", C.c_long), ("nray2", C.c_long),
         ("flux_fraction", C.c_double),
         ("dx1_set", C.c_double), ("dx2_set", C.c_double),
+        ("x1c_set", C.c_double), ("x2c_set", C.c_double), ("centre_set", C.c_long),
         ("kappa", C.c_double), ("lam1", C.c_double), ("lam2", C.c_double), ("mu_macro", C.c_double),
         ("mean_m", C.c_double), ("mean_m2", C.c_double), ("border", C.c_double),
         ("X1", C.c_double), ("X2", C.c_double), ("dX1", C.c_double), ("dX2", C.c_double),
@@ -92,17 +93,17 @@ def lib(path: Optional[str] = None):
         L.orc_alpha_direct.argtypes = [C.c_long, _dp, _dp, _dp, C.c_long, _dp, _dp, _dp, _dp, C.c_int]
         L.orc_alpha_direct_reversed.argtypes = [C.c_long, _dp, _dp, _dp, C.c_long, _dp, _dp, _dp, _dp]
         L.orc_lens_equation.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int, C.c_double, C.c_double,
-                                        C.c_long, _dp, _dp, _dp, _dp, _dp, _dp]
+                                        _dp, C.c_long, _dp, _dp, _dp, _dp, _dp, _dp]
         L.orc_sheet_alpha.argtypes = [C.c_double, C.c_int, C.c_double, C.c_double, C.c_long, _dp, _dp, _dp, _dp]
         L.orc_star_rect.argtypes = [C.c_long, _dp, C.c_double, C.c_double, _dp, _dp]
         L.orc_irs_rows.argtypes = [C.POINTER(Region), C.c_double, C.c_double, C.c_double, C.c_int, C.c_double,
-                                   C.c_double, C.c_long, _dp, _dp, _dp, C.c_void_p, C.c_long, C.c_long, _lp,
+                                   C.c_double, _dp, C.c_long, _dp, _dp, _dp, C.c_void_p, C.c_long, C.c_long, _lp,
                                    _dp, C.c_int]
         L.orc_irs_rows.restype = C.c_long
         L.orc_star_radius.argtypes = [C.c_long, _dp, C.c_double]
         L.orc_star_radius.restype = C.c_double
         L.orc_region_setup.argtypes = [C.POINTER(Region), C.c_double, C.c_double, C.c_double,
-                                       C.c_long, _dp, _dp, _dp]
+                                       C.c_long, _dp, _dp, _dp, C.c_int]
         L.orc_region_setup.restype = C.c_int
         L.orc_grid_points.argtypes = [C.POINTER(Region), C.c_long, C.c_long, _dp, _dp]
         L.orc_fmm_build.argtypes = [C.c_long, _dp, _dp, _dp, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int]
@@ -126,12 +127,12 @@ def lib(path: Optional[str] = None):
         L.orc_ipm_rows.argtypes = [C.POINTER(Region), C.c_long, C.c_long, _dp, _dp, _dp, _dp]
         L.orc_cell_features.argtypes = [_dp, _dp, _dp]
         L.orc_refine_cells.argtypes = [C.POINTER(Region), C.c_double, C.c_double, C.c_double, C.c_int, C.c_double,
-                                       C.c_double,
+                                       C.c_double, _dp,
                                        C.c_long, _dp, _dp, _dp, C.c_void_p, C.c_long, _lp, _lp, C.c_double,
                                        C.c_int, C.c_int, C.POINTER(C.c_ubyte), _dp, _lp]
         L.orc_normalise.argtypes = [C.POINTER(Region), _dp, _dp]
         L.orc_shoot_rows.argtypes = [C.POINTER(Region), C.c_double, C.c_double, C.c_double, C.c_int,
-                                     C.c_double, C.c_double, C.c_long, _dp, _dp, _dp, C.c_void_p, C.c_long,
+                                     C.c_double, C.c_double, _dp, C.c_long, _dp, _dp, _dp, C.c_void_p, C.c_long,
                                      C.c_long, _dp, _dp, C.c_int]
         _lib = L
     return _lib
@@ -163,9 +164,12 @@ class Lens:
     m: np.ndarray
     sheet: object = True
     rect_aspect: float = 0.0
+    psi3: object = None     # (psi_111, psi_112, psi_122, psi_222): third-order macro terms (app. D)
 
     def __post_init__(self):
         self.x, self.y, self.m = _f64(self.x), _f64(self.y), _f64(self.m)
+        self.psi3 = _f64(np.zeros(4) if self.psi3 is None else self.psi3)
+        assert self.psi3.shape == (4,)
         self.r_star = lib().orc_star_radius(len(self.m), _d(self.m), self.kappa_star)
         if self.sheet is True or self.sheet == "circle":
             self.sheet_code, self.e1, self.e2 = (1 if self.n else 0), self.r_star, self.r_star
@@ -200,7 +204,7 @@ def lens_equation(lens: Lens, zx, zy, ax, ay):
     zx, zy, ax, ay = map(_f64, (zx, zy, ax, ay))
     wx, wy = np.empty_like(zx), np.empty_like(zy)
     lib().orc_lens_equation(lens.kappa_star, lens.kappa_smooth, lens.gamma, lens.sheet_code,
-                            lens.e1, lens.e2, zx.size, _d(zx), _d(zy), _d(ax), _d(ay), _d(wx), _d(wy))
+                            lens.e1, lens.e2, _d(lens.psi3), zx.size, _d(zx), _d(zy), _d(ax), _d(ay), _d(wx), _d(wy))
     return wx, wy
 
 
@@ -228,11 +232,15 @@ class DegenerateMacro(ValueError):
 
 
 def region(lens: Lens, y1c=0.0, y2c=0.0, hw1=5.0, hw2=5.0, n1=256, n2=256, rays_per_pixel=1.0,
-           nray1=0, nray2=0, flux_fraction=0.01, dx1=0.0, dx2=0.0, **_ignored) -> Region:
+           nray1=0, nray2=0, flux_fraction=0.01, dx1=0.0, dx2=0.0, x1c=None, x2c=None, **_ignored) -> Region:
+    """Shooting region and ray grid; x1c/x2c give the image-plane centre
+    explicitly (needed, with dx1/dx2, when the lens has third-order terms)."""
+    centre = x1c is not None and x2c is not None
     R = Region(y1c=y1c, y2c=y2c, hw1=hw1, hw2=hw2, n1=n1, n2=n2, rays_per_pixel=rays_per_pixel,
-               nray1=nray1, nray2=nray2, flux_fraction=flux_fraction, dx1_set=dx1, dx2_set=dx2)
+               nray1=nray1, nray2=nray2, flux_fraction=flux_fraction, dx1_set=dx1, dx2_set=dx2,
+               x1c_set=x1c if centre else 0.0, x2c_set=x2c if centre else 0.0, centre_set=1 if centre else 0)
     rc = lib().orc_region_setup(C.byref(R), lens.kappa_star, lens.kappa_smooth, lens.gamma,
-                                lens.n, _d(lens.x), _d(lens.y), _d(lens.m))
+                                lens.n, _d(lens.x), _d(lens.y), _d(lens.m), 1 if np.any(lens.psi3 != 0) else 0)
     if rc == 2:
         raise DegenerateMacro("|1-kappa+-gamma| vanishes: shooting region is unbounded")
     if rc != 0:
@@ -375,7 +383,7 @@ def shoot_rows(R: Region, lens: Lens, row_lo: int, row_hi: int, fmm: Optional[FM
     n = (row_hi - row_lo) * R.nr1
     wx, wy = np.empty(n), np.empty(n)
     lib().orc_shoot_rows(C.byref(R), lens.kappa_star, lens.kappa_smooth, lens.gamma,
-                         lens.sheet_code, lens.e1, lens.e2, lens.n, _d(lens.x), _d(lens.y), _d(lens.m),
+                         lens.sheet_code, lens.e1, lens.e2, _d(lens.psi3), lens.n, _d(lens.x), _d(lens.y), _d(lens.m),
                          fmm.handle if fmm is not None else None, row_lo, row_hi, _d(wx), _d(wy),
                          nthreads)
     return wx, wy
@@ -461,7 +469,7 @@ def irs_map(lens: Lens, spec: dict, method: str = "direct", p: int = 0, rows=Non
     nrays = (row_hi - row_lo) * (R.nr1 - 1)
     uv = np.empty(2 * max(nrays, 1)) if want_uv else None
     out = lib().orc_irs_rows(C.byref(R), lens.kappa_star, lens.kappa_smooth, lens.gamma, lens.sheet_code,
-                             lens.e1, lens.e2, lens.n, _d(lens.x), _d(lens.y), _d(lens.m),
+                             lens.e1, lens.e2, _d(lens.psi3), lens.n, _d(lens.x), _d(lens.y), _d(lens.m),
                              fmm.handle if fmm is not None else None, row_lo, row_hi,
                              counts.ctypes.data_as(_lp), _d(uv) if want_uv else None, nthreads)
     mu = counts * (R.d1 * R.d2 / (R.pix1 * R.pix2))
@@ -502,7 +510,7 @@ def refine_cells(R: Region, lens: Lens, cells_a, cells_b, fmm: Optional[FMM] = N
     dep = np.zeros(R.n1 * R.n2)
     st = np.zeros(3, np.int64)
     lib().orc_refine_cells(C.byref(R), lens.kappa_star, lens.kappa_smooth, lens.gamma, lens.sheet_code,
-                           lens.e1, lens.e2, lens.n, _d(lens.x), _d(lens.y), _d(lens.m),
+                           lens.e1, lens.e2, _d(lens.psi3), lens.n, _d(lens.x), _d(lens.y), _d(lens.m),
                            fmm.handle if fmm is not None else None, ca.size, ca.ctypes.data_as(_lp),
                            cb.ctypes.data_as(_lp), tau, max_depth, window,
                            labels.ctypes.data_as(C.POINTER(C.c_ubyte)), _d(dep), st.ctypes.data_as(_lp))

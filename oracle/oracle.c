@@ -157,7 +157,28 @@ typedef struct {
     int sheet;           /* 0: none; 1: circular sheet of radius e1 = R_*;
                             2: rectangular sheet with corner (e1, e2) = (c1, c2) */
     double e1, e2;
+    double psi3[4];      /* third derivatives of the macro potential at the
+                            expansion point (app. D): psi_111, psi_112, psi_122, psi_222 */
 } orc_lens;
+
+static void lens_set_psi3(orc_lens *L, const double *psi3)
+{
+    for (int k = 0; k < 4; ++k) L->psi3[k] = psi3 ? psi3[k] : 0.0;
+}
+
+/*
+ * Deflection of the macro potential's third-order Taylor term (app. D: the
+ * potential expanded past second order near a macro critical curve),
+ * psi_3(x) = (1/6) sum_ijk psi_ijk x_i x_j x_k, i.e. its gradient
+ *   a_3,i = (1/2) sum_jk psi_ijk x_j x_k
+ * with the four independent psi_111, psi_112, psi_122, psi_222.
+ */
+static void macro3_alpha(const orc_lens *L, double x, double y, double *ax, double *ay)
+{
+    const double a = L->psi3[0], b = L->psi3[1], c = L->psi3[2], d = L->psi3[3];
+    *ax = 0.5 * (a * x * x + 2.0 * b * x * y + c * y * y);
+    *ay = 0.5 * (b * x * x + 2.0 * c * x * y + d * y * y);
+}
 
 /*
  * Deflection of a sheet of convergence -k_* spread over the rectangle
@@ -204,24 +225,27 @@ static void sheet_alpha(const orc_lens *L, double x, double y, double *sx, doubl
     }
 }
 
-/* w = (1-kappa) z + gamma conj(z) - a_*(z) - a_s(z), kappa = kappa_* + kappa_s */
+/* w = (1-kappa) z + gamma conj(z) - a_3(z) - a_*(z) - a_s(z), kappa = kappa_* + kappa_s
+   (a_3: the macro potential's third-order term, zero unless psi3 is set) */
 static void lens_equation(const orc_lens *L, double x, double y, double ax, double ay,
                           double *wx, double *wy)
 {
     double kappa = L->kappa_star + L->kappa_smooth;
     double w1 = (1.0 - kappa) * x + L->gamma * x - ax;
     double w2 = (1.0 - kappa) * y - L->gamma * y - ay;
-    double sx, sy;
+    double sx, sy, mx, my;
     sheet_alpha(L, x, y, &sx, &sy);
-    *wx = w1 - sx;
-    *wy = w2 - sy;
+    macro3_alpha(L, x, y, &mx, &my);
+    *wx = w1 - mx - sx;
+    *wy = w2 - my - sy;
 }
 
 void orc_lens_equation(double kappa_star, double kappa_smooth, double gamma, int sheet,
-                       double e1, double e2, long npts, const double *zx, const double *zy,
+                       double e1, double e2, const double *psi3, long npts, const double *zx, const double *zy,
                        const double *ax, const double *ay, double *wx, double *wy)
 {
-    orc_lens L = {kappa_star, kappa_smooth, gamma, sheet, e1, e2};
+    orc_lens L = {kappa_star, kappa_smooth, gamma, sheet, e1, e2, {0, 0, 0, 0}};
+    lens_set_psi3(&L, psi3);
     for (long q = 0; q < npts; ++q)
         lens_equation(&L, zx[q], zy[q], ax[q], ay[q], &wx[q], &wy[q]);
 }
@@ -230,7 +254,7 @@ void orc_lens_equation(double kappa_star, double kappa_smooth, double gamma, int
 void orc_sheet_alpha(double kappa_star, int sheet, double e1, double e2, long npts, const double *zx,
                      const double *zy, double *ax, double *ay)
 {
-    orc_lens L = {kappa_star, 0.0, 0.0, sheet, e1, e2};
+    orc_lens L = {kappa_star, 0.0, 0.0, sheet, e1, e2, {0, 0, 0, 0}};
     for (long q = 0; q < npts; ++q) sheet_alpha(&L, zx[q], zy[q], &ax[q], &ay[q]);
 }
 
@@ -267,6 +291,8 @@ typedef struct {
     long nray1, nray2;        /* explicit vertex counts (0: from rays_per_pixel) */
     double flux_fraction;     /* f of appendix A */
     double dx1_set, dx2_set;  /* explicit image-plane half-sizes (0: derived) */
+    double x1c_set, x2c_set;  /* explicit image-plane centre, used when centre_set */
+    long centre_set;
     /* outputs */
     double kappa, lam1, lam2, mu_macro;
     double mean_m, mean_m2, border;
@@ -287,13 +313,17 @@ typedef struct {
  * Returns 0 on success, 1 for invalid input, 2 for a degenerate macro model.
  */
 int orc_region_setup(orc_region *R, double kappa_star, double kappa_smooth, double gamma,
-                     long n, const double *sx, const double *sy, const double *sm)
+                     long n, const double *sx, const double *sy, const double *sm, int macro3)
 {
     if (!(R->hw1 > 0) || !(R->hw2 > 0) || R->n1 <= 0 || R->n2 <= 0) return 1;
     R->kappa = kappa_star + kappa_smooth;
     R->lam1 = 1.0 - R->kappa + gamma;
     R->lam2 = 1.0 - R->kappa - gamma;
-    if (fabs(R->lam1) < 1e-9 || fabs(R->lam2) < 1e-9) return 2;
+    /* with third-order macro terms (app. D) the images of the map need not sit
+       at the linear ones, and a critical line may cross the expansion point:
+       the caller gives the shooting region (centre and half-sizes) */
+    if (macro3 && !(R->centre_set && R->dx1_set > 0 && R->dx2_set > 0)) return 1;
+    if (!macro3 && (fabs(R->lam1) < 1e-9 || fabs(R->lam2) < 1e-9)) return 2;
     R->mu_macro = 1.0 / (R->lam1 * R->lam2);
 
     double s1 = 0.0, s2 = 0.0;
@@ -303,8 +333,8 @@ int orc_region_setup(orc_region *R, double kappa_star, double kappa_smooth, doub
     double f = R->flux_fraction > 0 ? R->flux_fraction : 0.01;
     R->border = (n && kappa_star > 0) ? sqrt(kappa_star * R->mean_m2 / (f * R->mean_m)) : 0.0;
 
-    R->X1 = R->y1c / R->lam1;
-    R->X2 = R->y2c / R->lam2;
+    R->X1 = R->centre_set ? R->x1c_set : R->y1c / R->lam1;
+    R->X2 = R->centre_set ? R->x2c_set : R->y2c / R->lam2;
     R->dX1 = R->dx1_set > 0 ? R->dx1_set : (R->hw1 + R->border) / fabs(R->lam1);
     R->dX2 = R->dx2_set > 0 ? R->dx2_set : (R->hw2 + R->border) / fabs(R->lam2);
     R->pix1 = 2.0 * R->hw1 / (double)R->n1;
@@ -1068,11 +1098,12 @@ static void shoot_rows(void *vctx, long lo, long hi)
 
 /* source positions of vertex rows [row_lo, row_hi) */
 void orc_shoot_rows(const orc_region *R, double kappa_star, double kappa_smooth, double gamma,
-                    int sheet, double e1, double e2, long n, const double *sx, const double *sy,
+                    int sheet, double e1, double e2, const double *psi3, long n, const double *sx, const double *sy,
                     const double *sm, const void *F, long row_lo, long row_hi,
                     double *wx, double *wy, int nthreads)
 {
-    orc_lens L = {kappa_star, kappa_smooth, gamma, sheet, e1, e2};
+    orc_lens L = {kappa_star, kappa_smooth, gamma, sheet, e1, e2, {0, 0, 0, 0}};
+    lens_set_psi3(&L, psi3);
     shoot_ctx c = {R, &L, n, sx, sy, sm, F, row_lo, wx, wy};
     parallel_for(row_hi - row_lo, nthreads, shoot_rows, &c);
 }
@@ -1119,10 +1150,11 @@ static void irs_shoot(void *vctx, long lo, long hi)
  * (u, v), row by row.  Returns the number of rays landing outside the map.
  */
 long orc_irs_rows(const orc_region *R, double kappa_star, double kappa_smooth, double gamma, int sheet,
-                  double e1, double e2, long n, const double *sx, const double *sy, const double *sm,
-                  const void *F, long row_lo, long row_hi, long *counts, double *uv, int nthreads)
+                  double e1, double e2, const double *psi3, long n, const double *sx, const double *sy,
+                  const double *sm, const void *F, long row_lo, long row_hi, long *counts, double *uv, int nthreads)
 {
-    orc_lens L = {kappa_star, kappa_smooth, gamma, sheet, e1, e2};
+    orc_lens L = {kappa_star, kappa_smooth, gamma, sheet, e1, e2, {0, 0, 0, 0}};
+    lens_set_psi3(&L, psi3);
     long nc = R->nr1 - 1, nrays = (row_hi - row_lo) * nc;
     double *wx = malloc((nrays > 0 ? nrays : 1) * sizeof(double));
     double *wy = malloc((nrays > 0 ? nrays : 1) * sizeof(double));
@@ -1323,13 +1355,14 @@ static int refine_rec(refine_ctx *c, double A0, double B0, double h, int d, cons
    normalised) receives the refined minus the plain deposits; stats =
    {tested (sub)cells, refined (sub)cells, skipped as too large}. */
 void orc_refine_cells(const orc_region *R, double kappa_star, double kappa_smooth, double gamma, int sheet,
-                      double e1, double e2, long n, const double *sx, const double *sy, const double *sm,
-                      const void *F,
+                      double e1, double e2, const double *psi3, long n, const double *sx, const double *sy,
+                      const double *sm, const void *F,
                       long ncells, const long *ca, const long *cb, double tau, int max_depth, int window,
                       unsigned char *label, double *dmap, long *stats)
 {
-    refine_ctx c = {R, {kappa_star, kappa_smooth, gamma, sheet, e1, e2}, n, sx, sy, sm, F, tau, max_depth, window,
-                    dmap, 0, 0, 0};
+    refine_ctx c = {R, {kappa_star, kappa_smooth, gamma, sheet, e1, e2, {0, 0, 0, 0}}, n, sx, sy, sm, F, tau,
+                    max_depth, window, dmap, 0, 0, 0};
+    lens_set_psi3(&c.L, psi3);
     for (long k = 0; k < ncells; ++k) {
         double u4[4], v4[4];
         double A = (double)ca[k], B = (double)cb[k];
