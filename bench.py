@@ -246,6 +246,38 @@ def paper_table1_variant() -> dict:
     return res
 
 
+def macrocaustic_variant() -> dict:
+    """A map across a macro fold caustic (the macro potential to third order,
+    app. D; workloads.macrocaustic): the library finds the macroimages of the
+    map inside the star disc and maps them in FP64."""
+    import torch
+    import paper_2506_02114_amd as mlm
+    import workloads as W
+    L, mspec, psi3 = W.macrocaustic()
+    sf = W.star_field(L.n_stars, L.kappa_star, "equal", seed=L.seed)
+    dev = torch.device("cuda:0")
+    lens = mlm.Lens(L.kappa_star, L.kappa_smooth, L.gamma, torch.from_numpy(sf.x).to(dev),
+                    torch.from_numpy(sf.y).to(dev), torch.from_numpy(sf.m).to(dev), psi3=psi3)
+    spec = mspec.asdict()
+    R = lens.region(**spec)
+    out = torch.empty((spec["n2"], spec["n1"]), dtype=torch.float64, device=dev)
+    lens.map(out=out, **spec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        _, st = lens.map(out=out, timing=1, **spec)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / 3
+    mu = out.cpu().numpy()
+    half = spec["n2"] // 2
+    print(f"[bench] macrocaustic: {sec * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    return {"stars": L.n_stars, "psi3": list(psi3), "rays": st["n_rays"], "order": st["order"],
+            "region": {k: R[k] for k in ("X1", "X2", "dX1", "dX2", "nr1", "nr2")}, "ms_per_map": sec * 1e3,
+            "rays_per_s": st["n_rays"] / sec, "stages_ms": {"tree": st["t_tree_ms"], "fmm": st["t_fmm_ms"],
+                                                            "shoot": st["t_shoot_ms"], "ipm": st["t_ipm_ms"]},
+            "mean_mu_below_caustic": float(mu[:half].mean()), "mean_mu_above_caustic": float(mu[half:].mean())}
+
+
 def learned_variant() -> dict:
     """The learned refinement (a small network flags the cells worth the
     refinement test): cells of two fields of the 1e5-star lens type and two
@@ -415,7 +447,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-check", action="store_true", help="only run the plain copy used to scale HBM counters")
     ap.add_argument("--no-variants", action="store_true", help="skip the mixed-precision and batched measurements")
-    ap.add_argument("--only", choices=["mixed", "batched", "table1", "highmag", "learned"],
+    ap.add_argument("--only", choices=["mixed", "batched", "table1", "highmag", "learned", "macrocaustic"],
                     help="run one variant alone (for profiling) and print it as the JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -434,7 +466,7 @@ def main():
     if args.only:
         torch.cuda.set_device(0)
         fn = {"batched": batched_variant, "table1": paper_table1_variant, "highmag": highmag_variant,
-              "learned": learned_variant}.get(args.only)
+              "learned": learned_variant, "macrocaustic": macrocaustic_variant}.get(args.only)
         if fn is None:
             print("--only mixed runs with the headline map: use the default run", file=sys.stderr)
             sys.exit(2)
@@ -568,6 +600,10 @@ def main():
             variants["learned_refinement"] = learned_variant()
         except Exception as e:
             variants["learned_refinement"] = {"error": str(e)}
+        try:
+            variants["macrocaustic"] = macrocaustic_variant()
+        except Exception as e:
+            variants["macrocaustic"] = {"error": str(e)}
         line["variants"] = variants
     if not args.no_cpu_baseline:
         # the machine's CPU share for one GPU is 16 threads

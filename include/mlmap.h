@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define MLM_ABI_VERSION 5
+#define MLM_ABI_VERSION 6
 
 typedef enum mlm_status {
     MLM_OK = 0,
@@ -95,6 +95,16 @@ typedef struct mlm_lens_params {
     int32_t sheet;
     int32_t reserved;
     double rect_aspect;
+    /* Third derivatives of the macro potential at the expansion point (app. D:
+     * near a macro critical curve the potential is expanded past second order):
+     * psi3 = (psi_111, psi_112, psi_122, psi_222).  The lens equation gains
+     * -a_3 with a_3,i = (1/2) sum_jk psi_ijk x_j x_k (the gradient of
+     * (1/6) sum_ijk psi_ijk x_i x_j x_k), in every kernel that shoots rays.
+     * All zero (the default): the second-order model of sec. 2.1.  With any
+     * nonzero, 1 - kappa -+ gamma may vanish (a fold through the expansion
+     * point), and the shooting region is the request's (x1c, x2c, dx1, dx2)
+     * when it sets centre_set, else derived as described at mlm_map_region. */
+    double psi3[4];
 } mlm_lens_params;
 
 typedef struct mlm_lens mlm_lens;
@@ -246,6 +256,10 @@ typedef struct mlm_map_request {
     int32_t one_stream;        /* 0 (default): the large-triangle passes of the IPM run on a
                                   second stream of the lens beside the cell pass (fork and join
                                   through events on req->stream); 1: every kernel on req->stream */
+    double x1c, x2c;           /* image-plane centre of the shooting region, used when
+                                  centre_set (with dx1, dx2 > 0 as its half-sizes) */
+    int32_t centre_set;
+    int32_t reserved3;
 } mlm_map_request;
 
 void mlm_map_request_init(mlm_map_request *req);

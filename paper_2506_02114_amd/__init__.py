@@ -46,7 +46,8 @@ class MLMError(RuntimeError):
 
 class LensParams(C.Structure):
     _fields_ = [("kappa_star", C.c_double), ("kappa_smooth", C.c_double), ("gamma", C.c_double),
-                ("sheet", C.c_int32), ("reserved", C.c_int32), ("rect_aspect", C.c_double)]
+                ("sheet", C.c_int32), ("reserved", C.c_int32), ("rect_aspect", C.c_double),
+                ("psi3", C.c_double * 4)]
 
 
 class LensInfo(C.Structure):
@@ -73,7 +74,8 @@ class MapRequest(C.Structure):
                 ("row_end", C.c_int64), ("stream", C.c_void_p), ("w_out", C.c_void_p),
                 ("timing", C.c_int32), ("refine", C.c_int32), ("refine_depth", C.c_int32),
                 ("refine_window", C.c_int32), ("refine_tau", C.c_double), ("refine_threshold", C.c_double),
-                ("refiner", C.c_void_p), ("mapping", C.c_int32), ("one_stream", C.c_int32)]
+                ("refiner", C.c_void_p), ("mapping", C.c_int32), ("one_stream", C.c_int32),
+                ("x1c", C.c_double), ("x2c", C.c_double), ("centre_set", C.c_int32), ("reserved3", C.c_int32)]
 
 
 class Region(C.Structure):
@@ -348,6 +350,10 @@ def make_request(**kw) -> MapRequest:
             if v is not None:
                 r.row_begin, r.row_end = int(v[0]), int(v[1])
             continue
+        if k in ("x1c", "x2c"):
+            if v is None:
+                continue
+            r.centre_set = 1
         if k not in REQUEST_KEYS:
             raise TypeError(f"unknown map request field {k!r}")
         setattr(r, k, v)
@@ -358,12 +364,15 @@ class Lens:
     """Macro model + star field resident on the GPU (see mlm_lens_create)."""
 
     def __init__(self, kappa_star: float, kappa_smooth: float, gamma: float, x, y, m, sheet=True,
-                 rect_aspect: float = 0.0):
+                 rect_aspect: float = 0.0, psi3=None):
         """sheet: True / "circle" (disc sheet), "rect" (rectangular sheet of
-        aspect c2 / c1 = rect_aspect), False / "none"."""
+        aspect c2 / c1 = rect_aspect), False / "none".  psi3: the macro
+        potential's third derivatives (psi_111, psi_112, psi_122, psi_222),
+        near a macro critical curve (None: second order only)."""
         L = _lib()
         self._h = C.c_void_p()
-        p = LensParams(kappa_star, kappa_smooth, gamma, _sheet_code(sheet), 0, rect_aspect)
+        p = LensParams(kappa_star, kappa_smooth, gamma, _sheet_code(sheet), 0, rect_aspect,
+                       (C.c_double * 4)(*([0.0] * 4 if psi3 is None else [float(v) for v in psi3])))
         if x is None:   # a field the library draws: see Lens.sampled
             return
         if _is_torch_cuda(x):

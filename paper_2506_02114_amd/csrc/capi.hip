@@ -497,6 +497,8 @@ void check_lens_params(const mlm_lens_params &P, int64_t n)
         fail(MLM_EINVAL, "a compensating sheet needs kappa_star > 0");
     if (P.sheet == MLM_SHEET_RECT && (!(P.rect_aspect > 0) || !std::isfinite(P.rect_aspect)))
         fail(MLM_EINVAL, "a rectangular sheet needs a finite rect_aspect > 0");
+    for (int k = 0; k < 4; ++k)
+        if (!std::isfinite(P.psi3[k])) fail(MLM_EINVAL, "psi3 must be finite");
 }
 
 // a lens from host copies of the stars (checked here); the library owns it
@@ -654,7 +656,9 @@ mlm_status mlm_field_cover(const mlm_lens_params *params, const mlm_field_params
     (void)field_count(g);
     double mm, mm2, X1, X2, dX1, dX2;
     field_moments(g, mm, mm2);
-    shooting_region(*params, mm, mm2, *req, X1, X2, dX1, dX2);
+    // (a lens with third-order terms needs its region stated here: with no
+    // star region yet there is nothing to search)
+    shooting_region(*params, mm, mm2, 0.0, 0.0, *req, X1, X2, dX1, dX2);
     const double a1 = std::fabs(X1) + dX1, a2 = std::fabs(X2) + dX2;
     if (f->shape == MLM_SHEET_RECT) {
         *extent1 = margin * a1;

@@ -116,8 +116,9 @@ struct LensConst {
     double kappa_star;
     double r_star2;         // R_*^2
     double c1, c2;          // corner of the star rectangle (rectangular sheet)
+    double psi3[4];         // third derivatives of the macro potential (app. D)
     int32_t sheet;          // 0: none, 1: circular sheet, 2: rectangular sheet
-    int32_t pad;
+    int32_t cubic;          // psi3 has a nonzero entry
 };
 
 // per-triangle data of the row-parallel IPM: counter-clockwise vertices
@@ -267,9 +268,11 @@ void field_extent(int shape, double kappa_star, double mass_sum, double aspect, 
 int64_t field_sample(const mlm_field_params &F, std::vector<double> &x, std::vector<double> &y,
                      std::vector<double> &m, double &e1, double &e2);
 // the shooting region's centre and half-sizes (sec. 2.3, app. A) for given
-// mass moments
-void shooting_region(const mlm_lens_params &P, double mean_m, double mean_m2, const mlm_map_request &q, double &X1,
-                     double &X2, double &dX1, double &dX2);
+// mass moments; (ext1, ext2): half-sizes of the star region's bounding box,
+// searched for the images of the map when the lens has third-order terms
+void shooting_region(const mlm_lens_params &P, double mean_m, double mean_m2, double ext1, double ext2,
+                     const mlm_map_request &q, double &X1, double &X2, double &dX1, double &dX2);
+bool has_psi3(const mlm_lens_params &P);
 
 // tree.hip
 void build_tree(mlm_lens *lens, const Region &R, const mlm_map_request &req, Tree &T,

@@ -283,7 +283,8 @@ LensConst lens_const(const mlm_lens *lens, const Region &R)
     lc.c1 = lens->ext1;
     lc.c2 = lens->ext2;
     lc.sheet = lens->n == 0 ? 0 : lens->params.sheet == MLM_SHEET_CIRCLE ? 1 : lens->params.sheet == MLM_SHEET_RECT ? 2 : 0;
-    lc.pad = 0;
+    for (int k = 0; k < 4; ++k) lc.psi3[k] = lens->params.psi3[k];
+    lc.cubic = has_psi3(lens->params) ? 1 : 0;
     return lc;
 }
 

@@ -83,9 +83,15 @@ __device__ inline void rect_sheet(double x, double y, double ks, double c1, doub
 __device__ inline void finish_vertex(const LensConst &lc, const MapGeom &g, double x, double y, double ax,
                                      double ay, double &w1, double &w2, double2 &uv)
 {
-    // macro model
+    // macro model, with its third-order term when the lens has one (app. D):
+    // the gradient of (1/6) sum psi_ijk x_i x_j x_k
     w1 = lc.lam1 * x - ax;
     w2 = lc.lam2 * y - ay;
+    if (lc.cubic) {
+        const double a = lc.psi3[0], b = lc.psi3[1], c = lc.psi3[2], d = lc.psi3[3];
+        w1 -= 0.5 * (a * x * x + 2.0 * b * x * y + c * y * y);
+        w2 -= 0.5 * (b * x * x + 2.0 * c * x * y + d * y * y);
+    }
     if (lc.sheet == 1) {
         // circular sheet: a_s = -k_* z inside R_*, -k_* R_*^2 / conj(z) outside
         double r2 = x * x + y * y;

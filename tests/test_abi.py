@@ -70,7 +70,7 @@ def test_struct_layouts_match_header(mlm):
 
 def test_version_and_status_strings(mlm):
     lib = mlm.load()
-    assert lib.mlm_abi_version() == 5
+    assert lib.mlm_abi_version() == 6
     assert lib.mlm_status_str(0) == b"MLM_OK"
     assert lib.mlm_status_str(2) == b"MLM_EDEGENERATE"
     assert lib.mlm_status_str(99) == b"MLM_UNKNOWN"

@@ -184,6 +184,28 @@ def config(name: str) -> Workload:
 CONFIGS = ("plain_small", "plain_large", "mixed_highmag")
 
 
+def macrocaustic(seed: int = 7):
+    """A map across a macro fold caustic (app. D): the macro model sits on
+    the critical line, 1 - kappa - gamma = 0, with kappa_* = 0.2, kappa_s =
+    0.3, gamma = 0.5 and the third derivative psi_222 = 0.002 (the others 0),
+    so y2 = -(psi_222 / 2) x2^2 along x2: sources below y2 = 0 have two
+    macroimages, those above none.  The map is 10 x 10 theta_* centred on
+    the caustic, 2000^2 px, 1 ray/px, equal masses; the star disc covers the
+    macroimages of the map widened by the border r (the library then finds
+    the images inside it) with a 1.2 margin.  The paper shows such a map
+    without stating its parameters.  Returns (lens spec, map spec, psi3)."""
+    ks, kss, g, d = 0.2, 0.3, 0.5, 0.002
+    f = 0.01
+    r = math.sqrt(ks / f)                       # border of app. A, equal masses
+    hw = 5.0
+    x1 = (hw + r) / abs(1.0 - ks - kss + g)
+    x2 = math.sqrt(2.0 * (hw + r) / d)          # outer edge of the macroimages
+    n = int(round(ks * (1.2 * math.hypot(x1, x2)) ** 2))
+    lens = LensSpec(ks, kss, g, n, "equal", seed=seed)
+    spec = MapSpec(y1c=0.0, y2c=0.0, hw1=hw, hw2=hw, n1=2000, n2=2000, flux_fraction=f)
+    return lens, spec, (0.0, 0.0, 0.0, d)
+
+
 def paper_table1(shape: str = "circle", seed: int = 1):
     """The paper's Table 1 map as far as the paper fixes it: kappa =
     kappa_* = gamma = 0.6 (its sec. 4.1 comparison lens), equal masses, a
