@@ -299,10 +299,15 @@ __global__ void k_map_big_bounds(const BatchMap *maps, int32_t nmaps, int64_t nt
 // device of the calls; calls are serialised by `mu`)
 // host threads (each with a stream of its own) that prepare a batch's maps
 constexpr int PREP_THREADS = 8;
+// slices of the persistent band pass: at least this many list entries, and
+// about this many items per chunk
+constexpr int64_t BAND_SLICE_MIN = 256;
+constexpr int64_t BAND_ITEMS_TARGET = 4096;
 
 struct BatchWs {
     std::mutex mu;
-    DevBuf maps, verts, tbig, toff, prep, rows, row0, bcnt, boffs, bcur, blist, counters, bounds, slice_map, slice_lo;
+    DevBuf maps, verts, tbig, toff, prep, rows, row0, bcnt, boffs, bcur, blist, counters, bounds, slice_map, slice_lo,
+        items, queue;
     hipStream_t prep_st[PREP_THREADS] = {};   // created on first use, default priority
 };
 
@@ -911,9 +916,34 @@ void map_impl(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_st
                     int32_t *blist = static_cast<int32_t *>(ws.bandlist.reserve((size_t)(nlist > 0 ? nlist : 1) * sizeof(int32_t)));
                     MLM_HIP(hipMemcpyAsync(bcur, boffs, (size_t)nbands * sizeof(unsigned long long), hipMemcpyDeviceToDevice, bst));
                     launch_band_scatter(nb, row0, rows, bh, nbands, bcur, blist, bst);
+                    // the persistent band pass: every band with a list, cut into
+                    // slices of at most `cut` entries
+                    std::vector<unsigned long long> hoff((size_t)nbands + 1);
+                    MLM_HIP(hipMemcpyAsync(hoff.data(), boffs, hoff.size() * sizeof(unsigned long long),
+                                           hipMemcpyDeviceToHost, bst));
+                    MLM_HIP(hipStreamSynchronize(bst));
+                    const int64_t cut = std::max<int64_t>(BAND_SLICE_MIN, nlist / BAND_ITEMS_TARGET);
+                    std::vector<BandItem> items;
+                    for (int64_t b = 0; b < nbands; ++b) {
+                        const int64_t lo = (int64_t)hoff[b], hi = (int64_t)hoff[b + 1];
+                        if (hi <= lo) continue;
+                        const int64_t k = (hi - lo + cut - 1) / cut;
+                        for (int64_t a = lo; a < hi; a += cut)
+                            items.push_back(BandItem{b, a, std::min(hi, a + cut), k > 1 ? 1 : 0, 0});
+                    }
+                    const int64_t nitems = (int64_t)items.size();
+                    BandItem *ditems =
+                        static_cast<BandItem *>(ws.bitems.reserve((size_t)std::max<int64_t>(nitems, 1) * sizeof(BandItem)));
+                    unsigned long long *queue =
+                        static_cast<unsigned long long *>(ws.bqueue.reserve(sizeof(unsigned long long)));
+                    if (nitems > 0) {
+                        MLM_HIP(hipMemcpyAsync(ditems, items.data(), (size_t)nitems * sizeof(BandItem),
+                                               hipMemcpyHostToDevice, bst));
+                        MLM_HIP(hipStreamSynchronize(bst));   // the host item table is released at the end of this block
+                    }
                     e_band0 = tm.mark_on(bst);
-                    launch_band(nbands, boffs, blist, prep, rows, bh, g, map, q.timing >= 2 ? cnt + 4 : nullptr, overlap,
-                                bst);
+                    launch_band_queue1(ditems, nitems, queue, blist, prep, rows, bh, g, map,
+                                       q.timing >= 2 ? cnt + 4 : nullptr, overlap, bst);
                     e_band1 = tm.mark_on(bst);
                 } else {
                     launch_big(nb, prep, rows, g, map, diff, st);
@@ -1452,8 +1482,29 @@ mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, i
                 static_cast<unsigned long long *>(B.bcur.reserve((size_t)bl * sizeof(unsigned long long)));
             MLM_HIP(hipMemcpyAsync(bcur, boffs, (size_t)bl * sizeof(unsigned long long), hipMemcpyDeviceToDevice, st));
             launch_band_scatter_batch(dmaps, ns, dsm, dsl, max_bands, row0, rows, bcur, blist, st);
+            // work items of the persistent band pass: every band with a list,
+            // cut into slices of at most `cut` entries so that the items number
+            // a few per workgroup the device holds
+            std::vector<unsigned long long> hoff((size_t)bl + 1);
+            MLM_HIP(hipMemcpyAsync(hoff.data(), boffs, hoff.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                   st));
             MLM_HIP(hipStreamSynchronize(st));   // the host slice tables are released at the end of this block
-            launch_band_batch(dmaps, nm, bl, boffs, blist, prep, rows, max_band_lds, st);
+            const int64_t cut = std::max<int64_t>(BAND_SLICE_MIN, nlist / BAND_ITEMS_TARGET);
+            std::vector<BandItem> items;
+            for (int64_t b = 0; b < bl; ++b) {
+                const int64_t lo = (int64_t)hoff[b], hi = (int64_t)hoff[b + 1];
+                if (hi <= lo) continue;
+                const int64_t k = (hi - lo + cut - 1) / cut;
+                for (int64_t a = lo; a < hi; a += cut)
+                    items.push_back(BandItem{b, a, std::min(hi, a + cut), k > 1 ? 1 : 0, 0});
+            }
+            const int64_t nitems = (int64_t)items.size();
+            BandItem *ditems = static_cast<BandItem *>(B.items.reserve((size_t)std::max<int64_t>(nitems, 1) * sizeof(BandItem)));
+            unsigned long long *queue = static_cast<unsigned long long *>(B.queue.reserve(sizeof(unsigned long long)));
+            if (nitems > 0)
+                MLM_HIP(hipMemcpyAsync(ditems, items.data(), (size_t)nitems * sizeof(BandItem), hipMemcpyHostToDevice, st));
+            launch_band_queue(dmaps, nm, ditems, nitems, queue, blist, prep, rows, max_band_lds, st);
+            MLM_HIP(hipStreamSynchronize(st));   // the host item table is released at the end of this block
         }
         const int ec = tm.mark();
         MLM_HIP(hipStreamSynchronize(st));   // the chunk's buffers are reused by the next one

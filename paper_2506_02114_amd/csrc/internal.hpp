@@ -171,6 +171,15 @@ struct BatchMap {
     int32_t bh, nbands, p, mixed;
 };
 
+// one work item of the batch's persistent band pass: a slice [lo, hi) of the
+// list of band `gband` (numbered over the batch's maps); `shared`: the band
+// is split over several items, so its rows are added to the map atomically
+struct BandItem {
+    int64_t gband;
+    int64_t lo, hi;
+    int32_t shared, pad;
+};
+
 // index of the map whose range [lo, next lo) holds item x (maps with empty
 // ranges are skipped: the last map whose lo <= x)
 template <class T>
@@ -219,7 +228,7 @@ struct Workspace {
     DevBuf ilist, mult, local, ops_m2m, ops_m2l, ops_l2l;
     DevBuf leaves, near, deriv, near_offs;
     DevBuf tile_off, tile_leaf, verts, map, wbuf, pts, counters, items, itemoff, tbig, tbigoff, bigprep, bigrows, bigrow0, rowoff, nbnd, nbndoff, diff, bandcnt, bandoff,
-        bandcur, bandlist, rfeat, rlogit, rflag, rpos, rcand, rlabel, rstats, irs_counts, rtflag, rtpos, rsub0, rsub1;
+        bandcur, bandlist, rfeat, rlogit, rflag, rpos, rcand, rlabel, rstats, irs_counts, rtflag, rtpos, rsub0, rsub1, bitems, bqueue;
     hipStream_t side = nullptr;           // second stream of a map: the large-triangle passes beside the cell pass
     hipEvent_t fork = nullptr, join = nullptr;
     void *pinned = nullptr;               // small pinned host buffer for read-backs
@@ -346,6 +355,12 @@ void launch_band_count_batch(const BatchMap *maps, int64_t nslices, const int32_
 void launch_band_scatter_batch(const BatchMap *maps, int64_t nslices, const int32_t *slice_map,
                                const int64_t *slice_lo, int32_t max_bands, const int32_t *row0, const int64_t *rows,
                                unsigned long long *cursor, int32_t *list, hipStream_t st);
+void launch_band_queue(const BatchMap *maps, int32_t nmaps, const BandItem *items, int64_t nitems,
+                       unsigned long long *queue, const int32_t *list, const BigPrep *prep, const int64_t *rows,
+                       int64_t lds_doubles, hipStream_t st);
+void launch_band_queue1(const BandItem *items, int64_t nitems, unsigned long long *queue, const int32_t *list,
+                        const BigPrep *prep, const int64_t *rows, int bh, const MapGeom &g, double *map,
+                        unsigned long long *work, bool atomic_all, hipStream_t st);
 void launch_band_batch(const BatchMap *maps, int32_t nmaps, int64_t nbands, const unsigned long long *band_off,
                        const int32_t *list, const BigPrep *prep, const int64_t *rows, int64_t lds_doubles,
                        hipStream_t st);

@@ -1235,6 +1235,61 @@ __global__ __launch_bounds__(BAND_THREADS) void k_band_batch(const BatchMap *__r
               nullptr, bdiff, wsum, false);
 }
 
+// The batch's band pass as one persistent launch: a grid the device holds at
+// once pulls work items from a device-wide counter until none are left.  An
+// item is a slice of one band's list (BandItem), so a heavy band is shared by
+// several workgroups instead of holding one while the others idle; a band
+// split into several items adds its rows to the map atomically.
+__global__ __launch_bounds__(BAND_THREADS) void k_band_queue(const BatchMap *__restrict__ maps, int32_t nmaps,
+                                                             const BandItem *__restrict__ items, int64_t nitems,
+                                                             unsigned long long *__restrict__ queue,
+                                                             const int32_t *__restrict__ list,
+                                                             const BigPrep *__restrict__ prep,
+                                                             const int64_t *__restrict__ rows)
+{
+    extern __shared__ double bdiff[];
+    __shared__ unsigned long long wsum[2];
+    __shared__ int64_t cur;
+    for (;;) {
+        if (threadIdx.x == 0) cur = (int64_t)atomicAdd(queue, 1ull);
+        __syncthreads();
+        const int64_t i = cur;
+        __syncthreads();   // every thread has read cur before the next item overwrites it
+        if (i >= nitems) break;   // the same for the whole workgroup
+        const BandItem it = items[i];
+        const int32_t m = batch_find(maps, nmaps, it.gband, &BatchMap::band_lo);
+        const BatchMap &d = maps[m];
+        band_rows(it.gband - d.band_lo, it.lo, it.hi, list, prep, rows, d.bh, d.g, d.map, nullptr, bdiff, wsum,
+                  it.shared != 0);
+    }
+}
+
+// The same for one map: items over its bands (BandItem.gband is the band);
+// with `atomic_all` every band's rows are added atomically (the cell pass
+// runs beside it).
+__global__ __launch_bounds__(BAND_THREADS) void k_band_queue1(const BandItem *__restrict__ items, int64_t nitems,
+                                                              unsigned long long *__restrict__ queue,
+                                                              const int32_t *__restrict__ list,
+                                                              const BigPrep *__restrict__ prep,
+                                                              const int64_t *__restrict__ rows, int bh, MapGeom g,
+                                                              double *__restrict__ map,
+                                                              unsigned long long *__restrict__ work, int atomic_all)
+{
+    extern __shared__ double bdiff[];
+    __shared__ unsigned long long wsum[2];
+    __shared__ int64_t cur;
+    for (;;) {
+        if (threadIdx.x == 0) cur = (int64_t)atomicAdd(queue, 1ull);
+        __syncthreads();
+        const int64_t i = cur;
+        __syncthreads();
+        if (i >= nitems) break;
+        const BandItem it = items[i];
+        band_rows(it.gband, it.lo, it.hi, list, prep, rows, bh, g, map, work, bdiff, wsum,
+                  atomic_all != 0 || it.shared != 0);
+    }
+}
+
 // band binning of a batch's large triangles.  The triangles of map m are
 // the contiguous range [big_lo, big_hi) of its BatchMap (they were gathered
 // in cell order); slice s of the launch holds up to BIN_TRIS of them and lies
@@ -1475,6 +1530,52 @@ void launch_big_gather_batch(const BatchMap *maps, int32_t nmaps, int64_t nctile
     if (nctiles > 0)
         hipLaunchKernelGGL(k_big_gather_batch, dim3((unsigned)nctiles), dim3(256), 0, st, maps, nmaps, tile_off, prep,
                            rows, row0);
+}
+
+static __global__ void k_zero_u64_1(unsigned long long *p) { *p = 0ull; }
+
+void launch_band_queue(const BatchMap *maps, int32_t nmaps, const BandItem *items, int64_t nitems,
+                       unsigned long long *queue, const int32_t *list, const BigPrep *prep, const int64_t *rows,
+                       int64_t lds_doubles, hipStream_t st)
+{
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_band_queue),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)(BAND_LDS_DOUBLES * sizeof(double)));
+    MLM_HIP(attr);
+    if (lds_doubles > BAND_LDS_DOUBLES) fail(MLM_EINVAL, "band of %lld doubles exceeds LDS", (long long)lds_doubles);
+    if (nitems <= 0) return;
+    const size_t shmem = (size_t)lds_doubles * sizeof(double);
+    // as many workgroups as the device holds at once at this LDS size
+    int dev = 0, cus = 0, per_cu = 0;
+    MLM_HIP(hipGetDevice(&dev));
+    MLM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    MLM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_band_queue),
+                                                         BAND_THREADS, shmem));
+    const int64_t grid = std::min<int64_t>(nitems, (int64_t)std::max(cus, 1) * std::max(per_cu, 1));
+    hipLaunchKernelGGL(k_zero_u64_1, dim3(1), dim3(1), 0, st, queue);
+    hipLaunchKernelGGL(k_band_queue, dim3((unsigned)grid), dim3(BAND_THREADS), shmem, st, maps, nmaps, items, nitems,
+                       queue, list, prep, rows);
+}
+
+void launch_band_queue1(const BandItem *items, int64_t nitems, unsigned long long *queue, const int32_t *list,
+                        const BigPrep *prep, const int64_t *rows, int bh, const MapGeom &g, double *map,
+                        unsigned long long *work, bool atomic_all, hipStream_t st)
+{
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_band_queue1),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)(BAND_LDS_DOUBLES * sizeof(double)));
+    MLM_HIP(attr);
+    if (nitems <= 0) return;
+    const size_t shmem = (size_t)bh * (size_t)g.n1 * sizeof(double);
+    int dev = 0, cus = 0, per_cu = 0;
+    MLM_HIP(hipGetDevice(&dev));
+    MLM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    MLM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_band_queue1),
+                                                         BAND_THREADS, shmem));
+    const int64_t grid = std::min<int64_t>(nitems, (int64_t)std::max(cus, 1) * std::max(per_cu, 1));
+    hipLaunchKernelGGL(k_zero_u64_1, dim3(1), dim3(1), 0, st, queue);
+    hipLaunchKernelGGL(k_band_queue1, dim3((unsigned)grid), dim3(BAND_THREADS), shmem, st, items, nitems, queue, list,
+                       prep, rows, bh, g, map, work, atomic_all ? 1 : 0);
 }
 
 void launch_band_count_batch(const BatchMap *maps, int64_t nslices, const int32_t *slice_map, const int64_t *slice_lo,
