@@ -341,9 +341,6 @@ void launch_band_count(int64_t nbig, const int32_t *row0, const int64_t *rows, i
                        hipStream_t st);
 void launch_band_scatter(int64_t nbig, const int32_t *row0, const int64_t *rows, int bh, int32_t nbands,
                          unsigned long long *cursor, int32_t *list, hipStream_t st);
-void launch_band(int32_t nbands, const unsigned long long *band_off, const int32_t *list, const BigPrep *prep,
-                 const int64_t *rows, int bh, const MapGeom &g, double *map, unsigned long long *work,
-                 bool atomic_flush, hipStream_t st);
 void launch_big_count(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int64_t vb0, const MapGeom &g,
                       int32_t *tile_big, hipStream_t st);
 void launch_ipm_batch(const BatchMap *maps, int32_t nmaps, int64_t nctiles, int32_t *tile_big, hipStream_t st);
@@ -361,9 +358,6 @@ void launch_band_queue(const BatchMap *maps, int32_t nmaps, const BandItem *item
 void launch_band_queue1(const BandItem *items, int64_t nitems, unsigned long long *queue, const int32_t *list,
                         const BigPrep *prep, const int64_t *rows, int bh, const MapGeom &g, double *map,
                         unsigned long long *work, bool atomic_all, hipStream_t st);
-void launch_band_batch(const BatchMap *maps, int32_t nmaps, int64_t nbands, const unsigned long long *band_off,
-                       const int32_t *list, const BigPrep *prep, const int64_t *rows, int64_t lds_doubles,
-                       hipStream_t st);
 int64_t scan_i32_to_u64(mlm_lens *lens, const int32_t *in, unsigned long long *out, int64_t n, hipStream_t st);
 
 // scan.hip: device-wide prefix sums (tmp: scan_tmp_bytes(n)); the total is

@@ -1053,8 +1053,8 @@ __global__ __launch_bounds__(256) void k_band_scatter(int64_t nbig, const int32_
     bin_scatter(lo, min(lo + BIN_TRIS, nbig), row0, rows, bh, nbands, sh, cursor, list);
 }
 
-// One workgroup per band of bh pixel rows; a thread takes one (listed
-// triangle, band row) item at a time.  Within a pixel row the triangle's area
+// A workgroup takes a band of bh pixel rows (or a slice of its list); a
+// thread takes one (listed triangle, band row) item at a time.  Within a pixel row the triangle's area
 // left of u = c is G(c) = -sum_e dv_e J_e(c), J_e(c) = I(c - ua_e, c - ub_e)
 // over the edges clipped to the row, so pixel i receives
 // sum_e delta_e(i), delta_e(i) = -dv_e (J_e(i + 1) - J_e(i)).  delta_e is zero
@@ -1063,15 +1063,10 @@ __global__ __launch_bounds__(256) void k_band_scatter(int64_t nbig, const int32_
 // D(i) = delta(i) - delta(i - 1), which an edge changes only at those columns
 // and the one after, and a prefix sum along the row gives the pixel areas
 // (the covered interior costs nothing).  Columns left of the map fold into
-// column 0, those right of it are dropped.  The band owns its rows, so the
-// differences live in LDS and no device-wide atomic is needed.
-// consecutive bands on one XCD (workgroups go round-robin over the 8 XCDs),
-// so a triangle's set-up read by neighbouring bands stays in that L2
-__device__ inline int64_t xcd_band(int64_t blk, int64_t nb)
-{
-    const int64_t per = nb / 8, rem = nb % 8, x = blk % 8, idx = blk / 8;
-    return x < rem ? x * (per + 1) + idx : rem * (per + 1) + (x - rem) * per + idx;
-}
+// column 0, those right of it are dropped.  The differences live in LDS, so
+// no device-wide atomic is needed per deposit; the rows are added to the map
+// once per band (atomically when the band is shared or the cell pass runs
+// beside it).
 
 // edge P->Q clipped to the pixel row rl <= v <= rl + 1 (su = du/dv): the u of
 // its ends and its extent dv; false if it has none in the row (an edge with
@@ -1202,37 +1197,6 @@ __device__ inline void band_rows(int64_t band, int64_t r0, int64_t r1, const int
         if (threadIdx.x < 2 && wsum[threadIdx.x]) atomicAdd(work + threadIdx.x, wsum[threadIdx.x]);
     }
     __syncthreads();   // the LDS may be reused for the workgroup's next band
-}
-
-__global__ __launch_bounds__(BAND_THREADS) void k_band(const unsigned long long *__restrict__ band_off,
-                                                       const int32_t *__restrict__ list,
-                                                       const BigPrep *__restrict__ prep,
-                                                       const int64_t *__restrict__ rows, int bh, MapGeom g,
-                                                       double *__restrict__ map, unsigned long long *__restrict__ work,
-                                                       int atomic_flush)
-{
-    extern __shared__ double bdiff[];      // bh x n1 differences
-    __shared__ unsigned long long wsum[2];
-    const int64_t band = xcd_band(blockIdx.x, gridDim.x);
-    band_rows(band, (int64_t)band_off[band], (int64_t)band_off[band + 1], list, prep, rows, bh, g, map, work, bdiff,
-              wsum, atomic_flush != 0);
-}
-
-// the bands of every map of a fused batch (band_off and list over the
-// batch's global band numbers)
-__global__ __launch_bounds__(BAND_THREADS) void k_band_batch(const BatchMap *__restrict__ maps, int32_t nmaps,
-                                                             const unsigned long long *__restrict__ band_off,
-                                                             const int32_t *__restrict__ list,
-                                                             const BigPrep *__restrict__ prep,
-                                                             const int64_t *__restrict__ rows)
-{
-    extern __shared__ double bdiff[];
-    __shared__ unsigned long long wsum[2];
-    const int64_t gb = xcd_band(blockIdx.x, gridDim.x);
-    const int32_t m = batch_find(maps, nmaps, gb, &BatchMap::band_lo);
-    const BatchMap &d = maps[m];
-    band_rows(gb - d.band_lo, (int64_t)band_off[gb], (int64_t)band_off[gb + 1], list, prep, rows, d.bh, d.g, d.map,
-              nullptr, bdiff, wsum, false);
 }
 
 // The batch's band pass as one persistent launch: a grid the device holds at
@@ -1503,19 +1467,6 @@ void launch_band_scatter(int64_t nbig, const int32_t *row0, const int64_t *rows,
     MLM_HIP(hipGetLastError());
 }
 
-void launch_band(int32_t nbands, const unsigned long long *band_off, const int32_t *list, const BigPrep *prep,
-                 const int64_t *rows, int bh, const MapGeom &g, double *map, unsigned long long *work,
-                 bool atomic_flush, hipStream_t st)
-{
-    size_t shmem = (size_t)bh * (size_t)g.n1 * sizeof(double);
-    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_band),
-                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                       (int)(BAND_LDS_DOUBLES * sizeof(double)));
-    MLM_HIP(attr);
-    if (nbands > 0)
-        hipLaunchKernelGGL(k_band, dim3((unsigned)nbands), dim3(BAND_THREADS), shmem, st, band_off, list, prep, rows, bh,
-                           g, map, work, atomic_flush ? 1 : 0);
-}
 
 void launch_ipm_batch(const BatchMap *maps, int32_t nmaps, int64_t nctiles, int32_t *tile_big, hipStream_t st)
 {
@@ -1602,19 +1553,6 @@ void launch_band_scatter_batch(const BatchMap *maps, int64_t nslices, const int3
     MLM_HIP(hipGetLastError());
 }
 
-void launch_band_batch(const BatchMap *maps, int32_t nmaps, int64_t nbands, const unsigned long long *band_off,
-                       const int32_t *list, const BigPrep *prep, const int64_t *rows, int64_t lds_doubles,
-                       hipStream_t st)
-{
-    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_band_batch),
-                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                       (int)(BAND_LDS_DOUBLES * sizeof(double)));
-    MLM_HIP(attr);
-    if (lds_doubles > BAND_LDS_DOUBLES) fail(MLM_EINVAL, "band of %lld doubles exceeds LDS", (long long)lds_doubles);
-    if (nbands > 0)
-        hipLaunchKernelGGL(k_band_batch, dim3((unsigned)nbands), dim3(BAND_THREADS), (size_t)lds_doubles * sizeof(double),
-                           st, maps, nmaps, band_off, list, prep, rows);
-}
 
 void launch_count_pieces(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int64_t vb0, const MapGeom &g,
                          unsigned long long *out, hipStream_t st)
