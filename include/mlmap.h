@@ -489,7 +489,8 @@ typedef struct mlm_batch_opts {
 
 typedef struct mlm_batch_stats {
     int64_t n_maps, n_chunks, n_rays, n_cells, n_big;
-    double t_prep_ms;        /* trees, FMM, leaf tables, tile plans (and tuning) */
+    double t_prep_ms;        /* host wall time of the preparing threads (trees, FMM, leaf tables,
+                                tile plans, tuning); the map passes of prepared chunks overlap it */
     double t_shoot_ms;       /* fused ray shooting */
     double t_ipm_ms;         /* fused IPM passes */
     double t_total_ms;       /* whole call, device time */

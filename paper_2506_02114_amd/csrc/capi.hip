@@ -10,6 +10,8 @@
 #include <mutex>
 #include <new>
 #include <set>
+#include <chrono>
+#include <condition_variable>
 #include <thread>
 #include <tuple>
 #include <vector>
@@ -309,6 +311,7 @@ struct BatchWs {
     DevBuf maps, verts, tbig, toff, prep, rows, row0, bcnt, boffs, bcur, blist, counters, bounds, slice_map, slice_lo,
         items, queue;
     hipStream_t prep_st[PREP_THREADS] = {};   // created on first use, default priority
+    std::vector<hipEvent_t> ready;            // per map: prepared (recorded on its preparing stream)
 };
 
 BatchWs &batch_ws()
@@ -1310,12 +1313,48 @@ mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, i
             setup_region(lenses[i], &qi, &Ri);
             (void)tune_leaf_max(lenses[i], qi, Ri, st);
         }
+    // Regions, sizes and the chunks first (host arithmetic only): chunks of
+    // consecutive maps that fit the vertex budget, one fused launch per stage
+    // for all maps of a chunk.
+    int64_t max_verts = 0;
+    for (int32_t i = 0; i < nmaps; ++i) {
+        MapPlan &m = P[i];
+        m.lens = lenses[i];
+        m.q = reqs[i];
+        setup_region(m.lens, &m.q, &m.R);
+        if (m.R.nr1 > INT32_MAX || m.R.nr2 > INT32_MAX) fail(MLM_ERANGE, "map %d: ray grid too large", i);
+        m.bh = band_height(m.q.n1, m.q.n2);
+        if (m.bh <= 0) fail(MLM_ENOTSUP, "map %d: %d x %d pixels is too wide for batched row bands", i, m.q.n1, m.q.n2);
+        m.nbands = (m.q.n2 + m.bh - 1) / m.bh;
+        m.nverts = m.R.nr1 * m.R.nr2;
+        m.ncells = (m.R.nr1 - 1) * (m.R.nr2 - 1);
+        m.nctiles = ((m.R.nr1 - 1 + 15) / 16) * ((m.R.nr2 - 1 + 15) / 16);
+        max_verts = std::max(max_verts, m.nverts);
+    }
+    const int64_t budget = std::max<int64_t>(o.vertex_budget > 0 ? o.vertex_budget : (1ll << 28), max_verts);
+    std::vector<int32_t> chunk_lo;
+    for (int32_t c0 = 0; c0 < nmaps;) {
+        chunk_lo.push_back(c0);
+        int32_t c1 = c0;
+        int64_t sv = 0;
+        while (c1 < nmaps && (c1 == c0 || sv + P[c1].nverts <= budget)) sv += P[c1++].nverts;
+        c0 = c1;
+    }
+    chunk_lo.push_back(nmaps);
+
     // A tree is built level by level with a host read of each level's size,
-    // so one stream would idle between levels: PREP_THREADS host threads
-    // take the maps in turn, each on a stream of its own that first waits for
-    // the caller's stream.
+    // so one stream would idle between levels: PREP_THREADS host threads take
+    // the maps in order, each on a stream of its own that first waits for the
+    // caller's stream; a prepared map records an event there.  The chunks'
+    // map passes start on the caller's stream as soon as their maps are
+    // prepared, while the threads go on with later maps.
     for (hipStream_t &ps : B.prep_st)
         if (!ps) MLM_HIP(hipStreamCreateWithFlags(&ps, hipStreamNonBlocking));
+    while ((int32_t)B.ready.size() < nmaps) {
+        hipEvent_t e;
+        MLM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        B.ready.push_back(e);
+    }
     hipEvent_t go;
     MLM_HIP(hipEventCreateWithFlags(&go, hipEventDisableTiming));
     MLM_HIP(hipEventRecord(go, st));
@@ -1324,7 +1363,11 @@ mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, i
     std::atomic<int32_t> next{0};
     std::atomic<bool> failed{false};
     std::exception_ptr err;
-    std::mutex err_mu;
+    std::mutex done_mu;                     // guards done[], err
+    std::condition_variable done_cv;
+    std::vector<char> done((size_t)nmaps, 0);
+    std::atomic<double> prep_ms{0.0};
+    const auto t_prep0 = std::chrono::steady_clock::now();
     auto prep_worker = [&](int t) {
         const hipStream_t ps = B.prep_st[t];
         Timer &pt = *ptm[t];
@@ -1332,10 +1375,6 @@ mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, i
             MLM_HIP(hipStreamWaitEvent(ps, go, 0));
             for (int32_t i = next++; i < nmaps && !failed; i = next++) {
                 MapPlan &m = P[i];
-                m.lens = lenses[i];
-                m.q = reqs[i];
-                setup_region(m.lens, &m.q, &m.R);
-                if (m.R.nr1 > INT32_MAX || m.R.nr2 > INT32_MAX) fail(MLM_ERANGE, "map %d: ray grid too large", i);
                 if (o.autotune) m.q.leaf_max = tune_leaf_max(m.lens, m.q, m.R, ps);
                 m.tm = &pt;
                 m.e_tree0 = pt.mark();
@@ -1351,48 +1390,70 @@ mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, i
                 const int64_t npix = (int64_t)m.q.n1 * m.q.n2;
                 m.map = m.q.device_out ? mus[i] : static_cast<double *>(m.lens->ws.map.reserve(npix * sizeof(double)));
                 fill(m.map, npix, 0.0, ps);
-                m.nverts = m.R.nr1 * m.R.nr2;
-                m.ncells = (m.R.nr1 - 1) * (m.R.nr2 - 1);
-                m.nctiles = ((m.R.nr1 - 1 + 15) / 16) * ((m.R.nr2 - 1 + 15) / 16);
-                m.bh = band_height(m.q.n1, m.q.n2);
-                if (m.bh <= 0)
-                    fail(MLM_ENOTSUP, "map %d: %d x %d pixels is too wide for batched row bands", i, m.q.n1, m.q.n2);
-                m.nbands = (m.q.n2 + m.bh - 1) / m.bh;
+                MLM_HIP(hipEventRecord(B.ready[i], ps));
+                {
+                    std::lock_guard<std::mutex> g(done_mu);
+                    done[i] = 1;
+                }
+                done_cv.notify_all();
             }
             MLM_HIP(hipStreamSynchronize(ps));
         } catch (...) {
             failed = true;
             (void)hipStreamSynchronize(ps);
-            std::lock_guard<std::mutex> g(err_mu);
-            if (!err) err = std::current_exception();
+            {
+                std::lock_guard<std::mutex> g(done_mu);
+                if (!err) err = std::current_exception();
+            }
+            done_cv.notify_all();
+        }
+        const double ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_prep0).count();
+        double cur = prep_ms.load();
+        while (ms > cur && !prep_ms.compare_exchange_weak(cur, ms)) {
         }
     };
-    {
-        std::vector<std::thread> pool;
-        for (int t = 1; t < PREP_THREADS; ++t) pool.emplace_back(prep_worker, t);
-        prep_worker(0);
-        for (std::thread &th : pool) th.join();
-    }
-    (void)hipEventDestroy(go);
-    if (err) std::rethrow_exception(err);
-    int64_t max_verts = 0, max_band_lds = 0;
-    for (const MapPlan &m : P) {
-        max_verts = std::max(max_verts, m.nverts);
-        max_band_lds = std::max<int64_t>(max_band_lds, (int64_t)m.bh * m.q.n1);
-    }
-    const int e_prep = tm.mark();
+    std::vector<std::thread> pool;
+    for (int t = 0; t < PREP_THREADS; ++t) pool.emplace_back(prep_worker, t);
+    // the preparing threads are joined on every way out of this call
+    struct Joiner {
+        std::vector<std::thread> &pool;
+        std::atomic<bool> &failed;
+        ~Joiner()
+        {
+            bool any = false;
+            for (std::thread &th : pool) any = any || th.joinable();
+            if (!any) return;
+            failed = true;   // leaving early: the threads stop at their next map
+            for (std::thread &th : pool)
+                if (th.joinable()) th.join();
+        }
+    } joiner{pool, failed};
 
     // chunks of consecutive maps that fit the vertex budget: one fused launch
     // per stage for all maps of a chunk
-    const int64_t budget = std::max<int64_t>(o.vertex_budget > 0 ? o.vertex_budget : (1ll << 28), max_verts);
     double t_shoot = 0.0, t_ipm = 0.0;
     int64_t n_chunks = 0, n_big = 0, n_rays = 0, n_cells = 0;
     std::vector<BatchMap> hm;
-    for (int32_t c0 = 0; c0 < nmaps; ++n_chunks) {
-        int32_t c1 = c0;
-        int64_t sv = 0;
-        while (c1 < nmaps && (c1 == c0 || sv + P[c1].nverts <= budget)) sv += P[c1++].nverts;
+    for (size_t ci = 0; ci + 1 < chunk_lo.size(); ++ci, ++n_chunks) {
+        const int32_t c0 = chunk_lo[ci], c1 = chunk_lo[ci + 1];
+        {   // the chunk's maps prepared (or a preparing thread failed)
+            std::unique_lock<std::mutex> g(done_mu);
+            done_cv.wait(g, [&] {
+                if (err) return true;
+                for (int32_t i = c0; i < c1; ++i)
+                    if (!done[i]) return false;
+                return true;
+            });
+            if (err) break;
+        }
+        for (int32_t i = c0; i < c1; ++i) MLM_HIP(hipStreamWaitEvent(st, B.ready[i], 0));
         const int32_t nm = c1 - c0;
+        int64_t sv = 0, max_band_lds = 0;
+        for (int32_t i = c0; i < c1; ++i) {
+            sv += P[i].nverts;
+            max_band_lds = std::max<int64_t>(max_band_lds, (int64_t)P[i].bh * P[i].q.n1);
+        }
         double2 *verts = static_cast<double2 *>(B.verts.reserve((size_t)sv * sizeof(double2)));
         hm.assign(nm, BatchMap{});
         int64_t vo = 0, tl = 0, ctl = 0, cl = 0, bl = 0;
@@ -1513,8 +1574,10 @@ mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, i
         n_big += nb;
         n_rays += vo;
         n_cells += cl;
-        c0 = c1;
     }
+    for (std::thread &th : pool) th.join();
+    (void)hipEventDestroy(go);
+    if (err) std::rethrow_exception(err);
     std::vector<unsigned long long> hc((size_t)nmaps * 8);
     MLM_HIP(hipMemcpyAsync(hc.data(), cnt, hc.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     for (int32_t i = 0; i < nmaps; ++i)
@@ -1548,7 +1611,7 @@ mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, i
         b.n_rays = n_rays;
         b.n_cells = n_cells;
         b.n_big = n_big;
-        b.t_prep_ms = tm.ms(e_start, e_prep);
+        b.t_prep_ms = prep_ms.load();
         b.t_shoot_ms = t_shoot;
         b.t_ipm_ms = t_ipm;
         b.t_total_ms = tm.ms(e_start, e_end);

@@ -177,12 +177,16 @@ template <> struct V4T<double> {
     __device__ static int row(int i, int g4) { return 4 * i + g4; }
 };
 
-// row stride of the LDS matrix: one element more than its 64 columns, so the
-// 32 rows of a column fall in different banks
-constexpr int BRS = 65;
+// The sources of a node go through the matrix cores in groups of GS: a
+// group's scaled coefficients fill a 32 x 2 GS block of LDS (row stride BRS,
+// one more than its columns so the rows of a column fall in other banks), so
+// a node's wavefront needs 9 KB of LDS, not the 17 KB that all 27 sources at
+// once would take, and more wavefronts fit a CU.
+constexpr int GS = 16;
+constexpr int BRS = 2 * GS + 1;
 template <class R> struct DownLds {
-    R B[32 * BRS];         // scaled source coefficients: row k - 1, columns (2 s, 2 s + 1) = (re, im) of
-                           // source s; then, in place, P B
+    R B[32 * BRS];         // a group's scaled source coefficients: row k - 1, columns (2 s, 2 s + 1) =
+                           // (re, im) of source s of the group; then, in place, P B
     typename Cx<R>::c2 b0[32];
     int off[32], src[32];
 };
@@ -231,39 +235,56 @@ __global__ __launch_bounds__(64) void k_downward(int64_t lo, int64_t hi, int lev
         L.b0[slot] = mult[(int64_t)en.src * P1];
     }
     wave_sync();
-    // B: b_k (-z0)^-k for k = 1..p (rows k - 1), zero elsewhere up to the tiles used
-    // (only the rows the products read: 16 for p <= 16, else 32)
-    const int ncol = ((2 * ns + 15) / 16) * 16;
+    // M2L, coefficient l = lane: sum over the sources of z0^-l (y_l - b_0 / l),
+    // y = P B with B the coefficients b_k (-z0)^-k (rows k - 1 = 0 .. p - 1;
+    // only the rows the products read: 16 for p <= 16, else 32)
+    const int l = lane;
+    const R il = l > 0 ? (R)1 / (R)l : (R)0;
+    C2 acc = Cx<R>::make(0, 0);
     const int lgr = p <= 16 ? 4 : 5;
-    for (int e = lane; e < (ncol / 2) << lgr; e += 64) {
-        const int k1 = e & ((1 << lgr) - 1), s2 = e >> lgr;   // row k1 = k - 1, source s2
-        R re = 0, im = 0;
-        if (s2 < ns && k1 < p) {
-            const C2 b = mult[(int64_t)L.src[s2] * P1 + k1 + 1], f = Sf[L.off[s2] * 32 + k1 + 1];
-            re = b.x * f.x - b.y * f.y;
-            im = b.x * f.y + b.y * f.x;
-        }
-        L.B[k1 * BRS + 2 * s2] = re;
-        L.B[k1 * BRS + 2 * s2 + 1] = im;
-    }
-    wave_sync();
-    // Y = P B on the matrix cores, in place: a 16-column block of B is read
-    // whole (both 16-row tiles of P) before Y's block overwrites it
     const int mt_n = (p + 15) / 16, kt_n = (p + 3) / 4;
     const int r = lane & 15, g4 = lane >> 4;
-    for (int nt = 0; nt < ncol / 16; ++nt) {
-        V4 acc0 = {}, acc1 = {};
-        for (int ks = 0; ks < kt_n; ++ks) {
-            const R b = L.B[(ks * 4 + g4) * BRS + nt * 16 + r];
-            acc0 = mma16(Pm[r * 32 + ks * 4 + g4], b, acc0);
-            if (mt_n > 1) acc1 = mma16(Pm[(16 + r) * 32 + ks * 4 + g4], b, acc1);
+    for (int g0 = 0; g0 < ns; g0 += GS) {
+        const int gn = min(GS, ns - g0);
+        const int ncol = ((2 * gn + 15) / 16) * 16;
+        for (int e = lane; e < (ncol / 2) << lgr; e += 64) {
+            const int k1 = e & ((1 << lgr) - 1), s2 = e >> lgr;   // row k1 = k - 1, source g0 + s2
+            R re = 0, im = 0;
+            if (s2 < gn && k1 < p) {
+                const C2 b = mult[(int64_t)L.src[g0 + s2] * P1 + k1 + 1], f = Sf[L.off[g0 + s2] * 32 + k1 + 1];
+                re = b.x * f.x - b.y * f.y;
+                im = b.x * f.y + b.y * f.x;
+            }
+            L.B[k1 * BRS + 2 * s2] = re;
+            L.B[k1 * BRS + 2 * s2 + 1] = im;
         }
         wave_sync();
+        // Y = P B on the matrix cores, in place: a 16-column block of B is read
+        // whole (both 16-row tiles of P) before Y's block overwrites it
+        for (int nt = 0; nt < ncol / 16; ++nt) {
+            V4 acc0 = {}, acc1 = {};
+            for (int ks = 0; ks < kt_n; ++ks) {
+                const R b = L.B[(ks * 4 + g4) * BRS + nt * 16 + r];
+                acc0 = mma16(Pm[r * 32 + ks * 4 + g4], b, acc0);
+                if (mt_n > 1) acc1 = mma16(Pm[(16 + r) * 32 + ks * 4 + g4], b, acc1);
+            }
+            wave_sync();
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            L.B[V4T<R>::row(i, g4) * BRS + nt * 16 + r] = acc0[i];
-            if (mt_n > 1) L.B[(16 + V4T<R>::row(i, g4)) * BRS + nt * 16 + r] = acc1[i];
+            for (int i = 0; i < 4; ++i) {
+                L.B[V4T<R>::row(i, g4) * BRS + nt * 16 + r] = acc0[i];
+                if (mt_n > 1) L.B[(16 + V4T<R>::row(i, g4)) * BRS + nt * 16 + r] = acc1[i];
+            }
         }
+        wave_sync();
+        if (l >= 1 && l <= p)
+            for (int s2 = 0; s2 < gn; ++s2) {
+                const C2 t = Tf[L.off[g0 + s2] * 32 + l];
+                const R yr = L.B[(l - 1) * BRS + 2 * s2] - L.b0[g0 + s2].x * il;
+                const R yi = L.B[(l - 1) * BRS + 2 * s2 + 1] - L.b0[g0 + s2].y * il;
+                acc.x += t.x * yr - t.y * yi;
+                acc.y += t.x * yi + t.y * yr;
+            }
+        wave_sync();   // the next group overwrites B
     }
     // P2L from the stars of interaction squares that are not nodes (parts of
     // coarser leaves): c_l += -m / (l zeta^l).  Lanes take the stars, the
@@ -302,15 +323,12 @@ __global__ __launch_bounds__(64) void k_downward(int64_t lo, int64_t hi, int lev
             }
         }
     }
-    wave_sync();
     // coefficient l = lane
-    const int l = lane;
     if (l > p) return;
     if (l == 0) {
         local[q * P1] = Cx<R>::make(0, 0);   // c_0 only shifts the potential
         return;
     }
-    C2 acc = Cx<R>::make(0, 0);
     // L2L from the parent (levels 0 and 1 have no far field)
     if (lev >= 3) {
         const int quad = (int)((c & 1ull) | (((c >> 1) & 1ull) << 1));
@@ -321,15 +339,6 @@ __global__ __launch_bounds__(64) void k_downward(int64_t lo, int64_t hi, int lev
             acc.x += o.x * v.x - o.y * v.y;
             acc.y += o.x * v.y + o.y * v.x;
         }
-    }
-    // M2L: z0^-l (y_l - b_0 / l) per source
-    const R il = (R)1 / (R)l;
-    for (int s2 = 0; s2 < ns; ++s2) {
-        const C2 t = Tf[L.off[s2] * 32 + l];
-        const R yr = L.B[(l - 1) * BRS + 2 * s2] - L.b0[s2].x * il;
-        const R yi = L.B[(l - 1) * BRS + 2 * s2 + 1] - L.b0[s2].y * il;
-        acc.x += t.x * yr - t.y * yi;
-        acc.y += t.x * yi + t.y * yr;
     }
     acc.x += p2l.x * il;
     acc.y += p2l.y * il;
