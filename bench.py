@@ -167,10 +167,12 @@ def batched_variant() -> dict:
     mlm.map_batch(lenses, reqs, outs, autotune=True)          # tunes and warms
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, b = mlm.map_batch(lenses, reqs, outs, autotune=True)
+    per_map, b = mlm.map_batch(lenses, reqs, outs, autotune=True)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     tuned = [o.clone() for o in outs]
+    from collections import Counter
+    schedules = Counter((s["leaf_max"], s["order"], s["big_pixels"]) for s in per_map)
     # fusion: the batch at the default leaf size against single calls
     mlm.map_batch(lenses, reqs, outs, autotune=False)
     fused = [o.clone() for o in outs]
@@ -200,6 +202,8 @@ def batched_variant() -> dict:
             "maps_per_hour": 256 * 3600.0 / t_batch, "s_256_single_calls": t_seq, "chunks": b["n_chunks"],
             "stage_ms": {"prep": b["t_prep_ms"], "shoot": b["t_shoot_ms"], "ipm": b["t_ipm_ms"]},
             "fused_vs_single_max_rel_default_leaf": worst,
+            "tuned_schedules": [{"leaf_max": k[0], "order": k[1], "big_pixels": k[2], "maps": v}
+                                for k, v in sorted(schedules.items())],
             "autotuned_mixed_vs_fp64_single": {"max": float(e.max()), "p999": float(q),
                                                "median": float(e.median()), "pixels": int(e.numel())}}
 

@@ -259,7 +259,9 @@ typedef struct mlm_map_request {
     double x1c, x2c;           /* image-plane centre of the shooting region, used when
                                   centre_set (with dx1, dx2 > 0 as its half-sizes) */
     int32_t centre_set;
-    int32_t reserved3;
+    int32_t big_pixels;        /* IPM: a triangle whose bounding box covers more pixels than this
+                                  goes through the row-band pass (0: 64; the batch's autotuner
+                                  picks it per class of map) */
 } mlm_map_request;
 
 void mlm_map_request_init(mlm_map_request *req);
@@ -391,6 +393,8 @@ typedef struct mlm_map_stats {
     int64_t n_col_pieces;    /* pixel pieces those columns evaluate (if timing) */
     int64_t n_pieces;        /* (triangle, pixel) pairs that meet inside the map, over all
                                 paths: the pieces the apportioning deposits (timing 2) */
+    int32_t leaf_max;        /* the split threshold the tree used (tuned in batches) */
+    int32_t big_pixels;      /* the IPM's band threshold used (tuned in batches) */
 } mlm_map_stats;
 
 /*

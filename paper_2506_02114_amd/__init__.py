@@ -75,7 +75,7 @@ class MapRequest(C.Structure):
                 ("timing", C.c_int32), ("refine", C.c_int32), ("refine_depth", C.c_int32),
                 ("refine_window", C.c_int32), ("refine_tau", C.c_double), ("refine_threshold", C.c_double),
                 ("refiner", C.c_void_p), ("mapping", C.c_int32), ("one_stream", C.c_int32),
-                ("x1c", C.c_double), ("x2c", C.c_double), ("centre_set", C.c_int32), ("reserved3", C.c_int32)]
+                ("x1c", C.c_double), ("x2c", C.c_double), ("centre_set", C.c_int32), ("big_pixels", C.c_int32)]
 
 
 class Region(C.Structure):
@@ -98,7 +98,7 @@ class MapStats(C.Structure):
                 ("n_refine_candidates", C.c_int64), ("n_refined", C.c_int64), ("n_refine_tests", C.c_int64),
                 ("n_refine_large", C.c_int64), ("t_refine_ms", C.c_double),
                 ("n_small", C.c_int64), ("n_col_items", C.c_int64), ("n_col_pieces", C.c_int64),
-                ("n_pieces", C.c_int64)]
+                ("n_pieces", C.c_int64), ("leaf_max", C.c_int32), ("big_pixels", C.c_int32)]
 
 
 class BatchOpts(C.Structure):

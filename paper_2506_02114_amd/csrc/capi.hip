@@ -249,6 +249,7 @@ void check_request(const mlm_map_request *q)
     if (!(q->eps >= 0) || !std::isfinite(q->eps)) fail(MLM_EINVAL, "eps must be finite and >= 0");
     if (q->refine < MLM_REFINE_NONE || q->refine > MLM_REFINE_LEARNED) fail(MLM_EINVAL, "unknown refine %d", q->refine);
     if (q->mapping != MLM_MAP_IPM && q->mapping != MLM_MAP_IRS) fail(MLM_EINVAL, "unknown mapping %d", q->mapping);
+    if (q->big_pixels < 0) fail(MLM_EINVAL, "big_pixels must be >= 0");
     if (q->mapping == MLM_MAP_IRS && (q->refine != MLM_REFINE_NONE || q->w_out))
         fail(MLM_ENOTSUP, "ray shooting (IRS) maps take no cell refinement and no w_out");
     if (q->refine != MLM_REFINE_NONE) {
@@ -344,6 +345,7 @@ MapGeom map_geom(const mlm_map_request &q, const Region &R)
     g.n1 = q.n1;
     g.n2 = q.n2;
     g.tri_weight = 0.5 * R.d1 * R.d2 / (R.pix1 * R.pix2);
+    g.big_px = big_pixels_of(q);
     return g;
 }
 
@@ -353,14 +355,25 @@ int order_for(const mlm_map_request &q, const Region &R, const Tree &T)
     return auto_order(R.mean_m, R.mean_m2, std::ldexp(R.L0, -(T.nlevels - 1)), q.eps > 0 ? q.eps : 1e-7);
 }
 
-// Leaf-size autotuner: for a map, the split threshold that minimises the
-// estimated time of tree + FMM + shooting, from timed trials on the map's
-// own stars and a sample of its grid rows; cached per class of map.  The
-// batch call tunes every class before its preparing threads start.
-std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int>, int> g_tune_cache;
+void map_impl(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_stats *stats);
 
-int tune_leaf_max(mlm_lens *lens, const mlm_map_request &q, const Region &R, hipStream_t st)
+// Autotuner of a class of maps (precision, order, log2 of rays per star):
+// 1. the leaf size (the split threshold of app. C.1) that minimises the time
+//    of tree + FMM + shooting, from timed trials on the map's own stars and a
+//    sample of its grid rows; the expansion order follows from the accuracy
+//    rule for each candidate tree (a bigger leaf needs a lower order);
+// 2. then the IPM's band threshold (bounding-box pixels above which a triangle
+//    goes by row bands) that minimises the time of the same sample strip mapped
+//    whole.
+// The result is cached per class for the process; the batch call tunes every
+// class before its preparing threads start, on an otherwise idle device.
+struct Tuned {
+    int leaf_max, big_px;
+};
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, Tuned> g_tune_cache;
+
+Tuned tune_map(mlm_lens *lens, const mlm_map_request &q, const Region &R, hipStream_t st)
 {
     const double rays = (double)R.nr1 * (double)R.nr2;
     const int cls = (int)std::floor(std::log2(std::max(1.0, rays / std::max<int64_t>(lens->n, 1))));
@@ -372,31 +385,58 @@ int tune_leaf_max(mlm_lens *lens, const mlm_map_request &q, const Region &R, hip
     }
     const int64_t srows = std::min<int64_t>(R.nr2, std::max<int64_t>(64, R.nr2 / 16));
     const int64_t vb0 = (R.nr2 - srows) / 2;
-    double2 *verts = static_cast<double2 *>(lens->ws.verts.reserve((size_t)(srows * R.nr1) * sizeof(double2)));
-    const MapGeom g = map_geom(q, R);
-    const LensConst lc = lens_const(lens, R);
-    int best = 32;
-    double best_t = 1e300;
-    for (int cand : {8, 16, 32, 64}) {
-        mlm_map_request qc = q;
-        qc.leaf_max = cand;
-        Timer tm(true, st);
-        const int a = tm.mark();
-        Tree T;
-        build_tree(lens, R, qc, T, st);
-        T.mixed = qc.precision == MLM_PREC_MIXED;
-        run_fmm(lens, T, order_for(qc, R, T), st);
-        build_leaf_tables(lens, T, st);
-        const int b = tm.mark();
-        const int64_t nt = plan_tiles(lens, T, R, vb0, vb0 + srows, st);
-        const int c = tm.mark();
-        launch_shoot(lens, T, R, lc, g, nt, vb0, verts, nullptr, st);
-        const int d = tm.mark();
-        MLM_HIP(hipStreamSynchronize(st));
-        const double est = tm.ms(a, b) + tm.ms(c, d) * (double)R.nr2 / (double)srows;
-        if (est < best_t) {
-            best_t = est;
-            best = cand;
+    Tuned best{32, big_pixels_of(q)};
+    {
+        double2 *verts = static_cast<double2 *>(lens->ws.verts.reserve((size_t)(srows * R.nr1) * sizeof(double2)));
+        const MapGeom g = map_geom(q, R);
+        const LensConst lc = lens_const(lens, R);
+        double best_t = 1e300;
+        for (int cand : {8, 16, 32, 64}) {
+            mlm_map_request qc = q;
+            qc.leaf_max = cand;
+            Timer tm(true, st);
+            const int a = tm.mark();
+            Tree T;
+            build_tree(lens, R, qc, T, st);
+            T.mixed = qc.precision == MLM_PREC_MIXED;
+            run_fmm(lens, T, order_for(qc, R, T), st);
+            build_leaf_tables(lens, T, st);
+            const int b = tm.mark();
+            const int64_t nt = plan_tiles(lens, T, R, vb0, vb0 + srows, st);
+            const int c = tm.mark();
+            launch_shoot(lens, T, R, lc, g, nt, vb0, verts, nullptr, st);
+            const int d = tm.mark();
+            MLM_HIP(hipStreamSynchronize(st));
+            const double est = tm.ms(a, b) + tm.ms(c, d) * (double)R.nr2 / (double)srows;
+            if (est < best_t) {
+                best_t = est;
+                best.leaf_max = cand;
+            }
+        }
+    }
+    if (q.mapping == MLM_MAP_IPM) {
+        // the sample strip mapped whole (device timing of the call) at each band threshold
+        const int64_t npix = (int64_t)q.n1 * q.n2;
+        double *mu = static_cast<double *>(lens->ws.tune_map.reserve((size_t)npix * sizeof(double)));
+        double best_t = 1e300;
+        for (int cand : {32, 64, 128, 192}) {
+            mlm_map_request qc = q;
+            qc.leaf_max = best.leaf_max;
+            qc.big_pixels = cand;
+            qc.row_begin = vb0;
+            qc.row_end = vb0 + srows - 1;
+            qc.device_out = 1;
+            qc.stream = st;
+            qc.timing = 1;
+            qc.refine = MLM_REFINE_NONE;
+            qc.w_out = nullptr;
+            mlm_map_stats S{};
+            map_impl(lens, &qc, mu, &S);
+            const double t = S.t_total_ms - S.t_tree_ms - S.t_fmm_ms;
+            if (t < best_t) {
+                best_t = t;
+                best.big_px = cand;
+            }
         }
     }
     std::lock_guard<std::mutex> g2(g_tune_mu);
@@ -799,6 +839,7 @@ void map_impl(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_st
     g.n1 = q.n1;
     g.n2 = q.n2;
     g.tri_weight = 0.5 * R.d1 * R.d2 / (R.pix1 * R.pix2);
+    g.big_px = big_pixels_of(q);
     LensConst lc = lens_const(lens, R);
 
     int64_t n_big = 0, n_big_rows = 0, n_cand = 0, n_refined = 0;
@@ -1064,6 +1105,8 @@ void map_impl(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_st
         S.n_col_items = wsum[1];
         S.n_col_pieces = wsum[2];
         S.n_pieces = q.timing >= 2 && !irs ? (int64_t)hc[6] : 0;
+        S.leaf_max = fmm ? T.nmax : 0;
+        S.big_pixels = g.big_px;
         S.n_refine_candidates = n_cand;
         S.n_refined = n_refined;
         if (refine_stats_zeroed) {
@@ -1311,7 +1354,7 @@ mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, i
             mlm_map_request qi = reqs[i];
             Region Ri{};
             setup_region(lenses[i], &qi, &Ri);
-            (void)tune_leaf_max(lenses[i], qi, Ri, st);
+            (void)tune_map(lenses[i], qi, Ri, st);
         }
     // Regions, sizes and the chunks first (host arithmetic only): chunks of
     // consecutive maps that fit the vertex budget, one fused launch per stage
@@ -1375,7 +1418,11 @@ mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, i
             MLM_HIP(hipStreamWaitEvent(ps, go, 0));
             for (int32_t i = next++; i < nmaps && !failed; i = next++) {
                 MapPlan &m = P[i];
-                if (o.autotune) m.q.leaf_max = tune_leaf_max(m.lens, m.q, m.R, ps);
+                if (o.autotune) {
+                    const Tuned tu = tune_map(m.lens, m.q, m.R, ps);
+                    m.q.leaf_max = tu.leaf_max;
+                    m.q.big_pixels = tu.big_px;
+                }
                 m.tm = &pt;
                 m.e_tree0 = pt.mark();
                 build_tree(m.lens, m.R, m.q, m.T, ps);
@@ -1601,6 +1648,8 @@ mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, i
             S.tri_area = 0.5 * m.R.d1 * m.R.d2;
             S.t_tree_ms = m.tm ? m.tm->ms(m.e_tree0, m.e_tree1) : 0.0;
             S.t_fmm_ms = m.tm ? m.tm->ms(m.e_tree1, m.e_fmm1) : 0.0;
+            S.leaf_max = m.T.nmax;
+            S.big_pixels = m.g.big_px;
             S.n_shoot_launches = S.n_ipm_launches = 0;
             stats[i] = S;
         }

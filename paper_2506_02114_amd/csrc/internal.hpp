@@ -150,7 +150,12 @@ struct MapGeom {
     double pix1, pix2;
     int32_t n1, n2;
     double tri_weight;      // image area of a triangle / pixel area
+    int32_t big_px;         // IPM: triangles whose bounding box covers more pixels go by row bands
+    int32_t pad;
 };
+
+// the band threshold of a request (bounding-box pixels), default 64
+inline int32_t big_pixels_of(const mlm_map_request &q) { return q.big_pixels > 0 ? q.big_pixels : 64; }
 
 // one map of a fused batch, as the batch kernels see it (device array, in
 // the order of the maps; the *_lo fields are non-decreasing prefix offsets)
@@ -228,7 +233,7 @@ struct Workspace {
     DevBuf ilist, mult, local, ops_m2m, ops_m2l, ops_l2l;
     DevBuf leaves, near, deriv, near_offs;
     DevBuf tile_off, tile_leaf, verts, map, wbuf, pts, counters, items, itemoff, tbig, tbigoff, bigprep, bigrows, bigrow0, rowoff, nbnd, nbndoff, diff, bandcnt, bandoff,
-        bandcur, bandlist, rfeat, rlogit, rflag, rpos, rcand, rlabel, rstats, irs_counts, rtflag, rtpos, rsub0, rsub1, bitems, bqueue;
+        bandcur, bandlist, rfeat, rlogit, rflag, rpos, rcand, rlabel, rstats, irs_counts, rtflag, rtpos, rsub0, rsub1, bitems, bqueue, tune_map;
     hipStream_t side = nullptr;           // second stream of a map: the large-triangle passes beside the cell pass
     hipEvent_t fork = nullptr, join = nullptr;
     void *pinned = nullptr;               // small pinned host buffer for read-backs

@@ -33,7 +33,6 @@ template <class R> struct Pt {
 };
 using P2 = Pt<double>;
 
-constexpr int64_t BIG_PIXELS = 192;  // bounding-box pixels above which a triangle goes by row bands
 
 // Part of segment P->Q with lo <= coordinate <= hi (AXIS 0: u, 1: v).  The
 // segment lies on a line whose other coordinate changes by `slope` per unit of
@@ -296,7 +295,7 @@ __device__ inline TriClass classify(P2 A, P2 B, P2 C, const MapGeom &g)
     }
     const int i0 = (int)fmax(fu0, 0.0), i1 = (int)fmin(fu1, (double)(g.n1 - 1));
     const int j0 = (int)fmax(fv0, 0.0), j1 = (int)fmin(fv1, (double)(g.n2 - 1));
-    if ((int64_t)(i1 - i0 + 1) * (j1 - j0 + 1) > BIG_PIXELS) {
+    if ((int64_t)(i1 - i0 + 1) * (j1 - j0 + 1) > (int64_t)g.big_px) {   // large: by row bands
         c.kind = 3;
         return c;
     }
