@@ -978,16 +978,15 @@ void map_impl(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_st
                     const int64_t nitems = (int64_t)items.size();
                     BandItem *ditems =
                         static_cast<BandItem *>(ws.bitems.reserve((size_t)std::max<int64_t>(nitems, 1) * sizeof(BandItem)));
-                    unsigned long long *queue =
-                        static_cast<unsigned long long *>(ws.bqueue.reserve(sizeof(unsigned long long)));
+                    unsigned long long *queue = static_cast<unsigned long long *>(ws.bqueue.reserve(QUEUE_BYTES));
                     if (nitems > 0) {
                         MLM_HIP(hipMemcpyAsync(ditems, items.data(), (size_t)nitems * sizeof(BandItem),
                                                hipMemcpyHostToDevice, bst));
                         MLM_HIP(hipStreamSynchronize(bst));   // the host item table is released at the end of this block
                     }
                     e_band0 = tm.mark_on(bst);
-                    launch_band_queue1(ditems, nitems, queue, blist, prep, rows, bh, g, map,
-                                       q.timing >= 2 ? cnt + 4 : nullptr, overlap, bst);
+                    launch_band_queue1(ditems, nitems, split_items(items.data(), nitems), queue, blist, prep, rows,
+                                       bh, g, map, q.timing >= 2 ? cnt + 4 : nullptr, overlap, bst);
                     e_band1 = tm.mark_on(bst);
                 } else {
                     launch_big(nb, prep, rows, g, map, diff, st);
@@ -1608,10 +1607,11 @@ mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, i
             }
             const int64_t nitems = (int64_t)items.size();
             BandItem *ditems = static_cast<BandItem *>(B.items.reserve((size_t)std::max<int64_t>(nitems, 1) * sizeof(BandItem)));
-            unsigned long long *queue = static_cast<unsigned long long *>(B.queue.reserve(sizeof(unsigned long long)));
+            unsigned long long *queue = static_cast<unsigned long long *>(B.queue.reserve(QUEUE_BYTES));
             if (nitems > 0)
                 MLM_HIP(hipMemcpyAsync(ditems, items.data(), (size_t)nitems * sizeof(BandItem), hipMemcpyHostToDevice, st));
-            launch_band_queue(dmaps, nm, ditems, nitems, queue, blist, prep, rows, max_band_lds, st);
+            launch_band_queue(dmaps, nm, ditems, nitems, split_items(items.data(), nitems), queue, blist, prep, rows,
+                              max_band_lds, st);
             MLM_HIP(hipStreamSynchronize(st));   // the host item table is released at the end of this block
         }
         const int ec = tm.mark();

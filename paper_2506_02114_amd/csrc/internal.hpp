@@ -185,6 +185,21 @@ struct BandItem {
     int32_t shared, pad;
 };
 
+// The persistent band passes keep one work counter per XCD: the item list
+// (in band order) is cut into NXCD contiguous ranges of about equal list
+// length, and a workgroup first drains the range of the XCD it runs on, so
+// the triangles a run of neighbouring bands shares are fetched into one L2
+// (workgroups are dispatched to the XCDs round-robin, so workgroup i runs on
+// XCD i mod NXCD); then it helps the other ranges.  The counters sit
+// QUEUE_STRIDE u64 apart, each on its own cache line.
+constexpr int NXCD = 8;
+constexpr int QUEUE_STRIDE = 32;
+constexpr size_t QUEUE_BYTES = (size_t)NXCD * QUEUE_STRIDE * sizeof(unsigned long long);
+struct ItemParts {
+    int64_t lo[NXCD + 1];   // range x is items [lo[x], lo[x + 1])
+};
+ItemParts split_items(const BandItem *items, int64_t n);
+
 // index of the map whose range [lo, next lo) holds item x (maps with empty
 // ranges are skipped: the last map whose lo <= x)
 template <class T>
@@ -358,9 +373,10 @@ void launch_band_scatter_batch(const BatchMap *maps, int64_t nslices, const int3
                                const int64_t *slice_lo, int32_t max_bands, const int32_t *row0, const int64_t *rows,
                                unsigned long long *cursor, int32_t *list, hipStream_t st);
 void launch_band_queue(const BatchMap *maps, int32_t nmaps, const BandItem *items, int64_t nitems,
-                       unsigned long long *queue, const int32_t *list, const BigPrep *prep, const int64_t *rows,
-                       int64_t lds_doubles, hipStream_t st);
-void launch_band_queue1(const BandItem *items, int64_t nitems, unsigned long long *queue, const int32_t *list,
+                       const ItemParts &parts, unsigned long long *queue, const int32_t *list, const BigPrep *prep,
+                       const int64_t *rows, int64_t lds_doubles, hipStream_t st);
+void launch_band_queue1(const BandItem *items, int64_t nitems, const ItemParts &parts, unsigned long long *queue,
+                        const int32_t *list,
                         const BigPrep *prep, const int64_t *rows, int bh, const MapGeom &g, double *map,
                         unsigned long long *work, bool atomic_all, hipStream_t st);
 int64_t scan_i32_to_u64(mlm_lens *lens, const int32_t *in, unsigned long long *out, int64_t n, hipStream_t st);

@@ -1198,13 +1198,29 @@ __device__ inline void band_rows(int64_t band, int64_t r0, int64_t r1, const int
     __syncthreads();   // the LDS may be reused for the workgroup's next band
 }
 
+// The next work item of a persistent band pass for this workgroup, or -1 when
+// every range is drained: its XCD's range first, then the others in turn.
+// `visited` (thread 0's own) counts the ranges found empty, so each counter is
+// pushed past its range at most once per workgroup and the loop ends.
+__device__ inline int64_t next_item(unsigned long long *queue, const ItemParts &parts, int &visited)
+{
+    const int home = (int)(blockIdx.x % NXCD);
+    while (visited < NXCD) {
+        const int x = (home + visited) % NXCD;
+        const int64_t k = (int64_t)atomicAdd(queue + (size_t)x * QUEUE_STRIDE, 1ull);
+        if (parts.lo[x] + k < parts.lo[x + 1]) return parts.lo[x] + k;
+        ++visited;
+    }
+    return -1;
+}
+
 // The batch's band pass as one persistent launch: a grid the device holds at
-// once pulls work items from a device-wide counter until none are left.  An
+// once pulls work items from device-wide counters until none are left.  An
 // item is a slice of one band's list (BandItem), so a heavy band is shared by
 // several workgroups instead of holding one while the others idle; a band
 // split into several items adds its rows to the map atomically.
 __global__ __launch_bounds__(BAND_THREADS) void k_band_queue(const BatchMap *__restrict__ maps, int32_t nmaps,
-                                                             const BandItem *__restrict__ items, int64_t nitems,
+                                                             const BandItem *__restrict__ items, ItemParts parts,
                                                              unsigned long long *__restrict__ queue,
                                                              const int32_t *__restrict__ list,
                                                              const BigPrep *__restrict__ prep,
@@ -1213,12 +1229,13 @@ __global__ __launch_bounds__(BAND_THREADS) void k_band_queue(const BatchMap *__r
     extern __shared__ double bdiff[];
     __shared__ unsigned long long wsum[2];
     __shared__ int64_t cur;
+    int visited = 0;
     for (;;) {
-        if (threadIdx.x == 0) cur = (int64_t)atomicAdd(queue, 1ull);
+        if (threadIdx.x == 0) cur = next_item(queue, parts, visited);
         __syncthreads();
         const int64_t i = cur;
         __syncthreads();   // every thread has read cur before the next item overwrites it
-        if (i >= nitems) break;   // the same for the whole workgroup
+        if (i < 0) break;   // the same for the whole workgroup
         const BandItem it = items[i];
         const int32_t m = batch_find(maps, nmaps, it.gband, &BatchMap::band_lo);
         const BatchMap &d = maps[m];
@@ -1230,7 +1247,7 @@ __global__ __launch_bounds__(BAND_THREADS) void k_band_queue(const BatchMap *__r
 // The same for one map: items over its bands (BandItem.gband is the band);
 // with `atomic_all` every band's rows are added atomically (the cell pass
 // runs beside it).
-__global__ __launch_bounds__(BAND_THREADS) void k_band_queue1(const BandItem *__restrict__ items, int64_t nitems,
+__global__ __launch_bounds__(BAND_THREADS) void k_band_queue1(const BandItem *__restrict__ items, ItemParts parts,
                                                               unsigned long long *__restrict__ queue,
                                                               const int32_t *__restrict__ list,
                                                               const BigPrep *__restrict__ prep,
@@ -1241,12 +1258,13 @@ __global__ __launch_bounds__(BAND_THREADS) void k_band_queue1(const BandItem *__
     extern __shared__ double bdiff[];
     __shared__ unsigned long long wsum[2];
     __shared__ int64_t cur;
+    int visited = 0;
     for (;;) {
-        if (threadIdx.x == 0) cur = (int64_t)atomicAdd(queue, 1ull);
+        if (threadIdx.x == 0) cur = next_item(queue, parts, visited);
         __syncthreads();
         const int64_t i = cur;
         __syncthreads();
-        if (i >= nitems) break;
+        if (i < 0) break;
         const BandItem it = items[i];
         band_rows(it.gband, it.lo, it.hi, list, prep, rows, bh, g, map, work, bdiff, wsum,
                   atomic_all != 0 || it.shared != 0);
@@ -1482,11 +1500,43 @@ void launch_big_gather_batch(const BatchMap *maps, int32_t nmaps, int64_t nctile
                            rows, row0);
 }
 
-static __global__ void k_zero_u64_1(unsigned long long *p) { *p = 0ull; }
+static __global__ void k_zero_queue(unsigned long long *q)
+{
+    if (threadIdx.x < NXCD) q[(size_t)threadIdx.x * QUEUE_STRIDE] = 0ull;
+}
+
+ItemParts split_items(const BandItem *items, int64_t n)
+{
+    // cut points at equal shares of the total list length
+    int64_t total = 0;
+    for (int64_t i = 0; i < n; ++i) total += items[i].hi - items[i].lo;
+    ItemParts p{};
+    int x = 1;
+    int64_t acc = 0;
+    for (int64_t i = 0; i < n && x < NXCD; ++i) {
+        acc += items[i].hi - items[i].lo;
+        while (x < NXCD && acc * NXCD >= total * x) p.lo[x++] = i + 1;
+    }
+    for (; x <= NXCD; ++x) p.lo[x] = n;
+    return p;
+}
+
+// grid of a persistent band pass: the workgroups of `kernel` the device holds
+// at once with `shmem` bytes of LDS, or fewer for few items (a multiple of
+// NXCD, so that every XCD's range has workgroups of its own)
+static int64_t resident_grid(const void *kernel, size_t shmem, int64_t nitems)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    MLM_HIP(hipGetDevice(&dev));
+    MLM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    MLM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, BAND_THREADS, shmem));
+    const int64_t full = (int64_t)std::max(cus, 1) * std::max(per_cu, 1);
+    return std::min(full, (nitems + NXCD - 1) / NXCD * NXCD);
+}
 
 void launch_band_queue(const BatchMap *maps, int32_t nmaps, const BandItem *items, int64_t nitems,
-                       unsigned long long *queue, const int32_t *list, const BigPrep *prep, const int64_t *rows,
-                       int64_t lds_doubles, hipStream_t st)
+                       const ItemParts &parts, unsigned long long *queue, const int32_t *list, const BigPrep *prep,
+                       const int64_t *rows, int64_t lds_doubles, hipStream_t st)
 {
     static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_band_queue),
                                                        hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1494,37 +1544,29 @@ void launch_band_queue(const BatchMap *maps, int32_t nmaps, const BandItem *item
     MLM_HIP(attr);
     if (lds_doubles > BAND_LDS_DOUBLES) fail(MLM_EINVAL, "band of %lld doubles exceeds LDS", (long long)lds_doubles);
     if (nitems <= 0) return;
+    if (parts.lo[0] != 0 || parts.lo[NXCD] != nitems) fail(MLM_EINVAL, "band item ranges do not cover the items");
     const size_t shmem = (size_t)lds_doubles * sizeof(double);
     // as many workgroups as the device holds at once at this LDS size
-    int dev = 0, cus = 0, per_cu = 0;
-    MLM_HIP(hipGetDevice(&dev));
-    MLM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    MLM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_band_queue),
-                                                         BAND_THREADS, shmem));
-    const int64_t grid = std::min<int64_t>(nitems, (int64_t)std::max(cus, 1) * std::max(per_cu, 1));
-    hipLaunchKernelGGL(k_zero_u64_1, dim3(1), dim3(1), 0, st, queue);
-    hipLaunchKernelGGL(k_band_queue, dim3((unsigned)grid), dim3(BAND_THREADS), shmem, st, maps, nmaps, items, nitems,
+    const int64_t grid = resident_grid(reinterpret_cast<const void *>(&k_band_queue), shmem, nitems);
+    hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(64), 0, st, queue);
+    hipLaunchKernelGGL(k_band_queue, dim3((unsigned)grid), dim3(BAND_THREADS), shmem, st, maps, nmaps, items, parts,
                        queue, list, prep, rows);
 }
 
-void launch_band_queue1(const BandItem *items, int64_t nitems, unsigned long long *queue, const int32_t *list,
-                        const BigPrep *prep, const int64_t *rows, int bh, const MapGeom &g, double *map,
-                        unsigned long long *work, bool atomic_all, hipStream_t st)
+void launch_band_queue1(const BandItem *items, int64_t nitems, const ItemParts &parts, unsigned long long *queue,
+                        const int32_t *list, const BigPrep *prep, const int64_t *rows, int bh, const MapGeom &g,
+                        double *map, unsigned long long *work, bool atomic_all, hipStream_t st)
 {
     static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_band_queue1),
                                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                                        (int)(BAND_LDS_DOUBLES * sizeof(double)));
     MLM_HIP(attr);
     if (nitems <= 0) return;
+    if (parts.lo[0] != 0 || parts.lo[NXCD] != nitems) fail(MLM_EINVAL, "band item ranges do not cover the items");
     const size_t shmem = (size_t)bh * (size_t)g.n1 * sizeof(double);
-    int dev = 0, cus = 0, per_cu = 0;
-    MLM_HIP(hipGetDevice(&dev));
-    MLM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    MLM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_band_queue1),
-                                                         BAND_THREADS, shmem));
-    const int64_t grid = std::min<int64_t>(nitems, (int64_t)std::max(cus, 1) * std::max(per_cu, 1));
-    hipLaunchKernelGGL(k_zero_u64_1, dim3(1), dim3(1), 0, st, queue);
-    hipLaunchKernelGGL(k_band_queue1, dim3((unsigned)grid), dim3(BAND_THREADS), shmem, st, items, nitems, queue, list,
+    const int64_t grid = resident_grid(reinterpret_cast<const void *>(&k_band_queue1), shmem, nitems);
+    hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(64), 0, st, queue);
+    hipLaunchKernelGGL(k_band_queue1, dim3((unsigned)grid), dim3(BAND_THREADS), shmem, st, items, parts, queue, list,
                        prep, rows, bh, g, map, work, atomic_all ? 1 : 0);
 }
 
