@@ -611,8 +611,11 @@ __device__ __forceinline__ void ipm_tile(const double2 *__restrict__ verts, int6
     __syncthreads();   // the window may be reused by the workgroup's next tile
 }
 
+// Registers capped at 128 per lane (four waves per SIMD, no spills): the
+// compiler's free choice (132) holds three, and the cell pass gains more from
+// the fourth wave hiding its LDS and cross-lane latency than it loses.
 template <bool MIXED>
-__global__ __launch_bounds__(256) void k_ipm(const double2 *__restrict__ verts, int64_t nr1, int64_t cb0,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_ipm(const double2 *__restrict__ verts, int64_t nr1, int64_t cb0,
                                              int64_t nrows, int64_t vb0, MapGeom g, double *__restrict__ map,
                                              unsigned long long *__restrict__ counters, int32_t *__restrict__ tile_big,
                                              unsigned long long *__restrict__ work)
@@ -931,7 +934,10 @@ __global__ __launch_bounds__(256) void k_big(int64_t nbig, const BigPrep *__rest
 // differences of its rows in LDS from the triangles' edges, prefix-sums its
 // own rows and adds them to the map.
 // ---------------------------------------------------------------------------
-constexpr int BAND_THREADS = 512;
+// Two band workgroups share a compute unit's LDS; 768 threads each with at
+// most 80 registers per lane (a few bytes spilled) keep six waves per SIMD,
+// where 512 threads left four.
+constexpr int BAND_THREADS = 768;
 constexpr int64_t BAND_LDS_DOUBLES = 8192;    // band difference rows (64 KiB)
 
 __device__ inline void band_range(int64_t j0, int64_t rows, int bh, int64_t &b0, int64_t &b1)
@@ -1219,7 +1225,7 @@ __device__ inline int64_t next_item(unsigned long long *queue, const ItemParts &
 // item is a slice of one band's list (BandItem), so a heavy band is shared by
 // several workgroups instead of holding one while the others idle; a band
 // split into several items adds its rows to the map atomically.
-__global__ __launch_bounds__(BAND_THREADS) void k_band_queue(const BatchMap *__restrict__ maps, int32_t nmaps,
+__global__ __launch_bounds__(BAND_THREADS) __attribute__((amdgpu_waves_per_eu(6))) void k_band_queue(const BatchMap *__restrict__ maps, int32_t nmaps,
                                                              const BandItem *__restrict__ items, ItemParts parts,
                                                              unsigned long long *__restrict__ queue,
                                                              const int32_t *__restrict__ list,
@@ -1247,7 +1253,7 @@ __global__ __launch_bounds__(BAND_THREADS) void k_band_queue(const BatchMap *__r
 // The same for one map: items over its bands (BandItem.gband is the band);
 // with `atomic_all` every band's rows are added atomically (the cell pass
 // runs beside it).
-__global__ __launch_bounds__(BAND_THREADS) void k_band_queue1(const BandItem *__restrict__ items, ItemParts parts,
+__global__ __launch_bounds__(BAND_THREADS) __attribute__((amdgpu_waves_per_eu(6))) void k_band_queue1(const BandItem *__restrict__ items, ItemParts parts,
                                                               unsigned long long *__restrict__ queue,
                                                               const int32_t *__restrict__ list,
                                                               const BigPrep *__restrict__ prep,
