@@ -39,8 +39,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6          # MI355X FP64 vector, dense
 # FETCH_SIZE x 2.0, WRITE_SIZE x 1.0.  Valid only for the IPM source they were
 # taken with, identified by its SHA-256 prefix.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
-IPM_TRAFFIC = {"ipm_sha256": "a8e4288d3ca909d0",                     # (fetch KiB, write KiB)
-               "k_ipm": (719914.5, 4175274.65625), "k_band": (1486720.8125, 31250.0)}
+IPM_TRAFFIC = {"ipm_sha256": "a9f751122b389124",                     # (fetch KiB, write KiB)
+               "k_ipm": (719910.725, 1694723.6625), "k_band_queue1": (5504891.7875, 277114.10625)}
 
 
 def file_sha(path: str) -> str:
@@ -536,7 +536,8 @@ def main():
                   "column_items": counts["n_col_items"], "pieces": counts["n_col_pieces"]}
     cells_roof["frac"] = cells_roof["achieved"] / cells_roof["peak"]
     band_roof = {"bound": "alu", "achieved": band_flops(counts) / (t_band * 1e-3) / 1e12,
-                 "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "traffic": traffic("k_band"), "kernel": "k_band",
+                 "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "traffic": traffic("k_band_queue1"),
+                 "kernel": "k_band_queue1",
                  "launch_ms": t_band, "launches_per_step": stats[0]["n_ipm_launches"],
                  "row_items": counts["n_band_rows"], "pieces": counts["n_band_pieces"]}
     band_roof["frac"] = band_roof["achieved"] / band_roof["peak"]
