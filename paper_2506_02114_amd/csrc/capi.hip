@@ -1771,14 +1771,31 @@ mlm_status mlm_refiner_predict(mlm_refiner *r, const float *feats, int64_t n, fl
     API_END
 }
 
-// one forward/backward over rows idx[0, n) into r->G (gradient + loss at [NP])
+// rows per forward/backward launch: bounds the per-wavefront partial
+// gradients (20 KB a wavefront of 32 rows) to 40 MB
+constexpr int64_t GRAD_CHUNK = 65536;
+
+// the staging and partial-gradient buffers of a batch of n rows (reserved
+// before a graph is captured, so that capturing allocates nothing)
+static void refiner_reserve(mlm_refiner *r, int64_t n)
+{
+    const int64_t c = std::min(n, GRAD_CHUNK);
+    r->xbuf.reserve((size_t)((c + 127) / 128) * 128 * 12 * sizeof(float));
+    r->gpart.reserve((size_t)mlp_part_rows(c) * (MLM_REFINER_PARAMS + 1) * sizeof(float));
+}
+
+// one forward/backward over rows idx[0, n) added to r->G (gradient + loss at
+// [NP]), in chunks of GRAD_CHUNK rows taken in order; the loss of each chunk
+// is divided by n
 static void refiner_batch(mlm_refiner *r, const float *df, const uint8_t *dy, const int64_t *didx, int64_t n,
                           float pos_weight, hipStream_t st)
 {
-    const int64_t nblk = (n + 127) / 128;
-    float *xbuf = static_cast<float *>(r->xbuf.reserve((size_t)nblk * 128 * 12 * sizeof(float)));
-    mlp_train_batch(df, dy, didx, n, r->W1b.as<uint16_t>(), r->W2b.as<uint16_t>(), r->P.as<float>(), pos_weight,
-                    r->G.as<float>(), xbuf, st);
+    refiner_reserve(r, n);
+    for (int64_t c0 = 0; c0 < n; c0 += GRAD_CHUNK) {
+        const int64_t c = std::min(GRAD_CHUNK, n - c0);
+        mlp_train_batch(df, dy, didx + c0, c, r->W1b.as<uint16_t>(), r->W2b.as<uint16_t>(), r->P.as<float>(),
+                        pos_weight, (float)n, r->G.as<float>(), r->gpart.as<float>(), r->xbuf.as<float>(), st);
+    }
 }
 
 mlm_status mlm_refiner_grads(mlm_refiner *r, const float *feats, const uint8_t *labels, int64_t n, float pos_weight,
@@ -1843,7 +1860,7 @@ mlm_status mlm_refiner_train(mlm_refiner *r, const mlm_train_opts *opts, const f
     MLM_HIP(hipEventRecord(ready, st));
     MLM_HIP(hipStreamWaitEvent(ts, ready, 0));
     (void)hipEventDestroy(ready);
-    r->xbuf.reserve((size_t)((std::min<int64_t>(o.batch, n) + 127) / 128) * 128 * 12 * sizeof(float));
+    refiner_reserve(r, std::min<int64_t>(o.batch, n));
     float *G = r->G.as<float>();
     int64_t *tstep = r->tstep.as<int64_t>();
     double *lacc = r->lacc.as<double>();

@@ -244,6 +244,16 @@ __global__ __launch_bounds__(64) void k_downward(int64_t lo, int64_t hi, int lev
     const int lgr = p <= 16 ? 4 : 5;
     const int mt_n = (p + 15) / 16, kt_n = (p + 3) / 4;
     const int r = lane & 15, g4 = lane >> 4;
+    // this lane's operands of P for every product below, loaded once: P is the
+    // same for every node and group, and reading it inside the product loop
+    // made each matrix-core step wait for a global load
+    constexpr int KTMAX = (MAX_ORDER + 4) / 4;
+    R pa[KTMAX], pb[KTMAX];
+#pragma unroll
+    for (int ks = 0; ks < KTMAX; ++ks) {
+        pa[ks] = ks < kt_n ? Pm[r * 32 + ks * 4 + g4] : (R)0;
+        pb[ks] = ks < kt_n && mt_n > 1 ? Pm[(16 + r) * 32 + ks * 4 + g4] : (R)0;
+    }
     for (int g0 = 0; g0 < ns; g0 += GS) {
         const int gn = min(GS, ns - g0);
         const int ncol = ((2 * gn + 15) / 16) * 16;
@@ -263,10 +273,13 @@ __global__ __launch_bounds__(64) void k_downward(int64_t lo, int64_t hi, int lev
         // whole (both 16-row tiles of P) before Y's block overwrites it
         for (int nt = 0; nt < ncol / 16; ++nt) {
             V4 acc0 = {}, acc1 = {};
-            for (int ks = 0; ks < kt_n; ++ks) {
-                const R b = L.B[(ks * 4 + g4) * BRS + nt * 16 + r];
-                acc0 = mma16(Pm[r * 32 + ks * 4 + g4], b, acc0);
-                if (mt_n > 1) acc1 = mma16(Pm[(16 + r) * 32 + ks * 4 + g4], b, acc1);
+#pragma unroll
+            for (int ks = 0; ks < KTMAX; ++ks) {
+                if (ks < kt_n) {
+                    const R b = L.B[(ks * 4 + g4) * BRS + nt * 16 + r];
+                    acc0 = mma16(pa[ks], b, acc0);
+                    if (mt_n > 1) acc1 = mma16(pb[ks], b, acc1);
+                }
             }
             wave_sync();
 #pragma unroll

@@ -273,7 +273,7 @@ struct mlm_lens {
 // refinement network: FP32 master weights, Adam moments, gradient (+ loss),
 // bf16 copies in the kernels' layouts, staging
 struct mlm_refiner {
-    mlm::DevBuf P, M, V, G, W1b, W2b, xbuf, idx, feats, labels, logits;
+    mlm::DevBuf P, M, V, G, W1b, W2b, xbuf, gpart, idx, feats, labels, logits;
     mlm::DevBuf tstep;     // Adam steps taken (int64, on the device: read by the step kernels)
     mlm::DevBuf lacc;      // loss summed over an epoch's rows (double)
     hipStream_t gst = nullptr;   // training stream (graph capture needs a stream of its own)
@@ -426,8 +426,15 @@ void launch_compact(int64_t n, const int32_t *flag, const int64_t *pos, int64_t 
 void mlp_pack(const float *P, uint16_t *W1b, uint16_t *W2b, hipStream_t st);
 void mlp_predict(const float *feats, int64_t n, const uint16_t *W1b, const uint16_t *W2b, const float *P,
                  float *logits, hipStream_t st);
+// rows of per-wavefront partial gradients (MLM_REFINER_PARAMS + 1 floats
+// each) that a batch of n samples needs
+int64_t mlp_part_rows(int64_t n);
+// the gradient (and loss, at [MLM_REFINER_PARAMS]) of n samples, each
+// sample's term divided by norm, added to grad in a fixed order: the same
+// bits on every run
 void mlp_train_batch(const float *feats, const uint8_t *y, const int64_t *idx, int64_t n, const uint16_t *W1b,
-                     const uint16_t *W2b, const float *P, float pos_weight, float *grad, float *xbuf, hipStream_t st);
+                     const uint16_t *W2b, const float *P, float pos_weight, float norm, float *grad, float *part,
+                     float *xbuf, hipStream_t st);
 void mlp_adam(float *P, float *M, float *V, float *grad, float lr, const int64_t *tstep, hipStream_t st);
 void mlp_step_end(float *G, int64_t *tstep, double *lacc, float nb, hipStream_t st);
 void mlp_zero(float *p, int64_t n, hipStream_t st);

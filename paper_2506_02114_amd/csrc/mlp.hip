@@ -240,22 +240,24 @@ __global__ __launch_bounds__(256) void k_mlp_predict(const float *__restrict__ f
 
 __device__ inline float softplus(float x) { return x > 0.0f ? x + log1pf(expf(-x)) : log1pf(expf(x)); }
 
-// forward and backward of samples idx[s] (s in [0, n)); gradients (FP32)
-// and the loss sum are added to grad[0 .. NP] (grad[NP] = loss); the loss is
-// divided by `norm` (the batch size)
+// forward and backward of samples idx[s] (s in [0, n)); each wavefront (32
+// samples) writes its whole gradient (FP32) and its part of the loss (at
+// [NP]; the loss is divided by `norm`, the batch size) to its own row
+// part[w * (NP + 1) ..], w = 4 blockIdx.x + wave, with no atomics: k_grad_sum
+// adds the rows in a fixed order, so a batch's gradient is the same bits on
+// every run
 __global__ __launch_bounds__(256) void k_mlp_train(const float *__restrict__ feats_all, const uint8_t *__restrict__ y_all,
                                                    const int64_t *__restrict__ idx, int64_t n,
                                                    const uint16_t *__restrict__ W1b,
                                                    const uint16_t *__restrict__ W2b, const float *__restrict__ P,
-                                                   float pos_weight, float norm, float *__restrict__ grad,
+                                                   float pos_weight, float norm, float *__restrict__ part,
                                                    float *__restrict__ xbuf)
 {
     __shared__ WaveLds lds[4];
-    __shared__ float g[NP + 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int t = threadIdx.x; t <= NP; t += blockDim.x) g[t] = 0.0f;
     WaveLds &L = lds[wave];
     const int64_t s0 = (int64_t)blockIdx.x * MB + wave * 32;
+    float *g = part + ((int64_t)blockIdx.x * 4 + wave) * (NP + 1);
     // gather this wavefront's samples into a contiguous staging area
     float *xs = xbuf + ((int64_t)blockIdx.x * MB + wave * 32) * 12;
     for (int e = lane; e < 32 * 12; e += 64) {
@@ -266,17 +268,22 @@ __global__ __launch_bounds__(256) void k_mlp_train(const float *__restrict__ fea
     __syncthreads();
     forward(xbuf + (int64_t)blockIdx.x * MB * 12, wave * 32, MB, W1b, W2b, P, L, lane);
     // loss and dL/dz
-    if (lane < 32) {
-        const int64_t s = s0 + lane;
-        float dz = 0.0f, l = 0.0f;
-        if (s < n) {
-            const float z = L.z[lane], y = (float)y_all[idx[s]];
-            const float sg = 1.0f / (1.0f + expf(-z));
-            l = pos_weight * y * softplus(-z) + (1.0f - y) * softplus(z);
-            dz = (pos_weight * y * (sg - 1.0f) + (1.0f - y) * sg) / norm;
+    {
+        float l = 0.0f;
+        if (lane < 32) {
+            const int64_t s = s0 + lane;
+            float dz = 0.0f;
+            if (s < n) {
+                const float z = L.z[lane], y = (float)y_all[idx[s]];
+                const float sg = 1.0f / (1.0f + expf(-z));
+                l = pos_weight * y * softplus(-z) + (1.0f - y) * softplus(z);
+                dz = (pos_weight * y * (sg - 1.0f) + (1.0f - y) * sg) / norm;
+            }
+            L.dz[lane] = dz;
         }
-        L.dz[lane] = dz;
-        atomicAdd(&g[NP], l / norm);
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) l += __shfl_xor(l, o, 64);
+        if (lane == 0) g[NP] = l / norm;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -293,12 +300,12 @@ __global__ __launch_bounds__(256) void k_mlp_train(const float *__restrict__ fea
             gb += d;
             L.d2[m * 64 + c] = f2bf(d);
         }
-        atomicAdd(&g[OW3 + c], gw);
-        atomicAdd(&g[OB2 + c], gb);
+        g[OW3 + c] = gw;
+        g[OB2 + c] = gb;
         if (lane == 0) {
             float s = 0.0f;
             for (int m = 0; m < 32; ++m) s += L.dz[m];
-            atomicAdd(&g[OB3], s);
+            g[OB3] = s;
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -311,20 +318,22 @@ __global__ __launch_bounds__(256) void k_mlp_train(const float *__restrict__ fea
             acc = tile_mma(L.h1 + ih * 32, 1, 64, L.d2 + jh * 32, 64, 1, 32, acc, lane);
             acc = tile_mma(L.h1lo + ih * 32, 1, 64, L.d2 + jh * 32, 64, 1, 32, acc, lane);
 #pragma unroll
-            for (int j = 0; j < 16; ++j)
-                atomicAdd(&g[OW2 + (ih * 32 + acc_row(j, lane)) * 64 + jh * 32 + acc_col(lane)], acc[j]);
+            for (int j = 0; j < 16; ++j) g[OW2 + (ih * 32 + acc_row(j, lane)) * 64 + jh * 32 + acc_col(lane)] = acc[j];
         }
     // gradient at layer-1 pre-activations: (d2 W2^T) masked; A(m, j) = d2[m][j], B(j, i) = W2[i][j]
     for (int ih = 0; ih < 2; ++ih) {
         f32x16 acc = {};
         acc = tile_mma(L.d2, 64, 1, W2b + ih * 32 * 64, 1, 64, 64, acc, lane);
+        float b1 = 0.0f;   // db1 of unit ih * 32 + acc_col(lane): this lane's rows, then the other half's
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int m = acc_row(j, lane), c = ih * 32 + acc_col(lane);
             const float d = L.h1[m * 64 + c] != 0 ? acc[j] : 0.0f;   // relu'(pre) = [h1 > 0]
             L.d1[m * 64 + c] = f2bf(d);
-            atomicAdd(&g[OB1 + c], d);
+            b1 += d;
         }
+        b1 += __shfl_xor(b1, 32, 64);
+        if (lane < 32) g[OB1 + ih * 32 + lane] = b1;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -347,12 +356,20 @@ __global__ __launch_bounds__(256) void k_mlp_train(const float *__restrict__ fea
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int k = acc_row(j, lane);
-            if (k < 12) atomicAdd(&g[OW1 + k * 64 + jh * 32 + acc_col(lane)], acc[j]);
+            if (k < 12) g[OW1 + k * 64 + jh * 32 + acc_col(lane)] = acc[j];
         }
     }
-    __syncthreads();
-    for (int t = threadIdx.x; t <= NP; t += blockDim.x)
-        if (g[t] != 0.0f) atomicAdd(grad + t, g[t]);
+}
+
+// grad[t] += sum over the rows w = 0 .. nrows - 1 of part[w * (NP + 1) + t],
+// in that order
+__global__ void k_grad_sum(const float *__restrict__ part, int64_t nrows, float *__restrict__ grad)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > NP) return;
+    float s = 0.0f;
+    for (int64_t w = 0; w < nrows; ++w) s += part[w * (NP + 1) + t];
+    grad[t] += s;
 }
 
 // bf16 copies of the weights in the layouts the kernels read
@@ -424,12 +441,16 @@ void mlp_predict(const float *feats, int64_t n, const uint16_t *W1b, const uint1
     if (n > 0) hipLaunchKernelGGL(k_mlp_predict, dim3(grid), dim3(256), 0, st, feats, n, W1b, W2b, P, logits);
 }
 
+int64_t mlp_part_rows(int64_t n) { return (n + MB - 1) / MB * 4; }
+
 void mlp_train_batch(const float *feats, const uint8_t *y, const int64_t *idx, int64_t n, const uint16_t *W1b,
-                     const uint16_t *W2b, const float *P, float pos_weight, float *grad, float *xbuf, hipStream_t st)
+                     const uint16_t *W2b, const float *P, float pos_weight, float norm, float *grad, float *part,
+                     float *xbuf, hipStream_t st)
 {
-    if (n > 0)
-        hipLaunchKernelGGL(k_mlp_train, dim3((unsigned)((n + MB - 1) / MB)), dim3(256), 0, st, feats, y, idx, n, W1b,
-                           W2b, P, pos_weight, (float)n, grad, xbuf);
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_mlp_train, dim3((unsigned)((n + MB - 1) / MB)), dim3(256), 0, st, feats, y, idx, n, W1b, W2b,
+                       P, pos_weight, norm, part, xbuf);
+    hipLaunchKernelGGL(k_grad_sum, dim3((NP + 1 + 255) / 256), dim3(256), 0, st, part, mlp_part_rows(n), grad);
 }
 
 void mlp_adam(float *P, float *M, float *V, float *grad, float lr, const int64_t *tstep, hipStream_t st)

@@ -120,6 +120,9 @@ __device__ inline void leaf_alpha(double dx, double dy, const LeafInfo &li, cons
 {
     // near field: a_* += m (z - z_i) / |z - z_i|^2
     R ax = 0, ay = 0;
+    // both loops unrolled so that several of their wavefront-uniform (scalar)
+    // loads are in flight before the first is needed
+#pragma unroll 4
     for (int32_t s = 0; s < li.near_cnt; ++s) {
         const double4 st = ns[s];
         const R ex = (R)(dx - st.x), ey = (R)(dy - st.y);
@@ -131,6 +134,7 @@ __device__ inline void leaf_alpha(double dx, double dy, const LeafInfo &li, cons
     const R zr = (R)(dx * li.invL), zi = (R)(dy * li.invL);
     if constexpr (sizeof(R) == sizeof(double)) {
         R sr = dv[p - 1].x, si = dv[p - 1].y;
+#pragma unroll 8
         for (int l = p - 2; l >= 0; --l) {
             const typename Cx<R>::c2 c = dv[l];
             const R nr = sr * zr - si * zi + c.x;
@@ -144,6 +148,7 @@ __device__ inline void leaf_alpha(double dx, double dy, const LeafInfo &li, cons
         R vr = 0, vi = 0;   // zeta sum_{l>=1} d_l zeta^(l-1)
         if (p >= 2) {
             R sr = dv[p - 1].x, si = dv[p - 1].y;
+#pragma unroll 8
             for (int l = p - 2; l >= 1; --l) {
                 const typename Cx<R>::c2 c = dv[l];
                 const R nr = sr * zr - si * zi + c.x;
