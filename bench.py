@@ -41,6 +41,13 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6          # MI355X FP64 vector, dense
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 IPM_TRAFFIC = {"ipm_sha256": "a9f751122b389124",                     # (fetch KiB, write KiB)
                "k_ipm": (719910.725, 1694723.6625), "k_band_queue1": (5504891.7875, 277114.10625)}
+# Wavefront vector instructions per launch of the same kernels (SQ_INSTS_VALU,
+# same runs and source).  A wave64 vector instruction holds its SIMD four
+# cycles, so 1024 SIMDs at 2.4 GHz issue at most 6.144e11 of them per second:
+# the kernels' issue time, set against their launch time, says how close they
+# run to the vector-issue limit that bounds them.
+IPM_VALU = {"k_ipm": 2.210e9, "k_band_queue1": 1.201e9}
+VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4
 
 
 def file_sha(path: str) -> str:
@@ -541,6 +548,14 @@ def main():
     t_band1 = sum(t["t_band_ms"] for t in one) / len(one)
     cells_roof["alone"] = {"launch_ms": t_cells1, "achieved": cells_flops(counts) / (t_cells1 * 1e-3) / 1e12}
     cells_roof["alone"]["frac"] = cells_roof["alone"]["achieved"] / cells_roof["peak"]
+
+    def valu_issue(kernel, t_alone_ms):
+        if not fresh:
+            return None
+        issue_ms = IPM_VALU[kernel] / VALU_ISSUE_PER_S * 1e3
+        return {"instructions": IPM_VALU[kernel], "issue_ms": issue_ms, "frac_of_launch_alone": issue_ms / t_alone_ms}
+
+    cells_roof["valu_issue"] = valu_issue("k_ipm", t_cells1)
     band_roof = {"bound": "alu", "achieved": band_flops(counts) / (t_band * 1e-3) / 1e12,
                  "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "traffic": traffic("k_band_queue1"),
                  "kernel": "k_band_queue1",
@@ -549,6 +564,7 @@ def main():
     band_roof["frac"] = band_roof["achieved"] / band_roof["peak"]
     band_roof["alone"] = {"launch_ms": t_band1, "achieved": band_flops(counts) / (t_band1 * 1e-3) / 1e12}
     band_roof["alone"]["frac"] = band_roof["alone"]["achieved"] / band_roof["peak"]
+    band_roof["valu_issue"] = valu_issue("k_band_queue1", t_band1)
     roof, other = (cells_roof, band_roof) if t_cells >= t_band else (band_roof, cells_roof)
     # the IPM stage priced by the survey's model: 25 flops per (triangle,
     # pixel) piece and 30 per triangle, over the whole stage's time
