@@ -48,6 +48,12 @@ IPM_TRAFFIC = {"ipm_sha256": "a9f751122b389124",                     # (fetch Ki
 # run to the vector-issue limit that bounds them.
 IPM_VALU = {"k_ipm": 2.210e9, "k_band_queue1": 1.201e9}
 VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4
+# The IPM scatter per launch (same runs and source): FP64 deposits summed in
+# LDS (SQ_INSTS_LDS_ATOMIC_BANDWIDTH x 64 B / 8 B) and atomic requests to L2
+# (TCC_ATOMIC: window flushes, deposits outside the window, shared band rows)
+IPM_SCATTER = {"k_ipm": {"lds_atomic_lanes": 3.547e8, "l2_atomic_requests": 3.987e7},
+               "k_band_queue1": {"lds_atomic_lanes": 1.053e9, "l2_atomic_requests": 4.34e6}}
+LDS_BYTES_PER_S = 256 * 2.4e9 * 128      # 128 bytes per clock per CU
 
 
 def file_sha(path: str) -> str:
@@ -556,6 +562,17 @@ def main():
         return {"instructions": IPM_VALU[kernel], "issue_ms": issue_ms, "frac_of_launch_alone": issue_ms / t_alone_ms}
 
     cells_roof["valu_issue"] = valu_issue("k_ipm", t_cells1)
+
+    def scatter(kernel, t_alone_ms):
+        if not fresh:
+            return None
+        c = IPM_SCATTER[kernel]
+        t = t_alone_ms * 1e-3
+        return {"lds_atomic_lanes": c["lds_atomic_lanes"], "lds_atomics_per_s": c["lds_atomic_lanes"] / t,
+                "lds_atomic_frac_of_lds_bytes": c["lds_atomic_lanes"] * 8 / t / LDS_BYTES_PER_S,
+                "l2_atomic_requests": c["l2_atomic_requests"], "l2_atomic_requests_per_s": c["l2_atomic_requests"] / t}
+
+    cells_roof["scatter"] = scatter("k_ipm", t_cells1)
     band_roof = {"bound": "alu", "achieved": band_flops(counts) / (t_band * 1e-3) / 1e12,
                  "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "traffic": traffic("k_band_queue1"),
                  "kernel": "k_band_queue1",
@@ -565,6 +582,7 @@ def main():
     band_roof["alone"] = {"launch_ms": t_band1, "achieved": band_flops(counts) / (t_band1 * 1e-3) / 1e12}
     band_roof["alone"]["frac"] = band_roof["alone"]["achieved"] / band_roof["peak"]
     band_roof["valu_issue"] = valu_issue("k_band_queue1", t_band1)
+    band_roof["scatter"] = scatter("k_band_queue1", t_band1)
     roof, other = (cells_roof, band_roof) if t_cells >= t_band else (band_roof, cells_roof)
     # the IPM stage priced by the survey's model: 25 flops per (triangle,
     # pixel) piece and 30 per triangle, over the whole stage's time
