@@ -141,9 +141,18 @@ Workspace::~Workspace()
     if (side) (void)hipStreamDestroy(side);
     if (fork) (void)hipEventDestroy(fork);
     if (join) (void)hipEventDestroy(join);
-    if (!pinned) return;
     std::lock_guard<std::mutex> g(g_alloc_mu);
-    (void)hipHostFree(pinned);
+    if (pinned) (void)hipHostFree(pinned);
+    if (spin) (void)hipHostFree(spin);
+}
+
+void *coherent_pinned(size_t bytes)
+{
+    std::lock_guard<std::mutex> g(g_alloc_mu);
+    void *p = nullptr;
+    MLM_HIP(hipHostMalloc(&p, bytes, hipHostMallocCoherent));
+    std::memset(p, 0, bytes);
+    return p;
 }
 
 void *pinned(mlm_lens *lens, size_t bytes)

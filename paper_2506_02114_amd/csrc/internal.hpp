@@ -253,6 +253,8 @@ struct Workspace {
     hipEvent_t fork = nullptr, join = nullptr;
     void *pinned = nullptr;               // small pinned host buffer for read-backs
     size_t pinned_cap = 0;
+    int64_t *spin = nullptr;              // coherent pinned slot of scan totals: {total, sequence}
+    int64_t spin_seq = 0;                 // sequence number of the last total asked for
     int ops_p = -1;                       // expansion order of the operator tables
     ~Workspace();
 };
@@ -382,14 +384,16 @@ void launch_band_queue1(const BandItem *items, int64_t nitems, const ItemParts &
 int64_t scan_i32_to_u64(mlm_lens *lens, const int32_t *in, unsigned long long *out, int64_t n, hipStream_t st);
 
 // scan.hip: device-wide prefix sums (tmp: scan_tmp_bytes(n)); the total is
-// stored to total_dev and/or total_host when they are given
+// stored to total_dev and/or total_host when they are given: total_host[0]
+// the total, then (after a system-scope fence) total_host[1] = seq, so a host
+// thread can wait for it without synchronising the stream
 size_t scan_tmp_bytes(int64_t n);
 void dev_scan_i32(const int32_t *in, int32_t *out, int64_t n, bool inclusive, void *tmp, int64_t *total_dev,
-                  int64_t *total_host, hipStream_t st);
+                  int64_t *total_host, int64_t seq, hipStream_t st);
 void dev_scan_i32_i64(const int32_t *in, int64_t *out, int64_t n, bool inclusive, void *tmp, int64_t *total_dev,
-                      int64_t *total_host, hipStream_t st);
+                      int64_t *total_host, int64_t seq, hipStream_t st);
 void dev_scan_i64(const int64_t *in, int64_t *out, int64_t n, bool inclusive, void *tmp, int64_t *total_dev,
-                  int64_t *total_host, hipStream_t st);
+                  int64_t *total_host, int64_t seq, hipStream_t st);
 // stable radix sort of (key, value) pairs by key bits [0, bits); the result
 // ends in kout/vout, kin/vin are overwritten (tmp: radix_sort_tmp_bytes(n))
 size_t radix_sort_tmp_bytes(int64_t n);
@@ -442,5 +446,7 @@ void mlp_step_reset(int64_t *tstep, double *lacc, bool steps, hipStream_t st);
 
 // helpers
 void *pinned(mlm_lens *lens, size_t bytes);
+// host memory the device writes coherently while it runs (zeroed)
+void *coherent_pinned(size_t bytes);
 
 }  // namespace mlm

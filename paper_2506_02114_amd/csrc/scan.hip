@@ -70,9 +70,18 @@ __global__ __launch_bounds__(SC_THREADS) void k_tile_sums(const TI *__restrict__
 
 // exclusive scan of the nt tile sums in place (one workgroup); the total goes
 // to total_dev and/or total_host when given
+// the total to the host: the value, then its sequence number behind a
+// system-scope fence, so a host thread that sees the number sees the value
+__device__ inline void store_host_total(int64_t *total_host, int64_t v, int64_t seq)
+{
+    total_host[0] = v;
+    __threadfence_system();
+    __hip_atomic_store(total_host + 1, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 template <class TO>
 __global__ __launch_bounds__(SC_THREADS) void k_scan_sums(TO *__restrict__ sums, int64_t nt, int64_t *total_dev,
-                                                         int64_t *total_host)
+                                                         int64_t *total_host, int64_t seq)
 {
     __shared__ TO part[SC_THREADS / 64];
     TO carry = 0;
@@ -86,7 +95,7 @@ __global__ __launch_bounds__(SC_THREADS) void k_scan_sums(TO *__restrict__ sums,
     }
     if (threadIdx.x == 0) {
         if (total_dev) *total_dev = (int64_t)carry;
-        if (total_host) *total_host = (int64_t)carry;
+        if (total_host) store_host_total(total_host, (int64_t)carry, seq);
     }
 }
 
@@ -97,7 +106,8 @@ __global__ __launch_bounds__(SC_THREADS) void k_scan_sums(TO *__restrict__ sums,
 template <class TI, class TO>
 __global__ __launch_bounds__(SC_THREADS) void k_tile_scan(const TI *__restrict__ in, int64_t n,
                                                          const TO *__restrict__ offs, TO *__restrict__ out,
-                                                         int inclusive, int64_t *total_dev, int64_t *total_host)
+                                                         int inclusive, int64_t *total_dev, int64_t *total_host,
+                                                         int64_t seq)
 {
     __shared__ TO part[SC_THREADS / 64];
     const int64_t base = (int64_t)blockIdx.x * SC_TILE + (int64_t)threadIdx.x * SC_ITEMS;
@@ -117,7 +127,7 @@ __global__ __launch_bounds__(SC_THREADS) void k_tile_scan(const TI *__restrict__
     }
     if (!offs && threadIdx.x == 0) {
         if (total_dev) *total_dev = (int64_t)total;
-        if (total_host) *total_host = (int64_t)total;
+        if (total_host) store_host_total(total_host, (int64_t)total, seq);
     }
 }
 
@@ -201,19 +211,19 @@ __global__ __launch_bounds__(SC_THREADS) void k_rs_scatter(const uint64_t *__res
 
 template <class TI, class TO>
 void scan_launch(const TI *in, TO *out, int64_t n, bool inclusive, TO *tile_sums, int64_t *total_dev,
-                 int64_t *total_host, hipStream_t st)
+                 int64_t *total_host, int64_t seq, hipStream_t st)
 {
     const unsigned nt = sc_tiles(n);
     if (nt <= 1) {
         hipLaunchKernelGGL((k_tile_scan<TI, TO>), dim3(1), dim3(SC_THREADS), 0, st, in, n, (const TO *)nullptr, out,
-                           inclusive ? 1 : 0, total_dev, total_host);
+                           inclusive ? 1 : 0, total_dev, total_host, seq);
         return;
     }
     hipLaunchKernelGGL((k_tile_sums<TI, TO>), dim3(nt), dim3(SC_THREADS), 0, st, in, n, tile_sums);
     hipLaunchKernelGGL((k_scan_sums<TO>), dim3(1), dim3(SC_THREADS), 0, st, tile_sums, (int64_t)nt, total_dev,
-                       total_host);
+                       total_host, seq);
     hipLaunchKernelGGL((k_tile_scan<TI, TO>), dim3(nt), dim3(SC_THREADS), 0, st, in, n, (const TO *)tile_sums, out,
-                       inclusive ? 1 : 0, (int64_t *)nullptr, (int64_t *)nullptr);
+                       inclusive ? 1 : 0, (int64_t *)nullptr, (int64_t *)nullptr, (int64_t)0);
 }
 
 }  // namespace
@@ -221,21 +231,24 @@ void scan_launch(const TI *in, TO *out, int64_t n, bool inclusive, TO *tile_sums
 size_t scan_tmp_bytes(int64_t n) { return (size_t)(sc_tiles(n) + 1) * sizeof(int64_t); }
 
 void dev_scan_i32(const int32_t *in, int32_t *out, int64_t n, bool inclusive, void *tmp, int64_t *total_dev,
-                  int64_t *total_host, hipStream_t st)
+                  int64_t *total_host, int64_t seq, hipStream_t st)
 {
-    if (n > 0) scan_launch<int32_t, int32_t>(in, out, n, inclusive, static_cast<int32_t *>(tmp), total_dev, total_host, st);
+    if (n > 0)
+        scan_launch<int32_t, int32_t>(in, out, n, inclusive, static_cast<int32_t *>(tmp), total_dev, total_host, seq, st);
 }
 
 void dev_scan_i32_i64(const int32_t *in, int64_t *out, int64_t n, bool inclusive, void *tmp, int64_t *total_dev,
-                      int64_t *total_host, hipStream_t st)
+                      int64_t *total_host, int64_t seq, hipStream_t st)
 {
-    if (n > 0) scan_launch<int32_t, int64_t>(in, out, n, inclusive, static_cast<int64_t *>(tmp), total_dev, total_host, st);
+    if (n > 0)
+        scan_launch<int32_t, int64_t>(in, out, n, inclusive, static_cast<int64_t *>(tmp), total_dev, total_host, seq, st);
 }
 
 void dev_scan_i64(const int64_t *in, int64_t *out, int64_t n, bool inclusive, void *tmp, int64_t *total_dev,
-                  int64_t *total_host, hipStream_t st)
+                  int64_t *total_host, int64_t seq, hipStream_t st)
 {
-    if (n > 0) scan_launch<int64_t, int64_t>(in, out, n, inclusive, static_cast<int64_t *>(tmp), total_dev, total_host, st);
+    if (n > 0)
+        scan_launch<int64_t, int64_t>(in, out, n, inclusive, static_cast<int64_t *>(tmp), total_dev, total_host, seq, st);
 }
 
 size_t radix_sort_tmp_bytes(int64_t n)
@@ -265,7 +278,7 @@ void radix_sort_pairs(uint64_t *kin, int32_t *vin, uint64_t *kout, int32_t *vout
         int32_t *vs = va, *vd = vb;
         hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nt), dim3(SC_THREADS), 0, st, ks, n, 8 * p, hist, nt);
         scan_launch<int32_t, int32_t>(hist, offs, RS_BINS * nt, false, static_cast<int32_t *>(stmp), nullptr, nullptr,
-                                      st);
+                                      0, st);
         hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nt), dim3(SC_THREADS), 0, st, ks, vs, n, 8 * p, offs, nt, kd,
                            vd);
         std::swap(ka, kb);

@@ -10,6 +10,9 @@
 // 3x3 neighbourhood as such references ("colleagues"), found from its
 // parent's in O(1), and the block count and the interaction lists follow
 // from them without searching the whole key array.
+#include <atomic>
+#include <chrono>
+
 #include "dev.hpp"
 
 namespace mlm {
@@ -229,27 +232,52 @@ T *grow_keep(DevBuf &b, size_t used_elems, size_t need_elems, hipStream_t st)
 
 void *scan_tmp(Workspace &ws, size_t bytes) { return ws.scan_tmp.reserve(bytes ? bytes : 1); }
 
-// A scan's total, read back to the host: the scan stores it straight into
-// pinned host memory (inside a scratch arena, which has no pinned buffer, into
-// a scratch slot that is copied), and the stream is synchronised.
+// A scan's total, read back to the host: the scan stores it straight into a
+// coherent pinned slot with a sequence number behind it, and the host spins
+// until that number appears instead of synchronising the stream (whose
+// wake-up would add its latency to every tree level and count).  After a
+// short spin it blocks on the stream instead, which also reports any error
+// of the queued work.  Inside a scratch arena (no pinned slot) the total goes
+// to a scratch slot that is copied, after a synchronisation.
 struct TotalSlot {
     int64_t *dev = nullptr, *host = nullptr;
+    int64_t seq = 0;
 };
 
 TotalSlot total_slot(mlm_lens *lens)
 {
     TotalSlot t;
-    if (Arena *a = thread_arena()) t.dev = static_cast<int64_t *>(a->take(sizeof(int64_t)));
-    else t.host = static_cast<int64_t *>(pinned(lens, sizeof(int64_t)));
+    if (Arena *a = thread_arena()) {
+        t.dev = static_cast<int64_t *>(a->take(sizeof(int64_t)));
+        return t;
+    }
+    Workspace &ws = lens->ws;
+    if (!ws.spin) ws.spin = static_cast<int64_t *>(coherent_pinned(2 * sizeof(int64_t)));
+    t.host = ws.spin;
+    t.seq = ++ws.spin_seq;
     return t;
 }
 
 int64_t read_total(const TotalSlot &t, hipStream_t st)
 {
-    int64_t v = 0;
-    if (t.dev) MLM_HIP(hipMemcpyAsync(&v, t.dev, sizeof v, hipMemcpyDeviceToHost, st));
-    MLM_HIP(hipStreamSynchronize(st));
-    return t.dev ? v : t.host[0];
+    if (t.dev) {
+        int64_t v = 0;
+        MLM_HIP(hipMemcpyAsync(&v, t.dev, sizeof v, hipMemcpyDeviceToHost, st));
+        MLM_HIP(hipStreamSynchronize(st));
+        return v;
+    }
+    const volatile int64_t *h = t.host;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int k = 1; h[1] != t.seq; ++k) {
+        if ((k & 255) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(200)) {
+            MLM_HIP(hipStreamSynchronize(st));
+            if (h[1] != t.seq) fail(MLM_EDEVICE, "a scan's total did not arrive");
+            break;
+        }
+        __builtin_ia32_pause();
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    return h[0];
 }
 
 // exclusive prefix sum of n int32 flags; returns the total
@@ -257,7 +285,7 @@ int64_t scan_total(mlm_lens *lens, const int32_t *in, int32_t *out, int64_t n, h
 {
     if (n == 0) return 0;
     const TotalSlot t = total_slot(lens);
-    dev_scan_i32(in, out, n, false, scan_tmp(lens->ws, scan_tmp_bytes(n)), t.dev, t.host, st);
+    dev_scan_i32(in, out, n, false, scan_tmp(lens->ws, scan_tmp_bytes(n)), t.dev, t.host, t.seq, st);
     return read_total(t, st);
 }
 
@@ -275,7 +303,7 @@ int64_t scan_i32_to_i64(mlm_lens *lens, const int32_t *in, int64_t *out, int64_t
     if (n == 0) return 0;
     const TotalSlot t = total_slot(lens);
     hipLaunchKernelGGL(k_zero_first, dim3(1), dim3(1), 0, st, out);
-    dev_scan_i32_i64(in, out + 1, n, true, scan_tmp(lens->ws, scan_tmp_bytes(n)), t.dev, t.host, st);
+    dev_scan_i32_i64(in, out + 1, n, true, scan_tmp(lens->ws, scan_tmp_bytes(n)), t.dev, t.host, t.seq, st);
     return read_total(t, st);
 }
 
@@ -290,7 +318,7 @@ int64_t scan_total_i64(mlm_lens *lens, const int64_t *in, int64_t *out, int64_t 
 {
     if (n == 0) return 0;
     const TotalSlot t = total_slot(lens);
-    dev_scan_i64(in, out, n, false, scan_tmp(lens->ws, scan_tmp_bytes(n)), t.dev, t.host, st);
+    dev_scan_i64(in, out, n, false, scan_tmp(lens->ws, scan_tmp_bytes(n)), t.dev, t.host, t.seq, st);
     return read_total(t, st);
 }
 
