@@ -174,11 +174,11 @@ def test_batch_errors(mlm):
 
 
 def test_batched_workload_draws(mlm, orc):
-    """The first 12 draws of the 256-map batched workload (1000^2 px, 1
-    ray/px, mixed precision), fused, against single-map calls; sampled rays
-    of two maps against the exact direct sum."""
+    """All 256 draws of the batched workload (1000^2 px, 1 ray/px, mixed
+    precision), fused, against single-map calls (compared on the device);
+    sampled rays of two maps against the exact direct sum."""
     import torch
-    draws = W.batch_draws(256, seed=4)[:12]
+    draws = W.batch_draws(256, seed=4)
     lenses, reqs, fields = [], [], []
     dev = torch.device("cuda")
     for wl in draws:
@@ -187,19 +187,20 @@ def test_batched_workload_draws(mlm, orc):
         lenses.append(mlm.Lens(L.kappa_star, L.kappa_smooth, L.gamma, torch.from_numpy(sf.x).to(dev),
                                torch.from_numpy(sf.y).to(dev), torch.from_numpy(sf.m).to(dev)))
         reqs.append(dict(wl.map.asdict(), precision="mixed"))
-        fields.append((L, sf))
+        fields.append((L, sf) if len(fields) < 2 else None)
     outs = [torch.empty((r["n2"], r["n1"]), dtype=torch.float64, device=dev) for r in reqs]
     stats, b = mlm.map_batch(lenses, reqs, outs)
     torch.cuda.synchronize()
     worst = 0.0
+    ref = torch.empty_like(outs[0])
     for lens, r, mu in zip(lenses, reqs, outs):
-        ref = torch.empty_like(mu)
+        if ref.shape != mu.shape:
+            ref = torch.empty_like(mu)
         lens.map(out=ref, **r)
-        a, c = mu.cpu().numpy(), ref.cpu().numpy()
-        pos = c > 0
-        assert np.all(np.abs(a[~pos]) < 1e-12)
-        worst = max(worst, float((np.abs(a[pos] - c[pos]) / c[pos]).max()))
-    _report("batched_workload_12_maps", max_rel_vs_single=worst, rays=b["n_rays"], chunks=b["n_chunks"],
+        pos = ref > 0
+        assert bool((mu[~pos].abs() < 1e-12).all())
+        worst = max(worst, float(((mu[pos] - ref[pos]).abs() / ref[pos]).max()))
+    _report("batched_workload_256_maps", max_rel_vs_single=worst, rays=b["n_rays"], chunks=b["n_chunks"],
             ms_total=b["t_total_ms"])
     assert worst < 1e-11
     for k in (0, 1):
