@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "colarea.hpp"
 #include "shoot_dev.hpp"
 
 namespace mlm {
@@ -33,62 +34,53 @@ __device__ inline double area2(double ua, double va, double ub, double vb, doubl
     return (ub - ua) * (vc - va) - (uc - ua) * (vb - va);
 }
 
-// part of polygon (xs, ys) with s (coord - c) >= 0, coord = x (axis 0) or y
-__device__ inline int clip_half(const double *xs, const double *ys, int n, int axis, double c, double s,
-                                double *ox, double *oy)
+// A triangle of the refinement in coordinates local to (ou, ov), an integer
+// point at or below its box (so the subtraction is exact): vertices, edge
+// slopes and its deposit per unit of covered area, w / S (S its signed
+// area; f = 0 for a degenerate or non-finite one, which deposits nothing).
+// Its pixel areas are column sums (colarea.hpp): in pixel column i the area
+// between rows j and j + 1 is H(j + 1 - ov) - H(j - ov), signed like S.
+struct RTri {
+    P2 T[3];
+    double sv[3], su[3];
+    double f;
+};
+
+__device__ inline RTri rtri(double u0, double v0, double u1, double v1, double u2, double v2, double ou, double ov,
+                            double w)
 {
-    int m = 0;
-    for (int k = 0; k < n; ++k) {
-        const int k1 = k + 1 == n ? 0 : k + 1;
-        const double a = s * ((axis ? ys[k] : xs[k]) - c), b = s * ((axis ? ys[k1] : xs[k1]) - c);
-        if (a >= 0.0) {
-            ox[m] = xs[k];
-            oy[m] = ys[k];
-            ++m;
-        }
-        if ((a >= 0.0) != (b >= 0.0)) {
-            const double t = a / (a - b);
-            ox[m] = xs[k] + t * (xs[k1] - xs[k]);
-            oy[m] = ys[k] + t * (ys[k1] - ys[k]);
-            ++m;
-        }
-    }
-    return m;
+    RTri t;
+    const double S = 0.5 * area2(u0, v0, u1, v1, u2, v2);
+    t.f = (S != 0.0 && isfinite(S)) ? w / S : 0.0;
+    if (t.f == 0.0) return t;
+    t.T[0] = P2{u0 - ou, v0 - ov};
+    t.T[1] = P2{u1 - ou, v1 - ov};
+    t.T[2] = P2{u2 - ou, v2 - ov};
+    tri_slopes(t.T, t.sv, t.su);
+    return t;
 }
 
-// signed area of triangle (u, v) inside pixel (i, j): clipped by the
-// pixel's four sides in coordinates local to its corner, then shoelace
-__device__ inline double tri_pixel_area(const double *u, const double *v, int64_t i, int64_t j)
-{
-    double px[8], py[8], qx[8], qy[8];
-    for (int k = 0; k < 3; ++k) {
-        px[k] = u[k] - (double)i;
-        py[k] = v[k] - (double)j;
-    }
-    int n = clip_half(px, py, 3, 0, 0.0, 1.0, qx, qy);
-    if (n < 3) return 0.0;
-    n = clip_half(qx, qy, n, 0, 1.0, -1.0, px, py);
-    if (n < 3) return 0.0;
-    n = clip_half(px, py, n, 1, 0.0, 1.0, qx, qy);
-    if (n < 3) return 0.0;
-    n = clip_half(qx, qy, n, 1, 1.0, -1.0, px, py);
-    if (n < 3) return 0.0;
-    double s = 0.0;
-    for (int k = 0; k < n; ++k) {
-        const int k1 = k + 1 == n ? 0 : k + 1;
-        s += px[k] * py[k1] - px[k1] * py[k];
-    }
-    return 0.5 * s;
-}
+// rows per pass of a column's sums (registers hold one pass)
+constexpr int RCH = 10;
 
-// deposit (magnification units) of a triangle of weight w (image area over
-// pixel area) into pixel (i, j)
-__device__ inline double tri_dep(double w, const double *u, const double *v, int64_t i, int64_t j)
+// adds the deposits of triangle t in pixel column i, rows jc .. jc + nr - 1,
+// to acc[0 .. nr)
+__device__ inline void column_deposits(const RTri &t, int64_t i, int64_t jc, int nr, double ou, double ov,
+                                       double (&acc)[RCH])
 {
-    const double S = 0.5 * area2(u[0], v[0], u[1], v[1], u[2], v[2]);
-    if (!(S != 0.0) || !isfinite(S)) return 0.0;
-    const double a = tri_pixel_area(u, v, i, j);
-    return a == 0.0 ? 0.0 : w * (a / S);
+    if (t.f == 0.0) return;
+    ColSegs<double> S;
+    const double cl = (double)i - ou;
+    col_segments(t.T, t.sv, t.su, cl, cl + 1.0, S);
+    double h0 = col_cumulative(S, (double)jc - ov);
+#pragma unroll
+    for (int k = 0; k < RCH; ++k) {
+        if (k < nr) {
+            const double h1 = col_cumulative(S, (double)(jc + k + 1) - ov);
+            acc[k] += t.f * (h1 - h0);
+            h0 = h1;
+        }
+    }
 }
 
 // 12 features of a mapped cell (corners 00, 10, 11, 01 in pixel units):
@@ -157,25 +149,34 @@ __device__ inline void shoot_uv(const RefineArgs &ra, double A, double B, double
 __device__ inline void add_cell(const RefineArgs &ra, double *map, double w, const double *u4, const double *v4,
                                 double sign)
 {
-    const int t[2][3] = {{0, 1, 2}, {0, 2, 3}};
+#pragma unroll 1
     for (int k = 0; k < 2; ++k) {
-        double tu[3], tv[3];
+        // triangle k of the cell: corners (0, 1, 2) or (0, 2, 3)
+        const double tu[3] = {u4[0], k ? u4[2] : u4[1], k ? u4[3] : u4[2]};
+        const double tv[3] = {v4[0], k ? v4[2] : v4[1], k ? v4[3] : v4[2]};
         bool ok = true;
-        for (int m = 0; m < 3; ++m) {
-            tu[m] = u4[t[k][m]];
-            tv[m] = v4[t[k][m]];
-            ok = ok && isfinite(tu[m]) && isfinite(tv[m]);
-        }
+#pragma unroll
+        for (int m = 0; m < 3; ++m) ok = ok && isfinite(tu[m]) && isfinite(tv[m]);
         if (!ok) continue;
-        const int64_t i0 = max((int64_t)floor(fmin(tu[0], fmin(tu[1], tu[2]))), (int64_t)0);
+        const double fu = floor(fmin(tu[0], fmin(tu[1], tu[2]))), fv = floor(fmin(tv[0], fmin(tv[1], tv[2])));
+        const int64_t i0 = max((int64_t)fu, (int64_t)0);
         const int64_t i1 = min((int64_t)floor(fmax(tu[0], fmax(tu[1], tu[2]))), (int64_t)ra.g.n1 - 1);
-        const int64_t j0 = max((int64_t)floor(fmin(tv[0], fmin(tv[1], tv[2]))), (int64_t)0);
+        const int64_t j0 = max((int64_t)fv, (int64_t)0);
         const int64_t j1 = min((int64_t)floor(fmax(tv[0], fmax(tv[1], tv[2]))), (int64_t)ra.g.n2 - 1);
-        for (int64_t j = j0; j <= j1; ++j)
+        if (i0 > i1 || j0 > j1) continue;
+        const RTri tri = rtri(tu[0], tv[0], tu[1], tv[1], tu[2], tv[2], fu, fv, sign * w);
+        for (int64_t jc = j0; jc <= j1; jc += RCH) {
+            const int nr = (int)min((int64_t)RCH, j1 - jc + 1);
             for (int64_t i = i0; i <= i1; ++i) {
-                const double d = tri_dep(w, tu, tv, i, j);
-                if (d != 0.0) unsafeAtomicAdd(map + j * (int64_t)ra.g.n1 + i, sign * d);
+                double d[RCH];
+#pragma unroll
+                for (int r = 0; r < RCH; ++r) d[r] = 0.0;
+                column_deposits(tri, i, jc, nr, fu, fv, d);
+#pragma unroll
+                for (int r = 0; r < RCH; ++r)
+                    if (r < nr && d[r] != 0.0) unsafeAtomicAdd(map + (jc + r) * (int64_t)ra.g.n1 + i, d[r]);
             }
+        }
     }
 }
 
@@ -202,6 +203,29 @@ __device__ inline void fill_grid(const RefineArgs &ra, const SubCell &c, double 
     shoot_uv(ra, c.A0 + hh, c.B0 + c.h, gu[2][1], gv[2][1]);
 }
 
+// triangle t of a refinement test: t = 0, 1 the (sub)cell's two, t = 2 ..
+// 9 its four children's two each (child (r, s) of the 3 x 3 grid, t = 2 +
+// 2 (2 r + s) + k), corners in the cell pass's order
+__device__ inline void test_triangle(int t, const SubCell &c, const double (&gu)[3][3], const double (&gv)[3][3],
+                                     double &a0, double &b0, double &a1, double &b1, double &a2, double &b2)
+{
+    switch (t) {
+#define MLM_TRI(T, U0, V0, U1, V1, U2, V2) \
+    case T: a0 = U0; b0 = V0; a1 = U1; b1 = V1; a2 = U2; b2 = V2; return;
+        MLM_TRI(0, c.u[0], c.v[0], c.u[1], c.v[1], c.u[2], c.v[2])
+        MLM_TRI(1, c.u[0], c.v[0], c.u[2], c.v[2], c.u[3], c.v[3])
+        MLM_TRI(2, gu[0][0], gv[0][0], gu[0][1], gv[0][1], gu[1][1], gv[1][1])
+        MLM_TRI(3, gu[0][0], gv[0][0], gu[1][1], gv[1][1], gu[1][0], gv[1][0])
+        MLM_TRI(4, gu[0][1], gv[0][1], gu[0][2], gv[0][2], gu[1][2], gv[1][2])
+        MLM_TRI(5, gu[0][1], gv[0][1], gu[1][2], gv[1][2], gu[1][1], gv[1][1])
+        MLM_TRI(6, gu[1][0], gv[1][0], gu[1][1], gv[1][1], gu[2][1], gv[2][1])
+        MLM_TRI(7, gu[1][0], gv[1][0], gu[2][1], gv[2][1], gu[2][0], gv[2][0])
+        MLM_TRI(8, gu[1][1], gv[1][1], gu[1][2], gv[1][2], gu[2][2], gv[2][2])
+        default: MLM_TRI(9, gu[1][1], gv[1][1], gu[2][2], gv[2][2], gu[2][1], gv[2][1])
+#undef MLM_TRI
+    }
+}
+
 __device__ inline bool refine_test(const RefineArgs &ra, const SubCell &c, double (&gu)[3][3], double (&gv)[3][3],
                                    int &too_large)
 {
@@ -224,24 +248,32 @@ __device__ inline bool refine_test(const RefineArgs &ra, const SubCell &c, doubl
     cell_features(c.u, c.v, f);
     if (folded(f)) return true;
     const double w = ra.g.tri_weight * c.h * c.h;   // parent triangle weight
-    const int64_t i0 = max((int64_t)floor(umin), (int64_t)0), i1 = min((int64_t)floor(umax), (int64_t)ra.g.n1 - 1);
-    const int64_t j0 = max((int64_t)floor(vmin), (int64_t)0), j1 = min((int64_t)floor(vmax), (int64_t)ra.g.n2 - 1);
-    const double pu[2][3] = {{c.u[0], c.u[1], c.u[2]}, {c.u[0], c.u[2], c.u[3]}};
-    const double pv[2][3] = {{c.v[0], c.v[1], c.v[2]}, {c.v[0], c.v[2], c.v[3]}};
+    const double ou = floor(umin), ov = floor(vmin);
+    const int64_t i0 = max((int64_t)ou, (int64_t)0), i1 = min((int64_t)floor(umax), (int64_t)ra.g.n1 - 1);
+    const int64_t j0 = max((int64_t)ov, (int64_t)0), j1 = min((int64_t)floor(vmax), (int64_t)ra.g.n2 - 1);
+    // L1 over the in-map pixels of (children's deposits - the cell's): pixel
+    // column by column, a pass of RCH rows at a time, one triangle after the
+    // other (t uniform across the wavefront, so the vertex choice is a scalar
+    // branch and only one triangle's column state is live)
     double l1 = 0.0;
-    for (int64_t j = j0; j <= j1; ++j)
+    for (int64_t jc = j0; jc <= j1; jc += RCH) {
+        const int nr = (int)min((int64_t)RCH, j1 - jc + 1);
         for (int64_t i = i0; i <= i1; ++i) {
-            double diff = -tri_dep(w, pu[0], pv[0], i, j) - tri_dep(w, pu[1], pv[1], i, j);
-            for (int r = 0; r < 2; ++r)
-                for (int s = 0; s < 2; ++s) {
-                    const double cu[2][3] = {{gu[r][s], gu[r][s + 1], gu[r + 1][s + 1]},
-                                             {gu[r][s], gu[r + 1][s + 1], gu[r + 1][s]}};
-                    const double cv[2][3] = {{gv[r][s], gv[r][s + 1], gv[r + 1][s + 1]},
-                                             {gv[r][s], gv[r + 1][s + 1], gv[r + 1][s]}};
-                    diff += tri_dep(0.25 * w, cu[0], cv[0], i, j) + tri_dep(0.25 * w, cu[1], cv[1], i, j);
-                }
-            l1 += fabs(diff);
+            double diff[RCH];
+#pragma unroll
+            for (int k = 0; k < RCH; ++k) diff[k] = 0.0;
+#pragma unroll 1
+            for (int t = 0; t < 10; ++t) {
+                double a0, b0, a1, b1, a2, b2;
+                test_triangle(t, c, gu, gv, a0, b0, a1, b1, a2, b2);
+                column_deposits(rtri(a0, b0, a1, b1, a2, b2, ou, ov, t < 2 ? -w : 0.25 * w), i, jc, nr, ou, ov,
+                                diff);
+            }
+#pragma unroll
+            for (int k = 0; k < RCH; ++k)
+                if (k < nr) l1 += fabs(diff[k]);
         }
+    }
     return l1 > ra.tau * 2.0 * w;
 }
 
@@ -322,7 +354,9 @@ __global__ __launch_bounds__(RBLK) void k_refine_expand(RefineArgs ra, int64_t n
     if (map) add_cell(ra, map, w, c.u, c.v, -1.0);
     const double hh = 0.5 * c.h;
     SubCell *dst = out + 4 * pos[t];
+#pragma unroll
     for (int r = 0; r < 2; ++r)
+#pragma unroll
         for (int s = 0; s < 2; ++s) {
             SubCell ch;
             ch.A0 = c.A0 + s * hh;
