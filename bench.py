@@ -26,7 +26,7 @@ import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
-IPM_SRC = os.path.join(ROOT, "paper_2506_02114_amd", "csrc", "ipm.hip")
+IPM_SRCS = [os.path.join(ROOT, "paper_2506_02114_amd", "csrc", f) for f in ("ipm.hip", "colarea.hpp")]
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
@@ -36,30 +36,34 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6          # MI355X FP64 vector, dense
 # HBM traffic of one launch of each IPM kernel on this workload, from two
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), scaled by
 # the same counters' reading of a plain 1 GiB device copy (--copy-check):
-# FETCH_SIZE x 2.0, WRITE_SIZE x 1.0.  Valid only for the IPM source they were
-# taken with, identified by its SHA-256 prefix.
+# FETCH_SIZE x 2.0, WRITE_SIZE x 1.0.  Valid only for the IPM sources they were
+# taken with (ipm.hip and colarea.hpp), identified by the SHA-256 prefix of
+# the two files' bytes in that order.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
-IPM_TRAFFIC = {"ipm_sha256": "a9f751122b389124",                     # (fetch KiB, write KiB)
-               "k_ipm": (719910.725, 1694723.6625), "k_band_queue1": (5504891.7875, 277114.10625)}
+IPM_TRAFFIC = {"ipm_sha256": "ff5d54cf1a7f173f",                     # (fetch KiB, write KiB)
+               "k_ipm": (719910.75, 1694723.6625), "k_band_queue1": (5514529.3875, 277117.11875)}
 # Wavefront vector instructions per launch of the same kernels (SQ_INSTS_VALU,
 # same runs and source).  A wave64 vector instruction holds its SIMD four
 # cycles, so 1024 SIMDs at 2.4 GHz issue at most 6.144e11 of them per second:
 # the kernels' issue time, set against their launch time, says how close they
 # run to the vector-issue limit that bounds them.
-IPM_VALU = {"k_ipm": 2.210e9, "k_band_queue1": 1.201e9}
+IPM_VALU = {"k_ipm": 2.21e+09, "k_band_queue1": 1.201e+09}
 VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4
 # The IPM scatter per launch (same runs and source): FP64 deposits summed in
 # LDS (SQ_INSTS_LDS_ATOMIC_BANDWIDTH x 64 B / 8 B) and atomic requests to L2
 # (TCC_ATOMIC: window flushes, deposits outside the window, shared band rows)
 IPM_SCATTER = {"k_ipm": {"lds_atomic_lanes": 3.547e8, "l2_atomic_requests": 3.987e7},
-               "k_band_queue1": {"lds_atomic_lanes": 1.053e9, "l2_atomic_requests": 4.34e6}}
+               "k_band_queue1": {"lds_atomic_lanes": 1.053e9, "l2_atomic_requests": 4.340e6}}
 LDS_BYTES_PER_S = 256 * 2.4e9 * 128      # 128 bytes per clock per CU
 
 
-def file_sha(path: str) -> str:
+def file_sha(paths) -> str:
     import hashlib
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def shoot_flops(stats: dict) -> float:
@@ -535,7 +539,7 @@ def main():
     shoot_roof["frac"] = shoot_roof["achieved"] / shoot_roof["peak"]
     # the two IPM kernels (one launch each per map on this workload); the
     # headline roofline is the one that takes longer
-    fresh = IPM_TRAFFIC["ipm_sha256"] == file_sha(IPM_SRC)
+    fresh = IPM_TRAFFIC["ipm_sha256"] == file_sha(IPM_SRCS)
 
     def traffic(kernel):
         t = IPM_TRAFFIC.get(kernel) if fresh else None
