@@ -361,15 +361,28 @@ __global__ __launch_bounds__(256) void k_mlp_train(const float *__restrict__ fea
     }
 }
 
-// grad[t] += sum over the rows w = 0 .. nrows - 1 of part[w * (NP + 1) + t],
-// in that order
-__global__ void k_grad_sum(const float *__restrict__ part, int64_t nrows, float *__restrict__ grad)
+// grad[t] += the sum over the rows w = 0 .. nrows - 1 of part[w * (NP + 1) + t],
+// in a fixed order: a workgroup takes 32 parameters; its thread (g, p) sums
+// the rows g, g + GS_GROUPS, ... of parameter p in order, and the GS_GROUPS
+// partial sums are then added in the order g = 0, 1, ...
+constexpr int GS_GROUPS = 8;
+__global__ __launch_bounds__(32 * GS_GROUPS) void k_grad_sum(const float *__restrict__ part, int64_t nrows,
+                                                             float *__restrict__ grad)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t > NP) return;
+    __shared__ float ps[GS_GROUPS][32];
+    const int p = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const int t = blockIdx.x * 32 + p;
     float s = 0.0f;
-    for (int64_t w = 0; w < nrows; ++w) s += part[w * (NP + 1) + t];
-    grad[t] += s;
+    if (t <= NP)
+        for (int64_t w = g; w < nrows; w += GS_GROUPS) s += part[w * (NP + 1) + t];
+    ps[g][p] = s;
+    __syncthreads();
+    if (g == 0 && t <= NP) {
+        float a = 0.0f;
+#pragma unroll
+        for (int k = 0; k < GS_GROUPS; ++k) a += ps[k][p];
+        grad[t] += a;
+    }
 }
 
 // bf16 copies of the weights in the layouts the kernels read
@@ -450,7 +463,7 @@ void mlp_train_batch(const float *feats, const uint8_t *y, const int64_t *idx, i
     if (n <= 0) return;
     hipLaunchKernelGGL(k_mlp_train, dim3((unsigned)((n + MB - 1) / MB)), dim3(256), 0, st, feats, y, idx, n, W1b, W2b,
                        P, pos_weight, norm, part, xbuf);
-    hipLaunchKernelGGL(k_grad_sum, dim3((NP + 1 + 255) / 256), dim3(256), 0, st, part, mlp_part_rows(n), grad);
+    hipLaunchKernelGGL(k_grad_sum, dim3((NP + 1 + 31) / 32), dim3(32 * GS_GROUPS), 0, st, part, mlp_part_rows(n), grad);
 }
 
 void mlp_adam(float *P, float *M, float *V, float *grad, float lr, const int64_t *tstep, hipStream_t st)

@@ -308,7 +308,9 @@ __device__ inline SubCell level_item(int64_t t, const int64_t *__restrict__ cand
 
 // flag[t] = the item is refined (and label[t] too, for candidate cells);
 // stats: [0] tested, [1] refined, [2] too large (one atomic per wavefront each)
-__global__ __launch_bounds__(RBLK) void k_refine_test(RefineArgs ra, int64_t n, const int64_t *__restrict__ cand,
+// (at most 168 registers, three waves per SIMD, a few bytes spilled: the
+// compiler's 173 held two, and the test is latency-bound on its rays' loads)
+__global__ __launch_bounds__(RBLK) __attribute__((amdgpu_waves_per_eu(3))) void k_refine_test(RefineArgs ra, int64_t n, const int64_t *__restrict__ cand,
                                                       const SubCell *__restrict__ list, int64_t nr1, int64_t vb0,
                                                       const double2 *__restrict__ verts, int32_t *__restrict__ flag,
                                                       uint8_t *__restrict__ label,
@@ -415,7 +417,7 @@ __global__ __launch_bounds__(RBLK) void k_sample_features(RefineArgs ra, int64_t
 }
 
 // the refinement test at depth 0 of arbitrary cells (labels only)
-__global__ __launch_bounds__(RBLK) void k_sample_labels(RefineArgs ra, int64_t n, const int64_t *__restrict__ ab,
+__global__ __launch_bounds__(RBLK) __attribute__((amdgpu_waves_per_eu(3))) void k_sample_labels(RefineArgs ra, int64_t n, const int64_t *__restrict__ ab,
                                                         uint8_t *__restrict__ label)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
