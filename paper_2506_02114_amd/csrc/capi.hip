@@ -1019,13 +1019,10 @@ void map_impl(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_st
                 int64_t ncand = ncells;
                 if (q.refine == MLM_REFINE_LEARNED) {
                     mlm_refiner *nn = q.refiner;
-                    float *feats = static_cast<float *>(ws.rfeat.reserve((size_t)ncells * 12 * sizeof(float)));
-                    float *logit = static_cast<float *>(ws.rlogit.reserve((size_t)ncells * sizeof(float)));
                     int32_t *flag = static_cast<int32_t *>(ws.rflag.reserve((size_t)ncells * sizeof(int32_t)));
                     int64_t *pos = static_cast<int64_t *>(ws.rpos.reserve((size_t)(ncells + 1) * sizeof(int64_t)));
-                    launch_cell_features(R.nr1, r0, ncells, vb0, verts, feats, st);
-                    mlp_predict(feats, ncells, nn->W1b.as<uint16_t>(), nn->W2b.as<uint16_t>(), nn->P.as<float>(), logit, st);
-                    launch_select(ncells, feats, logit, (float)q.refine_threshold, flag, st);
+                    mlp_flag_cells(R.nr1, r0, ncells, vb0, verts, nn->W1b.as<uint16_t>(), nn->W2b.as<uint16_t>(),
+                                   nn->P.as<float>(), (float)q.refine_threshold, flag, st);
                     ncand = scan_i32_to_i64(lens, flag, pos, ncells, st);
                     launch_compact(ncells, flag, pos, base, cand, st);
                 } else {

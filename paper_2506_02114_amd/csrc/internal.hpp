@@ -248,7 +248,7 @@ struct Workspace {
     DevBuf ilist, mult, local, ops_m2m, ops_m2l, ops_l2l;
     DevBuf leaves, near, deriv, near_offs;
     DevBuf tile_off, tile_leaf, verts, map, wbuf, pts, counters, items, itemoff, tbig, tbigoff, bigprep, bigrows, bigrow0, rowoff, nbnd, nbndoff, diff, bandcnt, bandoff,
-        bandcur, bandlist, rfeat, rlogit, rflag, rpos, rcand, rlabel, rstats, irs_counts, rtflag, rtpos, rsub0, rsub1, bitems, bqueue, tune_map;
+        bandcur, bandlist, rfeat, rflag, rpos, rcand, rlabel, rstats, irs_counts, rtflag, rtpos, rsub0, rsub1, bitems, bqueue, tune_map;
     hipStream_t side = nullptr;           // second stream of a map: the large-triangle passes beside the cell pass
     hipEvent_t fork = nullptr, join = nullptr;
     void *pinned = nullptr;               // small pinned host buffer for read-backs
@@ -417,17 +417,19 @@ void launch_refine_expand(const Tree &T, const Region &R, const LensConst &lc, c
                           int window, int64_t n, const int64_t *cand, const void *list, int64_t nr1, int64_t vb0,
                           const double2 *verts, const int32_t *flag, const int64_t *pos, double *map, void *out,
                           hipStream_t st);
-void launch_cell_features(int64_t nr1, int64_t cb0, int64_t ncells, int64_t vb0, const double2 *verts, float *feats,
-                          hipStream_t st);
 void launch_sample_features(const Tree &T, const Region &R, const LensConst &lc, const MapGeom &g, int64_t n,
                             const int64_t *ab, float *feats, hipStream_t st);
 void launch_sample_labels(const Tree &T, const Region &R, const LensConst &lc, const MapGeom &g, double tau,
                           int window, int64_t n, const int64_t *ab, uint8_t *label, hipStream_t st);
-void launch_select(int64_t n, const float *feats, const float *logits, float thr, int32_t *flag, hipStream_t st);
 void launch_compact(int64_t n, const int32_t *flag, const int64_t *pos, int64_t base, int64_t *cand, hipStream_t st);
 
 // mlp.hip
 void mlp_pack(const float *P, uint16_t *W1b, uint16_t *W2b, hipStream_t st);
+// flag[t] for the cells t of a strip (cells cb0 + t / (nr1 - 1) rows, vertex
+// rows from vb0): the network's logit of the cell's features above thr, or
+// the cell folded; the features are formed on the fly
+void mlp_flag_cells(int64_t nr1, int64_t cb0, int64_t ncells, int64_t vb0, const double2 *verts, const uint16_t *W1b,
+                    const uint16_t *W2b, const float *P, float thr, int32_t *flag, hipStream_t st);
 void mlp_predict(const float *feats, int64_t n, const uint16_t *W1b, const uint16_t *W2b, const float *P,
                  float *logits, hipStream_t st);
 // rows of per-wavefront partial gradients (MLM_REFINER_PARAMS + 1 floats

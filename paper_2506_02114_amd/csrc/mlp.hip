@@ -17,6 +17,7 @@
 // strides that make the transposes of the backward pass free.
 #include <algorithm>
 
+#include "cellfeat.hpp"
 #include "dev.hpp"
 
 namespace mlm {
@@ -160,12 +161,10 @@ __device__ inline f32x16 tile_mma_rows(const uint16_t *a, int sa, const uint16_t
     return acc;
 }
 
-__global__ __launch_bounds__(256) void k_mlp_predict(const float *__restrict__ feats, int64_t n,
-                                                     const uint16_t *__restrict__ W1b, const uint16_t *__restrict__ W2b,
-                                                     const float *__restrict__ P, float *__restrict__ logits)
+// the weights of the inference into the workgroup's LDS
+__device__ inline void stage_weights(PredictLds &S, const uint16_t *__restrict__ W1b, const uint16_t *__restrict__ W2b,
+                                     const float *__restrict__ P)
 {
-    __shared__ PredictLds S;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
         const int k = e >> 6, c = e & 63;   // W2b[k][c]
         S.w2t[c * PS + k] = W2b[e];
@@ -176,6 +175,64 @@ __global__ __launch_bounds__(256) void k_mlp_predict(const float *__restrict__ f
         S.b2[threadIdx.x] = P[OB2 + threadIdx.x];
         S.w3[threadIdx.x] = bf2f(f2bf(P[OW3 + threadIdx.x]));
     }
+}
+
+__device__ inline void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// the logit of sample `lane` (lanes < 32) of the tile whose inputs the wavefront
+// has staged in L.x
+__device__ inline float tile_logit(const PredictLds &S, PredictLds::Wave &L, float b3, int lane)
+{
+    for (int nh = 0; nh < 2; ++nh) {
+        f32x16 acc = {};
+        acc = tile_mma_rows(L.x, XS, S.w1t + nh * 32 * XS, XS, 16, acc, lane);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int m = acc_row(j, lane), c = nh * 32 + acc_col(lane);
+            const float h = fmaxf(acc[j] + S.b1[c], 0.0f);
+            const uint16_t hi = f2bf(h);
+            L.h1[m * PS + c] = hi;
+            L.h1lo[m * PS + c] = f2bf(h - bf2f(hi));
+        }
+    }
+    wave_sync_lds();
+    // layer 2 and each lane's share of layer 3: sum over its two columns
+    float part[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) part[j] = 0.0f;
+    for (int nh = 0; nh < 2; ++nh) {
+        f32x16 acc = {};
+        acc = tile_mma_rows(L.h1, PS, S.w2t + nh * 32 * PS, PS, 64, acc, lane);
+        acc = tile_mma_rows(L.h1lo, PS, S.w2t + nh * 32 * PS, PS, 64, acc, lane);
+        const int c = nh * 32 + acc_col(lane);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) part[j] += fmaxf(acc[j] + S.b2[c], 0.0f) * S.w3[c];
+    }
+    wave_sync_lds();
+    // the 32 partial sums of each sample, through LDS (h1 is free now)
+    float *zb = reinterpret_cast<float *>(L.h1);   // [32 samples][32 lanes]
+#pragma unroll
+    for (int j = 0; j < 16; ++j) zb[acc_row(j, lane) * 32 + acc_col(lane)] = part[j];
+    wave_sync_lds();
+    float z = b3;
+    if (lane < 32)
+        for (int q = 0; q < 32; ++q) z += zb[lane * 32 + ((q + lane) & 31)];
+    wave_sync_lds();   // the next tile overwrites the LDS
+    return z;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_predict(const float *__restrict__ feats, int64_t n,
+                                                     const uint16_t *__restrict__ W1b, const uint16_t *__restrict__ W2b,
+                                                     const float *__restrict__ P, float *__restrict__ logits)
+{
+    __shared__ PredictLds S;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    stage_weights(S, W1b, W2b, P);
     const float b3 = P[OB3];
     __syncthreads();
     PredictLds::Wave &L = S.w[wave];
@@ -187,54 +244,62 @@ __global__ __launch_bounds__(256) void k_mlp_predict(const float *__restrict__ f
             const int64_t s = s0 + m;
             L.x[m * XS + k] = (k < 12 && s < n) ? f2bf(feats[s * 12 + k]) : (uint16_t)0;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (int nh = 0; nh < 2; ++nh) {
-            f32x16 acc = {};
-            acc = tile_mma_rows(L.x, XS, S.w1t + nh * 32 * XS, XS, 16, acc, lane);
+        wave_sync_lds();
+        const float z = tile_logit(S, L, b3, lane);
+        if (lane < 32 && s0 + lane < n) logits[s0 + lane] = z;
+    }
+}
+
+// The cells of a strip (cells [cb0, cb0 + ncells / (nr1 - 1)) of the grid,
+// vertex rows from vb0 in `verts`) that the refinement tests: the network's
+// logit above thr, or folded.  Features are formed from the mapped corners
+// in the tile that uses them (zero for a cell with a non-finite corner, which
+// the test then leaves alone), so nothing per cell goes through memory but
+// the flag.
+__global__ __launch_bounds__(256) void k_mlp_flag_cells(int64_t nr1, int64_t cb0, int64_t ncells, int64_t vb0,
+                                                        const double2 *__restrict__ verts,
+                                                        const uint16_t *__restrict__ W1b,
+                                                        const uint16_t *__restrict__ W2b, const float *__restrict__ P,
+                                                        float thr, int32_t *__restrict__ flag)
+{
+    __shared__ PredictLds S;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    stage_weights(S, W1b, W2b, P);
+    const float b3 = P[OB3];
+    __syncthreads();
+    PredictLds::Wave &L = S.w[wave];
+    const int64_t ntiles = (ncells + 31) / 32, nwaves = (int64_t)gridDim.x * 4;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntiles; tile += nwaves) {
+        // cell m of the tile, half h of its features on this lane
+        const int m = lane & 31, h = lane >> 5;
+        const int64_t t = tile * 32 + m;
+        float f[6];
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const int m = acc_row(j, lane), c = nh * 32 + acc_col(lane);
-                const float h = fmaxf(acc[j] + S.b1[c], 0.0f);
-                const uint16_t hi = f2bf(h);
-                L.h1[m * PS + c] = hi;
-                L.h1lo[m * PS + c] = f2bf(h - bf2f(hi));
-            }
+        for (int k = 0; k < 6; ++k) f[k] = 0.0f;
+        if (t < ncells) {
+            const int64_t a = t % (nr1 - 1), b = cb0 + t / (nr1 - 1);
+            const double2 *r0 = verts + (b - vb0) * nr1, *r1 = r0 + nr1;
+            const double2 q[4] = {r0[a], r0[a + 1], r1[a + 1], r1[a]};
+            const double u4[4] = {q[0].x, q[1].x, q[2].x, q[3].x}, v4[4] = {q[0].y, q[1].y, q[2].y, q[3].y};
+            if (isfinite(u4[0]) && isfinite(u4[1]) && isfinite(u4[2]) && isfinite(u4[3]) && isfinite(v4[0]) &&
+                isfinite(v4[1]) && isfinite(v4[2]) && isfinite(v4[3]))
+                cell_features_half(u4, v4, h, f);
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // layer 2 and each lane's share of layer 3: sum over its two columns
-        float part[16];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) part[j] = 0.0f;
-        for (int nh = 0; nh < 2; ++nh) {
-            f32x16 acc = {};
-            acc = tile_mma_rows(L.h1, PS, S.w2t + nh * 32 * PS, PS, 64, acc, lane);
-            acc = tile_mma_rows(L.h1lo, PS, S.w2t + nh * 32 * PS, PS, 64, acc, lane);
-            const int c = nh * 32 + acc_col(lane);
-#pragma unroll
-            for (int j = 0; j < 16; ++j) part[j] += fmaxf(acc[j] + S.b2[c], 0.0f) * S.w3[c];
+        for (int k = 0; k < 4; ++k) L.x[m * XS + 4 * h + k] = f2bf(f[k]);
+        L.x[m * XS + 8 + 2 * h] = f2bf(f[4]);
+        L.x[m * XS + 9 + 2 * h] = f2bf(f[5]);
+        L.x[m * XS + 12 + 2 * h] = 0;
+        L.x[m * XS + 13 + 2 * h] = 0;
+        wave_sync_lds();
+        // folded: the four ear signs (0 or +-1, exact in bf16) of the staged row
+        bool fold = false;
+        if (lane < 32) {
+            const uint16_t *e = L.x + m * XS + 8;
+            fold = !(e[0] == e[1] && e[1] == e[2] && e[2] == e[3]);
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // the 32 partial sums of each sample, through LDS (h1 is free now)
-        float *zb = reinterpret_cast<float *>(L.h1);   // [32 samples][32 lanes]
-#pragma unroll
-        for (int j = 0; j < 16; ++j) zb[acc_row(j, lane) * 32 + acc_col(lane)] = part[j];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (lane < 32 && s0 + lane < n) {
-            float z = b3;
-            for (int q = 0; q < 32; ++q) z += zb[lane * 32 + ((q + lane) & 31)];
-            logits[s0 + lane] = z;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const float z = tile_logit(S, L, b3, lane);
+        if (lane < 32 && t < ncells) flag[t] = (z > thr || fold) ? 1 : 0;
     }
 }
 
@@ -444,14 +509,26 @@ void mlp_pack(const float *P, uint16_t *W1b, uint16_t *W2b, hipStream_t st)
     hipLaunchKernelGGL(k_mlp_pack, dim3(16), dim3(256), 0, st, P, W1b, W2b);
 }
 
+// a grid the device holds at once (three workgroups per CU at this LDS
+// size), each wavefront looping over tiles of 32 samples
+static unsigned predict_grid(int64_t n)
+{
+    const int64_t tiles = (n + 31) / 32;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, 256 * 3 * 4));
+}
+
+void mlp_flag_cells(int64_t nr1, int64_t cb0, int64_t ncells, int64_t vb0, const double2 *verts, const uint16_t *W1b,
+                    const uint16_t *W2b, const float *P, float thr, int32_t *flag, hipStream_t st)
+{
+    if (ncells > 0)
+        hipLaunchKernelGGL(k_mlp_flag_cells, dim3(predict_grid(ncells)), dim3(256), 0, st, nr1, cb0, ncells, vb0, verts,
+                           W1b, W2b, P, thr, flag);
+}
+
 void mlp_predict(const float *feats, int64_t n, const uint16_t *W1b, const uint16_t *W2b, const float *P,
                  float *logits, hipStream_t st)
 {
-    // a grid the device holds at once (three workgroups per CU at this LDS
-    // size), each wavefront looping over tiles of 32 samples
-    const int64_t tiles = (n + 31) / 32;
-    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, 256 * 3 * 4));
-    if (n > 0) hipLaunchKernelGGL(k_mlp_predict, dim3(grid), dim3(256), 0, st, feats, n, W1b, W2b, P, logits);
+    if (n > 0) hipLaunchKernelGGL(k_mlp_predict, dim3(predict_grid(n)), dim3(256), 0, st, feats, n, W1b, W2b, P, logits);
 }
 
 int64_t mlp_part_rows(int64_t n) { return (n + MB - 1) / MB * 4; }

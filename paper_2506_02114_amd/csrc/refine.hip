@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "cellfeat.hpp"
 #include "colarea.hpp"
 #include "shoot_dev.hpp"
 
@@ -24,15 +25,6 @@ namespace mlm {
 namespace {
 
 constexpr int RBLK = 64;
-
-__device__ inline double sgn(double x) { return (double)((x > 0.0) - (x < 0.0)); }
-
-// twice the signed area of (a, b, c), evaluated as written
-__device__ inline double area2(double ua, double va, double ub, double vb, double uc, double vc)
-{
-#pragma clang fp contract(off)
-    return (ub - ua) * (vc - va) - (uc - ua) * (vb - va);
-}
 
 // A triangle of the refinement in coordinates local to (ou, ov), an integer
 // point at or below its box (so the subtraction is exact): vertices, edge
@@ -83,27 +75,7 @@ __device__ inline void column_deposits(const RTri &t, int64_t i, int64_t jc, int
     }
 }
 
-// 12 features of a mapped cell (corners 00, 10, 11, 01 in pixel units):
-// sign(d) log(1 + |d|) of the corners' offsets from the corner of the pixel
-// holding their mean, then the signs of the mapped ears at the corners
-__device__ inline void cell_features(const double *u4, const double *v4, float *f)
-{
-    const double cu = floor(0.25 * (u4[0] + u4[1] + u4[2] + u4[3]));
-    const double cv = floor(0.25 * (v4[0] + v4[1] + v4[2] + v4[3]));
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const double du = u4[k] - cu, dv = v4[k] - cv;
-        f[2 * k] = (float)(sgn(du) * log1p(fabs(du)));
-        f[2 * k + 1] = (float)(sgn(dv) * log1p(fabs(dv)));
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int p = (k + 3) & 3, q = (k + 1) & 3;
-        f[8 + k] = (float)sgn(area2(u4[k], v4[k], u4[q], v4[q], u4[p], v4[p]));
-    }
-}
 
-__device__ inline bool folded(const float *f) { return !(f[8] == f[9] && f[9] == f[10] && f[10] == f[11]); }
 
 struct RefineArgs {
     double x0, y0, d1, d2;
@@ -376,29 +348,6 @@ __global__ __launch_bounds__(RBLK) void k_refine_expand(RefineArgs ra, int64_t n
         }
 }
 
-// features of every cell of a strip (cells [cb0, cb1) of the grid)
-__global__ __launch_bounds__(256) void k_cell_features(int64_t nr1, int64_t cb0, int64_t ncells, int64_t vb0,
-                                                       const double2 *__restrict__ verts, float *__restrict__ feats)
-{
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ncells) return;
-    const int64_t a = t % (nr1 - 1), b = cb0 + t / (nr1 - 1);
-    const double2 *r0 = verts + (b - vb0) * nr1, *r1 = r0 + nr1;
-    const double2 q[4] = {r0[a], r0[a + 1], r1[a + 1], r1[a]};
-    double u4[4], v4[4];
-    for (int m = 0; m < 4; ++m) {
-        u4[m] = q[m].x;
-        v4[m] = q[m].y;
-    }
-    float f[12];
-    if (isfinite(u4[0]) && isfinite(u4[1]) && isfinite(u4[2]) && isfinite(u4[3]) && isfinite(v4[0]) &&
-        isfinite(v4[1]) && isfinite(v4[2]) && isfinite(v4[3]))
-        cell_features(u4, v4, f);
-    else
-        for (int m = 0; m < 12; ++m) f[m] = 0.0f;
-    for (int m = 0; m < 12; ++m) feats[t * 12 + m] = f[m];
-}
-
 // features of arbitrary cells, corners shot on the spot
 __global__ __launch_bounds__(RBLK) void k_sample_features(RefineArgs ra, int64_t n, const int64_t *__restrict__ ab,
                                                           float *__restrict__ feats)
@@ -434,17 +383,6 @@ __global__ __launch_bounds__(RBLK) __attribute__((amdgpu_waves_per_eu(3))) void 
     double gu[3][3], gv[3][3];
     int large = 0;
     label[t] = refine_test(ra, c, gu, gv, large) ? 1 : 0;
-}
-
-// candidates of the learned variant: flag[t] = network says refine, or the
-// cell is folded; cells whose corners are not finite are never candidates
-__global__ __launch_bounds__(256) void k_select(int64_t n, const float *__restrict__ feats,
-                                                const float *__restrict__ logits, float thr, int32_t *__restrict__ flag)
-{
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    const float *f = feats + t * 12;
-    flag[t] = (logits[t] > thr || folded(f)) ? 1 : 0;
 }
 
 // cand[pos[t]] = base + t for flagged t (pos: exclusive scan of the flags,
@@ -515,14 +453,6 @@ void launch_refine_expand(const Tree &T, const Region &R, const LensConst &lc, c
                        static_cast<SubCell *>(out));
 }
 
-void launch_cell_features(int64_t nr1, int64_t cb0, int64_t ncells, int64_t vb0, const double2 *verts, float *feats,
-                          hipStream_t st)
-{
-    if (ncells > 0)
-        hipLaunchKernelGGL(k_cell_features, dim3((unsigned)((ncells + 255) / 256)), dim3(256), 0, st, nr1, cb0, ncells,
-                           vb0, verts, feats);
-}
-
 void launch_sample_features(const Tree &T, const Region &R, const LensConst &lc, const MapGeom &g, int64_t n,
                             const int64_t *ab, float *feats, hipStream_t st)
 {
@@ -538,12 +468,6 @@ void launch_sample_labels(const Tree &T, const Region &R, const LensConst &lc, c
     if (n <= 0) return;
     const RefineArgs ra = make_refine_args(T, R, lc, g, tau, 1, window);
     hipLaunchKernelGGL(k_sample_labels, dim3((unsigned)((n + RBLK - 1) / RBLK)), dim3(RBLK), 0, st, ra, n, ab, label);
-}
-
-void launch_select(int64_t n, const float *feats, const float *logits, float thr, int32_t *flag, hipStream_t st)
-{
-    if (n > 0)
-        hipLaunchKernelGGL(k_select, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, feats, logits, thr, flag);
 }
 
 void launch_compact(int64_t n, const int32_t *flag, const int64_t *pos, int64_t base, int64_t *cand, hipStream_t st)
