@@ -81,11 +81,9 @@ struct RefineArgs {
     double x0, y0, d1, d2;
     LensConst lc;
     MapGeom g;
-    LevelRanges lr;
     int nlevels, L0_exp, p;
     double L0;
-    const uint64_t *code;
-    const int32_t *leaf, *node_leaf;
+    const int32_t *child0, *leaf, *node_leaf;
     const LeafInfo *leaves;
     const double4 *near;
     const double2 *deriv;
@@ -102,7 +100,7 @@ __device__ inline void shoot_uv(const RefineArgs &ra, double A, double B, double
         x = ra.x0 + A * ra.d1;
         y = ra.y0 + B * ra.d2;
     }
-    const int64_t lf = find_leaf(x, y, ra.lr, ra.nlevels, ra.L0, ra.L0_exp, ra.code, ra.leaf, ra.node_leaf);
+    const int64_t lf = find_leaf(x, y, ra.nlevels, ra.L0, ra.L0_exp, ra.child0, ra.leaf, ra.node_leaf);
     if (lf < 0) {
         u = v = nan("");
         return;
@@ -409,15 +407,11 @@ RefineArgs make_refine_args(const Tree &T, const Region &R, const LensConst &lc,
     ra.d2 = R.d2;
     ra.lc = lc;
     ra.g = g;
-    for (int l = 0; l < T.nlevels; ++l) {
-        ra.lr.lo[l] = T.level_lo[l];
-        ra.lr.hi[l] = T.level_hi[l];
-    }
     ra.nlevels = T.nlevels;
     ra.L0_exp = T.L0_exp;
     ra.p = T.p;
     ra.L0 = T.L0;
-    ra.code = T.code;
+    ra.child0 = T.child0;
     ra.leaf = T.leaf;
     ra.node_leaf = T.node_leaf;
     ra.leaves = T.leaves;

@@ -224,11 +224,11 @@ __global__ void k_irs_mu(const unsigned long long *__restrict__ counts, int64_t 
     if (k < npix) map[k] = (double)counts[k] * w;
 }
 
-// w at arbitrary points: leaf by descending the levels, then as k_shoot
+// w at arbitrary points: leaf by descending the tree, then as k_shoot
 template <class R>
-__global__ void k_deflect_points(int64_t npts, const double2 *__restrict__ z, LevelRanges lr, int nlevels,
-                                 double L0, int L0_exp, const uint64_t *__restrict__ code,
-                                 const int32_t *__restrict__ leaf, const int32_t *__restrict__ node_leaf,
+__global__ void k_deflect_points(int64_t npts, const double2 *__restrict__ z, int nlevels, double L0, int L0_exp,
+                                 const int32_t *__restrict__ child0, const int32_t *__restrict__ leaf,
+                                 const int32_t *__restrict__ node_leaf,
                                  const LeafInfo *__restrict__ leaves, const double4 *__restrict__ near,
                                  const typename Cx<R>::c2 *__restrict__ deriv, int p, LensConst lc,
                                  double2 *__restrict__ w)
@@ -236,7 +236,7 @@ __global__ void k_deflect_points(int64_t npts, const double2 *__restrict__ z, Le
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= npts) return;
     double x = z[t].x, y = z[t].y;
-    const int64_t lf = find_leaf(x, y, lr, nlevels, L0, L0_exp, code, leaf, node_leaf);
+    const int64_t lf = find_leaf(x, y, nlevels, L0, L0_exp, child0, leaf, node_leaf);
     if (lf < 0) {
         w[t] = make_double2(nan(""), nan(""));
         return;
@@ -383,18 +383,12 @@ void launch_deflect_points(mlm_lens *lens, const Tree *T, const LensConst &lc, c
                            lens->d_m, (int32_t)lens->n, lc, w2);
         return;
     }
-    LevelRanges lr{};
-    for (int l = 0; l < T->nlevels; ++l) {
-        lr.lo[l] = T->level_lo[l];
-        lr.hi[l] = T->level_hi[l];
-    }
     if (T->mixed)
-        hipLaunchKernelGGL(k_deflect_points<float>, dim3(nblocks(n)), dim3(BLK), 0, st, n, z2, lr, T->nlevels, T->L0,
-                           T->L0_exp, T->code, T->leaf, T->node_leaf, T->leaves, T->near, T->deriv_f, T->p, lc, w2);
+        hipLaunchKernelGGL(k_deflect_points<float>, dim3(nblocks(n)), dim3(BLK), 0, st, n, z2, T->nlevels, T->L0,
+                           T->L0_exp, T->child0, T->leaf, T->node_leaf, T->leaves, T->near, T->deriv_f, T->p, lc, w2);
     else
-        hipLaunchKernelGGL(k_deflect_points<double>, dim3(nblocks(n)), dim3(BLK), 0, st, n, z2, lr, T->nlevels,
-                           T->L0, T->L0_exp, T->code, T->leaf, T->node_leaf, T->leaves, T->near, T->deriv, T->p, lc,
-                           w2);
+        hipLaunchKernelGGL(k_deflect_points<double>, dim3(nblocks(n)), dim3(BLK), 0, st, n, z2, T->nlevels, T->L0,
+                           T->L0_exp, T->child0, T->leaf, T->node_leaf, T->leaves, T->near, T->deriv, T->p, lc, w2);
 }
 
 }  // namespace mlm

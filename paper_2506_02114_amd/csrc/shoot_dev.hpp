@@ -164,30 +164,24 @@ __device__ inline void leaf_alpha(double dx, double dy, const LeafInfo &li, cons
     }
 }
 
-struct LevelRanges {
-    int64_t lo[KEY_BITS + 2], hi[KEY_BITS + 2];
-};
-
-// leaf containing (x, y): descend the levels, a binary search in each
-// level's sorted codes; -1 if the point lies in no leaf of the tree
-__device__ inline int64_t find_leaf(double x, double y, const LevelRanges &lr, int nlevels, double L0, int L0_exp,
-                                    const uint64_t *__restrict__ code, const int32_t *__restrict__ leaf,
+// leaf containing (x, y): down from the root through the children, the
+// quadrant of (x, y) one level down picking one (a divided node has all four,
+// at child0 + quadrant in Morton order), squares clamped to the root like the
+// star keys; -1 if the point lies in no leaf of the tree
+__device__ inline int64_t find_leaf(double x, double y, int nlevels, double L0, int L0_exp,
+                                    const int32_t *__restrict__ child0, const int32_t *__restrict__ leaf,
                                     const int32_t *__restrict__ node_leaf)
 {
-    int64_t lf = -1;
-    for (int lev = 0; lev < nlevels && lf < 0; ++lev) {
-        double scale = ldexp(1.0, lev - L0_exp);
-        uint64_t c = morton2((uint32_t)level_cell(x, L0, scale, lev), (uint32_t)level_cell(y, L0, scale, lev));
-        int64_t a = lr.lo[lev], b = lr.hi[lev];
-        while (a < b) {
-            int64_t mid = (a + b) >> 1;
-            if (code[mid] < c) a = mid + 1;
-            else b = mid;
-        }
-        if (a >= lr.hi[lev] || code[a] != c) break;
-        if (leaf[a]) lf = node_leaf[a];
+    int64_t node = 0;
+    for (int lev = 0; lev < nlevels; ++lev) {
+        if (leaf[node]) return node_leaf[node];
+        const int32_t c0 = child0[node];
+        if (c0 < 0) return -1;
+        const double scale = ldexp(1.0, lev + 1 - L0_exp);
+        const int64_t i = level_cell(x, L0, scale, lev + 1), j = level_cell(y, L0, scale, lev + 1);
+        node = (int64_t)c0 + ((i & 1) | ((j & 1) << 1));
     }
-    return lf;
+    return -1;
 }
 
 }  // namespace mlm
