@@ -40,8 +40,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6          # MI355X FP64 vector, dense
 # taken with (ipm.hip and colarea.hpp), identified by the SHA-256 prefix of
 # the two files' bytes in that order.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
-IPM_TRAFFIC = {"ipm_sha256": "ff5d54cf1a7f173f",                     # (fetch KiB, write KiB)
-               "k_ipm": (719910.75, 1694723.6625), "k_band_queue1": (5514529.3875, 277117.11875)}
+IPM_TRAFFIC = {"ipm_sha256": "807f2ce5d4fa8cd7",                     # (fetch KiB, write KiB)
+               "k_ipm": (719913.1625, 1694723.6625), "k_band_queue1": (5502708.25, 277098.4375)}
 # Wavefront vector instructions per launch of the same kernels (SQ_INSTS_VALU,
 # same runs and source).  A wave64 vector instruction holds its SIMD four
 # cycles, so 1024 SIMDs at 2.4 GHz issue at most 6.144e11 of them per second:

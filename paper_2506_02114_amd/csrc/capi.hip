@@ -954,7 +954,7 @@ void map_impl(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_st
                 BigPrep *prep = static_cast<BigPrep *>(ws.bigprep.reserve((size_t)nb * sizeof(BigPrep)));
                 int64_t *rows = static_cast<int64_t *>(ws.bigrows.reserve((size_t)nb * sizeof(int64_t)));
                 int32_t *row0 = static_cast<int32_t *>(ws.bigrow0.reserve((size_t)nb * sizeof(int32_t)));
-                launch_big_gather(verts, R.nr1, r0, r1, vb0, g, toff, prep, rows, row0, bst);
+                launch_big_gather(verts, R.nr1, r0, r1, vb0, g, nb, toff, prep, rows, row0, bst);
                 if (bh > 0) {
                     // large triangles by pixel bands: owned rows, LDS accumulation
                     const int32_t nbands = (int32_t)((g.n2 + bh - 1) / bh);

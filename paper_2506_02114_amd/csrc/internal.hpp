@@ -350,8 +350,12 @@ int64_t ipm_tile_count(int64_t nr1, int64_t nrows);
 void launch_ipm(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int64_t vb0, const MapGeom &g,
                 double *map, unsigned long long *counters, int32_t *tile_big, bool mixed, unsigned long long *work,
                 hipStream_t st);
+// the large triangles of the tiles into prep/rows/row0 at the tiles' offsets
+// tile_off (nbig in all; with fewer than one a tile, a resident grid skips
+// the empty tiles)
 void launch_big_gather(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int64_t vb0, const MapGeom &g,
-                       const int64_t *tile_off, BigPrep *prep, int64_t *rows, int32_t *row0, hipStream_t st);
+                       int64_t nbig, const int64_t *tile_off, BigPrep *prep, int64_t *rows, int32_t *row0,
+                       hipStream_t st);
 void launch_big(int64_t nbig, const BigPrep *prep, const int64_t *rows, const MapGeom &g, double *map, double *diff,
                 hipStream_t st);
 void launch_diff_rows(const MapGeom &g, const double *diff, double *map, hipStream_t st);

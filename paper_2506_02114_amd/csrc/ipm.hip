@@ -679,6 +679,53 @@ __global__ __launch_bounds__(256) void k_big_gather(const double2 *__restrict__ 
     gather_tile(verts, nr1, cb0, nrows, vb0, g, t, lo, hi, prep, rows, row0, wsum);
 }
 
+// Calls f(t) for the tiles t < tiles that hold large triangles (tile_off[t] <
+// tile_off[t + 1]), with the workgroup in step.  A resident grid strides over
+// the tiles; each workgroup reads the offsets of its next 256 tiles at once
+// (one per thread) and lists the ones that hold any, so that an empty tile
+// costs one load and no workgroup.
+template <class F>
+__device__ inline void for_big_tiles(int64_t tiles, const int64_t *__restrict__ tile_off, F &&f)
+{
+    __shared__ int64_t todo[256];
+    __shared__ int32_t nwave[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t G = gridDim.x;
+    for (int64_t base = blockIdx.x; base < tiles; base += G * 256) {
+        const int64_t t = base + (int64_t)threadIdx.x * G;
+        const bool has = t < tiles && tile_off[t] != tile_off[t + 1];
+        const unsigned long long m = __ballot(has);
+        if (lane == 0) nwave[wave] = __popcll(m);
+        __syncthreads();
+        int off = 0, n = 0;
+        for (int k = 0; k < 4; ++k) {
+            if (k < wave) off += nwave[k];
+            n += nwave[k];
+        }
+        if (has) todo[off + __popcll(m & ((1ull << lane) - 1ull))] = t;
+        __syncthreads();
+        for (int k = 0; k < n; ++k) {
+            f(todo[k]);
+            __syncthreads();   // the tile's LDS may be reused by the next
+        }
+    }
+}
+
+// The gather where most tiles hold no large triangle (a highly magnified
+// map, whose cells are far smaller than a pixel): a resident grid that skips
+// the empty tiles, instead of a workgroup per tile.
+__global__ __launch_bounds__(256) void k_big_gather_sparse(const double2 *__restrict__ verts, int64_t nr1,
+                                                           int64_t cb0, int64_t nrows, int64_t vb0, MapGeom g,
+                                                           int64_t tiles, const int64_t *__restrict__ tile_off,
+                                                           BigPrep *__restrict__ prep, int64_t *__restrict__ rows,
+                                                           int32_t *__restrict__ row0)
+{
+    __shared__ int32_t wsum[4];
+    for_big_tiles(tiles, tile_off, [&](int64_t t) {
+        gather_tile(verts, nr1, cb0, nrows, vb0, g, t, tile_off[t], tile_off[t + 1], prep, rows, row0, wsum);
+    });
+}
+
 // the batch's cell tiles: tile_off is the scan over all maps' tiles
 __global__ __launch_bounds__(256) void k_big_gather_batch(const BatchMap *__restrict__ maps, int32_t nmaps,
                                                           const int64_t *__restrict__ tile_off,
@@ -1306,6 +1353,19 @@ void launch_ipm(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int
                            counters, tile_big, work);
 }
 
+// grid of a persistent kernel: the workgroups of `threads` threads of `kernel`
+// the device holds at once with `shmem` bytes of LDS, or fewer for few items
+// (a multiple of NXCD, so that every XCD's range has workgroups of its own)
+static int64_t resident_grid(const void *kernel, int threads, size_t shmem, int64_t nitems)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    MLM_HIP(hipGetDevice(&dev));
+    MLM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    MLM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, shmem));
+    const int64_t full = (int64_t)std::max(cus, 1) * std::max(per_cu, 1);
+    return std::min(full, (nitems + NXCD - 1) / NXCD * NXCD);
+}
+
 int64_t ipm_tile_count(int64_t nr1, int64_t nrows)
 {
     const int64_t ncol = nr1 - 1;
@@ -1314,12 +1374,19 @@ int64_t ipm_tile_count(int64_t nr1, int64_t nrows)
 }
 
 void launch_big_gather(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int64_t vb0, const MapGeom &g,
-                       const int64_t *tile_off, BigPrep *prep, int64_t *rows, int32_t *row0, hipStream_t st)
+                       int64_t nbig, const int64_t *tile_off, BigPrep *prep, int64_t *rows, int32_t *row0,
+                       hipStream_t st)
 {
     const int64_t tiles = ipm_tile_count(nr1, cb1 - cb0);
-    if (tiles > 0)
+    if (tiles <= 0) return;
+    if (nbig < tiles) {   // fewer large triangles than tiles: most tiles are empty
+        const int64_t grid = resident_grid(reinterpret_cast<const void *>(&k_big_gather_sparse), 256, 0, tiles);
+        hipLaunchKernelGGL(k_big_gather_sparse, dim3((unsigned)grid), dim3(256), 0, st, verts, nr1, cb0, cb1 - cb0,
+                           vb0, g, tiles, tile_off, prep, rows, row0);
+    } else {
         hipLaunchKernelGGL(k_big_gather, dim3((unsigned)tiles), dim3(256), 0, st, verts, nr1, cb0, cb1 - cb0, vb0, g,
                            tile_off, prep, rows, row0);
+    }
 }
 
 void launch_big_count(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int64_t vb0, const MapGeom &g,
@@ -1425,19 +1492,6 @@ ItemParts split_items(const BandItem *items, int64_t n)
     return p;
 }
 
-// grid of a persistent band pass: the workgroups of `kernel` the device holds
-// at once with `shmem` bytes of LDS, or fewer for few items (a multiple of
-// NXCD, so that every XCD's range has workgroups of its own)
-static int64_t resident_grid(const void *kernel, size_t shmem, int64_t nitems)
-{
-    int dev = 0, cus = 0, per_cu = 0;
-    MLM_HIP(hipGetDevice(&dev));
-    MLM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    MLM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, BAND_THREADS, shmem));
-    const int64_t full = (int64_t)std::max(cus, 1) * std::max(per_cu, 1);
-    return std::min(full, (nitems + NXCD - 1) / NXCD * NXCD);
-}
-
 void launch_band_queue(const BatchMap *maps, int32_t nmaps, const BandItem *items, int64_t nitems,
                        const ItemParts &parts, unsigned long long *queue, const int32_t *list, const BigPrep *prep,
                        const int64_t *rows, int64_t lds_doubles, hipStream_t st)
@@ -1451,7 +1505,7 @@ void launch_band_queue(const BatchMap *maps, int32_t nmaps, const BandItem *item
     if (parts.lo[0] != 0 || parts.lo[NXCD] != nitems) fail(MLM_EINVAL, "band item ranges do not cover the items");
     const size_t shmem = (size_t)lds_doubles * sizeof(double);
     // as many workgroups as the device holds at once at this LDS size
-    const int64_t grid = resident_grid(reinterpret_cast<const void *>(&k_band_queue), shmem, nitems);
+    const int64_t grid = resident_grid(reinterpret_cast<const void *>(&k_band_queue), BAND_THREADS, shmem, nitems);
     hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(64), 0, st, queue);
     hipLaunchKernelGGL(k_band_queue, dim3((unsigned)grid), dim3(BAND_THREADS), shmem, st, maps, nmaps, items, parts,
                        queue, list, prep, rows);
@@ -1468,7 +1522,7 @@ void launch_band_queue1(const BandItem *items, int64_t nitems, const ItemParts &
     if (nitems <= 0) return;
     if (parts.lo[0] != 0 || parts.lo[NXCD] != nitems) fail(MLM_EINVAL, "band item ranges do not cover the items");
     const size_t shmem = (size_t)bh * (size_t)g.n1 * sizeof(double);
-    const int64_t grid = resident_grid(reinterpret_cast<const void *>(&k_band_queue1), shmem, nitems);
+    const int64_t grid = resident_grid(reinterpret_cast<const void *>(&k_band_queue1), BAND_THREADS, shmem, nitems);
     hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(64), 0, st, queue);
     hipLaunchKernelGGL(k_band_queue1, dim3((unsigned)grid), dim3(BAND_THREADS), shmem, st, items, parts, queue, list,
                        prep, rows, bh, g, map, work, atomic_all ? 1 : 0);
