@@ -32,15 +32,20 @@ __device__ inline double fdiv(double a, double b)
 }
 __device__ inline float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
-// edge slopes of a triangle: sv = dv/du (for clips along u), su = du/dv (along v)
+// edge slopes of a triangle: sv = dv/du (for clips along u), su = du/dv (along v);
+// a slope that overflows (an edge whose extent along one axis is below the
+// other's over the largest double) is taken as 0, as for an edge exactly
+// along that axis, so that both stay finite
 template <class R>
 __device__ inline void tri_slopes(const Pt<R> (&T)[3], R (&sv)[3], R (&su)[3])
 {
+    const R big = sizeof(R) == 4 ? R(3e38f) : R(1e308);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const R du = T[(k + 1) % 3].u - T[k].u, dv = T[(k + 1) % 3].v - T[k].v;
-        sv[k] = du != R(0) ? fdiv(dv, du) : R(0);
-        su[k] = dv != R(0) ? fdiv(du, dv) : R(0);
+        const R a = du != R(0) ? fdiv(dv, du) : R(0), b = dv != R(0) ? fdiv(du, dv) : R(0);
+        sv[k] = fabs(a) <= big ? a : R(0);
+        su[k] = fabs(b) <= big ? b : R(0);
     }
 }
 
@@ -60,21 +65,23 @@ template <class R> struct ColSegs {
 };
 
 // edge P->Q clipped to the column lo <= u <= hi, without branches: its ends
-// are clamped into the column (an end inside keeps its exact v); an edge that
-// misses the column clamps to a single point
+// are clamped into the column (an end inside keeps its exact v: for P the
+// clip's own product is then an exact zero, the slope being finite); an edge
+// that misses the column clamps to a single point, where d = 0 and lo = hi
+// make its term below zero at every r
 template <class R>
 __device__ inline ColSeg<R> col_seg(Pt<R> P, Pt<R> Q, R lo, R hi, R sv, R su)
 {
     ColSeg<R> s;
     const R eu = fmin(fmax(P.u, lo), hi), xu = fmin(fmax(Q.u, lo), hi);
-    const R ev = eu == P.u ? P.v : P.v + (eu - P.u) * sv;
-    const R xv = xu == Q.u ? Q.v : P.v + (xu - P.u) * sv;
+    const R ev = fma(eu - P.u, sv, P.v);
+    const R xv = xu == Q.u ? Q.v : fma(xu - P.u, sv, P.v);
     s.d = xu - eu;
     s.any = s.d != R(0) || ev != xv;
-    s.lo = s.any ? fmin(ev, xv) : R(0);
-    s.hi = s.any ? fmax(ev, xv) : R(0);
+    s.lo = fmin(ev, xv);
+    s.hi = fmax(ev, xv);
     s.mid = R(0.5) * (s.lo + s.hi);
-    s.c = s.d > R(0) ? R(0.5) * fabs(su) : (s.d < R(0) ? R(-0.5) * fabs(su) : R(0));
+    s.c = s.d != R(0) ? copysign(R(0.5) * fabs(su), s.d) : R(0);
     return s;
 }
 

@@ -315,9 +315,11 @@ __device__ inline int column_pieces(const P2 (&Td)[3], const double (&svd)[3], c
     // rows of the column's pieces, clamped to the triangle's in-map rows
     const int ja = (int)fmin(fmax(floor((double)cvmin) + fv0, (double)j0), (double)j1 + 1.0);
     const int jb = (int)fmax(fmin(floor((double)cvmax) + fv0, (double)j1), (double)j0 - 1.0);
-    R h0 = col_cumulative(S, (R)((double)ja - fv0));
+    R rj = (R)((double)ja - fv0);   // row line j local to fv0 (an integer: exact, also in FP32)
+    R h0 = col_cumulative(S, rj);
     for (int j = ja; j <= jb; ++j) {
-        const R h1 = col_cumulative(S, (R)((double)(j + 1) - fv0));
+        rj += R(1);
+        const R h1 = col_cumulative(S, rj);
         const double a2 = 2.0 * ((double)h1 - (double)h0);   // twice the piece area, signed like the triangle
         h0 = h1;
         if (a2 != 0.0) deposit_w(w, map, g, i, j, scale * a2);
