@@ -40,14 +40,14 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6          # MI355X FP64 vector, dense
 # taken with (ipm.hip and colarea.hpp), identified by the SHA-256 prefix of
 # the two files' bytes in that order.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
-IPM_TRAFFIC = {"ipm_sha256": "807f2ce5d4fa8cd7",                     # (fetch KiB, write KiB)
-               "k_ipm": (719913.1625, 1694723.6625), "k_band_queue1": (5502708.25, 277098.4375)}
+IPM_TRAFFIC = {"ipm_sha256": "a813834e53e157eb",                     # (fetch KiB, write KiB)
+               "k_ipm": (719912.0, 1694723.6625), "k_band_queue1": (5457746.45, 280186.8)}
 # Wavefront vector instructions per launch of the same kernels (SQ_INSTS_VALU,
 # same runs and source).  A wave64 vector instruction holds its SIMD four
 # cycles, so 1024 SIMDs at 2.4 GHz issue at most 6.144e11 of them per second:
 # the kernels' issue time, set against their launch time, says how close they
 # run to the vector-issue limit that bounds them.
-IPM_VALU = {"k_ipm": 2.21e+09, "k_band_queue1": 1.201e+09}
+IPM_VALU = {"k_ipm": 2.106e+09, "k_band_queue1": 1.173e+09}
 VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4
 # The IPM scatter per launch (same runs and source): FP64 deposits summed in
 # LDS (SQ_INSTS_LDS_ATOMIC_BANDWIDTH x 64 B / 8 B) and atomic requests to L2

@@ -1020,13 +1020,14 @@ __global__ __launch_bounds__(256) void k_band_scatter(int64_t nbig, const int32_
 // once per band (atomically when the band is shared or the cell pass runs
 // beside it).
 
-// edge P->Q clipped to the pixel row rl <= v <= rl + 1 (su = du/dv): the u of
-// its ends and its extent dv; false if it has none in the row (an edge with
-// P.v = Q.v included).  Ends inside the row keep their exact u.
+// edge P->Q clipped to the pixel row rl <= v <= rl + 1 (su = du/dv, finite):
+// the u of its ends and its extent dv; false if it has none in the row (an
+// edge with P.v = Q.v included).  Ends inside the row keep their exact u (for
+// P the clip's product is then an exact zero).
 __device__ inline bool row_clip(P2 P, P2 Q, double rl, double su, double &ua, double &ub, double &dv)
 {
     const double ev = fmin(fmax(P.v, rl), rl + 1.0), xv = fmin(fmax(Q.v, rl), rl + 1.0);
-    ua = ev == P.v ? P.u : P.u + (ev - P.v) * su;
+    ua = fma(ev - P.v, su, P.u);
     ub = xv == Q.v ? Q.u : P.u + (xv - P.v) * su;
     dv = xv - ev;
     return dv != 0.0;
