@@ -175,6 +175,7 @@ namespace {
 
 constexpr int64_t STRIP_VERTS = 1ll << 26;   // vertices per strip buffer (1 GiB of double2)
 constexpr int64_t IRS_STRIP_RAYS = 1ll << 30;   // rays per inverse-ray-shooting launch (nothing stored per ray)
+constexpr double FINE_CELLS_PER_PIXEL = 256.0;  // cells per map pixel from which the cell pass takes its 16 x 16 window
 
 __global__ void k_fill(double *p, int64_t n, double v)
 {
@@ -904,6 +905,13 @@ void map_impl(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_st
         double *wdev = nullptr;
         if (q.w_out) wdev = q.device_out ? q.w_out : static_cast<double *>(ws.wbuf.reserve((size_t)nbuf * sizeof(double2)));
 
+        // The cell pass sums its deposits in a 64 x 64 pixel LDS window per tile
+        // of 16 x 16 cells, or in a 16 x 16 one where the map holds so many
+        // cells per pixel that a tile lands in a pixel or two: there clearing
+        // and flushing 4096 window entries would cost more than the tile's
+        // cells (the shooting region covers the map, so cells per map pixel
+        // is how finely the cells divide a pixel on average).
+        const bool fine = (double)(R.nr1 - 1) * (double)(R.nr2 - 1) >= FINE_CELLS_PER_PIXEL * (double)g.n1 * (double)g.n2;
         for (int64_t r0 = cb0; r0 < cb1; ++nstrips) {
             int64_t r1 = std::min(cb1, r0 + rows_per_strip - 1);   // cells [r0, r1), vertex rows [r0, r1]
             int64_t vb0 = r0, vb1 = r1 + 1;
@@ -946,7 +954,7 @@ void map_impl(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_st
             }
             const int e_cells0 = tm.mark();
             launch_ipm(verts, R.nr1, r0, r1, vb0, g, map, cnt, overlap ? nullptr : tbig, q.precision == MLM_PREC_MIXED,
-                       q.timing >= 2 ? cnt + 8 : nullptr, st);
+                       fine, q.timing >= 2 ? cnt + 8 : nullptr, st);
             const int e_cells = tm.mark();
             int e_band0 = -1, e_band1 = -1;
             const int64_t nb = scan_i32_to_i64(lens, tbig, toff, ntl, bst);

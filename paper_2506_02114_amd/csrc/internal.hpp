@@ -347,9 +347,10 @@ constexpr int64_t BIN_TRIS = 2048;
 // cell tiles of the cell pass over cell rows [cb0, cb0 + nrows): one workgroup and one
 // large-triangle count each
 int64_t ipm_tile_count(int64_t nr1, int64_t nrows);
+// (fine: the 16 x 16 pixel LDS window, for maps of many cells per pixel)
 void launch_ipm(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int64_t vb0, const MapGeom &g,
-                double *map, unsigned long long *counters, int32_t *tile_big, bool mixed, unsigned long long *work,
-                hipStream_t st);
+                double *map, unsigned long long *counters, int32_t *tile_big, bool mixed, bool fine,
+                unsigned long long *work, hipStream_t st);
 // the large triangles of the tiles into prep/rows/row0 at the tiles' offsets
 // tile_off (nbig in all; with fewer than one a tile, a resident grid skips
 // the empty tiles)

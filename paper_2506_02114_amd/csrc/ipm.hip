@@ -123,22 +123,27 @@ __device__ inline void deposit(double *map, const MapGeom &g, int i, int j, doub
 }
 
 // pixel window of a workgroup in LDS: deposits inside it are summed there and
-// added to the map once per pixel at the end; the rest go straight to the map
-constexpr int WIN = 64;   // window side in pixels (WIN x WIN doubles)
+// added to the map once per pixel at the end; the rest go straight to the map.
+// Its side N is 64 pixels, or 16 where a tile's cells cover far less than a
+// pixel each (a highly magnified map), so that clearing and flushing the
+// window does not cost more than the tile's deposits.
+constexpr int WIN = 64;        // window side in pixels (WIN x WIN doubles)
+constexpr int WIN_FINE = 16;   // the side for maps of many cells per pixel
 
-struct Window {
-    double *acc;          // WIN x WIN, row-major
+template <int N> struct Window {
+    double *acc;          // N x N, row-major
     int i0, j0;           // map pixel of acc[0]
 };
 
-__device__ inline void deposit_w(const Window &w, double *map, const MapGeom &g, int i, int j, double val)
+template <int N>
+__device__ inline void deposit_w(const Window<N> &w, double *map, const MapGeom &g, int i, int j, double val)
 {
     const int di = i - w.i0, dj = j - w.j0;
-    if ((unsigned)di < (unsigned)WIN && (unsigned)dj < (unsigned)WIN)
+    if ((unsigned)di < (unsigned)N && (unsigned)dj < (unsigned)N)
         // workgroup scope: kept apart from the device-scope map deposit, so the
         // two are not merged into one generic (flat) atomic and this one stays
         // an LDS atomic
-        __hip_atomic_fetch_add(w.acc + dj * WIN + di, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(w.acc + dj * N + di, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     else
         deposit(map, g, i, j, val);
 }
@@ -222,7 +227,8 @@ __device__ inline double part_below(double a, double b, double c, double S)
     return n == 0 ? 0.0 : (n == 3 ? S : (n == 1 ? corner : S - corner));
 }
 
-__device__ inline void put_pixel(const Window &w, double *map, const MapGeom &g, int i, int j, double val)
+template <int N>
+__device__ inline void put_pixel(const Window<N> &w, double *map, const MapGeom &g, int i, int j, double val)
 {
     if (val != 0.0 && i >= 0 && j >= 0 && i < g.n1 && j < g.n2) deposit_w(w, map, g, i, j, val);
 }
@@ -234,8 +240,9 @@ __device__ inline void put_pixel(const Window &w, double *map, const MapGeom &g,
 // u = 1 cuts off, clipped below v = 1 (or HB minus it, when the corner is the
 // right-hand part).  Local coordinates are exact: a double minus a nearby
 // integer.
+template <int N>
 __device__ inline void small_triangle(P2 A, P2 B, P2 C, double fu0, double fv0, const MapGeom &g, double *map,
-                                      const Window &w)
+                                      const Window<N> &w)
 {
     const P2 a{A.u - fu0, A.v - fv0}, b{B.u - fu0, B.v - fv0}, c{C.u - fu0, C.v - fv0};
     const double S = 0.5 * twice_area(A, B, C, fu0, fv0);   // never 0: those go to one pixel
@@ -296,9 +303,9 @@ __device__ inline bool cell_in_one_pixel(P2 v00, P2 v10, P2 v11, P2 v01, const M
 // pixel pieces of one column of a triangle: T in coordinates local to the
 // integer point (fu0, fv0) (formed in FP64), cl = column - fu0; each piece is
 // a difference of the column's cumulative edge sum H at two row lines
-template <class R>
+template <class R, int N>
 __device__ inline int column_pieces(const P2 (&Td)[3], const double (&svd)[3], const double (&sud)[3], double cl, double fv0, int i, int j0, int j1,
-                                     double scale, const MapGeom &g, double *map, const Window &w)
+                                     double scale, const MapGeom &g, double *map, const Window<N> &w)
 {
     const Pt<R> T[3] = {Pt<R>{(R)Td[0].u, (R)Td[0].v}, Pt<R>{(R)Td[1].u, (R)Td[1].v}, Pt<R>{(R)Td[2].u, (R)Td[2].v}};
     const R sv[3] = {(R)svd[0], (R)svd[1], (R)svd[2]};
@@ -382,8 +389,8 @@ __device__ inline ColSetup shfl_setup(const ColSetup &s, int L)
 }
 
 // pixel column i0 + r of the triangle set up in `c`
-template <bool MIXED>
-__device__ inline int setup_column(const ColSetup &c, int r, const MapGeom &g, double *map, const Window &w)
+template <bool MIXED, int N>
+__device__ inline int setup_column(const ColSetup &c, int r, const MapGeom &g, double *map, const Window<N> &w)
 {
     const int i = c.i0 + r;
     const double cl = (double)i - c.fu0;
@@ -402,8 +409,8 @@ __device__ inline int setup_column(const ColSetup &c, int r, const MapGeom &g, d
 constexpr int CT = 16;   // cells per tile side
 
 // cell tile `tile` of a strip (a whole workgroup of 256 threads; acc is its
-// WIN x WIN LDS window)
-template <bool MIXED>
+// N x N LDS window)
+template <bool MIXED, int N>
 __device__ __forceinline__ void ipm_tile(const double2 *__restrict__ verts, int64_t nr1, int64_t cb0, int64_t nrows,
                                 int64_t vb0, const MapGeom &g, double *__restrict__ map,
                                 unsigned long long *__restrict__ counters, int32_t *__restrict__ tile_big, int64_t tile,
@@ -415,17 +422,17 @@ __device__ __forceinline__ void ipm_tile(const double2 *__restrict__ verts, int6
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t a = ta * CT + (lane & (CT - 1));
     const int64_t brow = tb * CT + wave * 4 + (lane >> 4);   // cell row within the strip
-    for (int k = threadIdx.x; k < WIN * WIN; k += blockDim.x) acc[k] = 0.0;
+    for (int k = threadIdx.x; k < N * N; k += blockDim.x) acc[k] = 0.0;
     // window anchored on the image of the tile's centre vertex
-    Window w;
+    Window<N> w;
     w.acc = acc;
     {
         const int64_t ca = min(ta * CT + CT / 2, ncol), cb = min(tb * CT + CT / 2, nrows);
         const double2 c = verts[(cb0 + cb - vb0) * nr1 + ca];
         const double fu = isfinite(c.x) ? fmin(fmax(floor(c.x), -1e9), 1e9) : 0.0;
         const double fv = isfinite(c.y) ? fmin(fmax(floor(c.y), -1e9), 1e9) : 0.0;
-        w.i0 = (int)fu - WIN / 2;
-        w.j0 = (int)fv - WIN / 2;
+        w.i0 = (int)fu - N / 2;
+        w.j0 = (int)fv - N / 2;
     }
     __syncthreads();
     unsigned n_small = 0, n_items = 0, n_pieces = 0;   // work counts (statistics)
@@ -501,10 +508,10 @@ __device__ __forceinline__ void ipm_tile(const double2 *__restrict__ verts, int6
         }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < WIN * WIN; k += blockDim.x) {
+    for (int k = threadIdx.x; k < N * N; k += blockDim.x) {
         const double v = acc[k];
         if (v != 0.0) {
-            const int i = w.i0 + (k % WIN), j = w.j0 + (k / WIN);
+            const int i = w.i0 + (k % N), j = w.j0 + (k / N);
             deposit(map, g, i, j, v);   // inside the map: only in-map pixels were deposited
         }
     }
@@ -521,7 +528,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                                              unsigned long long *__restrict__ work)
 {
     __shared__ double acc[WIN * WIN];
-    ipm_tile<MIXED>(verts, nr1, cb0, nrows, vb0, g, map, counters, tile_big, blockIdx.x, acc, work);
+    ipm_tile<MIXED, WIN>(verts, nr1, cb0, nrows, vb0, g, map, counters, tile_big, blockIdx.x, acc, work);
+}
+
+// the same with the 16 x 16 window
+template <bool MIXED>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_ipm_fine(const double2 *__restrict__ verts, int64_t nr1, int64_t cb0,
+                                             int64_t nrows, int64_t vb0, MapGeom g, double *__restrict__ map,
+                                             unsigned long long *__restrict__ counters, int32_t *__restrict__ tile_big,
+                                             unsigned long long *__restrict__ work)
+{
+    __shared__ double acc[WIN_FINE * WIN_FINE];
+    ipm_tile<MIXED, WIN_FINE>(verts, nr1, cb0, nrows, vb0, g, map, counters, tile_big, blockIdx.x, acc, work);
 }
 
 // every cell tile of every map of a fused batch in one launch (one
@@ -535,10 +553,10 @@ __global__ __launch_bounds__(256) void k_ipm_batch(const BatchMap *__restrict__ 
         const int32_t m = batch_find(maps, nmaps, t, &BatchMap::ctile_lo);
         const BatchMap &d = maps[m];
         if (d.mixed)
-            ipm_tile<true>(d.verts, d.nr1, 0, d.nrows, 0, d.g, d.map, d.counters, tile_big + d.ctile_lo, t - d.ctile_lo,
+            ipm_tile<true, WIN>(d.verts, d.nr1, 0, d.nrows, 0, d.g, d.map, d.counters, tile_big + d.ctile_lo, t - d.ctile_lo,
                            acc, nullptr);
         else
-            ipm_tile<false>(d.verts, d.nr1, 0, d.nrows, 0, d.g, d.map, d.counters, tile_big + d.ctile_lo, t - d.ctile_lo,
+            ipm_tile<false, WIN>(d.verts, d.nr1, 0, d.nrows, 0, d.g, d.map, d.counters, tile_big + d.ctile_lo, t - d.ctile_lo,
                             acc, nullptr);
     }
 }
@@ -1343,17 +1361,14 @@ __global__ __launch_bounds__(256) void k_count_pieces(const double2 *__restrict_
 }  // namespace
 
 void launch_ipm(const double2 *verts, int64_t nr1, int64_t cb0, int64_t cb1, int64_t vb0, const MapGeom &g,
-                double *map, unsigned long long *counters, int32_t *tile_big, bool mixed, unsigned long long *work,
-                hipStream_t st)
+                double *map, unsigned long long *counters, int32_t *tile_big, bool mixed, bool fine,
+                unsigned long long *work, hipStream_t st)
 {
     const int64_t nrows = cb1 - cb0, tiles = ipm_tile_count(nr1, nrows);
     if (tiles <= 0) return;
-    if (mixed)
-        hipLaunchKernelGGL(k_ipm<true>, dim3((unsigned)tiles), dim3(256), 0, st, verts, nr1, cb0, nrows, vb0, g, map,
-                           counters, tile_big, work);
-    else
-        hipLaunchKernelGGL(k_ipm<false>, dim3((unsigned)tiles), dim3(256), 0, st, verts, nr1, cb0, nrows, vb0, g, map,
-                           counters, tile_big, work);
+    auto *k = fine ? (mixed ? k_ipm_fine<true> : k_ipm_fine<false>) : (mixed ? k_ipm<true> : k_ipm<false>);
+    hipLaunchKernelGGL(k, dim3((unsigned)tiles), dim3(256), 0, st, verts, nr1, cb0, nrows, vb0, g, map, counters,
+                       tile_big, work);
 }
 
 // grid of a persistent kernel: the workgroups of `threads` threads of `kernel`

@@ -172,6 +172,28 @@ def test_map_small_matches_oracle(mlm, orc):
     assert mu.sum() * ref.region.pix1 * ref.region.pix2 == pytest.approx(ref.dep_total, rel=1e-9)
 
 
+def test_map_with_few_large_triangles_matches_oracle(mlm, orc):
+    """Coarse pixels over a fine ray grid (24^2 px, 1024^2 rays, one strip):
+    fewer large triangles than cell tiles, the case where the gather strides
+    a resident grid over the tiles and skips the empty ones, and 1800 cells
+    per pixel, where the cell pass sums in its 16 x 16 pixel window; the map
+    against the oracle's."""
+    wl = W.config("plain_small")
+    sf = wl.stars()
+    gl, ol = _pair(mlm, orc, 0.3, 0.0, 0.3, sf)
+    spec = _spec(wl, order=20, n1=24, n2=24, nray1=1024, nray2=1024)
+    R = gl.region(**spec)
+    tiles = -(-(R["nr1"] - 1) // 16) * -(-(R["nr2"] - 1) // 16)
+    mu, st = gl.map(timing=2, **spec)
+    ref = orc.magnification_map(ol, spec, method="fmm", p=20)
+    rel, zok = _rel_map_err(mu, ref.mu)
+    _report("map_few_large_triangles_vs_oracle_fmm", max=float(rel.max()), median=float(np.median(rel)),
+            big=st["n_big"], tiles=int(tiles))
+    assert 0 < st["n_big"] < tiles
+    assert zok and rel.max() < 1e-9
+    assert mu.sum() * ref.region.pix1 * ref.region.pix2 == pytest.approx(ref.dep_total, rel=1e-9)
+
+
 def test_timing_levels_and_work_counts(mlm):
     """timing 0, 1 and 2 make the same map; only timing 2 fills the IPM
     kernels' work counts, which obey their definitions' bounds."""
