@@ -40,8 +40,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6          # MI355X FP64 vector, dense
 # taken with (ipm.hip and colarea.hpp), identified by the SHA-256 prefix of
 # the two files' bytes in that order.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
-IPM_TRAFFIC = {"ipm_sha256": "a813834e53e157eb",                     # (fetch KiB, write KiB)
-               "k_ipm": (719912.0, 1694723.6625), "k_band_queue1": (5457746.45, 280186.8)}
+IPM_TRAFFIC = {"ipm_sha256": "f487ab820c5e507d",                     # (fetch KiB, write KiB)
+               "k_ipm": (719908.5625, 1694723.6625), "k_band_queue1": (5465138.0, 280190.83125)}
 # Wavefront vector instructions per launch of the same kernels (SQ_INSTS_VALU,
 # same runs and source).  A wave64 vector instruction holds its SIMD four
 # cycles, so 1024 SIMDs at 2.4 GHz issue at most 6.144e11 of them per second:
