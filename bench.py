@@ -40,19 +40,19 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6          # MI355X FP64 vector, dense
 # taken with (ipm.hip and colarea.hpp), identified by the SHA-256 prefix of
 # the two files' bytes in that order.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
-IPM_TRAFFIC = {"ipm_sha256": "f487ab820c5e507d",                     # (fetch KiB, write KiB)
-               "k_ipm": (719908.5625, 1694723.6625), "k_band_queue1": (5465138.0, 280190.83125)}
+IPM_TRAFFIC = {"ipm_sha256": "a530c3ebbb5bdec1",                     # (fetch KiB, write KiB)
+               "k_ipm": (719907.3125, 2278836.5375), "k_band_queue1": (5449613.4625, 280182.2875)}
 # Wavefront vector instructions per launch of the same kernels (SQ_INSTS_VALU,
 # same runs and source).  A wave64 vector instruction holds its SIMD four
 # cycles, so 1024 SIMDs at 2.4 GHz issue at most 6.144e11 of them per second:
 # the kernels' issue time, set against their launch time, says how close they
 # run to the vector-issue limit that bounds them.
-IPM_VALU = {"k_ipm": 2.106e+09, "k_band_queue1": 1.173e+09}
+IPM_VALU = {"k_ipm": 2.057e+09, "k_band_queue1": 1.173e+09}
 VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4
 # The IPM scatter per launch (same runs and source): FP64 deposits summed in
 # LDS (SQ_INSTS_LDS_ATOMIC_BANDWIDTH x 64 B / 8 B) and atomic requests to L2
 # (TCC_ATOMIC: window flushes, deposits outside the window, shared band rows)
-IPM_SCATTER = {"k_ipm": {"lds_atomic_lanes": 3.547e8, "l2_atomic_requests": 3.987e7},
+IPM_SCATTER = {"k_ipm": {"lds_atomic_lanes": 3.239e8, "l2_atomic_requests": 5.790e7},
                "k_band_queue1": {"lds_atomic_lanes": 1.053e9, "l2_atomic_requests": 4.340e6}}
 LDS_BYTES_PER_S = 256 * 2.4e9 * 128      # 128 bytes per clock per CU
 

@@ -905,10 +905,10 @@ void map_impl(mlm_lens *lens, const mlm_map_request *req, double *mu, mlm_map_st
         double *wdev = nullptr;
         if (q.w_out) wdev = q.device_out ? q.w_out : static_cast<double *>(ws.wbuf.reserve((size_t)nbuf * sizeof(double2)));
 
-        // The cell pass sums its deposits in a 64 x 64 pixel LDS window per tile
+        // The cell pass sums its deposits in a 48 x 48 pixel LDS window per tile
         // of 16 x 16 cells, or in a 16 x 16 one where the map holds so many
         // cells per pixel that a tile lands in a pixel or two: there clearing
-        // and flushing 4096 window entries would cost more than the tile's
+        // and flushing 2304 window entries would cost more than the tile's
         // cells (the shooting region covers the map, so cells per map pixel
         // is how finely the cells divide a pixel on average).
         const bool fine = (double)(R.nr1 - 1) * (double)(R.nr2 - 1) >= FINE_CELLS_PER_PIXEL * (double)g.n1 * (double)g.n2;

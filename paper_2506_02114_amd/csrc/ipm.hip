@@ -124,10 +124,12 @@ __device__ inline void deposit(double *map, const MapGeom &g, int i, int j, doub
 
 // pixel window of a workgroup in LDS: deposits inside it are summed there and
 // added to the map once per pixel at the end; the rest go straight to the map.
-// Its side N is 64 pixels, or 16 where a tile's cells cover far less than a
-// pixel each (a highly magnified map), so that clearing and flushing the
+// Its side N is 48 pixels (wide enough for most tiles' images at a few cells
+// per pixel; 18 KiB, so more cell-pass workgroups share a CU with the band
+// pass beside it than at 64), or 16 where a tile's cells cover far less than
+// a pixel each (a highly magnified map), so that clearing and flushing the
 // window does not cost more than the tile's deposits.
-constexpr int WIN = 64;        // window side in pixels (WIN x WIN doubles)
+constexpr int WIN = 48;        // window side in pixels (WIN x WIN doubles)
 constexpr int WIN_FINE = 16;   // the side for maps of many cells per pixel
 
 template <int N> struct Window {
