@@ -283,7 +283,7 @@ __global__ __launch_bounds__(256) void k_mlp_flag_cells(int64_t nr1, int64_t cb0
             const double u4[4] = {q[0].x, q[1].x, q[2].x, q[3].x}, v4[4] = {q[0].y, q[1].y, q[2].y, q[3].y};
             if (isfinite(u4[0]) && isfinite(u4[1]) && isfinite(u4[2]) && isfinite(u4[3]) && isfinite(v4[0]) &&
                 isfinite(v4[1]) && isfinite(v4[2]) && isfinite(v4[3]))
-                cell_features_half(u4, v4, h, f);
+                cell_features_half_f32(u4, v4, h, f);
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) L.x[m * XS + 4 * h + k] = f2bf(f[k]);
