@@ -186,7 +186,7 @@ __device__ inline void wave_sync_lds()
 
 // the logit of sample `lane` (lanes < 32) of the tile whose inputs the wavefront
 // has staged in L.x
-__device__ inline float tile_logit(const PredictLds &S, PredictLds::Wave &L, float b3, int lane)
+__device__ __forceinline__ float tile_logit(const PredictLds &S, PredictLds::Wave &L, float b3, int lane)
 {
     for (int nh = 0; nh < 2; ++nh) {
         f32x16 acc = {};
