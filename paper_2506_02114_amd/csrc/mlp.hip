@@ -31,13 +31,9 @@ constexpr int NP = 5057;
 constexpr int OW1 = 0, OB1 = 768, OW2 = 832, OB2 = 4928, OW3 = 4992, OB3 = 5056;
 constexpr int MB = 128;   // samples per workgroup (4 wavefronts x 32)
 
-// float -> bf16, round to nearest even (finite inputs)
-__device__ inline uint16_t f2bf(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+// float -> bf16, round to nearest even (finite inputs): one hardware
+// conversion (v_cvt_pk_bf16_f32) in the default rounding mode
+__device__ inline uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // C (32 x 32 tile) += A (32 x K) B (K x 32); A(m, k) = a[m * sam + k * sak],
