@@ -117,8 +117,10 @@ __global__ __launch_bounds__(64) void k_shoot_irs(ShootArgs sa, LensConst lc, Ma
     irs_count(pt.valid, uv, g, counts);
 }
 
-// shoot tile t of a map (one 64-lane wavefront per 8 x 8 tile)
-template <class R>
+// shoot tile t of a map (one 64-lane wavefront per 8 x 8 tile, a workgroup
+// of its own); STAGED: the leaf's near stars and coefficients through LDS
+// (leaf_alpha_tile), else through the scalar cache
+template <class R, bool STAGED = false>
 __device__ inline void shoot_tile(const ShootArgs &sa, const LensConst &lc, const MapGeom &g,
                                   const int32_t *__restrict__ tile_leaf, const int32_t *__restrict__ tile_off,
                                   const LeafInfo *__restrict__ leaves, const double4 *__restrict__ near,
@@ -134,7 +136,12 @@ __device__ inline void shoot_tile(const ShootArgs &sa, const LensConst &lc, cons
     const int64_t a = li.a_lo + ia, b = li.b_lo + ib;
     const double x = grid_pos(sa.x0, sa.d1, a), y = grid_pos(sa.y0, sa.d2, b);
     double ax, ay;
-    leaf_alpha<R>(x - li.cx, y - li.cy, li, near + li.near_off, deriv + (int64_t)lf * sa.p, sa.p, ax, ay);
+    if constexpr (STAGED) {
+        __shared__ LeafLds<R> S;   // the workgroup is this one wavefront
+        leaf_alpha_tile<R>(x - li.cx, y - li.cy, li, near + li.near_off, deriv + (int64_t)lf * sa.p, sa.p, ax, ay, S);
+    } else {
+        leaf_alpha<R>(x - li.cx, y - li.cy, li, near + li.near_off, deriv + (int64_t)lf * sa.p, sa.p, ax, ay);
+    }
     double w1, w2;
     double2 uv;
     finish_vertex(lc, g, x, y, ax, ay, w1, w2, uv);
@@ -155,6 +162,24 @@ __global__ __launch_bounds__(64) void k_shoot(ShootArgs sa, LensConst lc, MapGeo
                                               double2 *__restrict__ verts, double2 *__restrict__ w_out)
 {
     shoot_tile<R>(sa, lc, g, tile_leaf, tile_off, leaves, near, deriv, verts, w_out, blockIdx.x, threadIdx.x);
+}
+
+// the same with the leaf's stars and coefficients staged through LDS, for
+// maps of few tiles per leaf: there a tile's scalar loads of its leaf's stars
+// mostly miss the scalar cache, and waiting on them a few stars at a time
+// cost more than one vector load of 64 (on the 1e5-star map: shooting
+// 1.11 -> 0.81 ms); where a leaf has thousands of tiles they hit, and the
+// scalar path is the faster
+template <class R>
+__global__ __launch_bounds__(64) void k_shoot_staged(ShootArgs sa, LensConst lc, MapGeom g,
+                                                     const int32_t *__restrict__ tile_leaf,
+                                                     const int32_t *__restrict__ tile_off,
+                                                     const LeafInfo *__restrict__ leaves,
+                                                     const double4 *__restrict__ near,
+                                                     const typename Cx<R>::c2 *__restrict__ deriv,
+                                                     double2 *__restrict__ verts, double2 *__restrict__ w_out)
+{
+    shoot_tile<R, true>(sa, lc, g, tile_leaf, tile_off, leaves, near, deriv, verts, w_out, blockIdx.x, threadIdx.x);
 }
 
 // the maps of a fused batch: every tile of every map in one launch (one
@@ -310,20 +335,25 @@ int64_t plan_tiles(mlm_lens *lens, Tree &T, const Region &R, int64_t vb0, int64_
     return ntiles;
 }
 
+constexpr double STAGED_TILES_PER_LEAF = 256.0;
+
 void launch_shoot(mlm_lens *lens, const Tree &T, const Region &R, const LensConst &lc, const MapGeom &g,
                   int64_t ntiles, int64_t vb0, double2 *verts, double *w_out, hipStream_t st)
 {
     if (ntiles <= 0) return;
     Workspace &ws = lens->ws;
     ShootArgs sa{R.x0, R.y0, R.d1, R.d2, R.nr1, vb0, T.p, 0, 0.0};
+    // tiles of 64 rays per leaf over the whole grid: few, and each tile
+    // stages its leaf's stars through LDS
+    const bool staged = (double)R.nr1 * (double)R.nr2 < STAGED_TILES_PER_LEAF * 64.0 * (double)std::max<int64_t>(T.nleaves, 1);
     if (T.mixed)
-        hipLaunchKernelGGL(k_shoot<float>, dim3((unsigned)ntiles), dim3(64), 0, st, sa, lc, g,
-                           ws.tile_leaf.as<int32_t>(), ws.tile_off.as<int32_t>(), T.leaves, T.near, T.deriv_f, verts,
-                           reinterpret_cast<double2 *>(w_out));
+        hipLaunchKernelGGL(staged ? k_shoot_staged<float> : k_shoot<float>, dim3((unsigned)ntiles), dim3(64), 0, st, sa,
+                           lc, g, ws.tile_leaf.as<int32_t>(), ws.tile_off.as<int32_t>(), T.leaves, T.near, T.deriv_f,
+                           verts, reinterpret_cast<double2 *>(w_out));
     else
-        hipLaunchKernelGGL(k_shoot<double>, dim3((unsigned)ntiles), dim3(64), 0, st, sa, lc, g,
-                           ws.tile_leaf.as<int32_t>(), ws.tile_off.as<int32_t>(), T.leaves, T.near, T.deriv, verts,
-                           reinterpret_cast<double2 *>(w_out));
+        hipLaunchKernelGGL(staged ? k_shoot_staged<double> : k_shoot<double>, dim3((unsigned)ntiles), dim3(64), 0, st,
+                           sa, lc, g, ws.tile_leaf.as<int32_t>(), ws.tile_off.as<int32_t>(), T.leaves, T.near, T.deriv,
+                           verts, reinterpret_cast<double2 *>(w_out));
 }
 
 void launch_shoot_direct(mlm_lens *lens, const Region &R, const LensConst &lc, const MapGeom &g, int64_t vb0,

@@ -107,30 +107,16 @@ __device__ inline void finish_vertex(const LensConst &lc, const MapGeom &g, doub
     uv = make_double2((w1 - g.ylo1) / g.pix1, (w2 - g.ylo2) / g.pix2);
 }
 
-// far-field and near-field deflection at offset (dx, dy) from a leaf's
-// centre, in arithmetic type R; the offsets from the leaf centre and from
-// each near star are formed in FP64 (a ray may pass very close to a star).
+// far field at offset (dx, dy) from a leaf's centre, added to the near field
+// (ax, ay) already summed in type R: conj( sum_{l<p} deriv_l zeta^l ), Horner.
 // In FP32 the Taylor series is split: its value at the centre (the field of
 // every far star, as large as kappa_* |z|) is the leaf's FP64 f0, and FP32
 // carries only the variation across the leaf, zeta sum_{l>=1} d_l zeta^(l-1),
 // which is of the size of the field's derivative times the leaf's half-length
 template <class R>
-__device__ inline void leaf_alpha(double dx, double dy, const LeafInfo &li, const double4 *__restrict__ ns,
-                                  const typename Cx<R>::c2 *__restrict__ dv, int p, double &ax_out, double &ay_out)
+__device__ inline void far_field(double dx, double dy, const LeafInfo &li, const typename Cx<R>::c2 *dv, int p, R ax,
+                                 R ay, double &ax_out, double &ay_out)
 {
-    // near field: a_* += m (z - z_i) / |z - z_i|^2
-    R ax = 0, ay = 0;
-    // both loops unrolled so that several of their wavefront-uniform (scalar)
-    // loads are in flight before the first is needed
-#pragma unroll 4
-    for (int32_t s = 0; s < li.near_cnt; ++s) {
-        const double4 st = ns[s];
-        const R ex = (R)(dx - st.x), ey = (R)(dy - st.y);
-        const R f = near_div((R)st.z, ex * ex + ey * ey);
-        ax += f * ex;
-        ay += f * ey;
-    }
-    // far field: conj( sum_{l<p} deriv_l zeta^l ), Horner
     const R zr = (R)(dx * li.invL), zi = (R)(dy * li.invL);
     if constexpr (sizeof(R) == sizeof(double)) {
         R sr = dv[p - 1].x, si = dv[p - 1].y;
@@ -162,6 +148,63 @@ __device__ inline void leaf_alpha(double dx, double dy, const LeafInfo &li, cons
         ax_out = (double)ax + (li.f0x + (double)vr);
         ay_out = (double)ay - (li.f0y + (double)vi);
     }
+}
+
+// near field of one star: a_* += m (z - z_i) / |z - z_i|^2, the offset from
+// the star formed in FP64 (a ray may pass very close to a star)
+template <class R>
+__device__ inline void near_star(double dx, double dy, const double4 &st, R &ax, R &ay)
+{
+    const R ex = (R)(dx - st.x), ey = (R)(dy - st.y);
+    const R f = near_div((R)st.z, ex * ex + ey * ey);
+    ax += f * ex;
+    ay += f * ey;
+}
+
+// far-field and near-field deflection at offset (dx, dy) from a leaf's
+// centre, in arithmetic type R
+template <class R>
+__device__ inline void leaf_alpha(double dx, double dy, const LeafInfo &li, const double4 *__restrict__ ns,
+                                  const typename Cx<R>::c2 *__restrict__ dv, int p, double &ax_out, double &ay_out)
+{
+    R ax = 0, ay = 0;
+    // unrolled so that several of the wavefront-uniform (scalar) loads are in
+    // flight before the first is needed
+#pragma unroll 4
+    for (int32_t s = 0; s < li.near_cnt; ++s) near_star<R>(dx, dy, ns[s], ax, ay);
+    far_field<R>(dx, dy, li, dv, p, ax, ay, ax_out, ay_out);
+}
+
+// LDS of a wavefront whose rays all lie in one leaf: the leaf's near stars,
+// 64 at a time, and its Taylor coefficients
+template <class R> struct LeafLds {
+    double4 star[64];
+    typename Cx<R>::c2 d[MAX_ORDER + 1];
+};
+
+// leaf_alpha for a workgroup of one wavefront whose rays share the leaf: the
+// lanes load the leaf's near stars (64 at a time) and coefficients into LDS
+// together, so the wavefront waits on memory once per 64 stars instead of
+// once per few stars through the scalar cache; the same arithmetic in the
+// same order
+template <class R>
+__device__ inline void leaf_alpha_tile(double dx, double dy, const LeafInfo &li, const double4 *__restrict__ ns,
+                                       const typename Cx<R>::c2 *__restrict__ dv, int p, double &ax_out,
+                                       double &ay_out, LeafLds<R> &S)
+{
+    const int lane = (int)threadIdx.x & 63;
+    if (lane < p) S.d[lane] = dv[lane];
+    R ax = 0, ay = 0;
+    for (int32_t base = 0; base < li.near_cnt; base += 64) {
+        const int32_t n = min(64, li.near_cnt - base);
+        if (lane < n) S.star[lane] = ns[base + lane];
+        __syncthreads();
+#pragma unroll 2
+        for (int32_t s = 0; s < n; ++s) near_star<R>(dx, dy, S.star[s], ax, ay);
+        __syncthreads();   // the next 64 overwrite the stars
+    }
+    __syncthreads();       // the coefficients, when the leaf has no near star
+    far_field<R>(dx, dy, li, S.d, p, ax, ay, ax_out, ay_out);
 }
 
 // leaf containing (x, y): down from the root through the children, the
