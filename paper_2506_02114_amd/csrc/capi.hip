@@ -1544,6 +1544,8 @@ mlm_status mlm_map_batch(mlm_lens *const *lenses, const mlm_map_request *reqs, i
             d.nbands = (int32_t)m.nbands;
             d.p = m.T.p;
             d.mixed = m.T.mixed ? 1 : 0;
+            d.staged = shoot_staged(m.R, m.T) ? 1 : 0;
+            d.pad = 0;
             vo += m.nverts;
             tl += m.ntiles;
             ctl += m.nctiles;

@@ -174,6 +174,7 @@ struct BatchMap {
     int64_t tile_lo, ctile_lo, cell_lo, band_lo;   // first shoot tile, cell tile, cell, band
     int64_t big_lo, big_hi;           // this map's large triangles in the gathered list
     int32_t bh, nbands, p, mixed;
+    int32_t staged, pad;              // staged: shoot with the leaf's stars through LDS (shoot_staged)
 };
 
 // one work item of the batch's persistent band pass: a slice [lo, hi) of the
@@ -327,6 +328,9 @@ void launch_shoot_irs_direct(mlm_lens *lens, const Region &R, const LensConst &l
                              int64_t cb1, unsigned long long *counts, hipStream_t st);
 // map = counts * w
 void launch_irs_mu(const unsigned long long *counts, int64_t npix, double w, double *map, hipStream_t st);
+// whether a map's shooting stages each leaf's near stars through LDS: the
+// grid has few ray tiles (64 rays) per leaf, so the scalar cache would miss
+bool shoot_staged(const Region &R, const Tree &T);
 void launch_shoot(mlm_lens *lens, const Tree &T, const Region &R, const LensConst &lc,
                   const MapGeom &g, int64_t ntiles, int64_t vb0, double2 *verts, double *w_out,
                   hipStream_t st);

@@ -192,12 +192,24 @@ __global__ __launch_bounds__(64) void k_shoot_batch(const BatchMap *__restrict__
         const int32_t m = batch_find(maps, nmaps, t, &BatchMap::tile_lo);
         const BatchMap &d = maps[m];
         const ShootArgs sa{d.x0, d.y0, d.d1, d.d2, d.nr1, 0, d.p, 0, 0.0};
-        if (d.mixed)
-            shoot_tile<float>(sa, d.lc, d.g, d.tile_leaf, d.tile_off, d.leaves, d.near,
-                              static_cast<const float2 *>(d.deriv), d.verts, nullptr, t - d.tile_lo, threadIdx.x);
-        else
-            shoot_tile<double>(sa, d.lc, d.g, d.tile_leaf, d.tile_off, d.leaves, d.near,
-                               static_cast<const double2 *>(d.deriv), d.verts, nullptr, t - d.tile_lo, threadIdx.x);
+        // (the branches are uniform over the workgroup: one tile of one map)
+        if (d.mixed) {
+            if (d.staged)
+                shoot_tile<float, true>(sa, d.lc, d.g, d.tile_leaf, d.tile_off, d.leaves, d.near,
+                                        static_cast<const float2 *>(d.deriv), d.verts, nullptr, t - d.tile_lo,
+                                        threadIdx.x);
+            else
+                shoot_tile<float>(sa, d.lc, d.g, d.tile_leaf, d.tile_off, d.leaves, d.near,
+                                  static_cast<const float2 *>(d.deriv), d.verts, nullptr, t - d.tile_lo, threadIdx.x);
+        } else {
+            if (d.staged)
+                shoot_tile<double, true>(sa, d.lc, d.g, d.tile_leaf, d.tile_off, d.leaves, d.near,
+                                         static_cast<const double2 *>(d.deriv), d.verts, nullptr, t - d.tile_lo,
+                                         threadIdx.x);
+            else
+                shoot_tile<double>(sa, d.lc, d.g, d.tile_leaf, d.tile_off, d.leaves, d.near,
+                                   static_cast<const double2 *>(d.deriv), d.verts, nullptr, t - d.tile_lo, threadIdx.x);
+        }
     }
 }
 
@@ -337,15 +349,18 @@ int64_t plan_tiles(mlm_lens *lens, Tree &T, const Region &R, int64_t vb0, int64_
 
 constexpr double STAGED_TILES_PER_LEAF = 256.0;
 
+bool shoot_staged(const Region &R, const Tree &T)
+{
+    return (double)R.nr1 * (double)R.nr2 < STAGED_TILES_PER_LEAF * 64.0 * (double)std::max<int64_t>(T.nleaves, 1);
+}
+
 void launch_shoot(mlm_lens *lens, const Tree &T, const Region &R, const LensConst &lc, const MapGeom &g,
                   int64_t ntiles, int64_t vb0, double2 *verts, double *w_out, hipStream_t st)
 {
     if (ntiles <= 0) return;
     Workspace &ws = lens->ws;
     ShootArgs sa{R.x0, R.y0, R.d1, R.d2, R.nr1, vb0, T.p, 0, 0.0};
-    // tiles of 64 rays per leaf over the whole grid: few, and each tile
-    // stages its leaf's stars through LDS
-    const bool staged = (double)R.nr1 * (double)R.nr2 < STAGED_TILES_PER_LEAF * 64.0 * (double)std::max<int64_t>(T.nleaves, 1);
+    const bool staged = shoot_staged(R, T);
     if (T.mixed)
         hipLaunchKernelGGL(staged ? k_shoot_staged<float> : k_shoot<float>, dim3((unsigned)ntiles), dim3(64), 0, st, sa,
                            lc, g, ws.tile_leaf.as<int32_t>(), ws.tile_off.as<int32_t>(), T.leaves, T.near, T.deriv_f,
