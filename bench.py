@@ -41,7 +41,7 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6          # MI355X FP64 vector, dense
 # the two files' bytes in that order.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 IPM_TRAFFIC = {"ipm_sha256": "a530c3ebbb5bdec1",                     # (fetch KiB, write KiB)
-               "k_ipm": (719906.6875, 2278836.5375), "k_band_queue1": (5462013.2875, 280192.50625)}
+               "k_ipm": (719906.85, 2278836.5375), "k_band_queue1": (5470672.9125, 280193.3625)}
 # Wavefront vector instructions per launch of the same kernels (SQ_INSTS_VALU,
 # same runs and source).  A wave64 vector instruction holds its SIMD four
 # cycles, so 1024 SIMDs at 2.4 GHz issue at most 6.144e11 of them per second:
