@@ -588,14 +588,14 @@ def main():
     band_roof["valu_issue"] = valu_issue("k_band_queue1", t_band1)
     band_roof["scatter"] = scatter("k_band_queue1", t_band1)
     roof, other = (cells_roof, band_roof) if t_cells >= t_band else (band_roof, cells_roof)
-    # the IPM stage priced by the survey's model: 25 flops per (triangle,
-    # pixel) piece and 30 per triangle, over the whole stage's time
-    survey_flops = 25.0 * counts["n_pieces"] + 30.0 * 2.0 * counts["n_cells"]
-    ipm_survey = {"bound": "alu", "model": "25 flops per (triangle, pixel) piece + 30 per triangle",
-                  "achieved": survey_flops / (t_ipm * 1e-3) / 1e12, "peak": FP64_VECTOR_PEAK_TFLOPS,
+    # the IPM stage priced per piece: 25 flops per (triangle, pixel) piece
+    # and 30 per triangle, over the whole stage's time
+    piece_flops = 25.0 * counts["n_pieces"] + 30.0 * 2.0 * counts["n_cells"]
+    ipm_pieces = {"bound": "alu", "model": "25 flops per (triangle, pixel) piece + 30 per triangle",
+                  "achieved": piece_flops / (t_ipm * 1e-3) / 1e12, "peak": FP64_VECTOR_PEAK_TFLOPS,
                   "unit": "TFLOP/s", "stage_ms": t_ipm, "pieces": counts["n_pieces"],
                   "triangles": 2 * counts["n_cells"]}
-    ipm_survey["frac"] = ipm_survey["achieved"] / ipm_survey["peak"]
+    ipm_pieces["frac"] = ipm_pieces["achieved"] / ipm_pieces["peak"]
     line = {
         "metric": METRIC,
         "value": value,
@@ -622,7 +622,7 @@ def main():
         "roofline": roof,
         "roofline_" + other["kernel"]: other,
         "roofline_shoot": shoot_roof,
-        "roofline_ipm_stage_survey_model": ipm_survey,
+        "roofline_ipm_stage_piece_model": ipm_pieces,
         "tree": {"nodes": stats[0]["n_nodes"], "leaves": stats[0]["n_leaves"], "levels": stats[0]["n_levels"],
                  "near_pairs_per_ray": stats[0]["near_pairs"] / rays},
         "ipm": {"triangles": 2 * stats[0]["n_cells"], "row_path_triangles": stats[0]["n_big"],

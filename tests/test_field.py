@@ -69,7 +69,9 @@ def test_masses_follow_the_mass_function(mlm, kind, lo, hi):
 
 
 def test_moment_table(mlm):
-    # the survey's quadrature table: Salpeter 0.1-1, 0.1-2, Kroupa 0.08-1.5
+    # the first two moments of the mass functions by quadrature of their
+    # definitions, to four places: Salpeter (slope 2.35) over 0.1-1 and 0.1-2,
+    # Kroupa (slopes 1.3 below 0.5 and 2.3 above) over 0.08-1.5
     for kind, lo, hi, mm, mm2 in (("salpeter", 0.1, 1.0, 0.2234, 0.0754), ("salpeter", 0.1, 2.0, 0.2550, 0.1270),
                                   ("kroupa", 0.08, 1.5, 0.3251, 0.1830)):
         a, b = mlm.field_moments(mlm.field_params(0.3, kind, n_stars=1, m_lo=lo, m_hi=hi))
