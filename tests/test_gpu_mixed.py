@@ -23,8 +23,8 @@ round-off u = 2^-24 and the size of what FP32 carries:
 A regression that puts the field's magnitude back into FP32 (about
 kappa_* |z| ~ 100, i.e. ~1e-5 theta_* of absolute error) fails all three.
 The coefficients are FP64 in both modes, so they match the oracle's like the
-FP64 mode's (1e-11).  Measured values go to
-gpurun_out/parity_report_mixed.json.
+FP64 mode's (1e-11).  Measured values go to the report file
+parity_report_mixed.json.
 """
 import json
 import os
